@@ -1,0 +1,193 @@
+/*
+ * fbc.h -- C ABI of the line-periodic flexible-boundary-condition (FBC) pad update
+ * for MI355X (gfx950).
+ *
+ * The operation (Section 2.3.2, eq. flexbc.up=Gpipl*fipl, Algorithm 1 lines 5-8):
+ *     u^p  <-  u^p - alpha * G^{p|i+} [f_in],   then remove the mean pad displacement
+ * (eq. mean(u^p)=0), for a cell that is periodic along the dislocation line
+ * (Section 2.1).  G^{p|i+} is the Green matrix of the harmonic lattice (Section 3.2,
+ * eq. impl.up=Gpipl*fipl_mvm); because the cell is periodic along the line and the
+ * entries depend only on the separation, it is block-circulant in the layer index.
+ * The library therefore works per line mode m: rFFT of the interface forces along the
+ * line, one dense complex product w^(m) = G^(m) f^(m) per mode, inverse rFFT.
+ *
+ * Lattice and model.  fcc, lattice constant a, nearest-neighbour central springs of
+ * stiffness k (the local harmonic model K_h of Section 2.2.1).  Sites are indexed in
+ * the primitive basis b0 = a(1/2,-1/2,0) (along the line [1-10]), b1 = a(1/2,0,1/2),
+ * b2 = a(1/2,1/2,0): site (n0, n1, n2) is atom column (n1, n2) in layer n0 mod N_z, one
+ * atom per column and layer.
+ *
+ * Green function (Appendix B).  G^(m; dn1, dn2) is the inverse lattice Fourier
+ * transform of D(q)^{-1}, D the Fourier symbol of K_h, summed over the discrete
+ * Brillouin-zone grid of an M1 x M2 in-plane torus, with the singular q = 0 term
+ * dropped (pseudo-inverse gauge: the Green function is unique only up to a constant,
+ * Section 3.1).  The block coupling pad column b to interface column i is
+ * G^(m; n_b - n_i).  Forces with zero net force per layer make the result independent
+ * of the gauge; the check below enforces it.
+ *
+ * Conventions.
+ *   f  (interface forces)  : device FP64, per cell [n_rhs][N_z][n_i][3], row-major.
+ *   u  (pad displacements)  : device FP64, per cell [n_rhs][N_z][n_b][3], row-major.
+ *   Cells are packed back to back in the order given to fbc_assemble_G.
+ *   Forward line transform e^{-2 pi i m n0 / N_z}, unnormalised; inverse scaled 1/N_z.
+ *   Column sets are host int32 arrays [n][2] of (n1, n2).
+ *
+ * Ownership.  The caller owns f, u, the relax output buffer and the stream.  The
+ * context owns every device buffer it allocates (Green store, tables, scratch) and
+ * frees them in fbc_destroy.  Nothing of the caller's is retained across calls.
+ *
+ * Errors.  Every entry point returns an fbc_status; nothing throws across the ABI.
+ * Host-checkable arguments are validated before any device work is enqueued, so a
+ * call rejected with FBC_E_ARG / FBC_E_UNSUPPORTED leaves every output untouched.
+ * Data-dependent checks (non-finite forces, non-zero net force) run on the device
+ * inside the enqueued work: when one fails, the kernels that write u skip their
+ * writes (u is left untouched) and the failure is latched in the context; it is
+ * returned by fbc_sync_status(), which synchronises the stream.  Device/runtime
+ * failures give FBC_E_DEVICE with the HIP error text in fbc_last_error().
+ *
+ * Threads and streams.  A context may be used by one host thread and one stream at a
+ * time; calls that overlap on one context race on its scratch buffers.
+ */
+#ifndef FBC_H
+#define FBC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fbc_ctx fbc_ctx;
+
+typedef enum {
+    FBC_OK = 0,
+    FBC_E_ARG = -1,          /* invalid argument (null pointer, bad size, bad enum) */
+    FBC_E_NOMEM = -2,        /* device allocation failed */
+    FBC_E_NETFORCE = -3,     /* |sum_i f| > netforce_tol * sum_i |f| in some layer/component */
+    FBC_E_NONFINITE = -4,    /* NaN or Inf in the forces */
+    FBC_E_DEVICE = -5,       /* HIP runtime error (text in fbc_last_error) */
+    FBC_E_STATE = -6,        /* call out of order (e.g. relax step before relax begin) */
+    FBC_E_UNSUPPORTED = -7   /* valid request outside what this build implements */
+} fbc_status;
+
+/* How G^(m) is stored and applied (the per-mode product, Section 3.2 in spectral form). */
+typedef enum {
+    FBC_FORM_FP64 = 0,        /* dense FP64 complex blocks, FP64 MFMA                        */
+    FBC_FORM_FP32 = 1,        /* dense FP32 complex blocks, FP32 MFMA, FP64 across K chunks   */
+    FBC_FORM_SPLIT_BF16 = 2,  /* dense split-BF16 (hi+lo) blocks, BF16 MFMA with FP32
+                                 accumulation inside K chunks and FP64 across them            */
+    FBC_FORM_DTABLE_FP64 = 3  /* no dense store: FP64 table over distinct column offsets
+                                 (entries depend on n_b - n_i only), gathered into LDS
+                                 tiles and applied on FP64 MFMA                               */
+} fbc_form;
+
+/* Section 2.1 (eq. flexbc.bravais) and Section 2.2.1 (K_h). */
+typedef struct {
+    double a;          /* lattice constant (> 0); the index-space Green function depends only
+                          on bond directions and k, so a enters only the geometry      */
+    double spring_k;   /* nearest-neighbour central spring stiffness (> 0) */
+} fbc_lattice;
+
+/* One line-periodic cell (Section 2.1: period l3 = N_z a / sqrt 2; Section 2.2.2: the
+ * interface set Lambda^{i+} and the pad set Lambda^p, here unions of atom columns). */
+typedef struct {
+    int nz;                  /* layers along the line, power of two in [2, 4096]          */
+    int n_i;                 /* interface columns (>= 1)                                   */
+    int n_b;                 /* pad columns (>= 1)                                         */
+    int n_rhs;               /* force right-hand sides applied per call (>= 1)             */
+    const int32_t* cols_i;   /* host [n_i][2] (n1, n2); copied, not retained               */
+    const int32_t* cols_b;   /* host [n_b][2] (n1, n2); copied, not retained               */
+} fbc_cell;
+
+typedef struct {
+    int form;                /* fbc_form                                                   */
+    int bz_m1, bz_m2;        /* in-plane Brillouin-zone torus, powers of two in [8, 4096]  */
+    int check_netforce;      /* 1: latch FBC_E_NETFORCE / FBC_E_NONFINITE (device check)   */
+    int project_netforce;    /* 1: subtract the per-layer column mean of f before applying */
+    double netforce_tol;     /* relative tolerance of the net-force check (e.g. 1e-10)     */
+    int row_gauge;           /* reduced forms: subtract each block row's mean over i per
+                                mode before rounding (exact for zero-net-force f)        */
+} fbc_options;
+
+/* Fills *opt with defaults: FP64, 1024 x 1024 torus, check on, no projection, tol 1e-10,
+ * row_gauge on. */
+void fbc_default_options(fbc_options* opt);
+
+/* Assembles G^(m) for m = 0..N_z/2 of every cell on the device (Appendix B, discrete
+ * Brillouin-zone sum in FP64, then the chosen store), and the plan and scratch buffers.
+ * Done once per geometry (Section 3.2: built once, reused).  stream: hipStream_t or
+ * NULL.  Synchronises the stream before returning.  On success *out owns everything. */
+fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cells, int n_cells,
+                          const fbc_options* opt, void* stream, fbc_ctx** out);
+
+/* u <- u - alpha * G^{p|i+} f, then per RHS and Cartesian component the mean over all
+ * pad atoms of all layers is removed (Algorithm 1 lines 7-8).  alpha = -1 with u = 0
+ * gives u = G f minus its mean.  f, u: device pointers, packed by cell (see above).
+ * Asynchronous on `stream`; data-dependent failures are latched (fbc_sync_status). */
+fbc_status fbc_apply(fbc_ctx* ctx, const double* f, double* u, double alpha, void* stream);
+
+/* Same as fbc_apply without the mean removal and with u <- -G f (u overwritten): the
+ * raw harmonic response w = G^{p|i+} f (the matrix-vector product of Section 3.2). */
+fbc_status fbc_green_apply(fbc_ctx* ctx, const double* f, double* w, void* stream);
+
+/* Residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2). */
+typedef struct {
+    int relax;        /* 1: relax from the third iteration on (Algorithm 1 line 5)        */
+    double du_max;    /* > 0: bound ||alpha G f||_inf by du_max (Algorithm 2 lines 6-8)   */
+    double tol_f;     /* convergence flag: ||f_in||_inf < tol_f (Section 2.3.3)           */
+} fbc_relax_opts;
+
+/* Per RHS, written to device memory by fbc_relax_step (packed over all cells' RHS). */
+typedef struct {
+    double alpha;            /* alpha_{k+1} used for this update                 */
+    double f_inf;            /* ||f_in,k+1||_inf                                  */
+    double step_inf;         /* ||alpha G f_in,k+1||_inf                          */
+    double mean_removed[3];  /* mean pad displacement removed (per component)     */
+    int32_t converged;       /* f_inf < tol_f                                     */
+    int32_t k;               /* iteration index k before this step                */
+} fbc_relax_out;
+
+/* Resets the iteration: k = 0, alpha = 1 for every RHS. */
+fbc_status fbc_relax_begin(fbc_ctx* ctx, const fbc_relax_opts* opts, void* stream);
+
+/* One pass of Algorithm 1 lines 5-8 given f_in,k+1 (computed by the caller, line 4):
+ * alpha from Relax on raw residuals (k >= 2), optional step bound, pad update, mean
+ * removal.  No host synchronisation.  out_dev: device array [total RHS] or NULL. */
+fbc_status fbc_relax_step(fbc_ctx* ctx, const double* f_in, double* u,
+                          fbc_relax_out* out_dev, void* stream);
+
+/* Synchronises `stream`, returns and clears the latched device-side status. */
+fbc_status fbc_sync_status(fbc_ctx* ctx, void* stream);
+
+/* Introspection (sizes in bytes of the Green store; per-cell mode counts etc.). */
+typedef struct {
+    int n_cells;
+    int total_rhs;
+    int64_t store_bytes;       /* bytes of the G^ store (dense tiles or offset table)     */
+    int64_t scratch_bytes;     /* bytes of scratch owned by the context                   */
+    int64_t f_elems, u_elems;  /* doubles expected in f and u                             */
+    int64_t n_offsets;         /* distinct column offsets over all cells                  */
+} fbc_info;
+fbc_status fbc_get_info(const fbc_ctx* ctx, fbc_info* info);
+
+/* Copies G^(m) block rows of one cell to host for testing: out[rows][3 n_i] complex
+ * (interleaved re, im), rows = 3 * (b1 - b0), for pad columns b0..b1-1 at mode m, as
+ * the library stores it (FP64 forms only; reduced forms return FBC_E_UNSUPPORTED). */
+fbc_status fbc_copy_block_rows(fbc_ctx* ctx, int cell, int m, int b0, int b1, double* out_host);
+
+/* Kernel timing for measurement.  When enabled, every fbc_apply / fbc_green_apply /
+ * fbc_relax_step records a pair of HIP events on `stream` around the launch of the
+ * per-mode product kernel (the dominant kernel); up to 4096 pairs are kept.
+ * fbc_timing_read synchronises, returns the summed elapsed time in ms and the number
+ * of launches timed since the last read, and resets the list. */
+fbc_status fbc_timing(fbc_ctx* ctx, int enable);
+fbc_status fbc_timing_read(fbc_ctx* ctx, double* gemm_ms_total, int* n_launches);
+
+void fbc_destroy(fbc_ctx* ctx);
+const char* fbc_last_error(const fbc_ctx* ctx);
+const char* fbc_status_string(fbc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FBC_H */

@@ -1,0 +1,747 @@
+// C ABI of the FBC pad-update library: validation, planning, device buffers, and the
+// orchestration of the kernels (see include/fbc.h for the contract).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+int gemm_rb(int form, int ctmax);
+
+struct fbc_ctx {
+    int device = 0;
+    fbc_options opt{};
+    fbc_lattice lat{};
+    std::vector<CellPlan> cells;
+    int total_rhs = 0;
+    int64_t f_elems = 0, u_elems = 0;
+    int ctmax = 1;
+    // device buffers (all owned)
+    std::vector<void*> allocs;
+    void* store = nullptr;          // dense store (FP64 / FP32 / split BF16)
+    int64_t store_bytes = 0;
+    void* bfrag = nullptr;          // GEMM B operand
+    double* cbuf = nullptr;         // GEMM output
+    double* wbuf = nullptr;         // w[r][row][n0]
+    double* sums = nullptr;         // net force per layer
+    double* wmax_part = nullptr;
+    double* sum_part = nullptr;
+    double* mean = nullptr;         // [total_rhs][3]
+    double2* tw = nullptr;          // twiddle tables
+    int* status = nullptr;          // device latch
+    GemmJob* jobs = nullptr;
+    int njobs = 0;
+    int64_t scratch_bytes = 0;
+    int64_t n_offsets = 0;
+    // relax
+    double* fprev = nullptr;
+    double* alpha = nullptr;
+    double* finf = nullptr;
+    double* stepinf = nullptr;
+    double* rpart = nullptr;
+    double* rmean = nullptr;
+    fbc_relax_opts ropt{};
+    int relax_k = -1;
+    // per cell partial counts
+    std::vector<int> npart_irfft, npart_axpy;
+    std::vector<int64_t> wmax_off, sum_part_off, rpart_off;
+    std::string err;
+    // timing of the product kernel
+    int timing = 0;
+    std::vector<hipEvent_t> ev;      // 2 * kMaxTimed events, created on first enable
+    int n_timed = 0;
+};
+static const int kMaxTimed = 4096;
+
+static thread_local std::string g_err;
+
+static fbc_status fail(fbc_ctx* c, fbc_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, FBC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+static int ilog2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+static int64_t roundup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+static fbc_status dev_alloc(fbc_ctx* c, void** p, int64_t bytes) {
+    *p = nullptr;
+    if (bytes <= 0) return FBC_OK;
+    hipError_t e = hipMalloc(p, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(c, FBC_E_NOMEM, "hipMalloc(" + std::to_string(bytes) + " B): " + hipGetErrorString(e));
+    }
+    c->allocs.push_back(*p);
+    return FBC_OK;
+}
+
+static void free_all(fbc_ctx* c) {
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+extern "C" void fbc_default_options(fbc_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->form = FBC_FORM_FP64;
+    o->bz_m1 = 1024;
+    o->bz_m2 = 1024;
+    o->check_netforce = 1;
+    o->project_netforce = 0;
+    o->netforce_tol = 1e-10;
+    o->row_gauge = 1;
+}
+
+extern "C" const char* fbc_status_string(fbc_status s) {
+    switch (s) {
+        case FBC_OK: return "ok";
+        case FBC_E_ARG: return "invalid argument";
+        case FBC_E_NOMEM: return "out of device memory";
+        case FBC_E_NETFORCE: return "non-zero net force per layer";
+        case FBC_E_NONFINITE: return "non-finite force";
+        case FBC_E_DEVICE: return "device error";
+        case FBC_E_STATE: return "call out of order";
+        case FBC_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown";
+}
+
+extern "C" const char* fbc_last_error(const fbc_ctx* c) {
+    return c ? c->err.c_str() : g_err.c_str();
+}
+
+// Nearest-neighbour bonds of fcc in the primitive basis b0=(1/2,-1/2,0), b1=(1/2,0,1/2),
+// b2=(1/2,1/2,0) and the projectors k Rhat Rhat^T (Section 2.2.1, K_h of central springs).
+static BondTable make_bonds(double k) {
+    BondTable bt{};
+    // cubic (a = 1) basis columns
+    const double B[3][3] = {{0.5, 0.5, 0.5}, {-0.5, 0.0, 0.5}, {0.0, 0.5, 0.0}};
+    // inverse of B (rows), exact for this basis
+    double det = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                 B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                 B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+    double inv[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+            inv[i][j] = (B[i1][j1] * B[i2][j2] - B[i1][j2] * B[i2][j1]) / det;
+        }
+    int nb = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            for (int sa = -1; sa <= 1; sa += 2)
+                for (int sb = -1; sb <= 1; sb += 2) {
+                    double R[3] = {0, 0, 0};
+                    R[a] = 0.5 * sa;
+                    R[b] = 0.5 * sb;
+                    for (int i = 0; i < 3; ++i) {
+                        const double v = inv[i][0] * R[0] + inv[i][1] * R[1] + inv[i][2] * R[2];
+                        bt.n[nb][i] = (int)std::lround(v);
+                    }
+                    const double len2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+                    const int cc[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+                    for (int s = 0; s < 6; ++s) bt.p[nb][s] = k * R[cc[s][0]] * R[cc[s][1]] / len2;
+                    ++nb;
+                }
+    return bt;
+}
+
+// exp(-2 pi i j / n), j < n/2, from extended precision.
+static void twiddles(int n, std::vector<double2>& out) {
+    out.resize(std::max(1, n / 2));
+    for (int j = 0; j < n / 2; ++j) {
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * j / n;
+        out[j] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    if (n / 2 == 0) out[0] = make_double2(1.0, 0.0);
+}
+
+static int64_t store_elem_bytes(int form) {
+    return form == FBC_FORM_FP64 ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
+}
+// store elements (of the store type) per mode: FP64/FP32 mp*kp, BF16 2*mp*kp
+static int64_t store_mode_elems(int form, const CellPlan& p) {
+    return (int64_t)p.mp * p.kp * (form == FBC_FORM_SPLIT_BF16 ? 2 : 1);
+}
+static int64_t b_mode_elems(int form, const CellPlan& p) {
+    return (int64_t)16 * p.ct * p.kp * (form == FBC_FORM_SPLIT_BF16 ? 2 : 1);
+}
+static int64_t b_elem_bytes(int form) {
+    return (form == FBC_FORM_FP64 || form == FBC_FORM_DTABLE_FP64) ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
+}
+
+// ----------------------------------------------------------------------------------
+// Assembly of one cell's offset table and store.
+// ----------------------------------------------------------------------------------
+struct OffsetSet {
+    int d1min, d2min, w1, w2;
+    std::vector<int32_t> lut, d1, d2;
+};
+
+static OffsetSet offsets_of(const CellPlan& p) {
+    OffsetSet o{};
+    int b1lo = INT32_MAX, b1hi = INT32_MIN, b2lo = INT32_MAX, b2hi = INT32_MIN;
+    int i1lo = INT32_MAX, i1hi = INT32_MIN, i2lo = INT32_MAX, i2hi = INT32_MIN;
+    for (int b = 0; b < p.n_b; ++b) {
+        b1lo = std::min(b1lo, p.cols_b[2 * b]);
+        b1hi = std::max(b1hi, p.cols_b[2 * b]);
+        b2lo = std::min(b2lo, p.cols_b[2 * b + 1]);
+        b2hi = std::max(b2hi, p.cols_b[2 * b + 1]);
+    }
+    for (int i = 0; i < p.n_i; ++i) {
+        i1lo = std::min(i1lo, p.cols_i[2 * i]);
+        i1hi = std::max(i1hi, p.cols_i[2 * i]);
+        i2lo = std::min(i2lo, p.cols_i[2 * i + 1]);
+        i2hi = std::max(i2hi, p.cols_i[2 * i + 1]);
+    }
+    o.d1min = b1lo - i1hi;
+    o.d2min = b2lo - i2hi;
+    o.w1 = b1hi - i1lo - o.d1min + 1;
+    o.w2 = b2hi - i2lo - o.d2min + 1;
+    o.lut.assign((size_t)o.w1 * o.w2, -1);
+    for (int b = 0; b < p.n_b; ++b)
+        for (int i = 0; i < p.n_i; ++i) {
+            const int x = p.cols_b[2 * b] - p.cols_i[2 * i] - o.d1min;
+            const int y = p.cols_b[2 * b + 1] - p.cols_i[2 * i + 1] - o.d2min;
+            o.lut[(size_t)x * o.w2 + y] = 0;
+        }
+    int32_t n = 0;
+    for (int x = 0; x < o.w1; ++x)
+        for (int y = 0; y < o.w2; ++y) {
+            int32_t& e = o.lut[(size_t)x * o.w2 + y];
+            if (e == 0) {
+                e = n++;
+                o.d1.push_back(x + o.d1min);
+                o.d2.push_back(y + o.d2min);
+            }
+        }
+    return o;
+}
+
+static fbc_status assemble_cell(fbc_ctx* c, CellPlan& p, hipStream_t st, const BondTable& bt,
+                                double* sn_d, int logL) {
+    const int m1 = c->opt.bz_m1, m2 = c->opt.bz_m2;
+    const int form = c->opt.form;
+    OffsetSet os = offsets_of(p);
+    const int64_t n_off = (int64_t)os.d1.size();
+    c->n_offsets += n_off;
+    // temporary device buffers of this cell
+    std::vector<void*> tmp;
+    auto talloc = [&](void** ptr, int64_t bytes) -> fbc_status {
+        *ptr = nullptr;
+        hipError_t e = hipMalloc(ptr, (size_t)bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, FBC_E_NOMEM, "assembly scratch of " + std::to_string(bytes) + " B: " + hipGetErrorString(e));
+        }
+        tmp.push_back(*ptr);
+        return FBC_OK;
+    };
+    auto cleanup = [&]() {
+        for (void* q : tmp) (void)hipFree(q);
+    };
+    int32_t *lut_d, *d1_d, *d2_d;
+    double2* tab;
+    fbc_status s;
+    if ((s = talloc((void**)&lut_d, (int64_t)os.lut.size() * 4)) != FBC_OK ||
+        (s = talloc((void**)&d1_d, n_off * 4)) != FBC_OK ||
+        (s = talloc((void**)&d2_d, n_off * 4)) != FBC_OK ||
+        (s = talloc((void**)&tab, (int64_t)p.nm * n_off * 6 * 16)) != FBC_OK) {
+        cleanup();
+        return s;
+    }
+    (void)hipMemcpyAsync(lut_d, os.lut.data(), os.lut.size() * 4, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d1_d, os.d1.data(), n_off * 4, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d2_d, os.d2.data(), n_off * 4, hipMemcpyHostToDevice, st);
+    // twiddles for the in-plane transforms
+    std::vector<double2> tw1, tw2;
+    twiddles(m1, tw1);
+    twiddles(m2, tw2);
+    double2 *tw1_d, *tw2_d;
+    if ((s = talloc((void**)&tw1_d, (int64_t)tw1.size() * 16)) != FBC_OK ||
+        (s = talloc((void**)&tw2_d, (int64_t)tw2.size() * 16)) != FBC_OK) {
+        cleanup();
+        return s;
+    }
+    (void)hipMemcpyAsync(tw1_d, tw1.data(), tw1.size() * 16, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(tw2_d, tw2.data(), tw2.size() * 16, hipMemcpyHostToDevice, st);
+    // mode chunks sized to ~2 GiB of FFT workspace (x2 for the transpose)
+    const int64_t plane = (int64_t)m1 * m2;
+    const int64_t per_mode = plane * 3 * 16;
+    int chunk = (int)std::max<int64_t>(1, ((int64_t)1 << 31) / per_mode);
+    chunk = std::min(chunk, p.nm);
+    double2 *pk, *pt;
+    if ((s = talloc((void**)&pk, per_mode * chunk)) != FBC_OK ||
+        (s = talloc((void**)&pt, per_mode * chunk)) != FBC_OK) {
+        cleanup();
+        return s;
+    }
+    const double scale = 1.0 / ((double)m1 * m2);
+    for (int m0 = 0; m0 < p.nm; m0 += chunk) {
+        const int nmc = std::min(chunk, p.nm - m0);
+        launch_dinv(st, pk, m0, nmc, p.nz, m1, m2, logL, sn_d, bt);
+        // inverse 2-D FFT: rows (m2 contiguous), transpose, rows again -> t[comp][d2][d1]
+        launch_fft_rows(st, pk, (int64_t)nmc * 3 * m1, ilog2(m2), tw2_d, true);
+        launch_transpose_c(st, pk, pt, nmc * 3, m1, m2);
+        launch_fft_rows(st, pt, (int64_t)nmc * 3 * m2, ilog2(m1), tw1_d, true);
+        launch_gather_table(st, pt, tab + (int64_t)m0 * n_off * 6, nmc, m1, m2, n_off, d1_d, d2_d,
+                            n_off * 6, scale);
+    }
+    HIPCHK(c, hipGetLastError());
+    if (form == FBC_FORM_DTABLE_FP64) {
+        cleanup();
+        return fail(c, FBC_E_UNSUPPORTED, "offset-table form not built yet");
+    }
+    double2* rowmean = nullptr;
+    if (form != FBC_FORM_FP64 && c->opt.row_gauge) {
+        if ((s = talloc((void**)&rowmean, (int64_t)p.nm * p.n_b * 6 * 16)) != FBC_OK) {
+            cleanup();
+            return s;
+        }
+        launch_rowmean(st, tab, rowmean, p.nm, n_off, p.n_b, p.n_i, p.cols_b_d, p.cols_i_d, lut_d,
+                       os.d1min, os.d2min, os.w2);
+    }
+    char* base = (char*)c->store + p.a_off * store_elem_bytes(form);
+    launch_build_dense(st, form, base, tab, rowmean, p.nm, n_off, p.mp, p.kp, p.n_b, p.n_i,
+                       p.cols_b_d, p.cols_i_d, lut_d, os.d1min, os.d2min, os.w2);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    cleanup();
+    return FBC_OK;
+}
+
+// ----------------------------------------------------------------------------------
+// Work list of the per-mode products: every (cell, mode) unit goes to one XCD (work
+// groups are dispatched round-robin over the 8 XCDs by block index), so the B
+// fragments of a mode are shared through that XCD's L2.
+// ----------------------------------------------------------------------------------
+static std::vector<GemmJob> build_jobs(const fbc_ctx* c) {
+    const int form = c->opt.form;
+    const int rb = gemm_rb(form, c->ctmax);
+    const int tile_rb = 4 * rb;
+    std::vector<std::vector<GemmJob>> per_xcd(8);
+    std::vector<int64_t> load(8, 0);
+    struct Unit { int cell, m, tiles; };
+    std::vector<Unit> units;
+    for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
+        const CellPlan& p = c->cells[ci];
+        const int mb = p.mp / 16;
+        const int tiles = (mb + tile_rb - 1) / tile_rb;
+        for (int m = 0; m < p.nm; ++m) units.push_back({ci, m, tiles});
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.tiles > b.tiles; });
+    for (const Unit& u : units) {
+        int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const CellPlan& p = c->cells[u.cell];
+        for (int t = 0; t < u.tiles; ++t) {
+            GemmJob j{};
+            j.a_off = p.a_off + (int64_t)u.m * store_mode_elems(form, p);
+            j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
+            j.c_off = p.c_off + (int64_t)u.m * p.ct * p.mp * 16;
+            j.mb = p.mp / 16;
+            j.kp = p.kp;
+            j.rb0 = t * tile_rb;
+            j.ct = p.ct;
+            j.cell = u.cell;
+            per_xcd[x].push_back(j);
+        }
+        load[x] += u.tiles;
+    }
+    size_t mx = 0;
+    for (auto& v : per_xcd) mx = std::max(mx, v.size());
+    std::vector<GemmJob> out;
+    out.reserve(mx * 8);
+    for (size_t k = 0; k < mx; ++k)
+        for (int x = 0; x < 8; ++x) {
+            if (k < per_xcd[x].size()) out.push_back(per_xcd[x][k]);
+            else {
+                GemmJob z{};
+                z.mb = 0;      // empty job: every wave returns at once
+                out.push_back(z);
+            }
+        }
+    return out;
+}
+
+extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cells, int n_cells,
+                                     const fbc_options* opt, void* stream, fbc_ctx** out) {
+    if (!out) return fail(nullptr, FBC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!lat || !cells || !opt || n_cells <= 0) return fail(nullptr, FBC_E_ARG, "null argument or n_cells <= 0");
+    if (!(lat->a > 0) || !(lat->spring_k > 0) || !std::isfinite(lat->a) || !std::isfinite(lat->spring_k))
+        return fail(nullptr, FBC_E_ARG, "lattice constant and spring stiffness must be positive");
+    if (opt->form < FBC_FORM_FP64 || opt->form > FBC_FORM_DTABLE_FP64)
+        return fail(nullptr, FBC_E_ARG, "unknown form");
+    if (!is_pow2(opt->bz_m1) || !is_pow2(opt->bz_m2) || opt->bz_m1 < 8 || opt->bz_m2 < 8 ||
+        opt->bz_m1 > 4096 || opt->bz_m2 > 4096)
+        return fail(nullptr, FBC_E_ARG, "bz_m1, bz_m2 must be powers of two in [8, 4096]");
+    if (!(opt->netforce_tol >= 0)) return fail(nullptr, FBC_E_ARG, "netforce_tol must be >= 0");
+    for (int i = 0; i < n_cells; ++i) {
+        const fbc_cell& cl = cells[i];
+        if (!is_pow2(cl.nz) || cl.nz < 2 || cl.nz > 4096)
+            return fail(nullptr, FBC_E_ARG, "nz must be a power of two in [2, 4096]");
+        if (cl.n_i < 1 || cl.n_b < 1 || cl.n_rhs < 1 || !cl.cols_i || !cl.cols_b)
+            return fail(nullptr, FBC_E_ARG, "cell sizes must be >= 1 and column arrays non-null");
+        if ((int64_t)cl.n_i * 6 > (1 << 30) || (int64_t)cl.n_b * 3 > (1 << 30) || cl.n_rhs > 4096)
+            return fail(nullptr, FBC_E_ARG, "cell too large");
+    }
+    if (opt->form == FBC_FORM_DTABLE_FP64)
+        return fail(nullptr, FBC_E_UNSUPPORTED, "offset-table form not built yet");
+
+    fbc_ctx* c = new (std::nothrow) fbc_ctx();
+    if (!c) return fail(nullptr, FBC_E_NOMEM, "host allocation");
+    c->opt = *opt;
+    c->lat = *lat;
+    (void)hipGetDevice(&c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int form = opt->form;
+
+    // plan
+    int64_t f_off = 0, u_off = 0, a_off = 0, b_off = 0, c_off = 0, w_off = 0;
+    int rhs0 = 0;
+    for (int i = 0; i < n_cells; ++i) {
+        CellPlan p{};
+        p.nz = cells[i].nz;
+        p.nm = p.nz / 2 + 1;
+        p.n_i = cells[i].n_i;
+        p.n_b = cells[i].n_b;
+        p.R = cells[i].n_rhs;
+        p.K = 3 * p.n_i;
+        p.M = 3 * p.n_b;
+        p.kp = (int)roundup(6 * (int64_t)p.n_i, 32);
+        p.mp = (int)roundup(p.M, 16);
+        p.ct = (p.R + 7) / 8;
+        p.f_off = f_off;
+        p.u_off = u_off;
+        p.a_off = a_off;
+        p.b_off = b_off;
+        p.c_off = c_off;
+        p.w_off = w_off;
+        p.rhs0 = rhs0;
+        p.cols_i.assign(cells[i].cols_i, cells[i].cols_i + 2 * p.n_i);
+        p.cols_b.assign(cells[i].cols_b, cells[i].cols_b + 2 * p.n_b);
+        f_off += (int64_t)p.R * p.nz * p.K;
+        u_off += (int64_t)p.R * p.nz * p.M;
+        a_off += store_mode_elems(form, p) * p.nm;
+        b_off += b_mode_elems(form, p) * p.nm;
+        c_off += (int64_t)p.nm * p.ct * p.mp * 16;
+        w_off += (int64_t)p.R * p.M * p.nz;
+        rhs0 += p.R;
+        c->ctmax = std::max(c->ctmax, p.ct);
+        c->cells.push_back(p);
+    }
+    c->total_rhs = rhs0;
+    c->f_elems = f_off;
+    c->u_elems = u_off;
+    fbc_status s;
+    c->store_bytes = a_off * store_elem_bytes(form);
+    if ((s = dev_alloc(c, &c->store, c->store_bytes)) != FBC_OK) goto fail_out;
+    if ((s = dev_alloc(c, &c->bfrag, b_off * b_elem_bytes(form))) != FBC_OK) goto fail_out;
+    if ((s = dev_alloc(c, (void**)&c->cbuf, c_off * 8)) != FBC_OK) goto fail_out;
+    if ((s = dev_alloc(c, (void**)&c->wbuf, w_off * 8)) != FBC_OK) goto fail_out;
+    if ((s = dev_alloc(c, (void**)&c->status, 64)) != FBC_OK) goto fail_out;
+    c->scratch_bytes = b_off * b_elem_bytes(form) + c_off * 8 + w_off * 8;
+    {
+        // per-cell small buffers
+        int64_t sums_n = 0, wmax_n = 0, sp_n = 0, rp_n = 0;
+        for (auto& p : c->cells) {
+            sums_n += (int64_t)p.R * p.nz * 3;
+            int tr = (4 * p.nz <= 4096) ? std::min(64, 4096 / (4 * p.nz)) : 1;
+            const int np_ir = (p.M + tr - 1) / tr;
+            const int np_ax = ((p.M + 31) / 32) * ((p.nz + 31) / 32);
+            c->wmax_off.push_back(wmax_n);
+            c->sum_part_off.push_back(sp_n);
+            c->rpart_off.push_back(rp_n);
+            c->npart_irfft.push_back(np_ir);
+            c->npart_axpy.push_back(np_ax);
+            wmax_n += (int64_t)p.R * np_ir;
+            sp_n += (int64_t)p.R * np_ax * 3;
+            rp_n += (int64_t)p.R * 64 * 3;
+        }
+        if ((s = dev_alloc(c, (void**)&c->sums, sums_n * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->wmax_part, wmax_n * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->sum_part, sp_n * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->rpart, rp_n * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->mean, (int64_t)c->total_rhs * 3 * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->rmean, (int64_t)c->total_rhs * 3 * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->alpha, (int64_t)c->total_rhs * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->finf, (int64_t)c->total_rhs * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->stepinf, (int64_t)c->total_rhs * 8)) != FBC_OK) goto fail_out;
+        c->scratch_bytes += (sums_n + wmax_n + sp_n + rp_n + 5LL * c->total_rhs) * 8;
+    }
+    // line twiddles, per distinct nz
+    {
+        std::map<int, int64_t> off;
+        std::vector<double2> all, t;
+        for (auto& p : c->cells) {
+            if (!off.count(p.nz)) {
+                off[p.nz] = (int64_t)all.size();
+                twiddles(p.nz, t);
+                all.insert(all.end(), t.begin(), t.end());
+            }
+            p.tw_off = off[p.nz];
+            p.tw_n = p.nz;
+        }
+        if ((s = dev_alloc(c, (void**)&c->tw, (int64_t)all.size() * 16)) != FBC_OK) goto fail_out;
+        HIPCHK(c, hipMemcpyAsync(c->tw, all.data(), all.size() * 16, hipMemcpyHostToDevice, st));
+    }
+    for (auto& p : c->cells) {
+        if ((s = dev_alloc(c, (void**)&p.cols_i_d, (int64_t)p.n_i * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&p.cols_b_d, (int64_t)p.n_b * 8)) != FBC_OK) goto fail_out;
+        HIPCHK(c, hipMemcpyAsync(p.cols_i_d, p.cols_i.data(), (size_t)p.n_i * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(p.cols_b_d, p.cols_b.data(), (size_t)p.n_b * 8, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(c, hipMemsetAsync(c->bfrag, 0, (size_t)(b_off * b_elem_bytes(form)), st));
+    HIPCHK(c, hipMemsetAsync(c->status, 0, 64, st));
+    {
+        // sin(pi p / L) table, L = max over every line length and the torus sizes
+        int L = std::max(opt->bz_m1, opt->bz_m2);
+        for (auto& p : c->cells) L = std::max(L, p.nz);
+        const int logL = ilog2(L);
+        std::vector<double> sn(L);
+        for (int q = 0; q < L; ++q)
+            sn[q] = (double)sinl(3.14159265358979323846264338327950288L * q / L);
+        double* sn_d = nullptr;
+        if (hipMalloc((void**)&sn_d, (size_t)L * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            s = fail(c, FBC_E_NOMEM, "sin table");
+            goto fail_out;
+        }
+        (void)hipMemcpyAsync(sn_d, sn.data(), (size_t)L * 8, hipMemcpyHostToDevice, st);
+        const BondTable bt = make_bonds(lat->spring_k);
+        for (auto& p : c->cells) {
+            s = assemble_cell(c, p, st, bt, sn_d, logL);
+            if (s != FBC_OK) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(sn_d);
+                goto fail_out;
+            }
+        }
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(sn_d);
+    }
+    {
+        std::vector<GemmJob> jobs = build_jobs(c);
+        c->njobs = (int)jobs.size();
+        if ((s = dev_alloc(c, (void**)&c->jobs, (int64_t)jobs.size() * sizeof(GemmJob))) != FBC_OK) goto fail_out;
+        HIPCHK(c, hipMemcpyAsync(c->jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st));
+    }
+    if ((s = dev_alloc(c, (void**)&c->fprev, c->f_elems * 8)) != FBC_OK) goto fail_out;
+    HIPCHK(c, hipStreamSynchronize(st));
+    HIPCHK(c, hipGetLastError());
+    *out = c;
+    return FBC_OK;
+fail_out:
+    g_err = c->err;
+    (void)hipStreamSynchronize(st);
+    free_all(c);
+    delete c;
+    return s;
+}
+
+// ----------------------------------------------------------------------------------
+// Apply pipeline: net force -> line rFFT -> per-mode products -> inverse rFFT.
+// ----------------------------------------------------------------------------------
+static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
+    const int form = c->opt.form;
+    int64_t sums_off = 0;
+    for (auto& p : c->cells) {
+        const double* fc = f + p.f_off;
+        double* sums = c->sums + sums_off;
+        if (c->opt.check_netforce || c->opt.project_netforce)
+            launch_netforce(st, fc, sums, p.R, p.nz, p.n_i, c->opt.netforce_tol, c->opt.check_netforce,
+                            c->opt.project_netforce, c->status);
+        void* bm = (char*)c->bfrag + p.b_off * b_elem_bytes(form);
+        launch_line_rfft(st, form, fc, sums, c->opt.project_netforce, bm, p.R, p.nz, p.n_i, p.kp,
+                         p.ct, c->tw + p.tw_off);
+        sums_off += (int64_t)p.R * p.nz * 3;
+    }
+    const bool tm = c->timing && c->n_timed < kMaxTimed;
+    if (tm) (void)hipEventRecord(c->ev[2 * c->n_timed], st);
+    launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf, nullptr, nullptr,
+                nullptr, nullptr, 0, 0, 0);
+    if (tm) {
+        (void)hipEventRecord(c->ev[2 * c->n_timed + 1], st);
+        ++c->n_timed;
+    }
+    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+        auto& p = c->cells[ci];
+        launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
+                          p.nz, p.mp, p.M, p.ct, c->tw + p.tw_off, nullptr);
+    }
+}
+
+static fbc_status check_apply_args(fbc_ctx* c, const void* f, const void* u) {
+    if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
+    if (!f || !u) return fail(c, FBC_E_ARG, "f and u must be device pointers");
+    if (((uintptr_t)f & 7) || ((uintptr_t)u & 7)) return fail(c, FBC_E_ARG, "f and u must be 8-byte aligned");
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_apply(fbc_ctx* c, const double* f, double* u, double alpha, void* stream) {
+    fbc_status s = check_apply_args(c, f, u);
+    if (s != FBC_OK) return s;
+    if (!std::isfinite(alpha)) return fail(c, FBC_E_ARG, "alpha must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    enqueue_forward(c, f, st);
+    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+        auto& p = c->cells[ci];
+        double* uc = u + p.u_off;
+        double* sp = c->sum_part + c->sum_part_off[ci];
+        launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr);
+        launch_mean(st, uc, sp, c->npart_axpy[ci], c->mean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
+    }
+    HIPCHK(c, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_green_apply(fbc_ctx* c, const double* f, double* w, void* stream) {
+    fbc_status s = check_apply_args(c, f, w);
+    if (s != FBC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    enqueue_forward(c, f, st);
+    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+        auto& p = c->cells[ci];
+        double* wc = w + p.u_off;
+        launch_fill(st, wc, (int64_t)p.R * p.nz * p.M, 0.0);
+        launch_axpy(st, c->wbuf + p.w_off, wc, c->sum_part + c->sum_part_off[ci], p.R, p.nz, p.M, -1.0,
+                    nullptr, c->status, nullptr);
+    }
+    HIPCHK(c, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_relax_begin(fbc_ctx* c, const fbc_relax_opts* o, void* stream) {
+    if (!c || !o) return fail(c, FBC_E_ARG, "null argument");
+    if (!(o->du_max >= 0) || !(o->tol_f >= 0)) return fail(c, FBC_E_ARG, "du_max and tol_f must be >= 0");
+    c->ropt = *o;
+    c->relax_k = 0;
+    launch_fill((hipStream_t)stream, c->alpha, c->total_rhs, 1.0);
+    HIPCHK(c, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, fbc_relax_out* out,
+                                     void* stream) {
+    fbc_status s = check_apply_args(c, f_in, u);
+    if (s != FBC_OK) return s;
+    if (c->relax_k < 0) return fail(c, FBC_E_STATE, "fbc_relax_begin was not called");
+    hipStream_t st = (hipStream_t)stream;
+    const int k = c->relax_k;
+    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+        auto& p = c->cells[ci];
+        const int64_t per_rhs = (int64_t)p.nz * p.K;
+        launch_relax_alpha(st, f_in + p.f_off, c->fprev + p.f_off, c->rpart + c->rpart_off[ci],
+                           c->alpha + p.rhs0, c->finf + p.rhs0, p.R, per_rhs, k, c->ropt.relax);
+    }
+    enqueue_forward(c, f_in, st);
+    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+        auto& p = c->cells[ci];
+        launch_relax_clamp(st, c->wmax_part + c->wmax_off[ci], c->npart_irfft[ci], c->alpha + p.rhs0,
+                           c->stepinf + p.rhs0, p.R, c->ropt.du_max, k, c->ropt.relax);
+        double* uc = u + p.u_off;
+        double* sp = c->sum_part + c->sum_part_off[ci];
+        launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, 0.0, c->alpha + p.rhs0, c->status,
+                    nullptr);
+        launch_mean(st, uc, sp, c->npart_axpy[ci], c->rmean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
+    }
+    launch_relax_finish(st, f_in, c->fprev, c->f_elems, c->alpha, c->finf, c->stepinf, c->rmean, out,
+                        c->total_rhs, k, c->ropt.tol_f);
+    c->relax_k = k + 1;
+    HIPCHK(c, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_sync_status(fbc_ctx* c, void* stream) {
+    if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    int st = 0;
+    HIPCHK(c, hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemset(c->status, 0, sizeof(int)));
+    if (st & ST_NONFINITE) return fail(c, FBC_E_NONFINITE, "non-finite interface force");
+    if (st & ST_NETFORCE) return fail(c, FBC_E_NETFORCE, "net force per layer exceeds tolerance");
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_get_info(const fbc_ctx* c, fbc_info* info) {
+    if (!c || !info) return FBC_E_ARG;
+    info->n_cells = (int)c->cells.size();
+    info->total_rhs = c->total_rhs;
+    info->store_bytes = c->store_bytes;
+    info->scratch_bytes = c->scratch_bytes;
+    info->f_elems = c->f_elems;
+    info->u_elems = c->u_elems;
+    info->n_offsets = c->n_offsets;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_copy_block_rows(fbc_ctx* c, int cell, int m, int b0, int b1, double* out) {
+    if (!c || !out) return fail(c, FBC_E_ARG, "null argument");
+    if (cell < 0 || cell >= (int)c->cells.size()) return fail(c, FBC_E_ARG, "cell out of range");
+    const CellPlan& p = c->cells[cell];
+    if (m < 0 || m >= p.nm || b0 < 0 || b1 > p.n_b || b0 >= b1) return fail(c, FBC_E_ARG, "range");
+    if (c->opt.form != FBC_FORM_FP64) return fail(c, FBC_E_UNSUPPORTED, "FP64 dense store only");
+    const int64_t per_mode = (int64_t)p.mp * p.kp;
+    std::vector<double> blk(per_mode);
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(blk.data(), (double*)c->store + p.a_off + m * per_mode, per_mode * 8,
+                        hipMemcpyDeviceToHost));
+    const int rows = 3 * (b1 - b0);
+    for (int r = 0; r < rows; ++r)
+        for (int k = 0; k < 6 * p.n_i; ++k)
+            out[(int64_t)r * 6 * p.n_i + k] = blk[frag_off_f64(3 * b0 + r, k, p.kp)];
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_timing(fbc_ctx* c, int enable) {
+    if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
+    if (enable && c->ev.empty()) {
+        c->ev.resize(2 * kMaxTimed);
+        for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    c->timing = enable ? 1 : 0;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_timing_read(fbc_ctx* c, double* ms, int* n) {
+    if (!c || !ms || !n) return fail(c, FBC_E_ARG, "null argument");
+    double tot = 0.0;
+    for (int i = 0; i < c->n_timed; ++i) {
+        HIPCHK(c, hipEventSynchronize(c->ev[2 * i + 1]));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev[2 * i], c->ev[2 * i + 1]));
+        tot += t;
+    }
+    *ms = tot;
+    *n = c->n_timed;
+    c->n_timed = 0;
+    return FBC_OK;
+}
+
+extern "C" void fbc_destroy(fbc_ctx* c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    free_all(c);
+    delete c;
+}

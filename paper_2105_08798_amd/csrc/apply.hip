@@ -1,0 +1,508 @@
+// Line transforms, update and reductions of the FBC pad update (Section 2.3.2,
+// eq. flexbc.up=Gpipl*fipl with eq. mean(u^p)=0; Algorithm 1 lines 7-8), and the
+// residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2).
+// All reductions use a fixed partition and a fixed-order tree, so results are bitwise
+// reproducible from run to run (no floating-point atomics).
+#include "fft_lds.h"
+#include "kernels.h"
+
+#define NT 256
+
+// Block-wide sum of `nv` doubles per thread (in place in v), fixed order.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* red) {
+    for (int c = 0; c < NV; ++c) red[c * NT + threadIdx.x] = v[c];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int c = 0; c < NV; ++c) red[c * NT + threadIdx.x] += red[c * NT + threadIdx.x + s];
+        __syncthreads();
+    }
+    for (int c = 0; c < NV; ++c) v[c] = red[c * NT];
+    __syncthreads();
+}
+template <int NV>
+__device__ inline void block_max(double (&v)[NV], double* red) {
+    for (int c = 0; c < NV; ++c) red[c * NT + threadIdx.x] = v[c];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int c = 0; c < NV; ++c)
+                red[c * NT + threadIdx.x] = fmax(red[c * NT + threadIdx.x], red[c * NT + threadIdx.x + s]);
+        __syncthreads();
+    }
+    for (int c = 0; c < NV; ++c) v[c] = red[c * NT];
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------------------------
+// Net force per layer and component, and the finiteness check of the forces.
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_netforce(const double* __restrict__ f,
+                                                 double* __restrict__ sums, int nz, int n_i,
+                                                 double tol, int check, int project,
+                                                 int* __restrict__ status) {
+    __shared__ double red[7 * NT];
+    const int n0 = blockIdx.x, r = blockIdx.y;
+    const double* row = f + ((int64_t)r * nz + n0) * n_i * 3;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < n_i; i += NT) {
+        for (int c = 0; c < 3; ++c) {
+            const double x = row[3 * i + c];
+            v[c] += x;
+            v[3 + c] += fabs(x);
+            if (!isfinite(x)) v[6] = 1.0;
+        }
+    }
+    block_sum<7>(v, red);
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) sums[((int64_t)r * nz + n0) * 3 + c] = v[c];
+        if (check) {
+            int bits = 0;
+            if (v[6] != 0.0 || !isfinite(v[3] + v[4] + v[5])) bits |= ST_NONFINITE;
+            else if (!project)
+                for (int c = 0; c < 3; ++c)
+                    if (fabs(v[c]) > tol * v[3 + c]) bits |= ST_NETFORCE;
+            if (bits) atomicOr(status, bits);
+        }
+    }
+}
+
+void launch_netforce(hipStream_t st, const double* f, double* sums, int R, int nz, int n_i,
+                     double tol, int check, int project, int* status) {
+    hipLaunchKernelGGL(k_netforce, dim3(nz, R), dim3(NT), 0, st, f, sums, nz, n_i, tol, check,
+                       project, status);
+}
+
+// ----------------------------------------------------------------------------------
+// rFFT along the line for every (RHS, column component), written straight into the
+// GEMM B operand in MFMA fragment order.  Two real columns are packed into one complex
+// sequence; F_a(m) = (Z(m) + conj Z(-m))/2, F_b(m) = (Z(m) - conj Z(-m))/(2i).
+// B columns per 8-RHS tile: n = 16 ct + j carries (Re f, -Im f) against A's (Re, Im)
+// rows -> real part of the product; n + 8 carries (Im f, Re f) -> imaginary part.
+// ----------------------------------------------------------------------------------
+__device__ inline unsigned short f2bf(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <int FORM>
+__device__ inline void put_b(void* bm, int n, int kq, int kp, double v) {
+    if (FORM == FBC_FORM_FP64 || FORM == FBC_FORM_DTABLE_FP64) {
+        ((double*)bm)[frag_off_f64(n, kq, kp)] = v;
+    } else if (FORM == FBC_FORM_FP32) {
+        ((float*)bm)[frag_off_f32(n, kq, kp)] = (float)v;
+    } else {
+        const unsigned short hi = f2bf((float)v);
+        const unsigned short lo = f2bf((float)(v - (double)bf2f(hi)));
+        unsigned short* p = (unsigned short*)bm + frag_off_bf16(n, kq, kp);
+        p[0] = hi;
+        p[512] = lo;
+    }
+}
+
+template <int FORM>
+__global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
+                                                  const double* __restrict__ sums, int project,
+                                                  void* __restrict__ bfrag, int nz, int logn,
+                                                  int n_i, int kp, int ct, int tc,
+                                                  const double2* __restrict__ tw, double inv_ni) {
+    extern __shared__ double2 lds[];
+    const int r = blockIdx.y;
+    const int k0 = blockIdx.x * tc;
+    const int K = 3 * n_i;
+    const int nseq = tc >> 1;
+    double* ldsd = (double*)lds;
+    for (int t = threadIdx.x; t < nz * tc; t += NT) {
+        const int n0 = t / tc, c = t - n0 * tc, k = k0 + c;
+        double v = 0.0;
+        if (k < K) {
+            v = f[((int64_t)r * nz + n0) * K + k];
+            if (project) v -= sums[((int64_t)r * nz + n0) * 3 + (k % 3)] * inv_ni;
+        }
+        ldsd[2 * ((c >> 1) * nz + (int)bitrev(n0, logn)) + (c & 1)] = v;
+    }
+    __syncthreads();
+    lds_fft(lds, nseq, logn, tw, false);
+    const int nm = (nz >> 1) + 1;
+    // per mode: B elements of one mode occupy 16*ct*kp values (x2 for the bf16 split)
+    const int64_t mode_elems = (int64_t)16 * ct * kp * (FORM == FBC_FORM_SPLIT_BF16 ? 2 : 1);
+    const int tile = r >> 3, j = r & 7;
+    const int nre = 16 * tile + j, nim = nre + 8;
+    for (int t = threadIdx.x; t < nm * tc; t += NT) {
+        const int m = t / tc, c = t - m * tc, k = k0 + c;
+        if (k >= K) continue;
+        const double2 z = lds[(c >> 1) * nz + m];
+        const double2 zn = lds[(c >> 1) * nz + ((nz - m) & (nz - 1))];
+        double fr, fi;
+        if ((c & 1) == 0) {
+            fr = 0.5 * (z.x + zn.x);
+            fi = 0.5 * (z.y - zn.y);
+        } else {
+            fr = 0.5 * (z.y + zn.y);
+            fi = 0.5 * (zn.x - z.x);
+        }
+        if (m == 0 || 2 * m == nz) fi = 0.0;
+        void* bm;
+        if (FORM == FBC_FORM_FP64 || FORM == FBC_FORM_DTABLE_FP64)
+            bm = (double*)bfrag + m * mode_elems;
+        else if (FORM == FBC_FORM_FP32)
+            bm = (float*)bfrag + m * mode_elems;
+        else
+            bm = (unsigned short*)bfrag + m * mode_elems;
+        put_b<FORM>(bm, nre, 2 * k, kp, fr);
+        put_b<FORM>(bm, nre, 2 * k + 1, kp, -fi);
+        put_b<FORM>(bm, nim, 2 * k, kp, fi);
+        put_b<FORM>(bm, nim, 2 * k + 1, kp, fr);
+    }
+}
+
+void launch_line_rfft(hipStream_t st, int form, const double* f, const double* sums, int project,
+                      void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw) {
+    int logn = 0;
+    while ((1 << logn) < nz) ++logn;
+    const int K = 3 * n_i;
+    int tc = 8192 / nz;                  // nz * tc doubles = 64 KiB of LDS
+    if (tc > 256) tc = 256;
+    if (tc < 2) tc = 2;
+    const int kk = (K + 1) & ~1;
+    if (tc > kk) tc = kk;
+    tc &= ~1;
+    dim3 grid((K + tc - 1) / tc, R);
+    const size_t lds = (size_t)nz * tc * sizeof(double);
+    const double inv_ni = 1.0 / n_i;
+    switch (form) {
+        case FBC_FORM_FP32:
+            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP32>, grid, dim3(NT), lds, st, f, sums, project,
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_ni);
+            break;
+        case FBC_FORM_SPLIT_BF16:
+            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_BF16>, grid, dim3(NT), lds, st, f, sums,
+                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_ni);
+            break;
+        default:
+            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP64>, grid, dim3(NT), lds, st, f, sums, project,
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_ni);
+            break;
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// Inverse rFFT along the line of the per-mode products, two RHS per complex sequence
+// (Z = U_a + i U_b; U(-m) = conj U(m); the imaginary parts of modes 0 and Nz/2 are
+// dropped as a real inverse transform does).  Output w[r][row][n0] scaled by 1/Nz, and
+// per block and RHS the maximum |w| (for the step bound of Algorithm 2).
+// Input layout c[m][ct][mp][16]: columns 0..7 real parts, 8..15 imaginary parts.
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
+                                                   double* __restrict__ w,
+                                                   double* __restrict__ wmax_part, int R, int nz,
+                                                   int logn, int mp, int M, int ct, int tr, int pp,
+                                                   const double2* __restrict__ tw) {
+    extern __shared__ double2 lds[];
+    const int row0 = blockIdx.x * tr;
+    const int tile = blockIdx.y;
+    const int pair0 = blockIdx.z * pp;          // first RHS pair inside the 8-RHS tile
+    const int nseq = tr * pp;
+    const int nm = (nz >> 1) + 1;
+    const int64_t mode_stride = (int64_t)ct * mp * 16;
+    for (int t = threadIdx.x; t < nseq * nz; t += NT) {
+        const int s = t / nz, m = t - s * nz;
+        const int trr = s / pp, pj = s - trr * pp;
+        const int row = row0 + trr;
+        const int ja = 2 * (pair0 + pj);
+        double2 z = make_double2(0, 0);
+        if (row < M) {
+            const int mm = (m < nm) ? m : nz - m;
+            const double* src = c + mm * mode_stride + ((int64_t)tile * mp + row) * 16;
+            double ar = src[ja], ai = src[ja + 8], br = src[ja + 1], bi = src[ja + 9];
+            if (mm == 0 || 2 * mm == nz) { ai = 0.0; bi = 0.0; }
+            if (m >= nm) { ai = -ai; bi = -bi; }
+            z = make_double2(ar - bi, ai + br);     // U_a + i U_b
+        }
+        lds[s * nz + bitrev(m, logn)] = z;
+    }
+    __syncthreads();
+    lds_fft(lds, nseq, logn, tw, true);
+    const double scale = 1.0 / nz;
+    double mx[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // per RHS inside the tile
+    for (int t = threadIdx.x; t < nseq * nz; t += NT) {
+        const int s = t / nz, n0 = t - s * nz;
+        const int trr = s / pp, pj = s - trr * pp;
+        const int row = row0 + trr;
+        const int ja = 2 * (pair0 + pj);
+        const int ra = 8 * tile + ja;
+        if (row >= M) continue;
+        const double2 z = lds[s * nz + n0];
+        const double wa = z.x * scale, wb = z.y * scale;
+        if (ra < R) w[((int64_t)ra * M + row) * nz + n0] = wa;
+        if (ra + 1 < R) w[((int64_t)(ra + 1) * M + row) * nz + n0] = wb;
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+            if (q == ja) {
+                mx[q] = fmax(mx[q], fabs(wa));
+                mx[q + 1] = fmax(mx[q + 1], fabs(wb));
+            }
+        }
+    }
+    __syncthreads();
+    block_max<8>(mx, (double*)lds);      // the FFT buffer is free again
+    if (threadIdx.x < 8) {
+        const int rr = 8 * tile + threadIdx.x;
+        const int jj = threadIdx.x;
+        // each RHS is covered by exactly one pair group (blockIdx.z)
+        if (rr < R && jj >= 2 * pair0 && jj < 2 * (pair0 + pp))
+            wmax_part[(int64_t)rr * gridDim.x + blockIdx.x] = mx[jj];
+    }
+}
+
+void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
+                       int nz, int mp, int M, int ct, const double2* tw, int* n_part_out) {
+    int logn = 0;
+    while ((1 << logn) < nz) ++logn;
+    int pp, tr;
+    if (4 * nz <= 4096) {
+        pp = 4;
+        tr = 4096 / (4 * nz);
+        if (tr > 64) tr = 64;
+    } else {
+        pp = 4096 / nz;
+        tr = 1;
+    }
+    dim3 grid((M + tr - 1) / tr, ct, 4 / pp);
+    size_t lds = (size_t)tr * pp * nz * sizeof(double2);
+    if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
+    hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,
+                       ct, tr, pp, tw);
+    if (n_part_out) *n_part_out = (int)grid.x;
+}
+
+// ----------------------------------------------------------------------------------
+// u[r][n0][row] -= alpha_r * w[r][row][n0] (tiled transpose through LDS), with per
+// block partial sums of the updated u per Cartesian component (row % 3).
+// Skipped entirely when a data check has latched an error.
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, double* __restrict__ u,
+                                             double* __restrict__ sum_part, int nz, int M,
+                                             double alpha, const double* __restrict__ alpha_d,
+                                             const int* __restrict__ status) {
+    __shared__ double tile[32][33];
+    __shared__ double red[3 * NT];
+    if (status && *status) return;
+    const int r = blockIdx.z;
+    const int row0 = blockIdx.x * 32, n00 = blockIdx.y * 32;
+    const double a = alpha_d ? alpha_d[r] : alpha;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const double* wr = w + (int64_t)r * M * nz;
+    for (int y = ty; y < 32; y += 8) {
+        const int row = row0 + y, n0 = n00 + tx;
+        if (row < M && n0 < nz) tile[y][tx] = wr[(int64_t)row * nz + n0];
+    }
+    __syncthreads();
+    double v[3] = {0, 0, 0};
+    double* ur = u + (int64_t)r * nz * M;
+    for (int y = ty; y < 32; y += 8) {
+        const int n0 = n00 + y, row = row0 + tx;
+        if (row < M && n0 < nz) {
+            const int64_t idx = (int64_t)n0 * M + row;
+            const double x = ur[idx] - a * tile[tx][y];
+            ur[idx] = x;
+            v[row % 3] += x;
+        }
+    }
+    block_sum<3>(v, red);
+    if (threadIdx.x == 0) {
+        const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        for (int c = 0; c < 3; ++c) sum_part[((int64_t)r * nb + b) * 3 + c] = v[c];
+    }
+}
+
+void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
+                 int M, double alpha, const double* alpha_d, const int* status, int* n_part_out) {
+    dim3 grid((M + 31) / 32, (nz + 31) / 32, R);
+    hipLaunchKernelGGL(k_axpy, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d,
+                       status);
+    if (n_part_out) *n_part_out = (int)(grid.x * grid.y);
+}
+
+// Mean over all pad atoms and layers per RHS and component, then subtraction.
+__global__ void __launch_bounds__(NT) k_mean_reduce(const double* __restrict__ part, int n_part,
+                                                    double* __restrict__ mean_out, double inv_n,
+                                                    const int* __restrict__ status) {
+    __shared__ double red[3 * NT];
+    if (status && *status) return;
+    const int r = blockIdx.x;
+    double v[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < n_part; b += NT)
+        for (int c = 0; c < 3; ++c) v[c] += part[((int64_t)r * n_part + b) * 3 + c];
+    block_sum<3>(v, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) mean_out[r * 3 + c] = v[c] * inv_n;
+}
+
+__global__ void __launch_bounds__(NT) k_mean_sub(double* __restrict__ u,
+                                                 const double* __restrict__ mean, int64_t per_rhs,
+                                                 int R, const int* __restrict__ status) {
+    if (status && *status) return;
+    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (idx >= per_rhs * R) return;
+    const int r = (int)(idx / per_rhs);
+    const int64_t e = idx - (int64_t)r * per_rhs;
+    u[idx] -= mean[r * 3 + (int)(e % 3)];
+}
+
+void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, double* mean_out,
+                 int R, int nz, int M, const int* status) {
+    const double inv_n = 1.0 / ((double)nz * (M / 3));
+    hipLaunchKernelGGL(k_mean_reduce, dim3(R), dim3(NT), 0, st, sum_part, n_part, mean_out, inv_n,
+                       status);
+    const int64_t per_rhs = (int64_t)nz * M;
+    const int64_t total = per_rhs * R;
+    hipLaunchKernelGGL(k_mean_sub, dim3((unsigned)((total + NT - 1) / NT)), dim3(NT), 0, st, u,
+                       mean_out, per_rhs, R, status);
+}
+
+// ----------------------------------------------------------------------------------
+// Relax (Algorithm 2) on raw residuals, per RHS.  Stage 1: block partials of
+// <f_k, f_{k+1} - f_k>, ||f_{k+1} - f_k||^2 and ||f_{k+1}||_inf.  Stage 2: one block per
+// RHS reduces them in fixed order and sets alpha_{k+1} (alpha = 1 before the third
+// iteration or without relaxation; alpha < 0 -> 1; zero denominator keeps alpha_k).
+// ----------------------------------------------------------------------------------
+#define RELAX_PARTS 64
+__global__ void __launch_bounds__(NT) k_relax_part(const double* __restrict__ fnew,
+                                                   const double* __restrict__ fprev,
+                                                   double* __restrict__ part, int64_t per_rhs,
+                                                   int use_prev) {
+    __shared__ double red[3 * NT];
+    const int r = blockIdx.y;
+    const double* a = fnew + (int64_t)r * per_rhs;
+    const double* b = fprev + (int64_t)r * per_rhs;
+    double v[2] = {0, 0};
+    double mx[1] = {0};
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < per_rhs;
+         e += (int64_t)NT * gridDim.x) {
+        const double x = a[e];
+        mx[0] = fmax(mx[0], fabs(x));
+        if (use_prev) {
+            const double y = b[e];
+            const double d = x - y;
+            v[0] += y * d;
+            v[1] += d * d;
+        }
+    }
+    block_sum<2>(v, red);
+    block_max<1>(mx, red);
+    if (threadIdx.x == 0) {
+        double* p = part + ((int64_t)r * gridDim.x + blockIdx.x) * 3;
+        p[0] = v[0];
+        p[1] = v[1];
+        p[2] = mx[0];
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_relax_alpha(const double* __restrict__ part, int n_part,
+                                                    double* __restrict__ alpha_d,
+                                                    double* __restrict__ finf_d, int use_relax) {
+    __shared__ double red[2 * NT];
+    const int r = blockIdx.x;
+    double v[2] = {0, 0};
+    double mx[1] = {0};
+    for (int b = threadIdx.x; b < n_part; b += NT) {
+        v[0] += part[((int64_t)r * n_part + b) * 3 + 0];
+        v[1] += part[((int64_t)r * n_part + b) * 3 + 1];
+        mx[0] = fmax(mx[0], part[((int64_t)r * n_part + b) * 3 + 2]);
+    }
+    block_sum<2>(v, red);
+    block_max<1>(mx, red);
+    if (threadIdx.x == 0) {
+        finf_d[r] = mx[0];
+        double a = 1.0;
+        if (use_relax) {
+            const double prev = alpha_d[r];
+            a = prev;
+            if (v[1] > 0.0) a = -prev * v[0] / v[1];
+            if (a < 0.0) a = 1.0;
+        }
+        alpha_d[r] = a;
+    }
+}
+
+void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
+                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, int k,
+                        int relax) {
+    const int use = (relax && k >= 2) ? 1 : 0;
+    hipLaunchKernelGGL(k_relax_part, dim3(RELAX_PARTS, R), dim3(NT), 0, st, fnew, fprev, part,
+                       per_rhs, use);
+    hipLaunchKernelGGL(k_relax_alpha, dim3(R), dim3(NT), 0, st, part, RELAX_PARTS, alpha_d, finf_d,
+                       use);
+}
+
+// Step bound (Algorithm 2 lines 6-8) from the per-block maxima of |w|.
+__global__ void __launch_bounds__(NT) k_relax_clamp(const double* __restrict__ wmax_part,
+                                                    int n_part, double* __restrict__ alpha_d,
+                                                    double* __restrict__ stepinf_d, double du_max,
+                                                    int use_bound) {
+    __shared__ double red[NT];
+    const int r = blockIdx.x;
+    double mx[1] = {0};
+    for (int b = threadIdx.x; b < n_part; b += NT)
+        mx[0] = fmax(mx[0], wmax_part[(int64_t)r * n_part + b]);
+    block_max<1>(mx, red);
+    if (threadIdx.x == 0) {
+        double a = alpha_d[r];
+        if (use_bound && du_max > 0.0 && a * mx[0] > du_max) a = du_max / mx[0];
+        alpha_d[r] = a;
+        stepinf_d[r] = a * mx[0];
+    }
+}
+
+void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, double* alpha_d,
+                        double* stepinf_d, int R, double du_max, int k, int relax) {
+    const int use = (relax && k >= 2) ? 1 : 0;
+    hipLaunchKernelGGL(k_relax_clamp, dim3(R), dim3(NT), 0, st, wmax_part, n_part, alpha_d,
+                       stepinf_d, du_max, use);
+}
+
+__global__ void __launch_bounds__(NT) k_copy(const double* __restrict__ a, double* __restrict__ b,
+                                             int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ void k_relax_out(const double* __restrict__ alpha_d, const double* __restrict__ finf_d,
+                            const double* __restrict__ stepinf_d, const double* __restrict__ mean_d,
+                            fbc_relax_out* __restrict__ out, int R, int k, double tol_f) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    fbc_relax_out o;
+    o.alpha = alpha_d[r];
+    o.f_inf = finf_d[r];
+    o.step_inf = stepinf_d[r];
+    for (int c = 0; c < 3; ++c) o.mean_removed[c] = mean_d[r * 3 + c];
+    o.converged = finf_d[r] < tol_f ? 1 : 0;
+    o.k = k;
+    out[r] = o;
+}
+
+void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,
+                         const double* alpha_d, const double* finf_d, const double* stepinf_d,
+                         const double* mean_d, fbc_relax_out* out, int R, int k, double tol_f) {
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, fnew, fprev,
+                       n);
+    if (out)
+        hipLaunchKernelGGL(k_relax_out, dim3((R + 63) / 64), dim3(64), 0, st, alpha_d, finf_d,
+                           stepinf_d, mean_d, out, R, k, tol_f);
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_fill(hipStream_t st, double* p, int64_t n, double v) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, p, n, v);
+}

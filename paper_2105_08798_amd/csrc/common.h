@@ -1,0 +1,87 @@
+// Shared definitions of the FBC library (host plan + device kernels), gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/fbc.h"
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------------
+// MFMA fragment orders.  A real matrix X[rows][K'] (or the GEMM B operand, indexed
+// [col][K'] the same way) is stored as 16-row blocks; inside a block the 64 lanes of a
+// wave hold one MFMA operand each, so a wave-wide 16-byte load is 1 KiB contiguous.
+//   FP64 16x16x4 : lane l holds X[16 blk + l%16][4 t + l/16]; two k-steps per 16 B.
+//   FP32 16x16x4 : same lane map; four k-steps per 16 B.
+//   BF16 16x16x32: lane l holds X[16 blk + l%16][32 t + 8 (l/16) + j], j = 0..7;
+//                  hi and lo halves of the split are stored as consecutive 1 KiB runs.
+// Output of the 16x16 MFMAs: FP64 c[j] = C[4 j + l/16][l%16];
+//                            FP32 c[j] = C[4 (l/16) + j][l%16].
+// K' is padded to a multiple of 32 for every form (zeros).
+// ---------------------------------------------------------------------------------
+__host__ __device__ inline int64_t frag_off_f64(int64_t r, int64_t k, int64_t kp) {
+    int64_t blk = r >> 4, rr = r & 15;
+    int64_t lane = ((k & 3) << 4) | rr;
+    return (((blk * (kp >> 3) + (k >> 3)) * 64 + lane) << 1) + ((k >> 2) & 1);
+}
+__host__ __device__ inline int64_t frag_off_f32(int64_t r, int64_t k, int64_t kp) {
+    int64_t blk = r >> 4, rr = r & 15;
+    int64_t lane = ((k & 3) << 4) | rr;
+    return (((blk * (kp >> 4) + (k >> 4)) * 64 + lane) << 2) + ((k >> 2) & 3);
+}
+// element offset (in bf16 units) of the hi part; the lo part is at +512
+__host__ __device__ inline int64_t frag_off_bf16(int64_t r, int64_t k, int64_t kp) {
+    int64_t blk = r >> 4, rr = r & 15;
+    int64_t kk = k & 31;
+    int64_t lane = ((kk >> 3) << 4) | rr;
+    return ((((blk * (kp >> 5) + (k >> 5)) * 2) * 64 + lane) << 3) + (kk & 7);
+}
+
+// Symmetric 3x3 component index: xx yy zz xy xz yz
+__host__ __device__ inline int sym_idx(int c, int d) {
+    if (c == d) return c;
+    int lo = c < d ? c : d, hi = c < d ? d : c;
+    return (lo == 0) ? (hi == 1 ? 3 : 4) : 5;
+}
+
+// One work item of the per-mode complex product: a tile of up to 4*RB row blocks of
+// one mode of one cell.  Offsets are in elements of the respective arrays.
+struct GemmJob {
+    int64_t a_off;   // A store (dense forms) or table mode base (offset form)
+    int64_t b_off;   // B fragments of this mode
+    int64_t c_off;   // output [ct][mp][16] doubles of this mode
+    int32_t mb;      // row blocks of the mode (mp / 16)
+    int32_t kp;      // padded K' (multiple of 32)
+    int32_t rb0;     // first row block of this tile
+    int32_t ct;      // column tiles (8 RHS each)
+    int32_t cell;    // cell index (offset form)
+    int32_t pad;
+};
+
+// Device-side status latch bits
+enum { ST_NETFORCE = 1, ST_NONFINITE = 2 };
+
+struct CellPlan {
+    int nz, nm, n_i, n_b, R;
+    int K, M;            // complex K = 3 n_i, rows M = 3 n_b
+    int kp;              // padded real K' = roundup(6 n_i, 32)
+    int mp;              // padded rows = roundup(3 n_b, 16)
+    int ct;              // column tiles = ceil(R / 8)
+    int64_t f_off, u_off;        // offsets (doubles) into caller's f and u
+    int64_t a_off;               // dense store offset (elements of the store type) of mode 0
+    int64_t b_off;               // B fragments offset (elements) of mode 0
+    int64_t c_off;               // GEMM output offset (doubles) of mode 0
+    int64_t w_off;               // w scratch offset (doubles)
+    int64_t t_off;               // f transpose scratch offset (doubles)
+    int64_t red_off;             // reduction scratch offset (doubles)
+    int rhs0;                    // first global RHS index
+    int tw_n;                    // line length of the twiddle table used (== nz)
+    int64_t tw_off;              // twiddle table offset (double2) for nz
+    int32_t *cols_i_d, *cols_b_d;
+    std::vector<int32_t> cols_i, cols_b;
+};

@@ -1,0 +1,53 @@
+// Kernel launch wrappers of the FBC library (all enqueue on `st`, no synchronisation).
+#pragma once
+#include "common.h"
+
+struct BondTable {
+    int n[12][3];        // primitive-basis offsets of the 12 nearest-neighbour bonds
+    double p[12][6];     // k * Rhat Rhat^T in symmetric order xx yy zz xy xz yz
+};
+
+// ---- assembly (Appendix B, discrete Brillouin-zone sum) ----
+void launch_dinv(hipStream_t st, double2* pk, int m0, int nmc, int nz, int m1, int m2,
+                 int logL, const double* sn, const BondTable& bt);
+void launch_fft_rows(hipStream_t st, double2* data, int64_t nrows, int logn, const double2* tw,
+                     bool inverse);
+void launch_transpose_c(hipStream_t st, const double2* in, double2* out, int batches, int rows,
+                        int cols);
+void launch_gather_table(hipStream_t st, const double2* t, double2* tab, int nmc, int m1, int m2,
+                         int64_t n_off, const int32_t* off_d1, const int32_t* off_d2,
+                         int64_t tab_mode_stride, double scale);
+void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm, int64_t n_off,
+                    int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
+                    const int32_t* lut, int d1min, int d2min, int w2);
+void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
+                        const double2* rowmean, int nm, int64_t n_off, int mp, int kp, int n_b,
+                        int n_i, const int32_t* cols_b, const int32_t* cols_i, const int32_t* lut,
+                        int d1min, int d2min, int w2);
+
+// ---- apply (Section 2.3.2 update in line-mode form) ----
+void launch_netforce(hipStream_t st, const double* f, double* sums, int R, int nz, int n_i,
+                     double tol, int check, int project, int* status);
+void launch_line_rfft(hipStream_t st, int form, const double* f, const double* sums, int project,
+                      void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw);
+void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
+                 const void* a, const void* b, double* c, const double2* tab,
+                 const int32_t* const* cols_b, const int32_t* const* cols_i, const int32_t* lut,
+                 int d1min, int d2min, int w2);
+void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
+                       int nz, int mp, int M, int ct, const double2* tw, int* n_part_out);
+void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
+                 int M, double alpha, const double* alpha_d, const int* status,
+                 int* n_part_out);
+void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, double* mean_out,
+                 int R, int nz, int M, const int* status);
+
+// ---- relax (Section 2.3.3, Algorithm 2) ----
+void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
+                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, int k, int relax);
+void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, double* alpha_d,
+                        double* stepinf_d, int R, double du_max, int k, int relax);
+void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,
+                         const double* alpha_d, const double* finf_d, const double* stepinf_d,
+                         const double* mean_d, fbc_relax_out* out, int R, int k, double tol_f);
+void launch_fill(hipStream_t st, double* p, int64_t n, double v);

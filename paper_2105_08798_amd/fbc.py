@@ -1,0 +1,220 @@
+"""Thin ctypes binding of libfbc.so (argument marshalling only).
+
+Every step of the FBC update runs in the HIP library; this module converts Python
+arguments to the C structs of include/fbc.h and passes device pointers of torch
+tensors and the current HIP stream.  It raises if the built library is missing: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfbc.so")
+
+FBC_OK = 0
+STATUS = {0: "FBC_OK", -1: "FBC_E_ARG", -2: "FBC_E_NOMEM", -3: "FBC_E_NETFORCE",
+          -4: "FBC_E_NONFINITE", -5: "FBC_E_DEVICE", -6: "FBC_E_STATE", -7: "FBC_E_UNSUPPORTED"}
+FORMS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "dtable_fp64": 3}
+
+EXPORTED = [
+    "fbc_default_options", "fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin",
+    "fbc_relax_step", "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_destroy",
+    "fbc_last_error", "fbc_status_string", "fbc_timing", "fbc_timing_read",
+]
+
+
+class FbcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Lattice(C.Structure):
+    _fields_ = [("a", C.c_double), ("spring_k", C.c_double)]
+
+
+class Cell(C.Structure):
+    _fields_ = [("nz", C.c_int), ("n_i", C.c_int), ("n_b", C.c_int), ("n_rhs", C.c_int),
+                ("cols_i", C.POINTER(C.c_int32)), ("cols_b", C.POINTER(C.c_int32))]
+
+
+class Options(C.Structure):
+    _fields_ = [("form", C.c_int), ("bz_m1", C.c_int), ("bz_m2", C.c_int),
+                ("check_netforce", C.c_int), ("project_netforce", C.c_int),
+                ("netforce_tol", C.c_double), ("row_gauge", C.c_int)]
+
+
+class RelaxOpts(C.Structure):
+    _fields_ = [("relax", C.c_int), ("du_max", C.c_double), ("tol_f", C.c_double)]
+
+
+class RelaxOut(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("f_inf", C.c_double), ("step_inf", C.c_double),
+                ("mean_removed", C.c_double * 3), ("converged", C.c_int32), ("k", C.c_int32)]
+
+
+RELAX_OUT_DOUBLES = C.sizeof(RelaxOut) // 8
+
+
+class Info(C.Structure):
+    _fields_ = [("n_cells", C.c_int), ("total_rhs", C.c_int), ("store_bytes", C.c_int64),
+                ("scratch_bytes", C.c_int64), ("f_elems", C.c_int64), ("u_elems", C.c_int64),
+                ("n_offsets", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    vp, cp = C.c_void_p, C.c_char_p
+    lib.fbc_default_options.argtypes = [C.POINTER(Options)]
+    lib.fbc_default_options.restype = None
+    lib.fbc_assemble_G.argtypes = [C.POINTER(Lattice), C.POINTER(Cell), C.c_int, C.POINTER(Options),
+                                   vp, C.POINTER(vp)]
+    lib.fbc_apply.argtypes = [vp, vp, vp, C.c_double, vp]
+    lib.fbc_green_apply.argtypes = [vp, vp, vp, vp]
+    lib.fbc_relax_begin.argtypes = [vp, C.POINTER(RelaxOpts), vp]
+    lib.fbc_relax_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.fbc_sync_status.argtypes = [vp, vp]
+    lib.fbc_get_info.argtypes = [vp, C.POINTER(Info)]
+    lib.fbc_copy_block_rows.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
+    lib.fbc_timing.argtypes = [vp, C.c_int]
+    lib.fbc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.fbc_destroy.argtypes = [vp]
+    lib.fbc_destroy.restype = None
+    lib.fbc_last_error.argtypes = [vp]
+    lib.fbc_last_error.restype = cp
+    lib.fbc_status_string.argtypes = [C.c_int]
+    lib.fbc_status_string.restype = cp
+    for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
+                 "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+class FBC:
+    """One assembled context (cells, Green store, scratch) on the current device."""
+
+    def __init__(self, cells, bz: int | tuple, form: str = "fp64", spring_k: float = 1.0,
+                 lattice_a: float = 1.0, check_netforce: bool = True, project_netforce: bool = False,
+                 netforce_tol: float = 1e-10, row_gauge: bool = True, stream=None):
+        lib = load_library()
+        self._lib = lib
+        self.ctx = C.c_void_p()
+        bz1, bz2 = (bz, bz) if isinstance(bz, int) else bz
+        opt = Options()
+        lib.fbc_default_options(C.byref(opt))
+        opt.form = FORMS[form] if isinstance(form, str) else int(form)
+        opt.bz_m1, opt.bz_m2 = int(bz1), int(bz2)
+        opt.check_netforce = int(bool(check_netforce))
+        opt.project_netforce = int(bool(project_netforce))
+        opt.netforce_tol = float(netforce_tol)
+        opt.row_gauge = int(bool(row_gauge))
+        self.form = form
+        self._keep = []
+        arr = (Cell * len(cells))()
+        for k, c in enumerate(cells):
+            ci = np.ascontiguousarray(c.cols_i, dtype=np.int32)
+            cb = np.ascontiguousarray(c.cols_b, dtype=np.int32)
+            self._keep += [ci, cb]
+            arr[k] = Cell(int(c.nz), int(ci.shape[0]), int(cb.shape[0]), int(c.n_rhs),
+                          ci.ctypes.data_as(C.POINTER(C.c_int32)), cb.ctypes.data_as(C.POINTER(C.c_int32)))
+        lat = Lattice(float(lattice_a), float(spring_k))
+        st = _stream_handle(stream)
+        rc = lib.fbc_assemble_G(C.byref(lat), arr, len(cells), C.byref(opt), st, C.byref(self.ctx))
+        if rc != FBC_OK:
+            raise FbcError(rc, lib.fbc_last_error(None).decode())
+        self._keep = []
+        self.info = self.get_info()
+
+    def _check(self, rc):
+        if rc != FBC_OK:
+            raise FbcError(rc, self._lib.fbc_last_error(self.ctx).decode())
+
+    def get_info(self) -> Info:
+        info = Info()
+        self._check(self._lib.fbc_get_info(self.ctx, C.byref(info)))
+        return info
+
+    def apply(self, f, u, alpha: float = 1.0, stream=None):
+        self._check(self._lib.fbc_apply(self.ctx, _dptr(f), _dptr(u), float(alpha), _stream_handle(stream)))
+
+    def green_apply(self, f, w, stream=None):
+        self._check(self._lib.fbc_green_apply(self.ctx, _dptr(f), _dptr(w), _stream_handle(stream)))
+
+    def relax_begin(self, relax: bool = True, du_max: float = 0.0, tol_f: float = 1e-3, stream=None):
+        o = RelaxOpts(int(bool(relax)), float(du_max), float(tol_f))
+        self._check(self._lib.fbc_relax_begin(self.ctx, C.byref(o), _stream_handle(stream)))
+
+    def relax_step(self, f, u, out=None, stream=None):
+        """out: float64 CUDA tensor of at least total_rhs * RELAX_OUT_DOUBLES elements, or None."""
+        optr = _dptr(out) if out is not None else None
+        self._check(self._lib.fbc_relax_step(self.ctx, _dptr(f), _dptr(u), optr, _stream_handle(stream)))
+
+    def sync_status(self, stream=None) -> int:
+        return self._lib.fbc_sync_status(self.ctx, _stream_handle(stream))
+
+    def timing(self, enable: bool = True):
+        self._check(self._lib.fbc_timing(self.ctx, int(bool(enable))))
+
+    def timing_read(self) -> tuple[float, int]:
+        ms = C.c_double()
+        n = C.c_int()
+        self._check(self._lib.fbc_timing_read(self.ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def block_rows(self, cell: int, m: int, b0: int, b1: int, n_i: int) -> np.ndarray:
+        out = np.empty((3 * (b1 - b0), 6 * n_i), dtype=np.float64)
+        self._check(self._lib.fbc_copy_block_rows(self.ctx, cell, m, b0, b1, out.ctypes.data))
+        return out[:, 0::2] + 1j * out[:, 1::2]
+
+    def close(self):
+        if self.ctx:
+            self._lib.fbc_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def parse_relax_out(t) -> list[dict]:
+    """Decodes the device relax-out buffer (copied to host) into dicts."""
+    a = np.ascontiguousarray(t.detach().cpu().numpy()) if hasattr(t, "detach") else np.asarray(t)
+    raw = a.view(np.uint8)
+    out = []
+    n = raw.size // C.sizeof(RelaxOut)
+    for r in range(n):
+        o = RelaxOut.from_buffer_copy(raw[r * C.sizeof(RelaxOut):(r + 1) * C.sizeof(RelaxOut)].tobytes())
+        out.append(dict(alpha=o.alpha, f_inf=o.f_inf, step_inf=o.step_inf,
+                        mean_removed=list(o.mean_removed), converged=bool(o.converged), k=o.k))
+    return out

@@ -1,0 +1,236 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 forms <= 1e-10 relative (per RHS, 2-norm over all pad outputs, and
+max-abs relative to the largest output); reduced forms at the bound stated per form.
+Inputs come from the seeded workload module; expected values from oracle/ only.
+"""
+import numpy as np
+import pytest
+
+import fbc_workloads as W
+from oracle import apply as oap, green as ogr, relax as orx
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _ctx(cells, bz, **kw):
+    from paper_2105_08798_amd import FBC
+    return FBC(cells, bz, **kw)
+
+
+_GCACHE = {}
+
+
+def oracle_green(cell, bz):
+    key = (cell.nz, bz, cell.cols_i.tobytes(), cell.cols_b.tobytes())
+    if key not in _GCACHE:
+        _GCACHE[key] = ogr.green_modes_dense(cell.nz, bz, bz, cell.cols_b, cell.cols_i)
+    return _GCACHE[key]
+
+
+def rel_err(got, ref):
+    """max over RHS of ||got - ref|| / ||ref||, and max-abs error / max |ref|."""
+    n = ref.shape[0]
+    g = got.reshape(n, -1)
+    r = ref.reshape(n, -1)
+    per = np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)
+    return float(per.max()), float(np.abs(g - r).max() / np.abs(r).max())
+
+
+def run_apply(wl, form="fp64", alpha=1.0, seed=0, **kw):
+    dev = _dev()
+    ctx = _ctx(wl.cells, wl.bz, form=form, **kw)
+    f = torch.from_numpy(np.concatenate([c.forces.ravel() for c in wl.cells])).to(dev)
+    rng = np.random.default_rng(seed)
+    u0 = [rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01 for c in wl.cells]
+    u = torch.from_numpy(np.concatenate([x.ravel() for x in u0])).to(dev)
+    ctx.apply(f, u, alpha=alpha)
+    rc = ctx.sync_status()
+    got = u.cpu().numpy()
+    ctx.close()
+    return rc, got, u0
+
+
+def oracle_update(wl, u0, alpha=1.0):
+    out = []
+    for c, uc in zip(wl.cells, u0):
+        w = oap.apply_green(oracle_green(c, wl.bz), c.forces)
+        un, _ = oap.pad_update(uc, w, alpha)
+        out.append(un)
+    return out
+
+
+def split_cells(wl, flat):
+    out, off = [], 0
+    for c in wl.cells:
+        n = c.n_rhs * c.nz * c.n_b * 3
+        out.append(flat[off:off + n].reshape(c.n_rhs, c.nz, c.n_b, 3))
+        off += n
+    return out
+
+
+@pytest.mark.parametrize("name", ["parity", "micro", "tiny"])
+def test_fp64_apply_matches_oracle(name):
+    wl = W.make_single(name)
+    rc, got, u0 = run_apply(wl, "fp64", alpha=0.7)
+    assert rc == 0
+    ref = oracle_update(wl, u0, 0.7)
+    for g, r in zip(split_cells(wl, got), ref):
+        e2, emax = rel_err(g, r)
+        assert e2 < 1e-10 and emax < 1e-10, (name, e2, emax)
+
+
+@pytest.mark.parametrize("nz,n_i,n_b,R,bz", [(2, 7, 11, 1, 16), (32, 33, 50, 9, 32), (64, 21, 40, 17, 16),
+                                             (8, 1, 1, 2, 8)])
+def test_fp64_ragged_shapes(nz, n_i, n_b, R, bz):
+    wl = W.make_custom(nz, n_i, n_b, R, bz, seed=nz + n_i)
+    rc, got, u0 = run_apply(wl, "fp64", alpha=1.3)
+    assert rc == 0
+    ref = oracle_update(wl, u0, 1.3)
+    e2, emax = rel_err(split_cells(wl, got)[0], ref[0])
+    assert e2 < 1e-10 and emax < 1e-10, (e2, emax)
+
+
+def test_fp64_assembled_blocks_match_oracle():
+    _dev()
+    wl = W.make_single("parity")
+    c = wl.cells[0]
+    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    g = oracle_green(c, wl.bz)
+    for m in (0, 1, c.nz // 2):
+        got = ctx.block_rows(0, m, 0, c.n_b, c.n_i)
+        ref = g[m]
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max(), m
+    ctx.close()
+
+
+def test_green_apply_is_raw_response():
+    wl = W.make_single("parity")
+    c = wl.cells[0]
+    dev = _dev()
+    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    f = torch.from_numpy(c.forces).to(dev)
+    w = torch.full((c.n_rhs, c.nz, c.n_b, 3), 7.0, dtype=torch.float64, device=dev)
+    ctx.green_apply(f, w)
+    assert ctx.sync_status() == 0
+    ref = oap.apply_green(oracle_green(c, wl.bz), c.forces)
+    e2, emax = rel_err(w.cpu().numpy(), ref)
+    ctx.close()
+    assert e2 < 1e-10 and emax < 1e-10
+
+
+def test_multi_cell_context_matches_per_cell_oracle():
+    cells = W.make_custom(16, 30, 45, 3, 32, seed=1).cells + W.make_custom(8, 12, 20, 10, 32, seed=2).cells \
+        + W.make_custom(32, 50, 60, 1, 32, seed=3).cells
+    wl = W.Workload("three", cells, bz=32)
+    rc, got, u0 = run_apply(wl, "fp64", alpha=1.0)
+    assert rc == 0
+    for g, r in zip(split_cells(wl, got), oracle_update(wl, u0, 1.0)):
+        e2, emax = rel_err(g, r)
+        assert e2 < 1e-10 and emax < 1e-10
+
+
+def test_net_force_violation_latched_and_u_untouched():
+    wl = W.make_custom(8, 20, 30, 2, 16, seed=5, zero_net_force=False)
+    rc, got, u0 = run_apply(wl, "fp64")
+    from paper_2105_08798_amd.fbc import STATUS
+    assert STATUS[rc] == "FBC_E_NETFORCE"
+    assert np.array_equal(got, np.concatenate([x.ravel() for x in u0]))
+
+
+def test_nonfinite_force_latched():
+    wl = W.make_custom(8, 20, 30, 1, 16, seed=6)
+    wl.cells[0].forces[0, 3, 4, 1] = np.nan
+    rc, got, u0 = run_apply(wl, "fp64")
+    from paper_2105_08798_amd.fbc import STATUS
+    assert STATUS[rc] == "FBC_E_NONFINITE"
+    assert np.array_equal(got, np.concatenate([x.ravel() for x in u0]))
+
+
+def test_projection_of_net_force():
+    wl = W.make_custom(16, 25, 40, 2, 16, seed=7, zero_net_force=False)
+    rc, got, u0 = run_apply(wl, "fp64", project_netforce=True)
+    assert rc == 0
+    c = wl.cells[0]
+    fp = c.forces - c.forces.mean(axis=2, keepdims=True)
+    w = oap.apply_green(oracle_green(c, wl.bz), fp)
+    ref, _ = oap.pad_update(u0[0], w, 1.0)
+    e2, emax = rel_err(got.reshape(ref.shape), ref)
+    assert e2 < 1e-10 and emax < 1e-10
+
+
+def test_relax_sequence_matches_oracle():
+    wl = W.make_single("parity")
+    c = wl.cells[0]
+    dev = _dev()
+    from paper_2105_08798_amd import RELAX_OUT_DOUBLES, parse_relax_out
+    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    g = oracle_green(c, wl.bz)
+    rng = np.random.default_rng(11)
+    # residual sequence with partly contracting, partly rotating directions
+    base = c.forces
+    seq = [base]
+    for k in range(5):
+        nxt = 0.6 * seq[-1] + 0.2 * rng.normal(size=base.shape) * 0.1 * (0.5 ** k)
+        nxt -= nxt.mean(axis=2, keepdims=True)
+        seq.append(nxt)
+    u0 = rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01
+    u = torch.from_numpy(u0).to(dev)
+    st = orx.RelaxState(n_rhs=c.n_rhs, relax=True, du_max=0.05, tol_f=0.2)
+    ctx.relax_begin(relax=True, du_max=0.05, tol_f=0.2)
+    out = torch.zeros(c.n_rhs * RELAX_OUT_DOUBLES, dtype=torch.float64, device=dev)
+    uref = u0.copy()
+    for fk in seq:
+        ctx.relax_step(torch.from_numpy(fk).to(dev), u, out)
+        assert ctx.sync_status() == 0
+        uref, oref = orx.relax_step(st, fk, uref, lambda f: oap.apply_green(g, f))
+        got = parse_relax_out(out)
+        for r in range(c.n_rhs):
+            assert abs(got[r]["alpha"] - oref["alpha"][r]) <= 1e-10 * abs(oref["alpha"][r])
+            assert abs(got[r]["f_inf"] - oref["f_inf"][r]) <= 1e-15 * oref["f_inf"][r]
+            assert abs(got[r]["step_inf"] - oref["step_inf"][r]) <= 1e-10 * oref["step_inf"][r]
+            assert got[r]["converged"] == bool(oref["converged"][r])
+        e2, emax = rel_err(u.cpu().numpy(), uref)
+        assert e2 < 1e-10 and emax < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("form,bound", [("fp32", 1e-6), ("split_bf16", 2e-5)])
+def test_reduced_forms_error_bound(form, bound):
+    wl = W.make_single("parity")
+    c = wl.cells[0]
+    dev = _dev()
+    ctx = _ctx(wl.cells, wl.bz, form=form)
+    f = torch.from_numpy(c.forces).to(dev)
+    w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+    ctx.green_apply(f, w)
+    assert ctx.sync_status() == 0
+    ctx.close()
+    ref = oap.apply_green(oracle_green(c, wl.bz), c.forces)
+    e2, emax = rel_err(w.cpu().numpy(), ref)
+    print(f"{form}: rel err {e2:.3e} (max-abs {emax:.3e})")
+    assert e2 < bound, (form, e2)
+
+
+def test_repeated_apply_is_bitwise_reproducible():
+    wl = W.make_single("parity")
+    dev = _dev()
+    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    c = wl.cells[0]
+    f = torch.from_numpy(c.forces).to(dev)
+    outs = []
+    for _ in range(3):
+        u = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+        ctx.apply(f, u, alpha=1.0)
+        assert ctx.sync_status() == 0
+        outs.append(u.cpu().numpy())
+    ctx.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
