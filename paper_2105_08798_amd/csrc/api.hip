@@ -38,6 +38,12 @@ struct fbc_ctx {
     int njobs = 0;
     int64_t scratch_bytes = 0;
     int64_t n_offsets = 0;
+    // offset table (kept for the offset-table form)
+    int nz_max = 0;
+    double2* tab = nullptr;
+    int32_t* lut = nullptr;
+    int d1min = 0, d2min = 0, w2 = 0;
+    CellDev* celldev = nullptr;
     // relax
     double* fprev = nullptr;
     double* alpha = nullptr;
@@ -197,33 +203,43 @@ struct OffsetSet {
     std::vector<int32_t> lut, d1, d2;
 };
 
-static OffsetSet offsets_of(const CellPlan& p) {
+// Distinct column offsets n_b - n_i over every cell, indexed through a dense lookup
+// table over their bounding box (row-major over (d1, d2), so the numbering is fixed).
+static OffsetSet offsets_of(const std::vector<CellPlan>& cells) {
     OffsetSet o{};
-    int b1lo = INT32_MAX, b1hi = INT32_MIN, b2lo = INT32_MAX, b2hi = INT32_MIN;
-    int i1lo = INT32_MAX, i1hi = INT32_MIN, i2lo = INT32_MAX, i2hi = INT32_MIN;
-    for (int b = 0; b < p.n_b; ++b) {
-        b1lo = std::min(b1lo, p.cols_b[2 * b]);
-        b1hi = std::max(b1hi, p.cols_b[2 * b]);
-        b2lo = std::min(b2lo, p.cols_b[2 * b + 1]);
-        b2hi = std::max(b2hi, p.cols_b[2 * b + 1]);
-    }
-    for (int i = 0; i < p.n_i; ++i) {
-        i1lo = std::min(i1lo, p.cols_i[2 * i]);
-        i1hi = std::max(i1hi, p.cols_i[2 * i]);
-        i2lo = std::min(i2lo, p.cols_i[2 * i + 1]);
-        i2hi = std::max(i2hi, p.cols_i[2 * i + 1]);
-    }
-    o.d1min = b1lo - i1hi;
-    o.d2min = b2lo - i2hi;
-    o.w1 = b1hi - i1lo - o.d1min + 1;
-    o.w2 = b2hi - i2lo - o.d2min + 1;
-    o.lut.assign((size_t)o.w1 * o.w2, -1);
-    for (int b = 0; b < p.n_b; ++b)
-        for (int i = 0; i < p.n_i; ++i) {
-            const int x = p.cols_b[2 * b] - p.cols_i[2 * i] - o.d1min;
-            const int y = p.cols_b[2 * b + 1] - p.cols_i[2 * i + 1] - o.d2min;
-            o.lut[(size_t)x * o.w2 + y] = 0;
+    int lo1 = INT32_MAX, hi1 = INT32_MIN, lo2 = INT32_MAX, hi2 = INT32_MIN;
+    for (const CellPlan& p : cells) {
+        int b1lo = INT32_MAX, b1hi = INT32_MIN, b2lo = INT32_MAX, b2hi = INT32_MIN;
+        int i1lo = INT32_MAX, i1hi = INT32_MIN, i2lo = INT32_MAX, i2hi = INT32_MIN;
+        for (int b = 0; b < p.n_b; ++b) {
+            b1lo = std::min(b1lo, p.cols_b[2 * b]);
+            b1hi = std::max(b1hi, p.cols_b[2 * b]);
+            b2lo = std::min(b2lo, p.cols_b[2 * b + 1]);
+            b2hi = std::max(b2hi, p.cols_b[2 * b + 1]);
         }
+        for (int i = 0; i < p.n_i; ++i) {
+            i1lo = std::min(i1lo, p.cols_i[2 * i]);
+            i1hi = std::max(i1hi, p.cols_i[2 * i]);
+            i2lo = std::min(i2lo, p.cols_i[2 * i + 1]);
+            i2hi = std::max(i2hi, p.cols_i[2 * i + 1]);
+        }
+        lo1 = std::min(lo1, b1lo - i1hi);
+        hi1 = std::max(hi1, b1hi - i1lo);
+        lo2 = std::min(lo2, b2lo - i2hi);
+        hi2 = std::max(hi2, b2hi - i2lo);
+    }
+    o.d1min = lo1;
+    o.d2min = lo2;
+    o.w1 = hi1 - lo1 + 1;
+    o.w2 = hi2 - lo2 + 1;
+    o.lut.assign((size_t)o.w1 * o.w2, -1);
+    for (const CellPlan& p : cells)
+        for (int b = 0; b < p.n_b; ++b)
+            for (int i = 0; i < p.n_i; ++i) {
+                const int x = p.cols_b[2 * b] - p.cols_i[2 * i] - o.d1min;
+                const int y = p.cols_b[2 * b + 1] - p.cols_i[2 * i + 1] - o.d2min;
+                o.lut[(size_t)x * o.w2 + y] = 0;
+            }
     int32_t n = 0;
     for (int x = 0; x < o.w1; ++x)
         for (int y = 0; y < o.w2; ++y) {
@@ -237,14 +253,21 @@ static OffsetSet offsets_of(const CellPlan& p) {
     return o;
 }
 
-static fbc_status assemble_cell(fbc_ctx* c, CellPlan& p, hipStream_t st, const BondTable& bt,
-                                double* sn_d, int logL) {
+// Builds the offset table tab[t][o][6] for every line mode t = 0..nz_max/2 of the finest
+// line grid of the context (a cell with Nz layers reads table mode m * nz_max / Nz, the
+// same wavenumber), then either fills the dense stores of every cell and frees the
+// table, or keeps it for the offset-table form.
+static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, double* sn_d,
+                               int logL) {
     const int m1 = c->opt.bz_m1, m2 = c->opt.bz_m2;
     const int form = c->opt.form;
-    OffsetSet os = offsets_of(p);
+    OffsetSet os = offsets_of(c->cells);
     const int64_t n_off = (int64_t)os.d1.size();
-    c->n_offsets += n_off;
-    // temporary device buffers of this cell
+    c->n_offsets = n_off;
+    c->d1min = os.d1min;
+    c->d2min = os.d2min;
+    c->w2 = os.w2;
+    const int T = c->nz_max / 2 + 1;
     std::vector<void*> tmp;
     auto talloc = [&](void** ptr, int64_t bytes) -> fbc_status {
         *ptr = nullptr;
@@ -257,22 +280,27 @@ static fbc_status assemble_cell(fbc_ctx* c, CellPlan& p, hipStream_t st, const B
         return FBC_OK;
     };
     auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
         for (void* q : tmp) (void)hipFree(q);
     };
-    int32_t *lut_d, *d1_d, *d2_d;
-    double2* tab;
     fbc_status s;
-    if ((s = talloc((void**)&lut_d, (int64_t)os.lut.size() * 4)) != FBC_OK ||
-        (s = talloc((void**)&d1_d, n_off * 4)) != FBC_OK ||
-        (s = talloc((void**)&d2_d, n_off * 4)) != FBC_OK ||
-        (s = talloc((void**)&tab, (int64_t)p.nm * n_off * 6 * 16)) != FBC_OK) {
+    int32_t *d1_d, *d2_d;
+    const bool keep = (form == FBC_FORM_DTABLE_FP64);
+    if ((s = dev_alloc(c, (void**)&c->lut, (int64_t)os.lut.size() * 4)) != FBC_OK) return s;
+    if (keep) {
+        if ((s = dev_alloc(c, (void**)&c->tab, (int64_t)T * n_off * 96)) != FBC_OK) return s;
+        c->store_bytes = (int64_t)T * n_off * 96;
+    } else if ((s = talloc((void**)&c->tab, (int64_t)T * n_off * 96)) != FBC_OK) {
         cleanup();
         return s;
     }
-    (void)hipMemcpyAsync(lut_d, os.lut.data(), os.lut.size() * 4, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(d1_d, os.d1.data(), n_off * 4, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(d2_d, os.d2.data(), n_off * 4, hipMemcpyHostToDevice, st);
-    // twiddles for the in-plane transforms
+    if ((s = talloc((void**)&d1_d, n_off * 4)) != FBC_OK || (s = talloc((void**)&d2_d, n_off * 4)) != FBC_OK) {
+        cleanup();
+        return s;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->lut, os.lut.data(), os.lut.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(d1_d, os.d1.data(), n_off * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(d2_d, os.d2.data(), n_off * 4, hipMemcpyHostToDevice, st));
     std::vector<double2> tw1, tw2;
     twiddles(m1, tw1);
     twiddles(m2, tw2);
@@ -282,13 +310,13 @@ static fbc_status assemble_cell(fbc_ctx* c, CellPlan& p, hipStream_t st, const B
         cleanup();
         return s;
     }
-    (void)hipMemcpyAsync(tw1_d, tw1.data(), tw1.size() * 16, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(tw2_d, tw2.data(), tw2.size() * 16, hipMemcpyHostToDevice, st);
+    HIPCHK(c, hipMemcpyAsync(tw1_d, tw1.data(), tw1.size() * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(tw2_d, tw2.data(), tw2.size() * 16, hipMemcpyHostToDevice, st));
     // mode chunks sized to ~2 GiB of FFT workspace (x2 for the transpose)
     const int64_t plane = (int64_t)m1 * m2;
     const int64_t per_mode = plane * 3 * 16;
     int chunk = (int)std::max<int64_t>(1, ((int64_t)1 << 31) / per_mode);
-    chunk = std::min(chunk, p.nm);
+    chunk = std::min(chunk, T);
     double2 *pk, *pt;
     if ((s = talloc((void**)&pk, per_mode * chunk)) != FBC_OK ||
         (s = talloc((void**)&pt, per_mode * chunk)) != FBC_OK) {
@@ -296,34 +324,36 @@ static fbc_status assemble_cell(fbc_ctx* c, CellPlan& p, hipStream_t st, const B
         return s;
     }
     const double scale = 1.0 / ((double)m1 * m2);
-    for (int m0 = 0; m0 < p.nm; m0 += chunk) {
-        const int nmc = std::min(chunk, p.nm - m0);
-        launch_dinv(st, pk, m0, nmc, p.nz, m1, m2, logL, sn_d, bt);
+    for (int t0 = 0; t0 < T; t0 += chunk) {
+        const int nmc = std::min(chunk, T - t0);
+        launch_dinv(st, pk, t0, nmc, c->nz_max, m1, m2, logL, sn_d, bt);
         // inverse 2-D FFT: rows (m2 contiguous), transpose, rows again -> t[comp][d2][d1]
         launch_fft_rows(st, pk, (int64_t)nmc * 3 * m1, ilog2(m2), tw2_d, true);
         launch_transpose_c(st, pk, pt, nmc * 3, m1, m2);
         launch_fft_rows(st, pt, (int64_t)nmc * 3 * m2, ilog2(m1), tw1_d, true);
-        launch_gather_table(st, pt, tab + (int64_t)m0 * n_off * 6, nmc, m1, m2, n_off, d1_d, d2_d,
+        launch_gather_table(st, pt, c->tab + (int64_t)t0 * n_off * 6, nmc, m1, m2, n_off, d1_d, d2_d,
                             n_off * 6, scale);
     }
     HIPCHK(c, hipGetLastError());
-    if (form == FBC_FORM_DTABLE_FP64) {
-        cleanup();
-        return fail(c, FBC_E_UNSUPPORTED, "offset-table form not built yet");
-    }
-    double2* rowmean = nullptr;
-    if (form != FBC_FORM_FP64 && c->opt.row_gauge) {
-        if ((s = talloc((void**)&rowmean, (int64_t)p.nm * p.n_b * 6 * 16)) != FBC_OK) {
-            cleanup();
-            return s;
+    if (!keep) {
+        for (CellPlan& p : c->cells) {
+            const int mult = c->nz_max / p.nz;
+            double2* rowmean = nullptr;
+            if (form != FBC_FORM_FP64 && c->opt.row_gauge) {
+                if ((s = talloc((void**)&rowmean, (int64_t)p.nm * p.n_b * 6 * 16)) != FBC_OK) {
+                    cleanup();
+                    return s;
+                }
+                launch_rowmean(st, c->tab, rowmean, p.nm, mult, n_off, p.n_b, p.n_i, p.cols_b_d,
+                               p.cols_i_d, c->lut, os.d1min, os.d2min, os.w2);
+            }
+            char* base = (char*)c->store + p.a_off * store_elem_bytes(form);
+            launch_build_dense(st, form, base, c->tab, rowmean, p.nm, mult, n_off, p.mp, p.kp, p.n_b,
+                               p.n_i, p.cols_b_d, p.cols_i_d, c->lut, os.d1min, os.d2min, os.w2);
+            HIPCHK(c, hipGetLastError());
         }
-        launch_rowmean(st, tab, rowmean, p.nm, n_off, p.n_b, p.n_i, p.cols_b_d, p.cols_i_d, lut_d,
-                       os.d1min, os.d2min, os.w2);
+        c->tab = nullptr;
     }
-    char* base = (char*)c->store + p.a_off * store_elem_bytes(form);
-    launch_build_dense(st, form, base, tab, rowmean, p.nm, n_off, p.mp, p.kp, p.n_b, p.n_i,
-                       p.cols_b_d, p.cols_i_d, lut_d, os.d1min, os.d2min, os.w2);
-    HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     cleanup();
     return FBC_OK;
@@ -334,8 +364,37 @@ static fbc_status assemble_cell(fbc_ctx* c, CellPlan& p, hipStream_t st, const B
 // groups are dispatched round-robin over the 8 XCDs by block index), so the B
 // fragments of a mode are shared through that XCD's L2.
 // ----------------------------------------------------------------------------------
+// Offset-table form: all tiles of one table mode are consecutive (every XCD works on the
+// same table slice at a time, which stays in the last-level cache).
+static std::vector<GemmJob> build_jobs_dtab(const fbc_ctx* c) {
+    std::vector<GemmJob> out;
+    const int T = c->nz_max / 2 + 1;
+    for (int t = 0; t < T; ++t)
+        for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
+            const CellPlan& p = c->cells[ci];
+            const int mult = c->nz_max / p.nz;
+            if (t % mult) continue;
+            const int m = t / mult;
+            const int tiles = p.mp / 96;
+            for (int tl = 0; tl < tiles; ++tl) {
+                GemmJob j{};
+                j.a_off = (int64_t)t * c->n_offsets * 6;
+                j.b_off = p.b_off + (int64_t)m * b_mode_elems(FBC_FORM_DTABLE_FP64, p);
+                j.c_off = p.c_off + (int64_t)m * p.ct * p.mp * 16;
+                j.mb = p.mp / 16;
+                j.kp = p.kp;
+                j.rb0 = 6 * tl;
+                j.ct = p.ct;
+                j.cell = ci;
+                out.push_back(j);
+            }
+        }
+    return out;
+}
+
 static std::vector<GemmJob> build_jobs(const fbc_ctx* c) {
     const int form = c->opt.form;
+    if (form == FBC_FORM_DTABLE_FP64) return build_jobs_dtab(c);
     const int rb = gemm_rb(form, c->ctmax);
     const int tile_rb = 4 * rb;
     std::vector<std::vector<GemmJob>> per_xcd(8);
@@ -401,11 +460,10 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             return fail(nullptr, FBC_E_ARG, "nz must be a power of two in [2, 4096]");
         if (cl.n_i < 1 || cl.n_b < 1 || cl.n_rhs < 1 || !cl.cols_i || !cl.cols_b)
             return fail(nullptr, FBC_E_ARG, "cell sizes must be >= 1 and column arrays non-null");
-        if ((int64_t)cl.n_i * 6 > (1 << 30) || (int64_t)cl.n_b * 3 > (1 << 30) || cl.n_rhs > 4096)
+        if ((int64_t)cl.n_i * 6 > (1 << 30) || (int64_t)cl.n_b * 3 > (1 << 30))
             return fail(nullptr, FBC_E_ARG, "cell too large");
+        if (cl.n_rhs > 64) return fail(nullptr, FBC_E_ARG, "at most 64 RHS per cell");
     }
-    if (opt->form == FBC_FORM_DTABLE_FP64)
-        return fail(nullptr, FBC_E_UNSUPPORTED, "offset-table form not built yet");
 
     fbc_ctx* c = new (std::nothrow) fbc_ctx();
     if (!c) return fail(nullptr, FBC_E_NOMEM, "host allocation");
@@ -415,7 +473,13 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     hipStream_t st = (hipStream_t)stream;
     const int form = opt->form;
 
-    // plan
+    // plan: one column-tile count for the whole context (template of the product kernel),
+    // rows padded to whole work-group tiles, K' padded to a multiple of 64
+    int ctmax = 1;
+    for (int i = 0; i < n_cells; ++i) ctmax = std::max(ctmax, (cells[i].n_rhs + 7) / 8);
+    const int ctl = ctmax <= 1 ? 1 : ctmax <= 2 ? 2 : ctmax <= 4 ? 4 : 8;
+    const int rows_tile = 64 * gemm_rb(form, ctl);
+    c->ctmax = ctl;
     int64_t f_off = 0, u_off = 0, a_off = 0, b_off = 0, c_off = 0, w_off = 0;
     int rhs0 = 0;
     for (int i = 0; i < n_cells; ++i) {
@@ -427,9 +491,15 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         p.R = cells[i].n_rhs;
         p.K = 3 * p.n_i;
         p.M = 3 * p.n_b;
-        p.kp = (int)roundup(6 * (int64_t)p.n_i, 32);
-        p.mp = (int)roundup(p.M, 16);
-        p.ct = (p.R + 7) / 8;
+        if (form == FBC_FORM_DTABLE_FP64) {
+            p.kp = 6 * (int)roundup(p.n_i, 8);       // whole chunks of 8 interface columns
+            p.mp = (int)roundup(p.M, 96);            // whole tiles of 32 pad columns
+        } else {
+            p.kp = (int)roundup(6 * (int64_t)p.n_i, 64);
+            p.mp = (int)roundup(p.M, rows_tile);
+        }
+        p.ct = ctl;
+        p.ctr = (p.R + 7) / 8;
         p.f_off = f_off;
         p.u_off = u_off;
         p.a_off = a_off;
@@ -446,15 +516,17 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         c_off += (int64_t)p.nm * p.ct * p.mp * 16;
         w_off += (int64_t)p.R * p.M * p.nz;
         rhs0 += p.R;
-        c->ctmax = std::max(c->ctmax, p.ct);
+        c->nz_max = std::max(c->nz_max, p.nz);
         c->cells.push_back(p);
     }
     c->total_rhs = rhs0;
     c->f_elems = f_off;
     c->u_elems = u_off;
     fbc_status s;
-    c->store_bytes = a_off * store_elem_bytes(form);
-    if ((s = dev_alloc(c, &c->store, c->store_bytes)) != FBC_OK) goto fail_out;
+    if (form != FBC_FORM_DTABLE_FP64) {
+        c->store_bytes = a_off * store_elem_bytes(form);
+        if ((s = dev_alloc(c, &c->store, c->store_bytes)) != FBC_OK) goto fail_out;
+    }
     if ((s = dev_alloc(c, &c->bfrag, b_off * b_elem_bytes(form))) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->cbuf, c_off * 8)) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->wbuf, w_off * 8)) != FBC_OK) goto fail_out;
@@ -510,6 +582,12 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         HIPCHK(c, hipMemcpyAsync(p.cols_i_d, p.cols_i.data(), (size_t)p.n_i * 8, hipMemcpyHostToDevice, st));
         HIPCHK(c, hipMemcpyAsync(p.cols_b_d, p.cols_b.data(), (size_t)p.n_b * 8, hipMemcpyHostToDevice, st));
     }
+    {
+        std::vector<CellDev> cd;
+        for (auto& p : c->cells) cd.push_back(CellDev{p.cols_b_d, p.cols_i_d, p.n_b, p.n_i});
+        if ((s = dev_alloc(c, (void**)&c->celldev, (int64_t)cd.size() * sizeof(CellDev))) != FBC_OK) goto fail_out;
+        HIPCHK(c, hipMemcpyAsync(c->celldev, cd.data(), cd.size() * sizeof(CellDev), hipMemcpyHostToDevice, st));
+    }
     HIPCHK(c, hipMemsetAsync(c->bfrag, 0, (size_t)(b_off * b_elem_bytes(form)), st));
     HIPCHK(c, hipMemsetAsync(c->status, 0, 64, st));
     {
@@ -528,13 +606,11 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         }
         (void)hipMemcpyAsync(sn_d, sn.data(), (size_t)L * 8, hipMemcpyHostToDevice, st);
         const BondTable bt = make_bonds(lat->spring_k);
-        for (auto& p : c->cells) {
-            s = assemble_cell(c, p, st, bt, sn_d, logL);
-            if (s != FBC_OK) {
-                (void)hipStreamSynchronize(st);
-                (void)hipFree(sn_d);
-                goto fail_out;
-            }
+        s = assemble_all(c, st, bt, sn_d, logL);
+        if (s != FBC_OK) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(sn_d);
+            goto fail_out;
         }
         (void)hipStreamSynchronize(st);
         (void)hipFree(sn_d);
@@ -577,8 +653,11 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     }
     const bool tm = c->timing && c->n_timed < kMaxTimed;
     if (tm) (void)hipEventRecord(c->ev[2 * c->n_timed], st);
-    launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf, nullptr, nullptr,
-                nullptr, nullptr, 0, 0, 0);
+    if (form == FBC_FORM_DTABLE_FP64)
+        launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, (const double*)c->bfrag, c->cbuf,
+                         c->celldev, c->lut, c->d1min, c->d2min, c->w2);
+    else
+        launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf);
     if (tm) {
         (void)hipEventRecord(c->ev[2 * c->n_timed + 1], st);
         ++c->n_timed;
@@ -586,7 +665,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
-                          p.nz, p.mp, p.M, p.ct, c->tw + p.tw_off, nullptr);
+                          p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, nullptr);
     }
 }
 
@@ -699,7 +778,30 @@ extern "C" fbc_status fbc_copy_block_rows(fbc_ctx* c, int cell, int m, int b0, i
     if (cell < 0 || cell >= (int)c->cells.size()) return fail(c, FBC_E_ARG, "cell out of range");
     const CellPlan& p = c->cells[cell];
     if (m < 0 || m >= p.nm || b0 < 0 || b1 > p.n_b || b0 >= b1) return fail(c, FBC_E_ARG, "range");
-    if (c->opt.form != FBC_FORM_FP64) return fail(c, FBC_E_UNSUPPORTED, "FP64 dense store only");
+    if (c->opt.form == FBC_FORM_DTABLE_FP64) {
+        // reconstruct the block rows from the offset table
+        const int mult = c->nz_max / p.nz;
+        HIPCHK(c, hipDeviceSynchronize());
+        std::vector<double2> tabm((size_t)c->n_offsets * 6);
+        HIPCHK(c, hipMemcpy(tabm.data(), c->tab + (int64_t)m * mult * c->n_offsets * 6,
+                            tabm.size() * 16, hipMemcpyDeviceToHost));
+        OffsetSet os = offsets_of(c->cells);
+        for (int b = b0; b < b1; ++b)
+            for (int i = 0; i < p.n_i; ++i) {
+                const int x = p.cols_b[2 * b] - p.cols_i[2 * i] - os.d1min;
+                const int y = p.cols_b[2 * b + 1] - p.cols_i[2 * i + 1] - os.d2min;
+                const int64_t o = os.lut[(size_t)x * os.w2 + y];
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int d = 0; d < 3; ++d) {
+                        const double2 v = tabm[o * 6 + sym_idx(cc, d)];
+                        double* dst = out + ((int64_t)(3 * (b - b0) + cc) * 6 * p.n_i + 2 * (3 * i + d));
+                        dst[0] = v.x;
+                        dst[1] = v.y;
+                    }
+            }
+        return FBC_OK;
+    }
+    if (c->opt.form != FBC_FORM_FP64) return fail(c, FBC_E_UNSUPPORTED, "FP64 forms only");
     const int64_t per_mode = (int64_t)p.mp * p.kp;
     std::vector<double> blk(per_mode);
     HIPCHK(c, hipDeviceSynchronize());

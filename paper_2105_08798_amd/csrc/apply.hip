@@ -259,7 +259,8 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
 }
 
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
-                       int nz, int mp, int M, int ct, const double2* tw, int* n_part_out) {
+                       int nz, int mp, int M, int ct, int ct_grid, const double2* tw,
+                       int* n_part_out) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int pp, tr;
@@ -271,7 +272,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
         pp = 4096 / nz;
         tr = 1;
     }
-    dim3 grid((M + tr - 1) / tr, ct, 4 / pp);
+    dim3 grid((M + tr - 1) / tr, ct_grid, 4 / pp);
     size_t lds = (size_t)tr * pp * nz * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
     hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,

@@ -181,7 +181,7 @@ __device__ inline int64_t lut_index(const int32_t* __restrict__ cols_b,
 // reduced-precision forms).  One thread per (mode, pad column).
 __global__ void __launch_bounds__(256) k_rowmean(const double2* __restrict__ tab,
                                                  double2* __restrict__ rowmean, int nm,
-                                                 int64_t n_off, int n_b, int n_i,
+                                                 int mode_mult, int64_t n_off, int n_b, int n_i,
                                                  const int32_t* __restrict__ cols_b,
                                                  const int32_t* __restrict__ cols_i,
                                                  const int32_t* __restrict__ lut, int d1min,
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(256) k_rowmean(const double2* __restrict__ tab
     const int b = (int)(idx - (int64_t)m * n_b);
     double2 acc[6];
     for (int c = 0; c < 6; ++c) acc[c] = make_double2(0, 0);
-    const double2* tm = tab + (int64_t)m * n_off * 6;
+    const double2* tm = tab + (int64_t)m * mode_mult * n_off * 6;
     for (int i = 0; i < n_i; ++i) {
         const int64_t o = lut_index(cols_b, cols_i, b, i, lut, d1min, d2min, w2);
         for (int c = 0; c < 6; ++c) {
@@ -205,12 +205,13 @@ __global__ void __launch_bounds__(256) k_rowmean(const double2* __restrict__ tab
     for (int c = 0; c < 6; ++c) rowmean[idx * 6 + c] = make_double2(acc[c].x * s, acc[c].y * s);
 }
 
-void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm, int64_t n_off,
-                    int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
+void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm, int mode_mult,
+                    int64_t n_off, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
                     const int32_t* lut, int d1min, int d2min, int w2) {
     const int64_t total = (int64_t)nm * n_b;
     hipLaunchKernelGGL(k_rowmean, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, tab,
-                       rowmean, nm, n_off, n_b, n_i, cols_b, cols_i, lut, d1min, d2min, w2);
+                       rowmean, nm, mode_mult, n_off, n_b, n_i, cols_b, cols_i, lut, d1min, d2min,
+                       w2);
 }
 
 // ----------------------------------------------------------------------------------
@@ -225,7 +226,8 @@ __device__ inline unsigned short f32_to_bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-__device__ inline double dense_value(int row, int kq, int m, const double2* __restrict__ tab,
+__device__ inline double dense_value(int row, int kq, int m, int mode_mult,
+                                     const double2* __restrict__ tab,
                                      const double2* __restrict__ rowmean, int64_t n_off, int n_b,
                                      int n_i, const int32_t* __restrict__ cols_b,
                                      const int32_t* __restrict__ cols_i,
@@ -237,7 +239,7 @@ __device__ inline double dense_value(int row, int kq, int m, const double2* __re
     const int i = kc / 3, d = kc - 3 * i;
     const int s = sym_idx(c, d);
     const int64_t o = lut_index(cols_b, cols_i, b, i, lut, d1min, d2min, w2);
-    double2 v = tab[((int64_t)m * n_off + o) * 6 + s];
+    double2 v = tab[((int64_t)m * mode_mult * n_off + o) * 6 + s];
     if (rowmean) {
         const double2 r = rowmean[((int64_t)m * n_b + b) * 6 + s];
         v.x -= r.x;
@@ -249,7 +251,7 @@ __device__ inline double dense_value(int row, int kq, int m, const double2* __re
 __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict__ store,
                                                      const double2* __restrict__ tab,
                                                      const double2* __restrict__ rowmean, int nm,
-                                                     int64_t n_off, int mp, int kp, int n_b,
+                                                     int mode_mult, int64_t n_off, int mp, int kp, int n_b,
                                                      int n_i, const int32_t* __restrict__ cols_b,
                                                      const int32_t* __restrict__ cols_i,
                                                      const int32_t* __restrict__ lut, int d1min,
@@ -265,7 +267,7 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
         const int kp8 = kp >> 3;
         const int p = (int)(rest % kp8), blk = (int)(rest / kp8);
         const int row = 16 * blk + (lane & 15), kq = 8 * p + 4 * s + (lane >> 4);
-        ((double*)store)[e] = dense_value(row, kq, m, tab, rowmean, n_off, n_b, n_i, cols_b,
+        ((double*)store)[e] = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
                                           cols_i, lut, d1min, d2min, w2);
     } else if (form == FBC_FORM_FP32) {
         const int s = (int)(x & 3), lane = (int)((x >> 2) & 63);
@@ -273,7 +275,7 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
         const int kp16 = kp >> 4;
         const int q = (int)(rest % kp16), blk = (int)(rest / kp16);
         const int row = 16 * blk + (lane & 15), kq = 16 * q + 4 * s + (lane >> 4);
-        ((float*)store)[e] = (float)dense_value(row, kq, m, tab, rowmean, n_off, n_b, n_i, cols_b,
+        ((float*)store)[e] = (float)dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
                                                 cols_i, lut, d1min, d2min, w2);
     } else {  // split BF16: x indexes hi parts only; lo is written 512 elements later
         const int j = (int)(x & 7), lane = (int)((x >> 3) & 63);
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
         const int kp32 = kp >> 5;
         const int t = (int)(rest % kp32), blk = (int)(rest / kp32);
         const int row = 16 * blk + (lane & 15), kq = 32 * t + 8 * (lane >> 4) + j;
-        const double v = dense_value(row, kq, m, tab, rowmean, n_off, n_b, n_i, cols_b, cols_i,
+        const double v = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b, cols_i,
                                      lut, d1min, d2min, w2);
         const unsigned short hi = f32_to_bf16_rne((float)v);
         const unsigned short lo = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(hi)));
@@ -293,11 +295,11 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
 }
 
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
-                        const double2* rowmean, int nm, int64_t n_off, int mp, int kp, int n_b,
-                        int n_i, const int32_t* cols_b, const int32_t* cols_i, const int32_t* lut,
-                        int d1min, int d2min, int w2) {
+                        const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
+                        int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
+                        const int32_t* lut, int d1min, int d2min, int w2) {
     const int64_t total = (int64_t)mp * kp * nm;
     hipLaunchKernelGGL(k_build_dense, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                       form, store, tab, rowmean, nm, n_off, mp, kp, n_b, n_i, cols_b, cols_i, lut,
-                       d1min, d2min, w2);
+                       form, store, tab, rowmean, nm, mode_mult, n_off, mp, kp, n_b, n_i, cols_b,
+                       cols_i, lut, d1min, d2min, w2);
 }

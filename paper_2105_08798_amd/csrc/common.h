@@ -22,7 +22,7 @@ typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 //                  hi and lo halves of the split are stored as consecutive 1 KiB runs.
 // Output of the 16x16 MFMAs: FP64 c[j] = C[4 j + l/16][l%16];
 //                            FP32 c[j] = C[4 (l/16) + j][l%16].
-// K' is padded to a multiple of 32 for every form (zeros).
+// K' is padded to a multiple of 64 for every form (zeros).
 // ---------------------------------------------------------------------------------
 __host__ __device__ inline int64_t frag_off_f64(int64_t r, int64_t k, int64_t kp) {
     int64_t blk = r >> 4, rr = r & 15;
@@ -49,18 +49,25 @@ __host__ __device__ inline int sym_idx(int c, int d) {
     return (lo == 0) ? (hi == 1 ? 3 : 4) : 5;
 }
 
-// One work item of the per-mode complex product: a tile of up to 4*RB row blocks of
+// One work item of the per-mode complex product: a tile of 4*RB row blocks of
 // one mode of one cell.  Offsets are in elements of the respective arrays.
 struct GemmJob {
     int64_t a_off;   // A store (dense forms) or table mode base (offset form)
     int64_t b_off;   // B fragments of this mode
     int64_t c_off;   // output [ct][mp][16] doubles of this mode
     int32_t mb;      // row blocks of the mode (mp / 16)
-    int32_t kp;      // padded K' (multiple of 32)
+    int32_t kp;      // padded K' (multiple of 64)
     int32_t rb0;     // first row block of this tile
     int32_t ct;      // column tiles (8 RHS each)
     int32_t cell;    // cell index (offset form)
     int32_t pad;
+};
+
+// Per-cell device view used by the offset-table product kernel.
+struct CellDev {
+    const int32_t* cols_b;   // [n_b][2]
+    const int32_t* cols_i;   // [n_i][2]
+    int32_t n_b, n_i;
 };
 
 // Device-side status latch bits
@@ -69,9 +76,10 @@ enum { ST_NETFORCE = 1, ST_NONFINITE = 2 };
 struct CellPlan {
     int nz, nm, n_i, n_b, R;
     int K, M;            // complex K = 3 n_i, rows M = 3 n_b
-    int kp;              // padded real K' = roundup(6 n_i, 32)
-    int mp;              // padded rows = roundup(3 n_b, 16)
-    int ct;              // column tiles = ceil(R / 8)
+    int kp;              // padded real K' = roundup(6 n_i, 64)
+    int mp;              // padded rows = roundup(3 n_b, 64 * RB), a whole work-group tile
+    int ct;              // column tiles of the B / output layouts (same for every cell)
+    int ctr;             // column tiles holding RHS of this cell = ceil(R / 8)
     int64_t f_off, u_off;        // offsets (doubles) into caller's f and u
     int64_t a_off;               // dense store offset (elements of the store type) of mode 0
     int64_t b_off;               // B fragments offset (elements) of mode 0

@@ -34,7 +34,11 @@ static __device__ inline void store_c_f32acc(double* __restrict__ c, const GemmJ
 }
 
 // ------------------------------- FP64 ---------------------------------------------
-template <int RB, int CTM, int PF>
+// Branch-free main loop: the planner pads rows to whole work-group tiles (zero rows),
+// K' to a multiple of 64 and gives every cell of a context the same column-tile count,
+// so every wave runs full RB x CT tiles over the whole K; the prefetch index is clamped
+// to the last step instead of being predicated.
+template <int RB, int CT, int PF>
 __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jobs,
                                                   const double* __restrict__ A,
                                                   const double* __restrict__ B,
@@ -43,61 +47,49 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
-    const int nrb = min(RB, jb.mb - rbw);
-    const int nct = jb.ct;
     const int kp8 = jb.kp >> 3;
     const double2* a = (const double2*)(A + jb.a_off) + (int64_t)rbw * kp8 * 64 + lane;
     const double2* b = (const double2*)(B + jb.b_off) + lane;
-    d4_t acc[RB][CTM];
+    d4_t acc[RB][CT];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CTM; ++c) acc[r][c] = (d4_t){0, 0, 0, 0};
-    double2 ab[PF][RB], bb[PF][CTM];
+        for (int c = 0; c < CT; ++c) acc[r][c] = (d4_t){0, 0, 0, 0};
+    double2 ab[PF][RB], bb[PF][CT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
-            ab[u][r] = (r < nrb && u < kp8) ? a[((int64_t)r * kp8 + u) * 64] : make_double2(0, 0);
+        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kp8 + u) * 64];
 #pragma unroll
-        for (int c = 0; c < CTM; ++c)
-            bb[u][c] = (c < nct && u < kp8) ? b[((int64_t)c * kp8 + u) * 64] : make_double2(0, 0);
+        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + u) * 64];
     }
     for (int p0 = 0; p0 < kp8; p0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
-            const double2* av = ab[u];
-            const double2* bv = bb[u];
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int c = 0; c < CTM; ++c) {
-                    if (r < nrb && c < nct && p0 + u < kp8) {
-                        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r].x, bv[c].x, acc[r][c], 0, 0, 0);
-                        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r].y, bv[c].y, acc[r][c], 0, 0, 0);
-                    }
-                }
-            const int pn = p0 + u + PF;
-            if (pn < kp8) {
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
-                    if (r < nrb) ab[u][r] = a[((int64_t)r * kp8 + pn) * 64];
 #pragma unroll
-                for (int c = 0; c < CTM; ++c)
-                    if (c < nct) bb[u][c] = b[((int64_t)c * kp8 + pn) * 64];
-            }
+                    for (int c = 0; c < CT; ++c)
+                        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            h ? ab[u][r].y : ab[u][r].x, h ? bb[u][c].y : bb[u][c].x, acc[r][c], 0, 0, 0);
+            const int pn = min(p0 + u + PF, kp8 - 1);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kp8 + pn) * 64];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pn) * 64];
         }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CTM; ++c)
-            if (r < nrb && c < nct) store_c_f64(C, jb, rbw + r, c, lane, acc[r][c]);
+        for (int c = 0; c < CT; ++c) store_c_f64(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
 // ------------------------------- FP32 ---------------------------------------------
 // FP32 MFMA with FP32 accumulation inside chunks of KCH*16 real k, FP64 across chunks.
-template <int RB, int CTM, int PF, int KCH>
+template <int RB, int CT, int PF, int KCH>
 __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jobs,
                                                   const float* __restrict__ A,
                                                   const float* __restrict__ B,
@@ -106,60 +98,50 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
-    const int nrb = min(RB, jb.mb - rbw);
-    const int nct = jb.ct;
     const int kq = jb.kp >> 4;
     const float4* a = (const float4*)(A + jb.a_off) + (int64_t)rbw * kq * 64 + lane;
     const float4* b = (const float4*)(B + jb.b_off) + lane;
-    d4_t acc[RB][CTM];
-    f4_t ac32[RB][CTM];
+    d4_t acc[RB][CT];
+    f4_t ac32[RB][CT];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CTM; ++c) {
+        for (int c = 0; c < CT; ++c) {
             acc[r][c] = (d4_t){0, 0, 0, 0};
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
-    float4 ab[PF][RB], bb[PF][CTM];
-    const float4 z4 = make_float4(0, 0, 0, 0);
+    float4 ab[PF][RB], bb[PF][CT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = (r < nrb && u < kq) ? a[((int64_t)r * kq + u) * 64] : z4;
+        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kq + u) * 64];
 #pragma unroll
-        for (int c = 0; c < CTM; ++c) bb[u][c] = (c < nct && u < kq) ? b[((int64_t)c * kq + u) * 64] : z4;
+        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + u) * 64];
     }
     for (int q0 = 0; q0 < kq; q0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int c = 0; c < CTM; ++c) {
-                    if (r < nrb && c < nct && q0 + u < kq) {
-                        f4_t t = ac32[r][c];
-                        t = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[u][r].x, bb[u][c].x, t, 0, 0, 0);
-                        t = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[u][r].y, bb[u][c].y, t, 0, 0, 0);
-                        t = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[u][r].z, bb[u][c].z, t, 0, 0, 0);
-                        t = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[u][r].w, bb[u][c].w, t, 0, 0, 0);
-                        ac32[r][c] = t;
-                    }
-                }
-            const int qn = q0 + u + PF;
-            if (qn < kq) {
+            for (int h = 0; h < 4; ++h)
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
-                    if (r < nrb) ab[u][r] = a[((int64_t)r * kq + qn) * 64];
 #pragma unroll
-                for (int c = 0; c < CTM; ++c)
-                    if (c < nct) bb[u][c] = b[((int64_t)c * kq + qn) * 64];
-            }
+                    for (int c = 0; c < CT; ++c) {
+                        const float av = h == 0 ? ab[u][r].x : h == 1 ? ab[u][r].y : h == 2 ? ab[u][r].z : ab[u][r].w;
+                        const float bv = h == 0 ? bb[u][c].x : h == 1 ? bb[u][c].y : h == 2 ? bb[u][c].z : bb[u][c].w;
+                        ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, ac32[r][c], 0, 0, 0);
+                    }
+            const int qn = min(q0 + u + PF, kq - 1);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kq + qn) * 64];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qn) * 64];
         }
         if (((q0 + PF) % KCH) == 0 || q0 + PF >= kq) {
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int c = 0; c < CTM; ++c) {
+                for (int c = 0; c < CT; ++c) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc[r][c][j] += (double)ac32[r][c][j];
                     ac32[r][c] = (f4_t){0, 0, 0, 0};
@@ -169,14 +151,13 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CTM; ++c)
-            if (r < nrb && c < nct) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+        for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
 // ------------------------------- split BF16 ---------------------------------------
-// G ~ G_hi + G_lo, f ~ f_hi + f_lo; products hi*hi + hi*lo + lo*hi on BF16 MFMA with
+// G ~ G_hi + G_lo, f ~ f_hi + f_lo; products lo*hi + hi*lo + hi*hi on BF16 MFMA with
 // FP32 accumulation inside chunks of KCH*32 real k, FP64 across chunks.
-template <int RB, int CTM, int PF, int KCH>
+template <int RB, int CT, int PF, int KCH>
 __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ jobs,
                                                    const unsigned short* __restrict__ A,
                                                    const unsigned short* __restrict__ B,
@@ -185,36 +166,31 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
-    const int nrb = min(RB, jb.mb - rbw);
-    const int nct = jb.ct;
     const int kt = jb.kp >> 5;
     // 16-byte units: per (block, t): hi run of 64 units then lo run of 64 units
     const bf8_t* a = (const bf8_t*)(A + jb.a_off) + (int64_t)rbw * kt * 128 + lane;
     const bf8_t* b = (const bf8_t*)(B + jb.b_off) + lane;
-    d4_t acc[RB][CTM];
-    f4_t ac32[RB][CTM];
+    d4_t acc[RB][CT];
+    f4_t ac32[RB][CT];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CTM; ++c) {
+        for (int c = 0; c < CT; ++c) {
             acc[r][c] = (d4_t){0, 0, 0, 0};
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
-    bf8_t ah[PF][RB], al[PF][RB], bh[PF][CTM], bl[PF][CTM];
-    bf8_t zb;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) zb[j] = (__bf16)0.0f;
+    bf8_t ah[PF][RB], al[PF][RB], bh[PF][CT], bl[PF][CT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = (r < nrb && u < kt) ? a[((int64_t)r * kt + u) * 128] : zb;
-            al[u][r] = (r < nrb && u < kt) ? a[((int64_t)r * kt + u) * 128 + 64] : zb;
+            ah[u][r] = a[((int64_t)r * kt + u) * 128];
+            al[u][r] = a[((int64_t)r * kt + u) * 128 + 64];
         }
 #pragma unroll
-        for (int c = 0; c < CTM; ++c) {
-            bh[u][c] = (c < nct && u < kt) ? b[((int64_t)c * kt + u) * 128] : zb;
-            bl[u][c] = (c < nct && u < kt) ? b[((int64_t)c * kt + u) * 128 + 64] : zb;
+        for (int c = 0; c < CT; ++c) {
+            bh[u][c] = b[((int64_t)c * kt + u) * 128];
+            bl[u][c] = b[((int64_t)c * kt + u) * 128 + 64];
         }
     }
     for (int t0 = 0; t0 < kt; t0 += PF) {
@@ -223,36 +199,35 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int c = 0; c < CTM; ++c) {
-                    if (r < nrb && c < nct && t0 + u < kt) {
-                        f4_t t = ac32[r][c];
-                        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u][r], bh[u][c], t, 0, 0, 0);
-                        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][r], bl[u][c], t, 0, 0, 0);
-                        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][r], bh[u][c], t, 0, 0, 0);
-                        ac32[r][c] = t;
-                    }
-                }
-            const int tn = t0 + u + PF;
-            if (tn < kt) {
+                for (int c = 0; c < CT; ++c)
+                    ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u][r], bh[u][c], ac32[r][c], 0, 0, 0);
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (r < nrb) {
-                        ah[u][r] = a[((int64_t)r * kt + tn) * 128];
-                        al[u][r] = a[((int64_t)r * kt + tn) * 128 + 64];
-                    }
+            for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int c = 0; c < CTM; ++c)
-                    if (c < nct) {
-                        bh[u][c] = b[((int64_t)c * kt + tn) * 128];
-                        bl[u][c] = b[((int64_t)c * kt + tn) * 128 + 64];
-                    }
+                for (int c = 0; c < CT; ++c)
+                    ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][r], bl[u][c], ac32[r][c], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][r], bh[u][c], ac32[r][c], 0, 0, 0);
+            const int tn = min(t0 + u + PF, kt - 1);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                ah[u][r] = a[((int64_t)r * kt + tn) * 128];
+                al[u][r] = a[((int64_t)r * kt + tn) * 128 + 64];
+            }
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                bh[u][c] = b[((int64_t)c * kt + tn) * 128];
+                bl[u][c] = b[((int64_t)c * kt + tn) * 128 + 64];
             }
         }
         if (((t0 + PF) % KCH) == 0 || t0 + PF >= kt) {
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int c = 0; c < CTM; ++c) {
+                for (int c = 0; c < CT; ++c) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc[r][c][j] += (double)ac32[r][c][j];
                     ac32[r][c] = (f4_t){0, 0, 0, 0};
@@ -262,19 +237,18 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CTM; ++c)
-            if (r < nrb && c < nct) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+        for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
-// Row blocks per wave for a given column-tile count (register budget per lane).
+// Row blocks per wave for a given column-tile count (register budget per lane).  The
+// planner pads rows to 64*RB (a whole work-group tile) and K' to a multiple of 64.
 int gemm_rb(int form, int ctmax) {
     (void)form;
-    return ctmax <= 1 ? 4 : (ctmax <= 2 ? 4 : 2);
+    return ctmax <= 2 ? 4 : 2;
 }
 
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
-                 const void* a, const void* b, double* c, const double2*, const int32_t* const*,
-                 const int32_t* const*, const int32_t*, int, int, int) {
+                 const void* a, const void* b, double* c) {
     if (njobs <= 0) return;
     dim3 grid(njobs), blk(256);
 #define GEMM_CASE(KERN, RB, CT, ...)                                                           \
@@ -297,7 +271,117 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         if (ctmax <= 1) GEMM_CASE(k_gemm_bf16, 4, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_bf16, 4, 2, 2, 8);
         else if (ctmax <= 4) GEMM_CASE(k_gemm_bf16, 2, 4, 2, 8);
-        else GEMM_CASE(k_gemm_bf16, 2, 8, 1, 8);
+        else GEMM_CASE(k_gemm_bf16, 2, 8, 2, 8);
     }
 #undef GEMM_CASE
+}
+
+// ------------------------------- offset table (FP64) ------------------------------
+// No dense store: the blocks G^(m; n_b - n_i) are gathered from the table of distinct
+// column offsets (six symmetric complex components per offset, 96 bytes) into LDS, in
+// the FP64 MFMA fragment order, chunk by chunk of 8 interface columns (48 real k').  A
+// work group of two waves owns 32 pad columns (96 rows = 6 row blocks, 3 per wave) of
+// one mode; the B fragments of the chunk are staged in LDS once for both waves.
+#define DT_TB 32
+#define DT_TI 8
+template <int CT>
+__global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ jobs,
+                                                   const double2* __restrict__ tab,
+                                                   const double* __restrict__ B,
+                                                   double* __restrict__ C,
+                                                   const CellDev* __restrict__ cells,
+                                                   const int32_t* __restrict__ lut, int d1min,
+                                                   int d2min, int w2) {
+    __shared__ double As[6 * 6 * 128];          // [rb][p][lane][2]
+    __shared__ double Bs[CT * 6 * 128];         // [ct][p][lane][2]
+    __shared__ int scb[2 * DT_TB];
+    const GemmJob jb = jobs[blockIdx.x];
+    if (jb.mb == 0) return;
+    const CellDev cd = cells[jb.cell];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int b0 = (jb.rb0 / 6) * DT_TB;
+    if (tid < DT_TB) {
+        const int b = b0 + tid;
+        scb[2 * tid] = b < cd.n_b ? cd.cols_b[2 * b] : 0;
+        scb[2 * tid + 1] = b < cd.n_b ? cd.cols_b[2 * b + 1] : 0;
+    }
+    const double2* tm = tab + jb.a_off;
+    const double* bm = B + jb.b_off;
+    const int kp8 = jb.kp >> 3;
+    d4_t acc[3][CT];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[r][c] = (d4_t){0, 0, 0, 0};
+    __syncthreads();
+    for (int i0 = 0; i0 < cd.n_i; i0 += DT_TI) {
+        // gather 32 x 8 blocks, two per thread
+#pragma unroll
+        for (int q = tid; q < DT_TB * DT_TI; q += 128) {
+            const int bl = q >> 3, il = q & 7;
+            const int b = b0 + bl, i = i0 + il;
+            double2 v[6];
+            if (b < cd.n_b && i < cd.n_i) {
+                const int d1 = scb[2 * bl] - cd.cols_i[2 * i] - d1min;
+                const int d2 = scb[2 * bl + 1] - cd.cols_i[2 * i + 1] - d2min;
+                const double2* src = tm + (int64_t)lut[(int64_t)d1 * w2 + d2] * 6;
+#pragma unroll
+                for (int s = 0; s < 6; ++s) v[s] = src[s];
+            } else {
+#pragma unroll
+                for (int s = 0; s < 6; ++s) v[s] = make_double2(0, 0);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double2 x = v[sym_idx(c, d)];
+                    const int row = 3 * bl + c, kq = 6 * il + 2 * d;
+                    As[frag_off_f64(row, kq, 48)] = x.x;
+                    As[frag_off_f64(row, kq + 1, 48)] = x.y;
+                }
+        }
+        // B fragments of k' in [6 i0, 6 i0 + 48): 6 contiguous 1 KiB runs per column tile
+        const int p0 = (6 * i0) >> 3;
+        for (int e = tid; e < CT * 768; e += 128) {
+            const int ct = e / 768, x = e - ct * 768;
+            Bs[e] = bm[((int64_t)ct * kp8 + p0) * 128 + x];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            double2 av[3], bv[CT];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) av[r] = *(const double2*)&As[((3 * wave + r) * 6 + p) * 128 + 2 * lane];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) bv[c] = *(const double2*)&Bs[(c * 6 + p) * 128 + 2 * lane];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c)
+                        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(h ? av[r].y : av[r].x,
+                                                                         h ? bv[c].y : bv[c].x,
+                                                                         acc[r][c], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) store_c_f64(C, jb, jb.rb0 + 3 * wave + r, c, lane, acc[r][c]);
+}
+
+void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
+                      const double* b, double* c, const CellDev* cells, const int32_t* lut,
+                      int d1min, int d2min, int w2) {
+    if (njobs <= 0) return;
+    dim3 grid(njobs), blk(128);
+    switch (ct) {
+        case 1: hipLaunchKernelGGL(k_gemm_dtab<1>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
+        case 2: hipLaunchKernelGGL(k_gemm_dtab<2>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
+        case 4: hipLaunchKernelGGL(k_gemm_dtab<4>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
+        default: hipLaunchKernelGGL(k_gemm_dtab<8>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
+    }
 }

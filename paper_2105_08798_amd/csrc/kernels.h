@@ -17,13 +17,15 @@ void launch_transpose_c(hipStream_t st, const double2* in, double2* out, int bat
 void launch_gather_table(hipStream_t st, const double2* t, double2* tab, int nmc, int m1, int m2,
                          int64_t n_off, const int32_t* off_d1, const int32_t* off_d2,
                          int64_t tab_mode_stride, double scale);
-void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm, int64_t n_off,
-                    int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
+// Table modes are on the finest line grid of the context: cell mode m reads table mode
+// m * mode_mult.
+void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm, int mode_mult,
+                    int64_t n_off, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
                     const int32_t* lut, int d1min, int d2min, int w2);
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
-                        const double2* rowmean, int nm, int64_t n_off, int mp, int kp, int n_b,
-                        int n_i, const int32_t* cols_b, const int32_t* cols_i, const int32_t* lut,
-                        int d1min, int d2min, int w2);
+                        const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
+                        int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
+                        const int32_t* lut, int d1min, int d2min, int w2);
 
 // ---- apply (Section 2.3.2 update in line-mode form) ----
 void launch_netforce(hipStream_t st, const double* f, double* sums, int R, int nz, int n_i,
@@ -31,11 +33,15 @@ void launch_netforce(hipStream_t st, const double* f, double* sums, int R, int n
 void launch_line_rfft(hipStream_t st, int form, const double* f, const double* sums, int project,
                       void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw);
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
-                 const void* a, const void* b, double* c, const double2* tab,
-                 const int32_t* const* cols_b, const int32_t* const* cols_i, const int32_t* lut,
-                 int d1min, int d2min, int w2);
+                 const void* a, const void* b, double* c);
+// Offset-table form: 32 pad columns x all interface columns per work group, table
+// entries gathered into LDS in MFMA fragment order.
+void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
+                      const double* b, double* c, const CellDev* cells, const int32_t* lut,
+                      int d1min, int d2min, int w2);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
-                       int nz, int mp, int M, int ct, const double2* tw, int* n_part_out);
+                       int nz, int mp, int M, int ct, int ct_grid, const double2* tw,
+                       int* n_part_out);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status,
                  int* n_part_out);
