@@ -22,21 +22,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FBC boundary updates/sec + % MFMA/HBM roofline vs FP64 plain at 1e-6 rel err"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
-# bytes per complex entry of the stored G^ and of the B operand, per form
-G_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8}
-F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8}
-DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16 hi+lo (fp32 acc)"}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "dtable_fp64": 78.6}
+# bytes per complex entry of the stored G^ and of the B operand, per form (the offset
+# table form reads its table, whose size the library reports, instead of dense blocks)
+G_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "dtable_fp64": None}
+F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "dtable_fp64": 16}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16 hi+lo (fp32 acc)", "dtable_fp64": "f64"}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(cell, form: str) -> dict:
+def algorithmic(cell, form: str, store_bytes: int) -> dict:
     nm = cell.nz // 2 + 1
     M, K, R = 3 * cell.n_b, 3 * cell.n_i, cell.n_rhs
-    g = nm * M * K * G_BYTES[form]
+    g = nm * M * K * G_BYTES[form] if G_BYTES[form] else store_bytes
     fh = nm * R * K * F_BYTES[form]
     uh = nm * R * M * 16
     return dict(gemm_bytes=g + fh + uh, gemm_flops=8.0 * nm * M * K * R,
@@ -87,6 +88,7 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool) -> dic
     dt = time.perf_counter() - t0
     gemm_ms, n_gemm = ctx.timing_read()
     ctx.timing(False)
+    store_bytes = ctx.info.store_bytes
     rc = ctx.sync_status()
     if rc != 0:
         raise RuntimeError(f"{form}: status {rc} after the timed region")
@@ -99,6 +101,7 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool) -> dic
     torch.cuda.empty_cache()
     ms = 1000.0 * dt / steps
     out = dict(ms_per_step=ms, updates_per_s=c.n_rhs / (ms / 1000.0), assembly_s=t_asm,
+               store_bytes=int(store_bytes),
                gemm_ms=(gemm_ms / n_gemm) if n_gemm else None, gemm_launches_timed=n_gemm,
                graph=bool(graph))
     log(f"{form}: {ms:.3f} ms/step, GEMM {out['gemm_ms']} ms, {out['updates_per_s']:.1f} updates/s")
@@ -169,8 +172,8 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design for sharding pad rows across GPUs is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
         return 2
 
     import torch
@@ -203,7 +206,7 @@ def main() -> int:
     gold = np.load(samples) if os.path.exists(samples) else None
     out_forms = {}
     for form, r in res.items():
-        alg = algorithmic(c, form)
+        alg = algorithmic(c, form, r["store_bytes"])
         e_fp64 = rel_err(r["w"], ref_w) if (ref_w is not None and form != "fp64") else (0.0 if form == "fp64" else None)
         e_or = None
         if gold is not None:
@@ -218,12 +221,12 @@ def main() -> int:
             gemm_mfma_frac=(gemm_tfs / PEAK_TFLOPS[form]) if gemm_tfs else None,
             call_GBs=alg["call_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9,
             rel_err_vs_fp64_gpu=e_fp64, rel_err_vs_oracle_samples=e_or,
-            assembly_s=r["assembly_s"], graph=r["graph"])
+            assembly_s=r["assembly_s"], graph=r["graph"], store_GB=r["store_bytes"] / 1e9)
     ok = [f for f in out_forms if f == "fp64" or (out_forms[f]["rel_err_vs_oracle_samples"] or
                                                   out_forms[f]["rel_err_vs_fp64_gpu"] or 1.0) <= 1e-6]
     head = max(ok, key=lambda f: out_forms[f]["updates_per_s"]) if ok else forms[0]
     h = out_forms[head]
-    alg = algorithmic(c, head)
+    alg = algorithmic(c, head, res[head]["store_bytes"])
     roof = dict(bound="hbm", achieved=h["gemm_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=h["gemm_hbm_frac"], traffic=None, kernel=f"k_gemm ({head})",
                 bytes_per_launch=alg["gemm_bytes"])

@@ -36,6 +36,7 @@ struct fbc_ctx {
     int* status = nullptr;          // device latch
     GemmJob* jobs = nullptr;
     int njobs = 0;
+    int nsplit = 1;                 // K slices of the per-mode product
     int64_t scratch_bytes = 0;
     int64_t n_offsets = 0;
     // offset table (kept for the offset-table form)
@@ -376,18 +377,22 @@ static std::vector<GemmJob> build_jobs_dtab(const fbc_ctx* c) {
             if (t % mult) continue;
             const int m = t / mult;
             const int tiles = p.mp / 96;
-            for (int tl = 0; tl < tiles; ++tl) {
-                GemmJob j{};
-                j.a_off = (int64_t)t * c->n_offsets * 6;
-                j.b_off = p.b_off + (int64_t)m * b_mode_elems(FBC_FORM_DTABLE_FP64, p);
-                j.c_off = p.c_off + (int64_t)m * p.ct * p.mp * 16;
-                j.mb = p.mp / 16;
-                j.kp = p.kp;
-                j.rb0 = 6 * tl;
-                j.ct = p.ct;
-                j.cell = ci;
-                out.push_back(j);
-            }
+            const int nch = (p.n_i + 7) / 8;
+            for (int ks = 0; ks < c->nsplit; ++ks)
+                for (int tl = 0; tl < tiles; ++tl) {
+                    GemmJob j{};
+                    j.a_off = (int64_t)t * c->n_offsets * 6;
+                    j.b_off = p.b_off + (int64_t)m * b_mode_elems(FBC_FORM_DTABLE_FP64, p);
+                    j.c_off = p.c_off + ks * p.c_split + (int64_t)m * p.ct * p.mp * 16;
+                    j.mb = p.mp / 16;
+                    j.kp = p.kp;
+                    j.rb0 = 6 * tl;
+                    j.ct = p.ct;
+                    j.cell = ci;
+                    j.k0 = 8 * (int)((int64_t)nch * ks / c->nsplit);
+                    j.k1 = 8 * (int)((int64_t)nch * (ks + 1) / c->nsplit);
+                    out.push_back(j);
+                }
         }
     return out;
 }
@@ -411,19 +416,23 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c) {
     for (const Unit& u : units) {
         int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         const CellPlan& p = c->cells[u.cell];
-        for (int t = 0; t < u.tiles; ++t) {
-            GemmJob j{};
-            j.a_off = p.a_off + (int64_t)u.m * store_mode_elems(form, p);
-            j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
-            j.c_off = p.c_off + (int64_t)u.m * p.ct * p.mp * 16;
-            j.mb = p.mp / 16;
-            j.kp = p.kp;
-            j.rb0 = t * tile_rb;
-            j.ct = p.ct;
-            j.cell = u.cell;
-            per_xcd[x].push_back(j);
-        }
-        load[x] += u.tiles;
+        const int nch = p.kp / 64;
+        for (int ks = 0; ks < c->nsplit; ++ks)
+            for (int t = 0; t < u.tiles; ++t) {
+                GemmJob j{};
+                j.a_off = p.a_off + (int64_t)u.m * store_mode_elems(form, p);
+                j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
+                j.c_off = p.c_off + ks * p.c_split + (int64_t)u.m * p.ct * p.mp * 16;
+                j.mb = p.mp / 16;
+                j.kp = p.kp;
+                j.rb0 = t * tile_rb;
+                j.ct = p.ct;
+                j.cell = u.cell;
+                j.k0 = 64 * (int)((int64_t)nch * ks / c->nsplit);
+                j.k1 = 64 * (int)((int64_t)nch * (ks + 1) / c->nsplit);
+                per_xcd[x].push_back(j);
+            }
+        load[x] += (int64_t)u.tiles * c->nsplit;
     }
     size_t mx = 0;
     for (auto& v : per_xcd) mx = std::max(mx, v.size());
@@ -482,6 +491,8 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     c->ctmax = ctl;
     int64_t f_off = 0, u_off = 0, a_off = 0, b_off = 0, c_off = 0, w_off = 0;
     int rhs0 = 0;
+    int64_t tiles_total = 0;   // (cell, mode, row tile) work items before the K split
+    int kslices_max = 1 << 30;
     for (int i = 0; i < n_cells; ++i) {
         CellPlan p{};
         p.nz = cells[i].nz;
@@ -513,11 +524,31 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         u_off += (int64_t)p.R * p.nz * p.M;
         a_off += store_mode_elems(form, p) * p.nm;
         b_off += b_mode_elems(form, p) * p.nm;
-        c_off += (int64_t)p.nm * p.ct * p.mp * 16;
+        p.c_split = (int64_t)p.nm * p.ct * p.mp * 16;
+        if (form == FBC_FORM_DTABLE_FP64) {
+            tiles_total += (int64_t)p.nm * (p.mp / 96);
+            kslices_max = std::min(kslices_max, (p.n_i + 7) / 8);
+        } else {
+            tiles_total += (int64_t)p.nm * (p.mp / rows_tile);
+            kslices_max = std::min(kslices_max, p.kp / 64);
+        }
         w_off += (int64_t)p.R * p.M * p.nz;
         rhs0 += p.R;
         c->nz_max = std::max(c->nz_max, p.nz);
         c->cells.push_back(p);
+    }
+    // K slices: enough work items for several rounds of the resident work groups
+    // (256 CUs x 3 groups), so the last round leaves little of the chip idle
+    {
+        const int64_t want = 6 * 768;
+        int ks = (int)std::min<int64_t>((want + tiles_total - 1) / tiles_total, kslices_max);
+        c->nsplit = std::max(1, std::min(ks, 8));
+        int64_t co = 0;
+        for (auto& p : c->cells) {
+            p.c_off = co;
+            co += p.c_split * c->nsplit;
+        }
+        c_off = co;
     }
     c->total_rhs = rhs0;
     c->f_elems = f_off;
@@ -665,7 +696,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
-                          p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, nullptr);
+                          p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split, nullptr);
     }
 }
 
@@ -810,7 +841,7 @@ extern "C" fbc_status fbc_copy_block_rows(fbc_ctx* c, int cell, int m, int b0, i
     const int rows = 3 * (b1 - b0);
     for (int r = 0; r < rows; ++r)
         for (int k = 0; k < 6 * p.n_i; ++k)
-            out[(int64_t)r * 6 * p.n_i + k] = blk[frag_off_f64(3 * b0 + r, k, p.kp)];
+            out[(int64_t)r * 6 * p.n_i + k] = blk[frag_off_f64_km(3 * b0 + r, k, p.mp)];
     return FBC_OK;
 }
 

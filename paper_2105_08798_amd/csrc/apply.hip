@@ -8,6 +8,12 @@
 
 #define NT 256
 
+// Blocks of an elementwise grid-stride launch (a launch holds at most 2^32 work-items).
+static inline int64_t grid_blocks(int64_t n) {
+    const int64_t b = (n + NT - 1) / NT;
+    return b < (1 << 20) ? (b > 0 ? b : 1) : (1 << 20);
+}
+
 // Block-wide sum of `nv` doubles per thread (in place in v), fixed order.
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV], double* red) {
@@ -200,7 +206,8 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    double* __restrict__ w,
                                                    double* __restrict__ wmax_part, int R, int nz,
                                                    int logn, int mp, int M, int ct, int tr, int pp,
-                                                   const double2* __restrict__ tw) {
+                                                   const double2* __restrict__ tw, int nsplit,
+                                                   int64_t split_stride) {
     extern __shared__ double2 lds[];
     const int row0 = blockIdx.x * tr;
     const int tile = blockIdx.y;
@@ -218,6 +225,13 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
             const int mm = (m < nm) ? m : nz - m;
             const double* src = c + mm * mode_stride + ((int64_t)tile * mp + row) * 16;
             double ar = src[ja], ai = src[ja + 8], br = src[ja + 1], bi = src[ja + 9];
+            for (int ks = 1; ks < nsplit; ++ks) {      // K slices, summed in fixed order
+                const double* q = src + ks * split_stride;
+                ar += q[ja];
+                ai += q[ja + 8];
+                br += q[ja + 1];
+                bi += q[ja + 9];
+            }
             if (mm == 0 || 2 * mm == nz) { ai = 0.0; bi = 0.0; }
             if (m >= nm) { ai = -ai; bi = -bi; }
             z = make_double2(ar - bi, ai + br);     // U_a + i U_b
@@ -259,8 +273,8 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
 }
 
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
-                       int nz, int mp, int M, int ct, int ct_grid, const double2* tw,
-                       int* n_part_out) {
+                       int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
+                       int64_t split_stride, int* n_part_out) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int pp, tr;
@@ -276,7 +290,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
     size_t lds = (size_t)tr * pp * nz * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
     hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,
-                       ct, tr, pp, tw);
+                       ct, tr, pp, tw, nsplit, split_stride);
     if (n_part_out) *n_part_out = (int)grid.x;
 }
 
@@ -348,11 +362,12 @@ __global__ void __launch_bounds__(NT) k_mean_sub(double* __restrict__ u,
                                                  const double* __restrict__ mean, int64_t per_rhs,
                                                  int R, const int* __restrict__ status) {
     if (status && *status) return;
-    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (idx >= per_rhs * R) return;
-    const int r = (int)(idx / per_rhs);
-    const int64_t e = idx - (int64_t)r * per_rhs;
-    u[idx] -= mean[r * 3 + (int)(e % 3)];
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < per_rhs * R;
+         idx += (int64_t)gridDim.x * NT) {
+        const int r = (int)(idx / per_rhs);
+        const int64_t e = idx - (int64_t)r * per_rhs;
+        u[idx] -= mean[r * 3 + (int)(e % 3)];
+    }
 }
 
 void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, double* mean_out,
@@ -362,7 +377,7 @@ void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, 
                        status);
     const int64_t per_rhs = (int64_t)nz * M;
     const int64_t total = per_rhs * R;
-    hipLaunchKernelGGL(k_mean_sub, dim3((unsigned)((total + NT - 1) / NT)), dim3(NT), 0, st, u,
+    hipLaunchKernelGGL(k_mean_sub, dim3((unsigned)grid_blocks(total)), dim3(NT), 0, st, u,
                        mean_out, per_rhs, R, status);
 }
 
@@ -469,8 +484,8 @@ void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, dou
 
 __global__ void __launch_bounds__(NT) k_copy(const double* __restrict__ a, double* __restrict__ b,
                                              int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i < n) b[i] = a[i];
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        b[i] = a[i];
 }
 
 __global__ void k_relax_out(const double* __restrict__ alpha_d, const double* __restrict__ finf_d,
@@ -491,7 +506,7 @@ __global__ void k_relax_out(const double* __restrict__ alpha_d, const double* __
 void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,
                          const double* alpha_d, const double* finf_d, const double* stepinf_d,
                          const double* mean_d, fbc_relax_out* out, int R, int k, double tol_f) {
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, fnew, fprev,
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)grid_blocks(n)), dim3(NT), 0, st, fnew, fprev,
                        n);
     if (out)
         hipLaunchKernelGGL(k_relax_out, dim3((R + 63) / 64), dim3(64), 0, st, alpha_d, finf_d,
@@ -499,11 +514,11 @@ void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int6
 }
 
 __global__ void k_fill(double* p, int64_t n, double v) {
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        p[i] = v;
 }
 
 void launch_fill(hipStream_t st, double* p, int64_t n, double v) {
     if (n > 0)
-        hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, p, n, v);
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)grid_blocks(n)), dim3(NT), 0, st, p, n, v);
 }

@@ -2,6 +2,8 @@
 // transform of the inverted force-constant symbol, here a discrete Brillouin-zone sum
 // over an M1 x M2 in-plane torus for every line mode m; Section 3.2: blocks depend only
 // on the column offset, so one table over distinct offsets feeds every store form).
+#include <algorithm>
+
 #include "fft_lds.h"
 #include "kernels.h"
 
@@ -257,40 +259,41 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
                                                      const int32_t* __restrict__ lut, int d1min,
                                                      int d2min, int w2) {
     const int64_t per_mode = (int64_t)mp * kp;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= per_mode * nm) return;
+    const int64_t total = per_mode * nm;
+    // grid-stride: the element count can exceed the 2^32 work-items of one launch
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
     const int m = (int)(e / per_mode);
     const int64_t x = e - (int64_t)m * per_mode;
-    if (form == FBC_FORM_FP64) {
+    const int mb = mp >> 4;
+    if (form == FBC_FORM_FP64) {          // [p][blk][lane][2]
         const int s = (int)(x & 1), lane = (int)((x >> 1) & 63);
         const int64_t rest = x >> 7;
-        const int kp8 = kp >> 3;
-        const int p = (int)(rest % kp8), blk = (int)(rest / kp8);
+        const int blk = (int)(rest % mb), p = (int)(rest / mb);
         const int row = 16 * blk + (lane & 15), kq = 8 * p + 4 * s + (lane >> 4);
-        ((double*)store)[e] = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
-                                          cols_i, lut, d1min, d2min, w2);
-    } else if (form == FBC_FORM_FP32) {
+        ((double*)store)[e] = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i,
+                                          cols_b, cols_i, lut, d1min, d2min, w2);
+    } else if (form == FBC_FORM_FP32) {   // [q][blk][lane][4]
         const int s = (int)(x & 3), lane = (int)((x >> 2) & 63);
         const int64_t rest = x >> 8;
-        const int kp16 = kp >> 4;
-        const int q = (int)(rest % kp16), blk = (int)(rest / kp16);
+        const int blk = (int)(rest % mb), q = (int)(rest / mb);
         const int row = 16 * blk + (lane & 15), kq = 16 * q + 4 * s + (lane >> 4);
-        ((float*)store)[e] = (float)dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
-                                                cols_i, lut, d1min, d2min, w2);
-    } else {  // split BF16: x indexes hi parts only; lo is written 512 elements later
+        ((float*)store)[e] = (float)dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b,
+                                                n_i, cols_b, cols_i, lut, d1min, d2min, w2);
+    } else {  // split BF16 [t][blk][hi/lo][lane][8]: x indexes hi parts; lo is 512 later
         const int j = (int)(x & 7), lane = (int)((x >> 3) & 63);
         const int64_t rest = x >> 9;
-        const int kp32 = kp >> 5;
-        const int t = (int)(rest % kp32), blk = (int)(rest / kp32);
+        const int blk = (int)(rest % mb), t = (int)(rest / mb);
         const int row = 16 * blk + (lane & 15), kq = 32 * t + 8 * (lane >> 4) + j;
-        const double v = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b, cols_i,
-                                     lut, d1min, d2min, w2);
+        const double v = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
+                                     cols_i, lut, d1min, d2min, w2);
         const unsigned short hi = f32_to_bf16_rne((float)v);
         const unsigned short lo = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(hi)));
         unsigned short* out = (unsigned short*)store + (int64_t)m * per_mode * 2;
-        const int64_t base = ((((int64_t)blk * kp32 + t) * 2) * 64 + lane) * 8 + j;
+        const int64_t base = ((((int64_t)t * mb + blk) * 2) * 64 + lane) * 8 + j;
         out[base] = hi;
         out[base + 512] = lo;
+    }
     }
 }
 
@@ -299,7 +302,8 @@ void launch_build_dense(hipStream_t st, int form, void* store, const double2* ta
                         int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
                         const int32_t* lut, int d1min, int d2min, int w2) {
     const int64_t total = (int64_t)mp * kp * nm;
-    hipLaunchKernelGGL(k_build_dense, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_build_dense, dim3((unsigned)blocks), dim3(256), 0, st,
                        form, store, tab, rowmean, nm, mode_mult, n_off, mp, kp, n_b, n_i, cols_b,
                        cols_i, lut, d1min, d2min, w2);
 }

@@ -42,6 +42,15 @@ __host__ __device__ inline int64_t frag_off_bf16(int64_t r, int64_t k, int64_t k
     return ((((blk * (kp >> 5) + (k >> 5)) * 2) * 64 + lane) << 3) + (kk & 7);
 }
 
+// The dense G^ stores use the same lane map but are K-major across row blocks,
+// [k step][row block][lane], so the work groups of one mode, which advance through K at
+// about the same rate, read neighbouring addresses at any moment.
+__host__ __device__ inline int64_t frag_off_f64_km(int64_t r, int64_t k, int64_t mp) {
+    int64_t blk = r >> 4, rr = r & 15;
+    int64_t lane = ((k & 3) << 4) | rr;
+    return ((((k >> 3) * (mp >> 4) + blk) * 64 + lane) << 1) + ((k >> 2) & 1);
+}
+
 // Symmetric 3x3 component index: xx yy zz xy xz yz
 __host__ __device__ inline int sym_idx(int c, int d) {
     if (c == d) return c;
@@ -49,17 +58,20 @@ __host__ __device__ inline int sym_idx(int c, int d) {
     return (lo == 0) ? (hi == 1 ? 3 : 4) : 5;
 }
 
-// One work item of the per-mode complex product: a tile of 4*RB row blocks of
-// one mode of one cell.  Offsets are in elements of the respective arrays.
+// One work item of the per-mode complex product: a tile of 4*RB row blocks of one mode
+// of one cell over one slice of K (the K split keeps enough work items to fill the chip
+// evenly; the partial products of the slices are summed in fixed order by the inverse
+// line transform).  Offsets are in elements of the respective arrays.
 struct GemmJob {
     int64_t a_off;   // A store (dense forms) or table mode base (offset form)
     int64_t b_off;   // B fragments of this mode
-    int64_t c_off;   // output [ct][mp][16] doubles of this mode
+    int64_t c_off;   // output [ct][mp][16] doubles of this mode and K slice
     int32_t mb;      // row blocks of the mode (mp / 16)
-    int32_t kp;      // padded K' (multiple of 64)
+    int32_t kp;      // padded K' (row stride of the fragment arrays)
     int32_t rb0;     // first row block of this tile
     int32_t ct;      // column tiles (8 RHS each)
     int32_t cell;    // cell index (offset form)
+    int32_t k0, k1;  // K' slice [k0, k1) (dense forms) or interface columns [k0, k1)
     int32_t pad;
 };
 
@@ -83,7 +95,8 @@ struct CellPlan {
     int64_t f_off, u_off;        // offsets (doubles) into caller's f and u
     int64_t a_off;               // dense store offset (elements of the store type) of mode 0
     int64_t b_off;               // B fragments offset (elements) of mode 0
-    int64_t c_off;               // GEMM output offset (doubles) of mode 0
+    int64_t c_off;               // GEMM output offset (doubles) of mode 0, K slice 0
+    int64_t c_split;             // doubles per K slice of the GEMM output (nm*ct*mp*16)
     int64_t w_off;               // w scratch offset (doubles)
     int64_t t_off;               // f transpose scratch offset (doubles)
     int64_t red_off;             // reduction scratch offset (doubles)

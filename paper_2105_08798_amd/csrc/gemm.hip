@@ -48,7 +48,9 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
     const int kp8 = jb.kp >> 3;
-    const double2* a = (const double2*)(A + jb.a_off) + (int64_t)rbw * kp8 * 64 + lane;
+    const int pb = jb.k0 >> 3, pe = jb.k1 >> 3;
+    const int64_t mb = jb.mb;
+    const double2* a = (const double2*)(A + jb.a_off) + (int64_t)rbw * 64 + lane;   // K-major
     const double2* b = (const double2*)(B + jb.b_off) + lane;
     d4_t acc[RB][CT];
 #pragma unroll
@@ -59,11 +61,11 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kp8 + u) * 64];
+        for (int r = 0; r < RB; ++r) ab[u][r] = a[((pb + u) * mb + r) * 64];
 #pragma unroll
-        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + u) * 64];
+        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pb + u) * 64];
     }
-    for (int p0 = 0; p0 < kp8; p0 += PF) {
+    for (int p0 = pb; p0 < pe; p0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
 #pragma unroll
@@ -74,9 +76,9 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
                     for (int c = 0; c < CT; ++c)
                         acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                             h ? ab[u][r].y : ab[u][r].x, h ? bb[u][c].y : bb[u][c].x, acc[r][c], 0, 0, 0);
-            const int pn = min(p0 + u + PF, kp8 - 1);
+            const int pn = min(p0 + u + PF, pe - 1);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kp8 + pn) * 64];
+            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)pn * mb + r) * 64];
 #pragma unroll
             for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pn) * 64];
         }
@@ -99,7 +101,9 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
     const int kq = jb.kp >> 4;
-    const float4* a = (const float4*)(A + jb.a_off) + (int64_t)rbw * kq * 64 + lane;
+    const int qb = jb.k0 >> 4, qe = jb.k1 >> 4;
+    const int64_t mb = jb.mb;
+    const float4* a = (const float4*)(A + jb.a_off) + (int64_t)rbw * 64 + lane;     // K-major
     const float4* b = (const float4*)(B + jb.b_off) + lane;
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
@@ -114,11 +118,11 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kq + u) * 64];
+        for (int r = 0; r < RB; ++r) ab[u][r] = a[((qb + u) * mb + r) * 64];
 #pragma unroll
-        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + u) * 64];
+        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qb + u) * 64];
     }
-    for (int q0 = 0; q0 < kq; q0 += PF) {
+    for (int q0 = qb; q0 < qe; q0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
 #pragma unroll
@@ -131,13 +135,13 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
                         const float bv = h == 0 ? bb[u][c].x : h == 1 ? bb[u][c].y : h == 2 ? bb[u][c].z : bb[u][c].w;
                         ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, ac32[r][c], 0, 0, 0);
                     }
-            const int qn = min(q0 + u + PF, kq - 1);
+            const int qn = min(q0 + u + PF, qe - 1);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)r * kq + qn) * 64];
+            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)qn * mb + r) * 64];
 #pragma unroll
             for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qn) * 64];
         }
-        if (((q0 + PF) % KCH) == 0 || q0 + PF >= kq) {
+        if (((q0 - qb + PF) % KCH) == 0 || q0 + PF >= qe) {
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -167,8 +171,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
     const int kt = jb.kp >> 5;
+    const int tb = jb.k0 >> 5, te = jb.k1 >> 5;
     // 16-byte units: per (block, t): hi run of 64 units then lo run of 64 units
-    const bf8_t* a = (const bf8_t*)(A + jb.a_off) + (int64_t)rbw * kt * 128 + lane;
+    const int64_t mb = jb.mb;
+    const bf8_t* a = (const bf8_t*)(A + jb.a_off) + (int64_t)rbw * 128 + lane;      // K-major
     const bf8_t* b = (const bf8_t*)(B + jb.b_off) + lane;
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
@@ -184,16 +190,16 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
     for (int u = 0; u < PF; ++u) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = a[((int64_t)r * kt + u) * 128];
-            al[u][r] = a[((int64_t)r * kt + u) * 128 + 64];
+            ah[u][r] = a[((tb + u) * mb + r) * 128];
+            al[u][r] = a[((tb + u) * mb + r) * 128 + 64];
         }
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-            bh[u][c] = b[((int64_t)c * kt + u) * 128];
-            bl[u][c] = b[((int64_t)c * kt + u) * 128 + 64];
+            bh[u][c] = b[((int64_t)c * kt + tb + u) * 128];
+            bl[u][c] = b[((int64_t)c * kt + tb + u) * 128 + 64];
         }
     }
-    for (int t0 = 0; t0 < kt; t0 += PF) {
+    for (int t0 = tb; t0 < te; t0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
 #pragma unroll
@@ -211,11 +217,11 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
                     ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][r], bh[u][c], ac32[r][c], 0, 0, 0);
-            const int tn = min(t0 + u + PF, kt - 1);
+            const int tn = min(t0 + u + PF, te - 1);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                ah[u][r] = a[((int64_t)r * kt + tn) * 128];
-                al[u][r] = a[((int64_t)r * kt + tn) * 128 + 64];
+                ah[u][r] = a[((int64_t)tn * mb + r) * 128];
+                al[u][r] = a[((int64_t)tn * mb + r) * 128 + 64];
             }
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
@@ -223,7 +229,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
                 bl[u][c] = b[((int64_t)c * kt + tn) * 128 + 64];
             }
         }
-        if (((t0 + PF) % KCH) == 0 || t0 + PF >= kt) {
+        if (((t0 - tb + PF) % KCH) == 0 || t0 + PF >= te) {
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -314,7 +320,7 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[r][c] = (d4_t){0, 0, 0, 0};
     __syncthreads();
-    for (int i0 = 0; i0 < cd.n_i; i0 += DT_TI) {
+    for (int i0 = jb.k0; i0 < jb.k1; i0 += DT_TI) {
         // gather 32 x 8 blocks, two per thread
 #pragma unroll
         for (int q = tid; q < DT_TB * DT_TI; q += 128) {

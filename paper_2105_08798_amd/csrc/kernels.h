@@ -40,8 +40,8 @@ void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, co
                       const double* b, double* c, const CellDev* cells, const int32_t* lut,
                       int d1min, int d2min, int w2);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
-                       int nz, int mp, int M, int ct, int ct_grid, const double2* tw,
-                       int* n_part_out);
+                       int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
+                       int64_t split_stride, int* n_part_out);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status,
                  int* n_part_out);

@@ -35,6 +35,7 @@ def rel_err(got, ref):
 
 @pytest.mark.parametrize("name,form,bound", [
     ("medium", "fp64", 1e-10), ("medium", "fp32", 1e-6), ("medium", "split_bf16", 2e-5),
+    ("medium", "dtable_fp64", 1e-10),
     ("large", "fp64", 1e-10), ("large", "split_bf16", 2e-5),
 ])
 def test_fullsize_green_apply_matches_oracle_samples(name, form, bound):

@@ -77,10 +77,14 @@ def split_cells(wl, flat):
     return out
 
 
+FP64_FORMS = ["fp64", "dtable_fp64"]
+
+
+@pytest.mark.parametrize("form", FP64_FORMS)
 @pytest.mark.parametrize("name", ["parity", "micro", "tiny"])
-def test_fp64_apply_matches_oracle(name):
+def test_fp64_apply_matches_oracle(name, form):
     wl = W.make_single(name)
-    rc, got, u0 = run_apply(wl, "fp64", alpha=0.7)
+    rc, got, u0 = run_apply(wl, form, alpha=0.7)
     assert rc == 0
     ref = oracle_update(wl, u0, 0.7)
     for g, r in zip(split_cells(wl, got), ref):
@@ -89,21 +93,25 @@ def test_fp64_apply_matches_oracle(name):
 
 
 @pytest.mark.parametrize("nz,n_i,n_b,R,bz", [(2, 7, 11, 1, 16), (32, 33, 50, 9, 32), (64, 21, 40, 17, 16),
-                                             (8, 1, 1, 2, 8)])
-def test_fp64_ragged_shapes(nz, n_i, n_b, R, bz):
+                                             (8, 1, 1, 2, 8), (16, 130, 260, 33, 64),
+                                             (8, 20, 30, 2, 2048), (256, 20, 30, 2, 32), (16, 50, 80, 64, 64),
+                                             (1024, 9, 13, 3, 16), (4, 12, 20, 1, 4096)])
+@pytest.mark.parametrize("form", FP64_FORMS)
+def test_fp64_ragged_shapes(nz, n_i, n_b, R, bz, form):
     wl = W.make_custom(nz, n_i, n_b, R, bz, seed=nz + n_i)
-    rc, got, u0 = run_apply(wl, "fp64", alpha=1.3)
+    rc, got, u0 = run_apply(wl, form, alpha=1.3)
     assert rc == 0
     ref = oracle_update(wl, u0, 1.3)
     e2, emax = rel_err(split_cells(wl, got)[0], ref[0])
     assert e2 < 1e-10 and emax < 1e-10, (e2, emax)
 
 
-def test_fp64_assembled_blocks_match_oracle():
+@pytest.mark.parametrize("form", FP64_FORMS)
+def test_fp64_assembled_blocks_match_oracle(form):
     _dev()
     wl = W.make_single("parity")
     c = wl.cells[0]
-    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    ctx = _ctx(wl.cells, wl.bz, form=form)
     g = oracle_green(c, wl.bz)
     for m in (0, 1, c.nz // 2):
         got = ctx.block_rows(0, m, 0, c.n_b, c.n_i)
@@ -127,15 +135,17 @@ def test_green_apply_is_raw_response():
     assert e2 < 1e-10 and emax < 1e-10
 
 
-def test_multi_cell_context_matches_per_cell_oracle():
+@pytest.mark.parametrize("form", FP64_FORMS + ["fp32"])
+def test_multi_cell_context_matches_per_cell_oracle(form):
     cells = W.make_custom(16, 30, 45, 3, 32, seed=1).cells + W.make_custom(8, 12, 20, 10, 32, seed=2).cells \
         + W.make_custom(32, 50, 60, 1, 32, seed=3).cells
     wl = W.Workload("three", cells, bz=32)
-    rc, got, u0 = run_apply(wl, "fp64", alpha=1.0)
+    rc, got, u0 = run_apply(wl, form, alpha=1.0)
     assert rc == 0
+    tol = 1e-10 if form != "fp32" else 1e-6
     for g, r in zip(split_cells(wl, got), oracle_update(wl, u0, 1.0)):
         e2, emax = rel_err(g, r)
-        assert e2 < 1e-10 and emax < 1e-10
+        assert e2 < tol and emax < tol, (form, e2, emax)
 
 
 def test_net_force_violation_latched_and_u_untouched():
@@ -167,12 +177,13 @@ def test_projection_of_net_force():
     assert e2 < 1e-10 and emax < 1e-10
 
 
-def test_relax_sequence_matches_oracle():
+@pytest.mark.parametrize("form", FP64_FORMS)
+def test_relax_sequence_matches_oracle(form):
     wl = W.make_single("parity")
     c = wl.cells[0]
     dev = _dev()
     from paper_2105_08798_amd import RELAX_OUT_DOUBLES, parse_relax_out
-    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    ctx = _ctx(wl.cells, wl.bz, form=form)
     g = oracle_green(c, wl.bz)
     rng = np.random.default_rng(11)
     # residual sequence with partly contracting, partly rotating directions
