@@ -130,6 +130,27 @@ fbc_status fbc_apply(fbc_ctx* ctx, const double* f, double* u, double alpha, voi
  * raw harmonic response w = G^{p|i+} f (the matrix-vector product of Section 3.2). */
 fbc_status fbc_green_apply(fbc_ctx* ctx, const double* f, double* w, void* stream);
 
+/* fbc_apply replayed from a HIP graph: the first call with a given (f, u, alpha, stream)
+ * captures the whole kernel sequence of fbc_apply into a graph (one launch per update
+ * afterwards); a call with other arguments re-captures.  stream must be a created
+ * (non-default) stream that is not itself capturing.  Same contract as fbc_apply. */
+fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alpha, void* stream);
+
+/* Autotuner of the per-mode product launch.  Times every candidate work list -- K split
+ * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times three
+ * orders: 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first
+ * -- with `reps` launches each on this context (input f, device; w, device, same layout
+ * as u, is overwritten with G f), keeps the fastest and reports it in *out (may be
+ * NULL).  Synchronises the stream. */
+typedef struct {
+    int nsplit;
+    int order;
+    double gemm_ms;       /* average product time of the chosen list */
+    int n_candidates;
+} fbc_tune_result;
+fbc_status fbc_autotune(fbc_ctx* ctx, const double* f, double* w, int reps, fbc_tune_result* out,
+                        void* stream);
+
 /* Residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2). */
 typedef struct {
     int relax;        /* 1: relax from the third iteration on (Algorithm 1 line 5)        */
@@ -167,6 +188,9 @@ typedef struct {
     int64_t scratch_bytes;     /* bytes of scratch owned by the context                   */
     int64_t f_elems, u_elems;  /* doubles expected in f and u                             */
     int64_t n_offsets;         /* distinct column offsets over all cells                  */
+    int nsplit;                /* K slices of the per-mode product launch                 */
+    int job_order;             /* work-list order (see fbc_autotune)                      */
+    int n_jobs;                /* work groups of the per-mode product launch              */
 } fbc_info;
 fbc_status fbc_get_info(const fbc_ctx* ctx, fbc_info* info);
 

@@ -12,6 +12,8 @@
 #include "kernels.h"
 
 int gemm_rb(int form, int ctmax);
+extern "C" fbc_status fbc_timing(fbc_ctx* c, int enable);
+extern "C" fbc_status fbc_timing_read(fbc_ctx* c, double* ms, int* n);
 
 struct fbc_ctx {
     int device = 0;
@@ -37,6 +39,16 @@ struct fbc_ctx {
     GemmJob* jobs = nullptr;
     int njobs = 0;
     int nsplit = 1;                 // K slices of the per-mode product
+    int nsplit_cap = 1;             // K slices the output buffer holds
+    int job_order = 0;              // see build_jobs
+    int64_t jobs_cap = 0;
+    // captured update (fbc_apply_graph)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const double* g_f = nullptr;
+    double* g_u = nullptr;
+    double g_alpha = 0.0;
+    void* g_stream = nullptr;
     int64_t scratch_bytes = 0;
     int64_t n_offsets = 0;
     // offset table (kept for the offset-table form)
@@ -361,82 +373,74 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
 }
 
 // ----------------------------------------------------------------------------------
-// Work list of the per-mode products: every (cell, mode) unit goes to one XCD (work
-// groups are dispatched round-robin over the 8 XCDs by block index), so the B
-// fragments of a mode are shared through that XCD's L2.
+// Work list of the per-mode products.  A unit is one (cell, mode); it expands into
+// row tiles x K slices.  Orders:
+//   0  XCD-grouped: units, longest first, go to the least-loaded XCD (work groups are
+//      dispatched round-robin over the 8 XCDs by block index), so the B fragments of a
+//      mode are shared through one XCD's L2;
+//   1  mode-major: units by table mode, so every XCD works on the same table slice;
+//   2  longest-first: units by cost, natural order.
 // ----------------------------------------------------------------------------------
-// Offset-table form: all tiles of one table mode are consecutive (every XCD works on the
-// same table slice at a time, which stays in the last-level cache).
-static std::vector<GemmJob> build_jobs_dtab(const fbc_ctx* c) {
-    std::vector<GemmJob> out;
-    const int T = c->nz_max / 2 + 1;
-    for (int t = 0; t < T; ++t)
-        for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
-            const CellPlan& p = c->cells[ci];
-            const int mult = c->nz_max / p.nz;
-            if (t % mult) continue;
-            const int m = t / mult;
-            const int tiles = p.mp / 96;
-            const int nch = (p.n_i + 7) / 8;
-            for (int ks = 0; ks < c->nsplit; ++ks)
-                for (int tl = 0; tl < tiles; ++tl) {
-                    GemmJob j{};
-                    j.a_off = (int64_t)t * c->n_offsets * 6;
-                    j.b_off = p.b_off + (int64_t)m * b_mode_elems(FBC_FORM_DTABLE_FP64, p);
-                    j.c_off = p.c_off + ks * p.c_split + (int64_t)m * p.ct * p.mp * 16;
-                    j.mb = p.mp / 16;
-                    j.kp = p.kp;
-                    j.rb0 = 6 * tl;
-                    j.ct = p.ct;
-                    j.cell = ci;
-                    j.k0 = 8 * (int)((int64_t)nch * ks / c->nsplit);
-                    j.k1 = 8 * (int)((int64_t)nch * (ks + 1) / c->nsplit);
-                    out.push_back(j);
-                }
+struct Unit {
+    int cell, m, t;
+    int64_t cost;
+};
+
+static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<GemmJob>& out) {
+    const int form = c->opt.form;
+    const CellPlan& p = c->cells[u.cell];
+    const bool dt = (form == FBC_FORM_DTABLE_FP64);
+    const int tile_rows = dt ? 96 : 64 * gemm_rb(form, c->ctmax);
+    const int tiles = p.mp / tile_rows;
+    const int nch = dt ? (p.n_i + 7) / 8 : p.kp / 64;
+    const int unit_k = dt ? 8 : 64;
+    for (int ks = 0; ks < nsplit; ++ks)
+        for (int tl = 0; tl < tiles; ++tl) {
+            GemmJob j{};
+            j.a_off = dt ? (int64_t)u.t * c->n_offsets * 6 : p.a_off + (int64_t)u.m * store_mode_elems(form, p);
+            j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
+            j.c_off = p.c_off + ks * p.c_split + (int64_t)u.m * p.ct * p.mp * 16;
+            j.mb = p.mp / 16;
+            j.kp = p.kp;
+            j.rb0 = tl * (tile_rows / 16);
+            j.ct = p.ct;
+            j.cell = u.cell;
+            j.k0 = unit_k * (int)((int64_t)nch * ks / nsplit);
+            j.k1 = unit_k * (int)((int64_t)nch * (ks + 1) / nsplit);
+            out.push_back(j);
         }
-    return out;
 }
 
-static std::vector<GemmJob> build_jobs(const fbc_ctx* c) {
-    const int form = c->opt.form;
-    if (form == FBC_FORM_DTABLE_FP64) return build_jobs_dtab(c);
-    const int rb = gemm_rb(form, c->ctmax);
-    const int tile_rb = 4 * rb;
-    std::vector<std::vector<GemmJob>> per_xcd(8);
-    std::vector<int64_t> load(8, 0);
-    struct Unit { int cell, m, tiles; };
+static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) {
+    const bool dt = (c->opt.form == FBC_FORM_DTABLE_FP64);
     std::vector<Unit> units;
     for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
         const CellPlan& p = c->cells[ci];
-        const int mb = p.mp / 16;
-        const int tiles = (mb + tile_rb - 1) / tile_rb;
-        for (int m = 0; m < p.nm; ++m) units.push_back({ci, m, tiles});
+        const int mult = c->nz_max / p.nz;
+        const int64_t cost = (int64_t)p.mp * (dt ? 6 * ((p.n_i + 7) / 8) : p.kp);
+        for (int m = 0; m < p.nm; ++m) units.push_back({ci, m, m * mult, cost});
     }
-    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.tiles > b.tiles; });
+    std::vector<GemmJob> out;
+    if (order == 1) {
+        std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.t < b.t; });
+        for (const Unit& u : units) unit_jobs(c, u, nsplit, out);
+        return out;
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+    if (order == 2) {
+        for (const Unit& u : units) unit_jobs(c, u, nsplit, out);
+        return out;
+    }
+    std::vector<std::vector<GemmJob>> per_xcd(8);
+    std::vector<int64_t> load(8, 0);
     for (const Unit& u : units) {
-        int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        const CellPlan& p = c->cells[u.cell];
-        const int nch = p.kp / 64;
-        for (int ks = 0; ks < c->nsplit; ++ks)
-            for (int t = 0; t < u.tiles; ++t) {
-                GemmJob j{};
-                j.a_off = p.a_off + (int64_t)u.m * store_mode_elems(form, p);
-                j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
-                j.c_off = p.c_off + ks * p.c_split + (int64_t)u.m * p.ct * p.mp * 16;
-                j.mb = p.mp / 16;
-                j.kp = p.kp;
-                j.rb0 = t * tile_rb;
-                j.ct = p.ct;
-                j.cell = u.cell;
-                j.k0 = 64 * (int)((int64_t)nch * ks / c->nsplit);
-                j.k1 = 64 * (int)((int64_t)nch * (ks + 1) / c->nsplit);
-                per_xcd[x].push_back(j);
-            }
-        load[x] += (int64_t)u.tiles * c->nsplit;
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const size_t before = per_xcd[x].size();
+        unit_jobs(c, u, nsplit, per_xcd[x]);
+        load[x] += (int64_t)(per_xcd[x].size() - before) * u.cost / std::max<int64_t>(1, nsplit);
     }
     size_t mx = 0;
     for (auto& v : per_xcd) mx = std::max(mx, v.size());
-    std::vector<GemmJob> out;
     out.reserve(mx * 8);
     for (size_t k = 0; k < mx; ++k)
         for (int x = 0; x < 8; ++x) {
@@ -448,6 +452,27 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c) {
             }
         }
     return out;
+}
+
+static fbc_status upload_jobs(fbc_ctx* c, int nsplit, int order, hipStream_t st) {
+    std::vector<GemmJob> jobs = build_jobs(c, nsplit, order);
+    if ((int64_t)jobs.size() > c->jobs_cap) {
+        fbc_status s = dev_alloc(c, (void**)&c->jobs, (int64_t)jobs.size() * sizeof(GemmJob));
+        if (s != FBC_OK) return s;
+        c->jobs_cap = (int64_t)jobs.size();
+    }
+    HIPCHK(c, hipMemcpyAsync(c->jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->njobs = (int)jobs.size();
+    c->nsplit = nsplit;
+    c->job_order = order;
+    if (c->graph_exec) {                 // the captured update refers to the old list
+        (void)hipGraphExecDestroy(c->graph_exec);
+        (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+    }
+    return FBC_OK;
 }
 
 extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cells, int n_cells,
@@ -543,10 +568,16 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         const int64_t want = 6 * 768;
         int ks = (int)std::min<int64_t>((want + tiles_total - 1) / tiles_total, kslices_max);
         c->nsplit = std::max(1, std::min(ks, 8));
+        // room for up to 8 slices within 4 GiB of partial outputs (the autotuner may pick more)
+        int64_t per_split = 0;
+        for (auto& p : c->cells) per_split += p.c_split * 8;
+        int cap = (int)std::min<int64_t>(8, std::max<int64_t>(1, ((int64_t)4 << 30) / std::max<int64_t>(1, per_split)));
+        cap = std::min(cap, std::max(1, kslices_max));
+        c->nsplit_cap = std::max(cap, c->nsplit);
         int64_t co = 0;
         for (auto& p : c->cells) {
             p.c_off = co;
-            co += p.c_split * c->nsplit;
+            co += p.c_split * c->nsplit_cap;
         }
         c_off = co;
     }
@@ -646,12 +677,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         (void)hipStreamSynchronize(st);
         (void)hipFree(sn_d);
     }
-    {
-        std::vector<GemmJob> jobs = build_jobs(c);
-        c->njobs = (int)jobs.size();
-        if ((s = dev_alloc(c, (void**)&c->jobs, (int64_t)jobs.size() * sizeof(GemmJob))) != FBC_OK) goto fail_out;
-        HIPCHK(c, hipMemcpyAsync(c->jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st));
-    }
+    if ((s = upload_jobs(c, c->nsplit, form == FBC_FORM_DTABLE_FP64 ? 1 : 0, st)) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->fprev, c->f_elems * 8)) != FBC_OK) goto fail_out;
     HIPCHK(c, hipStreamSynchronize(st));
     HIPCHK(c, hipGetLastError());
@@ -721,6 +747,85 @@ extern "C" fbc_status fbc_apply(fbc_ctx* c, const double* f, double* u, double a
         launch_mean(st, uc, sp, c->npart_axpy[ci], c->mean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
     }
     HIPCHK(c, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_apply_graph(fbc_ctx* c, const double* f, double* u, double alpha,
+                                      void* stream) {
+    fbc_status s = check_apply_args(c, f, u);
+    if (s != FBC_OK) return s;
+    if (!std::isfinite(alpha)) return fail(c, FBC_E_ARG, "alpha must be finite");
+    if (!stream) return fail(c, FBC_E_ARG, "graph capture needs a non-default stream");
+    hipStream_t st = (hipStream_t)stream;
+    if (!(c->graph_exec && c->g_f == f && c->g_u == u && c->g_alpha == alpha && c->g_stream == stream)) {
+        if (c->graph_exec) {
+            (void)hipGraphExecDestroy(c->graph_exec);
+            (void)hipGraphDestroy(c->graph);
+            c->graph_exec = nullptr;
+            c->graph = nullptr;
+        }
+        const int timing = c->timing;
+        c->timing = 0;
+        HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        s = fbc_apply(c, f, u, alpha, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        c->timing = timing;
+        if (s != FBC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(c, FBC_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+        c->graph = g;
+        c->g_f = f;
+        c->g_u = u;
+        c->g_alpha = alpha;
+        c->g_stream = stream;
+    }
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, st));
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int reps,
+                                   fbc_tune_result* out, void* stream) {
+    fbc_status s = check_apply_args(c, f, w);
+    if (s != FBC_OK) return s;
+    if (reps < 1 || reps > 1000) return fail(c, FBC_E_ARG, "reps must be in [1, 1000]");
+    hipStream_t st = (hipStream_t)stream;
+    const int timing = c->timing;
+    double ms0;
+    int n0;
+    if ((s = fbc_timing(c, 1)) != FBC_OK) return s;
+    if ((s = fbc_timing_read(c, &ms0, &n0)) != FBC_OK) return s;   // drop earlier records
+    double best = 1e300;
+    int best_split = c->nsplit, best_order = c->job_order, ncand = 0;
+    for (int order = 0; order < 3; ++order)
+        for (int ks = 1; ks <= c->nsplit_cap; ks *= 2) {
+            if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) return s;
+            if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) return s;       // warm-up
+            if ((s = fbc_timing_read(c, &ms0, &n0)) != FBC_OK) return s;
+            for (int r = 0; r < reps; ++r)
+                if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) return s;
+            double ms;
+            int n;
+            if ((s = fbc_timing_read(c, &ms, &n)) != FBC_OK) return s;
+            ms /= std::max(1, n);
+            ++ncand;
+            if (ms < best) {
+                best = ms;
+                best_split = ks;
+                best_order = order;
+            }
+        }
+    if ((s = upload_jobs(c, best_split, best_order, st)) != FBC_OK) return s;
+    c->timing = timing;
+    if (out) {
+        out->nsplit = best_split;
+        out->order = best_order;
+        out->gemm_ms = best;
+        out->n_candidates = ncand;
+    }
     return FBC_OK;
 }
 
@@ -801,6 +906,9 @@ extern "C" fbc_status fbc_get_info(const fbc_ctx* c, fbc_info* info) {
     info->f_elems = c->f_elems;
     info->u_elems = c->u_elems;
     info->n_offsets = c->n_offsets;
+    info->nsplit = c->nsplit;
+    info->job_order = c->job_order;
+    info->n_jobs = c->njobs;
     return FBC_OK;
 }
 
@@ -875,6 +983,8 @@ extern "C" void fbc_destroy(fbc_ctx* c) {
     (void)hipDeviceSynchronize();
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     free_all(c);
     delete c;
 }

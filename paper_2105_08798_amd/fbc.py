@@ -23,7 +23,8 @@ FORMS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "dtable_fp64": 3}
 EXPORTED = [
     "fbc_default_options", "fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin",
     "fbc_relax_step", "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_destroy",
-    "fbc_last_error", "fbc_status_string", "fbc_timing", "fbc_timing_read",
+    "fbc_last_error", "fbc_status_string", "fbc_timing", "fbc_timing_read", "fbc_apply_graph",
+    "fbc_autotune",
 ]
 
 
@@ -63,7 +64,13 @@ RELAX_OUT_DOUBLES = C.sizeof(RelaxOut) // 8
 class Info(C.Structure):
     _fields_ = [("n_cells", C.c_int), ("total_rhs", C.c_int), ("store_bytes", C.c_int64),
                 ("scratch_bytes", C.c_int64), ("f_elems", C.c_int64), ("u_elems", C.c_int64),
-                ("n_offsets", C.c_int64)]
+                ("n_offsets", C.c_int64), ("nsplit", C.c_int), ("job_order", C.c_int),
+                ("n_jobs", C.c_int)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("nsplit", C.c_int), ("order", C.c_int), ("gemm_ms", C.c_double),
+                ("n_candidates", C.c_int)]
 
 
 _lib = None
@@ -88,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_sync_status.argtypes = [vp, vp]
     lib.fbc_get_info.argtypes = [vp, C.POINTER(Info)]
     lib.fbc_copy_block_rows.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
+    lib.fbc_apply_graph.argtypes = [vp, vp, vp, C.c_double, vp]
+    lib.fbc_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(TuneResult), vp]
     lib.fbc_timing.argtypes = [vp, C.c_int]
     lib.fbc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.fbc_destroy.argtypes = [vp]
@@ -97,7 +106,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_status_string.argtypes = [C.c_int]
     lib.fbc_status_string.restype = cp
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
-                 "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read"):
+                 "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read", "fbc_apply_graph", "fbc_autotune"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -165,6 +174,16 @@ class FBC:
 
     def apply(self, f, u, alpha: float = 1.0, stream=None):
         self._check(self._lib.fbc_apply(self.ctx, _dptr(f), _dptr(u), float(alpha), _stream_handle(stream)))
+
+    def apply_graph(self, f, u, alpha: float = 1.0, stream=None):
+        self._check(self._lib.fbc_apply_graph(self.ctx, _dptr(f), _dptr(u), float(alpha), _stream_handle(stream)))
+
+    def autotune(self, f, w, reps: int = 3, stream=None) -> dict:
+        r = TuneResult()
+        self._check(self._lib.fbc_autotune(self.ctx, _dptr(f), _dptr(w), int(reps), C.byref(r),
+                                           _stream_handle(stream)))
+        self.info = self.get_info()
+        return dict(nsplit=r.nsplit, order=r.order, gemm_ms=r.gemm_ms, n_candidates=r.n_candidates)
 
     def green_apply(self, f, w, stream=None):
         self._check(self._lib.fbc_green_apply(self.ctx, _dptr(f), _dptr(w), _stream_handle(stream)))

@@ -245,3 +245,51 @@ def test_repeated_apply_is_bitwise_reproducible():
         outs.append(u.cpu().numpy())
     ctx.close()
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
+@pytest.mark.parametrize("form", ["fp64", "dtable_fp64"])
+def test_graph_replay_matches_eager(form):
+    """Captured update replayed several times, with eager work and synchronisation between
+    replays; every replay must equal the eager result bitwise (same kernels, same order)."""
+    dev = _dev()
+    cells = W.make_custom(16, 40, 70, 3, 32, seed=21).cells + W.make_custom(32, 20, 30, 9, 32, seed=22).cells
+    wl = W.Workload("two", cells, bz=32)
+    ctx = _ctx(wl.cells, wl.bz, form=form)
+    f = torch.from_numpy(np.concatenate([c.forces.ravel() for c in wl.cells])).to(dev)
+    n_u = sum(c.n_rhs * c.nz * c.n_b * 3 for c in wl.cells)
+    u0 = torch.from_numpy(np.random.default_rng(3).normal(size=n_u) * 0.01).to(dev)
+    s = torch.cuda.Stream()
+    ref = u0.clone()
+    ctx.apply(f, ref, alpha=0.9)
+    assert ctx.sync_status() == 0
+    u = torch.empty_like(u0)
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            u.copy_(u0)
+            ctx.apply_graph(f, u, alpha=0.9, stream=s)
+        s.synchronize()
+        junk = torch.randn(1000, device=dev).sum().item()      # eager work between replays
+        assert np.isfinite(junk)
+        assert ctx.sync_status(stream=s) == 0
+        assert torch.equal(u, ref), rep
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "dtable_fp64", "split_bf16"])
+def test_autotune_keeps_results(form):
+    dev = _dev()
+    wl = W.make_single("parity")
+    c = wl.cells[0]
+    ctx = _ctx(wl.cells, wl.bz, form=form)
+    f = torch.from_numpy(c.forces).to(dev)
+    w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+    res = ctx.autotune(f, w, reps=2)
+    assert res["n_candidates"] >= 3 and res["gemm_ms"] > 0
+    assert ctx.info.nsplit == res["nsplit"] and ctx.info.job_order == res["order"]
+    w.zero_()
+    ctx.green_apply(f, w)
+    assert ctx.sync_status() == 0
+    ref = oap.apply_green(oracle_green(c, wl.bz), c.forces)
+    e2, emax = rel_err(w.cpu().numpy(), ref)
+    ctx.close()
+    assert e2 < (1e-10 if form != "split_bf16" else 2e-5), (form, res, e2)
