@@ -407,6 +407,7 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
             j.cell = u.cell;
             j.k0 = unit_k * (int)((int64_t)nch * ks / nsplit);
             j.k1 = unit_k * (int)((int64_t)nch * (ks + 1) / nsplit);
+            j.ct_active = p.ctr;
             out.push_back(j);
         }
 }

@@ -72,7 +72,7 @@ struct GemmJob {
     int32_t ct;      // column tiles (8 RHS each)
     int32_t cell;    // cell index (offset form)
     int32_t k0, k1;  // K' slice [k0, k1) (dense forms) or interface columns [k0, k1)
-    int32_t pad;
+    int32_t ct_active;  // column tiles holding RHS of this cell (offset form skips the rest)
 };
 
 // Per-cell device view used by the offset-table product kernel.

@@ -290,6 +290,9 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 // one mode; the B fragments of the chunk are staged in LDS once for both waves.
 #define DT_TB 32
 #define DT_TI 8
+// Register-prefetch pipeline: the gathers of chunk i+1 are issued right after chunk i has
+// been written to LDS, so their latency hides behind the MFMAs of chunk i.  jb.ct_active
+// column tiles carry RHS of this cell; the others are skipped.
 template <int CT>
 __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ jobs,
                                                    const double2* __restrict__ tab,
@@ -304,6 +307,7 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
     const GemmJob jb = jobs[blockIdx.x];
     if (jb.mb == 0) return;
     const CellDev cd = cells[jb.cell];
+    const int nca = jb.ct_active;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int b0 = (jb.rb0 / 6) * DT_TB;
     if (tid < DT_TB) {
@@ -320,39 +324,64 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[r][c] = (d4_t){0, 0, 0, 0};
     __syncthreads();
-    for (int i0 = jb.k0; i0 < jb.k1; i0 += DT_TI) {
-        // gather 32 x 8 blocks, two per thread
+    constexpr int VB = (CT <= 2) ? 6 * CT : 1;   // B prefetched in registers for CT <= 2
+    double2 va[2][6];
+    double vb[VB];
+    auto prefetch = [&](int i0) {
 #pragma unroll
-        for (int q = tid; q < DT_TB * DT_TI; q += 128) {
+        for (int h = 0; h < 2; ++h) {
+            const int q = tid + 128 * h;
             const int bl = q >> 3, il = q & 7;
             const int b = b0 + bl, i = i0 + il;
-            double2 v[6];
             if (b < cd.n_b && i < cd.n_i) {
                 const int d1 = scb[2 * bl] - cd.cols_i[2 * i] - d1min;
                 const int d2 = scb[2 * bl + 1] - cd.cols_i[2 * i + 1] - d2min;
                 const double2* src = tm + (int64_t)lut[(int64_t)d1 * w2 + d2] * 6;
 #pragma unroll
-                for (int s = 0; s < 6; ++s) v[s] = src[s];
+                for (int s = 0; s < 6; ++s) va[h][s] = src[s];
             } else {
 #pragma unroll
-                for (int s = 0; s < 6; ++s) v[s] = make_double2(0, 0);
+                for (int s = 0; s < 6; ++s) va[h][s] = make_double2(0, 0);
             }
+        }
+        if constexpr (CT <= 2) {
+            const int p0 = (6 * i0) >> 3;
+#pragma unroll
+            for (int j = 0; j < 6 * CT; ++j) {
+                const int e = tid + 128 * j;
+                const int ct = e / 768, x = e - ct * 768;
+                vb[j] = (ct < nca) ? bm[((int64_t)ct * kp8 + p0) * 128 + x] : 0.0;
+            }
+        }
+    };
+    prefetch(jb.k0);
+    for (int i0 = jb.k0; i0 < jb.k1; i0 += DT_TI) {
+        __syncthreads();                          // the previous chunk's MFMAs are done
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = tid + 128 * h;
+            const int bl = q >> 3, il = q & 7;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const double2 x = v[sym_idx(c, d)];
+                    const double2 x = va[h][sym_idx(c, d)];
                     const int row = 3 * bl + c, kq = 6 * il + 2 * d;
                     As[frag_off_f64(row, kq, 48)] = x.x;
                     As[frag_off_f64(row, kq + 1, 48)] = x.y;
                 }
         }
-        // B fragments of k' in [6 i0, 6 i0 + 48): 6 contiguous 1 KiB runs per column tile
-        const int p0 = (6 * i0) >> 3;
-        for (int e = tid; e < CT * 768; e += 128) {
-            const int ct = e / 768, x = e - ct * 768;
-            Bs[e] = bm[((int64_t)ct * kp8 + p0) * 128 + x];
+        if constexpr (CT <= 2) {
+#pragma unroll
+            for (int j = 0; j < 6 * CT; ++j) Bs[tid + 128 * j] = vb[j];
+        } else {
+            const int p0 = (6 * i0) >> 3;
+            for (int e = tid; e < CT * 768; e += 128) {
+                const int ct = e / 768, x = e - ct * 768;
+                Bs[e] = (ct < nca) ? bm[((int64_t)ct * kp8 + p0) * 128 + x] : 0.0;
+            }
         }
+        if (i0 + DT_TI < jb.k1) prefetch(i0 + DT_TI);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
@@ -367,16 +396,17 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
                 for (int r = 0; r < 3; ++r)
 #pragma unroll
                     for (int c = 0; c < CT; ++c)
-                        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(h ? av[r].y : av[r].x,
-                                                                         h ? bv[c].y : bv[c].x,
-                                                                         acc[r][c], 0, 0, 0);
+                        if (c < nca)
+                            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(h ? av[r].y : av[r].x,
+                                                                             h ? bv[c].y : bv[c].x,
+                                                                             acc[r][c], 0, 0, 0);
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) store_c_f64(C, jb, jb.rb0 + 3 * wave + r, c, lane, acc[r][c]);
+        for (int c = 0; c < CT; ++c)
+            if (c < nca) store_c_f64(C, jb, jb.rb0 + 3 * wave + r, c, lane, acc[r][c]);
 }
 
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
