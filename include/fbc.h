@@ -76,10 +76,20 @@ typedef enum {
     FBC_FORM_FP32 = 1,        /* dense FP32 complex blocks, FP32 MFMA, FP64 across K chunks   */
     FBC_FORM_SPLIT_BF16 = 2,  /* dense split-BF16 (hi+lo) blocks, BF16 MFMA with FP32
                                  accumulation inside K chunks and FP64 across them            */
-    FBC_FORM_DTABLE_FP64 = 3  /* no dense store: FP64 table over distinct column offsets
+    FBC_FORM_DTABLE_FP64 = 3, /* no dense store: FP64 table over distinct column offsets
                                  (entries depend on n_b - n_i only), gathered into LDS
                                  tiles and applied on FP64 MFMA                               */
+    FBC_FORM_SURROGATE = 4    /* offset-table product whose table is generated per mode
+                                 chunk before each product: exact lattice values for
+                                 in-plane distances <= r_c (kept, FP64), beyond it the
+                                 continuum Green function plus a learned correction
+                                 (Appendix B: exact near field, continuum far field);
+                                 needs options.surrogate with MLP weights set             */
 } fbc_form;
+
+/* Learned far field (see the fbc_sur_* and fbc_mlp_* calls below). */
+typedef struct fbc_sur fbc_sur;
+typedef struct fbc_mlp fbc_mlp;
 
 /* Section 2.1 (eq. flexbc.bravais) and Section 2.2.1 (K_h). */
 typedef struct {
@@ -107,10 +117,14 @@ typedef struct {
     double netforce_tol;     /* relative tolerance of the net-force check (e.g. 1e-10)     */
     int row_gauge;           /* reduced forms: subtract each block row's mean over i per
                                 mode before rounding (exact for zero-net-force f)        */
+    const fbc_sur* surrogate;/* FBC_FORM_SURROGATE: far-field object (not owned; must
+                                outlive the context and keep its MLP weights); else NULL */
+    int gen_modes;           /* FBC_FORM_SURROGATE: table modes generated per chunk
+                                (>= 0; 0: as many as fit in 2 GiB of scratch)            */
 } fbc_options;
 
 /* Fills *opt with defaults: FP64, 1024 x 1024 torus, check on, no projection, tol 1e-10,
- * row_gauge on. */
+ * row_gauge on, no surrogate. */
 void fbc_default_options(fbc_options* opt);
 
 /* Assembles G^(m) for m = 0..N_z/2 of every cell on the device (Appendix B, discrete
@@ -209,6 +223,73 @@ fbc_status fbc_timing_read(fbc_ctx* ctx, double* gemm_ms_total, int* n_launches)
 
 void fbc_destroy(fbc_ctx* ctx);
 const char* fbc_last_error(const fbc_ctx* ctx);
+
+/* ------------------------------------------------------------------------------------
+ * Learned far field (Section 3.1 eq. cgf and Appendix B: the lattice Green function is
+ * used exactly near the source and replaced by the continuum Green function G_cgf,
+ * homogeneous of degree -1, far from it; their difference is a smooth, decaying
+ * correction).  In the line-mode representation (theta0 = m / N_z, offset (dn1, dn2),
+ * in-plane distance rho, kappa = 2 pi theta0 / c, c = a / sqrt 2):
+ *     G_cgf(m; dn) = (1/c) exp(i pi theta0 dn1) G^_K(kappa, r_perp),
+ * G^_K the line transform of the anisotropic Kelvin solution of the cubic continuum
+ * with C11 = 2k/a, C12 = C44 = k/a (nearest-neighbour springs); m = 0 is regularised by
+ * dropping the 2 G_K(t) log(kappa) divergence (a constant gauge).  The correction is
+ *     G_lgf - G_cgf = env * exp(i pi theta0 dn1) * MLP(cos phi, sin phi, r_c / rho, 2 theta0),
+ * env = ||G_cgf||_F + 1e-3, the MLP 4 -> 128 -> 128 -> 128 -> 12 with SiLU activations
+ * giving the 6 complex components of the symmetric 3x3 block (xx, yy, zz, xy, xz, yz).
+ * Offsets with rho <= r_c are always taken from the exact table.
+ * ------------------------------------------------------------------------------------ */
+
+/* Last error text of the fbc_sur_* / fbc_mlp_* calls on this host thread. */
+const char* fbc_learned_last_error(void);
+
+/* Builds the continuum table H(kappa rho, phi) on the device (homogeneity: one table at
+ * unit in-plane distance; 256 in-plane directions, 256 log-spaced kappa rho in
+ * [1e-3, 40] plus kappa = 0; beyond 40 the continuum value is taken as zero).  r_c in
+ * lattice constants (> 0).  Synchronises `stream`. */
+fbc_status fbc_sur_create(const fbc_lattice* lat, double r_c, void* stream, fbc_sur** out);
+void fbc_sur_destroy(fbc_sur* s);
+
+/* Copies the network's current FP32 weights into the object as BF16 (round to nearest
+ * even) for inference; later training of `net` does not change them until called again.
+ * Synchronises `stream`. */
+fbc_status fbc_sur_set_mlp(fbc_sur* s, const fbc_mlp* net, void* stream);
+
+/* Evaluates n blocks: out[n][6] complex (interleaved re, im; device) at line wavenumber
+ * theta0[n] in [0, 1/2] and column offsets dn1[n], dn2[n] (all device).  use_mlp = 0:
+ * continuum value only; 1: continuum + learned correction (rho > r_c; rho <= r_c returns
+ * the continuum value, since the exact table lives in a context).  Asynchronous. */
+fbc_status fbc_sur_eval(const fbc_sur* s, const double* theta0, const int32_t* dn1,
+                        const int32_t* dn2, int n, int use_mlp, double* out, void* stream);
+
+/* Training data from an FBC_FORM_DTABLE_FP64 context, whose table holds the lattice
+ * values of every distinct offset and line mode of its cells: up to max_samples pairs
+ * (table mode, offset) drawn by a host generator seeded with `seed`, restricted to
+ * rho > r_c and kappa rho <= 40, each turned into features x[n][4] and target t[n][12]
+ * (the correction above divided by env and rotated by exp(-i pi theta0 dn1)); x, t are
+ * device FP32 buffers of max_samples rows.  *n_out = rows written.  Synchronises. */
+fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* table_ctx, int max_samples,
+                                uint64_t seed, float* x, float* t, int* n_out, void* stream);
+
+/* Trainable MLP with FP32 parameters, Adam state and a workspace for batches of up to
+ * max_batch rows (<= 2^22).  Weights drawn N(0, 1/fan_in) from `seed`, biases zero.
+ * Parameter layout, per layer l = 0..3: W_l [out][in] row-major, then b_l [out]. */
+fbc_status fbc_mlp_create(int max_batch, uint64_t seed, fbc_mlp** out);
+void fbc_mlp_destroy(fbc_mlp* m);
+int fbc_mlp_num_params(void);
+/* Synchronous host copies: host_in (may be NULL) replaces the parameters, then
+ * host_out (may be NULL) receives them; fbc_mlp_grad copies the last gradient. */
+fbc_status fbc_mlp_params(fbc_mlp* m, float* host_out, const float* host_in);
+fbc_status fbc_mlp_grad(fbc_mlp* m, float* host_out);
+/* Loss L = (1/n) sum_rows sum_j (y_j - t_j)^2 over a batch (x [n][4], t [n][12],
+ * device FP32) and its gradient with respect to the parameters (kept in the object);
+ * loss_dev: device float receiving L, or NULL.  Asynchronous. */
+fbc_status fbc_mlp_loss_grad(fbc_mlp* m, const float* x, const float* t, int n,
+                             float* loss_dev, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the last gradient. */
+fbc_status fbc_mlp_adam_step(fbc_mlp* m, float lr, void* stream);
+/* FP32 forward pass y [n][12] of x [n][4] (device). */
+fbc_status fbc_mlp_forward(fbc_mlp* m, const float* x, float* y, int n, void* stream);
 const char* fbc_status_string(fbc_status s);
 
 #ifdef __cplusplus

@@ -2,4 +2,5 @@
 
 The compute path is libfbc.so (include/fbc.h); this package only marshals arguments.
 """
-from .fbc import FBC, FbcError, FORMS, RELAX_OUT_DOUBLES, load_library, parse_relax_out  # noqa: F401
+from .fbc import (FBC, MLP, FORMS, RELAX_OUT_DOUBLES, FbcError, Surrogate, load_library,  # noqa: F401
+                  parse_relax_out)

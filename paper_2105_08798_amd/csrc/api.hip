@@ -9,73 +9,15 @@
 #include <string>
 #include <vector>
 
-#include "kernels.h"
+#include <cmath>
+
+#include "ctx.h"
 
 int gemm_rb(int form, int ctmax);
 extern "C" fbc_status fbc_timing(fbc_ctx* c, int enable);
 extern "C" fbc_status fbc_timing_read(fbc_ctx* c, double* ms, int* n);
 
-struct fbc_ctx {
-    int device = 0;
-    fbc_options opt{};
-    fbc_lattice lat{};
-    std::vector<CellPlan> cells;
-    int total_rhs = 0;
-    int64_t f_elems = 0, u_elems = 0;
-    int ctmax = 1;
-    // device buffers (all owned)
-    std::vector<void*> allocs;
-    void* store = nullptr;          // dense store (FP64 / FP32 / split BF16)
-    int64_t store_bytes = 0;
-    void* bfrag = nullptr;          // GEMM B operand
-    double* cbuf = nullptr;         // GEMM output
-    double* wbuf = nullptr;         // w[r][row][n0]
-    double* sums = nullptr;         // net force per layer
-    double* wmax_part = nullptr;
-    double* sum_part = nullptr;
-    double* mean = nullptr;         // [total_rhs][3]
-    double2* tw = nullptr;          // twiddle tables
-    int* status = nullptr;          // device latch
-    GemmJob* jobs = nullptr;
-    int njobs = 0;
-    int nsplit = 1;                 // K slices of the per-mode product
-    int nsplit_cap = 1;             // K slices the output buffer holds
-    int job_order = 0;              // see build_jobs
-    int64_t jobs_cap = 0;
-    // captured update (fbc_apply_graph)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    const double* g_f = nullptr;
-    double* g_u = nullptr;
-    double g_alpha = 0.0;
-    void* g_stream = nullptr;
-    int64_t scratch_bytes = 0;
-    int64_t n_offsets = 0;
-    // offset table (kept for the offset-table form)
-    int nz_max = 0;
-    double2* tab = nullptr;
-    int32_t* lut = nullptr;
-    int d1min = 0, d2min = 0, w2 = 0;
-    CellDev* celldev = nullptr;
-    // relax
-    double* fprev = nullptr;
-    double* alpha = nullptr;
-    double* finf = nullptr;
-    double* stepinf = nullptr;
-    double* rpart = nullptr;
-    double* rmean = nullptr;
-    fbc_relax_opts ropt{};
-    int relax_k = -1;
-    // per cell partial counts
-    std::vector<int> npart_irfft, npart_axpy;
-    std::vector<int64_t> wmax_off, sum_part_off, rpart_off;
-    std::string err;
-    // timing of the product kernel
-    int timing = 0;
-    std::vector<hipEvent_t> ev;      // 2 * kMaxTimed events, created on first enable
-    int n_timed = 0;
-};
-static const int kMaxTimed = 4096;
+
 
 static thread_local std::string g_err;
 
@@ -194,6 +136,10 @@ static void twiddles(int n, std::vector<double2>& out) {
     if (n / 2 == 0) out[0] = make_double2(1.0, 0.0);
 }
 
+static bool is_table_form(int form) {
+    return form == FBC_FORM_DTABLE_FP64 || form == FBC_FORM_SURROGATE;
+}
+
 static int64_t store_elem_bytes(int form) {
     return form == FBC_FORM_FP64 ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
 }
@@ -205,7 +151,7 @@ static int64_t b_mode_elems(int form, const CellPlan& p) {
     return (int64_t)16 * p.ct * p.kp * (form == FBC_FORM_SPLIT_BF16 ? 2 : 1);
 }
 static int64_t b_elem_bytes(int form) {
-    return (form == FBC_FORM_FP64 || form == FBC_FORM_DTABLE_FP64) ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
+    return (form == FBC_FORM_FP64 || is_table_form(form)) ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
 }
 
 // ----------------------------------------------------------------------------------
@@ -275,6 +221,52 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
     const int m1 = c->opt.bz_m1, m2 = c->opt.bz_m2;
     const int form = c->opt.form;
     OffsetSet os = offsets_of(c->cells);
+    const bool sur = (form == FBC_FORM_SURROGATE);
+    if (sur) {
+        // number offsets by increasing in-plane distance: the exact near field is a prefix,
+        // and so is, for every line mode, the part where the far field is not negligible
+        const int64_t n = (int64_t)os.d1.size();
+        std::vector<double> rho(n);
+        for (int64_t o = 0; o < n; ++o) {
+            const double xx = 0.5 * os.d1[o], yy = (os.d1[o] + 2.0 * os.d2[o]) * (0.5 * M_SQRT1_2);
+            rho[o] = std::sqrt(xx * xx + yy * yy);
+        }
+        std::vector<int32_t> ord(n);
+        for (int64_t o = 0; o < n; ++o) ord[o] = (int32_t)o;
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return rho[a] < rho[b]; });
+        std::vector<int32_t> rank(n), nd1(n), nd2(n);
+        for (int64_t r = 0; r < n; ++r) {
+            rank[ord[r]] = (int32_t)r;
+            nd1[r] = os.d1[ord[r]];
+            nd2[r] = os.d2[ord[r]];
+        }
+        for (auto& e : os.lut)
+            if (e >= 0) e = rank[e];
+        os.d1.swap(nd1);
+        os.d2.swap(nd2);
+        c->n_near = 0;
+        while (c->n_near < n && rho[ord[c->n_near]] <= c->sur->r_c) ++c->n_near;
+        const int T0 = c->nz_max / 2 + 1;
+        std::vector<int32_t> need(T0);
+        for (int t = 0; t < T0; ++t) {
+            if (t == 0) {
+                need[t] = (int32_t)n;
+                continue;
+            }
+            const double kap = 2.0 * M_PI * ((double)t / c->nz_max) * M_SQRT2;
+            const double rmax = c->sur->k.s_max / kap;
+            int64_t lo = c->n_near, hi = n;       // first rank with rho > rmax
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) / 2;
+                if (rho[ord[mid]] <= rmax) lo = mid + 1; else hi = mid;
+            }
+            need[t] = (int32_t)lo;
+        }
+        fbc_status s0;
+        if ((s0 = dev_alloc(c, (void**)&c->n_need, (int64_t)T0 * 4)) != FBC_OK) return s0;
+        HIPCHK(c, hipMemcpyAsync(c->n_need, need.data(), (size_t)T0 * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
     const int64_t n_off = (int64_t)os.d1.size();
     c->n_offsets = n_off;
     c->d1min = os.d1min;
@@ -299,15 +291,25 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
     fbc_status s;
     int32_t *d1_d, *d2_d;
     const bool keep = (form == FBC_FORM_DTABLE_FP64);
+    // the surrogate form keeps only the exact near field, for every table mode
+    const int64_t n_tab = sur ? c->n_near : n_off;
     if ((s = dev_alloc(c, (void**)&c->lut, (int64_t)os.lut.size() * 4)) != FBC_OK) return s;
     if (keep) {
         if ((s = dev_alloc(c, (void**)&c->tab, (int64_t)T * n_off * 96)) != FBC_OK) return s;
         c->store_bytes = (int64_t)T * n_off * 96;
+    } else if (sur) {
+        if ((s = dev_alloc(c, (void**)&c->near_tab, (int64_t)T * std::max<int64_t>(1, n_tab) * 96)) != FBC_OK) return s;
+        c->store_bytes = (int64_t)T * n_tab * 96;
     } else if ((s = talloc((void**)&c->tab, (int64_t)T * n_off * 96)) != FBC_OK) {
         cleanup();
         return s;
     }
-    if ((s = talloc((void**)&d1_d, n_off * 4)) != FBC_OK || (s = talloc((void**)&d2_d, n_off * 4)) != FBC_OK) {
+    if (is_table_form(form)) {
+        if ((s = dev_alloc(c, (void**)&d1_d, n_off * 4)) != FBC_OK || (s = dev_alloc(c, (void**)&d2_d, n_off * 4)) != FBC_OK)
+            return s;
+        c->off_d1 = d1_d;
+        c->off_d2 = d2_d;
+    } else if ((s = talloc((void**)&d1_d, n_off * 4)) != FBC_OK || (s = talloc((void**)&d2_d, n_off * 4)) != FBC_OK) {
         cleanup();
         return s;
     }
@@ -344,11 +346,27 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         launch_fft_rows(st, pk, (int64_t)nmc * 3 * m1, ilog2(m2), tw2_d, true);
         launch_transpose_c(st, pk, pt, nmc * 3, m1, m2);
         launch_fft_rows(st, pt, (int64_t)nmc * 3 * m2, ilog2(m1), tw1_d, true);
-        launch_gather_table(st, pt, c->tab + (int64_t)t0 * n_off * 6, nmc, m1, m2, n_off, d1_d, d2_d,
-                            n_off * 6, scale);
+        if (sur) {
+            if (n_tab > 0)
+                launch_gather_table(st, pt, c->near_tab + (int64_t)t0 * n_tab * 6, nmc, m1, m2, n_tab, d1_d,
+                                    d2_d, n_tab * 6, scale);
+        } else {
+            launch_gather_table(st, pt, c->tab + (int64_t)t0 * n_off * 6, nmc, m1, m2, n_off, d1_d, d2_d,
+                                n_off * 6, scale);
+        }
     }
     HIPCHK(c, hipGetLastError());
-    if (!keep) {
+    if (sur) {
+        // generated slices: as many table modes per chunk as fit in about 2 GiB
+        c->gen_modes = (int)std::max<int64_t>(1, std::min<int64_t>(T, ((int64_t)2 << 30) / std::max<int64_t>(1, n_off * 96)));
+        if (c->opt.gen_modes > 0) c->gen_modes = std::min(c->opt.gen_modes, T);
+        if ((s = dev_alloc(c, (void**)&c->gen, (int64_t)c->gen_modes * n_off * 96)) != FBC_OK) {
+            cleanup();
+            return s;
+        }
+        c->scratch_bytes += (int64_t)c->gen_modes * n_off * 96;
+    }
+    if (!keep && !sur) {
         for (CellPlan& p : c->cells) {
             const int mult = c->nz_max / p.nz;
             double2* rowmean = nullptr;
@@ -389,7 +407,7 @@ struct Unit {
 static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<GemmJob>& out) {
     const int form = c->opt.form;
     const CellPlan& p = c->cells[u.cell];
-    const bool dt = (form == FBC_FORM_DTABLE_FP64);
+    const bool dt = is_table_form(form);
     const int tile_rows = dt ? 96 : 64 * gemm_rb(form, c->ctmax);
     const int tiles = p.mp / tile_rows;
     const int nch = dt ? (p.n_i + 7) / 8 : p.kp / 64;
@@ -413,7 +431,7 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
 }
 
 static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) {
-    const bool dt = (c->opt.form == FBC_FORM_DTABLE_FP64);
+    const bool dt = is_table_form(c->opt.form);
     std::vector<Unit> units;
     for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
         const CellPlan& p = c->cells[ci];
@@ -467,6 +485,17 @@ static fbc_status upload_jobs(fbc_ctx* c, int nsplit, int order, hipStream_t st)
     c->njobs = (int)jobs.size();
     c->nsplit = nsplit;
     c->job_order = order;
+    c->chunk_job0.clear();
+    if (c->opt.form == FBC_FORM_SURROGATE && c->gen_modes > 0) {
+        // jobs are in table-mode order (order 1); record where each generated chunk starts
+        const int T = c->nz_max / 2 + 1;
+        size_t j = 0;
+        for (int t0 = 0; t0 < T; t0 += c->gen_modes) {
+            while (j < jobs.size() && jobs[j].a_off < (int64_t)t0 * c->n_offsets * 6) ++j;
+            c->chunk_job0.push_back((int)j);
+        }
+        c->chunk_job0.push_back((int)jobs.size());
+    }
     if (c->graph_exec) {                 // the captured update refers to the old list
         (void)hipGraphExecDestroy(c->graph_exec);
         (void)hipGraphDestroy(c->graph);
@@ -483,8 +512,11 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     if (!lat || !cells || !opt || n_cells <= 0) return fail(nullptr, FBC_E_ARG, "null argument or n_cells <= 0");
     if (!(lat->a > 0) || !(lat->spring_k > 0) || !std::isfinite(lat->a) || !std::isfinite(lat->spring_k))
         return fail(nullptr, FBC_E_ARG, "lattice constant and spring stiffness must be positive");
-    if (opt->form < FBC_FORM_FP64 || opt->form > FBC_FORM_DTABLE_FP64)
+    if (opt->form < FBC_FORM_FP64 || opt->form > FBC_FORM_SURROGATE)
         return fail(nullptr, FBC_E_ARG, "unknown form");
+    if (opt->form == FBC_FORM_SURROGATE && (!opt->surrogate || !opt->surrogate->has_mlp))
+        return fail(nullptr, FBC_E_ARG, "the surrogate form needs an fbc_sur with MLP weights");
+    if (opt->gen_modes < 0) return fail(nullptr, FBC_E_ARG, "gen_modes must be >= 0");
     if (!is_pow2(opt->bz_m1) || !is_pow2(opt->bz_m2) || opt->bz_m1 < 8 || opt->bz_m2 < 8 ||
         opt->bz_m1 > 4096 || opt->bz_m2 > 4096)
         return fail(nullptr, FBC_E_ARG, "bz_m1, bz_m2 must be powers of two in [8, 4096]");
@@ -504,6 +536,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     if (!c) return fail(nullptr, FBC_E_NOMEM, "host allocation");
     c->opt = *opt;
     c->lat = *lat;
+    c->sur = opt->surrogate;
     (void)hipGetDevice(&c->device);
     hipStream_t st = (hipStream_t)stream;
     const int form = opt->form;
@@ -528,7 +561,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         p.R = cells[i].n_rhs;
         p.K = 3 * p.n_i;
         p.M = 3 * p.n_b;
-        if (form == FBC_FORM_DTABLE_FP64) {
+        if (is_table_form(form)) {
             p.kp = 6 * (int)roundup(p.n_i, 8);       // whole chunks of 8 interface columns
             p.mp = (int)roundup(p.M, 96);            // whole tiles of 32 pad columns
         } else {
@@ -551,7 +584,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         a_off += store_mode_elems(form, p) * p.nm;
         b_off += b_mode_elems(form, p) * p.nm;
         p.c_split = (int64_t)p.nm * p.ct * p.mp * 16;
-        if (form == FBC_FORM_DTABLE_FP64) {
+        if (is_table_form(form)) {
             tiles_total += (int64_t)p.nm * (p.mp / 96);
             kslices_max = std::min(kslices_max, (p.n_i + 7) / 8);
         } else {
@@ -586,7 +619,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     c->f_elems = f_off;
     c->u_elems = u_off;
     fbc_status s;
-    if (form != FBC_FORM_DTABLE_FP64) {
+    if (!is_table_form(form)) {
         c->store_bytes = a_off * store_elem_bytes(form);
         if ((s = dev_alloc(c, &c->store, c->store_bytes)) != FBC_OK) goto fail_out;
     }
@@ -678,7 +711,8 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         (void)hipStreamSynchronize(st);
         (void)hipFree(sn_d);
     }
-    if ((s = upload_jobs(c, c->nsplit, form == FBC_FORM_DTABLE_FP64 ? 1 : 0, st)) != FBC_OK) goto fail_out;
+    if (form == FBC_FORM_SURROGATE) c->nsplit = 1;     // slices are generated per mode chunk
+    if ((s = upload_jobs(c, c->nsplit, is_table_form(form) ? 1 : 0, st)) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->fprev, c->f_elems * 8)) != FBC_OK) goto fail_out;
     HIPCHK(c, hipStreamSynchronize(st));
     HIPCHK(c, hipGetLastError());
@@ -711,8 +745,22 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     }
     const bool tm = c->timing && c->n_timed < kMaxTimed;
     if (tm) (void)hipEventRecord(c->ev[2 * c->n_timed], st);
-    if (form == FBC_FORM_DTABLE_FP64)
-        launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, (const double*)c->bfrag, c->cbuf,
+    if (form == FBC_FORM_SURROGATE) {
+        // generate a chunk of table modes, then run the products of those modes
+        const int T = c->nz_max / 2 + 1;
+        const fbc_sur* sv = c->sur;
+        for (size_t ch = 0; ch + 1 < c->chunk_job0.size(); ++ch) {
+            const int t0 = (int)ch * c->gen_modes;
+            const int nt = std::min(c->gen_modes, T - t0);
+            launch_sur_generate(st, sv->view(), sv->wb, sv->bias, sv->r_c, sv->env_floor, c->nz_max, t0, nt,
+                                c->near_tab, c->n_near, c->n_offsets, c->n_need, c->off_d1, c->off_d2,
+                                c->gen);
+            const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
+            launch_gemm_dtab(st, c->jobs + j0, j1 - j0, c->ctmax, c->gen, (int64_t)t0 * c->n_offsets * 6,
+                             (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2);
+        }
+    } else if (form == FBC_FORM_DTABLE_FP64)
+        launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, 0, (const double*)c->bfrag, c->cbuf,
                          c->celldev, c->lut, c->d1min, c->d2min, c->w2);
     else
         launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf);
@@ -793,6 +841,7 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
     fbc_status s = check_apply_args(c, f, w);
     if (s != FBC_OK) return s;
     if (reps < 1 || reps > 1000) return fail(c, FBC_E_ARG, "reps must be in [1, 1000]");
+    if (c->opt.form == FBC_FORM_SURROGATE) return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major list");
     hipStream_t st = (hipStream_t)stream;
     const int timing = c->timing;
     double ms0;
@@ -918,6 +967,7 @@ extern "C" fbc_status fbc_copy_block_rows(fbc_ctx* c, int cell, int m, int b0, i
     if (cell < 0 || cell >= (int)c->cells.size()) return fail(c, FBC_E_ARG, "cell out of range");
     const CellPlan& p = c->cells[cell];
     if (m < 0 || m >= p.nm || b0 < 0 || b1 > p.n_b || b0 >= b1) return fail(c, FBC_E_ARG, "range");
+    if (c->opt.form == FBC_FORM_SURROGATE) return fail(c, FBC_E_UNSUPPORTED, "no stored table in the surrogate form");
     if (c->opt.form == FBC_FORM_DTABLE_FP64) {
         // reconstruct the block rows from the offset table
         const int mult = c->nz_max / p.nz;

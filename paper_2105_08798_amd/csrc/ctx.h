@@ -1,0 +1,119 @@
+// Internal definitions shared by the C-ABI translation units.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "learned.h"
+
+struct fbc_sur;
+
+struct fbc_ctx {
+    int device = 0;
+    fbc_options opt{};
+    fbc_lattice lat{};
+    std::vector<CellPlan> cells;
+    int total_rhs = 0;
+    int64_t f_elems = 0, u_elems = 0;
+    int ctmax = 1;
+    // device buffers (all owned)
+    std::vector<void*> allocs;
+    void* store = nullptr;          // dense store (FP64 / FP32 / split BF16)
+    int64_t store_bytes = 0;
+    void* bfrag = nullptr;          // GEMM B operand
+    double* cbuf = nullptr;         // GEMM output
+    double* wbuf = nullptr;         // w[r][row][n0]
+    double* sums = nullptr;         // net force per layer
+    double* wmax_part = nullptr;
+    double* sum_part = nullptr;
+    double* mean = nullptr;         // [total_rhs][3]
+    double2* tw = nullptr;          // twiddle tables
+    int* status = nullptr;          // device latch
+    GemmJob* jobs = nullptr;
+    int njobs = 0;
+    int nsplit = 1;                 // K slices of the per-mode product
+    int nsplit_cap = 1;             // K slices the output buffer holds
+    int job_order = 0;              // see build_jobs
+    int64_t jobs_cap = 0;
+    // captured update (fbc_apply_graph)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const double* g_f = nullptr;
+    double* g_u = nullptr;
+    double g_alpha = 0.0;
+    void* g_stream = nullptr;
+    int64_t scratch_bytes = 0;
+    int64_t n_offsets = 0;
+    // offset table (kept for the offset-table form)
+    int nz_max = 0;
+    double2* tab = nullptr;
+    int32_t* lut = nullptr;
+    int d1min = 0, d2min = 0, w2 = 0;
+    CellDev* celldev = nullptr;
+    // surrogate form: exact near table, offsets by increasing distance, generated slices
+    const fbc_sur* sur = nullptr;
+    double2* near_tab = nullptr;     // [table mode][n_near][6]
+    int64_t n_near = 0;
+    int32_t* off_d1 = nullptr;       // device offsets in table order
+    int32_t* off_d2 = nullptr;
+    int32_t* n_need = nullptr;       // per table mode: offsets to generate (prefix)
+    double2* gen = nullptr;          // generated slices [chunk modes][n_off][6]
+    int gen_modes = 0;               // table modes per generated chunk
+    std::vector<int> chunk_job0;     // first job of each chunk (jobs sorted by table mode)
+    // relax
+    double* fprev = nullptr;
+    double* alpha = nullptr;
+    double* finf = nullptr;
+    double* stepinf = nullptr;
+    double* rpart = nullptr;
+    double* rmean = nullptr;
+    fbc_relax_opts ropt{};
+    int relax_k = -1;
+    // per cell partial counts
+    std::vector<int> npart_irfft, npart_axpy;
+    std::vector<int64_t> wmax_off, sum_part_off, rpart_off;
+    std::string err;
+    // timing of the product kernel
+    int timing = 0;
+    std::vector<hipEvent_t> ev;      // 2 * kMaxTimed events, created on first enable
+    int n_timed = 0;
+};
+static const int kMaxTimed = 4096;
+
+// Learned far-field object (continuum table + inference weights).
+struct fbc_sur {
+    double r_c = 6.0;
+    double env_floor = 1e-3;
+    CgfConst k{};
+    double2* H = nullptr;            // continuum table
+    double* g0 = nullptr;
+    unsigned short* wb = nullptr;    // transposed bf16 weights
+    float* bias = nullptr;
+    int has_mlp = 0;
+    std::vector<void*> allocs;
+    std::string err;
+    CgfView view() const {
+        CgfView v;
+        v.H = H;
+        v.g0 = g0;
+        v.nphi = k.nphi;
+        v.ns = k.ns;
+        v.ls_min = std::log(k.s_min);
+        v.dls = (std::log(k.s_max) - std::log(k.s_min)) / (k.ns - 1);
+        v.s_max = k.s_max;
+        return v;
+    }
+};
+
+// Trainable MLP (FP32 master weights, Adam state, gradient and workspace).
+struct fbc_mlp {
+    float* params = nullptr;
+    float* grad = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    float* ws = nullptr;
+    float* loss = nullptr;
+    int max_batch = 0;
+    int step = 0;
+    std::vector<void*> allocs;
+    std::string err;
+};

@@ -295,7 +295,7 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 // column tiles carry RHS of this cell; the others are skipped.
 template <int CT>
 __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ jobs,
-                                                   const double2* __restrict__ tab,
+                                                   const double2* __restrict__ tab, int64_t a_base,
                                                    const double* __restrict__ B,
                                                    double* __restrict__ C,
                                                    const CellDev* __restrict__ cells,
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
         scb[2 * tid] = b < cd.n_b ? cd.cols_b[2 * b] : 0;
         scb[2 * tid + 1] = b < cd.n_b ? cd.cols_b[2 * b + 1] : 0;
     }
-    const double2* tm = tab + jb.a_off;
+    const double2* tm = tab + (jb.a_off - a_base);
     const double* bm = B + jb.b_off;
     const int kp8 = jb.kp >> 3;
     d4_t acc[3][CT];
@@ -410,14 +410,14 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
 }
 
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
-                      const double* b, double* c, const CellDev* cells, const int32_t* lut,
-                      int d1min, int d2min, int w2) {
+                      int64_t a_base, const double* b, double* c, const CellDev* cells,
+                      const int32_t* lut, int d1min, int d2min, int w2) {
     if (njobs <= 0) return;
     dim3 grid(njobs), blk(128);
     switch (ct) {
-        case 1: hipLaunchKernelGGL(k_gemm_dtab<1>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
-        case 2: hipLaunchKernelGGL(k_gemm_dtab<2>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
-        case 4: hipLaunchKernelGGL(k_gemm_dtab<4>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
-        default: hipLaunchKernelGGL(k_gemm_dtab<8>, grid, blk, 0, st, jobs, tab, b, c, cells, lut, d1min, d2min, w2); break;
+        case 1: hipLaunchKernelGGL(k_gemm_dtab<1>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
+        case 2: hipLaunchKernelGGL(k_gemm_dtab<2>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
+        case 4: hipLaunchKernelGGL(k_gemm_dtab<4>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
+        default: hipLaunchKernelGGL(k_gemm_dtab<8>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
     }
 }

@@ -37,8 +37,8 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 // Offset-table form: 32 pad columns x all interface columns per work group, table
 // entries gathered into LDS in MFMA fragment order.
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
-                      const double* b, double* c, const CellDev* cells, const int32_t* lut,
-                      int d1min, int d2min, int w2);
+                      int64_t a_base, const double* b, double* c, const CellDev* cells,
+                      const int32_t* lut, int d1min, int d2min, int w2);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, int* n_part_out);

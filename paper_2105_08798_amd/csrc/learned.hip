@@ -1,0 +1,694 @@
+// Learned far-field form (beyond the exact near field): the continuum Green function
+// in the line-mode representation (Section 3.1, eq. cgf; Appendix B, lattice function ->
+// continuum function beyond a cut-off radius), tabulated once through its homogeneity,
+// and a 4-layer MLP for the correction G^_lgf - G^_cgf, with training kernels (forward,
+// backward, Adam) and the on-the-fly table generator of the surrogate form.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "learned.h"
+
+#define NTL 256
+
+// ----------------------------------------------------------------------------------
+// Kelvin solution of a cubic crystal: G_K(x) = 1/(8 pi^2 |x|) * circle integral of
+// Gamma(n)^{-1} over unit n normal to x (trapezoid rule over npsi nodes), with
+// Gamma_ii = C11 n_i^2 + C44 (|n|^2 - n_i^2), Gamma_ik = (C12 + C44) n_i n_k.
+// Output in symmetric order xx yy zz xy xz yz.
+// ----------------------------------------------------------------------------------
+__device__ inline void sym_inverse(const double g[6], double o[6]) {
+    const double a = g[0], b = g[1], c = g[2], xy = g[3], xz = g[4], yz = g[5];
+    const double cxx = b * c - yz * yz, cyy = a * c - xz * xz, czz = a * b - xy * xy;
+    const double cxy = xz * yz - xy * c, cxz = xy * yz - b * xz, cyz = xy * xz - a * yz;
+    const double inv = 1.0 / (a * cxx + xy * cxy + xz * cxz);
+    o[0] = cxx * inv; o[1] = cyy * inv; o[2] = czz * inv;
+    o[3] = cxy * inv; o[4] = cxz * inv; o[5] = cyz * inv;
+}
+
+__device__ void kelvin(const double x[3], const CgfConst& k, const double* __restrict__ cpsi,
+                       const double* __restrict__ spsi, double out[6]) {
+    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double xh[3] = {x[0] / r, x[1] / r, x[2] / r};
+    double hp[3] = {0, 0, 0};
+    if (fabs(xh[0]) < 0.9) hp[0] = 1.0; else hp[1] = 1.0;
+    double u[3] = {xh[1] * hp[2] - xh[2] * hp[1], xh[2] * hp[0] - xh[0] * hp[2], xh[0] * hp[1] - xh[1] * hp[0]};
+    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    u[0] /= un; u[1] /= un; u[2] /= un;
+    const double v[3] = {xh[1] * u[2] - xh[2] * u[1], xh[2] * u[0] - xh[0] * u[2], xh[0] * u[1] - xh[1] * u[0]};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int l = 0; l < k.npsi; ++l) {
+        const double n0 = cpsi[l] * u[0] + spsi[l] * v[0];
+        const double n1 = cpsi[l] * u[1] + spsi[l] * v[1];
+        const double n2 = cpsi[l] * u[2] + spsi[l] * v[2];
+        const double q0 = n0 * n0, q1 = n1 * n1, q2 = n2 * n2, tot = q0 + q1 + q2;
+        const double g[6] = {k.c11 * q0 + k.c44 * (tot - q0), k.c11 * q1 + k.c44 * (tot - q1),
+                             k.c11 * q2 + k.c44 * (tot - q2), (k.c12 + k.c44) * n0 * n1,
+                             (k.c12 + k.c44) * n0 * n2, (k.c12 + k.c44) * n1 * n2};
+        double o[6];
+        sym_inverse(g, o);
+        for (int c = 0; c < 6; ++c) acc[c] += o[c];
+    }
+    const double sc = 1.0 / (4.0 * M_PI * k.npsi * r);
+    for (int c = 0; c < 6; ++c) out[c] = acc[c] * sc;
+}
+
+// G0 = G_K(t) and g1(phi_j) = (r_hat_j . grad) G_K at t (central difference, step h).
+__global__ void k_cgf_g(CgfConst k, const double* __restrict__ cpsi, const double* __restrict__ spsi,
+                        const double* __restrict__ rhat, double* __restrict__ g0,
+                        double* __restrict__ g1) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > k.nphi) return;
+    if (j == k.nphi) {
+        kelvin(k.t, k, cpsi, spsi, g0);
+        return;
+    }
+    const double h = 1e-4;
+    double xp[3], xm[3], gp[6], gm[6];
+    for (int a = 0; a < 3; ++a) {
+        xp[a] = k.t[a] + h * rhat[3 * j + a];
+        xm[a] = k.t[a] - h * rhat[3 * j + a];
+    }
+    kelvin(xp, k, cpsi, spsi, gp);
+    kelvin(xm, k, cpsi, spsi, gm);
+    for (int c = 0; c < 6; ++c) g1[6 * j + c] = (gp[c] - gm[c]) / (2.0 * h);
+}
+
+// Remainder R(phi_j, z) = G_K(r_hat_j + z t) - G0/sqrt(z^2+1) - g1_j z/(z^2+1)^{3/2}.
+__global__ void __launch_bounds__(NTL) k_cgf_rem(CgfConst k, const double* __restrict__ cpsi,
+                                                 const double* __restrict__ spsi,
+                                                 const double* __restrict__ rhat,
+                                                 const double* __restrict__ g0,
+                                                 const double* __restrict__ g1,
+                                                 double* __restrict__ rem) {
+    const int64_t idx = (int64_t)blockIdx.x * NTL + threadIdx.x;
+    if (idx >= (int64_t)k.nphi * k.nzq) return;
+    const int j = (int)(idx / k.nzq);
+    const int q = (int)(idx - (int64_t)j * k.nzq);
+    const double z = -k.zmax + q * k.dz;
+    double x[3], g[6];
+    for (int a = 0; a < 3; ++a) x[a] = rhat[3 * j + a] + z * k.t[a];
+    kelvin(x, k, cpsi, spsi, g);
+    const double d = sqrt(z * z + 1.0);
+    const double e1 = 1.0 / d, e2 = z / (d * d * d);
+    for (int c = 0; c < 6; ++c) rem[idx * 6 + c] = g[c] - g0[c] * e1 - g1[6 * j + c] * e2;
+}
+
+// H(s_i, phi_j) = sum_q w_q exp(-i s_i z_q) R(phi_j, z_q) + 2 G0 K0(s) - 2 i s g1 K0(s),
+// stored as e^{s_i} H; the phase advances by a complex rotation per node (host tables
+// ph0, step).
+// Column i = ns holds the regularised kappa = 0 value (real): sum_q w_q R + 2 G0 (log 2 - gamma).
+__global__ void __launch_bounds__(NTL) k_cgf_transform(CgfConst k, const double* __restrict__ rem,
+                                                       const double* __restrict__ g0,
+                                                       const double* __restrict__ g1,
+                                                       const double2* __restrict__ ph0,
+                                                       const double2* __restrict__ step,
+                                                       const double* __restrict__ k0s,
+                                                       double2* __restrict__ H) {
+    const int idx = blockIdx.x * NTL + threadIdx.x;
+    if (idx >= k.nphi * (k.ns + 1)) return;
+    const int j = idx / (k.ns + 1);
+    const int i = idx - j * (k.ns + 1);
+    const double* rj = rem + (int64_t)j * k.nzq * 6;
+    double2 acc[6];
+    for (int c = 0; c < 6; ++c) acc[c] = make_double2(0, 0);
+    if (i < k.ns) {
+        double2 ph = ph0[i];
+        const double2 st = step[i];
+        for (int q = 0; q < k.nzq; ++q) {
+            const double w = (q == 0 || q == k.nzq - 1) ? 0.5 * k.dz : k.dz;
+            const double pr = w * ph.x, pi = w * ph.y;
+            for (int c = 0; c < 6; ++c) {
+                const double r = rj[q * 6 + c];
+                acc[c].x += pr * r;
+                acc[c].y += pi * r;
+            }
+            ph = make_double2(ph.x * st.x - ph.y * st.y, ph.x * st.y + ph.y * st.x);
+        }
+        const double K0 = k0s[2 * i], s = k0s[2 * i + 1];      // K0(s_i), s_i (host table)
+        // stored times e^{s}: the transform decays roughly like e^{-s}, and the scaled
+        // function varies slowly enough for cubic interpolation between nodes
+        const double es = exp(s);
+        for (int c = 0; c < 6; ++c) {
+            acc[c].x = (acc[c].x + 2.0 * g0[c] * K0) * es;
+            acc[c].y = (acc[c].y - 2.0 * s * g1[6 * j + c] * K0) * es;
+        }
+    } else {
+        for (int q = 0; q < k.nzq; ++q) {
+            const double w = (q == 0 || q == k.nzq - 1) ? 0.5 * k.dz : k.dz;
+            for (int c = 0; c < 6; ++c) acc[c].x += w * rj[q * 6 + c];
+        }
+        for (int c = 0; c < 6; ++c) acc[c].x += 2.0 * g0[c] * (M_LN2 - 0.57721566490153286061);
+    }
+    for (int c = 0; c < 6; ++c) H[(int64_t)idx * 6 + c] = acc[c];
+}
+
+// ----------------------------------------------------------------------------------
+// Evaluation of the far-field block at (theta0, dn1, dn2): Catmull-Rom interpolation
+// of H in (log s, phi), the small-s logarithm below s_min, zero above s_max.
+// ----------------------------------------------------------------------------------
+__device__ inline double cr_w(double t, int k) {
+    // Catmull-Rom weights for points -1, 0, 1, 2 at parameter t in [0, 1)
+    const double t2 = t * t, t3 = t2 * t;
+    switch (k) {
+        case 0: return 0.5 * (-t3 + 2.0 * t2 - t);
+        case 1: return 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+        case 2: return 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+        default: return 0.5 * (t3 - t2);
+    }
+}
+
+__device__ void cgf_eval(const CgfView& v, double theta0, int dn1, int dn2, double2 out[6]) {
+    const double x = 0.5 * dn1;
+    const double y = (dn1 + 2.0 * dn2) * (0.5 * M_SQRT1_2);
+    const double rho = sqrt(x * x + y * y);
+    double phi = atan2(y, x);
+    if (phi < 0.0) phi += 2.0 * M_PI;
+    const double fp = phi / (2.0 * M_PI) * v.nphi;
+    int jp = (int)floor(fp);
+    const double tp = fp - jp;
+    const double inv_c = M_SQRT2;    // 1 / c with c = a / sqrt 2, a = 1
+    for (int c = 0; c < 6; ++c) out[c] = make_double2(0, 0);
+    if (theta0 == 0.0) {
+        for (int a = 0; a < 4; ++a) {
+            const int jj = ((jp - 1 + a) % v.nphi + v.nphi) % v.nphi;
+            const double wa = cr_w(tp, a);
+            for (int c = 0; c < 6; ++c) out[c].x += wa * v.H[((int64_t)jj * (v.ns + 1) + v.ns) * 6 + c].x;
+        }
+        const double lr = log(rho);
+        for (int c = 0; c < 6; ++c) out[c].x = (out[c].x - 2.0 * v.g0[c] * lr) * inv_c;
+        return;
+    }
+    const double kappa = 2.0 * M_PI * theta0 * inv_c;
+    const double s = kappa * rho;
+    if (s > v.s_max) return;
+    double ls = log(s);
+    double extra = 0.0;       // below s_min: H(s) = H(s_min) - 2 G0 log(s / s_min)
+    if (ls < v.ls_min) {
+        extra = ls - v.ls_min;
+        ls = v.ls_min;
+    }
+    const double fs = (ls - v.ls_min) / v.dls;
+    int is = (int)floor(fs);
+    double ts = fs - is;
+    if (is >= v.ns - 1) {
+        is = v.ns - 2;
+        ts = 1.0;
+    }
+    for (int a = 0; a < 4; ++a) {
+        const int jj = ((jp - 1 + a) % v.nphi + v.nphi) % v.nphi;
+        const double wa = cr_w(tp, a);
+        for (int b = 0; b < 4; ++b) {
+            const int ii = min(max(is - 1 + b, 0), v.ns - 1);
+            const double w = wa * cr_w(ts, b);
+            const double2* h = v.H + ((int64_t)jj * (v.ns + 1) + ii) * 6;
+            for (int c = 0; c < 6; ++c) {
+                out[c].x += w * h[c].x;
+                out[c].y += w * h[c].y;
+            }
+        }
+    }
+    const double unscale = exp(-exp(ls));      // table holds e^{s} H
+    for (int c = 0; c < 6; ++c) {
+        out[c].x *= unscale;
+        out[c].y *= unscale;
+    }
+    if (extra != 0.0)
+        for (int c = 0; c < 6; ++c) out[c].x -= 2.0 * v.g0[c] * extra;
+    double sp, cp;
+    sincospi(theta0 * dn1, &sp, &cp);
+    for (int c = 0; c < 6; ++c) {
+        const double re = out[c].x * cp - out[c].y * sp;
+        const double im = out[c].x * sp + out[c].y * cp;
+        out[c] = make_double2(re * inv_c, im * inv_c);
+    }
+}
+
+__global__ void __launch_bounds__(NTL) k_cgf_points(CgfView v, const double* __restrict__ theta0,
+                                                    const int32_t* __restrict__ d1,
+                                                    const int32_t* __restrict__ d2, int n,
+                                                    double2* __restrict__ out) {
+    const int i = blockIdx.x * NTL + threadIdx.x;
+    if (i >= n) return;
+    double2 o[6];
+    cgf_eval(v, theta0[i], d1[i], d2[i], o);
+    for (int c = 0; c < 6; ++c) out[(int64_t)i * 6 + c] = o[c];
+}
+
+void launch_cgf_points(hipStream_t st, const CgfView& v, const double* theta0, const int32_t* d1,
+                       const int32_t* d2, int n, double2* out) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_cgf_points, dim3((n + NTL - 1) / NTL), dim3(NTL), 0, st, v, theta0, d1,
+                           d2, n, out);
+}
+
+void launch_cgf_build(hipStream_t st, const CgfConst& k, const double* cpsi, const double* spsi,
+                      const double* rhat, double* g0, double* g1, double* rem, const double2* ph0,
+                      const double2* step, const double* k0s, double2* H) {
+    hipLaunchKernelGGL(k_cgf_g, dim3((k.nphi + 1 + 63) / 64), dim3(64), 0, st, k, cpsi, spsi, rhat, g0, g1);
+    const int64_t nrem = (int64_t)k.nphi * k.nzq;
+    hipLaunchKernelGGL(k_cgf_rem, dim3((unsigned)((nrem + NTL - 1) / NTL)), dim3(NTL), 0, st, k, cpsi,
+                       spsi, rhat, g0, g1, rem);
+    const int nh = k.nphi * (k.ns + 1);
+    hipLaunchKernelGGL(k_cgf_transform, dim3((nh + NTL - 1) / NTL), dim3(NTL), 0, st, k, rem, g0, g1, ph0,
+                       step, k0s, H);
+}
+
+// ----------------------------------------------------------------------------------
+// MLP 4 -> 128 -> 128 -> 128 -> 12, SiLU, FP32 training kernels.
+// Parameter layout: per layer W [out][in] row-major, then b [out].
+// ----------------------------------------------------------------------------------
+__device__ inline float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ inline float silu_d(float z) {
+    const float s = 1.0f / (1.0f + expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// out[s][o] = b[o] + sum_i in[s][i] W[o][i]; z stored, a = silu(z) unless last.
+__global__ void __launch_bounds__(NTL) k_dense_fwd(const float* __restrict__ in, int n, int ni, int no,
+                                                   const float* __restrict__ W,
+                                                   const float* __restrict__ b,
+                                                   float* __restrict__ z, float* __restrict__ a,
+                                                   int last) {
+    const int64_t idx = (int64_t)blockIdx.x * NTL + threadIdx.x;
+    if (idx >= (int64_t)n * no) return;
+    const int s = (int)(idx / no), o = (int)(idx - (int64_t)s * no);
+    float acc = b[o];
+    const float* x = in + (int64_t)s * ni;
+    const float* w = W + (int64_t)o * ni;
+    for (int i = 0; i < ni; ++i) acc = fmaf(x[i], w[i], acc);
+    z[idx] = acc;
+    a[idx] = last ? acc : silu(acc);
+}
+
+// dz = da * silu'(z) (or da for the last layer).
+__global__ void __launch_bounds__(NTL) k_dense_dz(const float* __restrict__ da,
+                                                  const float* __restrict__ z, int64_t total,
+                                                  float* __restrict__ dz, int last) {
+    const int64_t idx = (int64_t)blockIdx.x * NTL + threadIdx.x;
+    if (idx < total) dz[idx] = last ? da[idx] : da[idx] * silu_d(z[idx]);
+}
+// din[s][i] = sum_o dz[s][o] W[o][i].
+__global__ void __launch_bounds__(NTL) k_dense_bwd_x(const float* __restrict__ dz, int n, int ni, int no,
+                                                     const float* __restrict__ W,
+                                                     float* __restrict__ din) {
+    const int64_t idx = (int64_t)blockIdx.x * NTL + threadIdx.x;
+    if (idx >= (int64_t)n * ni) return;
+    const int s = (int)(idx / ni), i = (int)(idx - (int64_t)s * ni);
+    float acc = 0.0f;
+    const float* g = dz + (int64_t)s * no;
+    for (int o = 0; o < no; ++o) acc = fmaf(g[o], W[(int64_t)o * ni + i], acc);
+    din[idx] = acc;
+}
+// dW[o][i] = sum_s dz[s][o] in[s][i] (FP64 sum, fixed order); db[o] = sum_s dz[s][o].
+__global__ void __launch_bounds__(NTL) k_dense_bwd_w(const float* __restrict__ dz,
+                                                     const float* __restrict__ in, int n, int ni,
+                                                     int no, float* __restrict__ dW,
+                                                     float* __restrict__ db) {
+    const int idx = blockIdx.x * NTL + threadIdx.x;
+    if (idx >= no * (ni + 1)) return;
+    const int o = idx / (ni + 1), i = idx - o * (ni + 1);
+    double acc = 0.0;
+    if (i < ni)
+        for (int s = 0; s < n; ++s) acc += (double)dz[(int64_t)s * no + o] * in[(int64_t)s * ni + i];
+    else
+        for (int s = 0; s < n; ++s) acc += dz[(int64_t)s * no + o];
+    if (i < ni) dW[(int64_t)o * ni + i] = (float)acc;
+    else db[o] = (float)acc;
+}
+
+// Loss: mean over samples of sum over outputs of (w (y - t))^2; dy = 2 w^2 (y - t) / n.
+__global__ void __launch_bounds__(NTL) k_loss(const float* __restrict__ y, const float* __restrict__ t,
+                                              const float* __restrict__ wt, int n, int no,
+                                              float* __restrict__ dy, double* __restrict__ part) {
+    __shared__ double red[NTL];
+    double acc = 0.0;
+    for (int64_t idx = (int64_t)blockIdx.x * NTL + threadIdx.x; idx < (int64_t)n * no;
+         idx += (int64_t)gridDim.x * NTL) {
+        const int s = (int)(idx / no);
+        const float w = wt ? wt[s] : 1.0f;
+        const float d = y[idx] - t[idx];
+        dy[idx] = 2.0f * w * w * d / n;
+        acc += (double)(w * d) * (w * d);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = NTL / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_loss_final(const double* __restrict__ part, int np, int n, float* __restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < np; ++i) s += part[i];
+        *loss = (float)(s / n);
+    }
+}
+
+__global__ void __launch_bounds__(NTL) k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int n,
+                                              float lr, float b1, float b2, float eps, float c1,
+                                              float c2) {
+    const int i = blockIdx.x * NTL + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+static const int MLP_SIZES[5] = {MLP_IN, MLP_H, MLP_H, MLP_H, MLP_OUT};
+
+static int64_t layer_off(int l) {
+    int64_t off = 0;
+    for (int k = 0; k < l; ++k) off += (int64_t)MLP_SIZES[k + 1] * MLP_SIZES[k] + MLP_SIZES[k + 1];
+    return off;
+}
+
+// Workspace: activations z_l, a_l for l = 1..4 and gradients, n samples.
+int64_t mlp_workspace_floats(int n) {
+    int64_t t = 0;
+    for (int l = 1; l <= 4; ++l) t += 4 * (int64_t)n * MLP_SIZES[l];   // z, a, dz, da
+    return t + (int64_t)n * MLP_H + 4096;
+}
+
+void launch_mlp_forward(hipStream_t st, const float* params, const float* x, int n, float* ws,
+                        float* y) {
+    const float* in = x;
+    float* p = ws;
+    for (int l = 0; l < 4; ++l) {
+        const int ni = MLP_SIZES[l], no = MLP_SIZES[l + 1];
+        float* z = p;
+        float* a = (l == 3 && y) ? y : p + (int64_t)n * no;
+        const int64_t tot = (int64_t)n * no;
+        hipLaunchKernelGGL(k_dense_fwd, dim3((unsigned)((tot + NTL - 1) / NTL)), dim3(NTL), 0, st, in, n, ni,
+                           no, params + layer_off(l), params + layer_off(l) + (int64_t)no * ni, z, a,
+                           l == 3 ? 1 : 0);
+        in = a;
+        p += 4 * (int64_t)n * no;
+    }
+}
+
+void launch_mlp_loss_grad(hipStream_t st, const float* params, const float* x, const float* t,
+                          const float* w, int n, float* ws, float* grad, float* loss) {
+    launch_mlp_forward(st, params, x, n, ws, nullptr);
+    // pointers per layer
+    float* zl[4];
+    float* al[4];
+    float* dzl[4];
+    float* dal[4];
+    float* p = ws;
+    for (int l = 0; l < 4; ++l) {
+        const int no = MLP_SIZES[l + 1];
+        zl[l] = p;
+        al[l] = p + (int64_t)n * no;
+        dzl[l] = p + 2 * (int64_t)n * no;
+        dal[l] = p + 3 * (int64_t)n * no;
+        p += 4 * (int64_t)n * no;
+    }
+    double* part = (double*)(p + (int64_t)n * MLP_H);
+    const int nb = 256;
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(NTL), 0, st, al[3], t, w, n, MLP_OUT, dal[3], part);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, part, nb, n, loss);
+    for (int l = 3; l >= 0; --l) {
+        const int ni = MLP_SIZES[l], no = MLP_SIZES[l + 1];
+        const float* Wl = params + layer_off(l);
+        const int64_t tot = (int64_t)n * no;
+        hipLaunchKernelGGL(k_dense_dz, dim3((unsigned)((tot + NTL - 1) / NTL)), dim3(NTL), 0, st, dal[l],
+                           zl[l], tot, dzl[l], l == 3 ? 1 : 0);
+        const float* in = (l == 0) ? x : al[l - 1];
+        const int nw = no * (ni + 1);
+        hipLaunchKernelGGL(k_dense_bwd_w, dim3((nw + NTL - 1) / NTL), dim3(NTL), 0, st, dzl[l], in, n, ni, no,
+                           grad + layer_off(l), grad + layer_off(l) + (int64_t)no * ni);
+        if (l > 0) {
+            const int64_t ti = (int64_t)n * ni;
+            hipLaunchKernelGGL(k_dense_bwd_x, dim3((unsigned)((ti + NTL - 1) / NTL)), dim3(NTL), 0, st, dzl[l],
+                               n, ni, no, Wl, dal[l - 1]);
+        }
+    }
+}
+
+void launch_adam(hipStream_t st, float* p, const float* g, float* m, float* v, int n, float lr, int step) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((n + NTL - 1) / NTL), dim3(NTL), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1,
+                       c2);
+}
+
+// ----------------------------------------------------------------------------------
+// Training samples and the surrogate table generator.
+// Features of (theta0, dn1, dn2): (cos phi, sin phi, r_c / rho, 2 theta0).
+// Target / output: exp(-i pi theta0 dn1) (G^_lgf - G^_cgf) / env, env = |G^_cgf|_F + floor,
+// 6 complex components (xx yy zz xy xz yz) as 12 reals.
+// ----------------------------------------------------------------------------------
+__device__ inline void sur_features(double theta0, int dn1, int dn2, double r_c, float f[4],
+                                    double* rho_out) {
+    const double x = 0.5 * dn1;
+    const double y = (dn1 + 2.0 * dn2) * (0.5 * M_SQRT1_2);
+    const double rho = sqrt(x * x + y * y);
+    f[0] = (float)(x / rho);
+    f[1] = (float)(y / rho);
+    f[2] = (float)(r_c / rho);
+    f[3] = (float)(2.0 * theta0);
+    *rho_out = rho;
+}
+
+__device__ inline double sur_env(const double2 g[6], double floor_) {
+    double s = 0.0;
+    for (int c = 0; c < 6; ++c) {
+        const double w = (c < 3) ? 1.0 : 2.0;     // off-diagonal entries appear twice
+        s += w * (g[c].x * g[c].x + g[c].y * g[c].y);
+    }
+    return sqrt(s) + floor_;
+}
+
+__global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* __restrict__ tab,
+                                                     int64_t n_off, int nz_tab,
+                                                     const int32_t* __restrict__ d1,
+                                                     const int32_t* __restrict__ d2,
+                                                     const int32_t* __restrict__ pick_t,
+                                                     const int32_t* __restrict__ pick_o, int n,
+                                                     double r_c, double env_floor,
+                                                     float* __restrict__ x, float* __restrict__ t) {
+    const int i = blockIdx.x * NTL + threadIdx.x;
+    if (i >= n) return;
+    const int tm = pick_t[i];
+    const int64_t o = pick_o[i];
+    const double theta0 = (double)tm / nz_tab;
+    double2 g[6];
+    cgf_eval(v, theta0, d1[o], d2[o], g);
+    float f[4];
+    double rho;
+    sur_features(theta0, d1[o], d2[o], r_c, f, &rho);
+    const double env = sur_env(g, env_floor);
+    double sp, cp;
+    sincospi(theta0 * d1[o], &sp, &cp);
+    const double2* l = tab + ((int64_t)tm * n_off + o) * 6;
+    for (int a = 0; a < 4; ++a) x[(int64_t)i * 4 + a] = f[a];
+    for (int c = 0; c < 6; ++c) {
+        const double dr = l[c].x - g[c].x, di = l[c].y - g[c].y;
+        // multiply by exp(-i pi theta0 dn1)
+        t[(int64_t)i * 12 + 2 * c] = (float)((dr * cp + di * sp) / env);
+        t[(int64_t)i * 12 + 2 * c + 1] = (float)((di * cp - dr * sp) / env);
+    }
+}
+
+void launch_sur_samples(hipStream_t st, const CgfView& v, const double2* tab, int64_t n_off, int nz_tab,
+                        const int32_t* d1, const int32_t* d2, const int32_t* pick_t,
+                        const int32_t* pick_o, int n, double r_c, double env_floor, float* x,
+                        float* t) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_sur_samples, dim3((n + NTL - 1) / NTL), dim3(NTL), 0, st, v, tab, n_off, nz_tab,
+                           d1, d2, pick_t, pick_o, n, r_c, env_floor, x, t);
+}
+
+// MLP forward of one sample, bf16 weights (transposed, [in][out], read with wave-uniform
+// addresses), FP32 accumulation.  The hidden vector of each thread lives in its own LDS
+// column hl[i * stride]; every layer reads its inputs from there and overwrites them with
+// its outputs (the column is private to the thread, so no barrier is needed).
+#define MLP_BLOCK 64
+__device__ inline float bfv(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+struct MlpW {
+    const unsigned short* w1t;   // [4][128]
+    const unsigned short* w2t;   // [128][128]
+    const unsigned short* w3t;   // [128][128]
+    const unsigned short* w4t;   // [128][12]
+    const float* b1;
+    const float* b2;
+    const float* b3;
+    const float* b4;
+};
+
+__device__ inline MlpW mlp_view(const unsigned short* wb, const float* bias) {
+    MlpW m;
+    m.w1t = wb;
+    m.w2t = m.w1t + MLP_IN * MLP_H;
+    m.w3t = m.w2t + MLP_H * MLP_H;
+    m.w4t = m.w3t + MLP_H * MLP_H;
+    m.b1 = bias;
+    m.b2 = m.b1 + MLP_H;
+    m.b3 = m.b2 + MLP_H;
+    m.b4 = m.b3 + MLP_H;
+    return m;
+}
+
+__device__ inline void mlp_hidden(const unsigned short* __restrict__ wt, const float* __restrict__ b,
+                                  float* hl, int stride) {
+    float acc[MLP_H];
+#pragma unroll
+    for (int o = 0; o < MLP_H; ++o) acc[o] = b[o];
+    for (int i = 0; i < MLP_H; ++i) {
+        const float v = hl[i * stride];
+        const unsigned short* w = wt + i * MLP_H;
+#pragma unroll
+        for (int o = 0; o < MLP_H; ++o) acc[o] = fmaf(bfv(w[o]), v, acc[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < MLP_H; ++o) hl[o * stride] = silu(acc[o]);
+}
+
+__device__ void mlp_bf16_eval(const MlpW& m, const float f[4], float* hl, int stride,
+                              float y[MLP_OUT]) {
+    {
+        float acc[MLP_H];
+#pragma unroll
+        for (int o = 0; o < MLP_H; ++o) {
+            float a = m.b1[o];
+#pragma unroll
+            for (int i = 0; i < MLP_IN; ++i) a = fmaf(bfv(m.w1t[i * MLP_H + o]), f[i], a);
+            acc[o] = a;
+        }
+#pragma unroll
+        for (int o = 0; o < MLP_H; ++o) hl[o * stride] = silu(acc[o]);
+    }
+    mlp_hidden(m.w2t, m.b2, hl, stride);
+    mlp_hidden(m.w3t, m.b3, hl, stride);
+#pragma unroll
+    for (int o = 0; o < MLP_OUT; ++o) y[o] = m.b4[o];
+    for (int i = 0; i < MLP_H; ++i) {
+        const float v = hl[i * stride];
+#pragma unroll
+        for (int o = 0; o < MLP_OUT; ++o) y[o] = fmaf(bfv(m.w4t[i * MLP_OUT + o]), v, y[o]);
+    }
+}
+
+// Far-field block (CGF, optionally + MLP correction) at arbitrary points (gain test).
+__global__ void __launch_bounds__(MLP_BLOCK) k_sur_points(CgfView v, const unsigned short* __restrict__ wb,
+                                                    const float* __restrict__ bias, int use_mlp,
+                                                    double r_c, double env_floor,
+                                                    const double* __restrict__ theta0,
+                                                    const int32_t* __restrict__ d1,
+                                                    const int32_t* __restrict__ d2, int n,
+                                                    double2* __restrict__ out) {
+    __shared__ float hl[MLP_H * MLP_BLOCK];
+    const MlpW m = mlp_view(wb, bias);
+    const int i = blockIdx.x * MLP_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double2 g[6];
+    cgf_eval(v, theta0[i], d1[i], d2[i], g);
+    if (use_mlp) {
+        float f[4], y[MLP_OUT];
+        double rho;
+        sur_features(theta0[i], d1[i], d2[i], r_c, f, &rho);
+        const double env = sur_env(g, env_floor);
+        mlp_bf16_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
+        double sp, cp;
+        sincospi(theta0[i] * d1[i], &sp, &cp);
+        for (int c = 0; c < 6; ++c) {
+            const double cr = env * y[2 * c], ci = env * y[2 * c + 1];
+            g[c].x += cr * cp - ci * sp;
+            g[c].y += cr * sp + ci * cp;
+        }
+    }
+    for (int c = 0; c < 6; ++c) out[(int64_t)i * 6 + c] = g[c];
+}
+
+void launch_sur_points(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
+                       int use_mlp, double r_c, double env_floor, const double* theta0,
+                       const int32_t* d1, const int32_t* d2, int n, double2* out) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_sur_points, dim3((n + MLP_BLOCK - 1) / MLP_BLOCK), dim3(MLP_BLOCK), 0, st, v, wb, bias, use_mlp,
+                           r_c, env_floor, theta0, d1, d2, n, out);
+}
+
+// Table slice generator of the surrogate form: table modes t0 .. t0+nt-1 for every
+// offset o (offsets numbered by increasing rho): o < n_near: exact lattice value;
+// o < n_need[t]: continuum + learned correction; beyond: zero (kappa rho > s_max).
+__global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const unsigned short* __restrict__ wb,
+                                                      const float* __restrict__ bias, double r_c,
+                                                      double env_floor, int nz_tab, int t0,
+                                                      const double2* __restrict__ near_tab,
+                                                      int64_t n_near, int64_t n_off,
+                                                      const int32_t* __restrict__ n_need,
+                                                      const int32_t* __restrict__ d1,
+                                                      const int32_t* __restrict__ d2,
+                                                      double2* __restrict__ out) {
+    __shared__ float hl[MLP_H * MLP_BLOCK];
+    const MlpW m = mlp_view(wb, bias);
+    const int tl = blockIdx.y;
+    const int tm = t0 + tl;
+    const int64_t o = (int64_t)blockIdx.x * MLP_BLOCK + threadIdx.x;
+    if (o >= n_off) return;
+    double2* dst = out + ((int64_t)tl * n_off + o) * 6;
+    if (o < n_near) {
+        const double2* src = near_tab + ((int64_t)tm * n_near + o) * 6;
+        for (int c = 0; c < 6; ++c) dst[c] = src[c];
+        return;
+    }
+    if (o >= n_need[tm]) {
+        for (int c = 0; c < 6; ++c) dst[c] = make_double2(0, 0);
+        return;
+    }
+    const double theta0 = (double)tm / nz_tab;
+    double2 g[6];
+    cgf_eval(v, theta0, d1[o], d2[o], g);
+    float f[4], y[MLP_OUT];
+    double rho;
+    sur_features(theta0, d1[o], d2[o], r_c, f, &rho);
+    const double env = sur_env(g, env_floor);
+    mlp_bf16_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
+    double sp, cp;
+    sincospi(theta0 * d1[o], &sp, &cp);
+    for (int c = 0; c < 6; ++c) {
+        const double cr = env * y[2 * c], ci = env * y[2 * c + 1];
+        dst[c] = make_double2(g[c].x + cr * cp - ci * sp, g[c].y + cr * sp + ci * cp);
+    }
+}
+
+void launch_sur_generate(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
+                         double r_c, double env_floor, int nz_tab, int t0, int nt,
+                         const double2* near_tab, int64_t n_near, int64_t n_off,
+                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, double2* out) {
+    dim3 grid((unsigned)((n_off + MLP_BLOCK - 1) / MLP_BLOCK), nt);
+    hipLaunchKernelGGL(k_sur_generate, grid, dim3(MLP_BLOCK), 0, st, v, wb, bias, r_c, env_floor, nz_tab, t0,
+                       near_tab, n_near, n_off, n_need, d1, d2, out);
+}
+
+// FP32 weights -> transposed bf16 (round to nearest even) and biases, for inference.
+__global__ void k_mlp_to_bf16(const float* __restrict__ params, unsigned short* __restrict__ wb,
+                              float* __restrict__ bias) {
+    const int sizes[5] = {MLP_IN, MLP_H, MLP_H, MLP_H, MLP_OUT};
+    int64_t off = 0, ow = 0, ob = 0;
+    for (int l = 0; l < 4; ++l) {
+        const int ni = sizes[l], no = sizes[l + 1];
+        for (int e = threadIdx.x; e < no * ni; e += blockDim.x) {
+            const int o = e / ni, i = e - o * ni;           // W [o][i] -> Wt [i][o]
+            unsigned u = __float_as_uint(params[off + e]);
+            u += 0x7FFFu + ((u >> 16) & 1u);
+            wb[ow + (int64_t)i * no + o] = (unsigned short)(u >> 16);
+        }
+        for (int i = threadIdx.x; i < no; i += blockDim.x) bias[ob + i] = params[off + (int64_t)no * ni + i];
+        off += (int64_t)no * ni + no;
+        ow += (int64_t)no * ni;
+        ob += no;
+    }
+}
+
+void launch_mlp_to_bf16(hipStream_t st, const float* params, unsigned short* wb, float* bias) {
+    hipLaunchKernelGGL(k_mlp_to_bf16, dim3(1), dim3(256), 0, st, params, wb, bias);
+}

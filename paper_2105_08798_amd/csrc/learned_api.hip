@@ -1,0 +1,309 @@
+// C ABI of the learned far-field form: continuum table, MLP training, evaluation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+static thread_local std::string g_lerr;
+
+static fbc_status lfail(std::string* dst, fbc_status s, const std::string& m) {
+    if (dst) *dst = m;
+    g_lerr = m;
+    return s;
+}
+
+#define LCHK(dst, expr)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return lfail(dst, FBC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+static fbc_status lalloc(std::vector<void*>& list, std::string* err, T** p, int64_t bytes) {
+    *p = nullptr;
+    if (bytes <= 0) return FBC_OK;
+    hipError_t e = hipMalloc((void**)p, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return lfail(err, FBC_E_NOMEM, "hipMalloc(" + std::to_string(bytes) + " B)");
+    }
+    list.push_back(*p);
+    return FBC_OK;
+}
+
+extern "C" const char* fbc_learned_last_error(void) { return g_lerr.c_str(); }
+
+// ----------------------------------------------------------------------------------
+// Continuum table.  Cubic constants of the nearest-neighbour central-spring crystal
+// (C11 = 2k/a, C12 = C44 = k/a), line direction [1-10], in-plane axes [001] and
+// [110]/sqrt2.  Grids: psi 48 nodes, phi 256 directions, z on [-400, 400] step 1/64,
+// s log-spaced on [1e-3, 40] (256 nodes) plus the kappa = 0 column.
+// ----------------------------------------------------------------------------------
+extern "C" fbc_status fbc_sur_create(const fbc_lattice* lat, double r_c, void* stream, fbc_sur** out) {
+    if (!out) return lfail(nullptr, FBC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!lat || !(lat->spring_k > 0) || !(lat->a > 0)) return lfail(nullptr, FBC_E_ARG, "lattice");
+    if (!(r_c > 0) || !(r_c < 1e4)) return lfail(nullptr, FBC_E_ARG, "r_c must be in (0, 1e4)");
+    fbc_sur* s = new (std::nothrow) fbc_sur();
+    if (!s) return lfail(nullptr, FBC_E_NOMEM, "host allocation");
+    hipStream_t st = (hipStream_t)stream;
+    s->r_c = r_c;
+    CgfConst& k = s->k;
+    k.c11 = 2.0 * lat->spring_k / lat->a;
+    k.c12 = lat->spring_k / lat->a;
+    k.c44 = lat->spring_k / lat->a;
+    k.t[0] = M_SQRT1_2;
+    k.t[1] = -M_SQRT1_2;
+    k.t[2] = 0.0;
+    k.npsi = 48;
+    k.nphi = 256;
+    k.zmax = 400.0;
+    k.dz = 1.0 / 64.0;
+    k.nzq = (int)std::lround(2.0 * k.zmax / k.dz) + 1;
+    k.ns = 256;
+    k.s_min = 1e-3;
+    k.s_max = 40.0;
+    std::vector<double> cpsi(k.npsi), spsi(k.npsi), rhat(3 * k.nphi);
+    for (int l = 0; l < k.npsi; ++l) {
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * l / k.npsi;
+        cpsi[l] = (double)cosl(a);
+        spsi[l] = (double)sinl(a);
+    }
+    const double e1[3] = {0, 0, 1}, e2[3] = {M_SQRT1_2, M_SQRT1_2, 0};
+    for (int j = 0; j < k.nphi; ++j) {
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * j / k.nphi;
+        const double c = (double)cosl(a), sn = (double)sinl(a);
+        for (int q = 0; q < 3; ++q) rhat[3 * j + q] = c * e1[q] + sn * e2[q];
+    }
+    std::vector<double2> ph0(k.ns), step(k.ns);
+    std::vector<double> k0s(2 * k.ns);
+    for (int i = 0; i < k.ns; ++i) {
+        const double si = k.s_min * std::pow(k.s_max / k.s_min, (double)i / (k.ns - 1));
+        const long double a0 = (long double)si * k.zmax;      // exp(-i s z0), z0 = -zmax
+        ph0[i] = make_double2((double)cosl(a0), (double)sinl(a0));
+        const long double a1 = -(long double)si * k.dz;
+        step[i] = make_double2((double)cosl(a1), (double)sinl(a1));
+        k0s[2 * i] = std::cyl_bessel_k(0.0, si);
+        k0s[2 * i + 1] = si;
+    }
+    double *d_cpsi, *d_spsi, *d_rhat, *d_g1, *d_rem, *d_k0s;
+    double2 *d_ph0, *d_step;
+    std::vector<void*> tmp;
+    fbc_status rc;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (void* p : tmp) (void)hipFree(p);
+    };
+    if ((rc = lalloc(tmp, &s->err, &d_cpsi, k.npsi * 8)) || (rc = lalloc(tmp, &s->err, &d_spsi, k.npsi * 8)) ||
+        (rc = lalloc(tmp, &s->err, &d_rhat, (int64_t)rhat.size() * 8)) ||
+        (rc = lalloc(tmp, &s->err, &d_g1, (int64_t)k.nphi * 6 * 8)) ||
+        (rc = lalloc(tmp, &s->err, &d_rem, (int64_t)k.nphi * k.nzq * 6 * 8)) ||
+        (rc = lalloc(tmp, &s->err, &d_k0s, (int64_t)k0s.size() * 8)) ||
+        (rc = lalloc(tmp, &s->err, &d_ph0, (int64_t)k.ns * 16)) ||
+        (rc = lalloc(tmp, &s->err, &d_step, (int64_t)k.ns * 16)) ||
+        (rc = lalloc(s->allocs, &s->err, &s->g0, 6 * 8)) ||
+        (rc = lalloc(s->allocs, &s->err, &s->H, (int64_t)k.nphi * (k.ns + 1) * 6 * 16)) ||
+        (rc = lalloc(s->allocs, &s->err, &s->wb, (int64_t)MLP_NW * 2)) ||
+        (rc = lalloc(s->allocs, &s->err, &s->bias, (int64_t)MLP_NB * 4))) {
+        cleanup();
+        for (void* p : s->allocs) (void)hipFree(p);
+        delete s;
+        return rc;
+    }
+    (void)hipMemcpyAsync(d_cpsi, cpsi.data(), k.npsi * 8, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d_spsi, spsi.data(), k.npsi * 8, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d_rhat, rhat.data(), rhat.size() * 8, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d_k0s, k0s.data(), k0s.size() * 8, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d_ph0, ph0.data(), ph0.size() * 16, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(d_step, step.data(), step.size() * 16, hipMemcpyHostToDevice, st);
+    launch_cgf_build(st, k, d_cpsi, d_spsi, d_rhat, s->g0, d_g1, d_rem, d_ph0, d_step, d_k0s, s->H);
+    hipError_t e = hipGetLastError();
+    cleanup();
+    if (e != hipSuccess) {
+        for (void* p : s->allocs) (void)hipFree(p);
+        delete s;
+        return lfail(nullptr, FBC_E_DEVICE, std::string("continuum table: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return FBC_OK;
+}
+
+extern "C" void fbc_sur_destroy(fbc_sur* s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : s->allocs) (void)hipFree(p);
+    delete s;
+}
+
+extern "C" fbc_status fbc_sur_set_mlp(fbc_sur* s, const fbc_mlp* net, void* stream) {
+    if (!s || !net) return lfail(nullptr, FBC_E_ARG, "null argument");
+    launch_mlp_to_bf16((hipStream_t)stream, net->params, s->wb, s->bias);
+    LCHK(&s->err, hipGetLastError());
+    LCHK(&s->err, hipStreamSynchronize((hipStream_t)stream));
+    s->has_mlp = 1;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_sur_eval(const fbc_sur* s, const double* theta0, const int32_t* dn1,
+                                   const int32_t* dn2, int n, int use_mlp, double* out, void* stream) {
+    if (!s || !theta0 || !dn1 || !dn2 || !out || n < 0) return lfail(nullptr, FBC_E_ARG, "null argument");
+    if (use_mlp && !s->has_mlp) return lfail(nullptr, FBC_E_STATE, "no MLP weights set");
+    launch_sur_points((hipStream_t)stream, s->view(), s->wb, s->bias, use_mlp ? 1 : 0, s->r_c, s->env_floor,
+                      theta0, dn1, dn2, n, (double2*)out);
+    LCHK(nullptr, hipGetLastError());
+    return FBC_OK;
+}
+
+// Training set from an offset-table context (its table holds lattice values for every
+// distinct offset and line mode of its cells): samples (mode t, offset o) with
+// |r_perp| > r_c and kappa |r_perp| <= s_max, drawn with a seeded generator.
+extern "C" fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* c, int max_samples,
+                                           uint64_t seed, float* x, float* t, int* n_out,
+                                           void* stream) {
+    if (!s || !c || !x || !t || !n_out || max_samples < 1) return lfail(nullptr, FBC_E_ARG, "null argument");
+    if (c->opt.form != FBC_FORM_DTABLE_FP64 || !c->tab || !c->off_d1)
+        return lfail(nullptr, FBC_E_STATE, "training data needs an offset-table context");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n_off = c->n_offsets;
+    const int T = c->nz_max / 2 + 1;
+    std::vector<int32_t> d1(n_off), d2(n_off);
+    LCHK(nullptr, hipMemcpy(d1.data(), c->off_d1, n_off * 4, hipMemcpyDeviceToHost));
+    LCHK(nullptr, hipMemcpy(d2.data(), c->off_d2, n_off * 4, hipMemcpyDeviceToHost));
+    std::vector<double> rho(n_off);
+    for (int64_t o = 0; o < n_off; ++o) {
+        const double xx = 0.5 * d1[o], yy = (d1[o] + 2.0 * d2[o]) * (0.5 * M_SQRT1_2);
+        rho[o] = std::sqrt(xx * xx + yy * yy);
+    }
+    std::mt19937_64 gen(seed);
+    std::uniform_int_distribution<int64_t> pick_o(0, n_off - 1);
+    std::uniform_int_distribution<int> pick_t(0, T - 1);
+    std::vector<int32_t> pt, po;
+    pt.reserve(max_samples);
+    po.reserve(max_samples);
+    int64_t tries = 0;
+    const int64_t max_tries = 200LL * max_samples + 1000;
+    while ((int)pt.size() < max_samples && tries < max_tries) {
+        ++tries;
+        const int64_t o = pick_o(gen);
+        const int tm = pick_t(gen);
+        if (rho[o] <= s->r_c) continue;
+        const double kap = 2.0 * M_PI * ((double)tm / c->nz_max) * M_SQRT2;
+        if (kap * rho[o] > s->k.s_max) continue;
+        pt.push_back(tm);
+        po.push_back((int32_t)o);
+    }
+    const int n = (int)pt.size();
+    int32_t *dpt = nullptr, *dpo = nullptr;
+    if (n > 0) {
+        LCHK(nullptr, hipMalloc((void**)&dpt, (size_t)n * 4));
+        if (hipMalloc((void**)&dpo, (size_t)n * 4) != hipSuccess) {
+            (void)hipFree(dpt);
+            return lfail(nullptr, FBC_E_NOMEM, "sample index list");
+        }
+        (void)hipMemcpyAsync(dpt, pt.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+        (void)hipMemcpyAsync(dpo, po.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+        launch_sur_samples(st, s->view(), c->tab, n_off, c->nz_max, c->off_d1, c->off_d2, dpt, dpo, n, s->r_c,
+                           s->env_floor, x, t);
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(dpt);
+        (void)hipFree(dpo);
+    }
+    *n_out = n;
+    LCHK(nullptr, hipGetLastError());
+    return FBC_OK;
+}
+
+// ----------------------------------------------------------------------------------
+// MLP training objects.
+// ----------------------------------------------------------------------------------
+extern "C" fbc_status fbc_mlp_create(int max_batch, uint64_t seed, fbc_mlp** out) {
+    if (!out) return lfail(nullptr, FBC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > (1 << 22)) return lfail(nullptr, FBC_E_ARG, "max_batch in [1, 2^22]");
+    fbc_mlp* m = new (std::nothrow) fbc_mlp();
+    if (!m) return lfail(nullptr, FBC_E_NOMEM, "host allocation");
+    m->max_batch = max_batch;
+    fbc_status rc;
+    if ((rc = lalloc(m->allocs, &m->err, &m->params, MLP_NPARAMS * 4)) ||
+        (rc = lalloc(m->allocs, &m->err, &m->grad, MLP_NPARAMS * 4)) ||
+        (rc = lalloc(m->allocs, &m->err, &m->m, MLP_NPARAMS * 4)) ||
+        (rc = lalloc(m->allocs, &m->err, &m->v, MLP_NPARAMS * 4)) ||
+        (rc = lalloc(m->allocs, &m->err, &m->loss, 64)) ||
+        (rc = lalloc(m->allocs, &m->err, &m->ws, mlp_workspace_floats(max_batch) * 4))) {
+        for (void* p : m->allocs) (void)hipFree(p);
+        delete m;
+        return rc;
+    }
+    // normal(0, 1/sqrt(fan_in)) weights, zero biases, from a seeded host generator
+    std::vector<float> p(MLP_NPARAMS, 0.0f);
+    std::mt19937_64 gen(seed);
+    const int sizes[5] = {MLP_IN, MLP_H, MLP_H, MLP_H, MLP_OUT};
+    int64_t off = 0;
+    for (int l = 0; l < 4; ++l) {
+        std::normal_distribution<double> nd(0.0, 1.0 / std::sqrt((double)sizes[l]));
+        for (int i = 0; i < sizes[l + 1] * sizes[l]; ++i) p[off + i] = (float)nd(gen);
+        off += (int64_t)sizes[l + 1] * sizes[l] + sizes[l + 1];
+    }
+    (void)hipMemcpy(m->params, p.data(), p.size() * 4, hipMemcpyHostToDevice);
+    (void)hipMemset(m->m, 0, MLP_NPARAMS * 4);
+    (void)hipMemset(m->v, 0, MLP_NPARAMS * 4);
+    *out = m;
+    return FBC_OK;
+}
+
+extern "C" void fbc_mlp_destroy(fbc_mlp* m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : m->allocs) (void)hipFree(p);
+    delete m;
+}
+
+extern "C" int fbc_mlp_num_params(void) { return MLP_NPARAMS; }
+
+extern "C" fbc_status fbc_mlp_params(fbc_mlp* m, float* host_out, const float* host_in) {
+    if (!m) return lfail(nullptr, FBC_E_ARG, "null argument");
+    LCHK(&m->err, hipDeviceSynchronize());
+    if (host_in) LCHK(&m->err, hipMemcpy(m->params, host_in, MLP_NPARAMS * 4, hipMemcpyHostToDevice));
+    if (host_out) LCHK(&m->err, hipMemcpy(host_out, m->params, MLP_NPARAMS * 4, hipMemcpyDeviceToHost));
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_mlp_grad(fbc_mlp* m, float* host_out) {
+    if (!m || !host_out) return lfail(nullptr, FBC_E_ARG, "null argument");
+    LCHK(&m->err, hipDeviceSynchronize());
+    LCHK(&m->err, hipMemcpy(host_out, m->grad, MLP_NPARAMS * 4, hipMemcpyDeviceToHost));
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_mlp_loss_grad(fbc_mlp* m, const float* x, const float* t, int n,
+                                        float* loss_dev, void* stream) {
+    if (!m || !x || !t) return lfail(nullptr, FBC_E_ARG, "null argument");
+    if (n < 1 || n > m->max_batch) return lfail(&m->err, FBC_E_ARG, "batch size out of range");
+    launch_mlp_loss_grad((hipStream_t)stream, m->params, x, t, nullptr, n, m->ws, m->grad,
+                         loss_dev ? loss_dev : m->loss);
+    LCHK(&m->err, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_mlp_adam_step(fbc_mlp* m, float lr, void* stream) {
+    if (!m || !(lr > 0)) return lfail(nullptr, FBC_E_ARG, "bad argument");
+    m->step += 1;
+    launch_adam((hipStream_t)stream, m->params, m->grad, m->m, m->v, MLP_NPARAMS, lr, m->step);
+    LCHK(&m->err, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_mlp_forward(fbc_mlp* m, const float* x, float* y, int n, void* stream) {
+    if (!m || !x || !y) return lfail(nullptr, FBC_E_ARG, "null argument");
+    if (n < 1 || n > m->max_batch) return lfail(&m->err, FBC_E_ARG, "batch size out of range");
+    launch_mlp_forward((hipStream_t)stream, m->params, x, n, m->ws, y);
+    LCHK(&m->err, hipGetLastError());
+    return FBC_OK;
+}

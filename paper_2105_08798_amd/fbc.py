@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(_HERE, "libfbc.so")
 FBC_OK = 0
 STATUS = {0: "FBC_OK", -1: "FBC_E_ARG", -2: "FBC_E_NOMEM", -3: "FBC_E_NETFORCE",
           -4: "FBC_E_NONFINITE", -5: "FBC_E_DEVICE", -6: "FBC_E_STATE", -7: "FBC_E_UNSUPPORTED"}
-FORMS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "dtable_fp64": 3}
+FORMS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "dtable_fp64": 3, "surrogate": 4}
 
 EXPORTED = [
     "fbc_default_options", "fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin",
     "fbc_relax_step", "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_destroy",
     "fbc_last_error", "fbc_status_string", "fbc_timing", "fbc_timing_read", "fbc_apply_graph",
-    "fbc_autotune",
+    "fbc_autotune", "fbc_learned_last_error", "fbc_sur_create", "fbc_sur_destroy", "fbc_sur_set_mlp",
+    "fbc_sur_eval", "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_destroy", "fbc_mlp_num_params",
+    "fbc_mlp_params", "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
 ]
 
 
@@ -46,7 +48,8 @@ class Cell(C.Structure):
 class Options(C.Structure):
     _fields_ = [("form", C.c_int), ("bz_m1", C.c_int), ("bz_m2", C.c_int),
                 ("check_netforce", C.c_int), ("project_netforce", C.c_int),
-                ("netforce_tol", C.c_double), ("row_gauge", C.c_int)]
+                ("netforce_tol", C.c_double), ("row_gauge", C.c_int), ("surrogate", C.c_void_p),
+                ("gen_modes", C.c_int)]
 
 
 class RelaxOpts(C.Structure):
@@ -105,8 +108,28 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_last_error.restype = cp
     lib.fbc_status_string.argtypes = [C.c_int]
     lib.fbc_status_string.restype = cp
+    lib.fbc_learned_last_error.argtypes = []
+    lib.fbc_learned_last_error.restype = cp
+    lib.fbc_sur_create.argtypes = [C.POINTER(Lattice), C.c_double, vp, C.POINTER(vp)]
+    lib.fbc_sur_destroy.argtypes = [vp]
+    lib.fbc_sur_destroy.restype = None
+    lib.fbc_sur_set_mlp.argtypes = [vp, vp, vp]
+    lib.fbc_sur_eval.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, vp, vp]
+    lib.fbc_sur_training_set.argtypes = [vp, vp, C.c_int, C.c_uint64, vp, vp, C.POINTER(C.c_int), vp]
+    lib.fbc_mlp_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
+    lib.fbc_mlp_destroy.argtypes = [vp]
+    lib.fbc_mlp_destroy.restype = None
+    lib.fbc_mlp_num_params.argtypes = []
+    lib.fbc_mlp_params.argtypes = [vp, vp, vp]
+    lib.fbc_mlp_grad.argtypes = [vp, vp]
+    lib.fbc_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp]
+    lib.fbc_mlp_adam_step.argtypes = [vp, C.c_float, vp]
+    lib.fbc_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
-                 "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read", "fbc_apply_graph", "fbc_autotune"):
+                 "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
+                 "fbc_apply_graph", "fbc_autotune", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
+                 "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_num_params", "fbc_mlp_params",
+                 "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -121,11 +144,17 @@ def _stream_handle(stream) -> int | None:
     return stream.cuda_stream
 
 
-def _dptr(t) -> int:
+def _dptr(t, dtype=None) -> int:
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError("expected a contiguous float64 CUDA tensor")
+    dtype = torch.float64 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
     return t.data_ptr()
+
+
+def _lcheck(lib, rc):
+    if rc != FBC_OK:
+        raise FbcError(rc, lib.fbc_learned_last_error().decode())
 
 
 class FBC:
@@ -133,7 +162,8 @@ class FBC:
 
     def __init__(self, cells, bz: int | tuple, form: str = "fp64", spring_k: float = 1.0,
                  lattice_a: float = 1.0, check_netforce: bool = True, project_netforce: bool = False,
-                 netforce_tol: float = 1e-10, row_gauge: bool = True, stream=None):
+                 netforce_tol: float = 1e-10, row_gauge: bool = True, surrogate=None, gen_modes: int = 0,
+                 stream=None):
         lib = load_library()
         self._lib = lib
         self.ctx = C.c_void_p()
@@ -146,6 +176,9 @@ class FBC:
         opt.project_netforce = int(bool(project_netforce))
         opt.netforce_tol = float(netforce_tol)
         opt.row_gauge = int(bool(row_gauge))
+        opt.surrogate = surrogate.handle.value if surrogate is not None else None
+        opt.gen_modes = int(gen_modes)
+        self._sur = surrogate          # the context reads it on every apply
         self.form = form
         self._keep = []
         arr = (Cell * len(cells))()
@@ -218,6 +251,106 @@ class FBC:
         if self.ctx:
             self._lib.fbc_destroy(self.ctx)
             self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Trainable far-field correction network (FP32 parameters and Adam state on device)."""
+
+    def __init__(self, max_batch: int, seed: int = 0):
+        lib = load_library()
+        self._lib = lib
+        self.handle = C.c_void_p()
+        _lcheck(lib, lib.fbc_mlp_create(int(max_batch), C.c_uint64(seed), C.byref(self.handle)))
+        self.n_params = lib.fbc_mlp_num_params()
+        self.max_batch = int(max_batch)
+
+    def params(self, new: np.ndarray | None = None) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        src = None
+        if new is not None:
+            src = np.ascontiguousarray(new, dtype=np.float32)
+            if src.size != self.n_params:
+                raise ValueError("parameter vector has the wrong length")
+        _lcheck(self._lib, self._lib.fbc_mlp_params(self.handle, out.ctypes.data,
+                                                    None if src is None else src.ctypes.data))
+        return out
+
+    def grad(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _lcheck(self._lib, self._lib.fbc_mlp_grad(self.handle, out.ctypes.data))
+        return out
+
+    def loss_grad(self, x, t, loss_out=None, stream=None):
+        import torch
+        n = int(x.shape[0])
+        _lcheck(self._lib, self._lib.fbc_mlp_loss_grad(
+            self.handle, _dptr(x, torch.float32), _dptr(t, torch.float32), n,
+            None if loss_out is None else _dptr(loss_out, torch.float32), _stream_handle(stream)))
+
+    def adam_step(self, lr: float, stream=None):
+        _lcheck(self._lib, self._lib.fbc_mlp_adam_step(self.handle, C.c_float(lr), _stream_handle(stream)))
+
+    def forward(self, x, y, stream=None):
+        import torch
+        _lcheck(self._lib, self._lib.fbc_mlp_forward(self.handle, _dptr(x, torch.float32),
+                                                     _dptr(y, torch.float32), int(x.shape[0]),
+                                                     _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            self._lib.fbc_mlp_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Surrogate:
+    """Continuum table plus BF16 inference weights of the far-field correction."""
+
+    def __init__(self, r_c: float = 6.0, spring_k: float = 1.0, lattice_a: float = 1.0, stream=None):
+        lib = load_library()
+        self._lib = lib
+        self.handle = C.c_void_p()
+        self.r_c = float(r_c)
+        lat = Lattice(float(lattice_a), float(spring_k))
+        _lcheck(lib, lib.fbc_sur_create(C.byref(lat), self.r_c, _stream_handle(stream), C.byref(self.handle)))
+
+    def set_mlp(self, net: MLP, stream=None):
+        _lcheck(self._lib, self._lib.fbc_sur_set_mlp(self.handle, net.handle, _stream_handle(stream)))
+
+    def eval(self, theta0, dn1, dn2, out, use_mlp: bool, stream=None):
+        """theta0 float64, dn1/dn2 int32 (device); out float64 [n, 6, 2] (device)."""
+        import torch
+        n = int(theta0.shape[0])
+        _lcheck(self._lib, self._lib.fbc_sur_eval(self.handle, _dptr(theta0), _dptr(dn1, torch.int32),
+                                                  _dptr(dn2, torch.int32), n, int(bool(use_mlp)),
+                                                  _dptr(out), _stream_handle(stream)))
+
+    def training_set(self, table_ctx: "FBC", max_samples: int, seed: int, stream=None):
+        """Returns (x [n, 4], t [n, 12]) float32 device tensors drawn from the table context."""
+        import torch
+        x = torch.empty((max_samples, 4), dtype=torch.float32, device="cuda")
+        t = torch.empty((max_samples, 12), dtype=torch.float32, device="cuda")
+        n = C.c_int()
+        _lcheck(self._lib, self._lib.fbc_sur_training_set(self.handle, table_ctx.ctx, int(max_samples),
+                                                          C.c_uint64(seed), x.data_ptr(), t.data_ptr(),
+                                                          C.byref(n), _stream_handle(stream)))
+        return x[:n.value], t[:n.value]
+
+    def close(self):
+        if self.handle:
+            self._lib.fbc_sur_destroy(self.handle)
+            self.handle = C.c_void_p()
 
     def __del__(self):
         try:

@@ -41,7 +41,7 @@ def test_struct_layouts_match_header_sizes():
     fbc, _ = _lib()
     assert C.sizeof(fbc.Cell) == 32
     assert C.sizeof(fbc.RelaxOut) == 56
-    assert C.sizeof(fbc.Options) == 40
+    assert C.sizeof(fbc.Options) == 56
 
 
 def test_default_options():
@@ -89,3 +89,26 @@ def test_null_context_calls_fail_cleanly():
     assert lib.fbc_sync_status(None, None) == -1
     lib.fbc_destroy(None)
     assert lib.fbc_status_string(-3) == b"non-zero net force per layer"
+
+
+def test_surrogate_form_needs_a_surrogate_object():
+    fbc, lib = _lib()
+    rc, out = _assemble(lib, fbc, form=4)
+    assert rc == -1 and not out.value
+
+
+def test_learned_calls_reject_bad_arguments_on_the_host():
+    fbc, lib = _lib()
+    from oracle import mlp as omlp
+    assert lib.fbc_mlp_num_params() == omlp.n_params()
+    out = C.c_void_p()
+    assert lib.fbc_mlp_create(0, C.c_uint64(1), C.byref(out)) == -1 and not out.value
+    assert lib.fbc_mlp_create(1 << 23, C.c_uint64(1), C.byref(out)) == -1 and not out.value
+    lat = fbc.Lattice(1.0, 1.0)
+    assert lib.fbc_sur_create(None, 6.0, None, C.byref(out)) == -1 and not out.value
+    assert lib.fbc_sur_create(C.byref(lat), -1.0, None, C.byref(out)) == -1 and not out.value
+    assert lib.fbc_sur_create(C.byref(fbc.Lattice(1.0, -1.0)), 6.0, None, C.byref(out)) == -1
+    assert lib.fbc_sur_eval(None, None, None, None, 1, 0, None, None) == -1
+    assert lib.fbc_mlp_loss_grad(None, None, None, 1, None, None) == -1
+    assert lib.fbc_mlp_adam_step(None, C.c_float(1e-3), None) == -1
+    assert lib.fbc_learned_last_error()

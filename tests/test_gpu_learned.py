@@ -1,0 +1,299 @@
+"""GPU tests of the learned far-field form (through the C ABI) against the FP64 oracle.
+
+* continuum Green function in the line-mode representation (table + interpolation on
+  the device) against the oracle's direct z quadrature;
+* MLP forward pass and parameter gradient (FP32 kernels) against the FP64 oracle with
+  the same FP32 parameters; BF16 inference against the oracle with BF16-rounded weights;
+* training data drawn from an offset-table context against oracle lattice and
+  continuum values;
+* the surrogate product form: exact when every offset lies inside r_c (any chunking),
+  and the gain test -- with the same continuum far field, the learned correction
+  must bring the pad update much closer to the exact lattice result than the
+  continuum alone.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import fbc_workloads as W
+from oracle import apply as oap, cgf as ocg, green as ogr, mlp as omlp, split as osp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SYM = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]     # component order of the 6-vectors
+R_C = 6.0
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _sym6(g):
+    return np.array([g[a, b] for a, b in SYM])
+
+
+def _features(theta0, dn1, dn2, r_c=R_C):
+    r = ocg.in_plane_vector(dn1, dn2)
+    x, y = r @ ocg.E1, r @ ocg.E2
+    rho = np.hypot(x, y)
+    return np.stack([x / rho, y / rho, r_c / rho, 2.0 * np.asarray(theta0)], axis=-1), rho
+
+
+_SUR = {}
+
+
+def _surrogate():
+    from paper_2105_08798_amd import Surrogate
+    if "s" not in _SUR:
+        _dev()
+        _SUR["s"] = Surrogate(r_c=R_C)
+    return _SUR["s"]
+
+
+def _eval(sur, theta0, d1, d2, use_mlp):
+    dev = _dev()
+    n = len(theta0)
+    out = torch.empty((n, 6, 2), dtype=torch.float64, device=dev)
+    sur.eval(torch.tensor(theta0, dtype=torch.float64, device=dev),
+             torch.tensor(d1, dtype=torch.int32, device=dev),
+             torch.tensor(d2, dtype=torch.int32, device=dev), out, use_mlp)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    return o[..., 0] + 1j * o[..., 1]
+
+
+CGF_POINTS = [(0, 64, 9, 3), (0, 64, -20, 31), (1, 64, 12, -30), (3, 64, -7, 2), (8, 64, 15, -9),
+              (16, 64, -4, 8), (32, 64, 5, -4), (5, 128, 60, -10)]
+
+
+def test_continuum_green_matches_oracle_quadrature():
+    sur = _surrogate()
+    cij = ocg.nn_fcc_stiffness(1.0)
+    th = [m / nz for m, nz, _, _ in CGF_POINTS]
+    d1 = [p[2] for p in CGF_POINTS]
+    d2 = [p[3] for p in CGF_POINTS]
+    got = _eval(sur, th, d1, d2, use_mlp=False)
+    for k, (m, nz, a, b) in enumerate(CGF_POINTS):
+        ref = _sym6(ocg.line_mode_cgf(nz, m, a, b, cij))
+        err = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        assert err < 2e-4, (CGF_POINTS[k], err)
+
+
+def test_mlp_forward_and_gradient_match_oracle():
+    from paper_2105_08798_amd import MLP
+    dev = _dev()
+    rng = np.random.default_rng(5)
+    n = 777                                  # ragged against the 256-thread launches
+    net = MLP(max_batch=1024, seed=3)
+    p = (omlp.init_params(rng) + 0.05 * rng.normal(size=omlp.n_params())).astype(np.float32)
+    net.params(p)
+    x = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    t = rng.normal(size=(n, 12)).astype(np.float32)
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    y = torch.empty((n, 12), dtype=torch.float32, device=dev)
+    net.forward(xd, y)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    net.loss_grad(xd, td, loss)
+    torch.cuda.synchronize()
+    p64 = p.astype(np.float64)
+    y_ref, _ = omlp.forward(p64, x.astype(np.float64))
+    l_ref, g_ref = omlp.loss_grad(p64, x.astype(np.float64), t.astype(np.float64))
+    y_got = y.cpu().numpy()
+    g_got = net.grad()
+    assert np.linalg.norm(y_got - y_ref) / np.linalg.norm(y_ref) < 1e-5
+    assert abs(loss.item() - l_ref) / l_ref < 1e-5
+    assert np.linalg.norm(g_got - g_ref) / np.linalg.norm(g_ref) < 1e-4
+    # every layer's block of the gradient, not just the total
+    off = 0
+    for i, o in zip(omlp.SIZES[:-1], omlp.SIZES[1:]):
+        sl = slice(off, off + o * i + o)
+        assert np.linalg.norm(g_got[sl] - g_ref[sl]) / np.linalg.norm(g_ref[sl]) < 1e-4, (i, o)
+        off += o * i + o
+    net.close()
+
+
+def test_adam_training_reduces_the_loss():
+    from paper_2105_08798_amd import MLP
+    dev = _dev()
+    rng = np.random.default_rng(9)
+    n = 2048
+    x = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    t = np.concatenate([np.sin(2 * x[:, :2]), x[:, 2:3] * x[:, 3:4], np.tile(np.cos(x[:, :1]), (1, 9))],
+                       axis=1).astype(np.float32)
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    net = MLP(max_batch=n, seed=1)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    net.loss_grad(xd, td, loss)
+    l0 = loss.item()
+    for _ in range(300):
+        net.loss_grad(xd, td, loss)
+        net.adam_step(2e-3)
+    net.loss_grad(xd, td, loss)
+    l1 = loss.item()
+    net.close()
+    assert l1 < 0.02 * l0, (l0, l1)
+
+
+def test_bf16_inference_matches_oracle_with_rounded_weights():
+    from paper_2105_08798_amd import MLP, Surrogate
+    _dev()
+    rng = np.random.default_rng(2)
+    net = MLP(max_batch=64, seed=4)
+    p = (omlp.init_params(rng) + 0.02 * rng.normal(size=omlp.n_params())).astype(np.float32)
+    net.params(p)
+    sur = Surrogate(r_c=R_C)
+    sur.set_mlp(net)
+    nz = 256
+    m = rng.integers(0, nz // 2 + 1, size=40)
+    d1 = rng.integers(-40, 41, size=40)
+    d2 = rng.integers(-40, 41, size=40)
+    _, rho = _features(m / nz, d1, d2)
+    keep = (rho > R_C + 0.5) & (2 * math.pi * (m / nz) * math.sqrt(2) * rho < 39.0)
+    m, d1, d2 = m[keep], d1[keep], d2[keep]
+    th = m / nz
+    g_c = _eval(sur, th, d1, d2, use_mlp=False)
+    g_m = _eval(sur, th, d1, d2, use_mlp=True)
+    w = np.sqrt(np.array([1, 1, 1, 2, 2, 2], dtype=np.float64))
+    env = np.linalg.norm(g_c * w, axis=1) + 1e-3
+    y_got = (g_m - g_c) * np.exp(-1j * math.pi * th * d1)[:, None] / env[:, None]
+    y_got = np.stack([y_got.real, y_got.imag], axis=-1).reshape(-1, 12)
+    pb = osp.round_bf16(p.astype(np.float64))
+    layers = omlp.unpack(pb.copy())
+    # biases stay FP32 in inference: put the FP32 biases back
+    flat = []
+    for (wl, _), (_, bl) in zip(layers, omlp.unpack(p.astype(np.float64))):
+        flat += [wl.ravel(), bl]
+    feats, _ = _features(th, d1, d2)
+    y_ref, _ = omlp.forward(np.concatenate(flat), feats.astype(np.float32).astype(np.float64))
+    err = np.linalg.norm(y_got - y_ref) / np.linalg.norm(y_ref)
+    sur.close()
+    net.close()
+    assert err < 2e-4, err
+
+
+def _train_geometry():
+    # rings of radius ~16 / 22: offsets up to ~45 a, torus 256 x 256
+    return W.make_custom(64, 384, 768, 1, 256, seed=21)
+
+
+def test_training_set_matches_oracle_values():
+    from paper_2105_08798_amd import FBC
+    _dev()
+    sur = _surrogate()
+    wl = _train_geometry()
+    ctx = FBC(wl.cells, wl.bz, form="dtable_fp64")
+    x, t = sur.training_set(ctx, 4096, seed=7)
+    ctx.close()
+    x, t = x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    assert x.shape[0] > 3000
+    rho = R_C / x[:, 2]
+    assert (rho > R_C * (1 - 1e-6)).all()          # r_c / rho is stored in FP32
+    nz = wl.cells[0].nz
+    cij = ocg.nn_fcc_stiffness(1.0)
+    for k in (0, 1, 2):
+        xx, yy = rho[k] * x[k, 0], rho[k] * x[k, 1]
+        d1 = int(round(2 * xx))
+        d2 = int(round((yy * 2 * math.sqrt(2) - d1) / 2))
+        m = int(round(x[k, 3] / 2 * nz))
+        lgf = _sym6(ogr.line_mode_green(nz, wl.bz, wl.bz, m)[d1 % wl.bz, d2 % wl.bz])
+        cg = _sym6(ocg.line_mode_cgf(nz, m, d1, d2, cij))
+        w = np.sqrt(np.array([1, 1, 1, 2, 2, 2]))
+        env = np.linalg.norm(cg * w) + 1e-3
+        ref = (lgf - cg) * np.exp(-1j * math.pi * (m / nz) * d1) / env
+        got = t[k, 0::2] + 1j * t[k, 1::2]
+        # the device continuum value is an interpolated table (~1e-4 of |G_cgf|)
+        assert np.abs(got - ref).max() < 5e-4 * np.linalg.norm(cg) / env + 1e-6, (k, got, ref)
+
+
+def _apply(cells, bz, form, alpha, u0, **kw):
+    from paper_2105_08798_amd import FBC
+    dev = _dev()
+    ctx = FBC(cells, bz, form=form, **kw)
+    f = torch.from_numpy(np.concatenate([c.forces.ravel() for c in cells])).to(dev)
+    u = torch.from_numpy(np.concatenate([x.ravel() for x in u0])).to(dev)
+    ctx.apply(f, u, alpha=alpha)
+    rc = ctx.sync_status()
+    got = u.cpu().numpy()
+    ctx.close()
+    assert rc == 0
+    return got
+
+
+def _oracle_update(cells, bz, u0, alpha):
+    out = []
+    for c, uc in zip(cells, u0):
+        g = ogr.green_modes_dense(c.nz, bz, bz, c.cols_b, c.cols_i)
+        out.append(oap.pad_update(uc, oap.apply_green(g, c.forces), alpha)[0].ravel())
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("gen_modes", [0, 1, 3])
+def test_surrogate_form_is_exact_inside_r_c(gen_modes):
+    """With r_c beyond every offset the generated table is the exact one, for any chunking."""
+    from paper_2105_08798_amd import MLP, Surrogate
+    _dev()
+    net = MLP(max_batch=16, seed=1)
+    sur = Surrogate(r_c=500.0)
+    sur.set_mlp(net)
+    cells = W.make_custom(16, 30, 45, 3, 32, seed=1).cells + W.make_custom(8, 12, 20, 5, 32, seed=2).cells
+    rng = np.random.default_rng(3)
+    u0 = [rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01 for c in cells]
+    got = _apply(cells, 32, "surrogate", 0.8, u0, surrogate=sur, gen_modes=gen_modes)
+    ref = _oracle_update(cells, 32, u0, 0.8)
+    sur.close()
+    net.close()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def _train(sur, net, ctx, steps=1500, batch=8192, seed=0):
+    dev = _dev()
+    x, t = sur.training_set(ctx, 1 << 17, seed=seed)
+    n = x.shape[0]
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    for s in range(steps):
+        idx = torch.randint(0, n, (batch,), device=dev, generator=g)
+        lr = 2e-3 * (0.5 * (1 + math.cos(math.pi * s / steps))) + 1e-5
+        net.loss_grad(x[idx].contiguous(), t[idx].contiguous())
+        net.adam_step(lr)
+    torch.cuda.synchronize()
+
+
+def test_gain_learned_correction_beats_the_continuum_alone():
+    from paper_2105_08798_amd import FBC, MLP, Surrogate
+    dev = _dev()
+    wl = _train_geometry()
+    tab = FBC(wl.cells, wl.bz, form="dtable_fp64")
+    net = MLP(max_batch=8192, seed=11)
+    sur = Surrogate(r_c=R_C)
+    _train(sur, net, tab)
+    # held-out samples of the same table (another seed)
+    xh, th = sur.training_set(tab, 8192, seed=99)
+    tab.close()
+    yh = torch.empty_like(th)
+    net.forward(xh, yh)
+    torch.cuda.synchronize()
+    pointwise = (torch.linalg.norm(yh - th) / torch.linalg.norm(th)).item()
+    sur.set_mlp(net)
+    zero = MLP(max_batch=16, seed=0)
+    zero.params(np.zeros(zero.n_params, dtype=np.float32))
+    cgf_only = Surrogate(r_c=R_C)
+    cgf_only.set_mlp(zero)
+    # a held-out geometry on the same torus: rings of radius ~12 / ~16
+    cells = W.make_custom(32, 256, 512, 2, 256, seed=23).cells
+    rng = np.random.default_rng(4)
+    u0 = [np.zeros((c.n_rhs, c.nz, c.n_b, 3)) for c in cells]
+    ref = _oracle_update(cells, 256, u0, -1.0)
+    e_mlp = np.linalg.norm(_apply(cells, 256, "surrogate", -1.0, u0, surrogate=sur) - ref) / np.linalg.norm(ref)
+    e_cgf = np.linalg.norm(_apply(cells, 256, "surrogate", -1.0, u0, surrogate=cgf_only) - ref) / np.linalg.norm(ref)
+    print(f"gain: pointwise held-out {pointwise:.3e}; update error continuum {e_cgf:.3e}, learned {e_mlp:.3e}")
+    for o in (sur, cgf_only, net, zero):
+        o.close()
+    del dev, rng
+    assert pointwise < 0.3
+    assert e_mlp < 0.5 * e_cgf, (e_mlp, e_cgf)
