@@ -233,11 +233,18 @@ const char* fbc_last_error(const fbc_ctx* ctx);
  *     G_cgf(m; dn) = (1/c) exp(i pi theta0 dn1) G^_K(kappa, r_perp),
  * G^_K the line transform of the anisotropic Kelvin solution of the cubic continuum
  * with C11 = 2k/a, C12 = C44 = k/a (nearest-neighbour springs); m = 0 is regularised by
- * dropping the 2 G_K(t) log(kappa) divergence (a constant gauge).  The correction is
- *     G_lgf - G_cgf = env * exp(i pi theta0 dn1) * MLP(cos phi, sin phi, r_c / rho, 2 theta0),
- * env = ||G_cgf||_F + 1e-3, the MLP 4 -> 128 -> 128 -> 128 -> 12 with SiLU activations
- * giving the 6 complex components of the symmetric 3x3 block (xx, yy, zz, xy, xz, yz).
- * Offsets with rho <= r_c are always taken from the exact table.
+ * dropping the 2 G_K(t) log(kappa) divergence (a constant gauge).  As in Appendix B, the
+ * lattice and continuum functions are matched by a constant: in a context, line mode 0
+ * adds C = mean of (G_lgf - G_cgf) over its exact offsets with r_c - 1.5 < rho <= r_c.
+ * The learned correction is
+ *     G_lgf - G_cgf - C [m = 0] = env * exp(i pi theta0 dn1) * MLP(features),
+ * features = (cos phi, sin phi, cos 2phi, sin 2phi, cos 4phi, sin 4phi, r_c / rho,
+ * 8 theta0), phi the in-plane angle from [001] towards [110], env = ||G_cgf||_F + 1e-3,
+ * the MLP 8 -> 128 -> 128 -> 128 -> 12 with SiLU activations giving the 6 complex
+ * components of the symmetric 3x3 block (xx, yy, zz, xy, xz, yz).  The correction is
+ * applied where kappa rho <= 6; beyond, blocks are below about 1e-3 of the line-mode-0
+ * scale and the continuum value is used alone.  Offsets with rho <= r_c are always
+ * taken from the exact table.
  * ------------------------------------------------------------------------------------ */
 
 /* Last error text of the fbc_sur_* / fbc_mlp_* calls on this host thread. */
@@ -258,15 +265,17 @@ fbc_status fbc_sur_set_mlp(fbc_sur* s, const fbc_mlp* net, void* stream);
 /* Evaluates n blocks: out[n][6] complex (interleaved re, im; device) at line wavenumber
  * theta0[n] in [0, 1/2] and column offsets dn1[n], dn2[n] (all device).  use_mlp = 0:
  * continuum value only; 1: continuum + learned correction (rho > r_c; rho <= r_c returns
- * the continuum value, since the exact table lives in a context).  Asynchronous. */
+ * the continuum value, since the exact table lives in a context).  The matching constant
+ * C also belongs to a context and is not added here.  Asynchronous. */
 fbc_status fbc_sur_eval(const fbc_sur* s, const double* theta0, const int32_t* dn1,
                         const int32_t* dn2, int n, int use_mlp, double* out, void* stream);
 
 /* Training data from an FBC_FORM_DTABLE_FP64 context, whose table holds the lattice
  * values of every distinct offset and line mode of its cells: up to max_samples pairs
  * (table mode, offset) drawn by a host generator seeded with `seed`, restricted to
- * rho > r_c and kappa rho <= 40, each turned into features x[n][4] and target t[n][12]
- * (the correction above divided by env and rotated by exp(-i pi theta0 dn1)); x, t are
+ * rho > r_c and kappa rho <= 6, each turned into features x[n][8] and target t[n][12]
+ * (the correction above, with the table context's own C, divided by env and rotated by
+ * exp(-i pi theta0 dn1)); x, t are
  * device FP32 buffers of max_samples rows.  *n_out = rows written.  Synchronises. */
 fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* table_ctx, int max_samples,
                                 uint64_t seed, float* x, float* t, int* n_out, void* stream);
@@ -281,14 +290,14 @@ int fbc_mlp_num_params(void);
  * host_out (may be NULL) receives them; fbc_mlp_grad copies the last gradient. */
 fbc_status fbc_mlp_params(fbc_mlp* m, float* host_out, const float* host_in);
 fbc_status fbc_mlp_grad(fbc_mlp* m, float* host_out);
-/* Loss L = (1/n) sum_rows sum_j (y_j - t_j)^2 over a batch (x [n][4], t [n][12],
+/* Loss L = (1/n) sum_rows sum_j (y_j - t_j)^2 over a batch (x [n][8], t [n][12],
  * device FP32) and its gradient with respect to the parameters (kept in the object);
  * loss_dev: device float receiving L, or NULL.  Asynchronous. */
 fbc_status fbc_mlp_loss_grad(fbc_mlp* m, const float* x, const float* t, int n,
                              float* loss_dev, void* stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the last gradient. */
 fbc_status fbc_mlp_adam_step(fbc_mlp* m, float lr, void* stream);
-/* FP32 forward pass y [n][12] of x [n][4] (device). */
+/* FP32 forward pass y [n][12] of x [n][8] (device). */
 fbc_status fbc_mlp_forward(fbc_mlp* m, const float* x, float* y, int n, void* stream);
 const char* fbc_status_string(fbc_status s);
 

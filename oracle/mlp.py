@@ -1,7 +1,7 @@
 """Four-layer MLP of the learned far-field form, FP64 forward and analytic backward
 (oracle; test infrastructure only).
 
-Layers 4 -> 128 -> 128 -> 128 -> 12 with SiLU activations (silu(z) = z / (1 + e^-z)),
+Layers 8 -> 128 -> 128 -> 128 -> 12 with SiLU activations (silu(z) = z / (1 + e^-z)),
 mean-squared-error loss.  Parameters are one flat array, layer by layer: W_l [out][in]
 row-major, then b_l [out].  The same layout is used by the HIP kernels.
 """
@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import numpy as np
 
-SIZES = (4, 128, 128, 128, 12)
+SIZES = (8, 128, 128, 128, 12)
 
 
 def n_params(sizes=SIZES) -> int:
@@ -40,7 +40,7 @@ def _sig(z):
 
 
 def forward(params: np.ndarray, x: np.ndarray, sizes=SIZES):
-    """x [n, 4] -> y [n, 12]; returns (y, cache of pre-activations and inputs)."""
+    """x [n, 8] -> y [n, 12]; returns (y, cache of pre-activations and inputs)."""
     layers = unpack(params, sizes)
     a = np.asarray(x, dtype=np.float64)
     cache = []

@@ -357,6 +357,13 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
     }
     HIPCHK(c, hipGetLastError());
     if (sur) {
+        if ((s = dev_alloc(c, (void**)&c->cmatch, 64)) != FBC_OK) {
+            cleanup();
+            return s;
+        }
+        launch_sur_const(st, c->sur->view(), c->near_tab, d1_d, d2_d, n_tab, c->sur->r_c - SUR_MATCH_SHELL,
+                         c->sur->r_c, c->cmatch);
+        HIPCHK(c, hipGetLastError());
         // generated slices: as many table modes per chunk as fit in about 2 GiB
         c->gen_modes = (int)std::max<int64_t>(1, std::min<int64_t>(T, ((int64_t)2 << 30) / std::max<int64_t>(1, n_off * 96)));
         if (c->opt.gen_modes > 0) c->gen_modes = std::min(c->opt.gen_modes, T);
@@ -754,7 +761,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
             const int nt = std::min(c->gen_modes, T - t0);
             launch_sur_generate(st, sv->view(), sv->wb, sv->bias, sv->r_c, sv->env_floor, c->nz_max, t0, nt,
                                 c->near_tab, c->n_near, c->n_offsets, c->n_need, c->off_d1, c->off_d2,
-                                c->gen);
+                                c->cmatch, c->gen);
             const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
             launch_gemm_dtab(st, c->jobs + j0, j1 - j0, c->ctmax, c->gen, (int64_t)t0 * c->n_offsets * 6,
                              (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2);

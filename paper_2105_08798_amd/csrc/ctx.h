@@ -59,6 +59,7 @@ struct fbc_ctx {
     double2* gen = nullptr;          // generated slices [chunk modes][n_off][6]
     int gen_modes = 0;               // table modes per generated chunk
     std::vector<int> chunk_job0;     // first job of each chunk (jobs sorted by table mode)
+    double* cmatch = nullptr;        // line-mode-0 matching constant (6 components)
     // relax
     double* fprev = nullptr;
     double* alpha = nullptr;

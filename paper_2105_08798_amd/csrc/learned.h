@@ -2,7 +2,7 @@
 #pragma once
 #include "kernels.h"
 
-#define MLP_IN 4
+#define MLP_IN 8
 #define MLP_H 128
 #define MLP_OUT 12
 #define MLP_NPARAMS (MLP_IN * MLP_H + MLP_H + 2 * (MLP_H * MLP_H + MLP_H) + MLP_H * MLP_OUT + MLP_OUT)
@@ -47,13 +47,21 @@ void launch_adam(hipStream_t st, float* p, const float* g, float* m, float* v, i
 
 void launch_sur_samples(hipStream_t st, const CgfView& v, const double2* tab, int64_t n_off, int nz_tab,
                         const int32_t* d1, const int32_t* d2, const int32_t* pick_t,
-                        const int32_t* pick_o, int n, double r_c, double env_floor, float* x,
-                        float* t);
+                        const int32_t* pick_o, int n, double r_c, double env_floor,
+                        const double* cmatch, float* x, float* t);
+// width of the shell inside r_c over which the line-mode-0 matching constant is averaged
+#define SUR_MATCH_SHELL 1.5
+// the learned correction covers kappa rho <= SUR_S_LEARN (beyond it the blocks are below
+// about 1e-3 of the line-mode-0 scale and the continuum value is used alone)
+#define SUR_S_LEARN 6.0
+void launch_sur_const(hipStream_t st, const CgfView& v, const double2* tab0, const int32_t* d1,
+                      const int32_t* d2, int64_t n, double r_lo, double r_hi, double* cmatch);
 void launch_sur_points(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
                        int use_mlp, double r_c, double env_floor, const double* theta0,
                        const int32_t* d1, const int32_t* d2, int n, double2* out);
 void launch_sur_generate(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
                          double r_c, double env_floor, int nz_tab, int t0, int nt,
                          const double2* near_tab, int64_t n_near, int64_t n_off,
-                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, double2* out);
+                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, const double* cmatch,
+                         double2* out);
 void launch_mlp_to_bf16(hipStream_t st, const float* params, unsigned short* wb, float* bias);

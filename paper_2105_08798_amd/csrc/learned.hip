@@ -255,7 +255,7 @@ void launch_cgf_build(hipStream_t st, const CgfConst& k, const double* cpsi, con
 }
 
 // ----------------------------------------------------------------------------------
-// MLP 4 -> 128 -> 128 -> 128 -> 12, SiLU, FP32 training kernels.
+// MLP 8 -> 128 -> 128 -> 128 -> 12, SiLU, FP32 training kernels.
 // Parameter layout: per layer W [out][in] row-major, then b [out].
 // ----------------------------------------------------------------------------------
 __device__ inline float silu(float z) { return z / (1.0f + expf(-z)); }
@@ -265,20 +265,33 @@ __device__ inline float silu_d(float z) {
 }
 
 // out[s][o] = b[o] + sum_i in[s][i] W[o][i]; z stored, a = silu(z) unless last.
+// A block takes FWD_S samples: W (transposed, [i][o]) and the input rows are staged in
+// LDS, then each thread forms outputs (s, o) with o running fastest across the wave.
+#define FWD_S 32
 __global__ void __launch_bounds__(NTL) k_dense_fwd(const float* __restrict__ in, int n, int ni, int no,
                                                    const float* __restrict__ W,
                                                    const float* __restrict__ b,
                                                    float* __restrict__ z, float* __restrict__ a,
                                                    int last) {
-    const int64_t idx = (int64_t)blockIdx.x * NTL + threadIdx.x;
-    if (idx >= (int64_t)n * no) return;
-    const int s = (int)(idx / no), o = (int)(idx - (int64_t)s * no);
-    float acc = b[o];
-    const float* x = in + (int64_t)s * ni;
-    const float* w = W + (int64_t)o * ni;
-    for (int i = 0; i < ni; ++i) acc = fmaf(x[i], w[i], acc);
-    z[idx] = acc;
-    a[idx] = last ? acc : silu(acc);
+    __shared__ float wt[MLP_H * MLP_H];
+    __shared__ float xs[FWD_S * MLP_H];
+    const int s0 = blockIdx.x * FWD_S;
+    const int ns = min(FWD_S, n - s0);
+    for (int e = threadIdx.x; e < ni * no; e += NTL) {
+        const int o = e / ni, i = e - o * ni;
+        wt[i * no + o] = W[e];
+    }
+    for (int e = threadIdx.x; e < ns * ni; e += NTL) xs[e] = in[(int64_t)s0 * ni + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < ns * no; e += NTL) {
+        const int sl = e / no, o = e - sl * no;
+        float acc = b[o];
+        const float* x = xs + sl * ni;
+        for (int i = 0; i < ni; ++i) acc = fmaf(x[i], wt[i * no + o], acc);
+        const int64_t idx = (int64_t)(s0 + sl) * no + o;
+        z[idx] = acc;
+        a[idx] = last ? acc : silu(acc);
+    }
 }
 
 // dz = da * silu'(z) (or da for the last layer).
@@ -300,22 +313,37 @@ __global__ void __launch_bounds__(NTL) k_dense_bwd_x(const float* __restrict__ d
     for (int o = 0; o < no; ++o) acc = fmaf(g[o], W[(int64_t)o * ni + i], acc);
     din[idx] = acc;
 }
-// dW[o][i] = sum_s dz[s][o] in[s][i] (FP64 sum, fixed order); db[o] = sum_s dz[s][o].
+// dW[o][i] = sum_s dz[s][o] in[s][i]; db[o] = sum_s dz[s][o].  The samples are cut into
+// gridDim.y chunks; each chunk's FP64 partial sum goes to part[chunk][o * (ni + 1) + i],
+// and k_dense_bwd_sum adds the chunks in fixed order (deterministic result).
 __global__ void __launch_bounds__(NTL) k_dense_bwd_w(const float* __restrict__ dz,
                                                      const float* __restrict__ in, int n, int ni,
-                                                     int no, float* __restrict__ dW,
-                                                     float* __restrict__ db) {
+                                                     int no, int chunk, double* __restrict__ part) {
     const int idx = blockIdx.x * NTL + threadIdx.x;
-    if (idx >= no * (ni + 1)) return;
+    const int nw = no * (ni + 1);
+    if (idx >= nw) return;
     const int o = idx / (ni + 1), i = idx - o * (ni + 1);
+    const int sa = blockIdx.y * chunk, sb = min(n, sa + chunk);
     double acc = 0.0;
     if (i < ni)
-        for (int s = 0; s < n; ++s) acc += (double)dz[(int64_t)s * no + o] * in[(int64_t)s * ni + i];
+        for (int s = sa; s < sb; ++s) acc += (double)dz[(int64_t)s * no + o] * in[(int64_t)s * ni + i];
     else
-        for (int s = 0; s < n; ++s) acc += dz[(int64_t)s * no + o];
+        for (int s = sa; s < sb; ++s) acc += dz[(int64_t)s * no + o];
+    part[(int64_t)blockIdx.y * nw + idx] = acc;
+}
+__global__ void __launch_bounds__(NTL) k_dense_bwd_sum(const double* __restrict__ part, int nchunk, int ni,
+                                                       int no, float* __restrict__ dW,
+                                                       float* __restrict__ db) {
+    const int idx = blockIdx.x * NTL + threadIdx.x;
+    const int nw = no * (ni + 1);
+    if (idx >= nw) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += part[(int64_t)c * nw + idx];
+    const int o = idx / (ni + 1), i = idx - o * (ni + 1);
     if (i < ni) dW[(int64_t)o * ni + i] = (float)acc;
     else db[o] = (float)acc;
 }
+#define BWD_CHUNKS 64
 
 // Loss: mean over samples of sum over outputs of (w (y - t))^2; dy = 2 w^2 (y - t) / n.
 __global__ void __launch_bounds__(NTL) k_loss(const float* __restrict__ y, const float* __restrict__ t,
@@ -373,7 +401,8 @@ static int64_t layer_off(int l) {
 int64_t mlp_workspace_floats(int n) {
     int64_t t = 0;
     for (int l = 1; l <= 4; ++l) t += 4 * (int64_t)n * MLP_SIZES[l];   // z, a, dz, da
-    return t + (int64_t)n * MLP_H + 4096;
+    // loss partials (256 doubles) and the weight-gradient chunk partials (doubles)
+    return t + (int64_t)n * MLP_H + 4096 + 2LL * BWD_CHUNKS * MLP_H * (MLP_H + 1);
 }
 
 void launch_mlp_forward(hipStream_t st, const float* params, const float* x, int n, float* ws,
@@ -385,7 +414,8 @@ void launch_mlp_forward(hipStream_t st, const float* params, const float* x, int
         float* z = p;
         float* a = (l == 3 && y) ? y : p + (int64_t)n * no;
         const int64_t tot = (int64_t)n * no;
-        hipLaunchKernelGGL(k_dense_fwd, dim3((unsigned)((tot + NTL - 1) / NTL)), dim3(NTL), 0, st, in, n, ni,
+        (void)tot;
+        hipLaunchKernelGGL(k_dense_fwd, dim3((unsigned)((n + FWD_S - 1) / FWD_S)), dim3(NTL), 0, st, in, n, ni,
                            no, params + layer_off(l), params + layer_off(l) + (int64_t)no * ni, z, a,
                            l == 3 ? 1 : 0);
         in = a;
@@ -411,6 +441,7 @@ void launch_mlp_loss_grad(hipStream_t st, const float* params, const float* x, c
         p += 4 * (int64_t)n * no;
     }
     double* part = (double*)(p + (int64_t)n * MLP_H);
+    double* wpart = part + 2048;              // after the 4096 floats of loss partials
     const int nb = 256;
     hipLaunchKernelGGL(k_loss, dim3(nb), dim3(NTL), 0, st, al[3], t, w, n, MLP_OUT, dal[3], part);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, part, nb, n, loss);
@@ -422,7 +453,11 @@ void launch_mlp_loss_grad(hipStream_t st, const float* params, const float* x, c
                            zl[l], tot, dzl[l], l == 3 ? 1 : 0);
         const float* in = (l == 0) ? x : al[l - 1];
         const int nw = no * (ni + 1);
-        hipLaunchKernelGGL(k_dense_bwd_w, dim3((nw + NTL - 1) / NTL), dim3(NTL), 0, st, dzl[l], in, n, ni, no,
+        const int chunk = std::max(64, (n + BWD_CHUNKS - 1) / BWD_CHUNKS);
+        const int nchunk = (n + chunk - 1) / chunk;
+        hipLaunchKernelGGL(k_dense_bwd_w, dim3((nw + NTL - 1) / NTL, nchunk), dim3(NTL), 0, st, dzl[l], in, n,
+                           ni, no, chunk, wpart);
+        hipLaunchKernelGGL(k_dense_bwd_sum, dim3((nw + NTL - 1) / NTL), dim3(NTL), 0, st, wpart, nchunk, ni, no,
                            grad + layer_off(l), grad + layer_off(l) + (int64_t)no * ni);
         if (l > 0) {
             const int64_t ti = (int64_t)n * ni;
@@ -441,21 +476,32 @@ void launch_adam(hipStream_t st, float* p, const float* g, float* m, float* v, i
 
 // ----------------------------------------------------------------------------------
 // Training samples and the surrogate table generator.
-// Features of (theta0, dn1, dn2): (cos phi, sin phi, r_c / rho, 2 theta0).
+// Features of (theta0, dn1, dn2): (cos phi, sin phi, cos 2phi, sin 2phi, cos 4phi,
+// sin 4phi, r_c / rho, 8 theta0); the low angular harmonics of the cubic anisotropy
+// are given explicitly.
 // Target / output: exp(-i pi theta0 dn1) (G^_lgf - G^_cgf) / env, env = |G^_cgf|_F + floor,
 // 6 complex components (xx yy zz xy xz yz) as 12 reals.
 // ----------------------------------------------------------------------------------
-__device__ inline void sur_features(double theta0, int dn1, int dn2, double r_c, float f[4],
+__device__ inline void sur_features(double theta0, int dn1, int dn2, double r_c, float f[MLP_IN],
                                     double* rho_out) {
     const double x = 0.5 * dn1;
     const double y = (dn1 + 2.0 * dn2) * (0.5 * M_SQRT1_2);
     const double rho = sqrt(x * x + y * y);
-    f[0] = (float)(x / rho);
-    f[1] = (float)(y / rho);
-    f[2] = (float)(r_c / rho);
-    f[3] = (float)(2.0 * theta0);
+    const double c1 = x / rho, s1 = y / rho;
+    const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * s1 * c1;
+    f[0] = (float)c1;
+    f[1] = (float)s1;
+    f[2] = (float)c2;
+    f[3] = (float)s2;
+    f[4] = (float)(c2 * c2 - s2 * s2);
+    f[5] = (float)(2.0 * s2 * c2);
+    f[6] = (float)(r_c / rho);
+    f[7] = (float)(8.0 * theta0);
     *rho_out = rho;
 }
+
+// kappa rho of line wavenumber theta0 at in-plane distance rho (a = 1, c = 1/sqrt2)
+__device__ inline double sur_s(double theta0, double rho) { return 2.0 * M_PI * theta0 * M_SQRT2 * rho; }
 
 __device__ inline double sur_env(const double2 g[6], double floor_) {
     double s = 0.0;
@@ -473,6 +519,7 @@ __global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* _
                                                      const int32_t* __restrict__ pick_t,
                                                      const int32_t* __restrict__ pick_o, int n,
                                                      double r_c, double env_floor,
+                                                     const double* __restrict__ cmatch,
                                                      float* __restrict__ x, float* __restrict__ t) {
     const int i = blockIdx.x * NTL + threadIdx.x;
     if (i >= n) return;
@@ -481,16 +528,16 @@ __global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* _
     const double theta0 = (double)tm / nz_tab;
     double2 g[6];
     cgf_eval(v, theta0, d1[o], d2[o], g);
-    float f[4];
+    float f[MLP_IN];
     double rho;
     sur_features(theta0, d1[o], d2[o], r_c, f, &rho);
     const double env = sur_env(g, env_floor);
     double sp, cp;
     sincospi(theta0 * d1[o], &sp, &cp);
     const double2* l = tab + ((int64_t)tm * n_off + o) * 6;
-    for (int a = 0; a < 4; ++a) x[(int64_t)i * 4 + a] = f[a];
+    for (int a = 0; a < MLP_IN; ++a) x[(int64_t)i * MLP_IN + a] = f[a];
     for (int c = 0; c < 6; ++c) {
-        const double dr = l[c].x - g[c].x, di = l[c].y - g[c].y;
+        const double dr = l[c].x - g[c].x - (tm == 0 ? cmatch[c] : 0.0), di = l[c].y - g[c].y;
         // multiply by exp(-i pi theta0 dn1)
         t[(int64_t)i * 12 + 2 * c] = (float)((dr * cp + di * sp) / env);
         t[(int64_t)i * 12 + 2 * c + 1] = (float)((di * cp - dr * sp) / env);
@@ -499,11 +546,46 @@ __global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* _
 
 void launch_sur_samples(hipStream_t st, const CgfView& v, const double2* tab, int64_t n_off, int nz_tab,
                         const int32_t* d1, const int32_t* d2, const int32_t* pick_t,
-                        const int32_t* pick_o, int n, double r_c, double env_floor, float* x,
-                        float* t) {
+                        const int32_t* pick_o, int n, double r_c, double env_floor,
+                        const double* cmatch, float* x, float* t) {
     if (n > 0)
         hipLaunchKernelGGL(k_sur_samples, dim3((n + NTL - 1) / NTL), dim3(NTL), 0, st, v, tab, n_off, nz_tab,
-                           d1, d2, pick_t, pick_o, n, r_c, env_floor, x, t);
+                           d1, d2, pick_t, pick_o, n, r_c, env_floor, cmatch, x, t);
+}
+
+// Matching constant of line mode 0 (Appendix B: the lattice and continuum functions differ
+// by a constant far from the source; it is measured where both are known): the mean of
+// G_lgf - G_cgf over the exact-table offsets with r_lo < rho <= r_hi.  One work group,
+// fixed assignment of offsets to threads and a fixed reduction tree: deterministic.
+__global__ void __launch_bounds__(NTL) k_sur_const(CgfView v, const double2* __restrict__ tab0,
+                                                   const int32_t* __restrict__ d1,
+                                                   const int32_t* __restrict__ d2, int64_t n,
+                                                   double r_lo, double r_hi,
+                                                   double* __restrict__ cmatch) {
+    __shared__ double red[7][NTL];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t o = threadIdx.x; o < n; o += NTL) {
+        const double x = 0.5 * d1[o], y = (d1[o] + 2.0 * d2[o]) * (0.5 * M_SQRT1_2);
+        const double rho = sqrt(x * x + y * y);
+        if (!(rho > r_lo && rho <= r_hi)) continue;
+        double2 g[6];
+        cgf_eval(v, 0.0, d1[o], d2[o], g);
+        for (int c = 0; c < 6; ++c) acc[c] += tab0[o * 6 + c].x - g[c].x;
+        acc[6] += 1.0;
+    }
+    for (int c = 0; c < 7; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int st = NTL / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int c = 0; c < 7; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) cmatch[threadIdx.x] = red[6][0] > 0 ? red[threadIdx.x][0] / red[6][0] : 0.0;
+}
+
+void launch_sur_const(hipStream_t st, const CgfView& v, const double2* tab0, const int32_t* d1,
+                      const int32_t* d2, int64_t n, double r_lo, double r_hi, double* cmatch) {
+    hipLaunchKernelGGL(k_sur_const, dim3(1), dim3(NTL), 0, st, v, tab0, d1, d2, n, r_lo, r_hi, cmatch);
 }
 
 // MLP forward of one sample, bf16 weights (transposed, [in][out], read with wave-uniform
@@ -552,7 +634,7 @@ __device__ inline void mlp_hidden(const unsigned short* __restrict__ wt, const f
     for (int o = 0; o < MLP_H; ++o) hl[o * stride] = silu(acc[o]);
 }
 
-__device__ void mlp_bf16_eval(const MlpW& m, const float f[4], float* hl, int stride,
+__device__ void mlp_bf16_eval(const MlpW& m, const float f[MLP_IN], float* hl, int stride,
                               float y[MLP_OUT]) {
     {
         float acc[MLP_H];
@@ -591,10 +673,10 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_points(CgfView v, const unsig
     if (i >= n) return;
     double2 g[6];
     cgf_eval(v, theta0[i], d1[i], d2[i], g);
-    if (use_mlp) {
-        float f[4], y[MLP_OUT];
-        double rho;
-        sur_features(theta0[i], d1[i], d2[i], r_c, f, &rho);
+    float f[MLP_IN], y[MLP_OUT];
+    double rho;
+    sur_features(theta0[i], d1[i], d2[i], r_c, f, &rho);
+    if (use_mlp && rho > r_c && sur_s(theta0[i], rho) <= SUR_S_LEARN) {
         const double env = sur_env(g, env_floor);
         mlp_bf16_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
         double sp, cp;
@@ -618,7 +700,8 @@ void launch_sur_points(hipStream_t st, const CgfView& v, const unsigned short* w
 
 // Table slice generator of the surrogate form: table modes t0 .. t0+nt-1 for every
 // offset o (offsets numbered by increasing rho): o < n_near: exact lattice value;
-// o < n_need[t]: continuum + learned correction; beyond: zero (kappa rho > s_max).
+// o < n_need[t]: continuum (+ matching constant at line mode 0, + learned correction
+// where kappa rho <= SUR_S_LEARN); beyond: zero (kappa rho > s_max).
 __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const unsigned short* __restrict__ wb,
                                                       const float* __restrict__ bias, double r_c,
                                                       double env_floor, int nz_tab, int t0,
@@ -627,6 +710,7 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const uns
                                                       const int32_t* __restrict__ n_need,
                                                       const int32_t* __restrict__ d1,
                                                       const int32_t* __restrict__ d2,
+                                                      const double* __restrict__ cmatch,
                                                       double2* __restrict__ out) {
     __shared__ float hl[MLP_H * MLP_BLOCK];
     const MlpW m = mlp_view(wb, bias);
@@ -647,26 +731,33 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const uns
     const double theta0 = (double)tm / nz_tab;
     double2 g[6];
     cgf_eval(v, theta0, d1[o], d2[o], g);
-    float f[4], y[MLP_OUT];
+    float f[MLP_IN], y[MLP_OUT];
     double rho;
     sur_features(theta0, d1[o], d2[o], r_c, f, &rho);
     const double env = sur_env(g, env_floor);
-    mlp_bf16_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
-    double sp, cp;
-    sincospi(theta0 * d1[o], &sp, &cp);
-    for (int c = 0; c < 6; ++c) {
-        const double cr = env * y[2 * c], ci = env * y[2 * c + 1];
-        dst[c] = make_double2(g[c].x + cr * cp - ci * sp, g[c].y + cr * sp + ci * cp);
+    if (tm == 0)
+        for (int c = 0; c < 6; ++c) g[c].x += cmatch[c];     // matching constant (line mode 0)
+    if (sur_s(theta0, rho) <= SUR_S_LEARN) {
+        mlp_bf16_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
+        double sp, cp;
+        sincospi(theta0 * d1[o], &sp, &cp);
+        for (int c = 0; c < 6; ++c) {
+            const double cr = env * y[2 * c], ci = env * y[2 * c + 1];
+            g[c].x += cr * cp - ci * sp;
+            g[c].y += cr * sp + ci * cp;
+        }
     }
+    for (int c = 0; c < 6; ++c) dst[c] = g[c];
 }
 
 void launch_sur_generate(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
                          double r_c, double env_floor, int nz_tab, int t0, int nt,
                          const double2* near_tab, int64_t n_near, int64_t n_off,
-                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, double2* out) {
+                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, const double* cmatch,
+                         double2* out) {
     dim3 grid((unsigned)((n_off + MLP_BLOCK - 1) / MLP_BLOCK), nt);
     hipLaunchKernelGGL(k_sur_generate, grid, dim3(MLP_BLOCK), 0, st, v, wb, bias, r_c, env_floor, nz_tab, t0,
-                       near_tab, n_near, n_off, n_need, d1, d2, out);
+                       near_tab, n_near, n_off, n_need, d1, d2, cmatch, out);
 }
 
 // FP32 weights -> transposed bf16 (round to nearest even) and biases, for inference.

@@ -163,7 +163,7 @@ extern "C" fbc_status fbc_sur_eval(const fbc_sur* s, const double* theta0, const
 
 // Training set from an offset-table context (its table holds lattice values for every
 // distinct offset and line mode of its cells): samples (mode t, offset o) with
-// |r_perp| > r_c and kappa |r_perp| <= s_max, drawn with a seeded generator.
+// |r_perp| > r_c and kappa |r_perp| <= SUR_S_LEARN, drawn with a seeded generator.
 extern "C" fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* c, int max_samples,
                                            uint64_t seed, float* x, float* t, int* n_out,
                                            void* stream) {
@@ -195,25 +195,25 @@ extern "C" fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* c, i
         const int tm = pick_t(gen);
         if (rho[o] <= s->r_c) continue;
         const double kap = 2.0 * M_PI * ((double)tm / c->nz_max) * M_SQRT2;
-        if (kap * rho[o] > s->k.s_max) continue;
+        if (kap * rho[o] > SUR_S_LEARN) continue;
         pt.push_back(tm);
         po.push_back((int32_t)o);
     }
     const int n = (int)pt.size();
-    int32_t *dpt = nullptr, *dpo = nullptr;
     if (n > 0) {
-        LCHK(nullptr, hipMalloc((void**)&dpt, (size_t)n * 4));
-        if (hipMalloc((void**)&dpo, (size_t)n * 4) != hipSuccess) {
-            (void)hipFree(dpt);
-            return lfail(nullptr, FBC_E_NOMEM, "sample index list");
-        }
+        // index lists and the context's own matching constant (line mode 0)
+        char* buf = nullptr;
+        LCHK(nullptr, hipMalloc((void**)&buf, (size_t)n * 8 + 64));
+        int32_t* dpt = (int32_t*)buf;
+        int32_t* dpo = dpt + n;
+        double* cm = (double*)(buf + (((size_t)n * 8 + 7) & ~(size_t)7));
         (void)hipMemcpyAsync(dpt, pt.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
         (void)hipMemcpyAsync(dpo, po.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+        launch_sur_const(st, s->view(), c->tab, c->off_d1, c->off_d2, n_off, s->r_c - SUR_MATCH_SHELL, s->r_c, cm);
         launch_sur_samples(st, s->view(), c->tab, n_off, c->nz_max, c->off_d1, c->off_d2, dpt, dpo, n, s->r_c,
-                           s->env_floor, x, t);
+                           s->env_floor, cm, x, t);
         (void)hipStreamSynchronize(st);
-        (void)hipFree(dpt);
-        (void)hipFree(dpo);
+        (void)hipFree(buf);
     }
     *n_out = n;
     LCHK(nullptr, hipGetLastError());

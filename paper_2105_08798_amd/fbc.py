@@ -337,9 +337,9 @@ class Surrogate:
                                                   _dptr(out), _stream_handle(stream)))
 
     def training_set(self, table_ctx: "FBC", max_samples: int, seed: int, stream=None):
-        """Returns (x [n, 4], t [n, 12]) float32 device tensors drawn from the table context."""
+        """Returns (x [n, 8], t [n, 12]) float32 device tensors drawn from the table context."""
         import torch
-        x = torch.empty((max_samples, 4), dtype=torch.float32, device="cuda")
+        x = torch.empty((max_samples, 8), dtype=torch.float32, device="cuda")
         t = torch.empty((max_samples, 12), dtype=torch.float32, device="cuda")
         n = C.c_int()
         _lcheck(self._lib, self._lib.fbc_sur_training_set(self.handle, table_ctx.ctx, int(max_samples),

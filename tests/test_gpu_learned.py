@@ -38,10 +38,17 @@ def _sym6(g):
 
 
 def _features(theta0, dn1, dn2, r_c=R_C):
+    """(cos phi, sin phi, cos 2phi, sin 2phi, cos 4phi, sin 4phi, r_c / rho, 8 theta0)"""
     r = ocg.in_plane_vector(dn1, dn2)
     x, y = r @ ocg.E1, r @ ocg.E2
     rho = np.hypot(x, y)
-    return np.stack([x / rho, y / rho, r_c / rho, 2.0 * np.asarray(theta0)], axis=-1), rho
+    phi = np.arctan2(y, x)
+    f = [np.cos(phi), np.sin(phi), np.cos(2 * phi), np.sin(2 * phi), np.cos(4 * phi), np.sin(4 * phi),
+         r_c / rho, 8.0 * np.asarray(theta0, dtype=np.float64)]
+    return np.stack(f, axis=-1), rho
+
+
+S_LEARN = 6.0
 
 
 _SUR = {}
@@ -92,7 +99,7 @@ def test_mlp_forward_and_gradient_match_oracle():
     net = MLP(max_batch=1024, seed=3)
     p = (omlp.init_params(rng) + 0.05 * rng.normal(size=omlp.n_params())).astype(np.float32)
     net.params(p)
-    x = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    x = rng.uniform(-1, 1, size=(n, omlp.SIZES[0])).astype(np.float32)
     t = rng.normal(size=(n, 12)).astype(np.float32)
     xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
     y = torch.empty((n, 12), dtype=torch.float32, device=dev)
@@ -122,8 +129,8 @@ def test_adam_training_reduces_the_loss():
     dev = _dev()
     rng = np.random.default_rng(9)
     n = 2048
-    x = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
-    t = np.concatenate([np.sin(2 * x[:, :2]), x[:, 2:3] * x[:, 3:4], np.tile(np.cos(x[:, :1]), (1, 9))],
+    x = rng.uniform(-1, 1, size=(n, omlp.SIZES[0])).astype(np.float32)
+    t = np.concatenate([np.sin(2 * x[:, :2]), x[:, 2:3] * x[:, 3:4], np.tile(np.cos(x[:, 4:5]), (1, 9))],
                        axis=1).astype(np.float32)
     xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
     net = MLP(max_batch=n, seed=1)
@@ -153,7 +160,7 @@ def test_bf16_inference_matches_oracle_with_rounded_weights():
     d1 = rng.integers(-40, 41, size=40)
     d2 = rng.integers(-40, 41, size=40)
     _, rho = _features(m / nz, d1, d2)
-    keep = (rho > R_C + 0.5) & (2 * math.pi * (m / nz) * math.sqrt(2) * rho < 39.0)
+    keep = (rho > R_C + 0.5) & (2 * math.pi * (m / nz) * math.sqrt(2) * rho < S_LEARN - 0.1)
     m, d1, d2 = m[keep], d1[keep], d2[keep]
     th = m / nz
     g_c = _eval(sur, th, d1, d2, use_mlp=False)
@@ -190,24 +197,43 @@ def test_training_set_matches_oracle_values():
     x, t = sur.training_set(ctx, 4096, seed=7)
     ctx.close()
     x, t = x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
-    assert x.shape[0] > 3000
-    rho = R_C / x[:, 2]
+    assert x.shape[0] == 4096
+    # the features are the stated functions of the sample's offset and wavenumber
+    d1 = np.round(2 * (R_C / x[:, 6]) * x[:, 0]).astype(int)
+    d2 = np.round(((R_C / x[:, 6]) * x[:, 1] * 2 * math.sqrt(2) - d1) / 2).astype(int)
+    f_ref, _ = _features(x[:, 7] / 8, d1, d2)
+    assert np.abs(x - f_ref).max() < 1e-6
+    rho = R_C / x[:, 6]
     assert (rho > R_C * (1 - 1e-6)).all()          # r_c / rho is stored in FP32
+    s_all = 2 * math.pi * (x[:, 7] / 8) * math.sqrt(2) * rho
+    assert (s_all <= S_LEARN * (1 + 1e-6)).all()
     nz = wl.cells[0].nz
     cij = ocg.nn_fcc_stiffness(1.0)
-    for k in (0, 1, 2):
+    w6 = np.sqrt(np.array([1, 1, 1, 2, 2, 2]))
+    pos = [k for k in range(x.shape[0]) if x[k, 7] > 0][:3]
+    zero = [k for k in range(x.shape[0]) if x[k, 7] == 0][:2]
+    assert len(pos) == 3 and len(zero) == 2
+    implied_c = []
+    for k in pos + zero:
         xx, yy = rho[k] * x[k, 0], rho[k] * x[k, 1]
         d1 = int(round(2 * xx))
         d2 = int(round((yy * 2 * math.sqrt(2) - d1) / 2))
-        m = int(round(x[k, 3] / 2 * nz))
+        m = int(round(x[k, 7] / 8 * nz))
         lgf = _sym6(ogr.line_mode_green(nz, wl.bz, wl.bz, m)[d1 % wl.bz, d2 % wl.bz])
         cg = _sym6(ocg.line_mode_cgf(nz, m, d1, d2, cij))
-        w = np.sqrt(np.array([1, 1, 1, 2, 2, 2]))
-        env = np.linalg.norm(cg * w) + 1e-3
-        ref = (lgf - cg) * np.exp(-1j * math.pi * (m / nz) * d1) / env
+        env = np.linalg.norm(cg * w6) + 1e-3
+        rot = np.exp(-1j * math.pi * (m / nz) * d1)
         got = t[k, 0::2] + 1j * t[k, 1::2]
-        # the device continuum value is an interpolated table (~1e-4 of |G_cgf|)
-        assert np.abs(got - ref).max() < 5e-4 * np.linalg.norm(cg) / env + 1e-6, (k, got, ref)
+        if m > 0:
+            ref = (lgf - cg) * rot / env
+            # the device continuum value is an interpolated table (~1e-4 of |G_cgf|)
+            assert np.abs(got - ref).max() < 5e-4 * np.linalg.norm(cg) / env + 1e-6, (k, got, ref)
+        else:
+            # line mode 0 subtracts the context's matching constant: a real constant
+            c_k = lgf - cg - got * env
+            assert np.abs(c_k.imag).max() < 1e-6 * np.abs(cg).max()
+            implied_c.append(c_k.real)
+    assert np.abs(implied_c[0] - implied_c[1]).max() < 2e-3 * np.abs(implied_c[0]).max(), implied_c
 
 
 def _apply(cells, bz, form, alpha, u0, **kw):
@@ -250,7 +276,7 @@ def test_surrogate_form_is_exact_inside_r_c(gen_modes):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
 
 
-def _train(sur, net, ctx, steps=1500, batch=8192, seed=0):
+def _train(sur, net, ctx, steps=6000, batch=8192, seed=0):
     dev = _dev()
     x, t = sur.training_set(ctx, 1 << 17, seed=seed)
     n = x.shape[0]
@@ -291,7 +317,8 @@ def test_gain_learned_correction_beats_the_continuum_alone():
     ref = _oracle_update(cells, 256, u0, -1.0)
     e_mlp = np.linalg.norm(_apply(cells, 256, "surrogate", -1.0, u0, surrogate=sur) - ref) / np.linalg.norm(ref)
     e_cgf = np.linalg.norm(_apply(cells, 256, "surrogate", -1.0, u0, surrogate=cgf_only) - ref) / np.linalg.norm(ref)
-    print(f"gain: pointwise held-out {pointwise:.3e}; update error continuum {e_cgf:.3e}, learned {e_mlp:.3e}")
+    print(f"gain: pointwise held-out {pointwise:.3e}; update error continuum + matching constant "
+          f"{e_cgf:.3e}, learned {e_mlp:.3e}")
     for o in (sur, cgf_only, net, zero):
         o.close()
     del dev, rng

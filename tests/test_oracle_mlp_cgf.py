@@ -27,10 +27,10 @@ def test_mlp_gradient_matches_central_differences():
 
 
 def test_mlp_layout_and_size():
-    assert mlp.n_params() == 4 * 128 + 128 + 2 * (128 * 128 + 128) + 128 * 12 + 12
+    assert mlp.n_params() == 8 * 128 + 128 + 2 * (128 * 128 + 128) + 128 * 12 + 12
     p = np.arange(mlp.n_params(), dtype=float)
     layers = mlp.unpack(p)
-    assert layers[0][0].shape == (128, 4) and layers[0][0][0, 1] == 1.0 and layers[0][1][0] == 512.0
+    assert layers[0][0].shape == (128, 8) and layers[0][0][0, 1] == 1.0 and layers[0][1][0] == 1024.0
 
 
 def test_kelvin_matches_isotropic_closed_form():
