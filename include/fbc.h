@@ -22,8 +22,12 @@
  * Brillouin-zone grid of an M1 x M2 in-plane torus, with the singular q = 0 term
  * dropped (pseudo-inverse gauge: the Green function is unique only up to a constant,
  * Section 3.1).  The block coupling pad column b to interface column i is
- * G^(m; n_b - n_i).  Forces with zero net force per layer make the result independent
- * of the gauge; the check below enforces it.
+ * G^(m; n_b - n_i).  The gauge is a constant 3x3 added to every block of line mode 0
+ * (Section 3.1: the Green function is unique up to a constant), so forces whose net
+ * force over the whole cell (all interface atoms of all layers) vanishes give a
+ * gauge-free result; the check below enforces it, or the projection removes that net
+ * force.  Net forces of single layers are allowed (the incompatibility forces of
+ * Algorithm 1 have them).
  *
  * Conventions.
  *   f  (interface forces)  : device FP64, per cell [n_rhs][N_z][n_i][3], row-major.
@@ -63,7 +67,8 @@ typedef enum {
     FBC_OK = 0,
     FBC_E_ARG = -1,          /* invalid argument (null pointer, bad size, bad enum) */
     FBC_E_NOMEM = -2,        /* device allocation failed */
-    FBC_E_NETFORCE = -3,     /* |sum_i f| > netforce_tol * sum_i |f| in some layer/component */
+    FBC_E_NETFORCE = -3,     /* |sum f| > netforce_tol * sum |f| for some RHS and component,
+                                sums over all interface atoms of all layers of a cell      */
     FBC_E_NONFINITE = -4,    /* NaN or Inf in the forces */
     FBC_E_DEVICE = -5,       /* HIP runtime error (text in fbc_last_error) */
     FBC_E_STATE = -6,        /* call out of order (e.g. relax step before relax begin) */
@@ -113,10 +118,12 @@ typedef struct {
     int form;                /* fbc_form                                                   */
     int bz_m1, bz_m2;        /* in-plane Brillouin-zone torus, powers of two in [8, 4096]  */
     int check_netforce;      /* 1: latch FBC_E_NETFORCE / FBC_E_NONFINITE (device check)   */
-    int project_netforce;    /* 1: subtract the per-layer column mean of f before applying */
+    int project_netforce;    /* 1: subtract from f its mean over all interface atoms of all
+                                layers (per RHS and component) before applying           */
     double netforce_tol;     /* relative tolerance of the net-force check (e.g. 1e-10)     */
-    int row_gauge;           /* reduced forms: subtract each block row's mean over i per
-                                mode before rounding (exact for zero-net-force f)        */
+    int row_gauge;           /* reduced forms: store each block row minus its mean over i
+                                per mode before rounding; the mean is added back in FP64
+                                against sum_i f^_i(m) (exact for any f)                  */
     const fbc_sur* surrogate;/* FBC_FORM_SURROGATE: far-field object (not owned; must
                                 outlive the context and keep its MLP weights); else NULL */
     int gen_modes;           /* FBC_FORM_SURROGATE: table modes generated per chunk

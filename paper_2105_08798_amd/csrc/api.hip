@@ -140,6 +140,12 @@ static bool is_table_form(int form) {
     return form == FBC_FORM_DTABLE_FP64 || form == FBC_FORM_SURROGATE;
 }
 
+// Row gauge: reduced dense forms store G^_bi(m) - mean_i G^_bi(m) (smaller dynamic range
+// before rounding) and add the mean back exactly (FP64) against sum_i f^_i(m).
+static bool row_gauge_active(const fbc_ctx* c) {
+    return c->opt.row_gauge && (c->opt.form == FBC_FORM_FP32 || c->opt.form == FBC_FORM_SPLIT_BF16);
+}
+
 static int64_t store_elem_bytes(int form) {
     return form == FBC_FORM_FP64 ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
 }
@@ -374,14 +380,25 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         c->scratch_bytes += (int64_t)c->gen_modes * n_off * 96;
     }
     if (!keep && !sur) {
-        for (CellPlan& p : c->cells) {
+        if (row_gauge_active(c)) {
+            // kept: the inverse transform adds R_b(m) . sum_i f^_i(m) back in FP64
+            int64_t tot_rm = 0;
+            for (CellPlan& p : c->cells) {
+                c->rowmean_off.push_back(tot_rm);
+                tot_rm += (int64_t)p.nm * p.n_b * 6;
+            }
+            if ((s = dev_alloc(c, (void**)&c->rowmean, tot_rm * 16)) != FBC_OK) {
+                cleanup();
+                return s;
+            }
+            c->scratch_bytes += tot_rm * 16;
+        }
+        for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+            CellPlan& p = c->cells[ci];
             const int mult = c->nz_max / p.nz;
             double2* rowmean = nullptr;
-            if (form != FBC_FORM_FP64 && c->opt.row_gauge) {
-                if ((s = talloc((void**)&rowmean, (int64_t)p.nm * p.n_b * 6 * 16)) != FBC_OK) {
-                    cleanup();
-                    return s;
-                }
+            if (row_gauge_active(c)) {
+                rowmean = c->rowmean + c->rowmean_off[ci];
                 launch_rowmean(st, c->tab, rowmean, p.nm, mult, n_off, p.n_b, p.n_i, p.cols_b_d,
                                p.cols_i_d, c->lut, os.d1min, os.d2min, os.w2);
             }
@@ -637,9 +654,11 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     c->scratch_bytes = b_off * b_elem_bytes(form) + c_off * 8 + w_off * 8;
     {
         // per-cell small buffers
-        int64_t sums_n = 0, wmax_n = 0, sp_n = 0, rp_n = 0;
+        int64_t sums_n = 0, wmax_n = 0, sp_n = 0, rp_n = 0, shat_n = 0;
         for (auto& p : c->cells) {
-            sums_n += (int64_t)p.R * p.nz * 3;
+            sums_n += (int64_t)p.R * p.nz * 6;
+            c->shat_off.push_back(shat_n);
+            shat_n += (int64_t)p.R * p.nm * 3;
             int tr = (4 * p.nz <= 4096) ? std::min(64, 4096 / (4 * p.nz)) : 1;
             const int np_ir = (p.M + tr - 1) / tr;
             const int np_ax = ((p.M + 31) / 32) * ((p.nz + 31) / 32);
@@ -653,6 +672,9 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             rp_n += (int64_t)p.R * 64 * 3;
         }
         if ((s = dev_alloc(c, (void**)&c->sums, sums_n * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->ftot, (int64_t)c->total_rhs * 3 * 8)) != FBC_OK) goto fail_out;
+        if ((s = dev_alloc(c, (void**)&c->shat, shat_n * 16)) != FBC_OK) goto fail_out;
+        c->scratch_bytes += shat_n * 16 + (int64_t)c->total_rhs * 24;
         if ((s = dev_alloc(c, (void**)&c->wmax_part, wmax_n * 8)) != FBC_OK) goto fail_out;
         if ((s = dev_alloc(c, (void**)&c->sum_part, sp_n * 8)) != FBC_OK) goto fail_out;
         if ((s = dev_alloc(c, (void**)&c->rpart, rp_n * 8)) != FBC_OK) goto fail_out;
@@ -739,16 +761,20 @@ fail_out:
 static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     const int form = c->opt.form;
     int64_t sums_off = 0;
-    for (auto& p : c->cells) {
+    const bool comp = row_gauge_active(c);
+    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+        auto& p = c->cells[ci];
         const double* fc = f + p.f_off;
         double* sums = c->sums + sums_off;
-        if (c->opt.check_netforce || c->opt.project_netforce)
-            launch_netforce(st, fc, sums, p.R, p.nz, p.n_i, c->opt.netforce_tol, c->opt.check_netforce,
-                            c->opt.project_netforce, c->status);
+        double* tot = c->ftot + 3 * p.rhs0;
+        if (c->opt.check_netforce || c->opt.project_netforce || comp)
+            launch_netforce(st, fc, sums, tot, comp ? c->shat + c->shat_off[ci] : nullptr, p.R, p.nz, p.n_i,
+                            c->opt.netforce_tol, c->opt.check_netforce, c->opt.project_netforce,
+                            c->tw + p.tw_off, c->status);
         void* bm = (char*)c->bfrag + p.b_off * b_elem_bytes(form);
-        launch_line_rfft(st, form, fc, sums, c->opt.project_netforce, bm, p.R, p.nz, p.n_i, p.kp,
+        launch_line_rfft(st, form, fc, tot, c->opt.project_netforce, bm, p.R, p.nz, p.n_i, p.kp,
                          p.ct, c->tw + p.tw_off);
-        sums_off += (int64_t)p.R * p.nz * 3;
+        sums_off += (int64_t)p.R * p.nz * 6;
     }
     const bool tm = c->timing && c->n_timed < kMaxTimed;
     if (tm) (void)hipEventRecord(c->ev[2 * c->n_timed], st);
@@ -778,7 +804,9 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
-                          p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split, nullptr);
+                          p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split,
+                          comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
+                          comp ? c->shat + c->shat_off[ci] : nullptr, nullptr);
     }
 }
 

@@ -46,8 +46,7 @@ __device__ inline void block_max(double (&v)[NV], double* red) {
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT) k_netforce(const double* __restrict__ f,
                                                  double* __restrict__ sums, int nz, int n_i,
-                                                 double tol, int check, int project,
-                                                 int* __restrict__ status) {
+                                                 int check, int* __restrict__ status) {
     __shared__ double red[7 * NT];
     const int n0 = blockIdx.x, r = blockIdx.y;
     const double* row = f + ((int64_t)r * nz + n0) * n_i * 3;
@@ -62,22 +61,70 @@ __global__ void __launch_bounds__(NT) k_netforce(const double* __restrict__ f,
     }
     block_sum<7>(v, red);
     if (threadIdx.x == 0) {
-        for (int c = 0; c < 3; ++c) sums[((int64_t)r * nz + n0) * 3 + c] = v[c];
-        if (check) {
+        for (int c = 0; c < 6; ++c) sums[((int64_t)r * nz + n0) * 6 + c] = v[c];
+        if (check && (v[6] != 0.0 || !isfinite(v[3] + v[4] + v[5]))) atomicOr(status, ST_NONFINITE);
+    }
+}
+
+// Net force of the whole cell per RHS and component (sum over layers in fixed order):
+// tot[r][c].  Only this total enters the gauge (line mode 0); the check compares it with
+// the total absolute force.
+__global__ void __launch_bounds__(NT) k_netforce_total(const double* __restrict__ sums, int nz,
+                                                       double tol, int check, int project,
+                                                       double* __restrict__ tot,
+                                                       int* __restrict__ status) {
+    __shared__ double red[6 * NT];
+    const int r = blockIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int n0 = threadIdx.x; n0 < nz; n0 += NT)
+        for (int c = 0; c < 6; ++c) v[c] += sums[((int64_t)r * nz + n0) * 6 + c];
+    block_sum<6>(v, red);
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) tot[r * 3 + c] = v[c];
+        if (check && !project) {
             int bits = 0;
-            if (v[6] != 0.0 || !isfinite(v[3] + v[4] + v[5])) bits |= ST_NONFINITE;
-            else if (!project)
-                for (int c = 0; c < 3; ++c)
-                    if (fabs(v[c]) > tol * v[3 + c]) bits |= ST_NETFORCE;
+            for (int c = 0; c < 3; ++c)
+                if (fabs(v[c]) > tol * v[3 + c]) bits |= ST_NETFORCE;
             if (bits) atomicOr(status, bits);
         }
     }
 }
 
-void launch_netforce(hipStream_t st, const double* f, double* sums, int R, int nz, int n_i,
-                     double tol, int check, int project, int* status) {
-    hipLaunchKernelGGL(k_netforce, dim3(nz, R), dim3(NT), 0, st, f, sums, nz, n_i, tol, check,
-                       project, status);
+// Line transform of the per-layer net force (after the projection, if any):
+// shat[r][m][c] = sum_n0 (s_c(n0) - tot_c / Nz) e^{-2 pi i m n0 / Nz}, m = 0..Nz/2.
+// It multiplies the subtracted row means in the inverse transform.
+__global__ void __launch_bounds__(NT) k_netforce_fft(const double* __restrict__ sums,
+                                                     const double* __restrict__ tot, int project,
+                                                     int nz, int logn,
+                                                     const double2* __restrict__ tw,
+                                                     double2* __restrict__ shat) {
+    extern __shared__ double2 lds[];
+    const int c = blockIdx.x, r = blockIdx.y;
+    const double sub = project ? tot[r * 3 + c] / nz : 0.0;
+    for (int n0 = threadIdx.x; n0 < nz; n0 += NT)
+        lds[bitrev(n0, logn)] = make_double2(sums[((int64_t)r * nz + n0) * 6 + c] - sub, 0.0);
+    __syncthreads();
+    lds_fft(lds, 1, logn, tw, false);
+    const int nm = (nz >> 1) + 1;
+    for (int m = threadIdx.x; m < nm; m += NT) {
+        double2 z = lds[m];
+        if (project && m == 0) z = make_double2(0.0, 0.0);
+        shat[((int64_t)r * nm + m) * 3 + c] = z;
+    }
+}
+
+void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat, int R,
+                     int nz, int n_i, double tol, int check, int project, const double2* tw,
+                     int* status) {
+    hipLaunchKernelGGL(k_netforce, dim3(nz, R), dim3(NT), 0, st, f, sums, nz, n_i, check, status);
+    hipLaunchKernelGGL(k_netforce_total, dim3(R), dim3(NT), 0, st, sums, nz, tol, check, project, tot,
+                       status);
+    if (shat) {
+        int logn = 0;
+        while ((1 << logn) < nz) ++logn;
+        hipLaunchKernelGGL(k_netforce_fft, dim3(3, R), dim3(NT), (size_t)nz * sizeof(double2), st, sums,
+                           tot, project, nz, logn, tw, shat);
+    }
 }
 
 // ----------------------------------------------------------------------------------
@@ -111,10 +158,10 @@ __device__ inline void put_b(void* bm, int n, int kq, int kp, double v) {
 
 template <int FORM>
 __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
-                                                  const double* __restrict__ sums, int project,
+                                                  const double* __restrict__ tot, int project,
                                                   void* __restrict__ bfrag, int nz, int logn,
                                                   int n_i, int kp, int ct, int tc,
-                                                  const double2* __restrict__ tw, double inv_ni) {
+                                                  const double2* __restrict__ tw, double inv_cnt) {
     extern __shared__ double2 lds[];
     const int r = blockIdx.y;
     const int k0 = blockIdx.x * tc;
@@ -126,7 +173,7 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
         double v = 0.0;
         if (k < K) {
             v = f[((int64_t)r * nz + n0) * K + k];
-            if (project) v -= sums[((int64_t)r * nz + n0) * 3 + (k % 3)] * inv_ni;
+            if (project) v -= tot[r * 3 + (k % 3)] * inv_cnt;     // mean over the cell's atoms
         }
         ldsd[2 * ((c >> 1) * nz + (int)bitrev(n0, logn)) + (c & 1)] = v;
     }
@@ -165,7 +212,7 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     }
 }
 
-void launch_line_rfft(hipStream_t st, int form, const double* f, const double* sums, int project,
+void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
                       void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
@@ -178,19 +225,19 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* s
     tc &= ~1;
     dim3 grid((K + tc - 1) / tc, R);
     const size_t lds = (size_t)nz * tc * sizeof(double);
-    const double inv_ni = 1.0 / n_i;
+    const double inv_cnt = 1.0 / ((double)n_i * nz);
     switch (form) {
         case FBC_FORM_FP32:
-            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP32>, grid, dim3(NT), lds, st, f, sums, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_ni);
+            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP32>, grid, dim3(NT), lds, st, f, tot, project,
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt);
             break;
         case FBC_FORM_SPLIT_BF16:
-            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_BF16>, grid, dim3(NT), lds, st, f, sums,
-                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_ni);
+            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_BF16>, grid, dim3(NT), lds, st, f, tot,
+                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt);
             break;
         default:
-            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP64>, grid, dim3(NT), lds, st, f, sums, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_ni);
+            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP64>, grid, dim3(NT), lds, st, f, tot, project,
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt);
             break;
     }
 }
@@ -207,7 +254,9 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    double* __restrict__ wmax_part, int R, int nz,
                                                    int logn, int mp, int M, int ct, int tr, int pp,
                                                    const double2* __restrict__ tw, int nsplit,
-                                                   int64_t split_stride) {
+                                                   int64_t split_stride,
+                                                   const double2* __restrict__ rowmean,
+                                                   const double2* __restrict__ shat) {
     extern __shared__ double2 lds[];
     const int row0 = blockIdx.x * tr;
     const int tile = blockIdx.y;
@@ -231,6 +280,24 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                 ai += q[ja + 8];
                 br += q[ja + 1];
                 bi += q[ja + 9];
+            }
+            if (rowmean) {
+                // exact FP64 compensation of the row gauge: + R_b(m) . sum_i f^_i(m)
+                const int b = row / 3, cc = row - 3 * b;
+                const double2* rm = rowmean + ((int64_t)mm * (M / 3) + b) * 6;
+                for (int d = 0; d < 3; ++d) {
+                    const double2 g = rm[sym_idx(cc, d)];
+                    if (8 * tile + ja < R) {
+                        const double2 sv = shat[((int64_t)(8 * tile + ja) * nm + mm) * 3 + d];
+                        ar += g.x * sv.x - g.y * sv.y;
+                        ai += g.x * sv.y + g.y * sv.x;
+                    }
+                    if (8 * tile + ja + 1 < R) {
+                        const double2 sv = shat[((int64_t)(8 * tile + ja + 1) * nm + mm) * 3 + d];
+                        br += g.x * sv.x - g.y * sv.y;
+                        bi += g.x * sv.y + g.y * sv.x;
+                    }
+                }
             }
             if (mm == 0 || 2 * mm == nz) { ai = 0.0; bi = 0.0; }
             if (m >= nm) { ai = -ai; bi = -bi; }
@@ -274,7 +341,8 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
 
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
-                       int64_t split_stride, int* n_part_out) {
+                       int64_t split_stride, const double2* rowmean, const double2* shat,
+                       int* n_part_out) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int pp, tr;
@@ -290,7 +358,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
     size_t lds = (size_t)tr * pp * nz * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
     hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,
-                       ct, tr, pp, tw, nsplit, split_stride);
+                       ct, tr, pp, tw, nsplit, split_stride, rowmean, shat);
     if (n_part_out) *n_part_out = (int)grid.x;
 }
 

@@ -22,7 +22,11 @@ struct fbc_ctx {
     void* bfrag = nullptr;          // GEMM B operand
     double* cbuf = nullptr;         // GEMM output
     double* wbuf = nullptr;         // w[r][row][n0]
-    double* sums = nullptr;         // net force per layer
+    double* sums = nullptr;         // per layer: net force and absolute force [r][n0][6]
+    double* ftot = nullptr;         // net force of each cell per RHS [total_rhs][3]
+    double2* shat = nullptr;        // line transform of the per-layer net force [r][m][3]
+    double2* rowmean = nullptr;     // row-gauge means [m][b][6] (reduced forms with row gauge)
+    std::vector<int64_t> shat_off, rowmean_off;
     double* wmax_part = nullptr;
     double* sum_part = nullptr;
     double* mean = nullptr;         // [total_rhs][3]

@@ -28,9 +28,12 @@ void launch_build_dense(hipStream_t st, int form, void* store, const double2* ta
                         const int32_t* lut, int d1min, int d2min, int w2);
 
 // ---- apply (Section 2.3.2 update in line-mode form) ----
-void launch_netforce(hipStream_t st, const double* f, double* sums, int R, int nz, int n_i,
-                     double tol, int check, int project, int* status);
-void launch_line_rfft(hipStream_t st, int form, const double* f, const double* sums, int project,
+// Per-layer sums sums[r][n0][6] (net force, absolute force), cell totals tot[r][3] with
+// the net-force check, and (shat != NULL) the line transform of the per-layer net force.
+void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat, int R,
+                     int nz, int n_i, double tol, int check, int project, const double2* tw,
+                     int* status);
+void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
                       void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw);
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
                  const void* a, const void* b, double* c);
@@ -41,7 +44,8 @@ void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, co
                       const int32_t* lut, int d1min, int d2min, int w2);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
-                       int64_t split_stride, int* n_part_out);
+                       int64_t split_stride, const double2* rowmean, const double2* shat,
+                       int* n_part_out);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status,
                  int* n_part_out);
