@@ -5,7 +5,7 @@ One step = one fbc_apply call: for every RHS of the cell, u <- u - G^{p|i+} f fo
 by mean removal (net-force check, line rFFT, per-mode products, inverse rFFT, update,
 mean), with f and u resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload medium] [--forms fp64,fp32,split_bf16]
+    python bench.py [--steps K] [--warmup W] [--workload medium] [--forms fp64,fp32,split_bf16,split_fp16]
 """
 from __future__ import annotations
 
@@ -22,12 +22,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FBC boundary updates/sec + % MFMA/HBM roofline vs FP64 plain at 1e-6 rel err"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "dtable_fp64": 78.6, "surrogate": 78.6}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0, "dtable_fp64": 78.6,
+               "surrogate": 78.6}
 # bytes per complex entry of the stored G^ and of the B operand, per form (the offset
 # table form reads its table, whose size the library reports, instead of dense blocks)
-G_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "dtable_fp64": None, "surrogate": None}
-F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "dtable_fp64": 16, "surrogate": 16}
-DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16 hi+lo (fp32 acc)", "dtable_fp64": "f64",
+G_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "split_fp16": 8, "dtable_fp64": None, "surrogate": None}
+F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "split_fp16": 8, "dtable_fp64": 16, "surrogate": 16}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16 hi+lo (fp32 acc)",
+         "split_fp16": "fp16 hi+lo, power-of-two scaled (fp32 acc)", "dtable_fp64": "f64",
          "surrogate": "f64 (generated table; bf16-weight MLP, fp32 acc)"}
 
 
@@ -52,8 +54,16 @@ def algorithmic(cells, form: str, store_bytes: int) -> dict:
     return dict(gemm_bytes=g_all + fh_all + uh_all, gemm_flops=fl_all, call_bytes=g_all + fu_all)
 
 
-KERNEL_PREFIX = {"fp64": "k_gemm_f64<", "fp32": "k_gemm_f32<", "split_bf16": "k_gemm_bf16<",
-                 "dtable_fp64": "k_gemm_dtab<", "surrogate": "k_gemm_dtab<"}
+def kernel_matches(form: str, name: str) -> bool:
+    """Whether a profiled kernel name is the product kernel of a form."""
+    if form == "fp64":
+        return name.startswith("k_gemm_f64<")
+    if form == "fp32":
+        return name.startswith("k_gemm_f32<")
+    if form in ("split_bf16", "split_fp16"):
+        half = "bf16" not in name and ("Float16" in name or "half" in name)
+        return name.startswith("k_gemm_split<") and (half == (form == "split_fp16"))
+    return name.startswith("k_gemm_dtab<")
 
 
 def measured_traffic(workload: str, form: str):
@@ -68,7 +78,7 @@ def measured_traffic(workload: str, form: str):
     if hashlib.sha256(src).hexdigest() != t.get("gemm_source_sha256"):
         return None
     for name, v in t["kernels"].items():
-        if name.startswith(KERNEL_PREFIX[form]):
+        if kernel_matches(form, name):
             return v["traffic_bytes"]
     return None
 
@@ -263,7 +273,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--forms", default=None,
-                    help="default fp64,fp32,split_bf16 (dtable_fp64 for the batched workload)")
+                    help="default fp64,fp32,split_bf16,split_fp16 (dtable_fp64 for the batched workload)")
     ap.add_argument("--graph", action="store_true", help="replay the update from a captured HIP graph")
     ap.add_argument("--autotune", action="store_true", help="autotune the product work list first")
     ap.add_argument("--no-cpu", action="store_true")
@@ -285,7 +295,7 @@ def main() -> int:
         return 1
     wl = W.make_batched() if args.workload == "batched" else W.make_single(args.workload)
     if args.forms is None:
-        args.forms = "dtable_fp64" if args.workload == "batched" else "fp64,fp32,split_bf16"
+        args.forms = "dtable_fp64" if args.workload == "batched" else "fp64,fp32,split_bf16,split_fp16"
     forms = [s for s in args.forms.split(",") if s]
     log(f"workload {args.workload}: {wl.description}, M={wl.bz}")
 

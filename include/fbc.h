@@ -84,12 +84,16 @@ typedef enum {
     FBC_FORM_DTABLE_FP64 = 3, /* no dense store: FP64 table over distinct column offsets
                                  (entries depend on n_b - n_i only), gathered into LDS
                                  tiles and applied on FP64 MFMA                               */
-    FBC_FORM_SURROGATE = 4    /* offset-table product whose table is generated per mode
+    FBC_FORM_SURROGATE = 4,   /* offset-table product whose table is generated per mode
                                  chunk before each product: exact lattice values for
                                  in-plane distances <= r_c (kept, FP64), beyond it the
                                  continuum Green function plus a learned correction
                                  (Appendix B: exact near field, continuum far field);
                                  needs options.surrogate with MLP weights set             */
+    FBC_FORM_SPLIT_FP16 = 5   /* dense split-FP16 blocks, scaled per line mode by a power of
+                                 two (hi = fp16(2^e G), lo = fp16(2^e G - hi): 22 bits at the
+                                 bytes of split BF16), forces likewise scaled per call, FP16
+                                 MFMA with FP32 accumulation inside K chunks, FP64 across  */
 } fbc_form;
 
 /* Learned far field (see the fbc_sur_* and fbc_mlp_* calls below). */

@@ -142,8 +142,10 @@ static bool is_table_form(int form) {
 
 // Row gauge: reduced dense forms store G^_bi(m) - mean_i G^_bi(m) (smaller dynamic range
 // before rounding) and add the mean back exactly (FP64) against sum_i f^_i(m).
+static bool is_split16(int form) { return form == FBC_FORM_SPLIT_BF16 || form == FBC_FORM_SPLIT_FP16; }
+
 static bool row_gauge_active(const fbc_ctx* c) {
-    return c->opt.row_gauge && (c->opt.form == FBC_FORM_FP32 || c->opt.form == FBC_FORM_SPLIT_BF16);
+    return c->opt.row_gauge && (c->opt.form == FBC_FORM_FP32 || is_split16(c->opt.form));
 }
 
 static int64_t store_elem_bytes(int form) {
@@ -151,10 +153,10 @@ static int64_t store_elem_bytes(int form) {
 }
 // store elements (of the store type) per mode: FP64/FP32 mp*kp, BF16 2*mp*kp
 static int64_t store_mode_elems(int form, const CellPlan& p) {
-    return (int64_t)p.mp * p.kp * (form == FBC_FORM_SPLIT_BF16 ? 2 : 1);
+    return (int64_t)p.mp * p.kp * (is_split16(form) ? 2 : 1);
 }
 static int64_t b_mode_elems(int form, const CellPlan& p) {
-    return (int64_t)16 * p.ct * p.kp * (form == FBC_FORM_SPLIT_BF16 ? 2 : 1);
+    return (int64_t)16 * p.ct * p.kp * (is_split16(form) ? 2 : 1);
 }
 static int64_t b_elem_bytes(int form) {
     return (form == FBC_FORM_FP64 || is_table_form(form)) ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
@@ -380,6 +382,19 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         c->scratch_bytes += (int64_t)c->gen_modes * n_off * 96;
     }
     if (!keep && !sur) {
+        if (form == FBC_FORM_SPLIT_FP16) {
+            // per cell mode: largest table magnitude, which fixes the power-of-two scale
+            int64_t na = 0;
+            for (CellPlan& p : c->cells) {
+                c->amax_off.push_back(na);
+                na += p.nm;
+            }
+            if ((s = dev_alloc(c, (void**)&c->amax, na * 8)) != FBC_OK ||
+                (s = dev_alloc(c, (void**)&c->bexp, (int64_t)c->cells.size() * 4)) != FBC_OK) {
+                cleanup();
+                return s;
+            }
+        }
         if (row_gauge_active(c)) {
             // kept: the inverse transform adds R_b(m) . sum_i f^_i(m) back in FP64
             int64_t tot_rm = 0;
@@ -404,7 +419,8 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
             }
             char* base = (char*)c->store + p.a_off * store_elem_bytes(form);
             launch_build_dense(st, form, base, c->tab, rowmean, p.nm, mult, n_off, p.mp, p.kp, p.n_b,
-                               p.n_i, p.cols_b_d, p.cols_i_d, c->lut, os.d1min, os.d2min, os.w2);
+                               p.n_i, p.cols_b_d, p.cols_i_d, c->lut, os.d1min, os.d2min, os.w2,
+                               form == FBC_FORM_SPLIT_FP16 ? c->amax + c->amax_off[ci] : nullptr);
             HIPCHK(c, hipGetLastError());
         }
         c->tab = nullptr;
@@ -536,7 +552,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     if (!lat || !cells || !opt || n_cells <= 0) return fail(nullptr, FBC_E_ARG, "null argument or n_cells <= 0");
     if (!(lat->a > 0) || !(lat->spring_k > 0) || !std::isfinite(lat->a) || !std::isfinite(lat->spring_k))
         return fail(nullptr, FBC_E_ARG, "lattice constant and spring stiffness must be positive");
-    if (opt->form < FBC_FORM_FP64 || opt->form > FBC_FORM_SURROGATE)
+    if (opt->form < FBC_FORM_FP64 || opt->form > FBC_FORM_SPLIT_FP16)
         return fail(nullptr, FBC_E_ARG, "unknown form");
     if (opt->form == FBC_FORM_SURROGATE && (!opt->surrogate || !opt->surrogate->has_mlp))
         return fail(nullptr, FBC_E_ARG, "the surrogate form needs an fbc_sur with MLP weights");
@@ -656,7 +672,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         // per-cell small buffers
         int64_t sums_n = 0, wmax_n = 0, sp_n = 0, rp_n = 0, shat_n = 0;
         for (auto& p : c->cells) {
-            sums_n += (int64_t)p.R * p.nz * 6;
+            sums_n += (int64_t)p.R * p.nz * 8;
             c->shat_off.push_back(shat_n);
             shat_n += (int64_t)p.R * p.nm * 3;
             int tr = (4 * p.nz <= 4096) ? std::min(64, 4096 / (4 * p.nz)) : 1;
@@ -762,19 +778,21 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     const int form = c->opt.form;
     int64_t sums_off = 0;
     const bool comp = row_gauge_active(c);
+    const bool f16 = (form == FBC_FORM_SPLIT_FP16);
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         const double* fc = f + p.f_off;
         double* sums = c->sums + sums_off;
         double* tot = c->ftot + 3 * p.rhs0;
-        if (c->opt.check_netforce || c->opt.project_netforce || comp)
+        int* bexp = f16 ? c->bexp + ci : nullptr;
+        if (c->opt.check_netforce || c->opt.project_netforce || comp || f16)
             launch_netforce(st, fc, sums, tot, comp ? c->shat + c->shat_off[ci] : nullptr, p.R, p.nz, p.n_i,
                             c->opt.netforce_tol, c->opt.check_netforce, c->opt.project_netforce,
-                            c->tw + p.tw_off, c->status);
+                            c->tw + p.tw_off, bexp, c->status);
         void* bm = (char*)c->bfrag + p.b_off * b_elem_bytes(form);
         launch_line_rfft(st, form, fc, tot, c->opt.project_netforce, bm, p.R, p.nz, p.n_i, p.kp,
-                         p.ct, c->tw + p.tw_off);
-        sums_off += (int64_t)p.R * p.nz * 6;
+                         p.ct, c->tw + p.tw_off, bexp);
+        sums_off += (int64_t)p.R * p.nz * 8;
     }
     const bool tm = c->timing && c->n_timed < kMaxTimed;
     if (tm) (void)hipEventRecord(c->ev[2 * c->n_timed], st);
@@ -806,7 +824,8 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
         launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
                           p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split,
                           comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
-                          comp ? c->shat + c->shat_off[ci] : nullptr, nullptr);
+                          comp ? c->shat + c->shat_off[ci] : nullptr,
+                          f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + ci : nullptr, nullptr);
     }
 }
 

@@ -41,6 +41,10 @@ __device__ inline void block_max(double (&v)[NV], double* red) {
     __syncthreads();
 }
 
+// Per-layer record of the force statistics: net force (3), absolute force (3), max |f|,
+// non-finite flag.
+#define NF_STRIDE 8
+
 // ----------------------------------------------------------------------------------
 // Net force per layer and component, and the finiteness check of the forces.
 // ----------------------------------------------------------------------------------
@@ -51,18 +55,39 @@ __global__ void __launch_bounds__(NT) k_netforce(const double* __restrict__ f,
     const int n0 = blockIdx.x, r = blockIdx.y;
     const double* row = f + ((int64_t)r * nz + n0) * n_i * 3;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    double mx[1] = {0.0};
     for (int i = threadIdx.x; i < n_i; i += NT) {
         for (int c = 0; c < 3; ++c) {
             const double x = row[3 * i + c];
             v[c] += x;
             v[3 + c] += fabs(x);
+            mx[0] = fmax(mx[0], fabs(x));
             if (!isfinite(x)) v[6] = 1.0;
         }
     }
     block_sum<7>(v, red);
+    block_max<1>(mx, red);
     if (threadIdx.x == 0) {
-        for (int c = 0; c < 6; ++c) sums[((int64_t)r * nz + n0) * 6 + c] = v[c];
+        double* o = sums + ((int64_t)r * nz + n0) * NF_STRIDE;
+        for (int c = 0; c < 6; ++c) o[c] = v[c];
+        o[6] = mx[0];
+        o[7] = v[6];
         if (check && (v[6] != 0.0 || !isfinite(v[3] + v[4] + v[5]))) atomicOr(status, ST_NONFINITE);
+    }
+}
+
+// Split-FP16 form: scale exponent of the force operand of a cell, from a bound on the
+// transformed forces, |f^(m)| <= sum_n0 |f(n0)| <= Nz max|f| (twice that after the
+// projection), so that the scaled values stay below 2^14.
+__global__ void __launch_bounds__(NT) k_bexp(const double* __restrict__ sums, int n_layers, int nz,
+                                             int* __restrict__ bexp) {
+    __shared__ double red[NT];
+    double mx[1] = {0.0};
+    for (int e = threadIdx.x; e < n_layers; e += NT) mx[0] = fmax(mx[0], sums[(int64_t)e * NF_STRIDE + 6]);
+    block_max<1>(mx, red);
+    if (threadIdx.x == 0) {
+        const double bound = 2.0 * nz * mx[0];
+        *bexp = (bound > 0.0 && isfinite(bound)) ? 13 - ilogb(bound) : 0;
     }
 }
 
@@ -77,7 +102,7 @@ __global__ void __launch_bounds__(NT) k_netforce_total(const double* __restrict_
     const int r = blockIdx.x;
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int n0 = threadIdx.x; n0 < nz; n0 += NT)
-        for (int c = 0; c < 6; ++c) v[c] += sums[((int64_t)r * nz + n0) * 6 + c];
+        for (int c = 0; c < 6; ++c) v[c] += sums[((int64_t)r * nz + n0) * NF_STRIDE + c];
     block_sum<6>(v, red);
     if (threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) tot[r * 3 + c] = v[c];
@@ -102,7 +127,7 @@ __global__ void __launch_bounds__(NT) k_netforce_fft(const double* __restrict__ 
     const int c = blockIdx.x, r = blockIdx.y;
     const double sub = project ? tot[r * 3 + c] / nz : 0.0;
     for (int n0 = threadIdx.x; n0 < nz; n0 += NT)
-        lds[bitrev(n0, logn)] = make_double2(sums[((int64_t)r * nz + n0) * 6 + c] - sub, 0.0);
+        lds[bitrev(n0, logn)] = make_double2(sums[((int64_t)r * nz + n0) * NF_STRIDE + c] - sub, 0.0);
     __syncthreads();
     lds_fft(lds, 1, logn, tw, false);
     const int nm = (nz >> 1) + 1;
@@ -115,10 +140,11 @@ __global__ void __launch_bounds__(NT) k_netforce_fft(const double* __restrict__ 
 
 void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat, int R,
                      int nz, int n_i, double tol, int check, int project, const double2* tw,
-                     int* status) {
+                     int* bexp, int* status) {
     hipLaunchKernelGGL(k_netforce, dim3(nz, R), dim3(NT), 0, st, f, sums, nz, n_i, check, status);
     hipLaunchKernelGGL(k_netforce_total, dim3(R), dim3(NT), 0, st, sums, nz, tol, check, project, tot,
                        status);
+    if (bexp) hipLaunchKernelGGL(k_bexp, dim3(1), dim3(NT), 0, st, sums, R * nz, nz, bexp);
     if (shat) {
         int logn = 0;
         while ((1 << logn) < nz) ++logn;
@@ -147,6 +173,12 @@ __device__ inline void put_b(void* bm, int n, int kq, int kp, double v) {
         ((double*)bm)[frag_off_f64(n, kq, kp)] = v;
     } else if (FORM == FBC_FORM_FP32) {
         ((float*)bm)[frag_off_f32(n, kq, kp)] = (float)v;
+    } else if (FORM == FBC_FORM_SPLIT_FP16) {        // v already scaled by 2^e
+        const _Float16 hi = (_Float16)(float)v;
+        const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
+        unsigned short* p = (unsigned short*)bm + frag_off_bf16(n, kq, kp);
+        p[0] = __builtin_bit_cast(unsigned short, hi);
+        p[512] = __builtin_bit_cast(unsigned short, lo);
     } else {
         const unsigned short hi = f2bf((float)v);
         const unsigned short lo = f2bf((float)(v - (double)bf2f(hi)));
@@ -161,8 +193,10 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                                                   const double* __restrict__ tot, int project,
                                                   void* __restrict__ bfrag, int nz, int logn,
                                                   int n_i, int kp, int ct, int tc,
-                                                  const double2* __restrict__ tw, double inv_cnt) {
+                                                  const double2* __restrict__ tw, double inv_cnt,
+                                                  const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
+    const int esc = (FORM == FBC_FORM_SPLIT_FP16) ? *bexp : 0;   // power-of-two operand scale
     const int r = blockIdx.y;
     const int k0 = blockIdx.x * tc;
     const int K = 3 * n_i;
@@ -174,6 +208,7 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
         if (k < K) {
             v = f[((int64_t)r * nz + n0) * K + k];
             if (project) v -= tot[r * 3 + (k % 3)] * inv_cnt;     // mean over the cell's atoms
+            if (FORM == FBC_FORM_SPLIT_FP16) v = ldexp(v, esc);
         }
         ldsd[2 * ((c >> 1) * nz + (int)bitrev(n0, logn)) + (c & 1)] = v;
     }
@@ -181,7 +216,8 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     lds_fft(lds, nseq, logn, tw, false);
     const int nm = (nz >> 1) + 1;
     // per mode: B elements of one mode occupy 16*ct*kp values (x2 for the bf16 split)
-    const int64_t mode_elems = (int64_t)16 * ct * kp * (FORM == FBC_FORM_SPLIT_BF16 ? 2 : 1);
+    const int64_t mode_elems =
+        (int64_t)16 * ct * kp * ((FORM == FBC_FORM_SPLIT_BF16 || FORM == FBC_FORM_SPLIT_FP16) ? 2 : 1);
     const int tile = r >> 3, j = r & 7;
     const int nre = 16 * tile + j, nim = nre + 8;
     for (int t = threadIdx.x; t < nm * tc; t += NT) {
@@ -213,7 +249,8 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
 }
 
 void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
-                      void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw) {
+                      void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw,
+                      const int* bexp) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     const int K = 3 * n_i;
@@ -229,15 +266,19 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
     switch (form) {
         case FBC_FORM_FP32:
             hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP32>, grid, dim3(NT), lds, st, f, tot, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt);
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
+            break;
+        case FBC_FORM_SPLIT_FP16:
+            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_FP16>, grid, dim3(NT), lds, st, f, tot,
+                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
             break;
         case FBC_FORM_SPLIT_BF16:
             hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_BF16>, grid, dim3(NT), lds, st, f, tot,
-                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt);
+                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
             break;
         default:
             hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP64>, grid, dim3(NT), lds, st, f, tot, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt);
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
             break;
     }
 }
@@ -256,8 +297,11 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    const double2* __restrict__ tw, int nsplit,
                                                    int64_t split_stride,
                                                    const double2* __restrict__ rowmean,
-                                                   const double2* __restrict__ shat) {
+                                                   const double2* __restrict__ shat,
+                                                   const unsigned long long* __restrict__ amax,
+                                                   const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
+    const int eb = bexp ? *bexp : 0;
     const int row0 = blockIdx.x * tr;
     const int tile = blockIdx.y;
     const int pair0 = blockIdx.z * pp;          // first RHS pair inside the 8-RHS tile
@@ -280,6 +324,13 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                 ai += q[ja + 8];
                 br += q[ja + 1];
                 bi += q[ja + 9];
+            }
+            if (amax) {     // split FP16: the product carries 2^(e_A(m) + e_B)
+                const double sc = ldexp(1.0, -(split16_exp_a(amax[mm]) + eb));
+                ar *= sc;
+                ai *= sc;
+                br *= sc;
+                bi *= sc;
             }
             if (rowmean) {
                 // exact FP64 compensation of the row gauge: + R_b(m) . sum_i f^_i(m)
@@ -342,7 +393,7 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,
-                       int* n_part_out) {
+                       const unsigned long long* amax, const int* bexp, int* n_part_out) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int pp, tr;
@@ -358,7 +409,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
     size_t lds = (size_t)tr * pp * nz * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
     hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,
-                       ct, tr, pp, tw, nsplit, split_stride, rowmean, shat);
+                       ct, tr, pp, tw, nsplit, split_stride, rowmean, shat, amax, bexp);
     if (n_part_out) *n_part_out = (int)grid.x;
 }
 

@@ -257,7 +257,8 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
                                                      int n_i, const int32_t* __restrict__ cols_b,
                                                      const int32_t* __restrict__ cols_i,
                                                      const int32_t* __restrict__ lut, int d1min,
-                                                     int d2min, int w2) {
+                                                     int d2min, int w2,
+                                                     const unsigned long long* __restrict__ amax) {
     const int64_t per_mode = (int64_t)mp * kp;
     const int64_t total = per_mode * nm;
     // grid-stride: the element count can exceed the 2^32 work-items of one launch
@@ -280,6 +281,20 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
         const int row = 16 * blk + (lane & 15), kq = 16 * q + 4 * s + (lane >> 4);
         ((float*)store)[e] = (float)dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b,
                                                 n_i, cols_b, cols_i, lut, d1min, d2min, w2);
+    } else if (form == FBC_FORM_SPLIT_FP16) {  // same layout as split BF16, scaled by 2^e(m)
+        const int j = (int)(x & 7), lane = (int)((x >> 3) & 63);
+        const int64_t rest = x >> 9;
+        const int blk = (int)(rest % mb), t = (int)(rest / mb);
+        const int row = 16 * blk + (lane & 15), kq = 32 * t + 8 * (lane >> 4) + j;
+        const double v = ldexp(dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
+                                           cols_i, lut, d1min, d2min, w2),
+                               split16_exp_a(amax[m]));
+        const _Float16 hi = (_Float16)(float)v;
+        const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
+        unsigned short* out = (unsigned short*)store + (int64_t)m * per_mode * 2;
+        const int64_t base = ((((int64_t)t * mb + blk) * 2) * 64 + lane) * 8 + j;
+        out[base] = __builtin_bit_cast(unsigned short, hi);
+        out[base + 512] = __builtin_bit_cast(unsigned short, lo);
     } else {  // split BF16 [t][blk][hi/lo][lane][8]: x indexes hi parts; lo is 512 later
         const int j = (int)(x & 7), lane = (int)((x >> 3) & 63);
         const int64_t rest = x >> 9;
@@ -297,13 +312,42 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
     }
 }
 
+// Largest magnitude of each table mode a cell reads (superset of its blocks), as the bit
+// pattern of a non-negative double: amax[m] = max over offsets, components, re/im.
+__global__ void __launch_bounds__(256) k_tab_absmax(const double2* __restrict__ tab, int mode_mult,
+                                                    int64_t n_off, unsigned long long* __restrict__ amax) {
+    __shared__ double red[256];
+    const int m = blockIdx.y;
+    const double2* tm = tab + (int64_t)m * mode_mult * n_off * 6;
+    double mx = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n_off * 6; e += (int64_t)gridDim.x * 256)
+        mx = fmax(mx, fmax(fabs(tm[e].x), fabs(tm[e].y)));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(amax + m, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
                         const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
                         int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
-                        const int32_t* lut, int d1min, int d2min, int w2) {
+                        const int32_t* lut, int d1min, int d2min, int w2, unsigned long long* amax) {
     const int64_t total = (int64_t)mp * kp * nm;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
+    if (form == FBC_FORM_SPLIT_FP16) {
+        hipLaunchKernelGGL(k_zero_u64, dim3((nm + 255) / 256), dim3(256), 0, st, amax, nm);
+        const int sl = (int)std::min<int64_t>(64, (n_off * 6 + 255) / 256);
+        hipLaunchKernelGGL(k_tab_absmax, dim3(sl, nm), dim3(256), 0, st, tab, mode_mult, n_off, amax);
+    }
     hipLaunchKernelGGL(k_build_dense, dim3((unsigned)blocks), dim3(256), 0, st,
                        form, store, tab, rowmean, nm, mode_mult, n_off, mp, kp, n_b, n_i, cols_b,
-                       cols_i, lut, d1min, d2min, w2);
+                       cols_i, lut, d1min, d2min, w2, amax);
 }

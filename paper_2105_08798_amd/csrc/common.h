@@ -10,6 +10,15 @@
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+
+// Split-FP16 form: power-of-two scale exponent of a line mode's blocks from the largest
+// table magnitude of that mode (bit pattern of a non-negative double).  |G - row mean|
+// <= 2 max, so 2^e |G - row mean| < 2^14, inside the FP16 range with headroom.
+__host__ __device__ inline int split16_exp_a(unsigned long long maxbits) {
+    const double m = __longlong_as_double((long long)maxbits);
+    return m > 0.0 ? 12 - ilogb(m) : 0;
+}
 typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------------

@@ -27,6 +27,9 @@ struct fbc_ctx {
     double2* shat = nullptr;        // line transform of the per-layer net force [r][m][3]
     double2* rowmean = nullptr;     // row-gauge means [m][b][6] (reduced forms with row gauge)
     std::vector<int64_t> shat_off, rowmean_off;
+    unsigned long long* amax = nullptr;  // split FP16: per cell mode, largest table magnitude
+    std::vector<int64_t> amax_off;
+    int* bexp = nullptr;            // split FP16: per cell, force operand scale exponent
     double* wmax_part = nullptr;
     double* sum_part = nullptr;
     double* mean = nullptr;         // [total_rhs][3]

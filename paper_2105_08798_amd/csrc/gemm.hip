@@ -161,11 +161,20 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
 // ------------------------------- split BF16 ---------------------------------------
 // G ~ G_hi + G_lo, f ~ f_hi + f_lo; products lo*hi + hi*lo + hi*hi on BF16 MFMA with
 // FP32 accumulation inside chunks of KCH*32 real k, FP64 across chunks.
-template <int RB, int CT, int PF, int KCH>
-__global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ jobs,
-                                                   const unsigned short* __restrict__ A,
-                                                   const unsigned short* __restrict__ B,
-                                                   double* __restrict__ C) {
+// The split-FP16 form runs the same kernel on FP16 MFMA; its operands carry power-of-two
+// scales that the inverse transform removes.
+__device__ inline f4_t mfma_16x16x32(bf8_t a, bf8_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f4_t mfma_16x16x32(h8_t a, h8_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+template <typename VT, int RB, int CT, int PF, int KCH>
+__global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ jobs,
+                                                    const unsigned short* __restrict__ A,
+                                                    const unsigned short* __restrict__ B,
+                                                    double* __restrict__ C) {
     const GemmJob jb = jobs[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
@@ -174,8 +183,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
     const int tb = jb.k0 >> 5, te = jb.k1 >> 5;
     // 16-byte units: per (block, t): hi run of 64 units then lo run of 64 units
     const int64_t mb = jb.mb;
-    const bf8_t* a = (const bf8_t*)(A + jb.a_off) + (int64_t)rbw * 128 + lane;      // K-major
-    const bf8_t* b = (const bf8_t*)(B + jb.b_off) + lane;
+    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)rbw * 128 + lane;      // K-major
+    const VT* b = (const VT*)(B + jb.b_off) + lane;
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
 #pragma unroll
@@ -185,7 +194,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
             acc[r][c] = (d4_t){0, 0, 0, 0};
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
-    bf8_t ah[PF][RB], al[PF][RB], bh[PF][CT], bl[PF][CT];
+    VT ah[PF][RB], al[PF][RB], bh[PF][CT], bl[PF][CT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
 #pragma unroll
@@ -206,17 +215,17 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmJob* __restrict__ j
             for (int r = 0; r < RB; ++r)
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u][r], bh[u][c], ac32[r][c], 0, 0, 0);
+                    ac32[r][c] = mfma_16x16x32(al[u][r], bh[u][c], ac32[r][c]);
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][r], bl[u][c], ac32[r][c], 0, 0, 0);
+                    ac32[r][c] = mfma_16x16x32(ah[u][r], bl[u][c], ac32[r][c]);
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][r], bh[u][c], ac32[r][c], 0, 0, 0);
+                    ac32[r][c] = mfma_16x16x32(ah[u][r], bh[u][c], ac32[r][c]);
             const int tn = min(t0 + u + PF, te - 1);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -272,12 +281,20 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         else if (ctmax <= 2) GEMM_CASE(k_gemm_f32, 4, 2, 4, 16);
         else if (ctmax <= 4) GEMM_CASE(k_gemm_f32, 2, 4, 2, 16);
         else GEMM_CASE(k_gemm_f32, 2, 8, 2, 16);
+    } else if (form == FBC_FORM_SPLIT_FP16) {
+        // shorter FP32 chunks: the representation error is ~2^-23, so the FP32 sums must
+        // not dominate
+        typedef unsigned short TA;
+        if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 4, 1, 2, 2);
+        else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split, h8_t, 2, 4, 2, 2);
+        else GEMM_CASE(k_gemm_split, h8_t, 2, 8, 2, 2);
     } else {
         typedef unsigned short TA;
-        if (ctmax <= 1) GEMM_CASE(k_gemm_bf16, 4, 1, 2, 8);
-        else if (ctmax <= 2) GEMM_CASE(k_gemm_bf16, 4, 2, 2, 8);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_bf16, 2, 4, 2, 8);
-        else GEMM_CASE(k_gemm_bf16, 2, 8, 2, 8);
+        if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 4, 1, 2, 8);
+        else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split, bf8_t, 2, 4, 2, 8);
+        else GEMM_CASE(k_gemm_split, bf8_t, 2, 8, 2, 8);
     }
 #undef GEMM_CASE
 }

@@ -25,16 +25,17 @@ void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
                         const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
                         int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
-                        const int32_t* lut, int d1min, int d2min, int w2);
+                        const int32_t* lut, int d1min, int d2min, int w2, unsigned long long* amax);
 
 // ---- apply (Section 2.3.2 update in line-mode form) ----
 // Per-layer sums sums[r][n0][6] (net force, absolute force), cell totals tot[r][3] with
 // the net-force check, and (shat != NULL) the line transform of the per-layer net force.
 void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat, int R,
                      int nz, int n_i, double tol, int check, int project, const double2* tw,
-                     int* status);
+                     int* bexp, int* status);
 void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
-                      void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw);
+                      void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw,
+                      const int* bexp);
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
                  const void* a, const void* b, double* c);
 // Offset-table form: 32 pad columns x all interface columns per work group, table
@@ -45,7 +46,7 @@ void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, co
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,
-                       int* n_part_out);
+                       const unsigned long long* amax, const int* bexp, int* n_part_out);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status,
                  int* n_part_out);

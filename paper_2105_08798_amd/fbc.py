@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfbc.so")
 FBC_OK = 0
 STATUS = {0: "FBC_OK", -1: "FBC_E_ARG", -2: "FBC_E_NOMEM", -3: "FBC_E_NETFORCE",
           -4: "FBC_E_NONFINITE", -5: "FBC_E_DEVICE", -6: "FBC_E_STATE", -7: "FBC_E_UNSUPPORTED"}
-FORMS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "dtable_fp64": 3, "surrogate": 4}
+FORMS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "dtable_fp64": 3, "surrogate": 4, "split_fp16": 5}
 
 EXPORTED = [
     "fbc_default_options", "fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin",

@@ -35,8 +35,8 @@ def rel_err(got, ref):
 
 @pytest.mark.parametrize("name,form,bound", [
     ("medium", "fp64", 1e-10), ("medium", "fp32", 1e-6), ("medium", "split_bf16", 2e-5),
-    ("medium", "dtable_fp64", 1e-10),
-    ("large", "fp64", 1e-10), ("large", "split_bf16", 2e-5),
+    ("medium", "split_fp16", 1e-6), ("medium", "dtable_fp64", 1e-10),
+    ("large", "fp64", 1e-10), ("large", "split_bf16", 2e-5), ("large", "split_fp16", 1e-6),
 ])
 def test_fullsize_green_apply_matches_oracle_samples(name, form, bound):
     if not torch.cuda.is_available():

@@ -79,6 +79,7 @@ def test_fp64_forms_two_step_convergence(form):
 # fixed-point displacement error bounds (relative, over A and i++): a few times what was
 # measured -- FP32 4.8e-8, split BF16 9.7e-7 -- the surrogate's from its far field
 @pytest.mark.parametrize("form,n_iter,bound", [("fp32", 6, 2e-7), ("split_bf16", 6, 3e-6),
+                                               ("split_fp16", 6, 3e-7),
                                                ("surrogate", 10, 1e-3)])
 def test_reduced_forms_converge_to_a_nearby_fixed_point(form, n_iter, bound):
     disc = _disc()
