@@ -60,9 +60,10 @@ def kernel_matches(form: str, name: str) -> bool:
         return name.startswith("k_gemm_f64<")
     if form == "fp32":
         return name.startswith("k_gemm_f32<")
-    if form in ("split_bf16", "split_fp16"):
-        half = "bf16" not in name and ("Float16" in name or "half" in name)
-        return name.startswith("k_gemm_split<") and (half == (form == "split_fp16"))
+    if form == "split_bf16":
+        return name.startswith("k_gemm_split<bf16x8")
+    if form == "split_fp16":
+        return name.startswith("k_gemm_split<f16x8")
     return name.startswith("k_gemm_dtab<")
 
 
