@@ -113,7 +113,7 @@ typedef struct {
     int nz;                  /* layers along the line, power of two in [2, 4096]          */
     int n_i;                 /* interface columns (>= 1)                                   */
     int n_b;                 /* pad columns (>= 1)                                         */
-    int n_rhs;               /* force right-hand sides applied per call (>= 1)             */
+    int n_rhs;               /* force right-hand sides applied per call, in [1, 65535]     */
     const int32_t* cols_i;   /* host [n_i][2] (n1, n2); copied, not retained               */
     const int32_t* cols_b;   /* host [n_b][2] (n1, n2); copied, not retained               */
 } fbc_cell;

@@ -569,6 +569,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             return fail(nullptr, FBC_E_ARG, "cell sizes must be >= 1 and column arrays non-null");
         if ((int64_t)cl.n_i * 6 > (1 << 30) || (int64_t)cl.n_b * 3 > (1 << 30))
             return fail(nullptr, FBC_E_ARG, "cell too large");
+        if (cl.n_rhs > 65535) return fail(nullptr, FBC_E_ARG, "n_rhs must be <= 65535");
         if (cl.n_rhs > 64) return fail(nullptr, FBC_E_ARG, "at most 64 RHS per cell");
     }
 

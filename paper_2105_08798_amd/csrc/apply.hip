@@ -4,6 +4,8 @@
 // All reductions use a fixed partition and a fixed-order tree, so results are bitwise
 // reproducible from run to run (no floating-point atomics).
 #include "fft_lds.h"
+#include <algorithm>
+
 #include "kernels.h"
 
 #define NT 256
@@ -197,11 +199,15 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                                                   const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
     const int esc = (FORM == FBC_FORM_SPLIT_FP16) ? *bexp : 0;   // power-of-two operand scale
-    const int r = blockIdx.y;
-    const int k0 = blockIdx.x * tc;
+    // RHS fastest across blocks: the 8 RHS of a column tile, whose B fragments share
+    // 256-byte lines, are written by neighbouring blocks close in time
+    const int r = blockIdx.x;
     const int K = 3 * n_i;
     const int nseq = tc >> 1;
+    const int nchunk = (K + tc - 1) / tc;
     double* ldsd = (double*)lds;
+    for (int cy = blockIdx.y; cy < nchunk; cy += gridDim.y) {     // column chunks (grid-stride)
+    const int k0 = cy * tc;
     for (int t = threadIdx.x; t < nz * tc; t += NT) {
         const int n0 = t / tc, c = t - n0 * tc, k = k0 + c;
         double v = 0.0;
@@ -246,6 +252,8 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
         put_b<FORM>(bm, nim, 2 * k, kp, fi);
         put_b<FORM>(bm, nim, 2 * k + 1, kp, fr);
     }
+    __syncthreads();        // the next chunk overwrites the LDS sequences
+    }
 }
 
 void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
@@ -260,7 +268,7 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
     const int kk = (K + 1) & ~1;
     if (tc > kk) tc = kk;
     tc &= ~1;
-    dim3 grid((K + tc - 1) / tc, R);
+    dim3 grid(R, (unsigned)std::min((K + tc - 1) / tc, 65535));
     const size_t lds = (size_t)nz * tc * sizeof(double);
     const double inv_cnt = 1.0 / ((double)n_i * nz);
     switch (form) {
@@ -308,22 +316,28 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     const int nseq = tr * pp;
     const int nm = (nz >> 1) + 1;
     const int64_t mode_stride = (int64_t)ct * mp * 16;
-    for (int t = threadIdx.x; t < nseq * nz; t += NT) {
-        const int s = t / nz, m = t - s * nz;
-        const int trr = s / pp, pj = s - trr * pp;
+    // Each (mode, row, RHS pair) of the product output is read once, pair fastest, then
+    // row, then mode: a wave reads whole 128-byte rows of one mode (coalesced); the
+    // mirrored half of the spectrum (m > Nz/2) is written from the same values.
+    for (int t = threadIdx.x; t < nm * tr * pp; t += NT) {
+        const int pj = t % pp;
+        const int rest = t / pp;
+        const int trr = rest % tr, mm = rest / tr;
+        const int s = trr * pp + pj;
         const int row = row0 + trr;
         const int ja = 2 * (pair0 + pj);
-        double2 z = make_double2(0, 0);
+        double2 z = make_double2(0, 0), zc = make_double2(0, 0);
         if (row < M) {
-            const int mm = (m < nm) ? m : nz - m;
             const double* src = c + mm * mode_stride + ((int64_t)tile * mp + row) * 16;
-            double ar = src[ja], ai = src[ja + 8], br = src[ja + 1], bi = src[ja + 9];
+            const double2 v0 = *(const double2*)(src + ja), v1 = *(const double2*)(src + ja + 8);
+            double ar = v0.x, br = v0.y, ai = v1.x, bi = v1.y;
             for (int ks = 1; ks < nsplit; ++ks) {      // K slices, summed in fixed order
                 const double* q = src + ks * split_stride;
-                ar += q[ja];
-                ai += q[ja + 8];
-                br += q[ja + 1];
-                bi += q[ja + 9];
+                const double2 q0 = *(const double2*)(q + ja), q1 = *(const double2*)(q + ja + 8);
+                ar += q0.x;
+                br += q0.y;
+                ai += q1.x;
+                bi += q1.y;
             }
             if (amax) {     // split FP16: the product carries 2^(e_A(m) + e_B)
                 const double sc = ldexp(1.0, -(split16_exp_a(amax[mm]) + eb));
@@ -351,10 +365,11 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                 }
             }
             if (mm == 0 || 2 * mm == nz) { ai = 0.0; bi = 0.0; }
-            if (m >= nm) { ai = -ai; bi = -bi; }
-            z = make_double2(ar - bi, ai + br);     // U_a + i U_b
+            z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
+            zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
         }
-        lds[s * nz + bitrev(m, logn)] = z;
+        lds[s * nz + bitrev(mm, logn)] = z;
+        if (mm > 0 && 2 * mm < nz) lds[s * nz + bitrev(nz - mm, logn)] = zc;
     }
     __syncthreads();
     lds_fft(lds, nseq, logn, tw, true);

@@ -255,10 +255,114 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
         for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
+// Variant for 4 or 8 column tiles (many RHS): the B fragments of a K step are the same
+// for the four waves of a work group, so they are loaded once per work group into LDS
+// (double buffered, one barrier per step) instead of once per wave from L2; each thread
+// stages CT/2 16-byte units of the next step in registers while the MFMAs of the current
+// step run.  A is streamed from HBM as in k_gemm_split, two steps ahead.
+template <typename VT, int RB, int CT, int PFA, int KCH>
+__global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restrict__ jobs,
+                                                        const unsigned short* __restrict__ A,
+                                                        const unsigned short* __restrict__ B,
+                                                        double* __restrict__ C) {
+    static_assert(CT >= 2 && (CT % 2) == 0, "B staging assumes an even tile count");
+    static_assert(PFA >= 2 && (PFA % 2) == 0, "A ring depth must be even");
+    constexpr int UNITS = CT * 128;          // 16-byte units of B per step (hi and lo runs)
+    constexpr int NU = UNITS / 256;          // per thread
+    __shared__ VT bs[2][UNITS];
+    const GemmJob jb = jobs[blockIdx.x];
+    if (jb.rb0 >= jb.mb) return;             // whole work group (empty job)
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int rbw = jb.rb0 + wave * RB;
+    const int kt = jb.kp >> 5;
+    const int tb = jb.k0 >> 5, te = jb.k1 >> 5;    // te - tb is even (K slices of 64 k')
+    const int64_t mb = jb.mb;
+    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)rbw * 128 + lane;      // K-major
+    const VT* b = (const VT*)(B + jb.b_off);
+    d4_t acc[RB][CT];
+    f4_t ac32[RB][CT];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            acc[r][c] = (d4_t){0, 0, 0, 0};
+            ac32[r][c] = (f4_t){0, 0, 0, 0};
+        }
+    VT stage[NU];
+    auto load_b = [&](int t) {
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int u = tid + 256 * j, c = u >> 7, rem = u & 127;
+            stage[j] = b[((int64_t)c * kt + t) * 128 + rem];
+        }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < NU; ++j) bs[buf][tid + 256 * j] = stage[j];
+    };
+    // A ring: PFA steps in flight per wave (memory-level parallelism for HBM latency)
+    VT ah[PFA][RB], al[PFA][RB];
+#pragma unroll
+    for (int u = 0; u < PFA; ++u) {
+        const int tl = min(tb + u, te - 1);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            ah[u][r] = a[((int64_t)tl * mb + r) * 128];
+            al[u][r] = a[((int64_t)tl * mb + r) * 128 + 64];
+        }
+    }
+    load_b(tb);
+    store_b(0);
+    __syncthreads();
+    for (int t0 = tb; t0 < te; t0 += PFA) {
+#pragma unroll
+        for (int u = 0; u < PFA; ++u) {
+            const int t = t0 + u;
+            if (t >= te) break;                    // same for every wave of the group
+            const int buf = u & 1;                 // t - tb has the parity of u (PFA even)
+            const bool more = (t + 1 < te);
+            if (more) load_b(t + 1);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const VT bh = bs[buf][c * 128 + lane];
+                const VT bl = bs[buf][c * 128 + 64 + lane];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    ac32[r][c] = mfma_16x16x32(al[u][r], bh, ac32[r][c]);
+                    ac32[r][c] = mfma_16x16x32(ah[u][r], bl, ac32[r][c]);
+                    ac32[r][c] = mfma_16x16x32(ah[u][r], bh, ac32[r][c]);
+                }
+            }
+            const int tn = min(t + PFA, te - 1);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                ah[u][r] = a[((int64_t)tn * mb + r) * 128];
+                al[u][r] = a[((int64_t)tn * mb + r) * 128 + 64];
+            }
+            if (((t - tb + 1) % KCH) == 0 || !more) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[r][c][j] += (double)ac32[r][c][j];
+                        ac32[r][c] = (f4_t){0, 0, 0, 0};
+                    }
+            }
+            if (more) store_b(buf ^ 1);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+}
+
 // Row blocks per wave for a given column-tile count (register budget per lane).  The
 // planner pads rows to 64*RB (a whole work-group tile) and K' to a multiple of 64.
 int gemm_rb(int form, int ctmax) {
-    (void)form;
+    if (form == FBC_FORM_SPLIT_BF16 || form == FBC_FORM_SPLIT_FP16) return ctmax <= 2 ? 4 : 1;
     return ctmax <= 2 ? 4 : 2;
 }
 
@@ -287,14 +391,14 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 4, 1, 2, 2);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split, h8_t, 2, 4, 2, 2);
-        else GEMM_CASE(k_gemm_split, h8_t, 2, 8, 2, 2);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 1, 4, 8, 2);
+        else GEMM_CASE(k_gemm_split_lds, h8_t, 1, 8, 8, 2);
     } else {
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 4, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split, bf8_t, 2, 4, 2, 8);
-        else GEMM_CASE(k_gemm_split, bf8_t, 2, 8, 2, 8);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 1, 4, 8, 8);
+        else GEMM_CASE(k_gemm_split_lds, bf8_t, 1, 8, 8, 8);
     }
 #undef GEMM_CASE
 }

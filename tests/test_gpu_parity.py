@@ -195,6 +195,18 @@ def test_layer_net_forces_with_zero_cell_total(form, tol):
     assert e2 < tol and emax < 3 * tol, (form, e2, emax)
 
 
+@pytest.mark.parametrize("form,tol", [("fp32", 1e-6), ("split_bf16", 2e-5), ("split_fp16", 1e-6)])
+@pytest.mark.parametrize("nz,n_i,n_b,R,bz", [(16, 50, 80, 20, 64), (8, 130, 260, 33, 64), (4, 40, 70, 64, 32)])
+def test_reduced_forms_many_rhs(nz, n_i, n_b, R, bz, form, tol):
+    """4 and 8 column tiles: the product kernels that share B through LDS."""
+    wl = W.make_custom(nz, n_i, n_b, R, bz, seed=nz + R)
+    rc, got, u0 = run_apply(wl, form, alpha=1.0)
+    assert rc == 0
+    ref = oracle_update(wl, u0, 1.0)[0]
+    e2, emax = rel_err(got.reshape(ref.shape), ref)
+    assert e2 < tol and emax < 3 * tol, (form, e2, emax)
+
+
 @pytest.mark.parametrize("form", ["fp32", "split_bf16", "split_fp16"])
 def test_projection_in_reduced_forms(form):
     wl = W.make_custom(16, 25, 40, 2, 16, seed=8, zero_net_force=False)
