@@ -208,15 +208,28 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     double* ldsd = (double*)lds;
     for (int cy = blockIdx.y; cy < nchunk; cy += gridDim.y) {     // column chunks (grid-stride)
     const int k0 = cy * tc;
-    for (int t = threadIdx.x; t < nz * tc; t += NT) {
-        const int n0 = t / tc, c = t - n0 * tc, k = k0 + c;
-        double v = 0.0;
-        if (k < K) {
-            v = f[((int64_t)r * nz + n0) * K + k];
-            if (project) v -= tot[r * 3 + (k % 3)] * inv_cnt;     // mean over the cell's atoms
-            if (FORM == FBC_FORM_SPLIT_FP16) v = ldexp(v, esc);
+    // loads issued in batches of 8 per thread before their LDS stores (latency hiding)
+    constexpr int LU = 8;
+    for (int t0 = threadIdx.x; t0 < nz * tc; t0 += NT * LU) {
+        double v[LU];
+#pragma unroll
+        for (int q = 0; q < LU; ++q) {
+            const int t = t0 + q * NT;
+            const int n0 = t / tc, c = t - n0 * tc, k = k0 + c;
+            v[q] = (t < nz * tc && k < K) ? f[((int64_t)r * nz + n0) * K + k] : 0.0;
         }
-        ldsd[2 * ((c >> 1) * nz + (int)bitrev(n0, logn)) + (c & 1)] = v;
+#pragma unroll
+        for (int q = 0; q < LU; ++q) {
+            const int t = t0 + q * NT;
+            if (t >= nz * tc) break;
+            const int n0 = t / tc, c = t - n0 * tc, k = k0 + c;
+            double x = v[q];
+            if (k < K) {
+                if (project) x -= tot[r * 3 + (k % 3)] * inv_cnt;     // mean over the cell's atoms
+                if (FORM == FBC_FORM_SPLIT_FP16) x = ldexp(x, esc);
+            }
+            ldsd[2 * ((c >> 1) * nz + (int)bitrev(n0, logn)) + (c & 1)] = x;
+        }
     }
     __syncthreads();
     lds_fft(lds, nseq, logn, tw, false);

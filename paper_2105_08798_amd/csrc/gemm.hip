@@ -322,15 +322,26 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
             const int buf = u & 1;                 // t - tb has the parity of u (PFA even)
             const bool more = (t + 1 < te);
             if (more) load_b(t + 1);
+            // two column tiles at a time, the three products of a tile interleaved with
+            // the other tile's, so dependent MFMAs are 2 RB instructions apart
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const VT bh = bs[buf][c * 128 + lane];
-                const VT bl = bs[buf][c * 128 + 64 + lane];
+            for (int c = 0; c < CT; c += 2) {
+                const VT bh0 = bs[buf][c * 128 + lane], bl0 = bs[buf][c * 128 + 64 + lane];
+                const VT bh1 = bs[buf][(c + 1) * 128 + lane], bl1 = bs[buf][(c + 1) * 128 + 64 + lane];
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    ac32[r][c] = mfma_16x16x32(al[u][r], bh, ac32[r][c]);
-                    ac32[r][c] = mfma_16x16x32(ah[u][r], bl, ac32[r][c]);
-                    ac32[r][c] = mfma_16x16x32(ah[u][r], bh, ac32[r][c]);
+                    ac32[r][c] = mfma_16x16x32(al[u][r], bh0, ac32[r][c]);
+                    ac32[r][c + 1] = mfma_16x16x32(al[u][r], bh1, ac32[r][c + 1]);
+                }
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    ac32[r][c] = mfma_16x16x32(ah[u][r], bl0, ac32[r][c]);
+                    ac32[r][c + 1] = mfma_16x16x32(ah[u][r], bl1, ac32[r][c + 1]);
+                }
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    ac32[r][c] = mfma_16x16x32(ah[u][r], bh0, ac32[r][c]);
+                    ac32[r][c + 1] = mfma_16x16x32(ah[u][r], bh1, ac32[r][c + 1]);
                 }
             }
             const int tn = min(t + PFA, te - 1);
@@ -362,7 +373,7 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
 // Row blocks per wave for a given column-tile count (register budget per lane).  The
 // planner pads rows to 64*RB (a whole work-group tile) and K' to a multiple of 64.
 int gemm_rb(int form, int ctmax) {
-    if (form == FBC_FORM_SPLIT_BF16 || form == FBC_FORM_SPLIT_FP16) return ctmax <= 2 ? 4 : 1;
+    if (form == FBC_FORM_SPLIT_BF16 || form == FBC_FORM_SPLIT_FP16) return ctmax <= 2 ? 4 : 2;
     return ctmax <= 2 ? 4 : 2;
 }
 
@@ -391,14 +402,14 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 4, 1, 2, 2);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 1, 4, 8, 2);
-        else GEMM_CASE(k_gemm_split_lds, h8_t, 1, 8, 8, 2);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 8, 4);
+        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 8, 4);
     } else {
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 4, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 1, 4, 8, 8);
-        else GEMM_CASE(k_gemm_split_lds, bf8_t, 1, 8, 8, 8);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 8, 8);
+        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 8, 8);
     }
 #undef GEMM_CASE
 }
