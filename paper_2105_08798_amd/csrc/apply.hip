@@ -332,7 +332,30 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     // Each (mode, row, RHS pair) of the product output is read once, pair fastest, then
     // row, then mode: a wave reads whole 128-byte rows of one mode (coalesced); the
     // mirrored half of the spectrum (m > Nz/2) is written from the same values.
-    for (int t = threadIdx.x; t < nm * tr * pp; t += NT) {
+    // The first K slice's loads are issued for LU iterations before any is used.
+    constexpr int LU = 4;
+    const int nload = nm * tr * pp;
+    for (int t0 = threadIdx.x; t0 < nload; t0 += NT * LU) {
+    double2 pv0[LU], pv1[LU];
+#pragma unroll
+    for (int q = 0; q < LU; ++q) {
+        const int t = t0 + q * NT;
+        const int pj = t % pp;
+        const int rest = t / pp;
+        const int trr = rest % tr, mm = rest / tr;
+        const int row = row0 + trr;
+        const int ja = 2 * (pair0 + pj);
+        pv0[q] = pv1[q] = make_double2(0, 0);
+        if (t < nload && row < M) {
+            const double* src = c + mm * mode_stride + ((int64_t)tile * mp + row) * 16;
+            pv0[q] = *(const double2*)(src + ja);
+            pv1[q] = *(const double2*)(src + ja + 8);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < LU; ++q) {
+        const int t = t0 + q * NT;
+        if (t >= nload) break;
         const int pj = t % pp;
         const int rest = t / pp;
         const int trr = rest % tr, mm = rest / tr;
@@ -342,7 +365,7 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
         double2 z = make_double2(0, 0), zc = make_double2(0, 0);
         if (row < M) {
             const double* src = c + mm * mode_stride + ((int64_t)tile * mp + row) * 16;
-            const double2 v0 = *(const double2*)(src + ja), v1 = *(const double2*)(src + ja + 8);
+            const double2 v0 = pv0[q], v1 = pv1[q];
             double ar = v0.x, br = v0.y, ai = v1.x, bi = v1.y;
             for (int ks = 1; ks < nsplit; ++ks) {      // K slices, summed in fixed order
                 const double* q = src + ks * split_stride;
@@ -383,6 +406,7 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
         }
         lds[s * nz + bitrev(mm, logn)] = z;
         if (mm > 0 && 2 * mm < nz) lds[s * nz + bitrev(nz - mm, logn)] = zc;
+    }
     }
     __syncthreads();
     lds_fft(lds, nseq, logn, tw, true);
