@@ -426,7 +426,8 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 // been written to LDS, so their latency hides behind the MFMAs of chunk i.  jb.ct_active
 // column tiles carry RHS of this cell; the others are skipped.
 template <int CT>
-__global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ jobs,
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
+k_gemm_dtab(const GemmJob* __restrict__ jobs,
                                                    const double2* __restrict__ tab, int64_t a_base,
                                                    const double* __restrict__ B,
                                                    double* __restrict__ C,
@@ -434,7 +435,9 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
                                                    const int32_t* __restrict__ lut, int d1min,
                                                    int d2min, int w2) {
     __shared__ double As[6 * 6 * 128];          // [rb][p][lane][2]
-    __shared__ double Bs[CT * 6 * 128];         // [ct][p][lane][2]
+    // CT <= 2: each wave keeps the chunk's B fragments in registers (no LDS, so four work
+    // groups fit per CU); more tiles are staged in LDS once for both waves
+    __shared__ double Bs[(CT <= 2 ? 1 : CT * 6 * 128)];   // [ct][p][lane][2]
     __shared__ int scb[2 * DT_TB];
     const GemmJob jb = jobs[blockIdx.x];
     if (jb.mb == 0) return;
@@ -456,9 +459,9 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[r][c] = (d4_t){0, 0, 0, 0};
     __syncthreads();
-    constexpr int VB = (CT <= 2) ? 6 * CT : 1;   // B prefetched in registers for CT <= 2
     double2 va[2][6];
-    double vb[VB];
+    double2 vb[CT <= 2 ? 6 : 1][CT <= 2 ? CT : 1];    // next chunk's B fragments (CT <= 2)
+    double2 bcur[CT <= 2 ? 6 : 1][CT <= 2 ? CT : 1];  // this chunk's
     auto prefetch = [&](int i0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -479,11 +482,11 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
         if constexpr (CT <= 2) {
             const int p0 = (6 * i0) >> 3;
 #pragma unroll
-            for (int j = 0; j < 6 * CT; ++j) {
-                const int e = tid + 128 * j;
-                const int ct = e / 768, x = e - ct * 768;
-                vb[j] = (ct < nca) ? bm[((int64_t)ct * kp8 + p0) * 128 + x] : 0.0;
-            }
+            for (int p = 0; p < 6; ++p)
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    vb[p][c] = (c < nca) ? *(const double2*)&bm[((int64_t)c * kp8 + p0 + p) * 128 + 2 * lane]
+                                         : make_double2(0.0, 0.0);
         }
     };
     prefetch(jb.k0);
@@ -505,7 +508,9 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
         }
         if constexpr (CT <= 2) {
 #pragma unroll
-            for (int j = 0; j < 6 * CT; ++j) Bs[tid + 128 * j] = vb[j];
+            for (int p = 0; p < 6; ++p)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) bcur[p][c] = vb[p][c];
         } else {
             const int p0 = (6 * i0) >> 3;
             for (int e = tid; e < CT * 768; e += 128) {
@@ -521,7 +526,10 @@ __global__ void __launch_bounds__(128) k_gemm_dtab(const GemmJob* __restrict__ j
 #pragma unroll
             for (int r = 0; r < 3; ++r) av[r] = *(const double2*)&As[((3 * wave + r) * 6 + p) * 128 + 2 * lane];
 #pragma unroll
-            for (int c = 0; c < CT; ++c) bv[c] = *(const double2*)&Bs[(c * 6 + p) * 128 + 2 * lane];
+            for (int c = 0; c < CT; ++c) {
+                if constexpr (CT <= 2) bv[c] = bcur[p][c];
+                else bv[c] = *(const double2*)&Bs[(c * 6 + p) * 128 + 2 * lane];
+            }
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
