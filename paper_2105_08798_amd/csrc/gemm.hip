@@ -434,7 +434,10 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
                                                    const CellDev* __restrict__ cells,
                                                    const int32_t* __restrict__ lut, int d1min,
                                                    int d2min, int w2) {
-    __shared__ double As[6 * 6 * 128];          // [rb][p][lane][2]
+    // A chunk in natural order [row][k'] with an odd row stride: the gathering threads'
+    // 8-byte writes and the MFMA lanes' 8-byte reads both fall into distinct banks
+    constexpr int AS = 49;
+    __shared__ double As[96 * AS];
     // CT <= 2: each wave keeps the chunk's B fragments in registers (no LDS, so four work
     // groups fit per CU); more tiles are staged in LDS once for both waves
     __shared__ double Bs[(CT <= 2 ? 1 : CT * 6 * 128)];   // [ct][p][lane][2]
@@ -502,8 +505,8 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
                 for (int d = 0; d < 3; ++d) {
                     const double2 x = va[h][sym_idx(c, d)];
                     const int row = 3 * bl + c, kq = 6 * il + 2 * d;
-                    As[frag_off_f64(row, kq, 48)] = x.x;
-                    As[frag_off_f64(row, kq + 1, 48)] = x.y;
+                    As[row * AS + kq] = x.x;
+                    As[row * AS + kq + 1] = x.y;
                 }
         }
         if constexpr (CT <= 2) {
@@ -524,7 +527,11 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
         for (int p = 0; p < 6; ++p) {
             double2 av[3], bv[CT];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) av[r] = *(const double2*)&As[((3 * wave + r) * 6 + p) * 128 + 2 * lane];
+            for (int r = 0; r < 3; ++r) {
+                // lane l holds A[16 rb + l%16][8 p + 4 h + l/16], h = 0, 1 (FP64 16x16x4 order)
+                const double* ap = &As[(16 * (3 * wave + r) + (lane & 15)) * AS + 8 * p + (lane >> 4)];
+                av[r] = make_double2(ap[0], ap[4]);
+            }
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 if constexpr (CT <= 2) bv[c] = bcur[p][c];
