@@ -186,6 +186,8 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
         gemm_ms, n_gemm = ctx.timing_read()
     ctx.timing(False)
     store_bytes = ctx.info.store_bytes
+    prod = dict(bytes=ctx.info.product_bytes, flops=ctx.info.product_flops,
+                skipped_fraction=ctx.info.skipped_fraction)
     rc = ctx.sync_status(stream=stream)
     if rc != 0:
         raise RuntimeError(f"{form}: status {rc} after the timed region")
@@ -203,7 +205,7 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     out = dict(ms_per_step=ms, updates_per_s=total_rhs / (ms / 1000.0), assembly_s=t_asm,
                store_bytes=int(store_bytes), autotune=tuned,
                gemm_ms=(gemm_ms / n_gemm) if n_gemm else None, gemm_launches_timed=n_gemm,
-               graph=bool(graph), surrogate_training=sur_info)
+               graph=bool(graph), surrogate_training=sur_info, product=prod)
     log(f"{form}: {ms:.3f} ms/step, GEMM {out['gemm_ms']} ms, {out['updates_per_s']:.1f} updates/s")
     return out, w_host
 
@@ -323,6 +325,10 @@ def main() -> int:
     out_forms = {}
     for form, r in res.items():
         alg = algorithmic(wl.cells, form, r["store_bytes"])
+        if r.get("product") and r["product"]["bytes"] > 0:
+            # the library's count over the blocks it does not skip (negligible-block windows)
+            alg["gemm_bytes"] = r["product"]["bytes"]
+            alg["gemm_flops"] = r["product"]["flops"]
         e_fp64 = None
         if ref_w is not None and form != ref_form:
             e_fp64 = max(rel_err(cell_view(wl, r["w"], k), cell_view(wl, ref_w, k)) for k in range(len(wl.cells)))
@@ -342,7 +348,9 @@ def main() -> int:
             call_GBs=alg["call_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9,
             rel_err_vs_fp64_gpu=e_fp64, rel_err_reference=ref_form, rel_err_vs_oracle_samples=e_or,
             assembly_s=r["assembly_s"], graph=r["graph"], store_GB=r["store_bytes"] / 1e9,
-            autotune=r["autotune"], surrogate_training=r["surrogate_training"])
+            autotune=r["autotune"], surrogate_training=r["surrogate_training"],
+            skipped_fraction=r["product"]["skipped_fraction"], product_bytes=alg["gemm_bytes"],
+            product_flops=alg["gemm_flops"])
     def err_of(f):
         e = out_forms[f]["rel_err_vs_oracle_samples"]
         if e is None:
@@ -353,7 +361,7 @@ def main() -> int:
     ok = [f for f in out_forms if f in ("fp64", "dtable_fp64") or (err_of(f) is not None and err_of(f) <= 1e-6)]
     head = max(ok, key=lambda f: out_forms[f]["updates_per_s"]) if ok else forms[0]
     h = out_forms[head]
-    alg = algorithmic(wl.cells, head, res[head]["store_bytes"])
+    alg = dict(gemm_bytes=h["product_bytes"], gemm_flops=h["product_flops"])
     traffic = measured_traffic(args.workload, head)
     roof = dict(bound="hbm", achieved=h["gemm_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=h["gemm_hbm_frac"], traffic=traffic, kernel=f"k_gemm ({head})",

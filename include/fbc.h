@@ -132,10 +132,18 @@ typedef struct {
                                 outlive the context and keep its MLP weights); else NULL */
     int gen_modes;           /* FBC_FORM_SURROGATE: table modes generated per chunk
                                 (>= 0; 0: as many as fit in 2 GiB of scratch)            */
+    double skip_tol;         /* negligible blocks: at line mode m the product skips the
+                                K chunks of a row tile whose blocks all lie farther than
+                                the farthest offset with |G^(m)| >= skip_tol * max |G^(m)|
+                                (the line-mode Green function decays with kappa rho).
+                                0: default (1e-16 for the FP64 forms, below the rounding
+                                of their assembly; 1e-12 for the reduced forms, below
+                                their rounding; the surrogate skips exactly its zero
+                                blocks, kappa rho > 40); < 0: no skipping               */
 } fbc_options;
 
 /* Fills *opt with defaults: FP64, 1024 x 1024 torus, check on, no projection, tol 1e-10,
- * row_gauge on, no surrogate. */
+ * row_gauge on, no surrogate, default skip tolerance. */
 void fbc_default_options(fbc_options* opt);
 
 /* Assembles G^(m) for m = 0..N_z/2 of every cell on the device (Appendix B, discrete
@@ -216,6 +224,12 @@ typedef struct {
     int nsplit;                /* K slices of the per-mode product launch                 */
     int job_order;             /* work-list order (see fbc_autotune)                      */
     int n_jobs;                /* work groups of the per-mode product launch              */
+    double product_bytes;      /* HBM bytes one product launch must read and write: the
+                                  stored blocks of the K chunks it does not skip (dense
+                                  forms) or the table (offset forms), plus f^ and w^    */
+    double product_flops;      /* real flops of the blocks it does not skip (8 per
+                                  complex multiply-add)                                 */
+    double skipped_fraction;   /* fraction of the (row, K) block area skipped             */
 } fbc_info;
 fbc_status fbc_get_info(const fbc_ctx* ctx, fbc_info* info);
 

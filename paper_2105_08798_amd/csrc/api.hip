@@ -220,6 +220,107 @@ static OffsetSet offsets_of(const std::vector<CellPlan>& cells) {
     return o;
 }
 
+// ----------------------------------------------------------------------------------
+// Negligible-block windows.  At line mode m the Green function decays with kappa rho;
+// rho_cut[t] is the farthest in-plane distance (table mode t) of a block that reaches the
+// skip tolerance.  A K chunk of a row tile is negligible when all its (pad, interface)
+// pairs lie farther than that; the product then runs, per (mode, tile), over the cyclic
+// window of chunks that contains every non-negligible one.
+// ----------------------------------------------------------------------------------
+static double pair_rho(int32_t a1, int32_t a2, int32_t b1, int32_t b2) {
+    const int d1 = a1 - b1, d2 = a2 - b2;
+    const double x = 0.5 * d1, y = (d1 + 2.0 * d2) * (0.5 * M_SQRT1_2);
+    return std::sqrt(x * x + y * y);
+}
+
+static double skip_tolerance(const fbc_options& o) {
+    if (o.skip_tol < 0) return -1.0;
+    if (o.skip_tol > 0) return o.skip_tol;
+    return (o.form == FBC_FORM_FP32 || o.form == FBC_FORM_SPLIT_BF16 || o.form == FBC_FORM_SPLIT_FP16) ? 1e-12
+                                                                                                    : 1e-16;
+}
+
+static void compute_windows(fbc_ctx* c, const std::vector<double>& rho_cut, int rows_tile) {
+    const bool dt = is_table_form(c->opt.form);
+    for (CellPlan& p : c->cells) {
+        const int mult = c->nz_max / p.nz;
+        p.n_tiles = dt ? p.mp / 96 : p.mp / rows_tile;
+        p.n_chunks = dt ? (p.n_i + 7) / 8 : p.kp / 64;
+        const int NT_ = p.n_tiles, NC = p.n_chunks;
+        // pad columns of a tile and interface columns of a chunk
+        auto tile_cols = [&](int tl, int& b0, int& b1) {
+            if (dt) { b0 = 32 * tl; b1 = std::min(p.n_b, b0 + 32); }
+            else { b0 = (tl * rows_tile) / 3; b1 = std::min(p.n_b, ((tl + 1) * rows_tile + 2) / 3); }
+        };
+        auto chunk_cols = [&](int ch, int& i0, int& i1) {
+            if (dt) { i0 = 8 * ch; i1 = std::min(p.n_i, i0 + 8); }
+            else { i0 = (32 * ch) / 3; i1 = std::min(p.n_i, (32 * (ch + 1) + 2) / 3); }
+        };
+        std::vector<float> rmin((size_t)NT_ * NC, INFINITY);
+        std::vector<uint8_t> real_chunk(NC, 0);
+        for (int ch = 0; ch < NC; ++ch) {
+            int i0, i1;
+            chunk_cols(ch, i0, i1);
+            real_chunk[ch] = i0 < i1;
+        }
+        for (int tl = 0; tl < NT_; ++tl) {
+            int b0, b1;
+            tile_cols(tl, b0, b1);
+            for (int b = b0; b < b1; ++b) {
+                const int32_t a1 = p.cols_b[2 * b], a2 = p.cols_b[2 * b + 1];
+                for (int ch = 0; ch < NC; ++ch) {
+                    int i0, i1;
+                    chunk_cols(ch, i0, i1);
+                    float& r = rmin[(size_t)tl * NC + ch];
+                    for (int i = i0; i < i1; ++i)
+                        r = std::min(r, (float)pair_rho(a1, a2, p.cols_i[2 * i], p.cols_i[2 * i + 1]));
+                }
+            }
+        }
+        p.win_start.assign((size_t)p.nm * NT_, 0);
+        p.win_len.assign((size_t)p.nm * NT_, NC);
+        p.mode_skips.assign(p.nm, 0);
+        std::vector<uint8_t> neg(NC);
+        for (int m = 0; m < p.nm; ++m) {
+            const double rc = rho_cut[(size_t)m * mult];
+            for (int tl = 0; tl < NT_; ++tl) {
+                int b0, b1;
+                tile_cols(tl, b0, b1);
+                int nneg = 0;
+                for (int ch = 0; ch < NC; ++ch) {
+                    // (float) rmin rounds; a 1e-6 relative margin keeps the test on the safe side
+                    neg[ch] = (double)rmin[(size_t)tl * NC + ch] > rc * (1.0 + 1e-6) + 1e-6;
+                    nneg += neg[ch];
+                }
+                int start = 0, len = NC;
+                if (nneg == NC) {
+                    len = 0;
+                } else if (nneg > 0) {
+                    // longest cyclic run of negligible chunks
+                    int best = 0, best_end = 0, run = 0;
+                    for (int q = 0; q < 2 * NC; ++q) {
+                        if (neg[q % NC]) {
+                            ++run;
+                            if (run > best && run <= NC) { best = run; best_end = q; }
+                        } else {
+                            run = 0;
+                        }
+                    }
+                    start = (best_end + 1) % NC;
+                    len = NC - best;
+                }
+                p.win_start[(size_t)m * NT_ + tl] = start;
+                p.win_len[(size_t)m * NT_ + tl] = len;
+                if (b0 < b1 && len < NC)
+                    for (int ch = 0; ch < NC; ++ch) {
+                        const bool in = ((ch - start + NC) % NC) < len;
+                        if (!in && real_chunk[ch]) p.mode_skips[m] = 1;
+                    }
+            }
+        }
+    }
+}
+
 // Builds the offset table tab[t][o][6] for every line mode t = 0..nz_max/2 of the finest
 // line grid of the context (a cell with Nz layers reads table mode m * nz_max / Nz, the
 // same wavenumber), then either fills the dense stores of every cell and frees the
@@ -270,6 +371,7 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
             }
             need[t] = (int32_t)lo;
         }
+        c->n_need_h = need;
         fbc_status s0;
         if ((s0 = dev_alloc(c, (void**)&c->n_need, (int64_t)T0 * 4)) != FBC_OK) return s0;
         HIPCHK(c, hipMemcpyAsync(c->n_need, need.data(), (size_t)T0 * 4, hipMemcpyHostToDevice, st));
@@ -364,6 +466,35 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         }
     }
     HIPCHK(c, hipGetLastError());
+    {
+        // distance cut-off per table mode, then the windows of every cell
+        std::vector<double> rho_cut(T, INFINITY);
+        const double tau = skip_tolerance(c->opt);
+        if (sur) {
+            if (tau >= 0)
+                for (int t = 1; t < T; ++t) {
+                    const double kap = 2.0 * M_PI * ((double)t / c->nz_max) * M_SQRT2;
+                    rho_cut[t] = std::max(c->sur->r_c, c->sur->k.s_max / kap);   // zero beyond
+                }
+        } else if (tau >= 0) {
+            unsigned long long* st2;
+            if ((s = talloc((void**)&st2, (int64_t)T * 16)) != FBC_OK) {
+                cleanup();
+                return s;
+            }
+            launch_tab_rhocut(st, c->tab, T, n_off, d1_d, d2_d, tau, st2, st2 + T);
+            std::vector<unsigned long long> bits(T);
+            HIPCHK(c, hipMemcpyAsync(bits.data(), st2 + T, (size_t)T * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            for (int t = 0; t < T; ++t) {
+                double v;
+                std::memcpy(&v, &bits[t], 8);
+                rho_cut[t] = v;
+            }
+        }
+        const int rows_tile = 64 * gemm_rb(form, c->ctmax);
+        compute_windows(c, rho_cut, rows_tile);
+    }
     if (sur) {
         if ((s = dev_alloc(c, (void**)&c->cmatch, 64)) != FBC_OK) {
             cleanup();
@@ -416,6 +547,11 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
                 rowmean = c->rowmean + c->rowmean_off[ci];
                 launch_rowmean(st, c->tab, rowmean, p.nm, mult, n_off, p.n_b, p.n_i, p.cols_b_d,
                                p.cols_i_d, c->lut, os.d1min, os.d2min, os.w2);
+                // no row gauge where chunks are skipped: the skipped blocks would otherwise
+                // drop their share of the row mean
+                for (int m = 0; m < p.nm; ++m)
+                    if (p.mode_skips[m])
+                        HIPCHK(c, hipMemsetAsync(rowmean + (int64_t)m * p.n_b * 6, 0, (size_t)p.n_b * 6 * 16, st));
             }
             char* base = (char*)c->store + p.a_off * store_elem_bytes(form);
             launch_build_dense(st, form, base, c->tab, rowmean, p.nm, mult, n_off, p.mp, p.kp, p.n_b,
@@ -428,6 +564,44 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
     HIPCHK(c, hipStreamSynchronize(st));
     cleanup();
     return FBC_OK;
+}
+
+// Algorithmic bytes and flops of one product launch over the non-skipped blocks.
+static void product_stats(fbc_ctx* c) {
+    const int form = c->opt.form;
+    const bool dt = is_table_form(form);
+    const int rows_tile = dt ? 96 : 64 * gemm_rb(form, c->ctmax);
+    const double eb = (form == FBC_FORM_FP64) ? 8.0 : 4.0;       // stored bytes per real entry
+    const double fb = (form == FBC_FORM_FP64 || dt) ? 16.0 : 8.0; // bytes per complex f^
+    double bytes = 0, flops = 0, area = 0, kept = 0;
+    for (const CellPlan& p : c->cells) {
+        for (int m = 0; m < p.nm; ++m) {
+            bytes += (double)p.R * p.K * fb + (double)p.R * p.M * 16.0;      // f^ in, w^ out
+            for (int tl = 0; tl < p.n_tiles; ++tl) {
+                const double rows = std::max(0, std::min(p.M, (tl + 1) * rows_tile) - tl * rows_tile);
+                const int ws = p.win_start[(size_t)m * p.n_tiles + tl];
+                const int wl = p.win_len[(size_t)m * p.n_tiles + tl];
+                for (int ch = 0; ch < p.n_chunks; ++ch) {
+                    const double kc = dt ? 3.0 * std::max(0, std::min(p.n_i, 8 * (ch + 1)) - 8 * ch)
+                                         : (double)std::max(0, std::min(p.K, 32 * (ch + 1)) - 32 * ch);
+                    area += rows * kc;
+                    if (((ch - ws + p.n_chunks) % p.n_chunks) < wl) {
+                        kept += rows * kc;
+                        flops += 8.0 * rows * kc * p.R;
+                        if (!dt) bytes += (double)rows_tile * 64.0 * eb;
+                    }
+                }
+            }
+        }
+    }
+    if (form == FBC_FORM_SURROGATE) {
+        for (int t : c->n_need_h) bytes += t * 96.0;     // generated slices, read once
+    } else if (dt) {
+        bytes += (double)c->store_bytes;
+    }
+    c->product_bytes = bytes;
+    c->product_flops = flops;
+    c->skipped_fraction = area > 0 ? 1.0 - kept / area : 0.0;
 }
 
 // ----------------------------------------------------------------------------------
@@ -450,10 +624,13 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
     const bool dt = is_table_form(form);
     const int tile_rows = dt ? 96 : 64 * gemm_rb(form, c->ctmax);
     const int tiles = p.mp / tile_rows;
-    const int nch = dt ? (p.n_i + 7) / 8 : p.kp / 64;
     const int unit_k = dt ? 8 : 64;
     for (int ks = 0; ks < nsplit; ++ks)
         for (int tl = 0; tl < tiles; ++tl) {
+            // the K slice ks of this tile's window (cyclic; empty slices write zeros)
+            const int ws = p.win_start[(size_t)u.m * p.n_tiles + tl];
+            const int wl = p.win_len[(size_t)u.m * p.n_tiles + tl];
+            const int a = (int)((int64_t)wl * ks / nsplit), e = (int)((int64_t)wl * (ks + 1) / nsplit);
             GemmJob j{};
             j.a_off = dt ? (int64_t)u.t * c->n_offsets * 6 : p.a_off + (int64_t)u.m * store_mode_elems(form, p);
             j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
@@ -463,8 +640,8 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
             j.rb0 = tl * (tile_rows / 16);
             j.ct = p.ct;
             j.cell = u.cell;
-            j.k0 = unit_k * (int)((int64_t)nch * ks / nsplit);
-            j.k1 = unit_k * (int)((int64_t)nch * (ks + 1) / nsplit);
+            j.k0 = (a == e) ? 0 : unit_k * (ws + a);
+            j.k1 = (a == e) ? 0 : unit_k * (ws + e);
             j.ct_active = p.ctr;
             out.push_back(j);
         }
@@ -476,8 +653,13 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) 
     for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
         const CellPlan& p = c->cells[ci];
         const int mult = c->nz_max / p.nz;
-        const int64_t cost = (int64_t)p.mp * (dt ? 6 * ((p.n_i + 7) / 8) : p.kp);
-        for (int m = 0; m < p.nm; ++m) units.push_back({ci, m, m * mult, cost});
+        const int64_t tile_rows = dt ? 96 : 64 * gemm_rb(c->opt.form, c->ctmax);
+        const int64_t unit_k = dt ? 48 : 64;
+        for (int m = 0; m < p.nm; ++m) {
+            int64_t cost = 0;
+            for (int tl = 0; tl < p.n_tiles; ++tl) cost += p.win_len[(size_t)m * p.n_tiles + tl];
+            units.push_back({ci, m, m * mult, cost * tile_rows * unit_k});
+        }
     }
     std::vector<GemmJob> out;
     if (order == 1) {
@@ -757,6 +939,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         (void)hipStreamSynchronize(st);
         (void)hipFree(sn_d);
     }
+    product_stats(c);
     if (form == FBC_FORM_SURROGATE) c->nsplit = 1;     // slices are generated per mode chunk
     if ((s = upload_jobs(c, c->nsplit, is_table_form(form) ? 1 : 0, st)) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->fprev, c->f_elems * 8)) != FBC_OK) goto fail_out;
@@ -804,16 +987,19 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
         for (size_t ch = 0; ch + 1 < c->chunk_job0.size(); ++ch) {
             const int t0 = (int)ch * c->gen_modes;
             const int nt = std::min(c->gen_modes, T - t0);
+            int64_t max_need = 0;
+            for (int t = t0; t < t0 + nt; ++t) max_need = std::max<int64_t>(max_need, c->n_need_h[t]);
             launch_sur_generate(st, sv->view(), sv->wb, sv->bias, sv->r_c, sv->env_floor, c->nz_max, t0, nt,
                                 c->near_tab, c->n_near, c->n_offsets, c->n_need, c->off_d1, c->off_d2,
-                                c->cmatch, c->gen);
+                                c->cmatch, c->gen, max_need);
             const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
             launch_gemm_dtab(st, c->jobs + j0, j1 - j0, c->ctmax, c->gen, (int64_t)t0 * c->n_offsets * 6,
-                             (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2);
+                             (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2,
+                             c->n_need, c->n_offsets);
         }
     } else if (form == FBC_FORM_DTABLE_FP64)
         launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, 0, (const double*)c->bfrag, c->cbuf,
-                         c->celldev, c->lut, c->d1min, c->d2min, c->w2);
+                         c->celldev, c->lut, c->d1min, c->d2min, c->w2, nullptr, c->n_offsets);
     else
         launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf);
     if (tm) {
@@ -1014,6 +1200,9 @@ extern "C" fbc_status fbc_get_info(const fbc_ctx* c, fbc_info* info) {
     info->nsplit = c->nsplit;
     info->job_order = c->job_order;
     info->n_jobs = c->njobs;
+    info->product_bytes = c->product_bytes;
+    info->product_flops = c->product_flops;
+    info->skipped_fraction = c->skipped_fraction;
     return FBC_OK;
 }
 

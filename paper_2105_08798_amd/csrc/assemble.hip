@@ -336,6 +336,49 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (i < n) p[i] = 0ull;
 }
 
+// Per table mode t: the largest in-plane distance of an offset whose block reaches
+// tau * amax[t] (bit pattern of a non-negative double, atomic max).  Blocks of offsets
+// farther than that are below the tolerance in this mode.
+__global__ void __launch_bounds__(256) k_tab_rhocut(const double2* __restrict__ tab, int64_t n_off,
+                                                    const int32_t* __restrict__ d1,
+                                                    const int32_t* __restrict__ d2, double tau,
+                                                    const unsigned long long* __restrict__ amax,
+                                                    unsigned long long* __restrict__ rhocut) {
+    __shared__ double red[256];
+    const int t = blockIdx.y;
+    const double thr = tau * __longlong_as_double((long long)amax[t]);
+    const double2* tm = tab + (int64_t)t * n_off * 6;
+    double mx = 0.0;
+    for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n_off; o += (int64_t)gridDim.x * 256) {
+        double g = 0.0;
+        for (int c = 0; c < 6; ++c) g = fmax(g, fmax(fabs(tm[o * 6 + c].x), fabs(tm[o * 6 + c].y)));
+        if (g >= thr) {
+            const double x = 0.5 * d1[o], y = (d1[o] + 2.0 * d2[o]) * (0.5 * M_SQRT1_2);
+            mx = fmax(mx, sqrt(x * x + y * y));
+        }
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(rhocut + t, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+void launch_tab_rhocut(hipStream_t st, const double2* tab, int T, int64_t n_off, const int32_t* d1,
+                       const int32_t* d2, double tau, unsigned long long* amax,
+                       unsigned long long* rhocut) {
+    hipLaunchKernelGGL(k_zero_u64, dim3((T + 255) / 256), dim3(256), 0, st, amax, T);
+    hipLaunchKernelGGL(k_zero_u64, dim3((T + 255) / 256), dim3(256), 0, st, rhocut, T);
+    const int sl = (int)std::min<int64_t>(64, (n_off * 6 + 255) / 256);
+    hipLaunchKernelGGL(k_tab_absmax, dim3(sl, T), dim3(256), 0, st, tab, 1, n_off, amax);
+    const int sl2 = (int)std::min<int64_t>(64, (n_off + 255) / 256);
+    hipLaunchKernelGGL(k_tab_rhocut, dim3(sl2, T), dim3(256), 0, st, tab, n_off, d1, d2, tau, amax, rhocut);
+}
+
+
+
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
                         const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
                         int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <cstdint>
 #include <vector>
 
 #include "../../include/fbc.h"
@@ -80,9 +81,15 @@ struct GemmJob {
     int32_t rb0;     // first row block of this tile
     int32_t ct;      // column tiles (8 RHS each)
     int32_t cell;    // cell index (offset form)
-    int32_t k0, k1;  // K' slice [k0, k1) (dense forms) or interface columns [k0, k1)
+    // K' range [k0, k1) (dense forms) or interface columns [k0, k1) (offset forms); the
+    // range is cyclic: indices at or beyond the padded K wrap to its start (windows around
+    // the non-negligible blocks of a tile may straddle the end); k0 == k1: empty (zeros)
+    int32_t k0, k1;
     int32_t ct_active;  // column tiles holding RHS of this cell (offset form skips the rest)
 };
+
+// Physical index of a step of a cyclic K range (idx < 2 n).
+__host__ __device__ inline int wrap_k(int idx, int n) { return idx >= n ? idx - n : idx; }
 
 // Per-cell device view used by the offset-table product kernel.
 struct CellDev {
@@ -114,4 +121,9 @@ struct CellPlan {
     int64_t tw_off;              // twiddle table offset (double2) for nz
     int32_t *cols_i_d, *cols_b_d;
     std::vector<int32_t> cols_i, cols_b;
+    // Negligible-block windows: per (mode, row tile) the cyclic range of K chunks that
+    // holds every block above the skip tolerance [win_start, win_start + win_len).
+    int n_tiles = 0, n_chunks = 0;
+    std::vector<int32_t> win_start, win_len;   // [nm][n_tiles]
+    std::vector<uint8_t> mode_skips;           // [nm]: some chunk of this mode is skipped
 };

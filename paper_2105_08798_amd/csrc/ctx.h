@@ -49,6 +49,7 @@ struct fbc_ctx {
     double g_alpha = 0.0;
     void* g_stream = nullptr;
     int64_t scratch_bytes = 0;
+    double product_bytes = 0, product_flops = 0, skipped_fraction = 0;   // see fbc_info
     int64_t n_offsets = 0;
     // offset table (kept for the offset-table form)
     int nz_max = 0;
@@ -63,6 +64,7 @@ struct fbc_ctx {
     int32_t* off_d1 = nullptr;       // device offsets in table order
     int32_t* off_d2 = nullptr;
     int32_t* n_need = nullptr;       // per table mode: offsets to generate (prefix)
+    std::vector<int32_t> n_need_h;   // host copy
     double2* gen = nullptr;          // generated slices [chunk modes][n_off][6]
     int gen_modes = 0;               // table modes per generated chunk
     std::vector<int> chunk_job0;     // first job of each chunk (jobs sorted by table mode)

@@ -10,6 +10,8 @@
 // mode and stay in L2 because the job list gives all tiles of a mode to one XCD.
 // Each work group is 4 waves; a wave owns RB row blocks (16 rows each) of one mode and
 // all column tiles of that mode, over the whole K.  Loads run PF steps ahead.
+#include <cstdint>
+
 #include "kernels.h"
 
 static __device__ inline void store_c_f64(double* __restrict__ c, const GemmJob& jb, int rb,
@@ -57,13 +59,21 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[r][c] = (d4_t){0, 0, 0, 0};
+    if (pe <= pb) {              // empty K slice: its partial output is zero
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) store_c_f64(C, jb, rbw + r, c, lane, acc[r][c]);
+        return;
+    }
     double2 ab[PF][RB], bb[PF][CT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
+        const int pw = wrap_k(pb + u, kp8);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = a[((pb + u) * mb + r) * 64];
+        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)pw * mb + r) * 64];
 #pragma unroll
-        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pb + u) * 64];
+        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pw) * 64];
     }
     for (int p0 = pb; p0 < pe; p0 += PF) {
 #pragma unroll
@@ -76,7 +86,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
                     for (int c = 0; c < CT; ++c)
                         acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                             h ? ab[u][r].y : ab[u][r].x, h ? bb[u][c].y : bb[u][c].x, acc[r][c], 0, 0, 0);
-            const int pn = min(p0 + u + PF, pe - 1);
+            const int pn = wrap_k(min(p0 + u + PF, pe - 1), kp8);
 #pragma unroll
             for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)pn * mb + r) * 64];
 #pragma unroll
@@ -114,13 +124,21 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
             acc[r][c] = (d4_t){0, 0, 0, 0};
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
+    if (qe <= qb) {              // empty K slice: its partial output is zero
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+        return;
+    }
     float4 ab[PF][RB], bb[PF][CT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
+        const int qw = wrap_k(qb + u, kq);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = a[((qb + u) * mb + r) * 64];
+        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)qw * mb + r) * 64];
 #pragma unroll
-        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qb + u) * 64];
+        for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qw) * 64];
     }
     for (int q0 = qb; q0 < qe; q0 += PF) {
 #pragma unroll
@@ -135,7 +153,7 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
                         const float bv = h == 0 ? bb[u][c].x : h == 1 ? bb[u][c].y : h == 2 ? bb[u][c].z : bb[u][c].w;
                         ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, ac32[r][c], 0, 0, 0);
                     }
-            const int qn = min(q0 + u + PF, qe - 1);
+            const int qn = wrap_k(min(q0 + u + PF, qe - 1), kq);
 #pragma unroll
             for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)qn * mb + r) * 64];
 #pragma unroll
@@ -194,18 +212,26 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
             acc[r][c] = (d4_t){0, 0, 0, 0};
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
+    if (te <= tb) {              // empty K slice: its partial output is zero
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+        return;
+    }
     VT ah[PF][RB], al[PF][RB], bh[PF][CT], bl[PF][CT];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
+        const int tw = wrap_k(tb + u, kt);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = a[((tb + u) * mb + r) * 128];
-            al[u][r] = a[((tb + u) * mb + r) * 128 + 64];
+            ah[u][r] = a[((int64_t)tw * mb + r) * 128];
+            al[u][r] = a[((int64_t)tw * mb + r) * 128 + 64];
         }
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-            bh[u][c] = b[((int64_t)c * kt + tb + u) * 128];
-            bl[u][c] = b[((int64_t)c * kt + tb + u) * 128 + 64];
+            bh[u][c] = b[((int64_t)c * kt + tw) * 128];
+            bl[u][c] = b[((int64_t)c * kt + tw) * 128 + 64];
         }
     }
     for (int t0 = tb; t0 < te; t0 += PF) {
@@ -226,7 +252,7 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
                     ac32[r][c] = mfma_16x16x32(ah[u][r], bh[u][c], ac32[r][c]);
-            const int tn = min(t0 + u + PF, te - 1);
+            const int tn = wrap_k(min(t0 + u + PF, te - 1), kt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 ah[u][r] = a[((int64_t)tn * mb + r) * 128];
@@ -290,21 +316,29 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
         }
     VT stage[NU];
     auto load_b = [&](int t) {
+        const int tw = wrap_k(t, kt);
 #pragma unroll
         for (int j = 0; j < NU; ++j) {
             const int u = tid + 256 * j, c = u >> 7, rem = u & 127;
-            stage[j] = b[((int64_t)c * kt + t) * 128 + rem];
+            stage[j] = b[((int64_t)c * kt + tw) * 128 + rem];
         }
     };
     auto store_b = [&](int buf) {
 #pragma unroll
         for (int j = 0; j < NU; ++j) bs[buf][tid + 256 * j] = stage[j];
     };
+    if (te <= tb) {              // empty K slice: its partial output is zero
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+        return;
+    }
     // A ring: PFA steps in flight per wave (memory-level parallelism for HBM latency)
     VT ah[PFA][RB], al[PFA][RB];
 #pragma unroll
     for (int u = 0; u < PFA; ++u) {
-        const int tl = min(tb + u, te - 1);
+        const int tl = wrap_k(min(tb + u, te - 1), kt);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             ah[u][r] = a[((int64_t)tl * mb + r) * 128];
@@ -344,7 +378,7 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
                     ac32[r][c + 1] = mfma_16x16x32(ah[u][r], bh1, ac32[r][c + 1]);
                 }
             }
-            const int tn = min(t + PFA, te - 1);
+            const int tn = wrap_k(min(t + PFA, te - 1), kt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 ah[u][r] = a[((int64_t)tn * mb + r) * 128];
@@ -433,7 +467,8 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
                                                    double* __restrict__ C,
                                                    const CellDev* __restrict__ cells,
                                                    const int32_t* __restrict__ lut, int d1min,
-                                                   int d2min, int w2) {
+                                                   int d2min, int w2,
+                                                   const int32_t* __restrict__ need, int64_t n_off) {
     // A chunk in natural order [row][k'] with an odd row stride: the gathering threads'
     // 8-byte writes and the MFMA lanes' 8-byte reads both fall into distinct banks
     constexpr int AS = 49;
@@ -454,6 +489,9 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
         scb[2 * tid + 1] = b < cd.n_b ? cd.cols_b[2 * b + 1] : 0;
     }
     const double2* tm = tab + (jb.a_off - a_base);
+    // generated tables (surrogate form) hold only the first need[t] offsets of table mode t;
+    // the rest are zero by definition and are not read
+    const int64_t o_lim = need ? (int64_t)need[jb.a_off / (6 * n_off)] : INT64_MAX;
     const double* bm = B + jb.b_off;
     const int kp8 = jb.kp >> 3;
     d4_t acc[3][CT];
@@ -465,7 +503,9 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
     double2 va[2][6];
     double2 vb[CT <= 2 ? 6 : 1][CT <= 2 ? CT : 1];    // next chunk's B fragments (CT <= 2)
     double2 bcur[CT <= 2 ? 6 : 1][CT <= 2 ? CT : 1];  // this chunk's
-    auto prefetch = [&](int i0) {
+    const int ni8 = jb.kp / 6;                  // interface columns rounded up to 8
+    auto prefetch = [&](int i0u) {
+        const int i0 = wrap_k(i0u, ni8);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int q = tid + 128 * h;
@@ -474,16 +514,22 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
             if (b < cd.n_b && i < cd.n_i) {
                 const int d1 = scb[2 * bl] - cd.cols_i[2 * i] - d1min;
                 const int d2 = scb[2 * bl + 1] - cd.cols_i[2 * i + 1] - d2min;
-                const double2* src = tm + (int64_t)lut[(int64_t)d1 * w2 + d2] * 6;
+                const int64_t o = lut[(int64_t)d1 * w2 + d2];
+                if (o < o_lim) {
+                    const double2* src = tm + o * 6;
 #pragma unroll
-                for (int s = 0; s < 6; ++s) va[h][s] = src[s];
+                    for (int s = 0; s < 6; ++s) va[h][s] = src[s];
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 6; ++s) va[h][s] = make_double2(0, 0);
+                }
             } else {
 #pragma unroll
                 for (int s = 0; s < 6; ++s) va[h][s] = make_double2(0, 0);
             }
         }
         if constexpr (CT <= 2) {
-            const int p0 = (6 * i0) >> 3;
+            const int p0 = (6 * i0) >> 3;      // physical chunk (i0 wrapped above)
 #pragma unroll
             for (int p = 0; p < 6; ++p)
 #pragma unroll
@@ -515,7 +561,7 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
 #pragma unroll
                 for (int c = 0; c < CT; ++c) bcur[p][c] = vb[p][c];
         } else {
-            const int p0 = (6 * i0) >> 3;
+            const int p0 = (6 * wrap_k(i0, ni8)) >> 3;
             for (int e = tid; e < CT * 768; e += 128) {
                 const int ct = e / 768, x = e - ct * 768;
                 Bs[e] = (ct < nca) ? bm[((int64_t)ct * kp8 + p0) * 128 + x] : 0.0;
@@ -558,13 +604,14 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
 
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
-                      const int32_t* lut, int d1min, int d2min, int w2) {
+                      const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
+                      int64_t n_off) {
     if (njobs <= 0) return;
     dim3 grid(njobs), blk(128);
     switch (ct) {
-        case 1: hipLaunchKernelGGL(k_gemm_dtab<1>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
-        case 2: hipLaunchKernelGGL(k_gemm_dtab<2>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
-        case 4: hipLaunchKernelGGL(k_gemm_dtab<4>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
-        default: hipLaunchKernelGGL(k_gemm_dtab<8>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2); break;
+        case 1: hipLaunchKernelGGL(k_gemm_dtab<1>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
+        case 2: hipLaunchKernelGGL(k_gemm_dtab<2>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
+        case 4: hipLaunchKernelGGL(k_gemm_dtab<4>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
+        default: hipLaunchKernelGGL(k_gemm_dtab<8>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
     }
 }

@@ -22,6 +22,11 @@ void launch_gather_table(hipStream_t st, const double2* t, double2* tab, int nmc
 void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm, int mode_mult,
                     int64_t n_off, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
                     const int32_t* lut, int d1min, int d2min, int w2);
+// Per table mode: largest magnitude (amax) and the distance beyond which every block is
+// below tau * amax (rhocut); both as bit patterns of non-negative doubles.
+void launch_tab_rhocut(hipStream_t st, const double2* tab, int T, int64_t n_off, const int32_t* d1,
+                       const int32_t* d2, double tau, unsigned long long* amax,
+                       unsigned long long* rhocut);
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
                         const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
                         int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
@@ -42,7 +47,8 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 // entries gathered into LDS in MFMA fragment order.
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
-                      const int32_t* lut, int d1min, int d2min, int w2);
+                      const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
+                      int64_t n_off);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,

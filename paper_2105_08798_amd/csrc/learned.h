@@ -63,5 +63,5 @@ void launch_sur_generate(hipStream_t st, const CgfView& v, const unsigned short*
                          double r_c, double env_floor, int nz_tab, int t0, int nt,
                          const double2* near_tab, int64_t n_near, int64_t n_off,
                          const int32_t* n_need, const int32_t* d1, const int32_t* d2, const double* cmatch,
-                         double2* out);
+                         double2* out, int64_t max_need);
 void launch_mlp_to_bf16(hipStream_t st, const float* params, unsigned short* wb, float* bias);

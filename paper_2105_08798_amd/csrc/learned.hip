@@ -701,7 +701,8 @@ void launch_sur_points(hipStream_t st, const CgfView& v, const unsigned short* w
 // Table slice generator of the surrogate form: table modes t0 .. t0+nt-1 for every
 // offset o (offsets numbered by increasing rho): o < n_near: exact lattice value;
 // o < n_need[t]: continuum (+ matching constant at line mode 0, + learned correction
-// where kappa rho <= SUR_S_LEARN); beyond: zero (kappa rho > s_max).
+// where kappa rho <= SUR_S_LEARN); beyond: zero (kappa rho > s_max), not written (the
+// product treats offsets at or beyond n_need[t] as zero).
 __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const unsigned short* __restrict__ wb,
                                                       const float* __restrict__ bias, double r_c,
                                                       double env_floor, int nz_tab, int t0,
@@ -724,10 +725,7 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const uns
         for (int c = 0; c < 6; ++c) dst[c] = src[c];
         return;
     }
-    if (o >= n_need[tm]) {
-        for (int c = 0; c < 6; ++c) dst[c] = make_double2(0, 0);
-        return;
-    }
+    if (o >= n_need[tm]) return;      // zero by definition; the product does not read it
     const double theta0 = (double)tm / nz_tab;
     double2 g[6];
     cgf_eval(v, theta0, d1[o], d2[o], g);
@@ -754,8 +752,9 @@ void launch_sur_generate(hipStream_t st, const CgfView& v, const unsigned short*
                          double r_c, double env_floor, int nz_tab, int t0, int nt,
                          const double2* near_tab, int64_t n_near, int64_t n_off,
                          const int32_t* n_need, const int32_t* d1, const int32_t* d2, const double* cmatch,
-                         double2* out) {
-    dim3 grid((unsigned)((n_off + MLP_BLOCK - 1) / MLP_BLOCK), nt);
+                         double2* out, int64_t max_need) {
+    if (max_need <= 0 || nt <= 0) return;
+    dim3 grid((unsigned)((max_need + MLP_BLOCK - 1) / MLP_BLOCK), nt);
     hipLaunchKernelGGL(k_sur_generate, grid, dim3(MLP_BLOCK), 0, st, v, wb, bias, r_c, env_floor, nz_tab, t0,
                        near_tab, n_near, n_off, n_need, d1, d2, cmatch, out);
 }

@@ -49,7 +49,7 @@ class Options(C.Structure):
     _fields_ = [("form", C.c_int), ("bz_m1", C.c_int), ("bz_m2", C.c_int),
                 ("check_netforce", C.c_int), ("project_netforce", C.c_int),
                 ("netforce_tol", C.c_double), ("row_gauge", C.c_int), ("surrogate", C.c_void_p),
-                ("gen_modes", C.c_int)]
+                ("gen_modes", C.c_int), ("skip_tol", C.c_double)]
 
 
 class RelaxOpts(C.Structure):
@@ -68,7 +68,8 @@ class Info(C.Structure):
     _fields_ = [("n_cells", C.c_int), ("total_rhs", C.c_int), ("store_bytes", C.c_int64),
                 ("scratch_bytes", C.c_int64), ("f_elems", C.c_int64), ("u_elems", C.c_int64),
                 ("n_offsets", C.c_int64), ("nsplit", C.c_int), ("job_order", C.c_int),
-                ("n_jobs", C.c_int)]
+                ("n_jobs", C.c_int), ("product_bytes", C.c_double), ("product_flops", C.c_double),
+                ("skipped_fraction", C.c_double)]
 
 
 class TuneResult(C.Structure):
@@ -163,7 +164,7 @@ class FBC:
     def __init__(self, cells, bz: int | tuple, form: str = "fp64", spring_k: float = 1.0,
                  lattice_a: float = 1.0, check_netforce: bool = True, project_netforce: bool = False,
                  netforce_tol: float = 1e-10, row_gauge: bool = True, surrogate=None, gen_modes: int = 0,
-                 stream=None):
+                 skip_tol: float = 0.0, stream=None):
         lib = load_library()
         self._lib = lib
         self.ctx = C.c_void_p()
@@ -178,6 +179,7 @@ class FBC:
         opt.row_gauge = int(bool(row_gauge))
         opt.surrogate = surrogate.handle.value if surrogate is not None else None
         opt.gen_modes = int(gen_modes)
+        opt.skip_tol = float(skip_tol)
         self._sur = surrogate          # the context reads it on every apply
         self.form = form
         self._keep = []

@@ -41,7 +41,7 @@ def test_struct_layouts_match_header_sizes():
     fbc, _ = _lib()
     assert C.sizeof(fbc.Cell) == 32
     assert C.sizeof(fbc.RelaxOut) == 56
-    assert C.sizeof(fbc.Options) == 56
+    assert C.sizeof(fbc.Options) == 64
 
 
 def test_default_options():

@@ -335,3 +335,34 @@ def test_autotune_keeps_results(form):
     e2, emax = rel_err(w.cpu().numpy(), ref)
     ctx.close()
     assert e2 < {"split_bf16": 2e-5, "split_fp16": 1e-6}.get(form, 1e-10), (form, res, e2)
+
+
+@pytest.mark.parametrize("form,tol", [("fp64", 1e-14), ("dtable_fp64", 1e-14), ("fp32", 1e-6),
+                                      ("split_fp16", 1e-6), ("split_bf16", 2e-5)])
+def test_negligible_block_skipping(form, tol):
+    """High line modes decay with kappa rho: the product skips the K chunks of a row tile
+    whose blocks are all below the skip tolerance.  FP64 forms: identical to the unskipped
+    product to rounding; reduced forms: within their tolerance of the oracle."""
+    dev = _dev()
+    # rings of radius ~17 / ~22: at the upper modes many pad tiles are far from most
+    # interface chunks
+    wl = W.make_custom(16, 400, 800, 3, 256, seed=31)
+    c = wl.cells[0]
+    f = torch.from_numpy(c.forces).to(dev)
+    out = {}
+    for tag, st in (("skip", 0.0), ("full", -1.0)):
+        ctx = _ctx(wl.cells, wl.bz, form=form, skip_tol=st)
+        w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+        ctx.green_apply(f, w)
+        assert ctx.sync_status() == 0
+        out[tag] = (w.cpu().numpy(), ctx.info.skipped_fraction, ctx.info.product_bytes)
+        ctx.close()
+    assert out["skip"][1] > 0.05 and out["full"][1] == 0.0, (out["skip"][1], out["full"][1])
+    if form in FP64_FORMS:
+        e2, emax = rel_err(out["skip"][0], out["full"][0])
+        assert e2 < tol and emax < tol, (e2, emax)
+    else:
+        assert out["skip"][2] < out["full"][2]
+    ref = oap.apply_green(oracle_green(c, wl.bz), c.forces)
+    e2, _ = rel_err(out["skip"][0], ref)
+    assert e2 < max(tol, 1e-10), (form, e2)
