@@ -858,7 +858,8 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             sums_n += (int64_t)p.R * p.nz * 8;
             c->shat_off.push_back(shat_n);
             shat_n += (int64_t)p.R * p.nm * 3;
-            int tr = (4 * p.nz <= 4096) ? std::min(64, 4096 / (4 * p.nz)) : 1;
+            int tr, pp;
+            irfft_shape(p.nz, &tr, &pp);
             const int np_ir = (p.M + tr - 1) / tr;
             const int np_ax = ((p.M + 31) / 32) * ((p.nz + 31) / 32);
             c->wmax_off.push_back(wmax_n);

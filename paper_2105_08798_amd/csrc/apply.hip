@@ -190,6 +190,43 @@ __device__ inline void put_b(void* bm, int n, int kq, int kp, double v) {
     }
 }
 
+// Whole 16-byte fragment units of one B column n for the 2G consecutive K' entries
+// kq0 .. kq0 + 2G - 1 (kq0 a multiple of 2G): FP64 units hold (kq, kq + 4), FP32 units
+// (kq, kq + 4, kq + 8, kq + 12), split units 8 consecutive kq (hi run, lo run 1 KiB on).
+template <int FORM, int NV>
+__device__ inline void put_b_units(void* bm, int n, int kq0, int kp, const double (&v)[NV]) {
+    if constexpr (FORM == FBC_FORM_FP64 || FORM == FBC_FORM_DTABLE_FP64) {
+        static_assert(NV == 8, "FP64 units cover 8 K' entries");
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            *(double2*)((double*)bm + frag_off_f64(n, kq0 + j, kp)) = make_double2(v[j], v[j + 4]);
+    } else if constexpr (FORM == FBC_FORM_FP32) {
+        static_assert(NV == 16, "FP32 units cover 16 K' entries");
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            *(float4*)((float*)bm + frag_off_f32(n, kq0 + j, kp)) =
+                make_float4((float)v[j], (float)v[j + 4], (float)v[j + 8], (float)v[j + 12]);
+    } else {
+        static_assert(NV == 8, "split units cover 8 K' entries");
+        us8_t hi, lo;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if constexpr (FORM == FBC_FORM_SPLIT_FP16) {
+                const _Float16 h = (_Float16)(float)v[j];
+                hi[j] = __builtin_bit_cast(unsigned short, h);
+                lo[j] = __builtin_bit_cast(unsigned short, (_Float16)(float)(v[j] - (double)(float)h));
+            } else {
+                const unsigned short h = f2bf((float)v[j]);
+                hi[j] = h;
+                lo[j] = f2bf((float)(v[j] - (double)bf2f(h)));
+            }
+        }
+        unsigned short* p = (unsigned short*)bm + frag_off_bf16(n, kq0, kp);
+        *(us8_t*)p = hi;
+        *(us8_t*)(p + 512) = lo;
+    }
+}
+
 template <int FORM>
 __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                                                   const double* __restrict__ tot, int project,
@@ -239,6 +276,49 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
         (int64_t)16 * ct * kp * ((FORM == FBC_FORM_SPLIT_BF16 || FORM == FBC_FORM_SPLIT_FP16) ? 2 : 1);
     const int tile = r >> 3, j = r & 7;
     const int nre = 16 * tile + j, nim = nre + 8;
+    // G consecutive complex columns per thread, written as whole 16-byte units
+    constexpr int G = (FORM == FBC_FORM_FP32) ? 8 : 4;
+    if (tc % G == 0) {
+        const int ng = tc / G;
+        for (int t = threadIdx.x; t < nm * ng; t += NT) {
+            const int m = t / ng, g = t - m * ng;
+            const int kb = k0 + g * G;
+            if (kb >= K) continue;
+            double vre[2 * G], vim[2 * G];
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const int c = g * G + q;
+                double fr = 0.0, fi = 0.0;
+                if (kb + q < K) {
+                    const double2 z = lds[(c >> 1) * nz + m];
+                    const double2 zn = lds[(c >> 1) * nz + ((nz - m) & (nz - 1))];
+                    if ((c & 1) == 0) {
+                        fr = 0.5 * (z.x + zn.x);
+                        fi = 0.5 * (z.y - zn.y);
+                    } else {
+                        fr = 0.5 * (z.y + zn.y);
+                        fi = 0.5 * (zn.x - z.x);
+                    }
+                    if (m == 0 || 2 * m == nz) fi = 0.0;
+                }
+                vre[2 * q] = fr;
+                vre[2 * q + 1] = -fi;
+                vim[2 * q] = fi;
+                vim[2 * q + 1] = fr;
+            }
+            void* bm;
+            if (FORM == FBC_FORM_FP64 || FORM == FBC_FORM_DTABLE_FP64)
+                bm = (double*)bfrag + m * mode_elems;
+            else if (FORM == FBC_FORM_FP32)
+                bm = (float*)bfrag + m * mode_elems;
+            else
+                bm = (unsigned short*)bfrag + m * mode_elems;
+            put_b_units<FORM>(bm, nre, 2 * kb, kp, vre);
+            put_b_units<FORM>(bm, nim, 2 * kb, kp, vim);
+        }
+        __syncthreads();        // the next chunk overwrites the LDS sequences
+        continue;
+    }
     for (int t = threadIdx.x; t < nm * tc; t += NT) {
         const int m = t / tc, c = t - m * tc, k = k0 + c;
         if (k >= K) continue;
@@ -442,6 +522,19 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     }
 }
 
+// Rows and RHS pairs per work group of the inverse transform: 2048 complex values
+// (32 KiB of LDS) per group where the line allows it.  The host sizes the per-group
+// partial maxima with the same shape.
+void irfft_shape(int nz, int* tr, int* pp) {
+    if (4 * nz <= 2048) {
+        *pp = 4;
+        *tr = std::min(64, 2048 / (4 * nz));
+    } else {
+        *pp = std::max(1, 2048 / nz);
+        *tr = 1;
+    }
+}
+
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,
@@ -449,14 +542,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int pp, tr;
-    if (4 * nz <= 4096) {
-        pp = 4;
-        tr = 4096 / (4 * nz);
-        if (tr > 64) tr = 64;
-    } else {
-        pp = 4096 / nz;
-        tr = 1;
-    }
+    irfft_shape(nz, &tr, &pp);
     dim3 grid((M + tr - 1) / tr, ct_grid, 4 / pp);
     size_t lds = (size_t)tr * pp * nz * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max

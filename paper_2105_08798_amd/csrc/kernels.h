@@ -49,6 +49,7 @@ void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, co
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
                       const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
                       int64_t n_off);
+void irfft_shape(int nz, int* tr, int* pp);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,
