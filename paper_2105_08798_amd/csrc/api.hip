@@ -634,7 +634,8 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
             GemmJob j{};
             j.a_off = dt ? (int64_t)u.t * c->n_offsets * 6 : p.a_off + (int64_t)u.m * store_mode_elems(form, p);
             j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
-            j.c_off = p.c_off + ks * p.c_split + (int64_t)u.m * p.ct * p.mp * 16;
+            j.c_off = p.c_off + ks * p.c_split + (int64_t)u.m * 16;
+            j.crs = p.nm * 16;
             j.mb = p.mp / 16;
             j.kp = p.kp;
             j.rb0 = tl * (tile_rows / 16);

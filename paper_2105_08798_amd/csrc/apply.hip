@@ -389,7 +389,7 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
 // (Z = U_a + i U_b; U(-m) = conj U(m); the imaginary parts of modes 0 and Nz/2 are
 // dropped as a real inverse transform does).  Output w[r][row][n0] scaled by 1/Nz, and
 // per block and RHS the maximum |w| (for the step bound of Algorithm 2).
-// Input layout c[m][ct][mp][16]: columns 0..7 real parts, 8..15 imaginary parts.
+// Input layout c[ct][mp][m][16]: columns 0..7 real parts, 8..15 imaginary parts.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    double* __restrict__ w,
@@ -408,10 +408,11 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     const int pair0 = blockIdx.z * pp;          // first RHS pair inside the 8-RHS tile
     const int nseq = tr * pp;
     const int nm = (nz >> 1) + 1;
-    const int64_t mode_stride = (int64_t)ct * mp * 16;
+    (void)ct;                                   // output layout [ct][mp][nm][16]
     // Each (mode, row, RHS pair) of the product output is read once, pair fastest, then
-    // row, then mode: a wave reads whole 128-byte rows of one mode (coalesced); the
-    // mirrored half of the spectrum (m > Nz/2) is written from the same values.
+    // mode, then row: the modes of a row are adjacent in the output, so a wave reads one
+    // contiguous run; the mirrored half of the spectrum (m > Nz/2) is written from the
+    // same values.
     // The first K slice's loads are issued for LU iterations before any is used.
     constexpr int LU = 4;
     const int nload = nm * tr * pp;
@@ -422,12 +423,12 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
         const int t = t0 + q * NT;
         const int pj = t % pp;
         const int rest = t / pp;
-        const int trr = rest % tr, mm = rest / tr;
+        const int mm = rest % nm, trr = rest / nm;
         const int row = row0 + trr;
         const int ja = 2 * (pair0 + pj);
         pv0[q] = pv1[q] = make_double2(0, 0);
         if (t < nload && row < M) {
-            const double* src = c + mm * mode_stride + ((int64_t)tile * mp + row) * 16;
+            const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
             pv0[q] = *(const double2*)(src + ja);
             pv1[q] = *(const double2*)(src + ja + 8);
         }
@@ -438,13 +439,13 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
         if (t >= nload) break;
         const int pj = t % pp;
         const int rest = t / pp;
-        const int trr = rest % tr, mm = rest / tr;
+        const int mm = rest % nm, trr = rest / nm;
         const int s = trr * pp + pj;
         const int row = row0 + trr;
         const int ja = 2 * (pair0 + pj);
         double2 z = make_double2(0, 0), zc = make_double2(0, 0);
         if (row < M) {
-            const double* src = c + mm * mode_stride + ((int64_t)tile * mp + row) * 16;
+            const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
             const double2 v0 = pv0[q], v1 = pv1[q];
             double ar = v0.x, br = v0.y, ai = v1.x, bi = v1.y;
             for (int ks = 1; ks < nsplit; ++ks) {      // K slices, summed in fixed order

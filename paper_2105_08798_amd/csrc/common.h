@@ -75,7 +75,7 @@ __host__ __device__ inline int sym_idx(int c, int d) {
 struct GemmJob {
     int64_t a_off;   // A store (dense forms) or table mode base (offset form)
     int64_t b_off;   // B fragments of this mode
-    int64_t c_off;   // output [ct][mp][16] doubles of this mode and K slice
+    int64_t c_off;   // output [ct][mp][nm][16] doubles: this mode's record, K slice
     int32_t mb;      // row blocks of the mode (mp / 16)
     int32_t kp;      // padded K' (row stride of the fragment arrays)
     int32_t rb0;     // first row block of this tile
@@ -86,6 +86,7 @@ struct GemmJob {
     // the non-negligible blocks of a tile may straddle the end); k0 == k1: empty (zeros)
     int32_t k0, k1;
     int32_t ct_active;  // column tiles holding RHS of this cell (offset form skips the rest)
+    int32_t crs;        // output row stride (doubles): the modes of a row are adjacent
 };
 
 // Physical index of a step of a cyclic K range (idx < 2 n).

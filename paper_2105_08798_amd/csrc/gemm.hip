@@ -21,7 +21,7 @@ static __device__ inline void store_c_f64(double* __restrict__ c, const GemmJob&
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int row = 16 * rb + 4 * j + (lane >> 4);      // FP64 16x16x4 output order
-        c[jb.c_off + ((int64_t)ctile * mp + row) * 16 + col] = acc[j];
+        c[jb.c_off + ((int64_t)ctile * mp + row) * jb.crs + col] = acc[j];
     }
 }
 static __device__ inline void store_c_f32acc(double* __restrict__ c, const GemmJob& jb, int rb,
@@ -31,7 +31,7 @@ static __device__ inline void store_c_f32acc(double* __restrict__ c, const GemmJ
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int row = 16 * rb + 4 * (lane >> 4) + j;      // FP32-accumulator output order
-        c[jb.c_off + ((int64_t)ctile * mp + row) * 16 + col] = acc[j];
+        c[jb.c_off + ((int64_t)ctile * mp + row) * jb.crs + col] = acc[j];
     }
 }
 
