@@ -278,7 +278,8 @@ def main() -> int:
     ap.add_argument("--forms", default=None,
                     help="default fp64,fp32,split_bf16,split_fp16 (dtable_fp64 for the batched workload)")
     ap.add_argument("--graph", action="store_true", help="replay the update from a captured HIP graph")
-    ap.add_argument("--autotune", action="store_true", help="autotune the product work list first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default work list (the library's autotuner picks K slices and order otherwise)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000, help="Adam steps of the surrogate's MLP")
     ap.add_argument("--cpu-modes", type=int, default=3)
@@ -313,8 +314,8 @@ def main() -> int:
     res = {}
     ref_w = None
     for form in forms:
-        r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph, args.autotune,
-                         args.train_steps)
+        r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph,
+                         not args.no_autotune and form != "surrogate", args.train_steps)
         r["w"] = w
         res[form] = r
     # reference result: plain FP64, else the FP64 offset table (both exact up to rounding)
