@@ -160,7 +160,8 @@ fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cells, int n_c
 fbc_status fbc_apply(fbc_ctx* ctx, const double* f, double* u, double alpha, void* stream);
 
 /* Same as fbc_apply without the mean removal and with u <- -G f (u overwritten): the
- * raw harmonic response w = G^{p|i+} f (the matrix-vector product of Section 3.2). */
+ * raw harmonic response w = G^{p|i+} f (the matrix-vector product of Section 3.2).  When
+ * a data check has latched an error, w is not computed (its contents are unspecified). */
 fbc_status fbc_green_apply(fbc_ctx* ctx, const double* f, double* w, void* stream);
 
 /* fbc_apply replayed from a HIP graph: the first call with a given (f, u, alpha, stream)

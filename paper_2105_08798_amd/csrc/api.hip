@@ -869,7 +869,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             c->npart_irfft.push_back(np_ir);
             c->npart_axpy.push_back(np_ax);
             wmax_n += (int64_t)p.R * np_ir;
-            sp_n += (int64_t)p.R * np_ax * 3;
+            sp_n += (int64_t)p.R * std::max(np_ax * 3, mean_blocks((int64_t)p.nz * p.M) * 6);
             rp_n += (int64_t)p.R * 64 * 3;
         }
         if ((s = dev_alloc(c, (void**)&c->sums, sums_n * 8)) != FBC_OK) goto fail_out;
@@ -960,7 +960,7 @@ fail_out:
 // ----------------------------------------------------------------------------------
 // Apply pipeline: net force -> line rFFT -> per-mode products -> inverse rFFT.
 // ----------------------------------------------------------------------------------
-static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
+static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to_w) {
     const int form = c->opt.form;
     int64_t sums_off = 0;
     const bool comp = row_gauge_active(c);
@@ -1008,6 +1008,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
         (void)hipEventRecord(c->ev[2 * c->n_timed + 1], st);
         ++c->n_timed;
     }
+    if (!to_w) return;
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
@@ -1015,6 +1016,43 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
                           comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
                           comp ? c->shat + c->shat_off[ci] : nullptr,
                           f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + ci : nullptr, nullptr);
+    }
+}
+
+// Fused inverse transform and update of every cell: u <- u - alpha G f minus the mean of
+// the result (mean_removal), or u <- -alpha G f.
+static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_removal, hipStream_t st) {
+    const bool comp = row_gauge_active(c);
+    const bool f16 = (c->opt.form == FBC_FORM_SPLIT_FP16);
+    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
+        auto& p = c->cells[ci];
+        const double2* rm = comp ? c->rowmean + c->rowmean_off[ci] : nullptr;
+        const double2* sh = comp ? c->shat + c->shat_off[ci] : nullptr;
+        const unsigned long long* am = f16 ? c->amax + c->amax_off[ci] : nullptr;
+        const int* be = f16 ? c->bexp + ci : nullptr;
+        int tr, pp;
+        if (!update_shape(p.nz, &tr, &pp)) {
+            // long lines: inverse transform into w, then the tiled transpose-update
+            double* uc = u + p.u_off;
+            double* sp = c->sum_part + c->sum_part_off[ci];
+            launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
+                              p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split, rm, sh,
+                              am, be, nullptr);
+            if (!mean_removal) launch_fill(st, uc, (int64_t)p.R * p.nz * p.M, 0.0);
+            launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr);
+            if (mean_removal)
+                launch_mean(st, uc, sp, c->npart_axpy[ci], c->mean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
+            continue;
+        }
+        double* mu = nullptr;
+        if (mean_removal) {
+            mu = c->mean + 3 * p.rhs0;
+            launch_update_mean(st, u + p.u_off, c->cbuf + p.c_off, c->sum_part + c->sum_part_off[ci], p.R,
+                               p.nz, p.mp, p.M, c->nsplit, p.c_split, rm, sh, am, be, alpha, mu, c->status);
+        }
+        launch_irfft_update(st, c->cbuf + p.c_off, u + p.u_off, p.R, p.nz, p.mp, p.M, p.ctr,
+                            c->tw + p.tw_off, c->nsplit, p.c_split, rm, sh, am, be, alpha, mu,
+                            mean_removal ? 1 : 0, c->status);
     }
 }
 
@@ -1030,14 +1068,9 @@ extern "C" fbc_status fbc_apply(fbc_ctx* c, const double* f, double* u, double a
     if (s != FBC_OK) return s;
     if (!std::isfinite(alpha)) return fail(c, FBC_E_ARG, "alpha must be finite");
     hipStream_t st = (hipStream_t)stream;
-    enqueue_forward(c, f, st);
-    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
-        auto& p = c->cells[ci];
-        double* uc = u + p.u_off;
-        double* sp = c->sum_part + c->sum_part_off[ci];
-        launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr);
-        launch_mean(st, uc, sp, c->npart_axpy[ci], c->mean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
-    }
+    // the forward half, then per cell the mean and the fused inverse transform + update
+    enqueue_forward(c, f, st, false);
+    enqueue_update(c, u, alpha, true, st);
     HIPCHK(c, hipGetLastError());
     return FBC_OK;
 }
@@ -1126,14 +1159,8 @@ extern "C" fbc_status fbc_green_apply(fbc_ctx* c, const double* f, double* w, vo
     fbc_status s = check_apply_args(c, f, w);
     if (s != FBC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    enqueue_forward(c, f, st);
-    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
-        auto& p = c->cells[ci];
-        double* wc = w + p.u_off;
-        launch_fill(st, wc, (int64_t)p.R * p.nz * p.M, 0.0);
-        launch_axpy(st, c->wbuf + p.w_off, wc, c->sum_part + c->sum_part_off[ci], p.R, p.nz, p.M, -1.0,
-                    nullptr, c->status, nullptr);
-    }
+    enqueue_forward(c, f, st, false);
+    enqueue_update(c, w, -1.0, false, st);
     HIPCHK(c, hipGetLastError());
     return FBC_OK;
 }
@@ -1161,7 +1188,7 @@ extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, 
         launch_relax_alpha(st, f_in + p.f_off, c->fprev + p.f_off, c->rpart + c->rpart_off[ci],
                            c->alpha + p.rhs0, c->finf + p.rhs0, p.R, per_rhs, k, c->ropt.relax);
     }
-    enqueue_forward(c, f_in, st);
+    enqueue_forward(c, f_in, st, true);
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         launch_relax_clamp(st, c->wmax_part + c->wmax_off[ci], c->npart_irfft[ci], c->alpha + p.rhs0,

@@ -241,6 +241,7 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     const int r = blockIdx.x;
     const int K = 3 * n_i;
     const int nseq = tc >> 1;
+    const int ss = nz + 1;                  // sequence stride (complex values)
     const int nchunk = (K + tc - 1) / tc;
     double* ldsd = (double*)lds;
     for (int cy = blockIdx.y; cy < nchunk; cy += gridDim.y) {     // column chunks (grid-stride)
@@ -265,11 +266,11 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                 if (project) x -= tot[r * 3 + (k % 3)] * inv_cnt;     // mean over the cell's atoms
                 if (FORM == FBC_FORM_SPLIT_FP16) x = ldexp(x, esc);
             }
-            ldsd[2 * ((c >> 1) * nz + (int)bitrev(n0, logn)) + (c & 1)] = x;
+            ldsd[2 * ((c >> 1) * ss + (int)bitrev(n0, logn)) + (c & 1)] = x;
         }
     }
     __syncthreads();
-    lds_fft(lds, nseq, logn, tw, false);
+    lds_fft_s<false>(lds, nseq, ss, logn, tw);
     const int nm = (nz >> 1) + 1;
     // per mode: B elements of one mode occupy 16*ct*kp values (x2 for the bf16 split)
     const int64_t mode_elems =
@@ -290,8 +291,8 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                 const int c = g * G + q;
                 double fr = 0.0, fi = 0.0;
                 if (kb + q < K) {
-                    const double2 z = lds[(c >> 1) * nz + m];
-                    const double2 zn = lds[(c >> 1) * nz + ((nz - m) & (nz - 1))];
+                    const double2 z = lds[(c >> 1) * ss + m];
+                    const double2 zn = lds[(c >> 1) * ss + ((nz - m) & (nz - 1))];
                     if ((c & 1) == 0) {
                         fr = 0.5 * (z.x + zn.x);
                         fi = 0.5 * (z.y - zn.y);
@@ -322,8 +323,8 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     for (int t = threadIdx.x; t < nm * tc; t += NT) {
         const int m = t / tc, c = t - m * tc, k = k0 + c;
         if (k >= K) continue;
-        const double2 z = lds[(c >> 1) * nz + m];
-        const double2 zn = lds[(c >> 1) * nz + ((nz - m) & (nz - 1))];
+        const double2 z = lds[(c >> 1) * ss + m];
+        const double2 zn = lds[(c >> 1) * ss + ((nz - m) & (nz - 1))];
         double fr, fi;
         if ((c & 1) == 0) {
             fr = 0.5 * (z.x + zn.x);
@@ -355,14 +356,16 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     const int K = 3 * n_i;
-    int tc = 8192 / nz;                  // nz * tc doubles = 64 KiB of LDS
-    if (tc > 256) tc = 256;
-    if (tc < 2) tc = 2;
+    // columns per work group: the largest power of two whose (Nz + 1) * tc doubles fit the
+    // LDS budget
+    constexpr int budget = 8192;          // 64 KiB
+    int tc = 256;
+    while (tc > 2 && tc * (nz + 1) > budget) tc >>= 1;
     const int kk = (K + 1) & ~1;
     if (tc > kk) tc = kk;
     tc &= ~1;
     dim3 grid(R, (unsigned)std::min((K + tc - 1) / tc, 65535));
-    const size_t lds = (size_t)nz * tc * sizeof(double);
+    const size_t lds = (size_t)(nz + 1) * tc * sizeof(double);
     const double inv_cnt = 1.0 / ((double)n_i * nz);
     switch (form) {
         case FBC_FORM_FP32:
@@ -387,14 +390,138 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
 // ----------------------------------------------------------------------------------
 // Inverse rFFT along the line of the per-mode products, two RHS per complex sequence
 // (Z = U_a + i U_b; U(-m) = conj U(m); the imaginary parts of modes 0 and Nz/2 are
-// dropped as a real inverse transform does).  Output w[r][row][n0] scaled by 1/Nz, and
-// per block and RHS the maximum |w| (for the step bound of Algorithm 2).
-// Input layout c[ct][mp][m][16]: columns 0..7 real parts, 8..15 imaginary parts.
+// dropped as a real inverse transform does).
+// Input layout c[ct][mp][m][16]: columns 0..7 real parts, 8..15 imaginary parts, one
+// record per K slice (split_stride apart).
 // ----------------------------------------------------------------------------------
+
+// Final value of one (row, mode) of an RHS pair (columns ja, ja + 1 of the tile): K
+// slices summed in fixed order, the split-FP16 scale removed, the row-gauge compensation
+// + R_b(m) . s^(m) added in FP64.  v0, v1: slice 0 at columns ja and ja + 8.  Every
+// kernel that consumes the product output goes through this function, so they agree
+// bit for bit.
+__device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R,
+                                   const double2* __restrict__ rowmean,
+                                   const double2* __restrict__ shat,
+                                   const unsigned long long* __restrict__ amax, int eb,
+                                   double& ar, double& br, double& ai, double& bi) {
+    if (amax) {     // split FP16: the product carries 2^(e_A(m) + e_B)
+        const double sc = ldexp(1.0, -(split16_exp_a(amax[mm]) + eb));
+        ar *= sc;
+        ai *= sc;
+        br *= sc;
+        bi *= sc;
+    }
+    if (rowmean) {
+        const int b = row / 3, cc = row - 3 * b;
+        const double2* rm = rowmean + ((int64_t)mm * (M / 3) + b) * 6;
+        for (int d = 0; d < 3; ++d) {
+            const double2 g = rm[sym_idx(cc, d)];
+            if (ra < R) {
+                const double2 sv = shat[((int64_t)ra * nm + mm) * 3 + d];
+                ar += g.x * sv.x - g.y * sv.y;
+                ai += g.x * sv.y + g.y * sv.x;
+            }
+            if (ra + 1 < R) {
+                const double2 sv = shat[((int64_t)(ra + 1) * nm + mm) * 3 + d];
+                br += g.x * sv.x - g.y * sv.y;
+                bi += g.x * sv.y + g.y * sv.x;
+            }
+        }
+    }
+    if (mm == 0 || mm == nm - 1) {      // modes 0 and Nz/2 are real
+        ai = 0.0;
+        bi = 0.0;
+    }
+}
+
+__device__ inline void mode_value(double2 v0, double2 v1, const double* __restrict__ src, int ja,
+                                  int nsplit, int64_t split_stride, int mm, int row, int M, int nm,
+                                  int ra, int R, const double2* __restrict__ rowmean,
+                                  const double2* __restrict__ shat,
+                                  const unsigned long long* __restrict__ amax, int eb,
+                                  double& ar, double& br, double& ai, double& bi) {
+    ar = v0.x;
+    br = v0.y;
+    ai = v1.x;
+    bi = v1.y;
+    for (int ks = 1; ks < nsplit; ++ks) {
+        const double* q = src + ks * split_stride;
+        const double2 q0 = *(const double2*)(q + ja), q1 = *(const double2*)(q + ja + 8);
+        ar += q0.x;
+        br += q0.y;
+        ai += q1.x;
+        bi += q1.y;
+    }
+    mode_adjust(mm, row, M, nm, ra, R, rowmean, shat, amax, eb, ar, br, ai, bi);
+}
+
+// Gathers the spectra of tr rows x pp RHS pairs of one column tile into LDS (bit-reversed,
+// sequence s = pj * tr + trr at s * ss) and inverse-transforms them.  Each (mode, row,
+// pair) of the product output is read once, pair fastest, then mode, then row: the modes
+// of a row are adjacent in the output, so a wave reads one contiguous run; the mirrored
+// half of the spectrum (m > Nz/2) is written from the same values.  The first K slice's
+// loads are issued LU at a time before any is used.
+__device__ inline void gather_inverse(double2* lds, const double* __restrict__ c, int tile, int row0,
+                                      int pair0, int tr, int pp, int ss, int R, int nz, int logn,
+                                      int mp, int M, const double2* __restrict__ tw, int nsplit,
+                                      int64_t split_stride, const double2* __restrict__ rowmean,
+                                      const double2* __restrict__ shat,
+                                      const unsigned long long* __restrict__ amax, int eb) {
+    const int nm = (nz >> 1) + 1;
+    constexpr int LU = 4;
+    const int nload = nm * tr * pp;
+    for (int t0 = threadIdx.x; t0 < nload; t0 += NT * LU) {
+        double2 pv0[LU], pv1[LU];
+#pragma unroll
+        for (int q = 0; q < LU; ++q) {
+            const int t = t0 + q * NT;
+            const int pj = t % pp;
+            const int rest = t / pp;
+            const int mm = rest % nm, trr = rest / nm;
+            const int row = row0 + trr;
+            const int ja = 2 * (pair0 + pj);
+            pv0[q] = pv1[q] = make_double2(0, 0);
+            if (t < nload && row < M) {
+                const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
+                pv0[q] = *(const double2*)(src + ja);
+                pv1[q] = *(const double2*)(src + ja + 8);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < LU; ++q) {
+            const int t = t0 + q * NT;
+            if (t >= nload) break;
+            const int pj = t % pp;
+            const int rest = t / pp;
+            const int mm = rest % nm, trr = rest / nm;
+            const int s = pj * tr + trr;
+            const int row = row0 + trr;
+            const int ja = 2 * (pair0 + pj);
+            double2 z = make_double2(0, 0), zc = make_double2(0, 0);
+            if (row < M) {
+                const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
+                double ar, br, ai, bi;
+                mode_value(pv0[q], pv1[q], src, ja, nsplit, split_stride, mm, row, M, nm, 8 * tile + ja, R,
+                           rowmean, shat, amax, eb, ar, br, ai, bi);
+                z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
+                zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
+            }
+            lds[s * ss + bitrev(mm, logn)] = z;
+            if (mm > 0 && 2 * mm < nz) lds[s * ss + bitrev(nz - mm, logn)] = zc;
+        }
+    }
+    __syncthreads();
+    lds_fft_s<true>(lds, tr * pp, ss, logn, tw);
+}
+
+// Inverse transform into the scratch w[r][row][n0] (scaled by 1/Nz), with per block and
+// RHS the maximum |w| (the step bound of Algorithm 2).  Used by the relaxation step,
+// whose step size depends on the whole of w before any update.
 __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    double* __restrict__ w,
                                                    double* __restrict__ wmax_part, int R, int nz,
-                                                   int logn, int mp, int M, int ct, int tr, int pp,
+                                                   int logn, int mp, int M, int tr, int pp,
                                                    const double2* __restrict__ tw, int nsplit,
                                                    int64_t split_stride,
                                                    const double2* __restrict__ rowmean,
@@ -407,100 +534,19 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     const int tile = blockIdx.y;
     const int pair0 = blockIdx.z * pp;          // first RHS pair inside the 8-RHS tile
     const int nseq = tr * pp;
-    const int nm = (nz >> 1) + 1;
-    (void)ct;                                   // output layout [ct][mp][nm][16]
-    // Each (mode, row, RHS pair) of the product output is read once, pair fastest, then
-    // mode, then row: the modes of a row are adjacent in the output, so a wave reads one
-    // contiguous run; the mirrored half of the spectrum (m > Nz/2) is written from the
-    // same values.
-    // The first K slice's loads are issued for LU iterations before any is used.
-    constexpr int LU = 4;
-    const int nload = nm * tr * pp;
-    for (int t0 = threadIdx.x; t0 < nload; t0 += NT * LU) {
-    double2 pv0[LU], pv1[LU];
-#pragma unroll
-    for (int q = 0; q < LU; ++q) {
-        const int t = t0 + q * NT;
-        const int pj = t % pp;
-        const int rest = t / pp;
-        const int mm = rest % nm, trr = rest / nm;
-        const int row = row0 + trr;
-        const int ja = 2 * (pair0 + pj);
-        pv0[q] = pv1[q] = make_double2(0, 0);
-        if (t < nload && row < M) {
-            const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
-            pv0[q] = *(const double2*)(src + ja);
-            pv1[q] = *(const double2*)(src + ja + 8);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < LU; ++q) {
-        const int t = t0 + q * NT;
-        if (t >= nload) break;
-        const int pj = t % pp;
-        const int rest = t / pp;
-        const int mm = rest % nm, trr = rest / nm;
-        const int s = trr * pp + pj;
-        const int row = row0 + trr;
-        const int ja = 2 * (pair0 + pj);
-        double2 z = make_double2(0, 0), zc = make_double2(0, 0);
-        if (row < M) {
-            const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
-            const double2 v0 = pv0[q], v1 = pv1[q];
-            double ar = v0.x, br = v0.y, ai = v1.x, bi = v1.y;
-            for (int ks = 1; ks < nsplit; ++ks) {      // K slices, summed in fixed order
-                const double* q = src + ks * split_stride;
-                const double2 q0 = *(const double2*)(q + ja), q1 = *(const double2*)(q + ja + 8);
-                ar += q0.x;
-                br += q0.y;
-                ai += q1.x;
-                bi += q1.y;
-            }
-            if (amax) {     // split FP16: the product carries 2^(e_A(m) + e_B)
-                const double sc = ldexp(1.0, -(split16_exp_a(amax[mm]) + eb));
-                ar *= sc;
-                ai *= sc;
-                br *= sc;
-                bi *= sc;
-            }
-            if (rowmean) {
-                // exact FP64 compensation of the row gauge: + R_b(m) . sum_i f^_i(m)
-                const int b = row / 3, cc = row - 3 * b;
-                const double2* rm = rowmean + ((int64_t)mm * (M / 3) + b) * 6;
-                for (int d = 0; d < 3; ++d) {
-                    const double2 g = rm[sym_idx(cc, d)];
-                    if (8 * tile + ja < R) {
-                        const double2 sv = shat[((int64_t)(8 * tile + ja) * nm + mm) * 3 + d];
-                        ar += g.x * sv.x - g.y * sv.y;
-                        ai += g.x * sv.y + g.y * sv.x;
-                    }
-                    if (8 * tile + ja + 1 < R) {
-                        const double2 sv = shat[((int64_t)(8 * tile + ja + 1) * nm + mm) * 3 + d];
-                        br += g.x * sv.x - g.y * sv.y;
-                        bi += g.x * sv.y + g.y * sv.x;
-                    }
-                }
-            }
-            if (mm == 0 || 2 * mm == nz) { ai = 0.0; bi = 0.0; }
-            z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
-            zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
-        }
-        lds[s * nz + bitrev(mm, logn)] = z;
-        if (mm > 0 && 2 * mm < nz) lds[s * nz + bitrev(nz - mm, logn)] = zc;
-    }
-    }
-    __syncthreads();
-    lds_fft(lds, nseq, logn, tw, true);
+    const int ss = nz + 1;
+    gather_inverse(lds, c, tile, row0, pair0, tr, pp, ss, R, nz, logn, mp, M, tw, nsplit, split_stride,
+                   rowmean, shat, amax, eb);
     const double scale = 1.0 / nz;
     double mx[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // per RHS inside the tile
     for (int t = threadIdx.x; t < nseq * nz; t += NT) {
         const int s = t / nz, n0 = t - s * nz;
-        const int trr = s / pp, pj = s - trr * pp;
+        const int pj = s / tr, trr = s - pj * tr;
         const int row = row0 + trr;
         const int ja = 2 * (pair0 + pj);
         const int ra = 8 * tile + ja;
         if (row >= M) continue;
-        const double2 z = lds[s * nz + n0];
+        const double2 z = lds[s * ss + n0];
         const double wa = z.x * scale, wb = z.y * scale;
         if (ra < R) w[((int64_t)ra * M + row) * nz + n0] = wa;
         if (ra + 1 < R) w[((int64_t)(ra + 1) * M + row) * nz + n0] = wb;
@@ -523,7 +569,7 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     }
 }
 
-// Rows and RHS pairs per work group of the inverse transform: 2048 complex values
+// Rows and RHS pairs per work group of the inverse transform into w: 2048 complex values
 // (32 KiB of LDS) per group where the line allows it.  The host sizes the per-group
 // partial maxima with the same shape.
 void irfft_shape(int nz, int* tr, int* pp) {
@@ -540,16 +586,314 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,
                        const unsigned long long* amax, const int* bexp, int* n_part_out) {
+    (void)ct;
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int pp, tr;
     irfft_shape(nz, &tr, &pp);
     dim3 grid((M + tr - 1) / tr, ct_grid, 4 / pp);
-    size_t lds = (size_t)tr * pp * nz * sizeof(double2);
+    size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
     hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,
-                       ct, tr, pp, tw, nsplit, split_stride, rowmean, shat, amax, bexp);
+                       tr, pp, tw, nsplit, split_stride, rowmean, shat, amax, bexp);
     if (n_part_out) *n_part_out = (int)grid.x;
+}
+
+// ----------------------------------------------------------------------------------
+// Fused inverse transform and pad update (Algorithm 1 lines 7-8):
+//   u[r][n0][row] <- (read_u ? u : 0) - alpha * w[r][row][n0] - mu[r][row % 3]
+// straight from the product output, without the w scratch.  A work group owns tr
+// consecutive rows (one contiguous run of u per layer) and pp RHS pairs of one column
+// tile.  Work groups are dealt to the 8 XCDs round robin by index; the 4/pp pair groups
+// of a row block get indices 8 apart, so they run on one XCD at about the same time and
+// share the product records (128 bytes per row and mode) through its L2.
+//  1. gather: the spectra in natural order (mode fastest across threads, so the LDS
+//     writes are consecutive), the K slices of LU work items loaded before any is used;
+//  2. decimation-in-frequency stages of half length Nz/2 .. 4 in LDS, neighbouring
+//     threads on neighbouring sequences (stride Nz + 1: distinct banks);
+//  3. per thread four consecutive bit-reversed slots of one sequence: the stages of half
+//     length 2 and 1 in registers, then four layers n0 = bitrev(slot) of u, rows fastest
+//     across threads (runs of tr values of u per layer).
+// mu (mean of the updated u, from k_update_mean) may be NULL (no mean removal).
+// Skipped entirely when a data check has latched an error.  Needs Nz >= 16.
+// ----------------------------------------------------------------------------------
+template <int NSM>
+__global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ c,
+                                                     double* __restrict__ u, int R, int nz, int logn,
+                                                     int mp, int M, int tr, int pp, int n_rg,
+                                                     int n_units, const double2* __restrict__ tw,
+                                                     int nsplit, int64_t split_stride,
+                                                     const double2* __restrict__ rowmean,
+                                                     const double2* __restrict__ shat,
+                                                     const unsigned long long* __restrict__ amax,
+                                                     const int* __restrict__ bexp, double alpha,
+                                                     const double* __restrict__ mu, int read_u,
+                                                     const int* __restrict__ status) {
+    extern __shared__ double2 lds[];
+    if (status && *status) return;
+    const int npg = 4 / pp;
+    const int xcd = blockIdx.x & 7, q8 = blockIdx.x >> 3;
+    const int pg = q8 % npg;
+    const int unit = (q8 / npg) * 8 + xcd;
+    if (unit >= n_units) return;
+    const int tile = unit / n_rg, rg = unit - tile * n_rg;
+    const int row0 = rg * tr, pair0 = pg * pp;
+    const int ss = nz + 1;
+    const int nm = (nz >> 1) + 1;
+    const int eb = bexp ? *bexp : 0;
+    const int nseq = tr * pp;
+    // 1. gather
+    {
+        constexpr int LU = NSM >= 8 ? 1 : 8 / NSM;
+        const int nload = nm * nseq;
+        for (int t0 = threadIdx.x; t0 < nload; t0 += NT * LU) {
+            double2 v0[LU][NSM], v1[LU][NSM];
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                const int t = t0 + k * NT;
+                const int mm = t % nm, rest = t / nm;
+                const int pj = rest % pp, trr = rest / pp;
+                const int row = row0 + trr;
+                const int ja = 2 * (pair0 + pj);
+                const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16 + ja;
+#pragma unroll
+                for (int ks = 0; ks < NSM; ++ks) {
+                    v0[k][ks] = v1[k][ks] = make_double2(0, 0);
+                    if (t < nload && row < M && ks < nsplit) {
+                        v0[k][ks] = *(const double2*)(src + ks * split_stride);
+                        v1[k][ks] = *(const double2*)(src + ks * split_stride + 8);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                const int t = t0 + k * NT;
+                if (t >= nload) break;
+                const int mm = t % nm, rest = t / nm;
+                const int pj = rest % pp, trr = rest / pp;
+                const int row = row0 + trr;
+                const int ja = 2 * (pair0 + pj);
+                double ar = v0[k][0].x, br = v0[k][0].y, ai = v1[k][0].x, bi = v1[k][0].y;
+#pragma unroll
+                for (int ks = 1; ks < NSM; ++ks) {     // K slices in fixed order (zeros past nsplit)
+                    if (ks < nsplit) {
+                        ar += v0[k][ks].x;
+                        br += v0[k][ks].y;
+                        ai += v1[k][ks].x;
+                        bi += v1[k][ks].y;
+                    }
+                }
+                double2 z = make_double2(0, 0), zc = make_double2(0, 0);
+                if (row < M) {
+                    mode_adjust(mm, row, M, nm, 8 * tile + ja, R, rowmean, shat, amax, eb, ar, br, ai, bi);
+                    z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
+                    zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
+                }
+                double2* sq = lds + (pj * tr + trr) * ss;
+                sq[mm] = z;
+                if (mm > 0 && 2 * mm < nz) sq[nz - mm] = zc;
+            }
+        }
+    }
+    __syncthreads();
+    // 2. stages of half length Nz/2 .. 4
+    lds_fft_dif_s<true>(lds, nseq, ss, logn, 2, tw);
+    // 3. last two stages in registers, then the update
+    const double scale = 1.0 / nz;
+    const double2 w0 = twid<true>(tw, 0), w1 = twid<true>(tw, nz >> 2);
+    const int nq = nz >> 2;
+    const int nitem = nseq * nq;
+    constexpr int LV = 2;
+    for (int t0 = threadIdx.x; t0 < nitem; t0 += NT * LV) {
+        double oa[LV][4], ob[LV][4];
+#pragma unroll
+        for (int k = 0; k < LV; ++k) {
+            const int t = t0 + k * NT;
+            const int trr = t % tr, rest = t / tr;
+            const int g = rest % nq, pj = rest / nq;
+            const int row = row0 + trr;
+            const int ra = 8 * tile + 2 * (pair0 + pj);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                oa[k][e] = ob[k][e] = 0.0;
+                if (read_u && t < nitem && row < M) {
+                    const int n0 = (int)bitrev(4 * g + e, logn);
+                    if (ra < R) oa[k][e] = u[((int64_t)ra * nz + n0) * M + row];
+                    if (ra + 1 < R) ob[k][e] = u[((int64_t)(ra + 1) * nz + n0) * M + row];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < LV; ++k) {
+            const int t = t0 + k * NT;
+            if (t >= nitem) break;
+            const int trr = t % tr, rest = t / tr;
+            const int g = rest % nq, pj = rest / nq;
+            const int row = row0 + trr;
+            if (row >= M) continue;
+            const int ra = 8 * tile + 2 * (pair0 + pj);
+            const double2* sq = lds + (pj * tr + trr) * ss + 4 * g;
+            double2 x0 = sq[0], x1 = sq[1], x2 = sq[2], x3 = sq[3];
+            dif(x0, x2, w0);
+            dif(x1, x3, w1);
+            dif(x0, x1, w0);
+            dif(x2, x3, w0);
+            const double2 xv[4] = {x0, x1, x2, x3};
+            const int cc = row % 3;
+            const double ma = (mu && ra < R) ? mu[ra * 3 + cc] : 0.0;
+            const double mb = (mu && ra + 1 < R) ? mu[(ra + 1) * 3 + cc] : 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int n0 = (int)bitrev(4 * g + e, logn);
+                if (ra < R) {
+                    const double x = oa[k][e] - alpha * (xv[e].x * scale);
+                    u[((int64_t)ra * nz + n0) * M + row] = mu ? x - ma : x;
+                }
+                if (ra + 1 < R) {
+                    const double x = ob[k][e] - alpha * (xv[e].y * scale);
+                    u[((int64_t)(ra + 1) * nz + n0) * M + row] = mu ? x - mb : x;
+                }
+            }
+        }
+    }
+}
+
+// Shape of the fused update's work groups: tr rows (16 where the line allows: 128-byte
+// runs of u) x one RHS pair x (Nz + 1) complex values of LDS, at most 64 KiB (measured on
+// MI355X: one pair per group with the pair groups sharing the product records through
+// L2 beats two or four pairs per group).  Returns false where fewer than 8 rows fit (long lines) or the line is shorter than 16:
+// the update then goes through the w scratch and the tiled transpose instead.
+bool update_shape(int nz, int* tr, int* pp) {
+    constexpr int budget = 4096;                  // complex values (64 KiB)
+    int t = 16;
+    const int p = 1;
+    while (t > 1 && t * p * (nz + 1) > budget) t >>= 1;
+    *tr = t;
+    *pp = p;
+    return t >= 8 && nz >= 16;
+}
+
+int update_blocks(int nz, int M, int ct_grid) {
+    int tr, pp;
+    update_shape(nz, &tr, &pp);
+    const int n_units = ct_grid * ((M + tr - 1) / tr);
+    return 8 * (4 / pp) * ((n_units + 7) / 8);
+}
+
+void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
+                         int ct_grid, const double2* tw, int nsplit, int64_t split_stride,
+                         const double2* rowmean, const double2* shat, const unsigned long long* amax,
+                         const int* bexp, double alpha, const double* mu, int read_u,
+                         const int* status) {
+    int logn = 0;
+    while ((1 << logn) < nz) ++logn;
+    int tr, pp;
+    update_shape(nz, &tr, &pp);
+    const int n_rg = (M + tr - 1) / tr;
+    const int n_units = ct_grid * n_rg;
+    const int nblk = update_blocks(nz, M, ct_grid);
+    const size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
+#define UPD_CASE(NS) \
+    hipLaunchKernelGGL(k_irfft_update<NS>, dim3(nblk), dim3(NT), lds, st, c, u, R, nz, logn, mp, M, tr, \
+                       pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, amax, bexp, alpha, mu, \
+                       read_u, status)
+    if (nsplit <= 1) UPD_CASE(1);
+    else if (nsplit <= 2) UPD_CASE(2);
+    else if (nsplit <= 4) UPD_CASE(4);
+    else UPD_CASE(8);
+#undef UPD_CASE
+}
+
+// ----------------------------------------------------------------------------------
+// Mean of the updated pad displacement, before the update is written:
+//   mean(u - alpha w) = (sum u - alpha sum w) / (Nz n_b)   per RHS and component,
+// where sum_n0 w[row][n0] is the line mode 0 of the row (the inverse transform's
+// constant term), so sum w needs only the mode-0 records.  k_mean_parts: partial sums
+// of u and of the mode-0 values over a fixed partition (nbr blocks per RHS);
+// k_update_mean: one block per RHS adds the partials in fixed order.
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_mean_parts(const double* __restrict__ u, const double* __restrict__ c,
+                                                   int64_t per_rhs, int nbr, int R, int nz, int mp, int M,
+                                                   int nsplit, int64_t split_stride,
+                                                   const double2* __restrict__ rowmean,
+                                                   const double2* __restrict__ shat,
+                                                   const unsigned long long* __restrict__ amax,
+                                                   const int* __restrict__ bexp,
+                                                   double* __restrict__ part,
+                                                   const int* __restrict__ status) {
+    __shared__ double red[6 * NT];
+    if (status && *status) return;
+    const int r = blockIdx.y, b = blockIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};     // sum u (3), sum w (3)
+    {
+        const int64_t len = (per_rhs + nbr - 1) / nbr;
+        const int64_t e0 = (int64_t)b * len, e1 = std::min(per_rhs, e0 + len);
+        const double* ur = u + (int64_t)r * per_rhs;
+        constexpr int LU = 4;
+        for (int64_t i0 = e0 + threadIdx.x; i0 < e1; i0 += (int64_t)NT * LU) {
+            double x[LU];
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                const int64_t i = i0 + (int64_t)k * NT;
+                x[k] = i < e1 ? ur[i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                const int64_t i = i0 + (int64_t)k * NT;
+                if (i < e1) v[(int)(i % 3)] += x[k];       // (n0 M + row) % 3 = row % 3
+            }
+        }
+    }
+    {
+        const int tile = r >> 3, ja = (r & 7) & ~1, odd = r & 1;
+        const int nm = (nz >> 1) + 1;
+        const int eb = bexp ? *bexp : 0;
+        const int lr = (M + nbr - 1) / nbr;
+        const int r1 = std::min(M, (b + 1) * lr);
+        for (int row = b * lr + threadIdx.x; row < r1; row += NT) {
+            const double* src = c + ((int64_t)tile * mp + row) * nm * 16;
+            double ar, br, ai, bi;
+            mode_value(*(const double2*)(src + ja), *(const double2*)(src + ja + 8), src, ja, nsplit,
+                       split_stride, 0, row, M, nm, 8 * tile + ja, R, rowmean, shat, amax, eb, ar, br, ai,
+                       bi);
+            v[3 + row % 3] += odd ? br : ar;
+        }
+    }
+    block_sum<6>(v, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) part[((int64_t)r * nbr + b) * 6 + k] = v[k];
+}
+
+int mean_blocks(int64_t per_rhs) {
+    const int64_t b = (per_rhs + (int64_t)NT * 32 - 1) / ((int64_t)NT * 32);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, b));
+}
+
+__global__ void __launch_bounds__(NT) k_update_mean(const double* __restrict__ part, int nbr, int nz, int n_b,
+                                                    double alpha, double* __restrict__ mu,
+                                                    const int* __restrict__ status) {
+    __shared__ double red[6 * NT];
+    if (status && *status) return;
+    const int r = blockIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nbr; b += NT)
+        for (int k = 0; k < 6; ++k) v[k] += part[((int64_t)r * nbr + b) * 6 + k];
+    block_sum<6>(v, red);
+    if (threadIdx.x == 0) {
+        const double inv_n = 1.0 / ((double)nz * n_b);
+        for (int cc = 0; cc < 3; ++cc) mu[r * 3 + cc] = (v[cc] - alpha * v[3 + cc]) * inv_n;
+    }
+}
+
+void launch_update_mean(hipStream_t st, const double* u, const double* c, double* part, int R, int nz,
+                        int mp, int M, int nsplit, int64_t split_stride, const double2* rowmean,
+                        const double2* shat, const unsigned long long* amax, const int* bexp,
+                        double alpha, double* mu, const int* status) {
+    const int64_t per_rhs = (int64_t)nz * M;
+    const int nbr = mean_blocks(per_rhs);
+    hipLaunchKernelGGL(k_mean_parts, dim3(nbr, R), dim3(NT), 0, st, u, c, per_rhs, nbr, R, nz, mp, M, nsplit,
+                       split_stride, rowmean, shat, amax, bexp, part, status);
+    hipLaunchKernelGGL(k_update_mean, dim3(R), dim3(NT), 0, st, part, nbr, nz, M / 3, alpha, mu, status);
 }
 
 // ----------------------------------------------------------------------------------

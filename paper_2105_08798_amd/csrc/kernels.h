@@ -59,6 +59,19 @@ void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, i
                  int* n_part_out);
 void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, double* mean_out,
                  int R, int nz, int M, const int* status);
+// fused inverse transform + update (fbc_apply, fbc_green_apply), and the mean it removes;
+// update_shape is false where the line is too long for the fused kernel
+bool update_shape(int nz, int* tr, int* pp);
+void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
+                         int ct_grid, const double2* tw, int nsplit, int64_t split_stride,
+                         const double2* rowmean, const double2* shat, const unsigned long long* amax,
+                         const int* bexp, double alpha, const double* mu, int read_u,
+                         const int* status);
+int mean_blocks(int64_t per_rhs);
+void launch_update_mean(hipStream_t st, const double* u, const double* c, double* part, int R, int nz,
+                        int mp, int M, int nsplit, int64_t split_stride, const double2* rowmean,
+                        const double2* shat, const unsigned long long* amax, const int* bexp,
+                        double alpha, double* mu, const int* status);
 
 // ---- relax (Section 2.3.3, Algorithm 2) ----
 void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
