@@ -173,14 +173,16 @@ fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alph
 /* Autotuner of the per-mode product launch.  Times every candidate work list -- K split
  * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times three
  * orders: 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first
- * -- with `reps` launches each on this context (input f, device; w, device, same layout
- * as u, is overwritten with G f), keeps the fastest and reports it in *out (may be
- * NULL).  Synchronises the stream. */
+ * -- with `reps` fbc_green_apply calls each on this context (input f, device; w, device,
+ * same layout as u, is overwritten with G f), keeps the list with the fastest whole call
+ * (the K slices also cost the inverse transform a read each) and reports it in *out (may
+ * be NULL).  Synchronises the stream. */
 typedef struct {
     int nsplit;
     int order;
     double gemm_ms;       /* average product time of the chosen list */
     int n_candidates;
+    double call_ms;       /* average fbc_green_apply time of the chosen list */
 } fbc_tune_result;
 fbc_status fbc_autotune(fbc_ctx* ctx, const double* f, double* w, int reps, fbc_tune_result* out,
                         void* stream);

@@ -1124,33 +1124,50 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
     int n0;
     if ((s = fbc_timing(c, 1)) != FBC_OK) return s;
     if ((s = fbc_timing_read(c, &ms0, &n0)) != FBC_OK) return s;   // drop earlier records
-    double best = 1e300;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, FBC_E_DEVICE, "hipEventCreate failed");
+    }
+    double best = 1e300, best_gemm = 0.0;
     int best_split = c->nsplit, best_order = c->job_order, ncand = 0;
-    for (int order = 0; order < 3; ++order)
-        for (int ks = 1; ks <= c->nsplit_cap; ks *= 2) {
-            if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) return s;
-            if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) return s;       // warm-up
-            if ((s = fbc_timing_read(c, &ms0, &n0)) != FBC_OK) return s;
-            for (int r = 0; r < reps; ++r)
-                if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) return s;
+    for (int order = 0; order < 3 && s == FBC_OK; ++order)
+        for (int ks = 1; ks <= c->nsplit_cap && s == FBC_OK; ks *= 2) {
+            if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) break;
+            if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) break;       // warm-up
+            if ((s = fbc_timing_read(c, &ms0, &n0)) != FBC_OK) break;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps && s == FBC_OK; ++r) s = fbc_green_apply(c, f, w, stream);
+            if (s != FBC_OK) break;
+            (void)hipEventRecord(e1, st);
             double ms;
             int n;
-            if ((s = fbc_timing_read(c, &ms, &n)) != FBC_OK) return s;
-            ms /= std::max(1, n);
+            if ((s = fbc_timing_read(c, &ms, &n)) != FBC_OK) break;
+            float call = 0.0f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&call, e0, e1) != hipSuccess) {
+                s = fail(c, FBC_E_DEVICE, "hipEventElapsedTime failed");
+                break;
+            }
             ++ncand;
-            if (ms < best) {
-                best = ms;
+            if (call / reps < best) {
+                best = call / reps;
+                best_gemm = ms / std::max(1, n);
                 best_split = ks;
                 best_order = order;
             }
         }
-    if ((s = upload_jobs(c, best_split, best_order, st)) != FBC_OK) return s;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s == FBC_OK) s = upload_jobs(c, best_split, best_order, st);
     c->timing = timing;
+    if (s != FBC_OK) return s;
     if (out) {
         out->nsplit = best_split;
         out->order = best_order;
-        out->gemm_ms = best;
+        out->gemm_ms = best_gemm;
         out->n_candidates = ncand;
+        out->call_ms = best;
     }
     return FBC_OK;
 }

@@ -236,8 +236,8 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                                                   const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
     const int esc = (FORM == FBC_FORM_SPLIT_FP16) ? *bexp : 0;   // power-of-two operand scale
-    // RHS fastest across blocks: the 8 RHS of a column tile, whose B fragments share
-    // 256-byte lines, are written by neighbouring blocks close in time
+    // RHS fastest across blocks: the 8 RHS of a column tile, whose 64-byte column runs
+    // fill the same 1 KiB fragment blocks, are written by neighbouring blocks close in time
     const int r = blockIdx.x;
     const int K = 3 * n_i;
     const int nseq = tc >> 1;

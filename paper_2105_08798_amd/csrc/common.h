@@ -33,23 +33,29 @@ typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 // Output of the 16x16 MFMAs: FP64 c[j] = C[4 j + l/16][l%16];
 //                            FP32 c[j] = C[4 (l/16) + j][l%16].
 // K' is padded to a multiple of 64 for every form (zeros).
+// The B operand (the transformed forces, one column per RHS and real/imaginary part)
+// keeps each column's four 16-byte units of a block together: lane l's unit sits at
+// position bpos(l) = 4 (l % 16) + l / 16 of its 1 KiB block, so the forward transform,
+// which produces one column at a time, writes 64-byte runs; a wave still reads the
+// whole block (lane order permuted).
 // ---------------------------------------------------------------------------------
+__host__ __device__ inline int bpos(int lane) { return ((lane & 15) << 2) | (lane >> 4); }
 __host__ __device__ inline int64_t frag_off_f64(int64_t r, int64_t k, int64_t kp) {
     int64_t blk = r >> 4, rr = r & 15;
     int64_t lane = ((k & 3) << 4) | rr;
-    return (((blk * (kp >> 3) + (k >> 3)) * 64 + lane) << 1) + ((k >> 2) & 1);
+    return (((blk * (kp >> 3) + (k >> 3)) * 64 + bpos((int)lane)) << 1) + ((k >> 2) & 1);
 }
 __host__ __device__ inline int64_t frag_off_f32(int64_t r, int64_t k, int64_t kp) {
     int64_t blk = r >> 4, rr = r & 15;
     int64_t lane = ((k & 3) << 4) | rr;
-    return (((blk * (kp >> 4) + (k >> 4)) * 64 + lane) << 2) + ((k >> 2) & 3);
+    return (((blk * (kp >> 4) + (k >> 4)) * 64 + bpos((int)lane)) << 2) + ((k >> 2) & 3);
 }
 // element offset (in bf16 units) of the hi part; the lo part is at +512
 __host__ __device__ inline int64_t frag_off_bf16(int64_t r, int64_t k, int64_t kp) {
     int64_t blk = r >> 4, rr = r & 15;
     int64_t kk = k & 31;
     int64_t lane = ((kk >> 3) << 4) | rr;
-    return ((((blk * (kp >> 5) + (k >> 5)) * 2) * 64 + lane) << 3) + (kk & 7);
+    return ((((blk * (kp >> 5) + (k >> 5)) * 2) * 64 + bpos((int)lane)) << 3) + (kk & 7);
 }
 
 // The dense G^ stores use the same lane map but are K-major across row blocks,

@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
     const int pb = jb.k0 >> 3, pe = jb.k1 >> 3;
     const int64_t mb = jb.mb;
     const double2* a = (const double2*)(A + jb.a_off) + (int64_t)rbw * 64 + lane;   // K-major
-    const double2* b = (const double2*)(B + jb.b_off) + lane;
+    const double2* b = (const double2*)(B + jb.b_off) + bpos(lane);
     d4_t acc[RB][CT];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
     const int qb = jb.k0 >> 4, qe = jb.k1 >> 4;
     const int64_t mb = jb.mb;
     const float4* a = (const float4*)(A + jb.a_off) + (int64_t)rbw * 64 + lane;     // K-major
-    const float4* b = (const float4*)(B + jb.b_off) + lane;
+    const float4* b = (const float4*)(B + jb.b_off) + bpos(lane);
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
 #pragma unroll
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
     // 16-byte units: per (block, t): hi run of 64 units then lo run of 64 units
     const int64_t mb = jb.mb;
     const VT* a = (const VT*)(A + jb.a_off) + (int64_t)rbw * 128 + lane;      // K-major
-    const VT* b = (const VT*)(B + jb.b_off) + lane;
+    const VT* b = (const VT*)(B + jb.b_off) + bpos(lane);
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
 #pragma unroll
@@ -319,8 +319,9 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
         const int tw = wrap_k(t, kt);
 #pragma unroll
         for (int j = 0; j < NU; ++j) {
+            // LDS in lane order, global in column-run order
             const int u = tid + 256 * j, c = u >> 7, rem = u & 127;
-            stage[j] = b[((int64_t)c * kt + tw) * 128 + rem];
+            stage[j] = b[((int64_t)c * kt + tw) * 128 + (rem & 64) + bpos(rem & 63)];
         }
     };
     auto store_b = [&](int buf) {
@@ -534,7 +535,7 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
             for (int p = 0; p < 6; ++p)
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    vb[p][c] = (c < nca) ? *(const double2*)&bm[((int64_t)c * kp8 + p0 + p) * 128 + 2 * lane]
+                    vb[p][c] = (c < nca) ? *(const double2*)&bm[((int64_t)c * kp8 + p0 + p) * 128 + 2 * bpos(lane)]
                                          : make_double2(0.0, 0.0);
         }
     };
@@ -562,9 +563,10 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
                 for (int c = 0; c < CT; ++c) bcur[p][c] = vb[p][c];
         } else {
             const int p0 = (6 * wrap_k(i0, ni8)) >> 3;
-            for (int e = tid; e < CT * 768; e += 128) {
+            for (int e = tid; e < CT * 768; e += 128) {      // LDS in lane order
                 const int ct = e / 768, x = e - ct * 768;
-                Bs[e] = (ct < nca) ? bm[((int64_t)ct * kp8 + p0) * 128 + x] : 0.0;
+                const int pl = x >> 7, l = (x >> 1) & 63, hh = x & 1;
+                Bs[e] = (ct < nca) ? bm[((int64_t)ct * kp8 + p0 + pl) * 128 + 2 * bpos(l) + hh] : 0.0;
             }
         }
         if (i0 + DT_TI < jb.k1) prefetch(i0 + DT_TI);

@@ -74,7 +74,7 @@ class Info(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("nsplit", C.c_int), ("order", C.c_int), ("gemm_ms", C.c_double),
-                ("n_candidates", C.c_int)]
+                ("n_candidates", C.c_int), ("call_ms", C.c_double)]
 
 
 _lib = None
@@ -218,7 +218,8 @@ class FBC:
         self._check(self._lib.fbc_autotune(self.ctx, _dptr(f), _dptr(w), int(reps), C.byref(r),
                                            _stream_handle(stream)))
         self.info = self.get_info()
-        return dict(nsplit=r.nsplit, order=r.order, gemm_ms=r.gemm_ms, n_candidates=r.n_candidates)
+        return dict(nsplit=r.nsplit, order=r.order, gemm_ms=r.gemm_ms, n_candidates=r.n_candidates,
+                    call_ms=r.call_ms)
 
     def green_apply(self, f, w, stream=None):
         self._check(self._lib.fbc_green_apply(self.ctx, _dptr(f), _dptr(w), _stream_handle(stream)))
