@@ -1031,8 +1031,8 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
         const unsigned long long* am = f16 ? c->amax + c->amax_off[ci] : nullptr;
         const int* be = f16 ? c->bexp + ci : nullptr;
         int tr, pp;
-        if (!update_shape(p.nz, &tr, &pp)) {
-            // long lines: inverse transform into w, then the tiled transpose-update
+        if (!update_shape(p.nz, p.M, p.ctr, &tr, &pp)) {
+            // long or short lines: inverse transform into w, then the tiled transpose-update
             double* uc = u + p.u_off;
             double* sp = c->sum_part + c->sum_part_off[ci];
             launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,

@@ -758,26 +758,24 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
     }
 }
 
-// Shape of the fused update's work groups: tr rows (16 where the line allows: 128-byte
-// runs of u) x one RHS pair x (Nz + 1) complex values of LDS, at most 64 KiB (measured on
-// MI355X: one pair per group with the pair groups sharing the product records through
-// L2 beats two or four pairs per group).  Returns false where fewer than 8 rows fit (long lines) or the line is shorter than 16:
-// the update then goes through the w scratch and the tiled transpose instead.
-bool update_shape(int nz, int* tr, int* pp) {
-    constexpr int budget = 4096;                  // complex values (64 KiB)
-    int t = 16;
-    const int p = 1;
-    while (t > 1 && t * p * (nz + 1) > budget) t >>= 1;
-    *tr = t;
-    *pp = p;
-    return t >= 8 && nz >= 16;
-}
-
-int update_blocks(int nz, int M, int ct_grid) {
-    int tr, pp;
-    update_shape(nz, &tr, &pp);
+// Shape of the fused update's work groups: 8 rows (64-byte runs of u; 33 KiB of LDS at
+// Nz = 256) x one RHS pair.  Measured on MI355X (medium and large workloads, autotuned
+// lists): 8 rows beat 4 (fewer groups in flight are not the limit; the read amplification
+// of 32-byte runs is) and match or beat 16 (half the groups per CU); one pair per group,
+// the pair groups sharing the product records through L2, beats two or four pairs per
+// group.  Returns false outside 16 <= Nz <= 256: the update then goes through the w
+// scratch and the tiled transpose.
+static int update_groups(int tr, int pp, int M, int ct_grid) {
     const int n_units = ct_grid * ((M + tr - 1) / tr);
     return 8 * (4 / pp) * ((n_units + 7) / 8);
+}
+
+bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp) {
+    (void)M;
+    (void)ct_grid;
+    *pp = 1;
+    *tr = 8;
+    return nz >= 16 && nz <= 256;
 }
 
 void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
@@ -788,10 +786,10 @@ void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int 
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int tr, pp;
-    update_shape(nz, &tr, &pp);
+    update_shape(nz, M, ct_grid, &tr, &pp);
     const int n_rg = (M + tr - 1) / tr;
     const int n_units = ct_grid * n_rg;
-    const int nblk = update_blocks(nz, M, ct_grid);
+    const int nblk = update_groups(tr, pp, M, ct_grid);
     const size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
 #define UPD_CASE(NS) \
     hipLaunchKernelGGL(k_irfft_update<NS>, dim3(nblk), dim3(NT), lds, st, c, u, R, nz, logn, mp, M, tr, \

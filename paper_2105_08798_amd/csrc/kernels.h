@@ -61,7 +61,7 @@ void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, 
                  int R, int nz, int M, const int* status);
 // fused inverse transform + update (fbc_apply, fbc_green_apply), and the mean it removes;
 // update_shape is false where the line is too long for the fused kernel
-bool update_shape(int nz, int* tr, int* pp);
+bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp);
 void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
                          int ct_grid, const double2* tw, int nsplit, int64_t split_stride,
                          const double2* rowmean, const double2* shat, const unsigned long long* amax,
