@@ -35,6 +35,22 @@ static __device__ inline void store_c_f32acc(double* __restrict__ c, const GemmJ
     }
 }
 
+// Loads of the stored G^ blocks: every byte is read once per update, so they go out as
+// nontemporal (streaming) loads and do not push the f^ fragments, the partial outputs and
+// the caller's arrays out of L2 and the Infinity Cache (measured on MI355X: the products
+// run 8-11 % faster than with ordinary loads).
+__device__ inline double2 ld_stream(const double2* p) {
+    typedef double dv2_t __attribute__((ext_vector_type(2)));
+    const dv2_t v = __builtin_nontemporal_load((const dv2_t*)p);
+    return make_double2(v[0], v[1]);
+}
+__device__ inline float4 ld_stream(const float4* p) {
+    const f4_t v = __builtin_nontemporal_load((const f4_t*)p);
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline bf8_t ld_stream(const bf8_t* p) { return __builtin_nontemporal_load(p); }
+__device__ inline h8_t ld_stream(const h8_t* p) { return __builtin_nontemporal_load(p); }
+
 // ------------------------------- FP64 ---------------------------------------------
 // Branch-free main loop: the planner pads rows to whole work-group tiles (zero rows),
 // K' to a multiple of 64 and gives every cell of a context the same column-tile count,
@@ -71,7 +87,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
     for (int u = 0; u < PF; ++u) {
         const int pw = wrap_k(pb + u, kp8);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)pw * mb + r) * 64];
+        for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)pw * mb + r) * 64));
 #pragma unroll
         for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pw) * 64];
     }
@@ -88,7 +104,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
                             h ? ab[u][r].y : ab[u][r].x, h ? bb[u][c].y : bb[u][c].x, acc[r][c], 0, 0, 0);
             const int pn = wrap_k(min(p0 + u + PF, pe - 1), kp8);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)pn * mb + r) * 64];
+            for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)pn * mb + r) * 64));
 #pragma unroll
             for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pn) * 64];
         }
@@ -136,7 +152,7 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
     for (int u = 0; u < PF; ++u) {
         const int qw = wrap_k(qb + u, kq);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)qw * mb + r) * 64];
+        for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)qw * mb + r) * 64));
 #pragma unroll
         for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qw) * 64];
     }
@@ -155,7 +171,7 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
                     }
             const int qn = wrap_k(min(q0 + u + PF, qe - 1), kq);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) ab[u][r] = a[((int64_t)qn * mb + r) * 64];
+            for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)qn * mb + r) * 64));
 #pragma unroll
             for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qn) * 64];
         }
@@ -225,8 +241,8 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
         const int tw = wrap_k(tb + u, kt);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = a[((int64_t)tw * mb + r) * 128];
-            al[u][r] = a[((int64_t)tw * mb + r) * 128 + 64];
+            ah[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128));
+            al[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128 + 64));
         }
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
@@ -255,8 +271,8 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
             const int tn = wrap_k(min(t0 + u + PF, te - 1), kt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                ah[u][r] = a[((int64_t)tn * mb + r) * 128];
-                al[u][r] = a[((int64_t)tn * mb + r) * 128 + 64];
+                ah[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128));
+                al[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128 + 64));
             }
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
@@ -342,8 +358,8 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
         const int tl = wrap_k(min(tb + u, te - 1), kt);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = a[((int64_t)tl * mb + r) * 128];
-            al[u][r] = a[((int64_t)tl * mb + r) * 128 + 64];
+            ah[u][r] = ld_stream(a + (((int64_t)tl * mb + r) * 128));
+            al[u][r] = ld_stream(a + (((int64_t)tl * mb + r) * 128 + 64));
         }
     }
     load_b(tb);
@@ -382,8 +398,8 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
             const int tn = wrap_k(min(t + PFA, te - 1), kt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                ah[u][r] = a[((int64_t)tn * mb + r) * 128];
-                al[u][r] = a[((int64_t)tn * mb + r) * 128 + 64];
+                ah[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128));
+                al[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128 + 64));
             }
             if (((t - tb + 1) % KCH) == 0 || !more) {
 #pragma unroll
