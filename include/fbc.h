@@ -171,9 +171,10 @@ fbc_status fbc_green_apply(fbc_ctx* ctx, const double* f, double* w, void* strea
 fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alpha, void* stream);
 
 /* Autotuner of the per-mode product launch.  Times every candidate work list -- K split
- * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times three
- * orders: 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first
- * -- with `reps` fbc_green_apply calls each on this context (input f, device; w, device,
+ * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times the orders:
+ * 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first, and for
+ * the offset-table form 3 persistent (jobs longest first, taken from a device work queue
+ * by as many work groups as fit on the chip) -- with `reps` fbc_green_apply calls each on this context (input f, device; w, device,
  * same layout as u, is overwritten with G f), keeps the list with the fastest whole call
  * (the K slices also cost the inverse transform a read each) and reports it in *out (may
  * be NULL).  Synchronises the stream. */
@@ -186,6 +187,15 @@ typedef struct {
 } fbc_tune_result;
 fbc_status fbc_autotune(fbc_ctx* ctx, const double* f, double* w, int reps, fbc_tune_result* out,
                         void* stream);
+
+/* Pins the work list of the per-mode product: nsplit K slices (1 .. the context's limit,
+ * fbc_info.nsplit after assembly is the default) in the given order (as listed for
+ * fbc_autotune; 3 only for FBC_FORM_DTABLE_FP64; the surrogate form accepts only its own
+ * list, nsplit 1, order 1).  Results do not depend on the order (every order partitions
+ * the same products); the number of K slices changes only the rounding (the slices'
+ * partial sums are added in fixed order).  A captured update
+ * (fbc_apply_graph) is captured again on its next call.  Synchronises the stream. */
+fbc_status fbc_set_work_list(fbc_ctx* ctx, int nsplit, int order, void* stream);
 
 /* Residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2). */
 typedef struct {

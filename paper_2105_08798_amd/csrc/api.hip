@@ -611,7 +611,9 @@ static void product_stats(fbc_ctx* c) {
 //      dispatched round-robin over the 8 XCDs by block index), so the B fragments of a
 //      mode are shared through one XCD's L2;
 //   1  mode-major: units by table mode, so every XCD works on the same table slice;
-//   2  longest-first: units by cost, natural order.
+//   2  longest-first: units by cost, natural order;
+//   3  (offset-table forms) jobs longest first, consumed by the persistent work-queue
+//      kernel: each work group takes the next job as it finishes the last.
 // ----------------------------------------------------------------------------------
 struct Unit {
     int cell, m, t;
@@ -669,8 +671,12 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) 
         return out;
     }
     std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
-    if (order == 2) {
+    if (order == 2 || order == 3) {
         for (const Unit& u : units) unit_jobs(c, u, nsplit, out);
+        if (order == 3)
+            std::stable_sort(out.begin(), out.end(), [](const GemmJob& a, const GemmJob& b) {
+                return (a.k1 - a.k0) > (b.k1 - b.k0);
+            });
         return out;
     }
     std::vector<std::vector<GemmJob>> per_xcd(8);
@@ -997,11 +1003,12 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
             const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
             launch_gemm_dtab(st, c->jobs + j0, j1 - j0, c->ctmax, c->gen, (int64_t)t0 * c->n_offsets * 6,
                              (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2,
-                             c->n_need, c->n_offsets);
+                             c->n_need, c->n_offsets, nullptr);
         }
     } else if (form == FBC_FORM_DTABLE_FP64)
         launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, 0, (const double*)c->bfrag, c->cbuf,
-                         c->celldev, c->lut, c->d1min, c->d2min, c->w2, nullptr, c->n_offsets);
+                         c->celldev, c->lut, c->d1min, c->d2min, c->w2, nullptr, c->n_offsets,
+                         c->job_order == 3 ? c->status + 8 : nullptr);
     else
         launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf);
     if (tm) {
@@ -1132,7 +1139,8 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
     }
     double best = 1e300, best_gemm = 0.0;
     int best_split = c->nsplit, best_order = c->job_order, ncand = 0;
-    for (int order = 0; order < 3 && s == FBC_OK; ++order)
+    const int n_orders = is_table_form(c->opt.form) ? 4 : 3;
+    for (int order = 0; order < n_orders && s == FBC_OK; ++order)
         for (int ks = 1; ks <= c->nsplit_cap && s == FBC_OK; ks *= 2) {
             if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) break;
             if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) break;       // warm-up
@@ -1170,6 +1178,18 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
         out->call_ms = best;
     }
     return FBC_OK;
+}
+
+extern "C" fbc_status fbc_set_work_list(fbc_ctx* c, int nsplit, int order, void* stream) {
+    if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
+    if (nsplit < 1 || nsplit > c->nsplit_cap)
+        return fail(c, FBC_E_ARG, "nsplit must be in [1, " + std::to_string(c->nsplit_cap) + "]");
+    if (order < 0 || order > 3) return fail(c, FBC_E_ARG, "order must be 0, 1, 2 or 3");
+    if (order == 3 && !is_table_form(c->opt.form))
+        return fail(c, FBC_E_UNSUPPORTED, "the persistent work list (order 3) needs an offset-table form");
+    if (c->opt.form == FBC_FORM_SURROGATE && (nsplit != 1 || order != 1))
+        return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major list (nsplit 1, order 1)");
+    return upload_jobs(c, nsplit, order, (hipStream_t)stream);
 }
 
 extern "C" fbc_status fbc_green_apply(fbc_ctx* c, const double* f, double* w, void* stream) {

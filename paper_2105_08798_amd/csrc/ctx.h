@@ -34,12 +34,13 @@ struct fbc_ctx {
     double* sum_part = nullptr;
     double* mean = nullptr;         // [total_rhs][3]
     double2* tw = nullptr;          // twiddle tables
-    int* status = nullptr;          // device latch
+    int* status = nullptr;          // 64 bytes: [0] device latch; [8], [9] work queue of the
+                                    // persistent product (next job, groups done), zero between launches
     GemmJob* jobs = nullptr;
     int njobs = 0;
     int nsplit = 1;                 // K slices of the per-mode product
     int nsplit_cap = 1;             // K slices the output buffer holds
-    int job_order = 0;              // see build_jobs
+    int job_order = 0;              // see build_jobs (3: persistent kernel, offset-table forms)
     int64_t jobs_cap = 0;
     // captured update (fbc_apply_graph)
     hipGraph_t graph = nullptr;

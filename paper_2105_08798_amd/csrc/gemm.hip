@@ -476,16 +476,15 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 // Register-prefetch pipeline: the gathers of chunk i+1 are issued right after chunk i has
 // been written to LDS, so their latency hides behind the MFMAs of chunk i.  jb.ct_active
 // column tiles carry RHS of this cell; the others are skipped.
+// One job of the offset-table product.  Every thread of the work group calls it with the
+// same job (its barriers are uniform); it leaves LDS free for the next job once a barrier
+// has followed it.
 template <int CT>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
-k_gemm_dtab(const GemmJob* __restrict__ jobs,
-                                                   const double2* __restrict__ tab, int64_t a_base,
-                                                   const double* __restrict__ B,
-                                                   double* __restrict__ C,
-                                                   const CellDev* __restrict__ cells,
-                                                   const int32_t* __restrict__ lut, int d1min,
-                                                   int d2min, int w2,
-                                                   const int32_t* __restrict__ need, int64_t n_off) {
+__device__ inline void dtab_job(const GemmJob& jb, const double2* __restrict__ tab, int64_t a_base,
+                                const double* __restrict__ B, double* __restrict__ C,
+                                const CellDev* __restrict__ cells, const int32_t* __restrict__ lut,
+                                int d1min, int d2min, int w2, const int32_t* __restrict__ need,
+                                int64_t n_off) {
     // A chunk in natural order [row][k'] with an odd row stride: the gathering threads'
     // 8-byte writes and the MFMA lanes' 8-byte reads both fall into distinct banks
     constexpr int AS = 49;
@@ -494,7 +493,6 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
     // groups fit per CU); more tiles are staged in LDS once for both waves
     __shared__ double Bs[(CT <= 2 ? 1 : CT * 6 * 128)];   // [ct][p][lane][2]
     __shared__ int scb[2 * DT_TB];
-    const GemmJob jb = jobs[blockIdx.x];
     if (jb.mb == 0) return;
     const CellDev cd = cells[jb.cell];
     const int nca = jb.ct_active;
@@ -620,12 +618,81 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs,
             if (c < nca) store_c_f64(C, jb, jb.rb0 + 3 * wave + r, c, lane, acc[r][c]);
 }
 
+// One work group per job, in list order.
+template <int CT>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
+k_gemm_dtab(const GemmJob* __restrict__ jobs, const double2* __restrict__ tab, int64_t a_base,
+            const double* __restrict__ B, double* __restrict__ C, const CellDev* __restrict__ cells,
+            const int32_t* __restrict__ lut, int d1min, int d2min, int w2,
+            const int32_t* __restrict__ need, int64_t n_off) {
+    dtab_job<CT>(jobs[blockIdx.x], tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
+}
+
+// Persistent form: as many work groups as fit on the chip at once, each taking the next
+// job of the list from a device counter until the list is exhausted (with the list
+// longest first, the groups that finish early take the short jobs: dynamic longest-
+// processing-time scheduling of uneven cells).  queue[0] is the next job, queue[1]
+// counts the groups that have left; the last one to leave sets both back to zero for
+// the next launch (so the launch can be replayed from a graph).  Every group leaves as
+// soon as it draws an index past the list.
+template <int CT>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
+k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+               const double2* __restrict__ tab, int64_t a_base, const double* __restrict__ B,
+               double* __restrict__ C, const CellDev* __restrict__ cells,
+               const int32_t* __restrict__ lut, int d1min, int d2min, int w2,
+               const int32_t* __restrict__ need, int64_t n_off) {
+    __shared__ int slot;
+    for (;;) {
+        if (threadIdx.x == 0) slot = atomicAdd(&queue[0], 1);
+        __syncthreads();
+        const int j = slot;
+        __syncthreads();                 // every thread has read slot; LDS of the last job free
+        if (j >= njobs) break;
+        dtab_job<CT>(jobs[j], tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&queue[0], 0);
+            atomicExch(&queue[1], 0);
+        }
+    }
+}
+
+template <int CT>
+static int dtab_pq_groups() {
+    static int groups = 0;               // per process; the library runs on one device type
+    if (groups == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_dtab_pq<CT>, 128, 0);
+        groups = std::max(1, per_cu) * std::max(1, cus);
+    }
+    return groups;
+}
+
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
                       const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
-                      int64_t n_off) {
+                      int64_t n_off, int* queue) {
     if (njobs <= 0) return;
-    dim3 grid(njobs), blk(128);
+    dim3 blk(128);
+    if (queue) {
+#define PQ_CASE(CT)                                                                             \
+    hipLaunchKernelGGL(k_gemm_dtab_pq<CT>, dim3(std::min(njobs, dtab_pq_groups<CT>())), blk, 0, st, jobs, \
+                       njobs, queue, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off)
+        switch (ct) {
+            case 1: PQ_CASE(1); break;
+            case 2: PQ_CASE(2); break;
+            case 4: PQ_CASE(4); break;
+            default: PQ_CASE(8); break;
+        }
+#undef PQ_CASE
+        return;
+    }
+    dim3 grid(njobs);
     switch (ct) {
         case 1: hipLaunchKernelGGL(k_gemm_dtab<1>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
         case 2: hipLaunchKernelGGL(k_gemm_dtab<2>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;

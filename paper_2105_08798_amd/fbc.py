@@ -24,7 +24,7 @@ EXPORTED = [
     "fbc_default_options", "fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin",
     "fbc_relax_step", "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_destroy",
     "fbc_last_error", "fbc_status_string", "fbc_timing", "fbc_timing_read", "fbc_apply_graph",
-    "fbc_autotune", "fbc_learned_last_error", "fbc_sur_create", "fbc_sur_destroy", "fbc_sur_set_mlp",
+    "fbc_autotune", "fbc_set_work_list", "fbc_learned_last_error", "fbc_sur_create", "fbc_sur_destroy", "fbc_sur_set_mlp",
     "fbc_sur_eval", "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_destroy", "fbc_mlp_num_params",
     "fbc_mlp_params", "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
 ]
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_copy_block_rows.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
     lib.fbc_apply_graph.argtypes = [vp, vp, vp, C.c_double, vp]
     lib.fbc_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(TuneResult), vp]
+    lib.fbc_set_work_list.argtypes = [vp, C.c_int, C.c_int, vp]
     lib.fbc_timing.argtypes = [vp, C.c_int]
     lib.fbc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.fbc_destroy.argtypes = [vp]
@@ -128,7 +129,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
-                 "fbc_apply_graph", "fbc_autotune", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
+                 "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
                  "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_num_params", "fbc_mlp_params",
                  "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward"):
         getattr(lib, name).restype = C.c_int
@@ -212,6 +213,10 @@ class FBC:
 
     def apply_graph(self, f, u, alpha: float = 1.0, stream=None):
         self._check(self._lib.fbc_apply_graph(self.ctx, _dptr(f), _dptr(u), float(alpha), _stream_handle(stream)))
+
+    def set_work_list(self, nsplit: int, order: int, stream=None):
+        self._check(self._lib.fbc_set_work_list(self.ctx, int(nsplit), int(order), _stream_handle(stream)))
+        self.info = self.get_info()
 
     def autotune(self, f, w, reps: int = 3, stream=None) -> dict:
         r = TuneResult()

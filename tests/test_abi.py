@@ -112,3 +112,9 @@ def test_learned_calls_reject_bad_arguments_on_the_host():
     assert lib.fbc_mlp_loss_grad(None, None, None, 1, None, None) == -1
     assert lib.fbc_mlp_adam_step(None, C.c_float(1e-3), None) == -1
     assert lib.fbc_learned_last_error()
+
+
+def test_tune_result_layout_and_null_context_work_list():
+    fbc, lib = _lib()
+    assert C.sizeof(fbc.TuneResult) == 32
+    assert lib.fbc_set_work_list(None, 1, 0, None) == -1

@@ -366,3 +366,65 @@ def test_negligible_block_skipping(form, tol):
     ref = oap.apply_green(oracle_green(c, wl.bz), c.forces)
     e2, _ = rel_err(out["skip"][0], ref)
     assert e2 < max(tol, 1e-10), (form, e2)
+
+
+def test_work_lists_give_identical_results():
+    """Every order of the work list (incl. the persistent work-queue kernel of the
+    offset-table form) partitions the same products, so for a given number of K slices
+    the update is bit-identical; other slice counts change only the rounding.  The
+    persistent kernel's queue is reset for the next launch (repeated calls and graph
+    replays agree)."""
+    dev = _dev()
+    cells = W.make_custom(16, 30, 45, 3, 32, seed=1).cells + W.make_custom(8, 12, 20, 10, 32, seed=2).cells \
+        + W.make_custom(32, 50, 60, 1, 32, seed=3).cells
+    wl = W.Workload("three", cells, bz=32)
+    f = torch.from_numpy(np.concatenate([c.forces.ravel() for c in wl.cells])).to(dev)
+    n_u = sum(c.n_rhs * c.nz * c.n_b * 3 for c in wl.cells)
+    ctx = _ctx(wl.cells, wl.bz, form="dtable_fp64")
+    ref = None
+    stream = torch.cuda.Stream()
+    for nsplit in (2, 1):
+        ref_split = None
+        for order in (0, 1, 2, 3):
+            ctx.set_work_list(nsplit, order)
+            assert ctx.info.nsplit == nsplit and ctx.info.job_order == order
+            for rep in range(2):
+                w = torch.zeros(n_u, dtype=torch.float64, device=dev)
+                ctx.green_apply(f, w)
+                assert ctx.sync_status() == 0
+                got = w.cpu().numpy()
+                if ref_split is None:
+                    ref_split = got
+                assert np.array_equal(got, ref_split), (nsplit, order, rep)
+        if ref is not None:
+            assert np.abs(ref_split - ref).max() <= 1e-13 * np.abs(ref).max()
+        ref = ref_split
+    # persistent list replayed from a captured graph, with eager calls in between
+    ctx.set_work_list(1, 3)
+    u0 = torch.zeros(n_u, dtype=torch.float64, device=dev)
+    u_eager = u0.clone()
+    ctx.apply(f, u_eager, alpha=1.0)
+    torch.cuda.synchronize()
+    u = torch.empty_like(u0)          # one buffer: the first call captures, the rest replay
+    for rep in range(3):
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        ctx.apply_graph(f, u, alpha=1.0, stream=stream)
+        stream.synchronize()
+        assert np.array_equal(u.cpu().numpy(), u_eager.cpu().numpy()), rep
+        w = torch.zeros(n_u, dtype=torch.float64, device=dev)
+        ctx.green_apply(f, w)
+        assert np.array_equal(w.cpu().numpy(), ref), rep
+    assert ctx.sync_status() == 0
+    ctx.close()
+
+
+def test_work_list_arguments_checked():
+    _dev()
+    wl = W.make_single("parity")
+    from paper_2105_08798_amd.fbc import FbcError
+    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    for nsplit, order in ((0, 0), (1, 4), (1, 3), (1 << 20, 0)):
+        with pytest.raises(FbcError):
+            ctx.set_work_list(nsplit, order)
+    ctx.close()
