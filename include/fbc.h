@@ -202,6 +202,9 @@ typedef struct {
     int relax;        /* 1: relax from the third iteration on (Algorithm 1 line 5)        */
     double du_max;    /* > 0: bound ||alpha G f||_inf by du_max (Algorithm 2 lines 6-8)   */
     double tol_f;     /* convergence flag: ||f_in||_inf < tol_f (Section 2.3.3)           */
+    double alpha_min; /* > 0: lower bound on alpha_{k+1} (the preprint's variant, Remark in
+                         Section 2.3.3), applied after the reset of negative values and
+                         before the du_max bound; 0: off                                   */
 } fbc_relax_opts;
 
 /* Per RHS, written to device memory by fbc_relax_step (packed over all cells' RHS). */

@@ -12,8 +12,13 @@ Relax always receives the raw (unscaled) incompatibility forces; then the pad
 update and mean removal.  The incompatibility-force criterion of Section 2.3.3
 (||f_in||_inf < tol) is reported as the convergence flag.
 
+Variant (the Remark in Section 2.3.3, the preprint's choice): a lower bound alpha_min on
+alpha_{k+1} in place of the incompatibility-force criterion.
+
 Readings where the paper is silent: a zero denominator keeps alpha_{k+1} = alpha_k;
-every RHS is an independent FBC iteration with its own alpha.
+every RHS is an independent FBC iteration with its own alpha; the lower bound acts after
+the reset of negative values and before the optional step bound (which stays a hard
+bound on the step).
 """
 from __future__ import annotations
 
@@ -24,8 +29,10 @@ import numpy as np
 from .apply import pad_update
 
 
-def relax_alpha(f_new: np.ndarray, f_old: np.ndarray, alpha_old: np.ndarray) -> np.ndarray:
-    """Algorithm 2 lines 1-4, per RHS (leading axis)."""
+def relax_alpha(f_new: np.ndarray, f_old: np.ndarray, alpha_old: np.ndarray,
+                alpha_min: float = 0.0) -> np.ndarray:
+    """Algorithm 2 lines 1-4, per RHS (leading axis); alpha_min > 0: the lower bound of the
+    Remark in Section 2.3.3."""
     n = f_new.shape[0]
     fn = f_new.reshape(n, -1)
     fo = f_old.reshape(n, -1)
@@ -36,6 +43,8 @@ def relax_alpha(f_new: np.ndarray, f_old: np.ndarray, alpha_old: np.ndarray) -> 
     nz = den > 0.0
     out[nz] = -alpha_old[nz] * num[nz] / den[nz]
     out[out < 0.0] = 1.0
+    if alpha_min > 0.0:
+        out = np.maximum(out, alpha_min)
     return out
 
 
@@ -53,6 +62,7 @@ class RelaxState:
     relax: bool = True
     du_max: float = 0.0          # <= 0 disables the step bound
     tol_f: float = 1e-3
+    alpha_min: float = 0.0       # > 0: lower bound on alpha (Remark in Section 2.3.3)
     k: int = 0
     alpha: np.ndarray = field(default=None)
     f_prev: np.ndarray = field(default=None)
@@ -70,7 +80,7 @@ def relax_step(state: RelaxState, f_new: np.ndarray, u: np.ndarray, apply_fn) ->
     w = apply_fn(f_new)
     w_inf = np.abs(w.reshape(n, -1)).max(axis=1)
     if state.relax and state.k >= 2:
-        alpha = relax_alpha(f_new, state.f_prev, state.alpha)
+        alpha = relax_alpha(f_new, state.f_prev, state.alpha, state.alpha_min)
         if state.du_max > 0.0:
             alpha = clamp_step(alpha, w_inf, state.du_max)
     else:

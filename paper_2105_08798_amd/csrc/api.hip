@@ -1204,7 +1204,8 @@ extern "C" fbc_status fbc_green_apply(fbc_ctx* c, const double* f, double* w, vo
 
 extern "C" fbc_status fbc_relax_begin(fbc_ctx* c, const fbc_relax_opts* o, void* stream) {
     if (!c || !o) return fail(c, FBC_E_ARG, "null argument");
-    if (!(o->du_max >= 0) || !(o->tol_f >= 0)) return fail(c, FBC_E_ARG, "du_max and tol_f must be >= 0");
+    if (!(o->du_max >= 0) || !(o->tol_f >= 0) || !(o->alpha_min >= 0) || !std::isfinite(o->alpha_min))
+        return fail(c, FBC_E_ARG, "du_max, tol_f and alpha_min must be >= 0 (alpha_min finite)");
     c->ropt = *o;
     c->relax_k = 0;
     launch_fill((hipStream_t)stream, c->alpha, c->total_rhs, 1.0);
@@ -1223,7 +1224,8 @@ extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, 
         auto& p = c->cells[ci];
         const int64_t per_rhs = (int64_t)p.nz * p.K;
         launch_relax_alpha(st, f_in + p.f_off, c->fprev + p.f_off, c->rpart + c->rpart_off[ci],
-                           c->alpha + p.rhs0, c->finf + p.rhs0, p.R, per_rhs, k, c->ropt.relax);
+                           c->alpha + p.rhs0, c->finf + p.rhs0, p.R, per_rhs, k, c->ropt.relax,
+                           c->ropt.alpha_min);
     }
     enqueue_forward(c, f_in, st, true);
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {

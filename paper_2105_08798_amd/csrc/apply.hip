@@ -1019,7 +1019,8 @@ __global__ void __launch_bounds__(NT) k_relax_part(const double* __restrict__ fn
 
 __global__ void __launch_bounds__(NT) k_relax_alpha(const double* __restrict__ part, int n_part,
                                                     double* __restrict__ alpha_d,
-                                                    double* __restrict__ finf_d, int use_relax) {
+                                                    double* __restrict__ finf_d, int use_relax,
+                                                    double alpha_min) {
     __shared__ double red[2 * NT];
     const int r = blockIdx.x;
     double v[2] = {0, 0};
@@ -1039,6 +1040,7 @@ __global__ void __launch_bounds__(NT) k_relax_alpha(const double* __restrict__ p
             a = prev;
             if (v[1] > 0.0) a = -prev * v[0] / v[1];
             if (a < 0.0) a = 1.0;
+            if (alpha_min > 0.0) a = fmax(a, alpha_min);   // Remark in Section 2.3.3
         }
         alpha_d[r] = a;
     }
@@ -1046,12 +1048,12 @@ __global__ void __launch_bounds__(NT) k_relax_alpha(const double* __restrict__ p
 
 void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
                         double* alpha_d, double* finf_d, int R, int64_t per_rhs, int k,
-                        int relax) {
+                        int relax, double alpha_min) {
     const int use = (relax && k >= 2) ? 1 : 0;
     hipLaunchKernelGGL(k_relax_part, dim3(RELAX_PARTS, R), dim3(NT), 0, st, fnew, fprev, part,
                        per_rhs, use);
     hipLaunchKernelGGL(k_relax_alpha, dim3(R), dim3(NT), 0, st, part, RELAX_PARTS, alpha_d, finf_d,
-                       use);
+                       use, alpha_min);
 }
 
 // Step bound (Algorithm 2 lines 6-8) from the per-block maxima of |w|.

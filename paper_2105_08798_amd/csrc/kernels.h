@@ -75,7 +75,8 @@ void launch_update_mean(hipStream_t st, const double* u, const double* c, double
 
 // ---- relax (Section 2.3.3, Algorithm 2) ----
 void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
-                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, int k, int relax);
+                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, int k, int relax,
+                        double alpha_min);
 void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, double* alpha_d,
                         double* stepinf_d, int R, double du_max, int k, int relax);
 void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,

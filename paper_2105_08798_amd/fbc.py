@@ -53,7 +53,7 @@ class Options(C.Structure):
 
 
 class RelaxOpts(C.Structure):
-    _fields_ = [("relax", C.c_int), ("du_max", C.c_double), ("tol_f", C.c_double)]
+    _fields_ = [("relax", C.c_int), ("du_max", C.c_double), ("tol_f", C.c_double), ("alpha_min", C.c_double)]
 
 
 class RelaxOut(C.Structure):
@@ -229,8 +229,9 @@ class FBC:
     def green_apply(self, f, w, stream=None):
         self._check(self._lib.fbc_green_apply(self.ctx, _dptr(f), _dptr(w), _stream_handle(stream)))
 
-    def relax_begin(self, relax: bool = True, du_max: float = 0.0, tol_f: float = 1e-3, stream=None):
-        o = RelaxOpts(int(bool(relax)), float(du_max), float(tol_f))
+    def relax_begin(self, relax: bool = True, du_max: float = 0.0, tol_f: float = 1e-3,
+                    alpha_min: float = 0.0, stream=None):
+        o = RelaxOpts(int(bool(relax)), float(du_max), float(tol_f), float(alpha_min))
         self._check(self._lib.fbc_relax_begin(self.ctx, C.byref(o), _stream_handle(stream)))
 
     def relax_step(self, f, u, out=None, stream=None):

@@ -41,6 +41,7 @@ def test_struct_layouts_match_header_sizes():
     fbc, _ = _lib()
     assert C.sizeof(fbc.Cell) == 32
     assert C.sizeof(fbc.RelaxOut) == 56
+    assert C.sizeof(fbc.RelaxOpts) == 32
     assert C.sizeof(fbc.Options) == 64
 
 

@@ -219,8 +219,9 @@ def test_projection_in_reduced_forms(form):
     assert e2 < (2e-5 if form == "split_bf16" else 1e-6), e2
 
 
+@pytest.mark.parametrize("alpha_min", [0.0, 3.0])
 @pytest.mark.parametrize("form", FP64_FORMS)
-def test_relax_sequence_matches_oracle(form):
+def test_relax_sequence_matches_oracle(form, alpha_min):
     wl = W.make_single("parity")
     c = wl.cells[0]
     dev = _dev()
@@ -237,8 +238,8 @@ def test_relax_sequence_matches_oracle(form):
         seq.append(nxt)
     u0 = rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01
     u = torch.from_numpy(u0).to(dev)
-    st = orx.RelaxState(n_rhs=c.n_rhs, relax=True, du_max=0.05, tol_f=0.2)
-    ctx.relax_begin(relax=True, du_max=0.05, tol_f=0.2)
+    st = orx.RelaxState(n_rhs=c.n_rhs, relax=True, du_max=0.05, tol_f=0.2, alpha_min=alpha_min)
+    ctx.relax_begin(relax=True, du_max=0.05, tol_f=0.2, alpha_min=alpha_min)
     out = torch.zeros(c.n_rhs * RELAX_OUT_DOUBLES, dtype=torch.float64, device=dev)
     uref = u0.copy()
     for fk in seq:

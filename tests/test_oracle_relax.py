@@ -32,6 +32,28 @@ def test_alpha_matches_aitken_formula_generic():
         assert np.isclose(out[r], ref if ref >= 0 else 1.0, rtol=1e-14)
 
 
+def test_alpha_lower_bound_variant():
+    """Remark in Section 2.3.3: alpha_{k+1} bounded below by alpha_min.  With
+    f_{k+1} = lambda f_k the unbounded value is alpha_k / (1 - lambda)."""
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=(4, 6, 10, 3))
+    lam = np.array([-3.0, -0.25, 0.5, 1.5])          # 0.25, 0.8, 2, negative (-> 1)
+    a0 = np.ones(4)
+    plain = relax.relax_alpha(lam[:, None, None, None] * f, f, a0)
+    assert np.allclose(plain, [0.25, 0.8, 2.0, 1.0], rtol=1e-13)
+    bounded = relax.relax_alpha(lam[:, None, None, None] * f, f, a0, alpha_min=0.5)
+    assert np.allclose(bounded, [0.5, 0.8, 2.0, 1.0], rtol=1e-13)
+    # a bound above 1 also lifts the reset value of negative alphas
+    assert np.allclose(relax.relax_alpha(1.5 * f, f, a0, alpha_min=1.2), 1.2)
+    # the step bound still caps the bounded value
+    st = relax.RelaxState(n_rhs=1, relax=True, du_max=1e-3, alpha_min=0.9, tol_f=0.0)
+    u = np.zeros((1, 6, 4, 3))
+    apply_fn = lambda g: g[:, :, :4, :]
+    for g in (f[:1], 0.5 * f[:1], -2.0 * f[:1]):
+        u, out = relax.relax_step(st, g, u, apply_fn)
+    assert out["step_inf"][0] <= 1e-3 * (1 + 1e-14)
+
+
 def test_step_clamp():
     a = np.array([2.0, 0.5])
     w_inf = np.array([1.0, 1.0])
