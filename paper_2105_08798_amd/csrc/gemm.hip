@@ -299,17 +299,20 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
 
 // Variant for 4 or 8 column tiles (many RHS): the B fragments of a K step are the same
 // for the four waves of a work group, so they are loaded once per work group into LDS
-// (double buffered, one barrier per step) instead of once per wave from L2; each thread
-// stages CT/2 16-byte units of the next step in registers while the MFMAs of the current
-// step run.  A is streamed from HBM as in k_gemm_split, two steps ahead.
-template <typename VT, int RB, int CT, int PFA, int KCH>
+// (double buffered) instead of once per wave from L2; each thread stages its share of the
+// next S steps in registers while the MFMAs of the current S steps run, and the group
+// meets at one barrier per S steps.  A is streamed from HBM as in k_gemm_split, PFA steps
+// ahead.  K windows and slices hold an even number of steps, so S = 2 needs no tail.
+template <typename VT, int RB, int CT, int PFA, int KCH, int S>
 __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restrict__ jobs,
                                                         const unsigned short* __restrict__ A,
                                                         const unsigned short* __restrict__ B,
                                                         double* __restrict__ C) {
     static_assert(CT >= 2 && (CT % 2) == 0, "B staging assumes an even tile count");
-    static_assert(PFA >= 2 && (PFA % 2) == 0, "A ring depth must be even");
-    constexpr int UNITS = CT * 128;          // 16-byte units of B per step (hi and lo runs)
+    static_assert(S == 1 || S == 2, "one or two K steps per barrier");
+    static_assert(PFA >= 2 * S && (PFA % (2 * S)) == 0, "A ring depth must be a multiple of 2 S");
+    constexpr int STEP_UNITS = CT * 128;     // 16-byte units of B per step (hi and lo runs)
+    constexpr int UNITS = STEP_UNITS * S;
     constexpr int NU = UNITS / 256;          // per thread
     __shared__ VT bs[2][UNITS];
     const GemmJob jb = jobs[blockIdx.x];
@@ -331,12 +334,13 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
     VT stage[NU];
-    auto load_b = [&](int t) {
-        const int tw = wrap_k(t, kt);
+    auto load_b = [&](int t) {              // steps t .. t + S - 1
 #pragma unroll
         for (int j = 0; j < NU; ++j) {
             // LDS in lane order, global in column-run order
-            const int u = tid + 256 * j, c = u >> 7, rem = u & 127;
+            const int u = tid + 256 * j, st = u / STEP_UNITS, u2 = u - st * STEP_UNITS;
+            const int c = u2 >> 7, rem = u2 & 127;
+            const int tw = wrap_k(t + st, kt);
             stage[j] = b[((int64_t)c * kt + tw) * 128 + (rem & 64) + bpos(rem & 63)];
         }
     };
@@ -370,15 +374,17 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
         for (int u = 0; u < PFA; ++u) {
             const int t = t0 + u;
             if (t >= te) break;                    // same for every wave of the group
-            const int buf = u & 1;                 // t - tb has the parity of u (PFA even)
-            const bool more = (t + 1 < te);
-            if (more) load_b(t + 1);
+            const int sidx = u % S;                // step inside the group of S
+            const int buf = (u / S) & 1;           // groups of S alternate (PFA / S even)
+            const bool more = (t + S - sidx < te); // a next group of S steps exists
+            if (sidx == 0 && more) load_b(t + S);
+            const VT* bb = bs[buf] + sidx * STEP_UNITS;
             // two column tiles at a time, the three products of a tile interleaved with
             // the other tile's, so dependent MFMAs are 2 RB instructions apart
 #pragma unroll
             for (int c = 0; c < CT; c += 2) {
-                const VT bh0 = bs[buf][c * 128 + lane], bl0 = bs[buf][c * 128 + 64 + lane];
-                const VT bh1 = bs[buf][(c + 1) * 128 + lane], bl1 = bs[buf][(c + 1) * 128 + 64 + lane];
+                const VT bh0 = bb[c * 128 + lane], bl0 = bb[c * 128 + 64 + lane];
+                const VT bh1 = bb[(c + 1) * 128 + lane], bl1 = bb[(c + 1) * 128 + 64 + lane];
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     ac32[r][c] = mfma_16x16x32(al[u][r], bh0, ac32[r][c]);
@@ -401,7 +407,7 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
                 ah[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128));
                 al[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128 + 64));
             }
-            if (((t - tb + 1) % KCH) == 0 || !more) {
+            if (((t - tb + 1) % KCH) == 0 || t + 1 == te) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -411,8 +417,10 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
                         ac32[r][c] = (f4_t){0, 0, 0, 0};
                     }
             }
-            if (more) store_b(buf ^ 1);
-            __syncthreads();
+            if (sidx == S - 1) {
+                if (more) store_b(buf ^ 1);
+                __syncthreads();
+            }
         }
     }
 #pragma unroll
@@ -453,14 +461,16 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 4, 1, 2, 2);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 8, 4);
-        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 8, 4);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 8, 4, 1);
+        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 8, 4, 1);
     } else {
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 4, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 8, 8);
-        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 8, 8);
+        // two K steps per barrier: 2 % faster than one on the 64-RHS workload (measured;
+        // the split-FP16 kernel gained nothing and keeps one)
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 8, 8, 2);
+        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 8, 8, 2);
     }
 #undef GEMM_CASE
 }
