@@ -190,11 +190,13 @@ fbc_status fbc_autotune(fbc_ctx* ctx, const double* f, double* w, int reps, fbc_
 
 /* Pins the work list of the per-mode product: nsplit K slices (1 .. the context's limit,
  * fbc_info.nsplit after assembly is the default) in the given order (as listed for
- * fbc_autotune; 3 only for FBC_FORM_DTABLE_FP64; the surrogate form accepts only its own
- * list, nsplit 1, order 1).  Results do not depend on the order (every order partitions
- * the same products); the number of K slices changes only the rounding (the slices'
- * partial sums are added in fixed order).  A captured update
- * (fbc_apply_graph) is captured again on its next call.  Synchronises the stream. */
+ * fbc_autotune; 3 only for the offset-table forms; the surrogate form accepts only its
+ * mode-major chunks, nsplit 1, with order 1 (one work group per job) or 3 (default: each
+ * chunk consumed by the persistent kernel, longest job first)).  Results do not depend
+ * on the order (every order partitions the same products); the number of K slices
+ * changes only the rounding (the slices' partial sums are added in fixed order).  A
+ * captured update (fbc_apply_graph) is captured again on its next call.  Synchronises
+ * the stream. */
 fbc_status fbc_set_work_list(fbc_ctx* ctx, int nsplit, int order, void* stream);
 
 /* Residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2). */

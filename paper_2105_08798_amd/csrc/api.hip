@@ -665,7 +665,7 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) 
         }
     }
     std::vector<GemmJob> out;
-    if (order == 1) {
+    if (order == 1 || (order == 3 && c->opt.form == FBC_FORM_SURROGATE)) {
         std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.t < b.t; });
         for (const Unit& u : units) unit_jobs(c, u, nsplit, out);
         return out;
@@ -709,14 +709,9 @@ static fbc_status upload_jobs(fbc_ctx* c, int nsplit, int order, hipStream_t st)
         if (s != FBC_OK) return s;
         c->jobs_cap = (int64_t)jobs.size();
     }
-    HIPCHK(c, hipMemcpyAsync(c->jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    c->njobs = (int)jobs.size();
-    c->nsplit = nsplit;
-    c->job_order = order;
     c->chunk_job0.clear();
     if (c->opt.form == FBC_FORM_SURROGATE && c->gen_modes > 0) {
-        // jobs are in table-mode order (order 1); record where each generated chunk starts
+        // jobs are in table-mode order; record where each generated chunk starts
         const int T = c->nz_max / 2 + 1;
         size_t j = 0;
         for (int t0 = 0; t0 < T; t0 += c->gen_modes) {
@@ -724,7 +719,16 @@ static fbc_status upload_jobs(fbc_ctx* c, int nsplit, int order, hipStream_t st)
             c->chunk_job0.push_back((int)j);
         }
         c->chunk_job0.push_back((int)jobs.size());
+        if (order == 3)      // persistent per chunk: longest job first inside each chunk
+            for (size_t ch = 0; ch + 1 < c->chunk_job0.size(); ++ch)
+                std::stable_sort(jobs.begin() + c->chunk_job0[ch], jobs.begin() + c->chunk_job0[ch + 1],
+                                 [](const GemmJob& a, const GemmJob& b) { return (a.k1 - a.k0) > (b.k1 - b.k0); });
     }
+    HIPCHK(c, hipMemcpyAsync(c->jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->njobs = (int)jobs.size();
+    c->nsplit = nsplit;
+    c->job_order = order;
     if (c->graph_exec) {                 // the captured update refers to the old list
         (void)hipGraphExecDestroy(c->graph_exec);
         (void)hipGraphDestroy(c->graph);
@@ -949,7 +953,11 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     }
     product_stats(c);
     if (form == FBC_FORM_SURROGATE) c->nsplit = 1;     // slices are generated per mode chunk
-    if ((s = upload_jobs(c, c->nsplit, is_table_form(form) ? 1 : 0, st)) != FBC_OK) goto fail_out;
+    // default lists: mode-major for the offset table, mode-major chunks consumed by the
+    // persistent kernel for the surrogate (1 % faster on the long workload), XCD-grouped
+    // for the dense stores
+    if ((s = upload_jobs(c, c->nsplit, form == FBC_FORM_SURROGATE ? 3 : is_table_form(form) ? 1 : 0, st)) != FBC_OK)
+        goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->fprev, c->f_elems * 8)) != FBC_OK) goto fail_out;
     HIPCHK(c, hipStreamSynchronize(st));
     HIPCHK(c, hipGetLastError());
@@ -1003,7 +1011,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
             const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
             launch_gemm_dtab(st, c->jobs + j0, j1 - j0, c->ctmax, c->gen, (int64_t)t0 * c->n_offsets * 6,
                              (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2,
-                             c->n_need, c->n_offsets, nullptr);
+                             c->n_need, c->n_offsets, c->job_order == 3 ? c->status + 8 : nullptr);
         }
     } else if (form == FBC_FORM_DTABLE_FP64)
         launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, 0, (const double*)c->bfrag, c->cbuf,
@@ -1187,8 +1195,8 @@ extern "C" fbc_status fbc_set_work_list(fbc_ctx* c, int nsplit, int order, void*
     if (order < 0 || order > 3) return fail(c, FBC_E_ARG, "order must be 0, 1, 2 or 3");
     if (order == 3 && !is_table_form(c->opt.form))
         return fail(c, FBC_E_UNSUPPORTED, "the persistent work list (order 3) needs an offset-table form");
-    if (c->opt.form == FBC_FORM_SURROGATE && (nsplit != 1 || order != 1))
-        return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major list (nsplit 1, order 1)");
+    if (c->opt.form == FBC_FORM_SURROGATE && (nsplit != 1 || (order != 1 && order != 3)))
+        return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major chunks (nsplit 1, order 1 or 3)");
     return upload_jobs(c, nsplit, order, (hipStream_t)stream);
 }
 

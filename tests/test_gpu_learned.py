@@ -276,6 +276,40 @@ def test_surrogate_form_is_exact_inside_r_c(gen_modes):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
 
 
+def test_surrogate_chunk_lists_identical():
+    """The surrogate's mode-major chunks consumed one work group per job (order 1) or by
+    the persistent work-queue kernel (order 3, longest job first in each chunk) give the
+    same bits; other lists are refused."""
+    from paper_2105_08798_amd import FBC, MLP, Surrogate
+    from paper_2105_08798_amd.fbc import FbcError
+    dev = _dev()
+    net = MLP(max_batch=16, seed=2)
+    sur = Surrogate(r_c=3.0)
+    sur.set_mlp(net)
+    cells = W.make_custom(16, 30, 45, 3, 32, seed=1).cells + W.make_custom(8, 12, 20, 5, 32, seed=2).cells
+    ctx = FBC(cells, 32, form="surrogate", surrogate=sur, gen_modes=2)
+    f = torch.from_numpy(np.concatenate([c.forces.ravel() for c in cells])).to(dev)
+    n_u = sum(c.n_rhs * c.nz * c.n_b * 3 for c in cells)
+    out = {}
+    for order in (1, 3, 1, 3):
+        ctx.set_work_list(1, order)
+        w = torch.zeros(n_u, dtype=torch.float64, device=dev)
+        ctx.green_apply(f, w)
+        assert ctx.sync_status() == 0
+        out.setdefault(order, []).append(w.cpu().numpy())
+    for order in (0, 2):
+        with pytest.raises(FbcError):
+            ctx.set_work_list(1, order)
+    ctx.close()
+    sur.close()
+    net.close()
+    ref = out[1][0]
+    assert np.abs(ref).max() > 0
+    for order in (1, 3):
+        for w in out[order]:
+            assert np.array_equal(w, ref), order
+
+
 def _train(sur, net, ctx, steps=6000, batch=8192, seed=0):
     dev = _dev()
     x, t = sur.training_set(ctx, 1 << 17, seed=seed)
