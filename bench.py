@@ -55,7 +55,9 @@ def algorithmic(cells, form: str, store_bytes: int) -> dict:
 
 
 def kernel_matches(form: str, name: str) -> bool:
-    """Whether a profiled kernel name is the product kernel of a form."""
+    """Whether a profiled kernel name is the product kernel of a form (either launch form:
+    one work group per job, or the persistent work-queue kernel `..._pq`)."""
+    name = name.replace("_pq<", "<")
     if form == "fp64":
         return name.startswith("k_gemm_f64<")
     if form == "fp32":

@@ -172,9 +172,9 @@ fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alph
 
 /* Autotuner of the per-mode product launch.  Times every candidate work list -- K split
  * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times the orders:
- * 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first, and for
- * the offset-table form 3 persistent (jobs longest first, taken from a device work queue
- * by as many work groups as fit on the chip) -- with `reps` fbc_green_apply calls each on this context (input f, device; w, device,
+ * 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first, 3
+ * persistent (jobs longest first, taken from a device work queue by as many work groups
+ * as fit on the chip) -- with `reps` fbc_green_apply calls each on this context (input f, device; w, device,
  * same layout as u, is overwritten with G f), keeps the list with the fastest whole call
  * (the K slices also cost the inverse transform a read each) and reports it in *out (may
  * be NULL).  Synchronises the stream. */
@@ -190,7 +190,7 @@ fbc_status fbc_autotune(fbc_ctx* ctx, const double* f, double* w, int reps, fbc_
 
 /* Pins the work list of the per-mode product: nsplit K slices (1 .. the context's limit,
  * fbc_info.nsplit after assembly is the default) in the given order (as listed for
- * fbc_autotune; 3 only for the offset-table forms; the surrogate form accepts only its
+ * fbc_autotune; the surrogate form accepts only its
  * mode-major chunks, nsplit 1, with order 1 (one work group per job) or 3 (default: each
  * chunk consumed by the persistent kernel, longest job first)).  Results do not depend
  * on the order (every order partitions the same products); the number of K slices

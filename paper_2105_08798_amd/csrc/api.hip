@@ -612,8 +612,9 @@ static void product_stats(fbc_ctx* c) {
 //      mode are shared through one XCD's L2;
 //   1  mode-major: units by table mode, so every XCD works on the same table slice;
 //   2  longest-first: units by cost, natural order;
-//   3  (offset-table forms) jobs longest first, consumed by the persistent work-queue
-//      kernel: each work group takes the next job as it finishes the last.
+//   3  jobs longest first, consumed by the persistent work-queue kernel: each work group
+//      takes the next job as it finishes the last (surrogate form: its mode-major chunks,
+//      longest job first inside each).
 // ----------------------------------------------------------------------------------
 struct Unit {
     int cell, m, t;
@@ -1018,7 +1019,8 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
                          c->celldev, c->lut, c->d1min, c->d2min, c->w2, nullptr, c->n_offsets,
                          c->job_order == 3 ? c->status + 8 : nullptr);
     else
-        launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf);
+        launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf,
+                    c->job_order == 3 ? c->status + 8 : nullptr);
     if (tm) {
         (void)hipEventRecord(c->ev[2 * c->n_timed + 1], st);
         ++c->n_timed;
@@ -1147,8 +1149,7 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
     }
     double best = 1e300, best_gemm = 0.0;
     int best_split = c->nsplit, best_order = c->job_order, ncand = 0;
-    const int n_orders = is_table_form(c->opt.form) ? 4 : 3;
-    for (int order = 0; order < n_orders && s == FBC_OK; ++order)
+    for (int order = 0; order < 4 && s == FBC_OK; ++order)
         for (int ks = 1; ks <= c->nsplit_cap && s == FBC_OK; ks *= 2) {
             if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) break;
             if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) break;       // warm-up
@@ -1193,8 +1194,6 @@ extern "C" fbc_status fbc_set_work_list(fbc_ctx* c, int nsplit, int order, void*
     if (nsplit < 1 || nsplit > c->nsplit_cap)
         return fail(c, FBC_E_ARG, "nsplit must be in [1, " + std::to_string(c->nsplit_cap) + "]");
     if (order < 0 || order > 3) return fail(c, FBC_E_ARG, "order must be 0, 1, 2 or 3");
-    if (order == 3 && !is_table_form(c->opt.form))
-        return fail(c, FBC_E_UNSUPPORTED, "the persistent work list (order 3) needs an offset-table form");
     if (c->opt.form == FBC_FORM_SURROGATE && (nsplit != 1 || (order != 1 && order != 3)))
         return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major chunks (nsplit 1, order 1 or 3)");
     return upload_jobs(c, nsplit, order, (hipStream_t)stream);

@@ -14,6 +14,10 @@
 
 #include "kernels.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 static __device__ inline void store_c_f64(double* __restrict__ c, const GemmJob& jb, int rb,
                                           int ctile, int lane, const d4_t& acc) {
     const int64_t mp = (int64_t)jb.mb * 16;
@@ -51,17 +55,62 @@ __device__ inline float4 ld_stream(const float4* p) {
 __device__ inline bf8_t ld_stream(const bf8_t* p) { return __builtin_nontemporal_load(p); }
 __device__ inline h8_t ld_stream(const h8_t* p) { return __builtin_nontemporal_load(p); }
 
+// Persistent work-queue form of the product kernels: as many work groups as fit on the
+// chip at once, each taking the next job of the list from a device counter until the list
+// is exhausted (with the list longest first, the groups that finish early take the short
+// jobs: dynamic longest-processing-time scheduling of uneven jobs).  queue[0] is the next
+// job, queue[1] counts the groups that have left; the last one to leave sets both back to
+// zero for the next launch (so the launch can be replayed from a graph).  Every group
+// leaves as soon as it draws an index past the list.
+__device__ inline int pq_next(int* __restrict__ queue, int* slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(&queue[0], 1);
+    __syncthreads();
+    const int j = __builtin_amdgcn_readfirstlane(*slot);   // uniform: the job fields go to SGPRs
+    __syncthreads();                     // every thread has read the slot; LDS of the last job free
+    return j;
+}
+__device__ inline void pq_done(int* __restrict__ queue) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&queue[0], 0);
+            atomicExch(&queue[1], 0);
+        }
+    }
+}
+
+// Work groups of a persistent launch: the kernel's occupancy per CU times the CUs
+// (cached per kernel; the library runs on one device type per process).
+static int pq_groups(const void* kernel, int per_cu) {
+    static std::mutex mu;
+    static std::map<const void*, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(kernel);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int g = std::max(1, per_cu) * std::max(1, cus);
+    cache[kernel] = g;
+    return g;
+}
+template <typename K>
+static int pq_groups_of(K kernel, int threads) {
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
+    return pq_groups((const void*)kernel, per_cu);
+}
+
 // ------------------------------- FP64 ---------------------------------------------
 // Branch-free main loop: the planner pads rows to whole work-group tiles (zero rows),
 // K' to a multiple of 64 and gives every cell of a context the same column-tile count,
 // so every wave runs full RB x CT tiles over the whole K; the prefetch index is clamped
 // to the last step instead of being predicated.
 template <int RB, int CT, int PF>
-__global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jobs,
+__device__ inline void gemm_f64_job(const GemmJob& jb,
                                                   const double* __restrict__ A,
                                                   const double* __restrict__ B,
                                                   double* __restrict__ C) {
-    const GemmJob jb = jobs[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
@@ -115,14 +164,30 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
         for (int c = 0; c < CT; ++c) store_c_f64(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
+template <int RB, int CT, int PF>
+__global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jobs, const double* __restrict__ A,
+        const double* __restrict__ B, double* __restrict__ C) {
+    const GemmJob jb = jobs[blockIdx.x];
+    gemm_f64_job<RB, CT, PF>(jb, A, B, C);
+}
+template <int RB, int CT, int PF>
+__global__ void __launch_bounds__(256) k_gemm_f64_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+        const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C) {
+    __shared__ int slot;
+    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+        const GemmJob jb = jobs[j];
+        gemm_f64_job<RB, CT, PF>(jb, A, B, C);
+    }
+    pq_done(queue);
+}
+
 // ------------------------------- FP32 ---------------------------------------------
 // FP32 MFMA with FP32 accumulation inside chunks of KCH*16 real k, FP64 across chunks.
 template <int RB, int CT, int PF, int KCH>
-__global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jobs,
+__device__ inline void gemm_f32_job(const GemmJob& jb,
                                                   const float* __restrict__ A,
                                                   const float* __restrict__ B,
                                                   double* __restrict__ C) {
-    const GemmJob jb = jobs[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
@@ -192,6 +257,23 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
         for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
+template <int RB, int CT, int PF, int KCH>
+__global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jobs, const float* __restrict__ A,
+        const float* __restrict__ B, double* __restrict__ C) {
+    const GemmJob jb = jobs[blockIdx.x];
+    gemm_f32_job<RB, CT, PF, KCH>(jb, A, B, C);
+}
+template <int RB, int CT, int PF, int KCH>
+__global__ void __launch_bounds__(256) k_gemm_f32_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+        const float* __restrict__ A, const float* __restrict__ B, double* __restrict__ C) {
+    __shared__ int slot;
+    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+        const GemmJob jb = jobs[j];
+        gemm_f32_job<RB, CT, PF, KCH>(jb, A, B, C);
+    }
+    pq_done(queue);
+}
+
 // ------------------------------- split BF16 ---------------------------------------
 // G ~ G_hi + G_lo, f ~ f_hi + f_lo; products lo*hi + hi*lo + hi*hi on BF16 MFMA with
 // FP32 accumulation inside chunks of KCH*32 real k, FP64 across chunks.
@@ -205,11 +287,10 @@ __device__ inline f4_t mfma_16x16x32(h8_t a, h8_t b, f4_t c) {
 }
 
 template <typename VT, int RB, int CT, int PF, int KCH>
-__global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ jobs,
+__device__ inline void gemm_split_job(const GemmJob& jb,
                                                     const unsigned short* __restrict__ A,
                                                     const unsigned short* __restrict__ B,
                                                     double* __restrict__ C) {
-    const GemmJob jb = jobs[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
@@ -297,6 +378,23 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
         for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
+template <typename VT, int RB, int CT, int PF, int KCH>
+__global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ jobs, const unsigned short* __restrict__ A,
+        const unsigned short* __restrict__ B, double* __restrict__ C) {
+    const GemmJob jb = jobs[blockIdx.x];
+    gemm_split_job<VT, RB, CT, PF, KCH>(jb, A, B, C);
+}
+template <typename VT, int RB, int CT, int PF, int KCH>
+__global__ void __launch_bounds__(256) k_gemm_split_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+        const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, double* __restrict__ C) {
+    __shared__ int slot;
+    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+        const GemmJob jb = jobs[j];
+        gemm_split_job<VT, RB, CT, PF, KCH>(jb, A, B, C);
+    }
+    pq_done(queue);
+}
+
 // Variant for 4 or 8 column tiles (many RHS): the B fragments of a K step are the same
 // for the four waves of a work group, so they are loaded once per work group into LDS
 // (double buffered) instead of once per wave from L2; each thread stages its share of the
@@ -304,7 +402,7 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
 // meets at one barrier per S steps.  A is streamed from HBM as in k_gemm_split, PFA steps
 // ahead.  K windows and slices hold an even number of steps, so S = 2 needs no tail.
 template <typename VT, int RB, int CT, int PFA, int KCH, int S>
-__global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restrict__ jobs,
+__device__ inline void gemm_split_lds_job(const GemmJob& jb,
                                                         const unsigned short* __restrict__ A,
                                                         const unsigned short* __restrict__ B,
                                                         double* __restrict__ C) {
@@ -315,7 +413,6 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
     constexpr int UNITS = STEP_UNITS * S;
     constexpr int NU = UNITS / 256;          // per thread
     __shared__ VT bs[2][UNITS];
-    const GemmJob jb = jobs[blockIdx.x];
     if (jb.rb0 >= jb.mb) return;             // whole work group (empty job)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int rbw = jb.rb0 + wave * RB;
@@ -429,6 +526,23 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
         for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
+template <typename VT, int RB, int CT, int PFA, int KCH, int S>
+__global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restrict__ jobs, const unsigned short* __restrict__ A,
+        const unsigned short* __restrict__ B, double* __restrict__ C) {
+    const GemmJob jb = jobs[blockIdx.x];
+    gemm_split_lds_job<VT, RB, CT, PFA, KCH, S>(jb, A, B, C);
+}
+template <typename VT, int RB, int CT, int PFA, int KCH, int S>
+__global__ void __launch_bounds__(256) k_gemm_split_lds_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+        const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, double* __restrict__ C) {
+    __shared__ int slot;
+    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+        const GemmJob jb = jobs[j];
+        gemm_split_lds_job<VT, RB, CT, PFA, KCH, S>(jb, A, B, C);
+    }
+    pq_done(queue);
+}
+
 // Row blocks per wave for a given column-tile count (register budget per lane).  The
 // planner pads rows to 64*RB (a whole work-group tile) and K' to a multiple of 64.
 int gemm_rb(int form, int ctmax) {
@@ -436,13 +550,23 @@ int gemm_rb(int form, int ctmax) {
     return ctmax <= 2 ? 4 : 2;
 }
 
+template <typename TA>
+static void launch_dense(void (*kn)(const GemmJob*, const TA*, const TA*, double*),
+                         void (*kp)(const GemmJob*, int, int*, const TA*, const TA*, double*),
+                         hipStream_t st, const GemmJob* jobs, int njobs, const void* a, const void* b,
+                         double* c, int* queue) {
+    if (queue)
+        hipLaunchKernelGGL(kp, dim3(std::min(njobs, pq_groups_of(kp, 256))), dim3(256), 0, st, jobs, njobs,
+                           queue, (const TA*)a, (const TA*)b, c);
+    else
+        hipLaunchKernelGGL(kn, dim3(njobs), dim3(256), 0, st, jobs, (const TA*)a, (const TA*)b, c);
+}
+
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
-                 const void* a, const void* b, double* c) {
+                 const void* a, const void* b, double* c, int* queue) {
     if (njobs <= 0) return;
-    dim3 grid(njobs), blk(256);
 #define GEMM_CASE(KERN, RB, CT, ...)                                                           \
-    hipLaunchKernelGGL((KERN<RB, CT, __VA_ARGS__>), grid, blk, 0, st, jobs, (const TA*)a,     \
-                       (const TA*)b, c)
+    launch_dense<TA>(KERN<RB, CT, __VA_ARGS__>, KERN##_pq<RB, CT, __VA_ARGS__>, st, jobs, njobs, a, b, c, queue)
     if (form == FBC_FORM_FP64) {
         typedef double TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_f64, 4, 1, 4);
@@ -635,16 +759,11 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs, const double2* __restrict__ tab, i
             const double* __restrict__ B, double* __restrict__ C, const CellDev* __restrict__ cells,
             const int32_t* __restrict__ lut, int d1min, int d2min, int w2,
             const int32_t* __restrict__ need, int64_t n_off) {
-    dtab_job<CT>(jobs[blockIdx.x], tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
+    const GemmJob jb = jobs[blockIdx.x];
+    dtab_job<CT>(jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
 }
 
-// Persistent form: as many work groups as fit on the chip at once, each taking the next
-// job of the list from a device counter until the list is exhausted (with the list
-// longest first, the groups that finish early take the short jobs: dynamic longest-
-// processing-time scheduling of uneven cells).  queue[0] is the next job, queue[1]
-// counts the groups that have left; the last one to leave sets both back to zero for
-// the next launch (so the launch can be replayed from a graph).  Every group leaves as
-// soon as it draws an index past the list.
+// Persistent form (work queue as for the dense products).
 template <int CT>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
 k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
@@ -653,34 +772,11 @@ k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ qu
                const int32_t* __restrict__ lut, int d1min, int d2min, int w2,
                const int32_t* __restrict__ need, int64_t n_off) {
     __shared__ int slot;
-    for (;;) {
-        if (threadIdx.x == 0) slot = atomicAdd(&queue[0], 1);
-        __syncthreads();
-        const int j = slot;
-        __syncthreads();                 // every thread has read slot; LDS of the last job free
-        if (j >= njobs) break;
-        dtab_job<CT>(jobs[j], tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
+    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+        const GemmJob jb = jobs[j];
+        dtab_job<CT>(jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
-            atomicExch(&queue[0], 0);
-            atomicExch(&queue[1], 0);
-        }
-    }
-}
-
-template <int CT>
-static int dtab_pq_groups() {
-    static int groups = 0;               // per process; the library runs on one device type
-    if (groups == 0) {
-        int per_cu = 0, dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_dtab_pq<CT>, 128, 0);
-        groups = std::max(1, per_cu) * std::max(1, cus);
-    }
-    return groups;
+    pq_done(queue);
 }
 
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
@@ -691,7 +787,7 @@ void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, co
     dim3 blk(128);
     if (queue) {
 #define PQ_CASE(CT)                                                                             \
-    hipLaunchKernelGGL(k_gemm_dtab_pq<CT>, dim3(std::min(njobs, dtab_pq_groups<CT>())), blk, 0, st, jobs, \
+    hipLaunchKernelGGL(k_gemm_dtab_pq<CT>, dim3(std::min(njobs, pq_groups_of(k_gemm_dtab_pq<CT>, 128))), blk, 0, st, jobs, \
                        njobs, queue, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off)
         switch (ct) {
             case 1: PQ_CASE(1); break;

@@ -42,7 +42,8 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
                       void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw,
                       const int* bexp);
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
-                 const void* a, const void* b, double* c);
+                 const void* a, const void* b, double* c,
+                 int* queue);   // queue != NULL: persistent work-queue kernel
 // Offset-table form: 32 pad columns x all interface columns per work group, table
 // entries gathered into LDS in MFMA fragment order.
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,

@@ -369,9 +369,10 @@ def test_negligible_block_skipping(form, tol):
     assert e2 < max(tol, 1e-10), (form, e2)
 
 
-def test_work_lists_give_identical_results():
-    """Every order of the work list (incl. the persistent work-queue kernel of the
-    offset-table form) partitions the same products, so for a given number of K slices
+@pytest.mark.parametrize("form", ["dtable_fp64", "fp64", "fp32", "split_fp16"])
+def test_work_lists_give_identical_results(form):
+    """Every order of the work list (incl. the persistent work-queue kernels) partitions
+    the same products, so for a given number of K slices
     the update is bit-identical; other slice counts change only the rounding.  The
     persistent kernel's queue is reset for the next launch (repeated calls and graph
     replays agree)."""
@@ -381,7 +382,7 @@ def test_work_lists_give_identical_results():
     wl = W.Workload("three", cells, bz=32)
     f = torch.from_numpy(np.concatenate([c.forces.ravel() for c in wl.cells])).to(dev)
     n_u = sum(c.n_rhs * c.nz * c.n_b * 3 for c in wl.cells)
-    ctx = _ctx(wl.cells, wl.bz, form="dtable_fp64")
+    ctx = _ctx(wl.cells, wl.bz, form=form)
     ref = None
     stream = torch.cuda.Stream()
     for nsplit in (2, 1):
@@ -397,8 +398,9 @@ def test_work_lists_give_identical_results():
                 if ref_split is None:
                     ref_split = got
                 assert np.array_equal(got, ref_split), (nsplit, order, rep)
-        if ref is not None:
-            assert np.abs(ref_split - ref).max() <= 1e-13 * np.abs(ref).max()
+        if ref is not None:      # other slice counts: rounding only
+            tol = 1e-13 if form in FP64_FORMS else 1e-6
+            assert np.abs(ref_split - ref).max() <= tol * np.abs(ref).max()
         ref = ref_split
     # persistent list replayed from a captured graph, with eager calls in between
     ctx.set_work_list(1, 3)
@@ -425,7 +427,7 @@ def test_work_list_arguments_checked():
     wl = W.make_single("parity")
     from paper_2105_08798_amd.fbc import FbcError
     ctx = _ctx(wl.cells, wl.bz, form="fp64")
-    for nsplit, order in ((0, 0), (1, 4), (1, 3), (1 << 20, 0)):
+    for nsplit, order in ((0, 0), (1, 4), (1, -1), (1 << 20, 0)):
         with pytest.raises(FbcError):
             ctx.set_work_list(nsplit, order)
     ctx.close()
