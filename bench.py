@@ -5,7 +5,7 @@ One step = one fbc_apply call: for every RHS of the cell, u <- u - G^{p|i+} f fo
 by mean removal (net-force check, line rFFT, per-mode products, inverse rFFT, update,
 mean), with f and u resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload medium] [--forms fp64,fp32,split_bf16,split_fp16]
+    python bench.py [--steps K] [--warmup W] [--workload medium] [--forms fp64,fp32,split_bf16,split_fp16,surrogate]
 """
 from __future__ import annotations
 
@@ -278,7 +278,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--forms", default=None,
-                    help="default fp64,fp32,split_bf16,split_fp16 (dtable_fp64 for the batched workload)")
+                    help="default fp64,fp32,split_bf16,split_fp16,surrogate (dtable_fp64 for the batched workload)")
     ap.add_argument("--graph", action="store_true", help="replay the update from a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default work list (the library's autotuner picks K slices and order otherwise)")
@@ -301,7 +301,7 @@ def main() -> int:
         return 1
     wl = W.make_batched() if args.workload == "batched" else W.make_single(args.workload)
     if args.forms is None:
-        args.forms = "dtable_fp64" if args.workload == "batched" else "fp64,fp32,split_bf16,split_fp16"
+        args.forms = "dtable_fp64" if args.workload == "batched" else "fp64,fp32,split_bf16,split_fp16,surrogate"
     forms = [s for s in args.forms.split(",") if s]
     log(f"workload {args.workload}: {wl.description}, M={wl.bz}")
 
