@@ -80,25 +80,22 @@ __device__ inline void pq_done(int* __restrict__ queue) {
 }
 
 // Work groups of a persistent launch: the kernel's occupancy per CU times the CUs
-// (cached per kernel; the library runs on one device type per process).
-static int pq_groups(const void* kernel, int per_cu) {
+// (queried once per kernel and cached; the library runs on one device type per process).
+template <typename K>
+static int pq_groups_of(K kernel, int threads) {
     static std::mutex mu;
     static std::map<const void*, int> cache;
     std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(kernel);
+    const void* key = (const void*)kernel;
+    auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    int dev = 0, cus = 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int g = std::max(1, per_cu) * std::max(1, cus);
-    cache[kernel] = g;
+    cache[key] = g;
     return g;
-}
-template <typename K>
-static int pq_groups_of(K kernel, int threads) {
-    int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
-    return pq_groups((const void*)kernel, per_cu);
 }
 
 // ------------------------------- FP64 ---------------------------------------------
