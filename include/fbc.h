@@ -174,10 +174,11 @@ fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alph
  * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times the orders:
  * 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first, 3
  * persistent (jobs longest first, taken from a device work queue by as many work groups
- * as fit on the chip) -- with `reps` fbc_green_apply calls each on this context (input f, device; w, device,
- * same layout as u, is overwritten with G f), keeps the list with the fastest whole call
- * (the K slices also cost the inverse transform a read each) and reports it in *out (may
- * be NULL).  Synchronises the stream. */
+ * as fit on the chip) -- with `reps` fbc_green_apply calls each on this context (input
+ * f, device; w, device, same layout as u, is overwritten with G f), keeps the list with
+ * the fastest whole call (the K slices also cost the inverse transform a read each) and
+ * reports it in *out (may be NULL).  The surrogate form is refused (FBC_E_UNSUPPORTED):
+ * it keeps its mode-major chunks.  Synchronises the stream. */
 typedef struct {
     int nsplit;
     int order;
@@ -190,9 +191,9 @@ fbc_status fbc_autotune(fbc_ctx* ctx, const double* f, double* w, int reps, fbc_
 
 /* Pins the work list of the per-mode product: nsplit K slices (1 .. the context's limit,
  * fbc_info.nsplit after assembly is the default) in the given order (as listed for
- * fbc_autotune; the surrogate form accepts only its
- * mode-major chunks, nsplit 1, with order 1 (one work group per job) or 3 (default: each
- * chunk consumed by the persistent kernel, longest job first)).  Results do not depend
+ * fbc_autotune; the surrogate form accepts only its mode-major chunks, nsplit 1, with
+ * order 1 (one work group per job) or 3 (default: each chunk consumed by the persistent
+ * kernel, longest job first)).  Out-of-range values: FBC_E_ARG.  Results do not depend
  * on the order (every order partitions the same products); the number of K slices
  * changes only the rounding (the slices' partial sums are added in fixed order).  A
  * captured update (fbc_apply_graph) is captured again on its next call.  Synchronises
