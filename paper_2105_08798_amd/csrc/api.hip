@@ -886,7 +886,8 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         if ((s = dev_alloc(c, (void**)&c->sums, sums_n * 8)) != FBC_OK) goto fail_out;
         if ((s = dev_alloc(c, (void**)&c->ftot, (int64_t)c->total_rhs * 3 * 8)) != FBC_OK) goto fail_out;
         if ((s = dev_alloc(c, (void**)&c->shat, shat_n * 16)) != FBC_OK) goto fail_out;
-        c->scratch_bytes += shat_n * 16 + (int64_t)c->total_rhs * 24;
+        if ((s = dev_alloc(c, (void**)&c->shat_on, (int64_t)c->total_rhs * 4)) != FBC_OK) goto fail_out;
+        c->scratch_bytes += shat_n * 16 + (int64_t)c->total_rhs * 28;
         if ((s = dev_alloc(c, (void**)&c->wmax_part, wmax_n * 8)) != FBC_OK) goto fail_out;
         if ((s = dev_alloc(c, (void**)&c->sum_part, sp_n * 8)) != FBC_OK) goto fail_out;
         if ((s = dev_alloc(c, (void**)&c->rpart, rp_n * 8)) != FBC_OK) goto fail_out;
@@ -987,9 +988,10 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
         double* tot = c->ftot + 3 * p.rhs0;
         int* bexp = f16 ? c->bexp + ci : nullptr;
         if (c->opt.check_netforce || c->opt.project_netforce || comp || f16)
-            launch_netforce(st, fc, sums, tot, comp ? c->shat + c->shat_off[ci] : nullptr, p.R, p.nz, p.n_i,
-                            c->opt.netforce_tol, c->opt.check_netforce, c->opt.project_netforce,
-                            c->tw + p.tw_off, bexp, c->status);
+            launch_netforce(st, fc, sums, tot, comp ? c->shat + c->shat_off[ci] : nullptr,
+                            comp ? c->shat_on + p.rhs0 : nullptr, p.R, p.nz, p.n_i, c->opt.netforce_tol,
+                            c->opt.check_netforce, c->opt.project_netforce, c->tw + p.tw_off, bexp,
+                            c->status);
         void* bm = (char*)c->bfrag + p.b_off * b_elem_bytes(form);
         launch_line_rfft(st, form, fc, tot, c->opt.project_netforce, bm, p.R, p.nz, p.n_i, p.kp,
                          p.ct, c->tw + p.tw_off, bexp);
@@ -1031,7 +1033,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
         launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
                           p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split,
                           comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
-                          comp ? c->shat + c->shat_off[ci] : nullptr,
+                          comp ? c->shat + c->shat_off[ci] : nullptr, comp ? c->shat_on + p.rhs0 : nullptr,
                           f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + ci : nullptr, nullptr);
     }
 }
@@ -1045,6 +1047,7 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
         auto& p = c->cells[ci];
         const double2* rm = comp ? c->rowmean + c->rowmean_off[ci] : nullptr;
         const double2* sh = comp ? c->shat + c->shat_off[ci] : nullptr;
+        const int* so = comp ? c->shat_on + p.rhs0 : nullptr;
         const unsigned long long* am = f16 ? c->amax + c->amax_off[ci] : nullptr;
         const int* be = f16 ? c->bexp + ci : nullptr;
         int tr, pp;
@@ -1054,7 +1057,7 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
             double* sp = c->sum_part + c->sum_part_off[ci];
             launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
                               p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split, rm, sh,
-                              am, be, nullptr);
+                              so, am, be, nullptr);
             if (!mean_removal) launch_fill(st, uc, (int64_t)p.R * p.nz * p.M, 0.0);
             launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr);
             if (mean_removal)
@@ -1065,10 +1068,10 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
         if (mean_removal) {
             mu = c->mean + 3 * p.rhs0;
             launch_update_mean(st, u + p.u_off, c->cbuf + p.c_off, c->sum_part + c->sum_part_off[ci], p.R,
-                               p.nz, p.mp, p.M, c->nsplit, p.c_split, rm, sh, am, be, alpha, mu, c->status);
+                               p.nz, p.mp, p.M, c->nsplit, p.c_split, rm, sh, so, am, be, alpha, mu, c->status);
         }
         launch_irfft_update(st, c->cbuf + p.c_off, u + p.u_off, p.R, p.nz, p.mp, p.M, p.ctr,
-                            c->tw + p.tw_off, c->nsplit, p.c_split, rm, sh, am, be, alpha, mu,
+                            c->tw + p.tw_off, c->nsplit, p.c_split, rm, sh, so, am, be, alpha, mu,
                             mean_removal ? 1 : 0, c->status);
     }
 }

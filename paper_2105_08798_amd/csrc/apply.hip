@@ -98,12 +98,16 @@ __global__ void __launch_bounds__(NT) k_bexp(const double* __restrict__ sums, in
 // the total absolute force.  With shat != NULL the same block then transforms the
 // per-layer net force along the line (after the projection, if any):
 // shat[r][m][c] = sum_n0 (s_c(n0) - tot_c / Nz) e^{-2 pi i m n0 / Nz}, m = 0..Nz/2,
-// which multiplies the subtracted row means in the inverse transform.
+// which multiplies the subtracted row means in the inverse transform.  A layer whose net
+// force lies within the rounding bound of its own summation, |s_c| <= n_i 2^-52 sum|f_c|,
+// is indistinguishable from a balanced one and enters as exactly zero; shat_on[r] = 0 then
+// records that the whole transform vanishes, so the compensation can be skipped.
 __global__ void __launch_bounds__(NT) k_netforce_total(const double* __restrict__ sums, int nz, int logn,
-                                                       double tol, int check, int project,
+                                                       int n_i, double tol, int check, int project,
                                                        double* __restrict__ tot,
                                                        const double2* __restrict__ tw,
                                                        double2* __restrict__ shat,
+                                                       int* __restrict__ shat_on,
                                                        int* __restrict__ status) {
     extern __shared__ double2 lds[];             // 3 Nz (line transforms); >= 6 NT doubles
     const int r = blockIdx.x;
@@ -122,31 +126,39 @@ __global__ void __launch_bounds__(NT) k_netforce_total(const double* __restrict_
     }
     if (!shat) return;
     // v[0..2] hold the totals in every thread after block_sum
+    const double gam = (double)n_i * 0x1p-52;
     for (int e = threadIdx.x; e < 3 * nz; e += NT) {
         const int c = e / nz, n0 = e - c * nz;
         const double sub = project ? v[c] / nz : 0.0;
-        lds[c * nz + bitrev(n0, logn)] = make_double2(sums[((int64_t)r * nz + n0) * NF_STRIDE + c] - sub, 0.0);
+        const double* o = sums + ((int64_t)r * nz + n0) * NF_STRIDE;
+        double s = o[c] - sub;
+        if (fabs(s) <= gam * o[3 + c] && isfinite(o[3 + c])) s = 0.0;
+        lds[c * nz + bitrev(n0, logn)] = make_double2(s, 0.0);
     }
     __syncthreads();
     lds_fft(lds, 3, logn, tw, false);
     const int nm = (nz >> 1) + 1;
+    int any = 0;
     for (int e = threadIdx.x; e < 3 * nm; e += NT) {
         const int m = e / 3, c = e - 3 * m;
         double2 z = lds[c * nz + m];
         if (project && m == 0) z = make_double2(0.0, 0.0);
         shat[((int64_t)r * nm + m) * 3 + c] = z;
+        any |= (z.x != 0.0 || z.y != 0.0);
     }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) shat_on[r] = any;     // 0: s^ = 0 exactly, the compensation adds 0
 }
 
-void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat, int R,
-                     int nz, int n_i, double tol, int check, int project, const double2* tw,
-                     int* bexp, int* status) {
+void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat,
+                     int* shat_on, int R, int nz, int n_i, double tol, int check, int project,
+                     const double2* tw, int* bexp, int* status) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     hipLaunchKernelGGL(k_netforce, dim3(nz, R), dim3(NT), 0, st, f, sums, nz, n_i, check, status);
     const size_t lds = std::max((size_t)3 * nz * sizeof(double2), (size_t)6 * NT * sizeof(double));
-    hipLaunchKernelGGL(k_netforce_total, dim3(R), dim3(NT), lds, st, sums, nz, logn, tol, check, project, tot,
-                       tw, shat, status);
+    hipLaunchKernelGGL(k_netforce_total, dim3(R), dim3(NT), lds, st, sums, nz, logn, n_i, tol, check, project, tot,
+                       tw, shat, shat_on, status);
     if (bexp) hipLaunchKernelGGL(k_bexp, dim3(1), dim3(NT), 0, st, sums, R * nz, nz, bexp);
 }
 
@@ -400,6 +412,7 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
 __device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R,
                                    const double2* __restrict__ rowmean,
                                    const double2* __restrict__ shat,
+                                   const int* __restrict__ shat_on,
                                    const unsigned long long* __restrict__ amax, int eb,
                                    double& ar, double& br, double& ai, double& bi) {
     if (amax) {     // split FP16: the product carries 2^(e_A(m) + e_B)
@@ -409,7 +422,9 @@ __device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R
         br *= sc;
         bi *= sc;
     }
-    if (rowmean) {
+    // the compensation is zero for RHS whose per-layer net forces all vanish (s^ = 0):
+    // skipped for them (shat_on[r] = 0), which saves its loads for the usual forces
+    if (rowmean && ((ra < R && shat_on[ra]) || (ra + 1 < R && shat_on[ra + 1]))) {
         const int b = row / 3, cc = row - 3 * b;
         const double2* rm = rowmean + ((int64_t)mm * (M / 3) + b) * 6;
         for (int d = 0; d < 3; ++d) {
@@ -435,7 +450,7 @@ __device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R
 __device__ inline void mode_value(double2 v0, double2 v1, const double* __restrict__ src, int ja,
                                   int nsplit, int64_t split_stride, int mm, int row, int M, int nm,
                                   int ra, int R, const double2* __restrict__ rowmean,
-                                  const double2* __restrict__ shat,
+                                  const double2* __restrict__ shat, const int* __restrict__ shat_on,
                                   const unsigned long long* __restrict__ amax, int eb,
                                   double& ar, double& br, double& ai, double& bi) {
     ar = v0.x;
@@ -450,7 +465,7 @@ __device__ inline void mode_value(double2 v0, double2 v1, const double* __restri
         ai += q1.x;
         bi += q1.y;
     }
-    mode_adjust(mm, row, M, nm, ra, R, rowmean, shat, amax, eb, ar, br, ai, bi);
+    mode_adjust(mm, row, M, nm, ra, R, rowmean, shat, shat_on, amax, eb, ar, br, ai, bi);
 }
 
 // Gathers the spectra of tr rows x pp RHS pairs of one column tile into LDS (bit-reversed,
@@ -463,7 +478,7 @@ __device__ inline void gather_inverse(double2* lds, const double* __restrict__ c
                                       int pair0, int tr, int pp, int ss, int R, int nz, int logn,
                                       int mp, int M, const double2* __restrict__ tw, int nsplit,
                                       int64_t split_stride, const double2* __restrict__ rowmean,
-                                      const double2* __restrict__ shat,
+                                      const double2* __restrict__ shat, const int* __restrict__ shat_on,
                                       const unsigned long long* __restrict__ amax, int eb) {
     const int nm = (nz >> 1) + 1;
     constexpr int LU = 4;
@@ -500,7 +515,7 @@ __device__ inline void gather_inverse(double2* lds, const double* __restrict__ c
                 const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
                 double ar, br, ai, bi;
                 mode_value(pv0[q], pv1[q], src, ja, nsplit, split_stride, mm, row, M, nm, 8 * tile + ja, R,
-                           rowmean, shat, amax, eb, ar, br, ai, bi);
+                           rowmean, shat, shat_on, amax, eb, ar, br, ai, bi);
                 z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
                 zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
             }
@@ -523,6 +538,7 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    int64_t split_stride,
                                                    const double2* __restrict__ rowmean,
                                                    const double2* __restrict__ shat,
+        const int* __restrict__ shat_on,
                                                    const unsigned long long* __restrict__ amax,
                                                    const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
@@ -533,7 +549,7 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     const int nseq = tr * pp;
     const int ss = nz + 1;
     gather_inverse(lds, c, tile, row0, pair0, tr, pp, ss, R, nz, logn, mp, M, tw, nsplit, split_stride,
-                   rowmean, shat, amax, eb);
+                   rowmean, shat, shat_on, amax, eb);
     const double scale = 1.0 / nz;
     double mx[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // per RHS inside the tile
     for (int t = threadIdx.x; t < nseq * nz; t += NT) {
@@ -582,7 +598,8 @@ void irfft_shape(int nz, int* tr, int* pp) {
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,
-                       const unsigned long long* amax, const int* bexp, int* n_part_out) {
+                       const int* shat_on, const unsigned long long* amax, const int* bexp,
+                       int* n_part_out) {
     (void)ct;
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
@@ -592,7 +609,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
     size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
     hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,
-                       tr, pp, tw, nsplit, split_stride, rowmean, shat, amax, bexp);
+                       tr, pp, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, bexp);
     if (n_part_out) *n_part_out = (int)grid.x;
 }
 
@@ -622,6 +639,7 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
                                                      int nsplit, int64_t split_stride,
                                                      const double2* __restrict__ rowmean,
                                                      const double2* __restrict__ shat,
+        const int* __restrict__ shat_on,
                                                      const unsigned long long* __restrict__ amax,
                                                      const int* __restrict__ bexp, double alpha,
                                                      const double* __restrict__ mu, int read_u,
@@ -682,7 +700,8 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
                 }
                 double2 z = make_double2(0, 0), zc = make_double2(0, 0);
                 if (row < M) {
-                    mode_adjust(mm, row, M, nm, 8 * tile + ja, R, rowmean, shat, amax, eb, ar, br, ai, bi);
+                    mode_adjust(mm, row, M, nm, 8 * tile + ja, R, rowmean, shat, shat_on, amax, eb, ar, br,
+                                ai, bi);
                     z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
                     zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
                 }
@@ -778,9 +797,9 @@ bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp) {
 
 void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
                          int ct_grid, const double2* tw, int nsplit, int64_t split_stride,
-                         const double2* rowmean, const double2* shat, const unsigned long long* amax,
-                         const int* bexp, double alpha, const double* mu, int read_u,
-                         const int* status) {
+                         const double2* rowmean, const double2* shat, const int* shat_on,
+                         const unsigned long long* amax, const int* bexp, double alpha,
+                         const double* mu, int read_u, const int* status) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int tr, pp;
@@ -791,7 +810,8 @@ void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int 
     const size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
 #define UPD_CASE(NS) \
     hipLaunchKernelGGL(k_irfft_update<NS>, dim3(nblk), dim3(NT), lds, st, c, u, R, nz, logn, mp, M, tr, \
-                       pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, amax, bexp, alpha, mu, \
+                       pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, bexp,  \
+                       alpha, mu, \
                        read_u, status)
     if (nsplit <= 1) UPD_CASE(1);
     else if (nsplit <= 2) UPD_CASE(2);
@@ -813,6 +833,7 @@ __global__ void __launch_bounds__(NT) k_mean_parts(const double* __restrict__ u,
                                                    int nsplit, int64_t split_stride,
                                                    const double2* __restrict__ rowmean,
                                                    const double2* __restrict__ shat,
+        const int* __restrict__ shat_on,
                                                    const unsigned long long* __restrict__ amax,
                                                    const int* __restrict__ bexp,
                                                    double* __restrict__ part,
@@ -850,8 +871,8 @@ __global__ void __launch_bounds__(NT) k_mean_parts(const double* __restrict__ u,
             const double* src = c + ((int64_t)tile * mp + row) * nm * 16;
             double ar, br, ai, bi;
             mode_value(*(const double2*)(src + ja), *(const double2*)(src + ja + 8), src, ja, nsplit,
-                       split_stride, 0, row, M, nm, 8 * tile + ja, R, rowmean, shat, amax, eb, ar, br, ai,
-                       bi);
+                       split_stride, 0, row, M, nm, 8 * tile + ja, R, rowmean, shat, shat_on, amax, eb, ar,
+                       br, ai, bi);
             v[3 + row % 3] += odd ? br : ar;
         }
     }
@@ -883,12 +904,12 @@ __global__ void __launch_bounds__(NT) k_update_mean(const double* __restrict__ p
 
 void launch_update_mean(hipStream_t st, const double* u, const double* c, double* part, int R, int nz,
                         int mp, int M, int nsplit, int64_t split_stride, const double2* rowmean,
-                        const double2* shat, const unsigned long long* amax, const int* bexp,
-                        double alpha, double* mu, const int* status) {
+                        const double2* shat, const int* shat_on, const unsigned long long* amax,
+                        const int* bexp, double alpha, double* mu, const int* status) {
     const int64_t per_rhs = (int64_t)nz * M;
     const int nbr = mean_blocks(per_rhs);
     hipLaunchKernelGGL(k_mean_parts, dim3(nbr, R), dim3(NT), 0, st, u, c, per_rhs, nbr, R, nz, mp, M, nsplit,
-                       split_stride, rowmean, shat, amax, bexp, part, status);
+                       split_stride, rowmean, shat, shat_on, amax, bexp, part, status);
     hipLaunchKernelGGL(k_update_mean, dim3(R), dim3(NT), 0, st, part, nbr, nz, M / 3, alpha, mu, status);
 }
 

@@ -25,6 +25,7 @@ struct fbc_ctx {
     double* sums = nullptr;         // per layer: net force and absolute force [r][n0][6]
     double* ftot = nullptr;         // net force of each cell per RHS [total_rhs][3]
     double2* shat = nullptr;        // line transform of the per-layer net force [r][m][3]
+    int* shat_on = nullptr;         // per RHS: 0 when that transform is exactly zero [total_rhs]
     double2* rowmean = nullptr;     // row-gauge means [m][b][6] (reduced forms with row gauge)
     std::vector<int64_t> shat_off, rowmean_off;
     unsigned long long* amax = nullptr;  // split FP16: per cell mode, largest table magnitude

@@ -35,9 +35,9 @@ void launch_build_dense(hipStream_t st, int form, void* store, const double2* ta
 // ---- apply (Section 2.3.2 update in line-mode form) ----
 // Per-layer sums sums[r][n0][6] (net force, absolute force), cell totals tot[r][3] with
 // the net-force check, and (shat != NULL) the line transform of the per-layer net force.
-void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat, int R,
-                     int nz, int n_i, double tol, int check, int project, const double2* tw,
-                     int* bexp, int* status);
+void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot, double2* shat,
+                     int* shat_on, int R, int nz, int n_i, double tol, int check, int project,
+                     const double2* tw, int* bexp, int* status);
 void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
                       void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw,
                       const int* bexp);
@@ -54,7 +54,8 @@ void irfft_shape(int nz, int* tr, int* pp);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,
                        int64_t split_stride, const double2* rowmean, const double2* shat,
-                       const unsigned long long* amax, const int* bexp, int* n_part_out);
+                       const int* shat_on, const unsigned long long* amax, const int* bexp,
+                       int* n_part_out);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status,
                  int* n_part_out);
@@ -65,14 +66,14 @@ void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, 
 bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp);
 void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
                          int ct_grid, const double2* tw, int nsplit, int64_t split_stride,
-                         const double2* rowmean, const double2* shat, const unsigned long long* amax,
-                         const int* bexp, double alpha, const double* mu, int read_u,
-                         const int* status);
+                         const double2* rowmean, const double2* shat, const int* shat_on,
+                         const unsigned long long* amax, const int* bexp, double alpha,
+                         const double* mu, int read_u, const int* status);
 int mean_blocks(int64_t per_rhs);
 void launch_update_mean(hipStream_t st, const double* u, const double* c, double* part, int R, int nz,
                         int mp, int M, int nsplit, int64_t split_stride, const double2* rowmean,
-                        const double2* shat, const unsigned long long* amax, const int* bexp,
-                        double alpha, double* mu, const int* status);
+                        const double2* shat, const int* shat_on, const unsigned long long* amax,
+                        const int* bexp, double alpha, double* mu, const int* status);
 
 // ---- relax (Section 2.3.3, Algorithm 2) ----
 void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,

@@ -196,6 +196,28 @@ def test_layer_net_forces_with_zero_cell_total(form, tol):
 
 
 @pytest.mark.parametrize("form,tol", [("fp32", 1e-6), ("split_bf16", 2e-5), ("split_fp16", 1e-6)])
+def test_layer_net_forces_mixed_rhs(form, tol):
+    """RHS whose layers are balanced sit beside RHS whose layers are not: the row-gauge
+    compensation is switched per RHS (a balanced layer's net force is only rounding
+    residue) and must stay on wherever a layer carries net force."""
+    wl = W.make_custom(32, 40, 70, 6, 32, seed=13, zero_net_force=False)
+    c = wl.cells[0]
+    f = c.forces - c.forces.mean(axis=(1, 2), keepdims=True)
+    for r in (2, 3, 5):                                       # balanced layers
+        f[r] = f[r] - f[r].mean(axis=1, keepdims=True)
+    c.forces = np.ascontiguousarray(f)
+    for r in (0, 1, 4):
+        assert np.abs(f[r].sum(axis=1)).max() > 1e-2
+    assert np.abs(f[2].sum(axis=1)).max() < 1e-12
+    rc, got, u0 = run_apply(wl, form, alpha=0.7)
+    assert rc == 0
+    ref = oracle_update(wl, u0, 0.7)[0]
+    for r in range(6):
+        e2, emax = rel_err(got.reshape(ref.shape)[r:r + 1], ref[r:r + 1])
+        assert e2 < tol and emax < 3 * tol, (form, r, e2, emax)
+
+
+@pytest.mark.parametrize("form,tol", [("fp32", 1e-6), ("split_bf16", 2e-5), ("split_fp16", 1e-6)])
 @pytest.mark.parametrize("nz,n_i,n_b,R,bz", [(16, 50, 80, 20, 64), (8, 130, 260, 33, 64), (4, 40, 70, 64, 32)])
 def test_reduced_forms_many_rhs(nz, n_i, n_b, R, bz, form, tol):
     """4 and 8 column tiles: the product kernels that share B through LDS."""
