@@ -394,10 +394,13 @@ __global__ void __launch_bounds__(256) k_gemm_split_pq(const GemmJob* __restrict
 
 // Variant for 4 or 8 column tiles (many RHS): the B fragments of a K step are the same
 // for the four waves of a work group, so they are loaded once per work group into LDS
-// (double buffered) instead of once per wave from L2; each thread stages its share of the
-// next S steps in registers while the MFMAs of the current S steps run, and the group
-// meets at one barrier per S steps.  A is streamed from HBM as in k_gemm_split, PFA steps
-// ahead.  K windows and slices hold an even number of steps, so S = 2 needs no tail.
+// (double buffered) instead of once per wave from L2, and the group meets at one barrier
+// per S steps.  A is streamed from HBM into a register ring PFA steps deep.  Each thread
+// also keeps its share of B for the same PFA steps in a ring of its own: vector-memory
+// loads complete in issue order, so the wait for B before it is copied into LDS would
+// otherwise also wait for every A load issued before it, and cut the effective depth of
+// the A ring down to the distance at which B was fetched.  K windows and slices hold an
+// even number of steps, so S = 2 needs no tail.
 template <typename VT, int RB, int CT, int PFA, int KCH, int S>
 __device__ inline void gemm_split_lds_job(const GemmJob& jb,
                                                         const unsigned short* __restrict__ A,
@@ -405,11 +408,10 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
                                                         double* __restrict__ C) {
     static_assert(CT >= 2 && (CT % 2) == 0, "B staging assumes an even tile count");
     static_assert(S == 1 || S == 2, "one or two K steps per barrier");
-    static_assert(PFA >= 2 * S && (PFA % (2 * S)) == 0, "A ring depth must be a multiple of 2 S");
+    static_assert(PFA >= 2 * S && (PFA % (2 * S)) == 0, "ring depth must be a multiple of 2 S");
     constexpr int STEP_UNITS = CT * 128;     // 16-byte units of B per step (hi and lo runs)
-    constexpr int UNITS = STEP_UNITS * S;
-    constexpr int NU = UNITS / 256;          // per thread
-    __shared__ VT bs[2][UNITS];
+    constexpr int NU = STEP_UNITS / 256;     // per thread and step
+    __shared__ VT bs[2][STEP_UNITS * S];
     if (jb.rb0 >= jb.mb) return;             // whole work group (empty job)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int rbw = jb.rb0 + wave * RB;
@@ -427,21 +429,6 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
             acc[r][c] = (d4_t){0, 0, 0, 0};
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
-    VT stage[NU];
-    auto load_b = [&](int t) {              // steps t .. t + S - 1
-#pragma unroll
-        for (int j = 0; j < NU; ++j) {
-            // LDS in lane order, global in column-run order
-            const int u = tid + 256 * j, st = u / STEP_UNITS, u2 = u - st * STEP_UNITS;
-            const int c = u2 >> 7, rem = u2 & 127;
-            const int tw = wrap_k(t + st, kt);
-            stage[j] = b[((int64_t)c * kt + tw) * 128 + (rem & 64) + bpos(rem & 63)];
-        }
-    };
-    auto store_b = [&](int buf) {
-#pragma unroll
-        for (int j = 0; j < NU; ++j) bs[buf][tid + 256 * j] = stage[j];
-    };
     if (te <= tb) {              // empty K slice: its partial output is zero
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -449,19 +436,34 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
             for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
         return;
     }
-    // A ring: PFA steps in flight per wave (memory-level parallelism for HBM latency)
-    VT ah[PFA][RB], al[PFA][RB];
+    // this thread's share of B for step t: LDS in lane order, global in column-run order
+    auto load_b = [&](VT (&dst)[NU], int t) {
+        const int tw = wrap_k(t, kt);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int u = tid + 256 * j, c = u >> 7, rem = u & 127;
+            dst[j] = b[((int64_t)c * kt + tw) * 128 + (rem & 64) + bpos(rem & 63)];
+        }
+    };
+    auto store_b = [&](int buf, int sidx, const VT (&src)[NU]) {
+#pragma unroll
+        for (int j = 0; j < NU; ++j) bs[buf][sidx * STEP_UNITS + tid + 256 * j] = src[j];
+    };
+    // rings: PFA steps of A and of this thread's share of B in flight
+    VT ah[PFA][RB], al[PFA][RB], br[PFA][NU];
 #pragma unroll
     for (int u = 0; u < PFA; ++u) {
-        const int tl = wrap_k(min(tb + u, te - 1), kt);
+        const int tl = min(tb + u, te - 1);
+        const int tw = wrap_k(tl, kt);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = ld_stream(a + (((int64_t)tl * mb + r) * 128));
-            al[u][r] = ld_stream(a + (((int64_t)tl * mb + r) * 128 + 64));
+            ah[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128));
+            al[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128 + 64));
         }
+        load_b(br[u], tl);
     }
-    load_b(tb);
-    store_b(0);
+#pragma unroll
+    for (int u = 0; u < S; ++u) store_b(0, u, br[u]);
     __syncthreads();
     for (int t0 = tb; t0 < te; t0 += PFA) {
 #pragma unroll
@@ -470,8 +472,6 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
             if (t >= te) break;                    // same for every wave of the group
             const int sidx = u % S;                // step inside the group of S
             const int buf = (u / S) & 1;           // groups of S alternate (PFA / S even)
-            const bool more = (t + S - sidx < te); // a next group of S steps exists
-            if (sidx == 0 && more) load_b(t + S);
             const VT* bb = bs[buf] + sidx * STEP_UNITS;
             // two column tiles at a time, the three products of a tile interleaved with
             // the other tile's, so dependent MFMAs are 2 RB instructions apart
@@ -495,12 +495,15 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
                     ac32[r][c + 1] = mfma_16x16x32(ah[u][r], bh1, ac32[r][c + 1]);
                 }
             }
-            const int tn = wrap_k(min(t + PFA, te - 1), kt);
+            // slot u is free (its B went to LDS before this group): refill it PFA ahead
+            const int tl = min(t + PFA, te - 1);
+            const int tn = wrap_k(tl, kt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 ah[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128));
                 al[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128 + 64));
             }
+            load_b(br[u], tl);
             if (((t - tb + 1) % KCH) == 0 || t + 1 == te) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
@@ -512,7 +515,10 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
                     }
             }
             if (sidx == S - 1) {
-                if (more) store_b(buf ^ 1);
+                if (t + 1 < te) {                  // next group of S steps, from the ring
+#pragma unroll
+                    for (int v = 1; v <= S; ++v) store_b(buf ^ 1, v - 1, br[(u + v) % PFA]);
+                }
                 __syncthreads();
             }
         }
@@ -582,16 +588,16 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 4, 1, 2, 2);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 8, 4, 1);
-        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 8, 4, 1);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2);
+        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2);
     } else {
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 4, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
         // two K steps per barrier: 2 % faster than one on the 64-RHS workload (measured;
         // the split-FP16 kernel gained nothing and keeps one)
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 8, 8, 2);
-        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 8, 8, 2);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2);
+        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2);
     }
 #undef GEMM_CASE
 }
