@@ -183,8 +183,8 @@ __device__ inline void put_b(void* bm, int n, int kq, int kp, double v) {
     } else if (FORM == FBC_FORM_FP32) {
         ((float*)bm)[frag_off_f32(n, kq, kp)] = (float)v;
     } else if (FORM == FBC_FORM_SPLIT_FP16) {        // v already scaled by 2^e
-        const _Float16 hi = (_Float16)(float)v;
-        const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
+        const _Float16 hi = f64_to_f16(v);
+        const _Float16 lo = f64_to_f16(v - (double)hi);
         unsigned short* p = (unsigned short*)bm + frag_off_bf16(n, kq, kp);
         p[0] = __builtin_bit_cast(unsigned short, hi);
         p[512] = __builtin_bit_cast(unsigned short, lo);
@@ -219,9 +219,9 @@ __device__ inline void put_b_units(void* bm, int n, int kq0, int kp, const doubl
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if constexpr (FORM == FBC_FORM_SPLIT_FP16) {
-                const _Float16 h = (_Float16)(float)v[j];
+                const _Float16 h = f64_to_f16(v[j]);
                 hi[j] = __builtin_bit_cast(unsigned short, h);
-                lo[j] = __builtin_bit_cast(unsigned short, (_Float16)(float)(v[j] - (double)(float)h));
+                lo[j] = __builtin_bit_cast(unsigned short, f64_to_f16(v[j] - (double)h));
             } else {
                 const unsigned short h = f2bf((float)v[j]);
                 hi[j] = h;

@@ -289,8 +289,8 @@ __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict_
         const double v = ldexp(dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
                                            cols_i, lut, d1min, d2min, w2),
                                split16_exp_a(amax[m]));
-        const _Float16 hi = (_Float16)(float)v;
-        const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
+        const _Float16 hi = f64_to_f16(v);
+        const _Float16 lo = f64_to_f16(v - (double)hi);
         unsigned short* out = (unsigned short*)store + (int64_t)m * per_mode * 2;
         const int64_t base = ((((int64_t)t * mb + blk) * 2) * 64 + lane) * 8 + j;
         out[base] = __builtin_bit_cast(unsigned short, hi);

@@ -40,6 +40,17 @@ typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 // whole block (lane order permuted).
 // ---------------------------------------------------------------------------------
 __host__ __device__ inline int bpos(int lane) { return ((lane & 15) << 2) | (lane >> 4); }
+
+// Round-to-nearest FP64 -> FP16 through FP32.  The result equals direct rounding (FP32
+// carries more than twice FP16's precision plus two bits, so the double rounding is
+// innocuous).  The empty asm keeps the compiler from merging the two hardware
+// conversions into one FP64 -> FP16 conversion, which it expands into a long integer
+// sequence.
+__device__ inline _Float16 f64_to_f16(double x) {
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return (_Float16)f;
+}
 __host__ __device__ inline int64_t frag_off_f64(int64_t r, int64_t k, int64_t kp) {
     int64_t blk = r >> 4, rr = r & 15;
     int64_t lane = ((k & 3) << 4) | rr;
