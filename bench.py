@@ -69,9 +69,10 @@ def kernel_matches(form: str, name: str) -> bool:
     return name.startswith("k_gemm_dtab<")
 
 
-def measured_traffic(workload: str, form: str):
+def measured_traffic(workload: str, form: str, product_bytes: float):
     """HBM bytes per product launch from the committed counter runs, or None when they
-    were taken on another workload or before the product kernels last changed."""
+    were taken on another workload, before the product kernels last changed, or on a
+    product of other algorithmic bytes (another set of kept blocks)."""
     import hashlib
     p = os.path.join(ROOT, "profiles", f"gemm_traffic_{workload}.json")
     if not os.path.exists(p):
@@ -82,6 +83,8 @@ def measured_traffic(workload: str, form: str):
         return None
     for name, v in t["kernels"].items():
         if kernel_matches(form, name):
+            if v.get("algorithmic_bytes") != product_bytes:
+                return None
             return v["traffic_bytes"]
     return None
 
@@ -365,7 +368,7 @@ def main() -> int:
     head = max(ok, key=lambda f: out_forms[f]["updates_per_s"]) if ok else forms[0]
     h = out_forms[head]
     alg = dict(gemm_bytes=h["product_bytes"], gemm_flops=h["product_flops"])
-    traffic = measured_traffic(args.workload, head)
+    traffic = measured_traffic(args.workload, head, h["product_bytes"])
     roof = dict(bound="hbm", achieved=h["gemm_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=h["gemm_hbm_frac"], traffic=traffic, kernel=f"k_gemm ({head})",
                 bytes_per_launch=alg["gemm_bytes"])

@@ -136,10 +136,10 @@ typedef struct {
                                 K chunks of a row tile whose blocks all lie farther than
                                 the farthest offset with |G^(m)| >= skip_tol * max |G^(m)|
                                 (the line-mode Green function decays with kappa rho).
-                                0: default (1e-16 for the FP64 forms, below the rounding
-                                of their assembly; 1e-12 for the reduced forms, below
-                                their rounding; the surrogate skips exactly its zero
-                                blocks, kappa rho > 40); < 0: no skipping               */
+                                0: default (1e-16 for the FP64 forms, at the rounding
+                                of their assembly; 1e-9 for the reduced forms, two orders
+                                below their rounding of ~1e-7; the surrogate skips
+                                exactly its zero blocks, kappa rho > 40); < 0: none     */
 } fbc_options;
 
 /* Fills *opt with defaults: FP64, 1024 x 1024 torus, check on, no projection, tol 1e-10,
