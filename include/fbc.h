@@ -343,6 +343,61 @@ fbc_status fbc_mlp_loss_grad(fbc_mlp* m, const float* x, const float* t, int n,
 fbc_status fbc_mlp_adam_step(fbc_mlp* m, float lr, void* stream);
 /* FP32 forward pass y [n][12] of x [n][8] (device). */
 fbc_status fbc_mlp_forward(fbc_mlp* m, const float* x, float* y, int n, void* stream);
+/* ------------------------------------------------------------------------------------
+ * Real-space periodic lattice Green function (Section 3.1, eqs. G~inf, plgf_conv,
+ * plgf_poly and plgf_rich; Appendix B): an independent route to the line-periodic Green
+ * function, for cross-checking the Brillouin-zone blocks and for geometries that are not
+ * unions of atom columns.
+ *
+ * G~inf(r) is the infinite-lattice Green function for |r| <= r_cut and the continuum
+ * (Kelvin) Green function beyond.  Within r_cut it is evaluated as the Green function of
+ * the torus_l^3 torus of the primitive cell (Brillouin-zone sum on that grid, q = 0
+ * dropped) minus a constant C, the mean of that torus function minus the continuum
+ * function over the lattice vectors of the shell r_cut < |r| <= r_match; C makes the two
+ * pieces join (the Green function is unique up to a constant).  The line-periodic value
+ * at a lattice vector r is the Richardson extrapolation (order N, from the partial sums
+ * k = n .. n + N) of G~_k(r) = sum over |i| <= k of G~inf(r + i N_z b0) - G~inf(i N_z b0).
+ *
+ * Lattice vectors are primitive-basis integers (n0, n1, n2) with b0 = (1, -1, 0)/2 along
+ * the line, b1 = (1, 0, 1)/2, b2 = (1, 1, 0)/2 (cube axes, a = 1); radii enter as
+ * 4 |r|^2 / a^2, integers, so r_cut = 5 a is r2x4_cut = 100.  Results do not depend on a.
+ * Outputs are the 6 components xx yy zz xy xz yz of the symmetric 3x3 block.
+ * ------------------------------------------------------------------------------------ */
+typedef struct fbc_plgf fbc_plgf;
+
+typedef struct {
+    int torus_l;        /* torus edge for the near-field table: power of two in [8, 256]  */
+    int r2x4_cut;       /* 4 r_cut^2 in [0, 576] (a = 1)                                  */
+    int r2x4_match;     /* 4 r_match^2 in (r2x4_cut, 1024]: outer radius of the C shell   */
+    int n_psi;          /* nodes of the continuum circle integral: multiple of 64 in
+                           [64, 1024]                                                     */
+} fbc_plgf_opts;
+
+/* Last error text of the fbc_plgf_* calls on this host thread. */
+const char* fbc_plgf_last_error(void);
+
+/* Builds the near-field table (torus sums, one work group per lattice vector of the table
+ * and the shell) and C on the device.  Synchronises `stream`.  FBC_E_ARG for out-of-range
+ * options; FBC_E_NOMEM / FBC_E_DEVICE as elsewhere.  The object owns its device memory. */
+fbc_status fbc_plgf_create(const fbc_lattice* lat, const fbc_plgf_opts* opts, void* stream,
+                           fbc_plgf** out);
+void fbc_plgf_destroy(fbc_plgf* p);
+
+/* Synchronous host copies of the table: *n_table = number of lattice vectors with
+ * |r| <= r_cut; vectors [n_table][3] (sorted by 4|r|^2, then n0, n1, n2), values
+ * [n_table][6] (G_torus - C) and c [6] may each be NULL. */
+fbc_status fbc_plgf_table(const fbc_plgf* p, int* n_table, int32_t* vectors, double* values,
+                          double* c);
+
+/* Line-periodic Green function at n lattice vectors disp [n][3] (device int32) for a line
+ * of nz layers (period nz b0, nz in [1, 65536]); out [n][6] (device FP64).  Richardson
+ * from the partial sums n_rich .. n_rich + order (n_rich >= 1, order in [0, 7],
+ * n_rich + order <= 16; the paper's choice is n_rich = 1, order = 5).  Asynchronous; the
+ * object holds the images of the origin for the call in flight, so calls on one object
+ * must be ordered (one stream). */
+fbc_status fbc_plgf_eval(fbc_plgf* p, const int32_t* disp, int64_t n, int nz, int n_rich,
+                         int order, double* out, void* stream);
+
 const char* fbc_status_string(fbc_status s);
 
 #ifdef __cplusplus

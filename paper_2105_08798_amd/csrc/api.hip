@@ -92,7 +92,7 @@ extern "C" const char* fbc_last_error(const fbc_ctx* c) {
 
 // Nearest-neighbour bonds of fcc in the primitive basis b0=(1/2,-1/2,0), b1=(1/2,0,1/2),
 // b2=(1/2,1/2,0) and the projectors k Rhat Rhat^T (Section 2.2.1, K_h of central springs).
-static BondTable make_bonds(double k) {
+BondTable make_bonds(double k) {
     BondTable bt{};
     // cubic (a = 1) basis columns
     const double B[3][3] = {{0.5, 0.5, 0.5}, {-0.5, 0.0, 0.5}, {0.0, 0.5, 0.0}};

@@ -7,50 +7,14 @@
 #include <cmath>
 #include <vector>
 
+#include "elastic.h"
 #include "learned.h"
 
 #define NTL 256
 
-// ----------------------------------------------------------------------------------
-// Kelvin solution of a cubic crystal: G_K(x) = 1/(8 pi^2 |x|) * circle integral of
-// Gamma(n)^{-1} over unit n normal to x (trapezoid rule over npsi nodes), with
-// Gamma_ii = C11 n_i^2 + C44 (|n|^2 - n_i^2), Gamma_ik = (C12 + C44) n_i n_k.
-// Output in symmetric order xx yy zz xy xz yz.
-// ----------------------------------------------------------------------------------
-__device__ inline void sym_inverse(const double g[6], double o[6]) {
-    const double a = g[0], b = g[1], c = g[2], xy = g[3], xz = g[4], yz = g[5];
-    const double cxx = b * c - yz * yz, cyy = a * c - xz * xz, czz = a * b - xy * xy;
-    const double cxy = xz * yz - xy * c, cxz = xy * yz - b * xz, cyz = xy * xz - a * yz;
-    const double inv = 1.0 / (a * cxx + xy * cxy + xz * cxz);
-    o[0] = cxx * inv; o[1] = cyy * inv; o[2] = czz * inv;
-    o[3] = cxy * inv; o[4] = cxz * inv; o[5] = cyz * inv;
-}
-
-__device__ void kelvin(const double x[3], const CgfConst& k, const double* __restrict__ cpsi,
-                       const double* __restrict__ spsi, double out[6]) {
-    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    const double xh[3] = {x[0] / r, x[1] / r, x[2] / r};
-    double hp[3] = {0, 0, 0};
-    if (fabs(xh[0]) < 0.9) hp[0] = 1.0; else hp[1] = 1.0;
-    double u[3] = {xh[1] * hp[2] - xh[2] * hp[1], xh[2] * hp[0] - xh[0] * hp[2], xh[0] * hp[1] - xh[1] * hp[0]};
-    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    u[0] /= un; u[1] /= un; u[2] /= un;
-    const double v[3] = {xh[1] * u[2] - xh[2] * u[1], xh[2] * u[0] - xh[0] * u[2], xh[0] * u[1] - xh[1] * u[0]};
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int l = 0; l < k.npsi; ++l) {
-        const double n0 = cpsi[l] * u[0] + spsi[l] * v[0];
-        const double n1 = cpsi[l] * u[1] + spsi[l] * v[1];
-        const double n2 = cpsi[l] * u[2] + spsi[l] * v[2];
-        const double q0 = n0 * n0, q1 = n1 * n1, q2 = n2 * n2, tot = q0 + q1 + q2;
-        const double g[6] = {k.c11 * q0 + k.c44 * (tot - q0), k.c11 * q1 + k.c44 * (tot - q1),
-                             k.c11 * q2 + k.c44 * (tot - q2), (k.c12 + k.c44) * n0 * n1,
-                             (k.c12 + k.c44) * n0 * n2, (k.c12 + k.c44) * n1 * n2};
-        double o[6];
-        sym_inverse(g, o);
-        for (int c = 0; c < 6; ++c) acc[c] += o[c];
-    }
-    const double sc = 1.0 / (4.0 * M_PI * k.npsi * r);
-    for (int c = 0; c < 6; ++c) out[c] = acc[c] * sc;
+__device__ inline void kelvin(const double x[3], const CgfConst& k, const double* __restrict__ cpsi,
+                              const double* __restrict__ spsi, double out[6]) {
+    kelvin_point(x, k.c11, k.c12, k.c44, k.npsi, cpsi, spsi, out);
 }
 
 // G0 = G_K(t) and g1(phi_j) = (r_hat_j . grad) G_K at t (central difference, step h).

@@ -27,6 +27,7 @@ EXPORTED = [
     "fbc_autotune", "fbc_set_work_list", "fbc_learned_last_error", "fbc_sur_create", "fbc_sur_destroy", "fbc_sur_set_mlp",
     "fbc_sur_eval", "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_destroy", "fbc_mlp_num_params",
     "fbc_mlp_params", "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
+    "fbc_plgf_last_error", "fbc_plgf_create", "fbc_plgf_destroy", "fbc_plgf_table", "fbc_plgf_eval",
 ]
 
 
@@ -70,6 +71,10 @@ class Info(C.Structure):
                 ("n_offsets", C.c_int64), ("nsplit", C.c_int), ("job_order", C.c_int),
                 ("n_jobs", C.c_int), ("product_bytes", C.c_double), ("product_flops", C.c_double),
                 ("skipped_fraction", C.c_double)]
+
+
+class PlgfOpts(C.Structure):
+    _fields_ = [("torus_l", C.c_int), ("r2x4_cut", C.c_int), ("r2x4_match", C.c_int), ("n_psi", C.c_int)]
 
 
 class TuneResult(C.Structure):
@@ -127,11 +132,19 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp]
     lib.fbc_mlp_adam_step.argtypes = [vp, C.c_float, vp]
     lib.fbc_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
+    lib.fbc_plgf_last_error.argtypes = []
+    lib.fbc_plgf_last_error.restype = cp
+    lib.fbc_plgf_create.argtypes = [C.POINTER(Lattice), C.POINTER(PlgfOpts), vp, C.POINTER(vp)]
+    lib.fbc_plgf_destroy.argtypes = [vp]
+    lib.fbc_plgf_destroy.restype = None
+    lib.fbc_plgf_table.argtypes = [vp, C.POINTER(C.c_int), vp, vp, vp]
+    lib.fbc_plgf_eval.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_int, vp, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
                  "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_num_params", "fbc_mlp_params",
-                 "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward"):
+                 "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
+                 "fbc_plgf_create", "fbc_plgf_table", "fbc_plgf_eval"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -359,6 +372,55 @@ class Surrogate:
     def close(self):
         if self.handle:
             self._lib.fbc_sur_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PeriodicGreen:
+    """Real-space line-periodic lattice Green function: near-field table within r_cut,
+    continuum beyond, image sum with Richardson extrapolation (fbc_plgf_*)."""
+
+    def __init__(self, torus_l: int = 64, r2x4_cut: int = 100, r2x4_match: int = 144, n_psi: int = 64,
+                 spring_k: float = 1.0, lattice_a: float = 1.0, stream=None):
+        lib = load_library()
+        self._lib = lib
+        self.handle = C.c_void_p()
+        lat = Lattice(float(lattice_a), float(spring_k))
+        opts = PlgfOpts(int(torus_l), int(r2x4_cut), int(r2x4_match), int(n_psi))
+        self._check(lib.fbc_plgf_create(C.byref(lat), C.byref(opts), _stream_handle(stream), C.byref(self.handle)))
+
+    def _check(self, rc):
+        if rc != FBC_OK:
+            raise FbcError(rc, self._lib.fbc_plgf_last_error().decode())
+
+    def table(self):
+        """(vectors int32 [T, 3], values float64 [T, 6], c float64 [6]) on the host."""
+        import numpy as np
+        n = C.c_int()
+        self._check(self._lib.fbc_plgf_table(self.handle, C.byref(n), None, None, None))
+        vec = np.zeros((n.value, 3), dtype=np.int32)
+        val = np.zeros((n.value, 6))
+        c = np.zeros(6)
+        self._check(self._lib.fbc_plgf_table(self.handle, C.byref(n), vec.ctypes.data, val.ctypes.data,
+                                             c.ctypes.data))
+        return vec, val, c
+
+    def eval(self, disp, out, nz: int, n_rich: int = 1, order: int = 5, stream=None):
+        """disp int32 [n, 3], out float64 [n, 6] (device tensors)."""
+        import torch
+        n = int(disp.shape[0])
+        self._check(self._lib.fbc_plgf_eval(self.handle, _dptr(disp, torch.int32) if n else None, n, int(nz),
+                                            int(n_rich), int(order), _dptr(out) if n else None,
+                                            _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            self._lib.fbc_plgf_destroy(self.handle)
             self.handle = C.c_void_p()
 
     def __del__(self):
