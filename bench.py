@@ -274,6 +274,92 @@ def _cpu_model() -> str:
     return "unknown"
 
 
+# Real-space periodic Green function (fbc_plgf_eval): algorithmic FP64 flops of one
+# continuum evaluation (64 circle nodes x 69 flops: node vector 9, acoustic tensor 24,
+# symmetric inverse 30, accumulation 6; wave sum 36; set-up 48) and of one image term.
+PLGF_FLOPS_KELVIN = 64 * 69 + 36 + 48
+PLGF_FLOPS_IMAGE = 12
+FP64_VECTOR_PEAK = 78.6
+
+
+def bench_plgf(args, torch) -> dict:
+    """Line-periodic Green function at every (column offset, layer offset) of the medium
+    cell: 70,666 distinct offsets x 128 layers, paper parameters (r_cut = 5 a, six images,
+    N = 5)."""
+    import fbc_workloads as W
+    from paper_2105_08798_amd import PeriodicGreen
+    wl = W.make_single("medium")
+    c = wl.cells[0]
+    nz = c.nz
+    d12 = np.unique((c.cols_b[:, None, :].astype(np.int64) - c.cols_i[None, :, :]).reshape(-1, 2), axis=0)
+    disp = np.empty((len(d12) * nz, 3), dtype=np.int32)
+    disp[:, 0] = np.tile(np.arange(nz), len(d12))
+    disp[:, 1:] = np.repeat(d12, nz, axis=0)
+    n_rich, order = 1, 5
+    K = n_rich + order
+    # continuum evaluations per call: images outside r_cut (4|B n|^2 > 100), integer test
+    n_cgf = 0
+    for i in range(-K, K + 1):
+        a = disp[:, 0].astype(np.int64) + i * nz + disp[:, 1] + disp[:, 2]
+        b = disp[:, 2].astype(np.int64) - disp[:, 0] - i * nz
+        n_cgf += int(((a * a + b * b + disp[:, 1].astype(np.int64) ** 2) > 100).sum())
+    origin_cgf = sum(1 for i in range(-K, K + 1) if 2 * (i * nz) ** 2 > 100)
+    flops = (n_cgf + origin_cgf) * PLGF_FLOPS_KELVIN + disp.shape[0] * (2 * K + 1) * PLGF_FLOPS_IMAGE
+    t0 = time.perf_counter()
+    pg = PeriodicGreen(torus_l=64, r2x4_cut=100, r2x4_match=144, n_psi=64)
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    d = torch.from_numpy(disp).cuda()
+    out = torch.empty((disp.shape[0], 6), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        pg.eval(d, out, nz, n_rich, order)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(args.steps):
+        pg.eval(d, out, nz, n_rich, order)
+    e1.record(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    # parity on a seeded sample against the oracle
+    from oracle import plgf as oplgf
+    rng = np.random.default_rng(0)
+    idx = rng.choice(disp.shape[0], 256, replace=False)
+    ora = oplgf.InfiniteLatticeGreen(64, 100, 144, n_psi=64)
+    ref = oplgf.periodic_green(ora, disp[idx].astype(np.int64), nz, n_rich, order)
+    ref6 = np.stack([ref[:, i, j] for i, j in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))], axis=-1)
+    got = out.cpu().numpy()[idx]
+    err = float(np.abs(got - ref6).max() / np.abs(ref6).max())
+    log(f"plgf: table {t_table:.2f} s, {disp.shape[0]} entries, {dt * 1e3:.3f} ms/call "
+        f"({ev_ms:.3f} ms by events), {flops / (ev_ms * 1e-3) / 1e12:.1f} TFLOP/s, err {err:.1e}")
+    line = {
+        "metric": "line-periodic lattice Green blocks/s (real-space construction, Section 3.1)",
+        "value": disp.shape[0] / dt, "unit": "3x3 blocks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"plgf: every (column offset, layer offset) of the medium cell "
+                               f"({len(d12)} offsets x {nz} layers), r_cut = 5 a, torus 64^3, "
+                               f"n = {n_rich}, N = {order}, 64 circle nodes",
+                   "rel_err_vs_oracle_sample": err, "table_s": t_table},
+        "roofline": {"bound": "alu", "achieved": flops / (ev_ms * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK,
+                     "unit": "TFLOP/s", "frac": flops / (ev_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK,
+                     "traffic": None, "kernel": "k_plgf_eval", "flops_per_launch": flops},
+    }
+    if not args.no_cpu:
+        sub = disp[rng.choice(disp.shape[0], 2048, replace=False)].astype(np.int64)
+        t0 = time.perf_counter()
+        oplgf.periodic_green(ora, sub, nz, n_rich, order)
+        tc = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": len(sub) / tc, "unit": "3x3 blocks/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{len(sub)} seeded entries of the same workload (numpy, one thread)",
+                                "cpu": _cpu_model()}
+    pg.close()
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +388,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "plgf":
+        print(json.dumps(bench_plgf(args, torch)), flush=True)
+        return 0
     wl = W.make_batched() if args.workload == "batched" else W.make_single(args.workload)
     if args.forms is None:
         args.forms = "dtable_fp64" if args.workload == "batched" else "fp64,fp32,split_bf16,split_fp16,surrogate"

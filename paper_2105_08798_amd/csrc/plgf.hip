@@ -174,37 +174,74 @@ __global__ void __launch_bounds__(NTP) k_plgf_origin(int nz, int K, PlgfConst k,
     if ((threadIdx.x & 63) < 6) origin[6 * (i + K) + (threadIdx.x & 63)] = g[threadIdx.x & 63];
 }
 
-struct RichW {
-    double w[8];
+// Richardson combination folded into one coefficient per image: Q0 = sum_k w_k G~_{n+k}
+// and G~_k sums the images |i| <= k, so image i enters with coef_i = sum of w_k over
+// n + k >= max(|i|, n).  coef[i + K], K = n + N.
+struct RichC {
+    double c[2 * PLGF_MAX_IMAGES + 1];
 };
 
-// One wave per displacement: partial sums G~_k over |i| <= k (the i = 0 term, then -k and
-// +k for k = 1..n_rich + order), folded into the Richardson combination as they complete.
-__global__ void __launch_bounds__(NTP) k_plgf_eval(const int32_t* __restrict__ disp, int64_t n, int nz,
-                                                   int n_rich, int order, RichW rw, PlgfConst k,
-                                                   const int* __restrict__ map,
+// 1/d by the hardware reciprocal and two Newton steps (relative error near 1 ulp).
+__device__ inline double rcp_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Kelvin solution at a lattice vector by one thread (nodes in sequence; cpsi/spsi are read
+// at a uniform index), the symmetric inverse with the Newton reciprocal.
+__device__ inline void kelvin_thread(int n0, int n1, int n2, const PlgfConst& k, const double* __restrict__ cpsi,
+                                     const double* __restrict__ spsi, double out[6]) {
+    double x[3];
+    cube_pos(n0, n1, n2, x);
+    const double rinv = rcp_nr(sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
+    const double xh[3] = {x[0] * rinv, x[1] * rinv, x[2] * rinv};
+    double u[3], v[3];
+    normal_pair(xh, u, v);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int l = 0; l < k.npsi; ++l) {
+        const double cl = cpsi[l], sl = spsi[l];
+        const double n[3] = {cl * u[0] + sl * v[0], cl * u[1] + sl * v[1], cl * u[2] + sl * v[2]};
+        double g[6];
+        acoustic(n, k.c11, k.c12, k.c44, g);
+        const double a = g[0], b = g[1], c = g[2], xy = g[3], xz = g[4], yz = g[5];
+        const double cxx = b * c - yz * yz, cyy = a * c - xz * xz, czz = a * b - xy * xy;
+        const double cxy = xz * yz - xy * c, cxz = xy * yz - b * xz, cyz = xy * xz - a * yz;
+        const double inv = rcp_nr(a * cxx + xy * cxy + xz * cxz);
+        acc[0] += cxx * inv; acc[1] += cyy * inv; acc[2] += czz * inv;
+        acc[3] += cxy * inv; acc[4] += cxz * inv; acc[5] += cyz * inv;
+    }
+    const double sc = rinv / (4.0 * M_PI * k.npsi);
+    for (int c = 0; c < 6; ++c) out[c] = acc[c] * sc;
+}
+
+// One thread per displacement: Q0 = sum_i coef_i [G~inf(r + i N_z b0) - G~inf(i N_z b0)].
+__global__ void __launch_bounds__(NTP) k_plgf_eval(const int32_t* __restrict__ disp, int64_t n, int nz, int K,
+                                                   RichC rc, PlgfConst k, const int* __restrict__ map,
                                                    const double* __restrict__ table,
                                                    const double* __restrict__ cpsi,
                                                    const double* __restrict__ spsi,
                                                    const double* __restrict__ origin,
                                                    double* __restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * (NTP / 64) + (threadIdx.x >> 6);
+    const int64_t j = (int64_t)blockIdx.x * NTP + threadIdx.x;
     if (j >= n) return;
-    const int K = n_rich + order;
     const int d0 = disp[3 * j], d1 = disp[3 * j + 1], d2 = disp[3 * j + 2];
-    double acc[6], q[6] = {0, 0, 0, 0, 0, 0}, t[6];
-    ginf_wave(d0, d1, d2, k, map, table, cpsi, spsi, t);
-    for (int c = 0; c < 6; ++c) acc[c] = t[c] - origin[6 * K + c];
-    for (int kk = 1; kk <= K; ++kk) {
-        for (int sgn = -1; sgn <= 1; sgn += 2) {
-            const int i = sgn * kk;
-            ginf_wave(d0 + i * nz, d1, d2, k, map, table, cpsi, spsi, t);
-            for (int c = 0; c < 6; ++c) acc[c] = acc[c] + t[c] - origin[6 * (i + K) + c];
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = -K; i <= K; ++i) {
+        const int m0 = d0 + i * nz;
+        double t[6];
+        if (four_r2(m0, d1, d2) <= k.r2x4_cut) {
+            const int ti = table_index(map, k, m0, d1, d2);
+            for (int c = 0; c < 6; ++c) t[c] = (ti >= 0) ? table[6 * ti + c] : __builtin_nan("");
+        } else {
+            kelvin_thread(m0, d1, d2, k, cpsi, spsi, t);
         }
-        if (kk >= n_rich)
-            for (int c = 0; c < 6; ++c) q[c] += rw.w[kk - n_rich] * acc[c];
+        const double w = rc.c[i + K];
+        for (int c = 0; c < 6; ++c) q[c] = fma(w, t[c] - origin[6 * (i + K) + c], q[c]);
     }
-    if ((threadIdx.x & 63) < 6) out[6 * j + (threadIdx.x & 63)] = q[threadIdx.x & 63];
+    for (int c = 0; c < 6; ++c) out[6 * j + c] = q[c];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -394,18 +431,23 @@ extern "C" fbc_status fbc_plgf_eval(fbc_plgf* p, const int32_t* disp, int64_t n,
         return pfail(FBC_E_ARG, "need n_rich >= 1, 0 <= order <= 7, n_rich + order <= 16");
     if (n == 0) return FBC_OK;
     hipStream_t st = (hipStream_t)stream;
-    RichW rw{};
-    double fact[8] = {1, 1, 2, 6, 24, 120, 720, 5040};
+    double w[8], fact[8] = {1, 1, 2, 6, 24, 120, 720, 5040};
     for (int i = 0; i <= order; ++i)
-        rw.w[i] = std::pow((double)(n_rich + i), order) * (((i + order) & 1) ? -1.0 : 1.0) / (fact[i] * fact[order - i]);
+        w[i] = std::pow((double)(n_rich + i), order) * (((i + order) & 1) ? -1.0 : 1.0) / (fact[i] * fact[order - i]);
     const int K = n_rich + order;
+    RichC rc{};
+    for (int i = -K; i <= K; ++i) {
+        double s = 0.0;
+        for (int kk = std::max(std::abs(i), n_rich); kk <= K; ++kk) s += w[kk - n_rich];
+        rc.c[i + K] = s;
+    }
     const int waves = NTP / 64;
     hipLaunchKernelGGL(k_plgf_origin, dim3((2 * K + 1 + waves - 1) / waves), dim3(NTP), 0, st, nz, K, p->kc,
                        p->map, p->table, p->cpsi, p->spsi, p->origin);
-    const int64_t blocks = (n + waves - 1) / waves;
+    const int64_t blocks = (n + NTP - 1) / NTP;
     if (blocks > 0x7fffffffLL) return pfail(FBC_E_ARG, "n too large");
-    hipLaunchKernelGGL(k_plgf_eval, dim3((unsigned)blocks), dim3(NTP), 0, st, disp, n, nz, n_rich, order, rw,
-                       p->kc, p->map, p->table, p->cpsi, p->spsi, p->origin, out);
+    hipLaunchKernelGGL(k_plgf_eval, dim3((unsigned)blocks), dim3(NTP), 0, st, disp, n, nz, K, rc, p->kc, p->map,
+                       p->table, p->cpsi, p->spsi, p->origin, out);
     PCHK(hipGetLastError());
     return FBC_OK;
 }
