@@ -127,53 +127,6 @@ __global__ void __launch_bounds__(NTP) k_plgf_match(const int32_t* __restrict__ 
     for (int e = threadIdx.x; e < 6 * n_table; e += NTP) table[e] = gl_table[e] - cc[e % 6];
 }
 
-// G~inf at one lattice vector, computed by a whole wave: the table within r_cut, else the
-// Kelvin circle integral with the quadrature nodes spread over the lanes and a fixed
-// butterfly sum.  Every lane returns the value.
-__device__ inline void ginf_wave(int n0, int n1, int n2, const PlgfConst& k, const int* __restrict__ map,
-                                 const double* __restrict__ table, const double* __restrict__ cpsi,
-                                 const double* __restrict__ spsi, double out[6]) {
-    if (four_r2(n0, n1, n2) <= k.r2x4_cut) {
-        const int t = table_index(map, k, n0, n1, n2);
-        for (int c = 0; c < 6; ++c) out[c] = (t >= 0) ? table[6 * t + c] : __builtin_nan("");
-        return;
-    }
-    const int lane = threadIdx.x & 63;
-    double x[3];
-    cube_pos(n0, n1, n2, x);
-    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    const double xh[3] = {x[0] / r, x[1] / r, x[2] / r};
-    double u[3], v[3];
-    normal_pair(xh, u, v);
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int l = lane; l < k.npsi; l += 64) {
-        const double n[3] = {cpsi[l] * u[0] + spsi[l] * v[0], cpsi[l] * u[1] + spsi[l] * v[1],
-                             cpsi[l] * u[2] + spsi[l] * v[2]};
-        double g[6], o[6];
-        acoustic(n, k.c11, k.c12, k.c44, g);
-        sym_inverse(g, o);
-        for (int c = 0; c < 6; ++c) acc[c] += o[c];
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-    const double sc = 1.0 / (4.0 * M_PI * k.npsi * r);
-    for (int c = 0; c < 6; ++c) out[c] = acc[c] * sc;
-}
-
-// Images of the origin, G~inf(i N_z e0) for i = -K..K (one wave per image).
-__global__ void __launch_bounds__(NTP) k_plgf_origin(int nz, int K, PlgfConst k, const int* __restrict__ map,
-                                                     const double* __restrict__ table,
-                                                     const double* __restrict__ cpsi,
-                                                     const double* __restrict__ spsi,
-                                                     double* __restrict__ origin) {
-    const int i = (int)(blockIdx.x * (NTP / 64) + (threadIdx.x >> 6)) - K;
-    if (i > K) return;
-    double g[6];
-    ginf_wave(i * nz, 0, 0, k, map, table, cpsi, spsi, g);
-    if ((threadIdx.x & 63) < 6) origin[6 * (i + K) + (threadIdx.x & 63)] = g[threadIdx.x & 63];
-}
-
 // Richardson combination folded into one coefficient per image: Q0 = sum_k w_k G~_{n+k}
 // and G~_k sums the images |i| <= k, so image i enters with coef_i = sum of w_k over
 // n + k >= max(|i|, n).  coef[i + K], K = n + N.
@@ -242,6 +195,26 @@ __global__ void __launch_bounds__(NTP) k_plgf_eval(const int32_t* __restrict__ d
         for (int c = 0; c < 6; ++c) q[c] = fma(w, t[c] - origin[6 * (i + K) + c], q[c]);
     }
     for (int c = 0; c < 6; ++c) out[6 * j + c] = q[c];
+}
+
+// Images of the origin, G~inf(i N_z b0) for i = -K..K (one thread per image, the same
+// evaluation as the displacement terms, so a zero displacement gives exactly zero).
+__global__ void __launch_bounds__(64) k_plgf_origin(int nz, int K, PlgfConst k, const int* __restrict__ map,
+                                                    const double* __restrict__ table,
+                                                    const double* __restrict__ cpsi,
+                                                    const double* __restrict__ spsi,
+                                                    double* __restrict__ origin) {
+    const int i = (int)threadIdx.x - K;
+    if (i > K) return;
+    const int m0 = i * nz;
+    double t[6];
+    if (four_r2(m0, 0, 0) <= k.r2x4_cut) {
+        const int ti = table_index(map, k, m0, 0, 0);
+        for (int c = 0; c < 6; ++c) t[c] = (ti >= 0) ? table[6 * ti + c] : __builtin_nan("");
+    } else {
+        kelvin_thread(m0, 0, 0, k, cpsi, spsi, t);
+    }
+    for (int c = 0; c < 6; ++c) origin[6 * (i + K) + c] = t[c];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -441,8 +414,7 @@ extern "C" fbc_status fbc_plgf_eval(fbc_plgf* p, const int32_t* disp, int64_t n,
         for (int kk = std::max(std::abs(i), n_rich); kk <= K; ++kk) s += w[kk - n_rich];
         rc.c[i + K] = s;
     }
-    const int waves = NTP / 64;
-    hipLaunchKernelGGL(k_plgf_origin, dim3((2 * K + 1 + waves - 1) / waves), dim3(NTP), 0, st, nz, K, p->kc,
+    hipLaunchKernelGGL(k_plgf_origin, dim3(1), dim3(64), 0, st, nz, K, p->kc,
                        p->map, p->table, p->cpsi, p->spsi, p->origin);
     const int64_t blocks = (n + NTP - 1) / NTP;
     if (blocks > 0x7fffffffLL) return pfail(FBC_E_ARG, "n too large");

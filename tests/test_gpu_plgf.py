@@ -62,6 +62,8 @@ def test_periodic_green_matches_oracle(pair, nz, n_rich, order):
     scale = np.abs(ref).max()
     assert np.isfinite(got).all()
     assert np.abs(got - ref).max() < 1e-10 * scale, np.abs(got - ref).max() / scale
+    # the origin's images are subtracted: the value at r = 0 is zero (gauge of eq. plgf_conv)
+    assert np.abs(ref[0]).max() == 0.0 and np.abs(got[0]).max() < 1e-14 * scale
 
 
 def test_full_line_modes_at_medium_geometry(pair):
