@@ -360,6 +360,83 @@ def bench_plgf(args, torch) -> dict:
     return line
 
 
+def bench_hmat(args, torch) -> dict:
+    """H-matrix form (Appendix C: b_min = 20, gamma = 2, eps = 1e-5) of every line mode of
+    the medium cell, built from the FP64 context's store; the H-matrix product over all
+    modes against the dense FP64 product of the same context."""
+    import fbc_workloads as W
+    from paper_2105_08798_amd import FBC, HMatrix
+    wl = W.make_single("medium")
+    c = wl.cells[0]
+    nm, R = c.nz // 2 + 1, c.n_rhs
+    dev = torch.device("cuda:0")
+    ctx = FBC(wl.cells, wl.bz, form="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = HMatrix(ctx, b_min=20, gamma=2, eps=1e-5, max_rank=args.max_rank)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    rng = np.random.default_rng(3)
+    fh = rng.normal(size=(nm, 3 * c.n_i, R)) + 1j * rng.normal(size=(nm, 3 * c.n_i, R))
+    x = torch.from_numpy(np.ascontiguousarray(np.stack([fh.real, fh.imag], axis=-1))).to(dev)
+    y = torch.empty((nm, 3 * c.n_b, R, 2), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        h.apply(x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        h.apply(x, y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # dense FP64 product of the same context (its own kernel timing)
+    f = torch.from_numpy(c.forces.ravel().copy()).to(dev)
+    w = torch.zeros(R * c.nz * c.n_b * 3, dtype=torch.float64, device=dev)
+    ctx.timing(True)
+    for _ in range(3):
+        ctx.green_apply(f, w)
+    torch.cuda.synchronize()
+    ctx.timing_read()
+    for _ in range(10):
+        ctx.green_apply(f, w)
+    torch.cuda.synchronize()
+    dense_ms, n_d = ctx.timing_read()
+    dense_ms = dense_ms / max(n_d, 1)
+    info = h.info
+    from oracle import green
+    yy = y.cpu().numpy()
+    got = yy[..., 0] + 1j * yy[..., 1]
+    errs = []
+    for m in (0, 7, 64):
+        a = green.green_modes_dense(c.nz, wl.bz, wl.bz, c.cols_b, c.cols_i, modes=[m])[0]
+        ref = a @ fh[m]
+        errs.append(float(np.linalg.norm(got[m] - ref) / np.linalg.norm(ref)))
+    bytes_ = info.stored_entries * 16 + nm * 3 * (c.n_i + c.n_b) * R * 16
+    log(f"hmat: build {t_build:.2f} s, {info.n_blocks} blocks ({info.n_low_rank} low rank), max rank "
+        f"{info.max_rank_used}, stored {info.stored_entries / info.dense_entries:.3f} of dense, "
+        f"{ms:.3f} ms per product (dense FP64 product {dense_ms:.3f} ms), errors {errs}")
+    line = {
+        "metric": "H-matrix products/s over all line modes (Appendix C form, FP64)",
+        "value": 1e3 / ms, "unit": "products/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"hmat: medium cell (N_z = {c.nz}, n_i = {c.n_i}, n_b = {c.n_b}, {R} RHS, "
+                               f"{nm} modes), b_min = 20, gamma = 2, eps = 1e-5, max rank {args.max_rank}",
+                   "build_s": t_build, "n_blocks": info.n_blocks, "n_low_rank": info.n_low_rank,
+                   "max_rank_used": info.max_rank_used, "n_over_rank": info.n_over_rank,
+                   "stored_fraction": info.stored_entries / info.dense_entries,
+                   "dense_fp64_product_ms": dense_ms, "rel_err_modes_0_7_64": errs},
+        "roofline": {"bound": "hbm", "achieved": bytes_ / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_hmat_vt + k_hmat_y", "bytes_per_launch": bytes_},
+    }
+    h.close()
+    ctx.close()
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,6 +451,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000, help="Adam steps of the surrogate's MLP")
     ap.add_argument("--cpu-modes", type=int, default=3)
+    ap.add_argument("--max-rank", type=int, default=64, help="rank bound of the H-matrix workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -390,6 +468,9 @@ def main() -> int:
         return 1
     if args.workload == "plgf":
         print(json.dumps(bench_plgf(args, torch)), flush=True)
+        return 0
+    if args.workload == "hmat":
+        print(json.dumps(bench_hmat(args, torch)), flush=True)
         return 0
     wl = W.make_batched() if args.workload == "batched" else W.make_single(args.workload)
     if args.forms is None:

@@ -398,6 +398,68 @@ fbc_status fbc_plgf_table(const fbc_plgf* p, int* n_table, int32_t* vectors, dou
 fbc_status fbc_plgf_eval(fbc_plgf* p, const int32_t* disp, int64_t n, int nz, int n_rich,
                          int order, double* out, void* stream);
 
+/* ------------------------------------------------------------------------------------
+ * H-matrix form of the per-mode Green blocks (Appendix C).  For every line mode m of a
+ * cell, G^(m) (3 n_b x 3 n_i complex) is split by the block partition of two cluster
+ * trees: binary space partitioning of the in-plane column positions, each cluster cut
+ * along the longer side of its bounding box at the median (ties by column index) until it
+ * holds at most b_min columns; a block t x s is low rank when
+ * min(diam t, diam s) <= gamma dist(t, s) (eq. geom_adm on the bounding boxes: diam =
+ * box diagonal, dist = distance between the boxes, decided in exact integers; the text's
+ * centroid distance admits touching half rings; the line direction is diagonalised
+ * by the line transform, so the periodic images s+- share the in-plane position of s), a
+ * dense leaf when both clusters are leaves, and subdivided otherwise.  Low-rank blocks
+ * are compressed by adaptive cross approximation with partial pivoting (eq. aca; first
+ * row of the block first, then the unused row of largest |u_k|; stop when
+ * |u_k| |v_k| <= eps ||S_k||_F holds for two consecutive terms); rows and columns of a
+ * block follow the tree order (first child's columns, then the second's).  A block that
+ * needs more than max_rank terms is applied from the dense store instead.  Paper:
+ * b_min = 20, gamma = 2, eps = 1e-5.
+ * ------------------------------------------------------------------------------------ */
+typedef struct fbc_hmat fbc_hmat;
+
+typedef struct {
+    int b_min;          /* minimal cluster size in atom columns (>= 1)                  */
+    int gamma;          /* admissibility constant, integer in [1, 64]                  */
+    double eps;         /* cross-approximation accuracy bound (> 0)                    */
+    int max_rank;       /* rank bound per block, in [1, 512]                           */
+} fbc_hmat_opts;
+
+typedef struct {
+    int n_blocks, n_low_rank, n_dense;   /* partition leaves (same for every mode)      */
+    int max_rank_used;                   /* largest rank over modes and blocks          */
+    int n_over_rank;                     /* (mode, block) pairs applied from the store   */
+    double stored_entries;               /* complex entries of the factors and dense
+                                            leaves over all modes                       */
+    double dense_entries;                /* the same matrices stored densely            */
+} fbc_hmat_info;
+
+/* Last error text of the fbc_hmat_* calls on this host thread. */
+const char* fbc_hmat_last_error(void);
+
+/* Builds the H-matrices of every line mode of `ctx` (FBC_FORM_FP64, exactly one cell;
+ * FBC_E_UNSUPPORTED otherwise) from its dense store; the context must outlive the
+ * object, which reads the store for dense leaves.  Trees and partition on the host
+ * (geometry only), the cross approximations on the device (one work group per block and
+ * mode).  Synchronises `stream`. */
+fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* opts, void* stream,
+                           fbc_hmat** out);
+void fbc_hmat_destroy(fbc_hmat* h);
+fbc_status fbc_hmat_get_info(const fbc_hmat* h, fbc_hmat_info* info);
+
+/* The partition as a host int32 stream: per block kind (1 low rank, 0 dense), n_t, n_s,
+ * the n_t pad and the n_s interface column indices (tree order).  *n_out = its length;
+ * out may be NULL to query it (else cap >= *n_out). */
+fbc_status fbc_hmat_partition(const fbc_hmat* h, int32_t* out, int64_t cap, int64_t* n_out);
+
+/* Ranks [n_modes][n_low_rank] (host; -1: over the rank bound). */
+fbc_status fbc_hmat_ranks(const fbc_hmat* h, int32_t* out);
+
+/* what = H f per mode: fhat [n_modes][3 n_i][R] and what [n_modes][3 n_b][R], complex
+ * FP64 interleaved (re, im), device; R = the cell's n_rhs.  Asynchronous; calls on one
+ * object must be ordered (it holds the products V^T f of the call in flight). */
+fbc_status fbc_hmat_apply(fbc_hmat* h, const double* fhat, double* what, void* stream);
+
 const char* fbc_status_string(fbc_status s);
 
 #ifdef __cplusplus

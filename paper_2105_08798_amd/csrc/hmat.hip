@@ -1,0 +1,642 @@
+// H-matrix form of the per-mode Green blocks (Appendix C): for every line mode m the
+// complex matrix G^(m) (3 n_b x 3 n_i, taken from an FP64 context's dense store) is split
+// by the block partition of two cluster trees (binary space partitioning of the in-plane
+// column positions, down to b_min columns; a block t x s is low rank when
+// min(diam t, diam s) <= gamma dist(t, s), eq. geom_adm, on the clusters' bounding boxes,
+// decided in exact integers), the
+// admissible blocks are compressed by adaptive cross approximation with partial pivoting
+// (eq. aca), and the H-matrix product y = H x replaces the dense product.  The line
+// direction is diagonalised by the line transform, so the admissibility is evaluated in
+// the plane (the periodic images s+ and s- share the in-plane position of s).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+#define NTH 256
+
+static thread_local std::string g_herr;
+
+static fbc_status hfail(fbc_status s, const std::string& m) {
+    g_herr = m;
+    return s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Host planning: cluster trees and block partition (geometry only, exact integers)
+// ---------------------------------------------------------------------------------------
+struct HNode {
+    std::vector<int> idx;             // column indices in tree order
+    long long xlo, xhi, ylo, yhi, sx, sy;
+    long long n, diam8;               // 8 diam^2 = 2 dX^2 + dY^2
+    int child[2] = {-1, -1};
+};
+
+static int build_tree(std::vector<HNode>& nodes, const std::vector<int32_t>& cols, std::vector<int> idx,
+                      int b_min) {
+    HNode h;
+    h.n = (long long)idx.size();
+    h.xlo = h.ylo = (1LL << 40);
+    h.xhi = h.yhi = -(1LL << 40);
+    h.sx = h.sy = 0;
+    for (int c : idx) {
+        const long long X = cols[2 * c], Y = (long long)cols[2 * c] + 2LL * cols[2 * c + 1];
+        h.xlo = std::min(h.xlo, X); h.xhi = std::max(h.xhi, X);
+        h.ylo = std::min(h.ylo, Y); h.yhi = std::max(h.yhi, Y);
+        h.sx += X; h.sy += Y;
+    }
+    const long long dx = h.xhi - h.xlo, dy = h.yhi - h.ylo;
+    h.diam8 = 2 * dx * dx + dy * dy;
+    const int me = (int)nodes.size();
+    nodes.push_back(h);
+    if ((int)idx.size() > b_min) {
+        const bool on_x = 2 * dx * dx >= dy * dy;      // longer side of the bounding box
+        auto key = [&](int c) -> long long {
+            return on_x ? (long long)cols[2 * c] : (long long)cols[2 * c] + 2LL * cols[2 * c + 1];
+        };
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+            const long long ka = key(a), kb = key(b);
+            return ka != kb ? ka < kb : a < b;
+        });
+        const size_t half = idx.size() / 2;
+        std::vector<int> lo(idx.begin(), idx.begin() + half), hi(idx.begin() + half, idx.end());
+        const int c0 = build_tree(nodes, cols, lo, b_min);
+        const int c1 = build_tree(nodes, cols, hi, b_min);
+        nodes[me].child[0] = c0;
+        nodes[me].child[1] = c1;
+        nodes[me].idx.clear();
+        nodes[me].idx.insert(nodes[me].idx.end(), nodes[c0].idx.begin(), nodes[c0].idx.end());
+        nodes[me].idx.insert(nodes[me].idx.end(), nodes[c1].idx.begin(), nodes[c1].idx.end());
+    } else {
+        nodes[me].idx = idx;
+    }
+    return me;
+}
+
+// eq. geom_adm on bounding boxes: min(diam t, diam s) <= gamma dist(t, s), with
+// 8 diam^2 = 2 dX^2 + dY^2 and 8 dist^2 = 2 gX^2 + gY^2 (gX, gY: gaps between the boxes).
+static bool admissible(const HNode& t, const HNode& s, int gamma) {
+    const long long gx = std::max(0LL, std::max(s.xlo - t.xhi, t.xlo - s.xhi));
+    const long long gy = std::max(0LL, std::max(s.ylo - t.yhi, t.ylo - s.yhi));
+    return std::min(t.diam8, s.diam8) <= (long long)gamma * gamma * (2 * gx * gx + gy * gy);
+}
+
+struct HPart {
+    int kind;      // 1 low rank, 0 dense
+    int t, s;      // tree nodes
+};
+
+static void partition(const std::vector<HNode>& tb, const std::vector<HNode>& ti, int t, int s, int gamma,
+                      std::vector<HPart>& out) {
+    if (admissible(tb[t], ti[s], gamma)) {
+        out.push_back({1, t, s});
+        return;
+    }
+    const bool tl = tb[t].child[0] < 0, sl = ti[s].child[0] < 0;
+    if (tl && sl) {
+        out.push_back({0, t, s});
+        return;
+    }
+    const int tc[2] = {tl ? t : tb[t].child[0], tl ? -1 : tb[t].child[1]};
+    const int sc[2] = {sl ? s : ti[s].child[0], sl ? -1 : ti[s].child[1]};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            if (tc[a] >= 0 && sc[b] >= 0) partition(tb, ti, tc[a], sc[b], gamma, out);
+}
+
+// Device block description.
+struct HBlk {
+    int kind;            // 1 low rank, 0 dense
+    int t_off, nt;       // pad columns: tcols[t_off .. t_off + nt)
+    int s_off, ns;       // interface columns: scols[s_off .. s_off + ns)
+    int cap;             // rank capacity (low rank)
+    int64_t u_off, v_off;   // factor offsets within a mode (double2)
+    int lr;              // index among the low-rank blocks (T workspace)
+};
+
+struct HStore {
+    const double* a;     // dense store of mode 0 (FP64, fragment layout)
+    int64_t per_mode;    // mp * kp
+    int mp;
+};
+
+__device__ inline double2 entry(const HStore& st, int m, int row, int col) {
+    const double* a = st.a + (int64_t)m * st.per_mode;
+    return make_double2(a[frag_off_f64_km(row, 2 * col, st.mp)], a[frag_off_f64_km(row, 2 * col + 1, st.mp)]);
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Fixed-order reductions over the work group.
+__device__ inline double block_sum_d(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = NTH / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// argmax with the smallest index among equal values; val < 0 marks "none".
+__device__ inline void block_argmax(double& val, int& idx, double* redv, int* redi) {
+    redv[threadIdx.x] = val;
+    redi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int s = NTH / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const double v2 = redv[threadIdx.x + s];
+            const int i2 = redi[threadIdx.x + s];
+            if (v2 > redv[threadIdx.x] || (v2 == redv[threadIdx.x] && i2 < redi[threadIdx.x] && v2 >= 0)) {
+                redv[threadIdx.x] = v2;
+                redi[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    val = redv[0];
+    idx = redi[0];
+    __syncthreads();
+}
+
+__device__ inline int gcol(const int32_t* __restrict__ cols, int off, int j) { return 3 * cols[off + j / 3] + j % 3; }
+
+// Adaptive cross approximation of one (low-rank block, mode): one work group.
+__global__ void __launch_bounds__(NTH) k_hmat_aca(const HBlk* __restrict__ blks, const int* __restrict__ lr_ids,
+                                                  const int32_t* __restrict__ tcols,
+                                                  const int32_t* __restrict__ scols, HStore st,
+                                                  double eps, int max_rank, int64_t u_mode, int64_t v_mode,
+                                                  double2* __restrict__ U, double2* __restrict__ V,
+                                                  int* __restrict__ rank, int n_lr) {
+    __shared__ double redv[NTH];
+    __shared__ int redi[NTH];
+    extern __shared__ unsigned char used[];
+    const int li = blockIdx.x, m = blockIdx.y;
+    const HBlk b = blks[lr_ids[li]];
+    const int nr = 3 * b.nt, nc = 3 * b.ns;
+    double2* Ub = U + (int64_t)m * u_mode + b.u_off;     // U[l * nr + r]
+    double2* Vb = V + (int64_t)m * v_mode + b.v_off;     // V[l * nc + j]
+    for (int r = threadIdx.x; r < nr; r += NTH) used[r] = 0;
+    __syncthreads();
+    int i = 0, k = 0, result = 0, small = 0;
+    double norm2 = 0.0;
+    for (;;) {
+        if (k >= max_rank) {             // another term would exceed the rank bound
+            result = -1;
+            break;
+        }
+        // residual row i into V[k]
+        double bestv = -1.0;
+        int bestj = 0x7fffffff;
+        double2* vk = Vb + (int64_t)k * nc;
+        const int grow = gcol(tcols, b.t_off, i);
+        for (int j = threadIdx.x; j < nc; j += NTH) {
+            double2 a = entry(st, m, grow, gcol(scols, b.s_off, j));
+            for (int l = 0; l < k; ++l) {
+                const double2 p = cmul(Ub[(int64_t)l * nr + i], Vb[(int64_t)l * nc + j]);
+                a.x -= p.x;
+                a.y -= p.y;
+            }
+            vk[j] = a;
+            const double mag = hypot(a.x, a.y);
+            if (mag > bestv) { bestv = mag; bestj = j; }
+        }
+        if (threadIdx.x == 0) used[i] = 1;
+        block_argmax(bestv, bestj, redv, redi);
+        __syncthreads();
+        if (bestv <= 0.0) {
+            // vanishing residual row: the next unused row, or stop
+            int cand = 0x7fffffff;
+            for (int r = threadIdx.x; r < nr; r += NTH)
+                if (!used[r]) { cand = r; break; }
+            double cv = (cand == 0x7fffffff) ? -1.0 : 1.0;
+            int ci = cand;
+            block_argmax(cv, ci, redv, redi);
+            if (cv < 0.0) break;
+            i = ci;
+            continue;
+        }
+        const double2 piv = vk[bestj];
+        __syncthreads();
+        const double den = piv.x * piv.x + piv.y * piv.y;
+        const double2 pinv = make_double2(piv.x / den, -piv.y / den);
+        double nv2 = 0.0;
+        for (int j = threadIdx.x; j < nc; j += NTH) {
+            const double2 v = cmul(vk[j], pinv);
+            vk[j] = v;
+            nv2 += v.x * v.x + v.y * v.y;
+        }
+        __syncthreads();
+        // residual column bestj into U[k]
+        double2* uk = Ub + (int64_t)k * nr;
+        const int gc = gcol(scols, b.s_off, bestj);
+        double nu2 = 0.0;
+        for (int r = threadIdx.x; r < nr; r += NTH) {
+            double2 a = entry(st, m, gcol(tcols, b.t_off, r), gc);
+            for (int l = 0; l < k; ++l) {
+                const double2 p = cmul(Vb[(int64_t)l * nc + bestj], Ub[(int64_t)l * nr + r]);
+                a.x -= p.x;
+                a.y -= p.y;
+            }
+            uk[r] = a;
+            nu2 += a.x * a.x + a.y * a.y;
+        }
+        __syncthreads();
+        nu2 = block_sum_d(nu2, redv);
+        nv2 = block_sum_d(nv2, redv);
+        // cross terms 2 Re sum_l (u_l^H u_k)(v_l^H v_k)
+        double cross = 0.0;
+        for (int l = 0; l < k; ++l) {
+            double ur = 0, ui = 0, vr = 0, vi = 0;
+            for (int r = threadIdx.x; r < nr; r += NTH) {
+                const double2 a = Ub[(int64_t)l * nr + r], c = uk[r];
+                ur += a.x * c.x + a.y * c.y;
+                ui += a.x * c.y - a.y * c.x;
+            }
+            for (int j = threadIdx.x; j < nc; j += NTH) {
+                const double2 a = Vb[(int64_t)l * nc + j], c = vk[j];
+                vr += a.x * c.x + a.y * c.y;
+                vi += a.x * c.y - a.y * c.x;
+            }
+            ur = block_sum_d(ur, redv);
+            ui = block_sum_d(ui, redv);
+            vr = block_sum_d(vr, redv);
+            vi = block_sum_d(vi, redv);
+            cross += 2.0 * (ur * vr - ui * vi);
+        }
+        norm2 = norm2 + cross + nu2 * nv2;
+        ++k;
+        // stop after two consecutive terms below the bound (one small term can come from
+        // a row that misses the block's large entries)
+        small = (sqrt(nu2 * nv2) <= eps * sqrt(fmax(norm2, 0.0))) ? small + 1 : 0;
+        if (small == 2) break;
+        // next pivot row: the unused row of largest |u_k|
+        double bu = -1.0;
+        int bi = 0x7fffffff;
+        for (int r = threadIdx.x; r < nr; r += NTH) {
+            if (used[r]) continue;
+            const double mag = hypot(uk[r].x, uk[r].y);
+            if (mag > bu) { bu = mag; bi = r; }
+        }
+        block_argmax(bu, bi, redv, redi);
+        if (bu < 0.0) break;
+        i = bi;
+    }
+    if (threadIdx.x == 0) rank[(int64_t)m * n_lr + li] = (result < 0) ? -1 : k;
+}
+
+// T[lr][l][r] = sum_j V[l][j] x[col_j][r] for the low-rank blocks.
+__global__ void __launch_bounds__(NTH) k_hmat_vt(const HBlk* __restrict__ blks, const int* __restrict__ lr_ids,
+                                                 const int32_t* __restrict__ scols, const double2* __restrict__ V,
+                                                 int64_t v_mode, const int* __restrict__ rank, int n_lr,
+                                                 int max_rank, const double2* __restrict__ x, int n_i, int R,
+                                                 double2* __restrict__ T) {
+    const int li = blockIdx.x, m = blockIdx.y;
+    const int k = rank[(int64_t)m * n_lr + li];
+    if (k <= 0) return;
+    const HBlk b = blks[lr_ids[li]];
+    const int nc = 3 * b.ns;
+    const double2* Vb = V + (int64_t)m * v_mode + b.v_off;
+    const double2* xm = x + (int64_t)m * 3 * n_i * R;
+    double2* Tb = T + ((int64_t)m * n_lr + li) * max_rank * R;
+    for (int e = threadIdx.x; e < k * R; e += NTH) {
+        const int l = e / R, r = e - l * R;
+        double2 acc = make_double2(0, 0);
+        for (int j = 0; j < nc; ++j) {
+            const double2 p = cmul(Vb[(int64_t)l * nc + j], xm[(int64_t)gcol(scols, b.s_off, j) * R + r]);
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+        Tb[(int64_t)l * R + r] = acc;
+    }
+}
+
+struct HContrib {
+    int blk;           // block index
+    int row0;          // first row of this leaf within the block's rows
+};
+
+// y rows of one pad leaf: sum over the blocks that cover it (low rank: U rows times T;
+// dense or over the rank bound: the stored entries times x).  A thread owns one row and
+// up to HR right-hand sides, so each factor or stored entry is read once per HR of them.
+#define HR 8
+__global__ void __launch_bounds__(NTH) k_hmat_y(const HBlk* __restrict__ blks, const int32_t* __restrict__ scols,
+                                                const int32_t* __restrict__ leaf_cols,
+                                                const int* __restrict__ leaf_off,
+                                                const HContrib* __restrict__ contrib,
+                                                const int* __restrict__ contrib_off, HStore st,
+                                                const double2* __restrict__ U, int64_t u_mode,
+                                                const double2* __restrict__ T, const int* __restrict__ rank,
+                                                int n_lr, int max_rank, const double2* __restrict__ x, int n_i,
+                                                int n_b, int R, double2* __restrict__ y) {
+    const int leaf = blockIdx.x, m = blockIdx.y;
+    const int c0 = leaf_off[leaf], nl = leaf_off[leaf + 1] - c0;
+    const int nrc = (R + HR - 1) / HR;
+    const double2* xm = x + (int64_t)m * 3 * n_i * R;
+    for (int e = threadIdx.x; e < 3 * nl * nrc; e += NTH) {
+        const int rl = e / nrc, r0 = (e - rl * nrc) * HR;       // row within the leaf, first RHS
+        const int nr_here = min(HR, R - r0);
+        const int grow = 3 * leaf_cols[c0 + rl / 3] + rl % 3;
+        double2 acc[HR];
+#pragma unroll
+        for (int q = 0; q < HR; ++q) acc[q] = make_double2(0, 0);
+        for (int q2 = contrib_off[leaf]; q2 < contrib_off[leaf + 1]; ++q2) {
+            const HContrib cb = contrib[q2];
+            const HBlk b = blks[cb.blk];
+            const int br = cb.row0 + rl;                 // row within the block
+            const int k = (b.kind == 1) ? rank[(int64_t)m * n_lr + b.lr] : -1;
+            if (k >= 0) {
+                const double2* Ub = U + (int64_t)m * u_mode + b.u_off;
+                const double2* Tb = T + ((int64_t)m * n_lr + b.lr) * max_rank * R + r0;
+                const int nr = 3 * b.nt;
+                for (int l = 0; l < k; ++l) {
+                    const double2 u = Ub[(int64_t)l * nr + br];
+#pragma unroll
+                    for (int q = 0; q < HR; ++q)
+                        if (q < nr_here) {
+                            const double2 p = cmul(u, Tb[(int64_t)l * R + q]);
+                            acc[q].x += p.x;
+                            acc[q].y += p.y;
+                        }
+                }
+            } else {
+                for (int j = 0; j < 3 * b.ns; ++j) {
+                    const int gc = gcol(scols, b.s_off, j);
+                    const double2 a = entry(st, m, grow, gc);
+                    const double2* xr = xm + (int64_t)gc * R + r0;
+#pragma unroll
+                    for (int q = 0; q < HR; ++q)
+                        if (q < nr_here) {
+                            const double2 p = cmul(a, xr[q]);
+                            acc[q].x += p.x;
+                            acc[q].y += p.y;
+                        }
+                }
+            }
+        }
+        double2* yr = y + ((int64_t)m * 3 * n_b + grow) * R + r0;
+#pragma unroll
+        for (int q = 0; q < HR; ++q)
+            if (q < nr_here) yr[q] = acc[q];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------
+struct fbc_hmat {
+    const fbc_ctx* ctx = nullptr;
+    int nm = 0, n_i = 0, n_b = 0, R = 0, max_rank = 0;
+    int n_lr = 0, n_dense = 0, n_leaves = 0;
+    int64_t u_mode = 0, v_mode = 0;
+    HStore st{};
+    std::vector<HBlk> blk;
+    std::vector<int32_t> part_stream;     // kind, nt, ns, t cols, s cols per block
+    std::vector<int> rank_h;              // [nm][n_lr]
+    std::vector<void*> allocs;
+    HBlk* blk_d = nullptr;
+    int* lr_ids = nullptr;
+    int32_t *tcols = nullptr, *scols = nullptr, *leaf_cols = nullptr;
+    int *leaf_off = nullptr, *contrib_off = nullptr;
+    HContrib* contrib = nullptr;
+    double2 *U = nullptr, *V = nullptr, *T = nullptr;
+    int* rank = nullptr;
+    double stored = 0, dense_total = 0;
+    int max_rank_used = 0, n_overflow = 0;
+};
+
+static void hmat_free(fbc_hmat* h) {
+    if (!h) return;
+    for (void* a : h->allocs) (void)hipFree(a);
+    delete h;
+}
+
+template <class T>
+static fbc_status halloc(fbc_hmat* h, T** p, int64_t bytes) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void**)p, (size_t)std::max<int64_t>(bytes, 16));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return hfail(FBC_E_NOMEM, "hipMalloc(" + std::to_string(bytes) + " B)");
+    }
+    h->allocs.push_back(*p);
+    return FBC_OK;
+}
+
+extern "C" const char* fbc_hmat_last_error(void) { return g_herr.c_str(); }
+
+extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o, void* stream, fbc_hmat** out) {
+    if (!out) return hfail(FBC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctx || !o) return hfail(FBC_E_ARG, "context and options must not be NULL");
+    if (ctx->opt.form != FBC_FORM_FP64 || ctx->cells.size() != 1)
+        return hfail(FBC_E_UNSUPPORTED, "needs an FBC_FORM_FP64 context of one cell");
+    if (o->b_min < 1 || o->gamma < 1 || o->gamma > 64 || !(o->eps > 0) || o->max_rank < 1 || o->max_rank > 512)
+        return hfail(FBC_E_ARG, "need b_min >= 1, gamma in [1, 64], eps > 0, max_rank in [1, 512]");
+    const CellPlan& p = ctx->cells[0];
+    hipStream_t sm = (hipStream_t)stream;
+    fbc_hmat* h = new (std::nothrow) fbc_hmat();
+    if (!h) return hfail(FBC_E_NOMEM, "host allocation");
+    h->ctx = ctx;
+    h->nm = p.nm;
+    h->n_i = p.n_i;
+    h->n_b = p.n_b;
+    h->R = p.R;
+    h->max_rank = o->max_rank;
+    h->st.a = (const double*)ctx->store + p.a_off;
+    h->st.per_mode = (int64_t)p.mp * p.kp;
+    h->st.mp = p.mp;
+    // Steps 1 and 2 on the host
+    std::vector<HNode> tb, ti;
+    std::vector<int> all_b(p.n_b), all_i(p.n_i);
+    for (int c = 0; c < p.n_b; ++c) all_b[c] = c;
+    for (int c = 0; c < p.n_i; ++c) all_i[c] = c;
+    build_tree(tb, p.cols_b, all_b, o->b_min);
+    build_tree(ti, p.cols_i, all_i, o->b_min);
+    std::vector<HPart> part;
+    partition(tb, ti, 0, 0, o->gamma, part);
+    std::vector<int32_t> tcols, scols;
+    std::vector<int> lr_ids;
+    int64_t u_mode = 0, v_mode = 0;
+    for (const HPart& q : part) {
+        HBlk b{};
+        b.kind = q.kind;
+        b.t_off = (int)tcols.size();
+        b.nt = (int)tb[q.t].idx.size();
+        b.s_off = (int)scols.size();
+        b.ns = (int)ti[q.s].idx.size();
+        tcols.insert(tcols.end(), tb[q.t].idx.begin(), tb[q.t].idx.end());
+        scols.insert(scols.end(), ti[q.s].idx.begin(), ti[q.s].idx.end());
+        h->part_stream.push_back(q.kind);
+        h->part_stream.push_back(b.nt);
+        h->part_stream.push_back(b.ns);
+        h->part_stream.insert(h->part_stream.end(), tb[q.t].idx.begin(), tb[q.t].idx.end());
+        h->part_stream.insert(h->part_stream.end(), ti[q.s].idx.begin(), ti[q.s].idx.end());
+        b.lr = -1;
+        if (q.kind == 1) {
+            b.cap = o->max_rank;
+            b.u_off = u_mode;
+            b.v_off = v_mode;
+            u_mode += (int64_t)3 * b.nt * b.cap;
+            v_mode += (int64_t)3 * b.ns * b.cap;
+            b.lr = (int)lr_ids.size();
+            lr_ids.push_back((int)h->blk.size());
+        }
+        h->blk.push_back(b);
+    }
+    h->n_lr = (int)lr_ids.size();
+    h->n_dense = (int)h->blk.size() - h->n_lr;
+    h->u_mode = u_mode;
+    h->v_mode = v_mode;
+    // pad leaves and the blocks covering them: a leaf's columns are a contiguous run of the
+    // columns of every ancestor, in tree order
+    std::vector<int> leaf_node;
+    for (int n = 0; n < (int)tb.size(); ++n)
+        if (tb[n].child[0] < 0) leaf_node.push_back(n);
+    h->n_leaves = (int)leaf_node.size();
+    std::vector<int32_t> leaf_cols;
+    std::vector<int> leaf_off(1, 0);
+    std::vector<int> pos_in_tree(p.n_b);           // position of a column in the root's order
+    for (size_t k = 0; k < tb[0].idx.size(); ++k) pos_in_tree[tb[0].idx[k]] = (int)k;
+    for (int n : leaf_node) {
+        leaf_cols.insert(leaf_cols.end(), tb[n].idx.begin(), tb[n].idx.end());
+        leaf_off.push_back((int)leaf_cols.size());
+    }
+    std::vector<HContrib> contrib;
+    std::vector<int> contrib_off(1, 0);
+    for (int L = 0; L < h->n_leaves; ++L) {
+        const int first = pos_in_tree[tb[leaf_node[L]].idx[0]];
+        for (int bi = 0; bi < (int)h->blk.size(); ++bi) {
+            const HBlk& b = h->blk[bi];
+            const int tfirst = pos_in_tree[tcols[b.t_off]];
+            if (first >= tfirst && first < tfirst + b.nt) contrib.push_back({bi, 3 * (first - tfirst)});
+        }
+        contrib_off.push_back((int)contrib.size());
+    }
+    // device data
+    fbc_status s;
+    const int64_t t_elems = (int64_t)p.nm * std::max(h->n_lr, 1) * o->max_rank * p.R;
+    if ((s = halloc(h, &h->blk_d, (int64_t)h->blk.size() * sizeof(HBlk))) != FBC_OK ||
+        (s = halloc(h, &h->lr_ids, (int64_t)lr_ids.size() * 4)) != FBC_OK ||
+        (s = halloc(h, &h->tcols, (int64_t)tcols.size() * 4)) != FBC_OK ||
+        (s = halloc(h, &h->scols, (int64_t)scols.size() * 4)) != FBC_OK ||
+        (s = halloc(h, &h->leaf_cols, (int64_t)leaf_cols.size() * 4)) != FBC_OK ||
+        (s = halloc(h, &h->leaf_off, (int64_t)leaf_off.size() * 4)) != FBC_OK ||
+        (s = halloc(h, &h->contrib, (int64_t)contrib.size() * sizeof(HContrib))) != FBC_OK ||
+        (s = halloc(h, &h->contrib_off, (int64_t)contrib_off.size() * 4)) != FBC_OK ||
+        (s = halloc(h, &h->U, (int64_t)p.nm * u_mode * 16)) != FBC_OK ||
+        (s = halloc(h, &h->V, (int64_t)p.nm * v_mode * 16)) != FBC_OK ||
+        (s = halloc(h, &h->T, t_elems * 16)) != FBC_OK ||
+        (s = halloc(h, &h->rank, (int64_t)p.nm * std::max(h->n_lr, 1) * 4)) != FBC_OK) {
+        hmat_free(h);
+        return s;
+    }
+    hipError_t e = hipSuccess;
+    auto up = [&](void* d, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, sm);
+    };
+    up(h->blk_d, h->blk.data(), h->blk.size() * sizeof(HBlk));
+    up(h->lr_ids, lr_ids.data(), lr_ids.size() * 4);
+    up(h->tcols, tcols.data(), tcols.size() * 4);
+    up(h->scols, scols.data(), scols.size() * 4);
+    up(h->leaf_cols, leaf_cols.data(), leaf_cols.size() * 4);
+    up(h->leaf_off, leaf_off.data(), leaf_off.size() * 4);
+    up(h->contrib, contrib.data(), contrib.size() * sizeof(HContrib));
+    up(h->contrib_off, contrib_off.data(), contrib_off.size() * 4);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(sm);
+        hmat_free(h);
+        return hfail(FBC_E_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    // Step 3 on the device
+    if (h->n_lr > 0) {
+        int max_rows = 1;
+        for (int li : lr_ids) max_rows = std::max(max_rows, 3 * h->blk[li].nt);
+        hipLaunchKernelGGL(k_hmat_aca, dim3(h->n_lr, p.nm), dim3(NTH), (size_t)max_rows, sm, h->blk_d, h->lr_ids,
+                           h->tcols, h->scols, h->st, o->eps, o->max_rank, u_mode, v_mode, h->U, h->V, h->rank,
+                           h->n_lr);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    if (e == hipSuccess && h->n_lr > 0) {
+        h->rank_h.resize((size_t)p.nm * h->n_lr);
+        e = hipMemcpy(h->rank_h.data(), h->rank, h->rank_h.size() * 4, hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess) {
+        hmat_free(h);
+        return hfail(FBC_E_DEVICE, std::string("cross approximation: ") + hipGetErrorString(e));
+    }
+    for (int m = 0; m < p.nm; ++m)
+        for (const HBlk& b : h->blk) {
+            const double dense = 9.0 * b.nt * b.ns;
+            h->dense_total += dense;
+            if (b.kind == 1) {
+                const int k = h->rank_h[(size_t)m * h->n_lr + b.lr];
+                if (k < 0) {
+                    ++h->n_overflow;
+                    h->stored += dense;
+                } else {
+                    h->stored += (double)k * 3.0 * (b.nt + b.ns);
+                    h->max_rank_used = std::max(h->max_rank_used, k);
+                }
+            } else {
+                h->stored += dense;
+            }
+        }
+    *out = h;
+    return FBC_OK;
+}
+
+extern "C" void fbc_hmat_destroy(fbc_hmat* h) { hmat_free(h); }
+
+extern "C" fbc_status fbc_hmat_get_info(const fbc_hmat* h, fbc_hmat_info* info) {
+    if (!h || !info) return hfail(FBC_E_ARG, "null argument");
+    info->n_blocks = (int)h->blk.size();
+    info->n_low_rank = h->n_lr;
+    info->n_dense = h->n_dense;
+    info->max_rank_used = h->max_rank_used;
+    info->n_over_rank = h->n_overflow;
+    info->stored_entries = h->stored;
+    info->dense_entries = h->dense_total;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_hmat_partition(const fbc_hmat* h, int32_t* out, int64_t cap, int64_t* n_out) {
+    if (!h || !n_out) return hfail(FBC_E_ARG, "null argument");
+    *n_out = (int64_t)h->part_stream.size();
+    if (out) {
+        if (cap < *n_out) return hfail(FBC_E_ARG, "out too small");
+        std::memcpy(out, h->part_stream.data(), h->part_stream.size() * 4);
+    }
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_hmat_ranks(const fbc_hmat* h, int32_t* out) {
+    if (!h || !out) return hfail(FBC_E_ARG, "null argument");
+    if (!h->rank_h.empty()) std::memcpy(out, h->rank_h.data(), h->rank_h.size() * 4);
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_hmat_apply(fbc_hmat* h, const double* fhat, double* what, void* stream) {
+    if (!h) return hfail(FBC_E_ARG, "object is NULL");
+    if (!fhat || !what) return hfail(FBC_E_ARG, "fhat and what must be device pointers");
+    hipStream_t sm = (hipStream_t)stream;
+    if (h->n_lr > 0)
+        hipLaunchKernelGGL(k_hmat_vt, dim3(h->n_lr, h->nm), dim3(NTH), 0, sm, h->blk_d, h->lr_ids, h->scols, h->V,
+                           h->v_mode, h->rank, h->n_lr, h->max_rank, (const double2*)fhat, h->n_i, h->R, h->T);
+    hipLaunchKernelGGL(k_hmat_y, dim3(h->n_leaves, h->nm), dim3(NTH), 0, sm, h->blk_d, h->scols, h->leaf_cols,
+                       h->leaf_off, h->contrib, h->contrib_off, h->st, h->U, h->u_mode, h->T, h->rank, h->n_lr,
+                       h->max_rank, (const double2*)fhat, h->n_i, h->n_b, h->R, (double2*)what);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hfail(FBC_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return FBC_OK;
+}

@@ -28,6 +28,8 @@ EXPORTED = [
     "fbc_sur_eval", "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_destroy", "fbc_mlp_num_params",
     "fbc_mlp_params", "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
     "fbc_plgf_last_error", "fbc_plgf_create", "fbc_plgf_destroy", "fbc_plgf_table", "fbc_plgf_eval",
+    "fbc_hmat_last_error", "fbc_hmat_create", "fbc_hmat_destroy", "fbc_hmat_get_info", "fbc_hmat_partition",
+    "fbc_hmat_ranks", "fbc_hmat_apply",
 ]
 
 
@@ -75,6 +77,15 @@ class Info(C.Structure):
 
 class PlgfOpts(C.Structure):
     _fields_ = [("torus_l", C.c_int), ("r2x4_cut", C.c_int), ("r2x4_match", C.c_int), ("n_psi", C.c_int)]
+
+
+class HmatOpts(C.Structure):
+    _fields_ = [("b_min", C.c_int), ("gamma", C.c_int), ("eps", C.c_double), ("max_rank", C.c_int)]
+
+
+class HmatInfo(C.Structure):
+    _fields_ = [("n_blocks", C.c_int), ("n_low_rank", C.c_int), ("n_dense", C.c_int), ("max_rank_used", C.c_int),
+                ("n_over_rank", C.c_int), ("stored_entries", C.c_double), ("dense_entries", C.c_double)]
 
 
 class TuneResult(C.Structure):
@@ -139,12 +150,22 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_plgf_destroy.restype = None
     lib.fbc_plgf_table.argtypes = [vp, C.POINTER(C.c_int), vp, vp, vp]
     lib.fbc_plgf_eval.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_int, vp, vp]
+    lib.fbc_hmat_last_error.argtypes = []
+    lib.fbc_hmat_last_error.restype = cp
+    lib.fbc_hmat_create.argtypes = [vp, C.POINTER(HmatOpts), vp, C.POINTER(vp)]
+    lib.fbc_hmat_destroy.argtypes = [vp]
+    lib.fbc_hmat_destroy.restype = None
+    lib.fbc_hmat_get_info.argtypes = [vp, C.POINTER(HmatInfo)]
+    lib.fbc_hmat_partition.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.fbc_hmat_ranks.argtypes = [vp, vp]
+    lib.fbc_hmat_apply.argtypes = [vp, vp, vp, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
                  "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_num_params", "fbc_mlp_params",
                  "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
-                 "fbc_plgf_create", "fbc_plgf_table", "fbc_plgf_eval"):
+                 "fbc_plgf_create", "fbc_plgf_table", "fbc_plgf_eval", "fbc_hmat_create", "fbc_hmat_get_info",
+                 "fbc_hmat_partition", "fbc_hmat_ranks", "fbc_hmat_apply"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -421,6 +442,62 @@ class PeriodicGreen:
     def close(self):
         if self.handle:
             self._lib.fbc_plgf_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HMatrix:
+    """H-matrices of every line mode of a one-cell FP64 context (fbc_hmat_*)."""
+
+    def __init__(self, ctx: "FBC", b_min: int = 20, gamma: int = 2, eps: float = 1e-5, max_rank: int = 64,
+                 stream=None):
+        lib = load_library()
+        self._lib = lib
+        self._ctx = ctx                      # the store must outlive this object
+        self.handle = C.c_void_p()
+        opts = HmatOpts(int(b_min), int(gamma), float(eps), int(max_rank))
+        self._check(lib.fbc_hmat_create(ctx.ctx, C.byref(opts), _stream_handle(stream), C.byref(self.handle)))
+        self.info = HmatInfo()
+        self._check(lib.fbc_hmat_get_info(self.handle, C.byref(self.info)))
+
+    def _check(self, rc):
+        if rc != FBC_OK:
+            raise FbcError(rc, self._lib.fbc_hmat_last_error().decode())
+
+    def partition(self):
+        """List of (kind, t columns, s columns); kind 1 low rank, 0 dense."""
+        import numpy as np
+        n = C.c_int64()
+        self._check(self._lib.fbc_hmat_partition(self.handle, None, 0, C.byref(n)))
+        buf = np.zeros(n.value, dtype=np.int32)
+        self._check(self._lib.fbc_hmat_partition(self.handle, buf.ctypes.data, n.value, C.byref(n)))
+        out, k = [], 0
+        while k < len(buf):
+            kind, nt, ns = int(buf[k]), int(buf[k + 1]), int(buf[k + 2])
+            t = buf[k + 3:k + 3 + nt].copy()
+            s = buf[k + 3 + nt:k + 3 + nt + ns].copy()
+            out.append((kind, t, s))
+            k += 3 + nt + ns
+        return out
+
+    def ranks(self, n_modes: int):
+        import numpy as np
+        r = np.zeros((n_modes, self.info.n_low_rank), dtype=np.int32)
+        self._check(self._lib.fbc_hmat_ranks(self.handle, r.ctypes.data))
+        return r
+
+    def apply(self, fhat, what, stream=None):
+        """fhat float64 [n_modes, 3 n_i, R, 2], what float64 [n_modes, 3 n_b, R, 2] (device)."""
+        self._check(self._lib.fbc_hmat_apply(self.handle, _dptr(fhat), _dptr(what), _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            self._lib.fbc_hmat_destroy(self.handle)
             self.handle = C.c_void_p()
 
     def __del__(self):
