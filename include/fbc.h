@@ -72,7 +72,7 @@ typedef enum {
     FBC_E_NONFINITE = -4,    /* NaN or Inf in the forces */
     FBC_E_DEVICE = -5,       /* HIP runtime error (text in fbc_last_error) */
     FBC_E_STATE = -6,        /* call out of order (e.g. relax step before relax begin) */
-    FBC_E_UNSUPPORTED = -7   /* valid request outside what this build implements */
+    FBC_E_UNSUPPORTED = -7   /* valid request outside what the library implements */
 } fbc_status;
 
 /* How G^(m) is stored and applied (the per-mode product, Section 3.2 in spectral form). */
