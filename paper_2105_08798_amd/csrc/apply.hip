@@ -58,13 +58,26 @@ __global__ void __launch_bounds__(NT) k_netforce(const double* __restrict__ f,
     const double* row = f + ((int64_t)r * nz + n0) * n_i * 3;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     double mx[1] = {0.0};
-    for (int i = threadIdx.x; i < n_i; i += NT) {
-        for (int c = 0; c < 3; ++c) {
-            const double x = row[3 * i + c];
-            v[c] += x;
-            v[3 + c] += fabs(x);
-            mx[0] = fmax(mx[0], fabs(x));
-            if (!isfinite(x)) v[6] = 1.0;
+    // columns i = tid, tid + NT, ... in order; the loads of LU of them are issued together
+    constexpr int LU = 4;
+    for (int i0 = threadIdx.x; i0 < n_i; i0 += NT * LU) {
+        double x[LU][3];
+#pragma unroll
+        for (int k = 0; k < LU; ++k) {
+            const int i = i0 + k * NT;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x[k][c] = (i < n_i) ? row[3 * i + c] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < LU; ++k) {
+            if (i0 + k * NT >= n_i) break;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[c] += x[k][c];
+                v[3 + c] += fabs(x[k][c]);
+                mx[0] = fmax(mx[0], fabs(x[k][c]));
+                if (!isfinite(x[k][c])) v[6] = 1.0;
+            }
         }
     }
     block_sum<7>(v, red);
@@ -854,10 +867,13 @@ __global__ void __launch_bounds__(NT) k_mean_parts(const double* __restrict__ u,
                 const int64_t i = i0 + (int64_t)k * NT;
                 x[k] = i < e1 ? ur[i] : 0.0;
             }
+            // component (n0 M + row) % 3 = i % 3; NT % 3 = 1, so it advances by one per k
+            static_assert(NT % 3 == 1, "component stepping assumes NT = 1 mod 3");
+            const int c0 = (int)(i0 % 3);
 #pragma unroll
             for (int k = 0; k < LU; ++k) {
                 const int64_t i = i0 + (int64_t)k * NT;
-                if (i < e1) v[(int)(i % 3)] += x[k];       // (n0 M + row) % 3 = row % 3
+                if (i < e1) v[(c0 + k) % 3] += x[k];
             }
         }
     }
