@@ -112,3 +112,28 @@ def test_medium_geometry_sampled_modes():
     assert h.info.stored_entries < 0.8 * h.info.dense_entries
     h.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("kw", [dict(b_min=10000), dict(max_rank=1), dict(gamma=1, eps=1e-12)])
+def test_degenerate_partitions_reproduce_the_dense_product(small, kw):
+    # one leaf per tree (everything dense), a rank bound that sends every low-rank block
+    # back to the store, and a strict criterion with a tight bound
+    from paper_2105_08798_amd import HMatrix
+    wl, ctx = small
+    c = wl.cells[0]
+    h = HMatrix(ctx, **kw)
+    h._ctx_nb3 = 3 * len(c.cols_b)
+    nm = c.nz // 2 + 1
+    rng = np.random.default_rng(11)
+    fhat = rng.normal(size=(nm, 3 * len(c.cols_i), 2)) + 1j * rng.normal(size=(nm, 3 * len(c.cols_i), 2))
+    got = _apply(h, fhat)
+    dense = green.green_modes_dense(16, 256, 256, c.cols_b, c.cols_i)
+    tol = 1e-10 if "eps" not in kw else 1e-9
+    for m in range(nm):
+        ref = dense[m] @ fhat[m]
+        assert np.linalg.norm(got[m] - ref) / np.linalg.norm(ref) < tol, (kw, m)
+    if kw.get("b_min") == 10000:
+        assert h.info.n_blocks == 1 and h.info.n_dense == 1
+    if kw.get("max_rank") == 1:
+        assert h.info.n_over_rank > 0
+    h.close()

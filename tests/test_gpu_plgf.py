@@ -96,3 +96,22 @@ def test_empty_and_bad_arguments(pair):
     for kw in (dict(torus_l=48), dict(n_psi=100), dict(r2x4_match=100), dict(r2x4_cut=-1)):
         with pytest.raises(FbcError):
             PeriodicGreen(**kw)
+
+
+@pytest.mark.parametrize("torus_l,r2x4_cut,r2x4_match,n_psi", [(16, 0, 8, 128), (16, 24, 36, 64)])
+def test_degenerate_tables_match_oracle(torus_l, r2x4_cut, r2x4_match, n_psi):
+    # r_cut = 0: the table holds only the origin, every other term is the continuum;
+    # a small torus and a doubled quadrature
+    _dev()
+    from paper_2105_08798_amd import PeriodicGreen
+    gpu = PeriodicGreen(torus_l=torus_l, r2x4_cut=r2x4_cut, r2x4_match=r2x4_match, n_psi=n_psi)
+    ora = plgf.InfiniteLatticeGreen(torus_l, r2x4_cut, r2x4_match, n_psi=n_psi)
+    vec, val, c = gpu.table()
+    assert np.array_equal(vec, ora.vectors.astype(np.int32))
+    assert np.abs(val - sym6(ora.table)).max() < 1e-12 * np.abs(ora.table).max()
+    rng = np.random.default_rng(torus_l + r2x4_cut)
+    disp = rng.integers(-6, 7, size=(30, 3))
+    got = run_eval(gpu, disp, 8)
+    ref = sym6(plgf.periodic_green(ora, disp, 8))
+    assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+    gpu.close()
