@@ -161,7 +161,8 @@ def make_custom(nz: int, n_i: int, n_b: int, n_rhs: int, bz: int, seed: int,
     rng = np.random.default_rng(seed)
     ci, cb = ring_columns(n_i, n_b)
     f = gaussian_forces(rng, n_rhs, nz, n_i, zero_net_force=zero_net_force)
-    return Workload(name=f"custom-{nz}-{n_i}-{n_b}-{n_rhs}-{bz}", cells=[Cell(nz, ci, cb, n_rhs, f)], bz=bz)
+    return Workload(name=f"custom-{nz}-{n_i}-{n_b}-{n_rhs}-{bz}", cells=[Cell(nz, ci, cb, n_rhs, f)], bz=bz,
+                    description=f"N_z={nz}, n_i={n_i}, n_b={n_b}, {n_rhs} RHS")
 
 
 def make_batched(n_cells: int = 32, seed: int = 1003, bz: int = 2048,
