@@ -2,7 +2,7 @@
  * fbc.h -- C ABI of the line-periodic flexible-boundary-condition (FBC) pad update
  * for MI355X (gfx950).
  *
- * The operation (Section 2.3.2, eq. flexbc.up=Gpipl*fipl, Algorithm 1 lines 5-8):
+ * The operation (Section 2.3.2, eq. flexbc.up=Gpipl*fipl, Algorithm 1):
  *     u^p  <-  u^p - alpha * G^{p|i+} [f_in],   then remove the mean pad displacement
  * (eq. mean(u^p)=0), for a cell that is periodic along the dislocation line
  * (Section 2.1).  G^{p|i+} is the Green matrix of the harmonic lattice (Section 3.2,
@@ -154,7 +154,7 @@ fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cells, int n_c
                           const fbc_options* opt, void* stream, fbc_ctx** out);
 
 /* u <- u - alpha * G^{p|i+} f, then per RHS and Cartesian component the mean over all
- * pad atoms of all layers is removed (Algorithm 1 lines 7-8).  alpha = -1 with u = 0
+ * pad atoms of all layers is removed (update step of Algorithm 1).  alpha = -1 with u = 0
  * gives u = G f minus its mean.  f, u: device pointers, packed by cell (see above).
  * Asynchronous on `stream`; data-dependent failures are latched (fbc_sync_status). */
 fbc_status fbc_apply(fbc_ctx* ctx, const double* f, double* u, double alpha, void* stream);
@@ -202,8 +202,8 @@ fbc_status fbc_set_work_list(fbc_ctx* ctx, int nsplit, int order, void* stream);
 
 /* Residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2). */
 typedef struct {
-    int relax;        /* 1: relax from the third iteration on (Algorithm 1 line 5)        */
-    double du_max;    /* > 0: bound ||alpha G f||_inf by du_max (Algorithm 2 lines 6-8)   */
+    int relax;        /* 1: relax from the third iteration on (Algorithm 1)               */
+    double du_max;    /* > 0: bound ||alpha G f||_inf by du_max (Algorithm 2)             */
     double tol_f;     /* convergence flag: ||f_in||_inf < tol_f (Section 2.3.3)           */
     double alpha_min; /* > 0: lower bound on alpha_{k+1} (the preprint's variant, Remark in
                          Section 2.3.3), applied after the reset of negative values and
@@ -223,7 +223,7 @@ typedef struct {
 /* Resets the iteration: k = 0, alpha = 1 for every RHS. */
 fbc_status fbc_relax_begin(fbc_ctx* ctx, const fbc_relax_opts* opts, void* stream);
 
-/* One pass of Algorithm 1 lines 5-8 given f_in,k+1 (computed by the caller, line 4):
+/* One pass of Algorithm 1 from the relaxation on, given f_in,k+1 (computed by the caller):
  * alpha from Relax on raw residuals (k >= 2), optional step bound, pad update, mean
  * removal.  No host synchronisation.  out_dev: device array [total RHS] or NULL. */
 fbc_status fbc_relax_step(fbc_ctx* ctx, const double* f_in, double* u,

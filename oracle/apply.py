@@ -10,7 +10,7 @@ block-diagonalises it:
   3. w_b(n0) = (1/Nz) sum_m w^_b(m) e^{+2 pi i m n0 / Nz}      (inverse)
 Real forces give Hermitian spectra, so modes 0..Nz/2 suffice (rfft / irfft).
 
-Algorithm 1 (line 7, line 8) and eq. mean(u^p)=0: u^p <- u^p - alpha w, then the mean
+Update step of Algorithm 1 and eq. mean(u^p)=0: u^p <- u^p - alpha w, then the mean
 of each Cartesian component over all pad atoms of all layers is subtracted.
 """
 from __future__ import annotations
@@ -65,7 +65,7 @@ def apply_direct(greal: np.ndarray, cols_b: np.ndarray, cols_i: np.ndarray, f: n
 
 def pad_update(u: np.ndarray, w: np.ndarray, alpha) -> tuple[np.ndarray, np.ndarray]:
     """u <- u - alpha w, then subtract the per-component mean over all pad atoms and
-    layers (Algorithm 1, lines 7-8; eq. mean(u^p)=0).  alpha: scalar or [R].
+    layers (update step of Algorithm 1; eq. mean(u^p)=0).  alpha: scalar or [R].
     Returns (u_new, removed_mean[R, 3])."""
     a = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (u.shape[0],))
     v = u - a[:, None, None, None] * w

@@ -6,7 +6,7 @@ Algorithm 2 (Relax):
     alpha_{k+1} = -alpha_k <f_k, f_{k+1} - f_k> / ||f_{k+1} - f_k||^2
     alpha_{k+1} < 0  ->  alpha_{k+1} = 1
     optional: if ||alpha_{k+1} G f_{k+1}||_inf > du_max, alpha_{k+1} = du_max / ||G f_{k+1}||_inf
-Algorithm 1, lines 5-8: relaxation only when enabled and k >= 2 (alpha = 1 before,
+Algorithm 1, relaxation and update: relaxation only when enabled and k >= 2 (alpha = 1 before,
 with alpha_2 = 1 as the starting value); the update uses alpha_{k+1} f_in,k+1 while
 Relax always receives the raw (unscaled) incompatibility forces; then the pad
 update and mean removal.  The incompatibility-force criterion of Section 2.3.3
@@ -31,7 +31,7 @@ from .apply import pad_update
 
 def relax_alpha(f_new: np.ndarray, f_old: np.ndarray, alpha_old: np.ndarray,
                 alpha_min: float = 0.0) -> np.ndarray:
-    """Algorithm 2 lines 1-4, per RHS (leading axis); alpha_min > 0: the lower bound of the
+    """Algorithm 2, the residual-based alpha (eq. alpha), per RHS (leading axis); alpha_min > 0: the lower bound of the
     Remark in Section 2.3.3."""
     n = f_new.shape[0]
     fn = f_new.reshape(n, -1)
@@ -49,7 +49,7 @@ def relax_alpha(f_new: np.ndarray, f_old: np.ndarray, alpha_old: np.ndarray,
 
 
 def clamp_step(alpha: np.ndarray, w_inf: np.ndarray, du_max: float) -> np.ndarray:
-    """Algorithm 2 lines 6-8 (optional step bound)."""
+    """Algorithm 2, the optional step bound."""
     out = alpha.copy()
     hit = alpha * w_inf > du_max
     out[hit] = du_max / w_inf[hit]
@@ -73,7 +73,7 @@ class RelaxState:
 
 
 def relax_step(state: RelaxState, f_new: np.ndarray, u: np.ndarray, apply_fn) -> tuple[np.ndarray, dict]:
-    """One pass of Algorithm 1 lines 5-9 given f_in,k+1 (line 4, supplied by the caller).
+    """One pass of Algorithm 1 from the relaxation on, given f_in,k+1 (supplied by the caller).
 
     apply_fn(f) must return G^{p|i+} f with the layout of u.  Returns (u_new, out)."""
     n = f_new.shape[0]

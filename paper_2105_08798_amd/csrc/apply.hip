@@ -1,5 +1,5 @@
 // Line transforms, update and reductions of the FBC pad update (Section 2.3.2,
-// eq. flexbc.up=Gpipl*fipl with eq. mean(u^p)=0; Algorithm 1 lines 7-8), and the
+// eq. flexbc.up=Gpipl*fipl with eq. mean(u^p)=0; the update step of Algorithm 1), and the
 // residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2).
 // All reductions use a fixed partition and a fixed-order tree, so results are bitwise
 // reproducible from run to run (no floating-point atomics).
@@ -627,7 +627,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
 }
 
 // ----------------------------------------------------------------------------------
-// Fused inverse transform and pad update (Algorithm 1 lines 7-8):
+// Fused inverse transform and pad update (the update step of Algorithm 1):
 //   u[r][n0][row] <- (read_u ? u : 0) - alpha * w[r][row][n0] - mu[r][row % 3]
 // straight from the product output, without the w scratch.  A work group owns tr
 // consecutive rows (one contiguous run of u per layer) and pp RHS pairs of one column
@@ -1093,7 +1093,7 @@ void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev,
                        use, alpha_min);
 }
 
-// Step bound (Algorithm 2 lines 6-8) from the per-block maxima of |w|.
+// Step bound (the optional bound on the step in Algorithm 2) from the per-block maxima of |w|.
 __global__ void __launch_bounds__(NT) k_relax_clamp(const double* __restrict__ wmax_part,
                                                     int n_part, double* __restrict__ alpha_d,
                                                     double* __restrict__ stepinf_d, double du_max,

@@ -120,8 +120,8 @@ def run_loop(disc: HarmonicDisc, f_ext: np.ndarray, update, n_iter: int):
     hist = []
     u_a = None
     for k in range(n_iter):
-        u_a = disc.solve_ah(f_ext, u_p)                       # line 3
-        f_in = disc.incompatibility_force(u_a, u_p)           # line 4
+        u_a = disc.solve_ah(f_ext, u_p)                       # atomistic solve with fixed pad
+        f_in = disc.incompatibility_force(u_a, u_p)           # incompatibility forces
         hist.append(float(np.abs(f_in).max()))
-        u_p = update(f_in, k)                                 # lines 5-8
+        u_p = update(f_in, k)                                 # relaxation, pad update, mean
     return u_a, u_p, hist
