@@ -229,6 +229,23 @@ fbc_status fbc_relax_begin(fbc_ctx* ctx, const fbc_relax_opts* opts, void* strea
 fbc_status fbc_relax_step(fbc_ctx* ctx, const double* f_in, double* u,
                           fbc_relax_out* out_dev, void* stream);
 
+/* Checkpoint and resume of the relaxation (Section 2.3.3): the iteration's state is the
+ * options, the index k, alpha_k of every RHS and the previous raw incompatibility forces
+ * f_in,k (eq. alpha takes the difference f_in,k+1 - f_in,k).  fbc_relax_get_state copies
+ * it out: alpha [total RHS] and f_prev [f elements, the layout of f] are host or device
+ * pointers owned by the caller; f_prev holds meaningful values only for k >= 1.
+ * fbc_relax_set_state loads a saved state into a context of the same cells (a fresh one
+ * after a restart), replacing fbc_relax_begin; f_prev is read only for k > 0 and may be
+ * NULL otherwise.  Both synchronise `stream` before they return, so host buffers are
+ * complete (get) or may be reused (set).  FBC_E_STATE from get before fbc_relax_begin or
+ * set; FBC_E_ARG for NULL pointers, k < 0 or invalid options.  Steps continued from a
+ * loaded state are bitwise those of the uninterrupted iteration when both contexts use
+ * the same work list (fbc_set_work_list: K slices change the rounding). */
+fbc_status fbc_relax_get_state(fbc_ctx* ctx, fbc_relax_opts* opts, int32_t* k, double* alpha,
+                               double* f_prev, void* stream);
+fbc_status fbc_relax_set_state(fbc_ctx* ctx, const fbc_relax_opts* opts, int32_t k,
+                               const double* alpha, const double* f_prev, void* stream);
+
 /* Synchronises `stream`, returns and clears the latched device-side status. */
 fbc_status fbc_sync_status(fbc_ctx* ctx, void* stream);
 

@@ -1214,10 +1214,16 @@ extern "C" fbc_status fbc_green_apply(fbc_ctx* c, const double* f, double* w, vo
     return FBC_OK;
 }
 
-extern "C" fbc_status fbc_relax_begin(fbc_ctx* c, const fbc_relax_opts* o, void* stream) {
-    if (!c || !o) return fail(c, FBC_E_ARG, "null argument");
+static fbc_status check_relax_opts(fbc_ctx* c, const fbc_relax_opts* o) {
     if (!(o->du_max >= 0) || !(o->tol_f >= 0) || !(o->alpha_min >= 0) || !std::isfinite(o->alpha_min))
         return fail(c, FBC_E_ARG, "du_max, tol_f and alpha_min must be >= 0 (alpha_min finite)");
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_relax_begin(fbc_ctx* c, const fbc_relax_opts* o, void* stream) {
+    if (!c || !o) return fail(c, FBC_E_ARG, "null argument");
+    fbc_status s = check_relax_opts(c, o);
+    if (s != FBC_OK) return s;
     c->ropt = *o;
     c->relax_k = 0;
     launch_fill((hipStream_t)stream, c->alpha, c->total_rhs, 1.0);
@@ -1254,6 +1260,35 @@ extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, 
                         c->total_rhs, k, c->ropt.tol_f);
     c->relax_k = k + 1;
     HIPCHK(c, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_relax_get_state(fbc_ctx* c, fbc_relax_opts* opts, int32_t* k, double* alpha,
+                                          double* f_prev, void* stream) {
+    if (!c || !opts || !k || !alpha || !f_prev) return fail(c, FBC_E_ARG, "null argument");
+    if (c->relax_k < 0) return fail(c, FBC_E_STATE, "fbc_relax_begin was not called");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, hipMemcpyAsync(alpha, c->alpha, (size_t)c->total_rhs * sizeof(double), hipMemcpyDefault, st));
+    HIPCHK(c, hipMemcpyAsync(f_prev, c->fprev, (size_t)c->f_elems * sizeof(double), hipMemcpyDefault, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    *opts = c->ropt;
+    *k = c->relax_k;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_relax_set_state(fbc_ctx* c, const fbc_relax_opts* opts, int32_t k,
+                                          const double* alpha, const double* f_prev, void* stream) {
+    if (!c || !opts || !alpha || (k > 0 && !f_prev)) return fail(c, FBC_E_ARG, "null argument");
+    if (k < 0) return fail(c, FBC_E_ARG, "k must be >= 0");
+    fbc_status s = check_relax_opts(c, opts);
+    if (s != FBC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, hipMemcpyAsync(c->alpha, alpha, (size_t)c->total_rhs * sizeof(double), hipMemcpyDefault, st));
+    if (k > 0)
+        HIPCHK(c, hipMemcpyAsync(c->fprev, f_prev, (size_t)c->f_elems * sizeof(double), hipMemcpyDefault, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->ropt = *opts;
+    c->relax_k = k;
     return FBC_OK;
 }
 

@@ -22,7 +22,7 @@ FORMS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "dtable_fp64": 3, "surrogate": 4
 
 EXPORTED = [
     "fbc_default_options", "fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin",
-    "fbc_relax_step", "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_destroy",
+    "fbc_relax_step", "fbc_relax_get_state", "fbc_relax_set_state", "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_destroy",
     "fbc_last_error", "fbc_status_string", "fbc_timing", "fbc_timing_read", "fbc_apply_graph",
     "fbc_autotune", "fbc_set_work_list", "fbc_learned_last_error", "fbc_sur_create", "fbc_sur_destroy", "fbc_sur_set_mlp",
     "fbc_sur_eval", "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_destroy", "fbc_mlp_num_params",
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_green_apply.argtypes = [vp, vp, vp, vp]
     lib.fbc_relax_begin.argtypes = [vp, C.POINTER(RelaxOpts), vp]
     lib.fbc_relax_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.fbc_relax_get_state.argtypes = [vp, C.POINTER(RelaxOpts), C.POINTER(C.c_int32), vp, vp, vp]
+    lib.fbc_relax_set_state.argtypes = [vp, C.POINTER(RelaxOpts), C.c_int32, vp, vp, vp]
     lib.fbc_sync_status.argtypes = [vp, vp]
     lib.fbc_get_info.argtypes = [vp, C.POINTER(Info)]
     lib.fbc_copy_block_rows.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
@@ -160,6 +162,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_hmat_ranks.argtypes = [vp, vp]
     lib.fbc_hmat_apply.argtypes = [vp, vp, vp, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
+                 "fbc_relax_get_state", "fbc_relax_set_state",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
                  "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_num_params", "fbc_mlp_params",
@@ -272,6 +275,30 @@ class FBC:
         """out: float64 CUDA tensor of at least total_rhs * RELAX_OUT_DOUBLES elements, or None."""
         optr = _dptr(out) if out is not None else None
         self._check(self._lib.fbc_relax_step(self.ctx, _dptr(f), _dptr(u), optr, _stream_handle(stream)))
+
+    def relax_state(self, stream=None) -> dict:
+        """Checkpoint of the relaxation: options, k, alpha_k per RHS (host array) and the
+        previous raw incompatibility forces (float64 CUDA tensor in the layout of f)."""
+        import torch
+        info = self.get_info()
+        o = RelaxOpts()
+        k = C.c_int32()
+        alpha = np.empty(info.total_rhs, dtype=np.float64)
+        f_prev = torch.empty(info.f_elems, dtype=torch.float64, device="cuda")
+        self._check(self._lib.fbc_relax_get_state(self.ctx, C.byref(o), C.byref(k), alpha.ctypes.data,
+                                                  _dptr(f_prev), _stream_handle(stream)))
+        return dict(relax=bool(o.relax), du_max=o.du_max, tol_f=o.tol_f, alpha_min=o.alpha_min, k=k.value,
+                    alpha=alpha, f_prev=f_prev)
+
+    def set_relax_state(self, state: dict, stream=None):
+        """Loads a state from relax_state() (in place of relax_begin)."""
+        o = RelaxOpts(int(bool(state["relax"])), float(state["du_max"]), float(state["tol_f"]),
+                      float(state["alpha_min"]))
+        alpha = np.ascontiguousarray(state["alpha"], dtype=np.float64)
+        f_prev = state["f_prev"]
+        self._check(self._lib.fbc_relax_set_state(self.ctx, C.byref(o), int(state["k"]), alpha.ctypes.data,
+                                                  _dptr(f_prev) if f_prev is not None else None,
+                                                  _stream_handle(stream)))
 
     def sync_status(self, stream=None) -> int:
         return self._lib.fbc_sync_status(self.ctx, _stream_handle(stream))

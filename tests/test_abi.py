@@ -88,6 +88,8 @@ def test_null_context_calls_fail_cleanly():
     assert lib.fbc_apply(None, None, None, 1.0, None) == -1
     assert lib.fbc_relax_step(None, None, None, None, None) == -1
     assert lib.fbc_sync_status(None, None) == -1
+    assert lib.fbc_relax_get_state(None, None, None, None, None, None) == -1
+    assert lib.fbc_relax_set_state(None, None, 0, None, None, None) == -1
     lib.fbc_destroy(None)
     assert lib.fbc_status_string(-3) == b"non-zero net force per layer"
 

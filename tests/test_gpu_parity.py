@@ -453,3 +453,60 @@ def test_work_list_arguments_checked():
         with pytest.raises(FbcError):
             ctx.set_work_list(nsplit, order)
     ctx.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_relax_checkpoint_resume_is_bitwise(form):
+    # checkpoint after three steps, resume in a fresh context of the same cells (same
+    # default work list), continue: every later step equals the uninterrupted run bit for bit
+    wl = W.make_single("parity")
+    c = wl.cells[0]
+    dev = _dev()
+    from paper_2105_08798_amd import RELAX_OUT_DOUBLES, FbcError
+    rng = np.random.default_rng(21)
+    seq = [c.forces]
+    for k in range(5):
+        nxt = 0.6 * seq[-1] + 0.02 * rng.normal(size=c.forces.shape) * (0.5 ** k)
+        nxt -= nxt.mean(axis=2, keepdims=True)
+        seq.append(nxt)
+    u0 = torch.from_numpy(rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01).to(dev)
+    opts = dict(relax=True, du_max=0.05, tol_f=0.2, alpha_min=0.0)
+
+    def run(ctx, u, steps):
+        outs = []
+        for fk in steps:
+            out = torch.zeros(c.n_rhs * RELAX_OUT_DOUBLES, dtype=torch.float64, device=dev)
+            ctx.relax_step(torch.from_numpy(fk).to(dev), u, out)
+            assert ctx.sync_status() == 0
+            outs.append(out.cpu().numpy())
+        return outs
+
+    a = _ctx(wl.cells, wl.bz, form=form)
+    a.relax_begin(**opts)
+    ua = u0.clone()
+    ref_out = run(a, ua, seq)
+    a.close()
+
+    b = _ctx(wl.cells, wl.bz, form=form)
+    with pytest.raises(FbcError):
+        b.relax_state()                          # no iteration yet
+    b.relax_begin(**opts)
+    ub = u0.clone()
+    run(b, ub, seq[:3])
+    state = b.relax_state()
+    u_ckpt = ub.cpu()
+    b.close()
+    assert state["k"] == 3 and state["relax"] and state["du_max"] == 0.05
+    assert np.array_equal(state["f_prev"].cpu().numpy(), seq[2].reshape(-1))
+
+    r = _ctx(wl.cells, wl.bz, form=form)
+    for bad in (dict(state, k=-1), dict(state, du_max=-1.0), dict(state, f_prev=None)):
+        with pytest.raises((FbcError, TypeError)):
+            r.set_relax_state(bad)
+    r.set_relax_state(state)
+    ur = u_ckpt.to(dev)
+    got_out = run(r, ur, seq[3:])
+    r.close()
+    for g, e in zip(got_out, ref_out[3:]):
+        assert np.array_equal(g, e)
+    assert torch.equal(ur, ua)
