@@ -136,6 +136,10 @@ __device__ inline void gemm_f64_job(const GemmJob& jb,
         for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)pw * mb + r) * 64));
 #pragma unroll
         for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pw) * 64];
+
+        // keeps the ring's loads in slot order (slot 0 first), so the first wait of the main
+        // loop leaves the later slots in flight instead of draining every load
+        __builtin_amdgcn_sched_barrier(0);
     }
     for (int p0 = pb; p0 < pe; p0 += PF) {
 #pragma unroll
@@ -217,6 +221,10 @@ __device__ inline void gemm_f32_job(const GemmJob& jb,
         for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)qw * mb + r) * 64));
 #pragma unroll
         for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qw) * 64];
+
+        // keeps the ring's loads in slot order (slot 0 first), so the first wait of the main
+        // loop leaves the later slots in flight instead of draining every load
+        __builtin_amdgcn_sched_barrier(0);
     }
     for (int q0 = qb; q0 < qe; q0 += PF) {
 #pragma unroll
@@ -236,6 +244,8 @@ __device__ inline void gemm_f32_job(const GemmJob& jb,
             for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)qn * mb + r) * 64));
 #pragma unroll
             for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qn) * 64];
+
+            __builtin_amdgcn_sched_barrier(0);     // the same order in every ring pass
         }
         if (((q0 - qb + PF) % KCH) == 0 || q0 + PF >= qe) {
 #pragma unroll
@@ -327,6 +337,9 @@ __device__ inline void gemm_split_job(const GemmJob& jb,
             bh[u][c] = b[((int64_t)c * kt + tw) * 128];
             bl[u][c] = b[((int64_t)c * kt + tw) * 128 + 64];
         }
+        // keeps the ring's loads in slot order (slot 0 first), so the first wait of the main
+        // loop leaves the later slots in flight instead of draining every load
+        __builtin_amdgcn_sched_barrier(0);
     }
     for (int t0 = tb; t0 < te; t0 += PF) {
 #pragma unroll
@@ -357,6 +370,7 @@ __device__ inline void gemm_split_job(const GemmJob& jb,
                 bh[u][c] = b[((int64_t)c * kt + tn) * 128];
                 bl[u][c] = b[((int64_t)c * kt + tn) * 128 + 64];
             }
+            __builtin_amdgcn_sched_barrier(0);     // the same order in every ring pass
         }
         if (((t0 - tb + PF) % KCH) == 0 || t0 + PF >= te) {
 #pragma unroll
