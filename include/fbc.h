@@ -360,6 +360,18 @@ fbc_status fbc_mlp_loss_grad(fbc_mlp* m, const float* x, const float* t, int n,
 fbc_status fbc_mlp_adam_step(fbc_mlp* m, float lr, void* stream);
 /* FP32 forward pass y [n][12] of x [n][8] (device). */
 fbc_status fbc_mlp_forward(fbc_mlp* m, const float* x, float* y, int n, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the same forward pass (same kernels, bitwise the
+ * result of fbc_mlp_forward) with the layer activations kept in a workspace of 64 MiB that
+ * the library holds statically on every GPU it runs on (until the process ends) instead
+ * of the network's own workspace; n is not limited by max_batch but by that workspace:
+ * n in [1, fbc_mlp_forward_noalloc_max_rows()] (10591 rows), else FBC_E_ARG.  Calls no
+ * allocating routine; asynchronous on `stream`.  The network's device must be current
+ * (FBC_E_ARG otherwise).  All calls on one GPU share the workspace: calls that overlap on
+ * one GPU (other streams, other threads) race; calls ordered on one stream do not.  Every
+ * workspace value is written before it is read, so nothing carries over between calls. */
+fbc_status fbc_mlp_forward_noalloc(const fbc_mlp* m, const float* x, float* y, int n, void* stream);
+int fbc_mlp_forward_noalloc_max_rows(void);
 /* ------------------------------------------------------------------------------------
  * Real-space periodic lattice Green function (Section 3.1, eqs. G~inf, plgf_conv,
  * plgf_poly and plgf_rich; Appendix B): an independent route to the line-periodic Green

@@ -126,6 +126,7 @@ struct fbc_mlp {
     float* loss = nullptr;
     int max_batch = 0;
     int step = 0;
+    int device = 0;                  // device holding the parameters
     std::vector<void*> allocs;
     std::string err;
 };

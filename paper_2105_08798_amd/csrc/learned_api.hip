@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -230,6 +231,7 @@ extern "C" fbc_status fbc_mlp_create(int max_batch, uint64_t seed, fbc_mlp** out
     fbc_mlp* m = new (std::nothrow) fbc_mlp();
     if (!m) return lfail(nullptr, FBC_E_NOMEM, "host allocation");
     m->max_batch = max_batch;
+    (void)hipGetDevice(&m->device);
     fbc_status rc;
     if ((rc = lalloc(m->allocs, &m->err, &m->params, MLP_NPARAMS * 4)) ||
         (rc = lalloc(m->allocs, &m->err, &m->grad, MLP_NPARAMS * 4)) ||
@@ -305,5 +307,61 @@ extern "C" fbc_status fbc_mlp_forward(fbc_mlp* m, const float* x, float* y, int 
     if (n < 1 || n > m->max_batch) return lfail(&m->err, FBC_E_ARG, "batch size out of range");
     launch_mlp_forward((hipStream_t)stream, m->params, x, n, m->ws, y);
     LCHK(&m->err, hipGetLastError());
+    return FBC_OK;
+}
+
+// ----------------------------------------------------------------------------------
+// Forward pass without device allocation, for callers that cannot allocate (code under
+// HIP graph capture, serving loops): the layer activations go to a file-scope device
+// array instead of the network's workspace.  Each GPU the library runs on holds its own
+// copy of the array until the process ends; every call on that GPU shares it.
+// ----------------------------------------------------------------------------------
+static constexpr int64_t kNoAllocBytes = (int64_t)64 << 20;
+static __device__ __align__(256) float scratch[kNoAllocBytes / 4];
+
+// Floats of the forward workspace for n rows (z and a of every layer in the layout of
+// launch_mlp_forward, 4 n x width per layer).
+static int64_t forward_ws_floats(int64_t n) { return 4 * n * (3 * MLP_H + MLP_OUT); }
+static const int kNoAllocRows = (int)(kNoAllocBytes / 4 / forward_ws_floats(1));
+
+// Device address of this GPU's copy of `scratch`, looked up once per device with that
+// device current; host code never passes the array's own name to a kernel.
+static std::mutex g_scratch_mu;
+static std::vector<float*> g_scratch_dev;
+
+static fbc_status scratch_address(int dev, float** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return lfail(nullptr, FBC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_dev[dev] = (float*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return FBC_OK;
+}
+
+extern "C" int fbc_mlp_forward_noalloc_max_rows(void) { return kNoAllocRows; }
+
+extern "C" fbc_status fbc_mlp_forward_noalloc(const fbc_mlp* m, const float* x, float* y, int n, void* stream) {
+    if (!m || !x || !y) return lfail(nullptr, FBC_E_ARG, "null argument");
+    if (n < 1 || n > kNoAllocRows)
+        return lfail(nullptr, FBC_E_ARG, "n must be in [1, " + std::to_string(kNoAllocRows) +
+                                             "]: the static workspace holds " + std::to_string(kNoAllocBytes) + " B");
+    int dev = -1;
+    LCHK(nullptr, hipGetDevice(&dev));
+    if (dev != m->device)
+        return lfail(nullptr, FBC_E_ARG, "the network's device (" + std::to_string(m->device) +
+                                             ") must be current (current: " + std::to_string(dev) + ")");
+    float* ws = nullptr;
+    fbc_status s = scratch_address(dev, &ws);
+    if (s != FBC_OK) return s;
+    // every workspace value is written before it is read: nothing needs clearing
+    launch_mlp_forward((hipStream_t)stream, m->params, x, n, ws, y);
+    LCHK(nullptr, hipGetLastError());
     return FBC_OK;
 }

@@ -29,7 +29,7 @@ EXPORTED = [
     "fbc_mlp_params", "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
     "fbc_plgf_last_error", "fbc_plgf_create", "fbc_plgf_destroy", "fbc_plgf_table", "fbc_plgf_eval",
     "fbc_hmat_last_error", "fbc_hmat_create", "fbc_hmat_destroy", "fbc_hmat_get_info", "fbc_hmat_partition",
-    "fbc_hmat_ranks", "fbc_hmat_apply",
+    "fbc_hmat_ranks", "fbc_hmat_apply", "fbc_mlp_forward_noalloc", "fbc_mlp_forward_noalloc_max_rows",
 ]
 
 
@@ -145,6 +145,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp]
     lib.fbc_mlp_adam_step.argtypes = [vp, C.c_float, vp]
     lib.fbc_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
+    lib.fbc_mlp_forward_noalloc.argtypes = [vp, vp, vp, C.c_int, vp]
+    lib.fbc_mlp_forward_noalloc_max_rows.argtypes = []
+    lib.fbc_mlp_forward_noalloc_max_rows.restype = C.c_int
     lib.fbc_plgf_last_error.argtypes = []
     lib.fbc_plgf_last_error.restype = cp
     lib.fbc_plgf_create.argtypes = [C.POINTER(Lattice), C.POINTER(PlgfOpts), vp, C.POINTER(vp)]
@@ -167,7 +170,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
                  "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_num_params", "fbc_mlp_params",
                  "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
-                 "fbc_plgf_create", "fbc_plgf_table", "fbc_plgf_eval", "fbc_hmat_create", "fbc_hmat_get_info",
+                 "fbc_mlp_forward_noalloc", "fbc_plgf_create", "fbc_plgf_table", "fbc_plgf_eval", "fbc_hmat_create", "fbc_hmat_get_info",
                  "fbc_hmat_partition", "fbc_hmat_ranks", "fbc_hmat_apply"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -371,6 +374,16 @@ class MLP:
         _lcheck(self._lib, self._lib.fbc_mlp_forward(self.handle, _dptr(x, torch.float32),
                                                      _dptr(y, torch.float32), int(x.shape[0]),
                                                      _stream_handle(stream)))
+
+    def forward_noalloc(self, x, y, stream=None):
+        """The same forward pass with the activations in the library's static workspace."""
+        import torch
+        _lcheck(self._lib, self._lib.fbc_mlp_forward_noalloc(self.handle, _dptr(x, torch.float32),
+                                                             _dptr(y, torch.float32), int(x.shape[0]),
+                                                             _stream_handle(stream)))
+
+    def noalloc_max_rows(self) -> int:
+        return int(self._lib.fbc_mlp_forward_noalloc_max_rows())
 
     def close(self):
         if self.handle:
