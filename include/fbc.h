@@ -466,11 +466,12 @@ typedef struct {
 /* Last error text of the fbc_hmat_* calls on this host thread. */
 const char* fbc_hmat_last_error(void);
 
-/* Builds the H-matrices of every line mode of `ctx` (FBC_FORM_FP64, exactly one cell;
- * FBC_E_UNSUPPORTED otherwise) from its dense store; the context must outlive the
- * object, which reads the store for dense leaves.  Trees and partition on the host
- * (geometry only), the cross approximations on the device (one work group per block and
- * mode).  Synchronises `stream`. */
+/* Builds the H-matrices of every line mode of `ctx` (FBC_FORM_DTABLE_FP64, exactly one
+ * cell; FBC_E_UNSUPPORTED otherwise) from its offset table (the entries depend on the
+ * column offset only, Section 3.2, so no dense matrix is ever formed); the context must
+ * outlive the object, which reads the table for dense leaves.  Trees and partition on the
+ * host (geometry only), the cross approximations on the device (one work group per block
+ * and mode).  Synchronises `stream`. */
 fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* opts, void* stream,
                            fbc_hmat** out);
 void fbc_hmat_destroy(fbc_hmat* h);

@@ -151,9 +151,10 @@ static bool row_gauge_active(const fbc_ctx* c) {
 static int64_t store_elem_bytes(int form) {
     return form == FBC_FORM_FP64 ? 8 : (form == FBC_FORM_FP32 ? 4 : 2);
 }
-// store elements (of the store type) per mode: FP64/FP32 mp*kp, BF16 2*mp*kp
-static int64_t store_mode_elems(int form, const CellPlan& p) {
-    return (int64_t)p.mp * p.kp * (is_split16(form) ? 2 : 1);
+// Store elements (of the store type) of one chunk-tile of the compact dense store:
+// rows_tile rows x 64 K' (x2 for the hi and lo parts of the split forms).
+static int64_t chunk_tile_elems(int form, int rows_tile) {
+    return (int64_t)rows_tile * 64 * (is_split16(form) ? 2 : 1);
 }
 static int64_t b_mode_elems(int form, const CellPlan& p) {
     return (int64_t)16 * p.ct * p.kp * (is_split16(form) ? 2 : 1);
@@ -523,7 +524,7 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
                 na += p.nm;
             }
             if ((s = dev_alloc(c, (void**)&c->amax, na * 8)) != FBC_OK ||
-                (s = dev_alloc(c, (void**)&c->bexp, (int64_t)c->cells.size() * 4)) != FBC_OK) {
+                (s = dev_alloc(c, (void**)&c->bexp, (int64_t)c->total_rhs * 4)) != FBC_OK) {
                 cleanup();
                 return s;
             }
@@ -541,6 +542,31 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
             }
             c->scratch_bytes += tot_rm * 16;
         }
+        // compact store: the chunk-tiles of every window, cell after cell
+        const int rows_tile = 64 * gemm_rb(form, c->ctmax);
+        const int64_t cte = chunk_tile_elems(form, rows_tile);
+        int64_t a_tot = 0, max_reg = 0;
+        for (CellPlan& p : c->cells) {
+            const int nreg = p.nm * p.n_tiles;
+            p.reg_pre.assign((size_t)nreg + 1, 0);
+            for (int r = 0; r < nreg; ++r) p.reg_pre[r + 1] = p.reg_pre[r] + p.win_len[r];
+            p.n_ct = p.reg_pre[nreg];
+            p.a_off = a_tot;
+            a_tot += p.n_ct * cte;
+            max_reg = std::max<int64_t>(max_reg, nreg);
+        }
+        c->store_bytes = a_tot * store_elem_bytes(form);
+        if ((s = dev_alloc(c, &c->store, std::max<int64_t>(c->store_bytes, 256))) != FBC_OK) {
+            cleanup();
+            return fail(c, FBC_E_NOMEM, "dense store of " + std::to_string(c->store_bytes) +
+                                            " B (the blocks inside the negligible-block windows): " + c->err);
+        }
+        int64_t* reg_d;
+        int32_t* ws_d;
+        if ((s = talloc((void**)&reg_d, (max_reg + 1) * 8)) != FBC_OK || (s = talloc((void**)&ws_d, max_reg * 4 + 4)) != FBC_OK) {
+            cleanup();
+            return s;
+        }
         for (size_t ci = 0; ci < c->cells.size(); ++ci) {
             CellPlan& p = c->cells[ci];
             const int mult = c->nz_max / p.nz;
@@ -556,9 +582,13 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
                         HIPCHK(c, hipMemsetAsync(rowmean + (int64_t)m * p.n_b * 6, 0, (size_t)p.n_b * 6 * 16, st));
             }
             char* base = (char*)c->store + p.a_off * store_elem_bytes(form);
-            launch_build_dense(st, form, base, c->tab, rowmean, p.nm, mult, n_off, p.mp, p.kp, p.n_b,
-                               p.n_i, p.cols_b_d, p.cols_i_d, c->lut, os.d1min, os.d2min, os.w2,
-                               form == FBC_FORM_SPLIT_FP16 ? c->amax + c->amax_off[ci] : nullptr);
+            // the previous cell's build must be done with the staging lists before they change
+            HIPCHK(c, hipStreamSynchronize(st));
+            HIPCHK(c, hipMemcpyAsync(reg_d, p.reg_pre.data(), p.reg_pre.size() * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(ws_d, p.win_start.data(), p.win_start.size() * 4, hipMemcpyHostToDevice, st));
+            launch_build_dense(st, form, base, c->tab, rowmean, reg_d, ws_d, p.nm, p.n_tiles, p.n_chunks, rows_tile,
+                               p.n_ct, mult, n_off, p.n_b, p.n_i, p.cols_b_d, p.cols_i_d, c->lut, os.d1min,
+                               os.d2min, os.w2, form == FBC_FORM_SPLIT_FP16 ? c->amax + c->amax_off[ci] : nullptr);
             HIPCHK(c, hipGetLastError());
         }
         c->tab = nullptr;
@@ -637,7 +667,8 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
             const int wl = p.win_len[(size_t)u.m * p.n_tiles + tl];
             const int a = (int)((int64_t)wl * ks / nsplit), e = (int)((int64_t)wl * (ks + 1) / nsplit);
             GemmJob j{};
-            j.a_off = dt ? (int64_t)u.t * c->n_offsets * 6 : p.a_off + (int64_t)u.m * store_mode_elems(form, p);
+            j.a_off = dt ? (int64_t)u.t * c->n_offsets * 6
+                         : p.a_off + (p.reg_pre[(size_t)u.m * p.n_tiles + tl] + a) * chunk_tile_elems(form, tile_rows);
             j.b_off = p.b_off + (int64_t)u.m * b_mode_elems(form, p);
             j.c_off = p.c_off + ks * p.c_split + (int64_t)u.m * 16;
             j.crs = p.nm * 16;
@@ -785,7 +816,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     const int ctl = ctmax <= 1 ? 1 : ctmax <= 2 ? 2 : ctmax <= 4 ? 4 : 8;
     const int rows_tile = 64 * gemm_rb(form, ctl);
     c->ctmax = ctl;
-    int64_t f_off = 0, u_off = 0, a_off = 0, b_off = 0, c_off = 0, w_off = 0;
+    int64_t f_off = 0, u_off = 0, b_off = 0, c_off = 0, w_off = 0;
     int rhs0 = 0;
     int64_t tiles_total = 0;   // (cell, mode, row tile) work items before the K split
     int kslices_max = 1 << 30;
@@ -809,7 +840,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         p.ctr = (p.R + 7) / 8;
         p.f_off = f_off;
         p.u_off = u_off;
-        p.a_off = a_off;
+        p.a_off = 0;
         p.b_off = b_off;
         p.c_off = c_off;
         p.w_off = w_off;
@@ -818,7 +849,6 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         p.cols_b.assign(cells[i].cols_b, cells[i].cols_b + 2 * p.n_b);
         f_off += (int64_t)p.R * p.nz * p.K;
         u_off += (int64_t)p.R * p.nz * p.M;
-        a_off += store_mode_elems(form, p) * p.nm;
         b_off += b_mode_elems(form, p) * p.nm;
         p.c_split = (int64_t)p.nm * p.ct * p.mp * 16;
         if (is_table_form(form)) {
@@ -856,10 +886,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     c->f_elems = f_off;
     c->u_elems = u_off;
     fbc_status s;
-    if (!is_table_form(form)) {
-        c->store_bytes = a_off * store_elem_bytes(form);
-        if ((s = dev_alloc(c, &c->store, c->store_bytes)) != FBC_OK) goto fail_out;
-    }
+    // the dense store is allocated once the negligible-block windows are known (assembly)
     if ((s = dev_alloc(c, &c->bfrag, b_off * b_elem_bytes(form))) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->cbuf, c_off * 8)) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->wbuf, w_off * 8)) != FBC_OK) goto fail_out;
@@ -988,7 +1015,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
         const double* fc = f + p.f_off;
         double* sums = c->sums + sums_off;
         double* tot = c->ftot + 3 * p.rhs0;
-        int* bexp = f16 ? c->bexp + ci : nullptr;
+        int* bexp = f16 ? c->bexp + p.rhs0 : nullptr;
         if (c->opt.check_netforce || c->opt.project_netforce || comp || f16)
             launch_netforce(st, fc, sums, tot, comp ? c->shat + c->shat_off[ci] : nullptr,
                             comp ? c->shat_on + p.rhs0 : nullptr, p.R, p.nz, p.n_i, c->opt.netforce_tol,
@@ -1036,7 +1063,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
                           p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split,
                           comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
                           comp ? c->shat + c->shat_off[ci] : nullptr, comp ? c->shat_on + p.rhs0 : nullptr,
-                          f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + ci : nullptr, nullptr);
+                          f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + p.rhs0 : nullptr, nullptr);
     }
 }
 
@@ -1051,7 +1078,7 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
         const double2* sh = comp ? c->shat + c->shat_off[ci] : nullptr;
         const int* so = comp ? c->shat_on + p.rhs0 : nullptr;
         const unsigned long long* am = f16 ? c->amax + c->amax_off[ci] : nullptr;
-        const int* be = f16 ? c->bexp + ci : nullptr;
+        const int* be = f16 ? c->bexp + p.rhs0 : nullptr;
         int tr, pp;
         if (!update_shape(p.nz, p.M, p.ctr, &tr, &pp)) {
             // long or short lines: inverse transform into w, then the tiled transpose-update
@@ -1351,15 +1378,36 @@ extern "C" fbc_status fbc_copy_block_rows(fbc_ctx* c, int cell, int m, int b0, i
         return FBC_OK;
     }
     if (c->opt.form != FBC_FORM_FP64) return fail(c, FBC_E_UNSUPPORTED, "FP64 forms only");
-    const int64_t per_mode = (int64_t)p.mp * p.kp;
-    std::vector<double> blk(per_mode);
-    HIPCHK(c, hipDeviceSynchronize());
-    HIPCHK(c, hipMemcpy(blk.data(), (double*)c->store + p.a_off + m * per_mode, per_mode * 8,
-                        hipMemcpyDeviceToHost));
+    // compact store: the row tiles covering the rows, their windows at mode m; blocks
+    // outside a window are the product's zeros
+    const int rows_tile = 64 * gemm_rb(c->opt.form, c->ctmax);
+    const int64_t cte = chunk_tile_elems(c->opt.form, rows_tile);
+    const int trb = rows_tile / 16;
     const int rows = 3 * (b1 - b0);
-    for (int r = 0; r < rows; ++r)
-        for (int k = 0; k < 6 * p.n_i; ++k)
-            out[(int64_t)r * 6 * p.n_i + k] = blk[frag_off_f64_km(3 * b0 + r, k, p.mp)];
+    std::fill(out, out + (int64_t)rows * 6 * p.n_i, 0.0);
+    HIPCHK(c, hipDeviceSynchronize());
+    std::vector<double> reg;
+    for (int tl = (3 * b0) / rows_tile; tl <= (3 * b1 - 1) / rows_tile; ++tl) {
+        const int r = m * p.n_tiles + tl;
+        const int ws = p.win_start[r], wl = p.win_len[r];
+        if (wl == 0) continue;
+        reg.resize((size_t)wl * cte);
+        HIPCHK(c, hipMemcpy(reg.data(), (double*)c->store + p.a_off + p.reg_pre[r] * cte, reg.size() * 8,
+                            hipMemcpyDeviceToHost));
+        for (int row = std::max(3 * b0, tl * rows_tile); row < std::min(3 * b1, (tl + 1) * rows_tile); ++row) {
+            const int rr = row - tl * rows_tile, blk = rr >> 4;
+            for (int j = 0; j < wl; ++j) {
+                const int ch = (ws + j) % p.n_chunks;
+                for (int x = 0; x < 64; ++x) {
+                    const int k = 64 * ch + x;
+                    if (k >= 6 * p.n_i) break;
+                    const int lane = ((x & 3) << 4) | (rr & 15);
+                    const int64_t el = (int64_t)j * cte + ((((x >> 3) * trb + blk) * 64 + lane) << 1) + ((x >> 2) & 1);
+                    out[(int64_t)(row - 3 * b0) * 6 * p.n_i + k] = reg[el];
+                }
+            }
+        }
+    }
     return FBC_OK;
 }
 

@@ -91,18 +91,22 @@ __global__ void __launch_bounds__(NT) k_netforce(const double* __restrict__ f,
     }
 }
 
-// Split-FP16 form: scale exponent of the force operand of a cell, from a bound on the
-// transformed forces, |f^(m)| <= sum_n0 |f(n0)| <= Nz max|f| (twice that after the
-// projection), so that the scaled values stay below 2^14.
-__global__ void __launch_bounds__(NT) k_bexp(const double* __restrict__ sums, int n_layers, int nz,
+// Split-FP16 form: scale exponent of the force operand of each RHS (one work group per
+// RHS), from a bound on its transformed forces, |f^(m)| <= sum_n0 |f(n0)| <= Nz max|f|
+// (twice that after the projection), so that the scaled values stay below 2^14.  One
+// exponent per RHS: a RHS far smaller than another of the same cell (a converged one
+// beside one that is not) keeps its full 22-bit split instead of falling into subnormals.
+__global__ void __launch_bounds__(NT) k_bexp(const double* __restrict__ sums, int nz,
                                              int* __restrict__ bexp) {
     __shared__ double red[NT];
+    const int r = blockIdx.x;
     double mx[1] = {0.0};
-    for (int e = threadIdx.x; e < n_layers; e += NT) mx[0] = fmax(mx[0], sums[(int64_t)e * NF_STRIDE + 6]);
+    for (int n0 = threadIdx.x; n0 < nz; n0 += NT)
+        mx[0] = fmax(mx[0], sums[((int64_t)r * nz + n0) * NF_STRIDE + 6]);
     block_max<1>(mx, red);
     if (threadIdx.x == 0) {
         const double bound = 2.0 * nz * mx[0];
-        *bexp = (bound > 0.0 && isfinite(bound)) ? 13 - ilogb(bound) : 0;
+        bexp[r] = (bound > 0.0 && isfinite(bound)) ? 13 - ilogb(bound) : 0;
     }
 }
 
@@ -172,7 +176,7 @@ void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot,
     const size_t lds = std::max((size_t)3 * nz * sizeof(double2), (size_t)6 * NT * sizeof(double));
     hipLaunchKernelGGL(k_netforce_total, dim3(R), dim3(NT), lds, st, sums, nz, logn, n_i, tol, check, project, tot,
                        tw, shat, shat_on, status);
-    if (bexp) hipLaunchKernelGGL(k_bexp, dim3(1), dim3(NT), 0, st, sums, R * nz, nz, bexp);
+    if (bexp) hipLaunchKernelGGL(k_bexp, dim3(R), dim3(NT), 0, st, sums, nz, bexp);
 }
 
 // ----------------------------------------------------------------------------------
@@ -255,10 +259,10 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                                                   const double2* __restrict__ tw, double inv_cnt,
                                                   const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
-    const int esc = (FORM == FBC_FORM_SPLIT_FP16) ? *bexp : 0;   // power-of-two operand scale
     // RHS fastest across blocks: the 8 RHS of a column tile, whose 64-byte column runs
     // fill the same 1 KiB fragment blocks, are written by neighbouring blocks close in time
     const int r = blockIdx.x;
+    const int esc = (FORM == FBC_FORM_SPLIT_FP16) ? bexp[r] : 0;   // power-of-two operand scale
     const int K = 3 * n_i;
     const int nseq = tc >> 1;
     const int ss = nz + 1;                  // sequence stride (complex values)
@@ -426,14 +430,17 @@ __device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R
                                    const double2* __restrict__ rowmean,
                                    const double2* __restrict__ shat,
                                    const int* __restrict__ shat_on,
-                                   const unsigned long long* __restrict__ amax, int eb,
+                                   const unsigned long long* __restrict__ amax,
+                                   const int* __restrict__ bexp,
                                    double& ar, double& br, double& ai, double& bi) {
-    if (amax) {     // split FP16: the product carries 2^(e_A(m) + e_B)
-        const double sc = ldexp(1.0, -(split16_exp_a(amax[mm]) + eb));
-        ar *= sc;
-        ai *= sc;
-        br *= sc;
-        bi *= sc;
+    if (amax) {     // split FP16: the product of RHS r carries 2^(e_A(m) + e_B(r))
+        const int ea = split16_exp_a(amax[mm]);
+        const double sa = ldexp(1.0, -(ea + (ra < R ? bexp[ra] : 0)));
+        const double sb = ldexp(1.0, -(ea + (ra + 1 < R ? bexp[ra + 1] : 0)));
+        ar *= sa;
+        ai *= sa;
+        br *= sb;
+        bi *= sb;
     }
     // the compensation is zero for RHS whose per-layer net forces all vanish (s^ = 0):
     // skipped for them (shat_on[r] = 0), which saves its loads for the usual forces
@@ -464,7 +471,8 @@ __device__ inline void mode_value(double2 v0, double2 v1, const double* __restri
                                   int nsplit, int64_t split_stride, int mm, int row, int M, int nm,
                                   int ra, int R, const double2* __restrict__ rowmean,
                                   const double2* __restrict__ shat, const int* __restrict__ shat_on,
-                                  const unsigned long long* __restrict__ amax, int eb,
+                                  const unsigned long long* __restrict__ amax,
+                                  const int* __restrict__ bexp,
                                   double& ar, double& br, double& ai, double& bi) {
     ar = v0.x;
     br = v0.y;
@@ -478,7 +486,7 @@ __device__ inline void mode_value(double2 v0, double2 v1, const double* __restri
         ai += q1.x;
         bi += q1.y;
     }
-    mode_adjust(mm, row, M, nm, ra, R, rowmean, shat, shat_on, amax, eb, ar, br, ai, bi);
+    mode_adjust(mm, row, M, nm, ra, R, rowmean, shat, shat_on, amax, bexp, ar, br, ai, bi);
 }
 
 // Gathers the spectra of tr rows x pp RHS pairs of one column tile into LDS (bit-reversed,
@@ -492,7 +500,8 @@ __device__ inline void gather_inverse(double2* lds, const double* __restrict__ c
                                       int mp, int M, const double2* __restrict__ tw, int nsplit,
                                       int64_t split_stride, const double2* __restrict__ rowmean,
                                       const double2* __restrict__ shat, const int* __restrict__ shat_on,
-                                      const unsigned long long* __restrict__ amax, int eb) {
+                                      const unsigned long long* __restrict__ amax,
+                                      const int* __restrict__ bexp) {
     const int nm = (nz >> 1) + 1;
     constexpr int LU = 4;
     const int nload = nm * tr * pp;
@@ -528,7 +537,7 @@ __device__ inline void gather_inverse(double2* lds, const double* __restrict__ c
                 const double* src = c + (((int64_t)tile * mp + row) * nm + mm) * 16;
                 double ar, br, ai, bi;
                 mode_value(pv0[q], pv1[q], src, ja, nsplit, split_stride, mm, row, M, nm, 8 * tile + ja, R,
-                           rowmean, shat, shat_on, amax, eb, ar, br, ai, bi);
+                           rowmean, shat, shat_on, amax, bexp, ar, br, ai, bi);
                 z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
                 zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
             }
@@ -555,14 +564,13 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    const unsigned long long* __restrict__ amax,
                                                    const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
-    const int eb = bexp ? *bexp : 0;
     const int row0 = blockIdx.x * tr;
     const int tile = blockIdx.y;
     const int pair0 = blockIdx.z * pp;          // first RHS pair inside the 8-RHS tile
     const int nseq = tr * pp;
     const int ss = nz + 1;
     gather_inverse(lds, c, tile, row0, pair0, tr, pp, ss, R, nz, logn, mp, M, tw, nsplit, split_stride,
-                   rowmean, shat, shat_on, amax, eb);
+                   rowmean, shat, shat_on, amax, bexp);
     const double scale = 1.0 / nz;
     double mx[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // per RHS inside the tile
     for (int t = threadIdx.x; t < nseq * nz; t += NT) {
@@ -668,7 +676,6 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
     const int row0 = rg * tr, pair0 = pg * pp;
     const int ss = nz + 1;
     const int nm = (nz >> 1) + 1;
-    const int eb = bexp ? *bexp : 0;
     const int nseq = tr * pp;
     // 1. gather
     {
@@ -713,7 +720,7 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
                 }
                 double2 z = make_double2(0, 0), zc = make_double2(0, 0);
                 if (row < M) {
-                    mode_adjust(mm, row, M, nm, 8 * tile + ja, R, rowmean, shat, shat_on, amax, eb, ar, br,
+                    mode_adjust(mm, row, M, nm, 8 * tile + ja, R, rowmean, shat, shat_on, amax, bexp, ar, br,
                                 ai, bi);
                     z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
                     zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
@@ -880,14 +887,13 @@ __global__ void __launch_bounds__(NT) k_mean_parts(const double* __restrict__ u,
     {
         const int tile = r >> 3, ja = (r & 7) & ~1, odd = r & 1;
         const int nm = (nz >> 1) + 1;
-        const int eb = bexp ? *bexp : 0;
         const int lr = (M + nbr - 1) / nbr;
         const int r1 = std::min(M, (b + 1) * lr);
         for (int row = b * lr + threadIdx.x; row < r1; row += NT) {
             const double* src = c + ((int64_t)tile * mp + row) * nm * 16;
             double ar, br, ai, bi;
             mode_value(*(const double2*)(src + ja), *(const double2*)(src + ja + 8), src, ja, nsplit,
-                       split_stride, 0, row, M, nm, 8 * tile + ja, R, rowmean, shat, shat_on, amax, eb, ar,
+                       split_stride, 0, row, M, nm, 8 * tile + ja, R, rowmean, shat, shat_on, amax, bexp, ar,
                        br, ai, bi);
             v[3 + row % 3] += odd ? br : ar;
         }

@@ -250,65 +250,79 @@ __device__ inline double dense_value(int row, int kq, int m, int mode_mult,
     return part ? v.y : v.x;
 }
 
+// Compact dense store of one cell: only the K chunks inside the negligible-block window
+// of each (mode, row tile) are stored.  The store is a sequence of chunk-tiles (64 K' x
+// tile_rows rows each) in (mode, tile, window position) order: region r = m n_tiles + tl
+// holds win_len[r] chunk-tiles from reg_pre[r] on, the window position j holding the
+// cyclic chunk (win_start[r] + j) mod n_chunks.  Inside a chunk-tile the MFMA fragment
+// order of the product kernels, K-major across the tile's row blocks:
+//   FP64  [8 steps of 8 k'][row block][lane][2]
+//   FP32  [4 steps of 16 k'][row block][lane][4]
+//   split [2 steps of 32 k'][row block][hi, lo][lane][8]
+// One work group per chunk-tile.
 __global__ void __launch_bounds__(256) k_build_dense(int form, void* __restrict__ store,
                                                      const double2* __restrict__ tab,
-                                                     const double2* __restrict__ rowmean, int nm,
-                                                     int mode_mult, int64_t n_off, int mp, int kp, int n_b,
+                                                     const double2* __restrict__ rowmean,
+                                                     const int64_t* __restrict__ reg_pre,
+                                                     const int32_t* __restrict__ win_start, int n_reg,
+                                                     int n_tiles, int n_chunks, int tile_rows,
+                                                     int64_t n_ct, int mode_mult, int64_t n_off, int n_b,
                                                      int n_i, const int32_t* __restrict__ cols_b,
                                                      const int32_t* __restrict__ cols_i,
                                                      const int32_t* __restrict__ lut, int d1min,
                                                      int d2min, int w2,
                                                      const unsigned long long* __restrict__ amax) {
-    const int64_t per_mode = (int64_t)mp * kp;
-    const int64_t total = per_mode * nm;
-    // grid-stride: the element count can exceed the 2^32 work-items of one launch
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-    const int m = (int)(e / per_mode);
-    const int64_t x = e - (int64_t)m * per_mode;
-    const int mb = mp >> 4;
-    if (form == FBC_FORM_FP64) {          // [p][blk][lane][2]
-        const int s = (int)(x & 1), lane = (int)((x >> 1) & 63);
-        const int64_t rest = x >> 7;
-        const int blk = (int)(rest % mb), p = (int)(rest / mb);
-        const int row = 16 * blk + (lane & 15), kq = 8 * p + 4 * s + (lane >> 4);
-        ((double*)store)[e] = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i,
-                                          cols_b, cols_i, lut, d1min, d2min, w2);
-    } else if (form == FBC_FORM_FP32) {   // [q][blk][lane][4]
-        const int s = (int)(x & 3), lane = (int)((x >> 2) & 63);
-        const int64_t rest = x >> 8;
-        const int blk = (int)(rest % mb), q = (int)(rest / mb);
-        const int row = 16 * blk + (lane & 15), kq = 16 * q + 4 * s + (lane >> 4);
-        ((float*)store)[e] = (float)dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b,
-                                                n_i, cols_b, cols_i, lut, d1min, d2min, w2);
-    } else if (form == FBC_FORM_SPLIT_FP16) {  // same layout as split BF16, scaled by 2^e(m)
-        const int j = (int)(x & 7), lane = (int)((x >> 3) & 63);
-        const int64_t rest = x >> 9;
-        const int blk = (int)(rest % mb), t = (int)(rest / mb);
-        const int row = 16 * blk + (lane & 15), kq = 32 * t + 8 * (lane >> 4) + j;
-        const double v = ldexp(dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
-                                           cols_i, lut, d1min, d2min, w2),
-                               split16_exp_a(amax[m]));
-        const _Float16 hi = f64_to_f16(v);
-        const _Float16 lo = f64_to_f16(v - (double)hi);
-        unsigned short* out = (unsigned short*)store + (int64_t)m * per_mode * 2;
-        const int64_t base = ((((int64_t)t * mb + blk) * 2) * 64 + lane) * 8 + j;
-        out[base] = __builtin_bit_cast(unsigned short, hi);
-        out[base + 512] = __builtin_bit_cast(unsigned short, lo);
-    } else {  // split BF16 [t][blk][hi/lo][lane][8]: x indexes hi parts; lo is 512 later
-        const int j = (int)(x & 7), lane = (int)((x >> 3) & 63);
-        const int64_t rest = x >> 9;
-        const int blk = (int)(rest % mb), t = (int)(rest / mb);
-        const int row = 16 * blk + (lane & 15), kq = 32 * t + 8 * (lane >> 4) + j;
-        const double v = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
-                                     cols_i, lut, d1min, d2min, w2);
-        const unsigned short hi = f32_to_bf16_rne((float)v);
-        const unsigned short lo = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(hi)));
-        unsigned short* out = (unsigned short*)store + (int64_t)m * per_mode * 2;
-        const int64_t base = ((((int64_t)t * mb + blk) * 2) * 64 + lane) * 8 + j;
-        out[base] = hi;
-        out[base + 512] = lo;
-    }
+    const int trb = tile_rows >> 4;               // row blocks of a tile
+    const int64_t ce = (int64_t)tile_rows * 64;   // real entries of a chunk-tile
+    for (int64_t g = blockIdx.x; g < n_ct; g += gridDim.x) {
+        // region of chunk-tile g: the last r with reg_pre[r] <= g (regions may be empty)
+        int lo = 0, hi = n_reg;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (reg_pre[mid] <= g) lo = mid; else hi = mid;
+        }
+        const int r = lo;
+        const int m = r / n_tiles, tl = r - m * n_tiles;
+        int ch = win_start[r] + (int)(g - reg_pre[r]);
+        if (ch >= n_chunks) ch -= n_chunks;
+        const int row0 = tl * tile_rows, k0 = 64 * ch;
+        for (int64_t x = threadIdx.x; x < ce; x += blockDim.x) {
+            if (form == FBC_FORM_FP64) {
+                const int sub = (int)(x & 1), lane = (int)((x >> 1) & 63);
+                const int rest = (int)(x >> 7);
+                const int blk = rest % trb, st = rest / trb;
+                const int row = row0 + 16 * blk + (lane & 15), kq = k0 + 8 * st + 4 * sub + (lane >> 4);
+                ((double*)store)[g * ce + x] = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i,
+                                                           cols_b, cols_i, lut, d1min, d2min, w2);
+            } else if (form == FBC_FORM_FP32) {
+                const int sub = (int)(x & 3), lane = (int)((x >> 2) & 63);
+                const int rest = (int)(x >> 8);
+                const int blk = rest % trb, st = rest / trb;
+                const int row = row0 + 16 * blk + (lane & 15), kq = k0 + 16 * st + 4 * sub + (lane >> 4);
+                ((float*)store)[g * ce + x] = (float)dense_value(row, kq, m, mode_mult, tab, rowmean, n_off,
+                                                                 n_b, n_i, cols_b, cols_i, lut, d1min, d2min, w2);
+            } else {   // split: x indexes the hi parts; the lo part of a unit is 512 later
+                const int j = (int)(x & 7), lane = (int)((x >> 3) & 63);
+                const int rest = (int)(x >> 9);
+                const int blk = rest % trb, st = rest / trb;
+                const int row = row0 + 16 * blk + (lane & 15), kq = k0 + 32 * st + 8 * (lane >> 4) + j;
+                const double v = dense_value(row, kq, m, mode_mult, tab, rowmean, n_off, n_b, n_i, cols_b,
+                                             cols_i, lut, d1min, d2min, w2);
+                unsigned short* out = (unsigned short*)store + g * 2 * ce;
+                const int64_t base = ((((int64_t)st * trb + blk) * 2) * 64 + lane) * 8 + j;
+                if (form == FBC_FORM_SPLIT_FP16) {   // scaled by 2^e(m)
+                    const double vs = ldexp(v, split16_exp_a(amax[m]));
+                    const _Float16 h = f64_to_f16(vs);
+                    const _Float16 l = f64_to_f16(vs - (double)h);
+                    out[base] = __builtin_bit_cast(unsigned short, h);
+                    out[base + 512] = __builtin_bit_cast(unsigned short, l);
+                } else {
+                    const unsigned short h = f32_to_bf16_rne((float)v);
+                    out[base] = h;
+                    out[base + 512] = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(h)));
+                }
+            }
+        }
     }
 }
 
@@ -380,17 +394,18 @@ void launch_tab_rhocut(hipStream_t st, const double2* tab, int T, int64_t n_off,
 
 
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
-                        const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
-                        int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
+                        const double2* rowmean, const int64_t* reg_pre, const int32_t* win_start,
+                        int nm, int n_tiles, int n_chunks, int tile_rows, int64_t n_ct, int mode_mult,
+                        int64_t n_off, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
                         const int32_t* lut, int d1min, int d2min, int w2, unsigned long long* amax) {
-    const int64_t total = (int64_t)mp * kp * nm;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
     if (form == FBC_FORM_SPLIT_FP16) {
         hipLaunchKernelGGL(k_zero_u64, dim3((nm + 255) / 256), dim3(256), 0, st, amax, nm);
         const int sl = (int)std::min<int64_t>(64, (n_off * 6 + 255) / 256);
         hipLaunchKernelGGL(k_tab_absmax, dim3(sl, nm), dim3(256), 0, st, tab, mode_mult, n_off, amax);
     }
-    hipLaunchKernelGGL(k_build_dense, dim3((unsigned)blocks), dim3(256), 0, st,
-                       form, store, tab, rowmean, nm, mode_mult, n_off, mp, kp, n_b, n_i, cols_b,
-                       cols_i, lut, d1min, d2min, w2, amax);
+    if (n_ct <= 0) return;
+    const int64_t blocks = std::min<int64_t>(n_ct, 1 << 20);
+    hipLaunchKernelGGL(k_build_dense, dim3((unsigned)blocks), dim3(256), 0, st, form, store, tab, rowmean,
+                       reg_pre, win_start, nm * n_tiles, n_tiles, n_chunks, tile_rows, n_ct, mode_mult, n_off,
+                       n_b, n_i, cols_b, cols_i, lut, d1min, d2min, w2, amax);
 }

@@ -144,4 +144,8 @@ struct CellPlan {
     int n_tiles = 0, n_chunks = 0;
     std::vector<int32_t> win_start, win_len;   // [nm][n_tiles]
     std::vector<uint8_t> mode_skips;           // [nm]: some chunk of this mode is skipped
+    // Compact dense store: region r = m n_tiles + tl holds the win_len[r] chunk-tiles of
+    // that window from chunk-tile reg_pre[r] on (cell-local); n_ct = reg_pre[nm n_tiles].
+    std::vector<int64_t> reg_pre;
+    int64_t n_ct = 0;
 };

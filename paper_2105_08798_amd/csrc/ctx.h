@@ -30,7 +30,7 @@ struct fbc_ctx {
     std::vector<int64_t> shat_off, rowmean_off;
     unsigned long long* amax = nullptr;  // split FP16: per cell mode, largest table magnitude
     std::vector<int64_t> amax_off;
-    int* bexp = nullptr;            // split FP16: per cell, force operand scale exponent
+    int* bexp = nullptr;            // split FP16: per RHS, force operand scale exponent [total_rhs]
     double* wmax_part = nullptr;
     double* sum_part = nullptr;
     double* mean = nullptr;         // [total_rhs][3]

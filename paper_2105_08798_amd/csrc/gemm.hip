@@ -6,8 +6,11 @@
 // parts of 8 RHS in columns 0..7 and their imaginary parts in columns 8..15.
 //
 // A is streamed once from HBM in MFMA fragment order (each wave-wide 16-byte load is
-// 1 KiB contiguous, no LDS); B fragments are re-read by every row tile of the same
-// mode and stay in L2 because the job list gives all tiles of a mode to one XCD.
+// 1 KiB contiguous, no LDS) from the compact store: a job's stored blocks are the K
+// chunks of its (mode, row tile) window, one contiguous run, K-major across the tile's
+// row blocks, so a work group streams one sequential region; B fragments are re-read by
+// every row tile of the same mode and stay in L2 because the job list gives all tiles
+// of a mode to one XCD.
 // Each work group is 4 waves; a wave owns RB row blocks (16 rows each) of one mode and
 // all column tiles of that mode, over the whole K.  Loads run PF steps ahead.
 #include <cstdint>
@@ -113,8 +116,8 @@ __device__ inline void gemm_f64_job(const GemmJob& jb,
     if (rbw >= jb.mb) return;
     const int kp8 = jb.kp >> 3;
     const int pb = jb.k0 >> 3, pe = jb.k1 >> 3;
-    const int64_t mb = jb.mb;
-    const double2* a = (const double2*)(A + jb.a_off) + (int64_t)rbw * 64 + lane;   // K-major
+    constexpr int TRB = 4 * RB;          // row blocks of the tile: the A step stride
+    const double2* a = (const double2*)(A + jb.a_off) + (int64_t)(wave * RB) * 64 + lane;
     const double2* b = (const double2*)(B + jb.b_off) + bpos(lane);
     d4_t acc[RB][CT];
 #pragma unroll
@@ -132,8 +135,9 @@ __device__ inline void gemm_f64_job(const GemmJob& jb,
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const int pw = wrap_k(pb + u, kp8);
+        const int pa = min(u, pe - pb - 1);       // A: step inside the job's stored run
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)pw * mb + r) * 64));
+        for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)pa * TRB + r) * 64));
 #pragma unroll
         for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pw) * 64];
 
@@ -152,9 +156,10 @@ __device__ inline void gemm_f64_job(const GemmJob& jb,
                     for (int c = 0; c < CT; ++c)
                         acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                             h ? ab[u][r].y : ab[u][r].x, h ? bb[u][c].y : bb[u][c].x, acc[r][c], 0, 0, 0);
-            const int pn = wrap_k(min(p0 + u + PF, pe - 1), kp8);
+            const int pl = min(p0 + u + PF, pe - 1);
+            const int pn = wrap_k(pl, kp8);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)pn * mb + r) * 64));
+            for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)(pl - pb) * TRB + r) * 64));
 #pragma unroll
             for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kp8 + pn) * 64];
         }
@@ -194,8 +199,8 @@ __device__ inline void gemm_f32_job(const GemmJob& jb,
     if (rbw >= jb.mb) return;
     const int kq = jb.kp >> 4;
     const int qb = jb.k0 >> 4, qe = jb.k1 >> 4;
-    const int64_t mb = jb.mb;
-    const float4* a = (const float4*)(A + jb.a_off) + (int64_t)rbw * 64 + lane;     // K-major
+    constexpr int TRB = 4 * RB;          // row blocks of the tile: the A step stride
+    const float4* a = (const float4*)(A + jb.a_off) + (int64_t)(wave * RB) * 64 + lane;
     const float4* b = (const float4*)(B + jb.b_off) + bpos(lane);
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
@@ -217,8 +222,9 @@ __device__ inline void gemm_f32_job(const GemmJob& jb,
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const int qw = wrap_k(qb + u, kq);
+        const int qa = min(u, qe - qb - 1);       // A: step inside the job's stored run
 #pragma unroll
-        for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)qw * mb + r) * 64));
+        for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)qa * TRB + r) * 64));
 #pragma unroll
         for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qw) * 64];
 
@@ -239,9 +245,10 @@ __device__ inline void gemm_f32_job(const GemmJob& jb,
                         const float bv = h == 0 ? bb[u][c].x : h == 1 ? bb[u][c].y : h == 2 ? bb[u][c].z : bb[u][c].w;
                         ac32[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, ac32[r][c], 0, 0, 0);
                     }
-            const int qn = wrap_k(min(q0 + u + PF, qe - 1), kq);
+            const int ql = min(q0 + u + PF, qe - 1);
+            const int qn = wrap_k(ql, kq);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)qn * mb + r) * 64));
+            for (int r = 0; r < RB; ++r) ab[u][r] = ld_stream(a + (((int64_t)(ql - qb) * TRB + r) * 64));
 #pragma unroll
             for (int c = 0; c < CT; ++c) bb[u][c] = b[((int64_t)c * kq + qn) * 64];
 
@@ -304,8 +311,8 @@ __device__ inline void gemm_split_job(const GemmJob& jb,
     const int kt = jb.kp >> 5;
     const int tb = jb.k0 >> 5, te = jb.k1 >> 5;
     // 16-byte units: per (block, t): hi run of 64 units then lo run of 64 units
-    const int64_t mb = jb.mb;
-    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)rbw * 128 + lane;      // K-major
+    constexpr int TRB = 4 * RB;          // row blocks of the tile: the A step stride
+    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)(wave * RB) * 128 + lane;
     const VT* b = (const VT*)(B + jb.b_off) + bpos(lane);
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
@@ -327,10 +334,11 @@ __device__ inline void gemm_split_job(const GemmJob& jb,
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const int tw = wrap_k(tb + u, kt);
+        const int ta = min(u, te - tb - 1);       // A: step inside the job's stored run
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128));
-            al[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128 + 64));
+            ah[u][r] = ld_stream(a + (((int64_t)ta * TRB + r) * 128));
+            al[u][r] = ld_stream(a + (((int64_t)ta * TRB + r) * 128 + 64));
         }
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
@@ -359,11 +367,12 @@ __device__ inline void gemm_split_job(const GemmJob& jb,
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
                     ac32[r][c] = mfma_16x16x32(ah[u][r], bh[u][c], ac32[r][c]);
-            const int tn = wrap_k(min(t0 + u + PF, te - 1), kt);
+            const int tl = min(t0 + u + PF, te - 1);
+            const int tn = wrap_k(tl, kt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                ah[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128));
-                al[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128 + 64));
+                ah[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128));
+                al[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128 + 64));
             }
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
@@ -431,8 +440,8 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
     const int rbw = jb.rb0 + wave * RB;
     const int kt = jb.kp >> 5;
     const int tb = jb.k0 >> 5, te = jb.k1 >> 5;    // te - tb is even (K slices of 64 k')
-    const int64_t mb = jb.mb;
-    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)rbw * 128 + lane;      // K-major
+    constexpr int TRB = 4 * RB;          // row blocks of the tile: the A step stride
+    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)(wave * RB) * 128 + lane;
     const VT* b = (const VT*)(B + jb.b_off);
     d4_t acc[RB][CT];
     f4_t ac32[RB][CT];
@@ -468,11 +477,10 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
 #pragma unroll
     for (int u = 0; u < PFA; ++u) {
         const int tl = min(tb + u, te - 1);
-        const int tw = wrap_k(tl, kt);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128));
-            al[u][r] = ld_stream(a + (((int64_t)tw * mb + r) * 128 + 64));
+            ah[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128));
+            al[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128 + 64));
         }
         load_b(br[u], tl);
     }
@@ -511,11 +519,10 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
             }
             // slot u is free (its B went to LDS before this group): refill it PFA ahead
             const int tl = min(t + PFA, te - 1);
-            const int tn = wrap_k(tl, kt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                ah[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128));
-                al[u][r] = ld_stream(a + (((int64_t)tn * mb + r) * 128 + 64));
+                ah[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128));
+                al[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128 + 64));
             }
             load_b(br[u], tl);
             if (((t - tb + 1) % KCH) == 0 || t + 1 == te) {

@@ -1,5 +1,7 @@
 // H-matrix form of the per-mode Green blocks (Appendix C): for every line mode m the
-// complex matrix G^(m) (3 n_b x 3 n_i, taken from an FP64 context's dense store) is split
+// complex matrix G^(m) (3 n_b x 3 n_i, its entries read from the FP64 offset table of a
+// context -- they depend on the column offset n_b - n_i only, Section 3.2 -- so no dense
+// store is needed) is split
 // by the block partition of two cluster trees (binary space partitioning of the in-plane
 // column positions, down to b_min columns; a block t x s is low rank when
 // min(diam t, diam s) <= gamma dist(t, s), eq. geom_adm, on the clusters' bounding boxes,
@@ -118,15 +120,23 @@ struct HBlk {
     int lr;              // index among the low-rank blocks (T workspace)
 };
 
+// Entries of G^(m): the offset table [mode][offset][6] of a one-cell FP64 offset-table
+// context, through its lookup over the bounding box of the column offsets.
 struct HStore {
-    const double* a;     // dense store of mode 0 (FP64, fragment layout)
-    int64_t per_mode;    // mp * kp
-    int mp;
+    const double2* tab;
+    const int32_t* lut;
+    const int32_t* cols_b;   // [n_b][2]
+    const int32_t* cols_i;   // [n_i][2]
+    int64_t n_off;
+    int d1min, d2min, w2;
 };
 
 __device__ inline double2 entry(const HStore& st, int m, int row, int col) {
-    const double* a = st.a + (int64_t)m * st.per_mode;
-    return make_double2(a[frag_off_f64_km(row, 2 * col, st.mp)], a[frag_off_f64_km(row, 2 * col + 1, st.mp)]);
+    const int b = row / 3, c = row - 3 * b, i = col / 3, d = col - 3 * i;
+    const int x = st.cols_b[2 * b] - st.cols_i[2 * i] - st.d1min;
+    const int y = st.cols_b[2 * b + 1] - st.cols_i[2 * i + 1] - st.d2min;
+    const int64_t o = st.lut[(int64_t)x * st.w2 + y];
+    return st.tab[((int64_t)m * st.n_off + o) * 6 + sym_idx(c, d)];
 }
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -438,8 +448,8 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
     if (!out) return hfail(FBC_E_ARG, "out is NULL");
     *out = nullptr;
     if (!ctx || !o) return hfail(FBC_E_ARG, "context and options must not be NULL");
-    if (ctx->opt.form != FBC_FORM_FP64 || ctx->cells.size() != 1)
-        return hfail(FBC_E_UNSUPPORTED, "needs an FBC_FORM_FP64 context of one cell");
+    if (ctx->opt.form != FBC_FORM_DTABLE_FP64 || ctx->cells.size() != 1)
+        return hfail(FBC_E_UNSUPPORTED, "needs an FBC_FORM_DTABLE_FP64 context of one cell");
     if (o->b_min < 1 || o->gamma < 1 || o->gamma > 64 || !(o->eps > 0) || o->max_rank < 1 || o->max_rank > 512)
         return hfail(FBC_E_ARG, "need b_min >= 1, gamma in [1, 64], eps > 0, max_rank in [1, 512]");
     const CellPlan& p = ctx->cells[0];
@@ -452,9 +462,14 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
     h->n_b = p.n_b;
     h->R = p.R;
     h->max_rank = o->max_rank;
-    h->st.a = (const double*)ctx->store + p.a_off;
-    h->st.per_mode = (int64_t)p.mp * p.kp;
-    h->st.mp = p.mp;
+    h->st.tab = ctx->tab;
+    h->st.lut = ctx->lut;
+    h->st.cols_b = p.cols_b_d;
+    h->st.cols_i = p.cols_i_d;
+    h->st.n_off = ctx->n_offsets;
+    h->st.d1min = ctx->d1min;
+    h->st.d2min = ctx->d2min;
+    h->st.w2 = ctx->w2;
     // Steps 1 and 2 on the host
     std::vector<HNode> tb, ti;
     std::vector<int> all_b(p.n_b), all_i(p.n_i);

@@ -27,9 +27,13 @@ void launch_rowmean(hipStream_t st, const double2* tab, double2* rowmean, int nm
 void launch_tab_rhocut(hipStream_t st, const double2* tab, int T, int64_t n_off, const int32_t* d1,
                        const int32_t* d2, double tau, unsigned long long* amax,
                        unsigned long long* rhocut);
+// Compact dense store of one cell (chunk-tiles of the negligible-block windows; see
+// k_build_dense): reg_pre [nm * n_tiles + 1] (prefix sums of the window lengths, in
+// chunk-tiles) and win_start [nm * n_tiles] on the device; n_ct = reg_pre[last].
 void launch_build_dense(hipStream_t st, int form, void* store, const double2* tab,
-                        const double2* rowmean, int nm, int mode_mult, int64_t n_off, int mp,
-                        int kp, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
+                        const double2* rowmean, const int64_t* reg_pre, const int32_t* win_start,
+                        int nm, int n_tiles, int n_chunks, int tile_rows, int64_t n_ct, int mode_mult,
+                        int64_t n_off, int n_b, int n_i, const int32_t* cols_b, const int32_t* cols_i,
                         const int32_t* lut, int d1min, int d2min, int w2, unsigned long long* amax);
 
 // ---- apply (Section 2.3.2 update in line-mode form) ----

@@ -18,7 +18,7 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def _ctx(wl, form="fp64"):
+def _ctx(wl, form="dtable_fp64"):
     from paper_2105_08798_amd import FBC
     return FBC(wl.cells, wl.bz, form=form)
 
@@ -83,10 +83,11 @@ def test_rejects_unsupported_contexts_and_options(small):
     for kw in (dict(b_min=0), dict(gamma=0), dict(eps=0.0), dict(max_rank=0)):
         with pytest.raises(FbcError):
             HMatrix(ctx, **kw)
-    c32 = _ctx(wl, "fp32")
-    with pytest.raises(FbcError):
-        HMatrix(c32)
-    c32.close()
+    for form in ("fp32", "fp64"):        # entries come from the offset table only
+        other = _ctx(wl, form)
+        with pytest.raises(FbcError):
+            HMatrix(other)
+        other.close()
 
 
 def test_medium_geometry_sampled_modes():

@@ -296,6 +296,32 @@ def test_reduced_forms_error_bound(form, bound):
     assert e2 < bound, (form, e2)
 
 
+@pytest.mark.parametrize("form,bound", [("fp32", 1e-6), ("split_fp16", 1e-6)])
+@pytest.mark.parametrize("R", [3, 10])
+def test_rhs_of_very_different_scale(form, bound, R):
+    """RHS whose forces differ by many orders of magnitude in one call (a converged
+    residual beside one that is not, as in a batched Algorithm 1 loop): every RHS keeps
+    its own relative error.  The split-FP16 operand scale is per RHS."""
+    _dev()
+    wl = W.make_custom(16, 60, 100, R, 32, seed=31)
+    c = wl.cells[0]
+    scales = np.array([1.0, 1e-4, 1e-8, 1e-2, 1e-6][:R] + [10.0 ** (-k) for k in range(max(0, R - 5))])
+    c.forces = np.ascontiguousarray(c.forces * scales[:, None, None, None])
+    dev = _dev()
+    ctx = _ctx(wl.cells, wl.bz, form=form)
+    f = torch.from_numpy(c.forces).to(dev)
+    w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+    ctx.green_apply(f, w)
+    assert ctx.sync_status() == 0
+    ctx.close()
+    got = w.cpu().numpy()
+    ref = oap.apply_green(oracle_green(c, wl.bz), c.forces)
+    for r in range(R):
+        e2, emax = rel_err(got[r:r + 1], ref[r:r + 1])
+        print(f"{form} R={R} rhs {r} scale {scales[r]:.0e}: rel err {e2:.2e}", flush=True)
+        assert e2 < bound and emax < 3 * bound, (form, r, scales[r], e2, emax)
+
+
 def test_repeated_apply_is_bitwise_reproducible():
     wl = W.make_single("parity")
     dev = _dev()
