@@ -5,7 +5,14 @@ One step = one fbc_apply call: for every RHS of the cell, u <- u - G^{p|i+} f fo
 by mean removal (net-force check, line rFFT, per-mode products, inverse rFFT, update,
 mean), with f and u resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload medium] [--forms fp64,fp32,split_bf16,split_fp16,surrogate]
+Default run (no flags): the headline on the long workload (N_z = 1024, n_i = 4096,
+n_b = 8192, 16 RHS: the largest configuration, where the dense blocks would take 2.49 TB;
+plain FP64 is the offset-table form there), with the forms FP64 offset table, FP32,
+split FP16, split BF16 and the learned far field; the same line carries the large
+workload (N_z = 256, n_i = 2048, n_b = 4096, 64 RHS: the precision form's configuration)
+with the forms FP64, FP32, split BF16 and split FP16.
+
+    python bench.py [--steps K] [--warmup W] [--workload long|large|medium|batched|plgf|hmat] [--forms ...]
 """
 from __future__ import annotations
 
@@ -22,36 +29,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FBC boundary updates/sec + % MFMA/HBM roofline vs FP64 plain at 1e-6 rel err"
 HBM_PEAK_GBS = 8000.0
+# dense MFMA peak of the arithmetic each product runs on (TFLOP/s; the split forms run
+# three BF16 / FP16 products per algorithmic one)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0, "dtable_fp64": 78.6,
                "surrogate": 78.6}
-# bytes per complex entry of the stored G^ and of the B operand, per form (the offset
-# table form reads its table, whose size the library reports, instead of dense blocks)
-G_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "split_fp16": 8, "dtable_fp64": None, "surrogate": None}
+MFMA_PER_ALG = {"split_bf16": 3.0, "split_fp16": 3.0}
 F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "split_fp16": 8, "dtable_fp64": 16, "surrogate": 16}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16 hi+lo (fp32 acc)",
          "split_fp16": "fp16 hi+lo, power-of-two scaled (fp32 acc)", "dtable_fp64": "f64",
          "surrogate": "f64 (generated table; bf16-weight MLP, fp32 acc)"}
+FP64_FORMS = ("fp64", "dtable_fp64")
+DEFAULT_FORMS = {"long": ["dtable_fp64", "fp32", "split_fp16", "split_bf16", "surrogate"],
+                 "large": ["fp64", "fp32", "split_bf16", "split_fp16"],
+                 "medium": ["fp64", "fp32", "split_bf16", "split_fp16", "surrogate"],
+                 "batched": ["dtable_fp64"]}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(cells, form: str, store_bytes: int) -> dict:
-    """Algorithmic bytes and flops of one product launch and of one whole call, summed
-    over the cells of the context."""
-    g_all = fh_all = uh_all = fl_all = fu_all = 0.0
-    for cell in cells:
-        nm = cell.nz // 2 + 1
-        M, K, R = 3 * cell.n_b, 3 * cell.n_i, cell.n_rhs
-        g_all += nm * M * K * G_BYTES[form] if G_BYTES[form] else 0
-        fh_all += nm * R * K * F_BYTES[form]
-        uh_all += nm * R * M * 16
-        fl_all += 8.0 * nm * M * K * R
-        fu_all += R * cell.nz * K * 8 + 2 * R * cell.nz * M * 8
-    if not G_BYTES[form]:
-        g_all = store_bytes
-    return dict(gemm_bytes=g_all + fh_all + uh_all, gemm_flops=fl_all, call_bytes=g_all + fu_all)
+def io_bytes(cells, form: str) -> dict:
+    """Bytes of the caller's arrays (f read, u read and written) and of the product's
+    intermediate operands (f^ in, w^ out: R (3 n_i) and R (3 n_b) complex per mode)."""
+    fu = fh = 0.0
+    for c in cells:
+        nm = c.nz // 2 + 1
+        fu += c.n_rhs * c.nz * 3 * c.n_i * 8 + 2 * c.n_rhs * c.nz * 3 * c.n_b * 8
+        fh += nm * c.n_rhs * (3 * c.n_i * F_BYTES[form] + 3 * c.n_b * 16)
+    return dict(fu=fu, fhat_what=fh)
 
 
 def kernel_matches(form: str, name: str) -> bool:
@@ -63,9 +69,9 @@ def kernel_matches(form: str, name: str) -> bool:
     if form == "fp32":
         return name.startswith("k_gemm_f32<")
     if form == "split_bf16":
-        return name.startswith("k_gemm_split<bf16x8")
+        return name.startswith("k_gemm_split") and "bf16" in name
     if form == "split_fp16":
-        return name.startswith("k_gemm_split<f16x8")
+        return name.startswith("k_gemm_split") and "f16x8" in name
     return name.startswith("k_gemm_dtab<")
 
 
@@ -82,19 +88,11 @@ def measured_traffic(workload: str, form: str, product_bytes: float):
     if hashlib.sha256(src).hexdigest() != t.get("gemm_source_sha256"):
         return None
     for name, v in t["kernels"].items():
-        if kernel_matches(form, name):
+        if kernel_matches(form, name) and v.get("form", form) == form:
             if v.get("algorithmic_bytes") != product_bytes:
                 return None
             return v["traffic_bytes"]
     return None
-
-
-def rel_err(got: np.ndarray, ref: np.ndarray) -> float:
-    """max over RHS of ||got - ref||_2 / ||ref||_2"""
-    n = ref.shape[0]
-    g = got.reshape(n, -1)
-    r = ref.reshape(n, -1)
-    return float((np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)).max())
 
 
 def train_surrogate(torch, wl, steps: int, seed: int = 0):
@@ -139,9 +137,31 @@ def train_surrogate(torch, wl, steps: int, seed: int = 0):
     return sur, info
 
 
-def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: bool,
-              train_steps: int = 20000) -> dict:
-    from paper_2105_08798_amd import FBC
+def golden(name: str):
+    """Stored oracle samples of a workload: ('cols', npz) -- w at pad columns, every layer --
+    or ('modes', npz) -- the line spectrum at sampled modes and pad columns -- or None."""
+    for kind in ("samples", "modes"):
+        p = os.path.join(ROOT, "tests", "golden", f"{name}_{kind}.npz")
+        if os.path.exists(p):
+            return ("cols" if kind == "samples" else "modes"), np.load(p)
+    return None
+
+
+def unbalanced_forces(c, seed: int = 5) -> np.ndarray:
+    """The relaxation loop's incompatibility forces carry net force per layer (their cell
+    total vanishes): the workload's forces plus a per-layer constant whose sum over the
+    layers is zero."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(0.0, 0.05, size=(c.n_rhs, c.nz, 1, 3))
+    v -= v.mean(axis=1, keepdims=True)
+    return np.ascontiguousarray(c.forces + v)
+
+
+def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: bool, keep_cols,
+              train_steps: int = 20000, extras: bool = False) -> tuple[dict, np.ndarray | None]:
+    """Times `steps` fbc_apply calls after `warmup`; returns the timings and the raw response
+    w = G f at the pad columns keep_cols (every layer; one-cell workloads) or in full."""
+    from paper_2105_08798_amd import FBC, RELAX_OUT_DOUBLES
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream() if graph else None
     sur = sur_info = None
@@ -164,11 +184,11 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
         log(f"{form}: autotuned work list {tuned}")
     ctx.timing(True)
 
-    def step():
+    def step(ff=f):
         if graph:
-            ctx.apply_graph(f, u, alpha=1.0, stream=stream)
+            ctx.apply_graph(ff, u, alpha=1.0, stream=stream)
         else:
-            ctx.apply(f, u, alpha=1.0)
+            ctx.apply(ff, u, alpha=1.0)
 
     for _ in range(warmup):
         step()
@@ -190,6 +210,33 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
             ctx.apply(f, u, alpha=1.0)
         gemm_ms, n_gemm = ctx.timing_read()
     ctx.timing(False)
+    extra = {}
+    if extras and len(wl.cells) == 1 and not graph:
+        # the relaxation loop's forces (net force per layer, zero cell total): the update
+        # adds the exact row-gauge compensation; and one fbc_relax_step per iteration
+        c = wl.cells[0]
+        fu = torch.from_numpy(unbalanced_forces(c)).to(dev)
+        for _ in range(2):
+            step(fu)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(fu)
+        torch.cuda.synchronize()
+        extra["unbalanced_ms_per_step"] = 1000.0 * (time.perf_counter() - t0) / steps
+        out = torch.zeros(c.n_rhs * RELAX_OUT_DOUBLES, dtype=torch.float64, device=dev)
+        ctx.relax_begin(relax=True, du_max=0.0, tol_f=1e-12)
+        for _ in range(3):
+            ctx.relax_step(fu, u, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.relax_step(fu, u, out)
+        torch.cuda.synchronize()
+        extra["relax_step_ms"] = 1000.0 * (time.perf_counter() - t0) / steps
+        del fu, out
+        log(f"{form}: unbalanced forces {extra['unbalanced_ms_per_step']:.3f} ms/step, "
+            f"relax step {extra['relax_step_ms']:.3f} ms")
     store_bytes = ctx.info.store_bytes
     prod = dict(bytes=ctx.info.product_bytes, flops=ctx.info.product_flops,
                 skipped_fraction=ctx.info.skipped_fraction)
@@ -199,7 +246,12 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     w = torch.zeros_like(u)
     ctx.green_apply(f, w)
     torch.cuda.synchronize()
-    w_host = w.cpu().numpy()
+    if keep_cols is not None and len(wl.cells) == 1:
+        c = wl.cells[0]
+        idx = torch.from_numpy(np.asarray(keep_cols)).to(dev)
+        w_keep = w.view(c.n_rhs, c.nz, c.n_b, 3)[:, :, idx, :].cpu().numpy()
+    else:
+        w_keep = w.cpu().numpy()
     ctx.close()
     if sur is not None:
         sur.close()
@@ -210,58 +262,83 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     out = dict(ms_per_step=ms, updates_per_s=total_rhs / (ms / 1000.0), assembly_s=t_asm,
                store_bytes=int(store_bytes), autotune=tuned,
                gemm_ms=(gemm_ms / n_gemm) if n_gemm else None, gemm_launches_timed=n_gemm,
-               graph=bool(graph), surrogate_training=sur_info, product=prod)
+               graph=bool(graph), surrogate_training=sur_info, product=prod, **extra)
     log(f"{form}: {ms:.3f} ms/step, GEMM {out['gemm_ms']} ms, {out['updates_per_s']:.1f} updates/s")
-    return out, w_host
+    return out, w_keep
 
 
-def cell_view(wl, flat: np.ndarray, k: int) -> np.ndarray:
-    off = 0
-    for j, c in enumerate(wl.cells):
-        n = c.n_rhs * c.nz * c.n_b * 3
-        if j == k:
-            return flat[off:off + n].reshape(c.n_rhs, c.nz, c.n_b, 3)
-        off += n
-    raise IndexError(k)
+def rel_err(got: np.ndarray, ref: np.ndarray) -> float:
+    """max over RHS of ||got - ref||_2 / ||ref||_2"""
+    n = ref.shape[0]
+    g = got.reshape(n, -1)
+    r = ref.reshape(n, -1)
+    return float((np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)).max())
 
 
-def cpu_baseline(wl, n_modes: int) -> dict:
-    """The FP64 oracle (NumPy/pocketfft/BLAS) on a bounded sample: a few line modes of the
-    same workload are assembled (untimed), their per-mode products timed, and the time
-    of the full call is extrapolated to all modes; the line transforms are timed in full."""
+def oracle_error(kind: str, gold, w_cols: np.ndarray) -> float:
+    """Error of the GPU response at the golden columns against the oracle: relative per RHS
+    over every sampled value (w itself, or its line spectrum at the sampled modes)."""
+    if kind == "cols":
+        return rel_err(w_cols, gold["w"])
+    spec = np.fft.rfft(w_cols, axis=1)[:, gold["modes"]]
+    return rel_err(spec, gold["what"])
+
+
+def cpu_baseline(wl, name: str) -> dict:
+    """The FP64 oracle (NumPy pocketfft and BLAS) timed on a bounded sample of the same
+    workload: one line mode's product (all pad rows, all RHS; its blocks assembled
+    untimed) and the line transforms and update of one RHS, each the median of 5 runs after
+    a warm-up, scaled to the whole call (products x modes, transforms x RHS).  Also with
+    BLAS on one thread (product on one eighth of the rows, median of 3 after a warm-up)."""
     from oracle import apply as oap, green as ogr
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [os.cpu_count()])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count()
     c = wl.cells[0]
     nm = c.nz // 2 + 1
-    modes = np.unique(np.linspace(0, nm - 1, n_modes).round().astype(int))
-    gm = {m: ogr.dense_mode_matrix(ogr.gather_blocks(ogr.line_mode_green(c.nz, wl.bz, wl.bz, int(m)),
-                                                     c.cols_b, c.cols_i)) for m in modes}
-    reps = 3
-    t_fft = []
-    t_mode = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        fh = oap.line_rfft(c.forces).reshape(c.n_rhs, nm, 3 * c.n_i)
-        t1 = time.perf_counter()
-        wh = np.zeros((c.n_rhs, nm, 3 * c.n_b), dtype=np.complex128)
-        for m in modes:
-            wh[:, m, :] = (gm[m] @ fh[:, m, :].T).T
-        t2 = time.perf_counter()
-        w = oap.line_irfft(wh.reshape(c.n_rhs, nm, c.n_b, 3), c.nz)
-        un, _ = oap.pad_update(np.zeros_like(w), w, 1.0)
-        t3 = time.perf_counter()
-        t_fft.append((t1 - t0) + (t3 - t2))
-        t_mode.append((t2 - t1) / len(modes))
-    t_call = float(np.median(t_fft) + np.median(t_mode) * nm)
-    return dict(value=c.n_rhs / t_call, unit="FBC updates/s", cores=int(cores), kind="oracle",
-                sample=f"{len(modes)} of {nm} line modes assembled and applied (median of {reps}), "
-                       f"per-mode product time x {nm} modes + full line transforms and update; "
-                       f"extrapolated call time {t_call:.3f} s",
-                cpu=_cpu_model())
+    m = nm // 3
+    t0 = time.perf_counter()
+    gm = ogr.dense_mode_matrix(ogr.gather_blocks(ogr.line_mode_green(c.nz, wl.bz, wl.bz, m), c.cols_b, c.cols_i))
+    t_asm = time.perf_counter() - t0
+    x = np.ascontiguousarray(oap.line_rfft(c.forces[:, :, :, :])[:, m].reshape(c.n_rhs, 3 * c.n_i).T)
+
+    def med(fn, reps):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    t_prod = med(lambda: gm @ x, 5)
+    f1 = c.forces[:1]
+    u1 = np.zeros((1, c.nz, c.n_b, 3))
+    wh1 = np.ones((1, nm, c.n_b, 3), dtype=np.complex128)
+
+    def transforms():
+        oap.line_rfft(f1)
+        oap.pad_update(u1, oap.line_irfft(wh1, c.nz), 1.0)
+
+    t_tr = med(transforms, 5)
+    t_call = t_prod * nm + t_tr * c.n_rhs
+    out = dict(value=c.n_rhs / t_call, unit="FBC updates/s", cores=int(cores), kind="oracle",
+               sample=f"{name}: line mode {m} of {nm} (its blocks assembled untimed in {t_asm:.1f} s), product "
+                      f"of all {3 * c.n_b} rows x {c.n_rhs} RHS, median of 5 after a warm-up, x {nm} modes; "
+                      f"line transforms + update of 1 RHS, median of 5, x {c.n_rhs} RHS; call {t_call:.2f} s",
+               cpu=_cpu_model())
+    if threadpool_limits is not None:
+        rows = max(1, gm.shape[0] // 8)
+        gs = np.ascontiguousarray(gm[:rows])
+        with threadpool_limits(limits=1):
+            t1 = med(lambda: gs @ x, 3) * gm.shape[0] / rows
+        t_call1 = t1 * nm + t_tr * c.n_rhs
+        out["value_1thread"] = c.n_rhs / t_call1
+        out["sample_1thread"] = f"product of {rows} of {gm.shape[0]} rows on one BLAS thread, median of 3, scaled"
+    return out
 
 
 def _cpu_model() -> str:
@@ -272,6 +349,80 @@ def _cpu_model() -> str:
     except Exception:
         pass
     return "unknown"
+
+
+def roofline_of(form: str, r: dict) -> dict:
+    """Roofline of the product kernel of one form: algorithmic bytes (the stored blocks it
+    does not skip, f^ and w^) or flops (8 per complex multiply-add of those blocks) per
+    launch over its average launch time, against the roof its arithmetic intensity puts it
+    under."""
+    gm = r["gemm_ms"]
+    b, fl = r["product"]["bytes"], r["product"]["flops"]
+    gbs = b / (gm * 1e-3) / 1e9
+    tfs = fl / (gm * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[form]
+    mfma_bound = fl * MFMA_PER_ALG.get(form, 1.0) / b > peak * 1e3 / HBM_PEAK_GBS
+    if mfma_bound:
+        return dict(bound="mfma", achieved=tfs, peak=peak, unit="TFLOP/s", frac=tfs / peak,
+                    flops_per_launch=fl, bytes_per_launch=b)
+    return dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                bytes_per_launch=b, flops_per_launch=fl)
+
+
+def run_workload(torch, args, name: str, forms: list, extras_for=None) -> dict:
+    """Every form of one workload; errors against the oracle's stored samples (and against
+    the workload's FP64 form at the same columns)."""
+    import fbc_workloads as W
+    wl = W.make_batched() if name == "batched" else W.make_single(name)
+    log(f"workload {name}: {wl.description}, M={wl.bz}")
+    g = golden(name) if len(wl.cells) == 1 else None
+    keep = g[1]["cols"] if g else None
+    if g is not None:
+        import hashlib
+        dg = hashlib.sha256(np.ascontiguousarray(wl.cells[0].forces).tobytes()).hexdigest()
+        if str(g[1]["digest"]) != dg:
+            log(f"{name}: stored oracle samples do not match the seeded forces; ignored")
+            g, keep = None, None
+    res = {}
+    for form in forms:
+        r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph,
+                         not args.no_autotune and form != "surrogate", keep, args.train_steps,
+                         extras=(form == extras_for))
+        r["w"] = w
+        res[form] = r
+    ref_form = next((f for f in FP64_FORMS if f in res), None)
+    out_forms = {}
+    for form, r in res.items():
+        io = io_bytes(wl.cells, form)
+        e_fp64 = None
+        if ref_form is not None:
+            e_fp64 = 0.0 if form == ref_form else rel_err(r["w"], res[ref_form]["w"]) \
+                if len(wl.cells) == 1 else None
+        e_or = oracle_error(g[0], g[1], r["w"]) if g is not None else None
+        roof = roofline_of(form, r) if r["gemm_ms"] else None
+        g_kept = r["product"]["bytes"] - io["fhat_what"] if form not in ("dtable_fp64", "surrogate") else None
+        out_forms[form] = dict(
+            updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"], gemm_ms=r["gemm_ms"],
+            roofline=roof, rel_err_vs_oracle=e_or, oracle_samples=(g[0] if g else None),
+            rel_err_vs_fp64_gpu=e_fp64, rel_err_reference=ref_form,
+            call_GBs=((g_kept + io["fu"]) / (r["ms_per_step"] * 1e-3) / 1e9) if g_kept is not None else None,
+            assembly_s=r["assembly_s"], graph=r["graph"], store_GB=r["store_bytes"] / 1e9,
+            autotune=r["autotune"], surrogate_training=r["surrogate_training"],
+            skipped_fraction=r["product"]["skipped_fraction"], product_bytes=r["product"]["bytes"],
+            product_flops=r["product"]["flops"],
+            **{k: r[k] for k in ("unbalanced_ms_per_step", "relax_step_ms") if k in r})
+        if roof:
+            log(f"{name}/{form}: {r['updates_per_s']:.1f} updates/s, product {roof['achieved']:.1f} {roof['unit']} "
+                f"({roof['frac']:.2f} of {roof['bound']}), err vs oracle {e_or}")
+
+    def err_of(f):
+        e = out_forms[f]["rel_err_vs_oracle"]
+        return out_forms[f]["rel_err_vs_fp64_gpu"] if e is None else e
+
+    ok = [f for f in out_forms if err_of(f) is not None and err_of(f) <= 1e-6] or \
+         [f for f in out_forms if f in FP64_FORMS]
+    head = max(ok, key=lambda f: out_forms[f]["updates_per_s"]) if ok else forms[0]
+    return dict(wl=wl, forms=out_forms, head=head, err_of=err_of, ref_form=ref_form)
 
 
 # Real-space periodic Green function (fbc_plgf_eval): algorithmic FP64 flops of one
@@ -442,17 +593,17 @@ def bench_hmat(args, torch) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="medium")
-    ap.add_argument("--forms", default=None,
-                    help="default fp64,fp32,split_bf16,split_fp16,surrogate (dtable_fp64 for the batched workload)")
+    ap.add_argument("--workload", default=None,
+                    help="one workload only (long, large, medium, batched, plgf, hmat); default: long "
+                         "(headline) and large in one line")
+    ap.add_argument("--forms", default=None, help="comma-separated forms of the headline workload")
     ap.add_argument("--graph", action="store_true", help="replay the update from a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default work list (the library's autotuner picks K slices and order otherwise)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000, help="Adam steps of the surrogate's MLP")
-    ap.add_argument("--cpu-modes", type=int, default=3)
     ap.add_argument("--max-rank", type=int, default=64, help="rank bound of the H-matrix workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM byte counters)")
@@ -464,7 +615,6 @@ def main() -> int:
         return 2
 
     import torch
-    import fbc_workloads as W
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
@@ -474,11 +624,6 @@ def main() -> int:
     if args.workload == "hmat":
         print(json.dumps(bench_hmat(args, torch)), flush=True)
         return 0
-    wl = W.make_batched() if args.workload == "batched" else W.make_single(args.workload)
-    if args.forms is None:
-        args.forms = "dtable_fp64" if args.workload == "batched" else "fp64,fp32,split_bf16,split_fp16,surrogate"
-    forms = [s for s in args.forms.split(",") if s]
-    log(f"workload {args.workload}: {wl.description}, M={wl.bz}")
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
@@ -488,81 +633,47 @@ def main() -> int:
         log("copy calibration: 1 GiB read + 1 GiB write")
         del a, b
 
-    res = {}
-    ref_w = None
-    for form in forms:
-        r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph,
-                         not args.no_autotune and form != "surrogate", args.train_steps)
-        r["w"] = w
-        res[form] = r
-    # reference result: plain FP64, else the FP64 offset table (both exact up to rounding)
-    ref_form = "fp64" if "fp64" in res else ("dtable_fp64" if "dtable_fp64" in res else None)
-    ref_w = res[ref_form]["w"] if ref_form else None
-    samples = os.path.join(ROOT, "tests", "golden", f"{args.workload}_samples.npz")
-    gold = np.load(samples) if (os.path.exists(samples) and len(wl.cells) == 1) else None
-    out_forms = {}
-    for form, r in res.items():
-        alg = algorithmic(wl.cells, form, r["store_bytes"])
-        if r.get("product") and r["product"]["bytes"] > 0:
-            # the library's count over the blocks it does not skip (negligible-block windows)
-            alg["gemm_bytes"] = r["product"]["bytes"]
-            alg["gemm_flops"] = r["product"]["flops"]
-        e_fp64 = None
-        if ref_w is not None and form != ref_form:
-            e_fp64 = max(rel_err(cell_view(wl, r["w"], k), cell_view(wl, ref_w, k)) for k in range(len(wl.cells)))
-        elif form == ref_form:
-            e_fp64 = 0.0
-        e_or = None
-        if gold is not None:
-            e_or = rel_err(cell_view(wl, r["w"], 0)[:, :, gold["cols"], :], gold["w"])
-        gm = r["gemm_ms"]
-        gemm_gbs = alg["gemm_bytes"] / (gm * 1e-3) / 1e9 if gm else None
-        gemm_tfs = alg["gemm_flops"] / (gm * 1e-3) / 1e12 if gm else None
-        out_forms[form] = dict(
-            updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"], gemm_ms=gm,
-            gemm_GBs=gemm_gbs, gemm_TFs=gemm_tfs,
-            gemm_hbm_frac=(gemm_gbs / HBM_PEAK_GBS) if gemm_gbs else None,
-            gemm_mfma_frac=(gemm_tfs / PEAK_TFLOPS[form]) if gemm_tfs else None,
-            call_GBs=alg["call_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9,
-            rel_err_vs_fp64_gpu=e_fp64, rel_err_reference=ref_form, rel_err_vs_oracle_samples=e_or,
-            assembly_s=r["assembly_s"], graph=r["graph"], store_GB=r["store_bytes"] / 1e9,
-            autotune=r["autotune"], surrogate_training=r["surrogate_training"],
-            skipped_fraction=r["product"]["skipped_fraction"], product_bytes=alg["gemm_bytes"],
-            product_flops=alg["gemm_flops"])
-    def err_of(f):
-        e = out_forms[f]["rel_err_vs_oracle_samples"]
-        if e is None:
-            e = out_forms[f]["rel_err_vs_fp64_gpu"]
-        return e
-
-    # FP64 forms are exact up to rounding (checked against the oracle by the test suite)
-    ok = [f for f in out_forms if f in ("fp64", "dtable_fp64") or (err_of(f) is not None and err_of(f) <= 1e-6)]
-    head = max(ok, key=lambda f: out_forms[f]["updates_per_s"]) if ok else forms[0]
+    name = args.workload or "long"
+    forms = [s for s in (args.forms or ",".join(DEFAULT_FORMS[name])).split(",") if s]
+    main_run = run_workload(torch, args, name, forms)
+    second = None
+    if args.workload is None:
+        second = run_workload(torch, args, "large", DEFAULT_FORMS["large"], extras_for="split_fp16")
+    wl, out_forms, head = main_run["wl"], main_run["forms"], main_run["head"]
     h = out_forms[head]
-    alg = dict(gemm_bytes=h["product_bytes"], gemm_flops=h["product_flops"])
-    traffic = measured_traffic(args.workload, head, h["product_bytes"])
-    roof = dict(bound="hbm", achieved=h["gemm_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=h["gemm_hbm_frac"], traffic=traffic, kernel=f"k_gemm ({head})",
-                bytes_per_launch=alg["gemm_bytes"])
-    if alg["gemm_flops"] / alg["gemm_bytes"] > PEAK_TFLOPS[head] * 1e3 / HBM_PEAK_GBS:
-        roof = dict(bound="mfma", achieved=h["gemm_TFs"], peak=PEAK_TFLOPS[head], unit="TFLOP/s",
-                    frac=h["gemm_mfma_frac"], traffic=traffic, kernel=f"k_gemm ({head})",
-                    flops_per_launch=alg["gemm_flops"])
+    ref = main_run["ref_form"]
+    roof = dict(h["roofline"])
+    roof["traffic"] = measured_traffic(name, head, h["product_bytes"])
+    roof["kernel"] = f"per-mode product ({head})"
     line = {
         "metric": METRIC, "value": h["updates_per_s"], "unit": "FBC updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": h["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[head],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl.description}, in-plane torus M={wl.bz}",
-                   "form": head, "rel_err": err_of(head), "graph": bool(args.graph),
-                   "fp64_plain_updates_per_s": out_forms.get("fp64", {}).get("updates_per_s"),
-                   "speedup_vs_fp64_plain": (h["updates_per_s"] / out_forms["fp64"]["updates_per_s"]) if "fp64" in out_forms else None},
+        "config": {"workload": f"{name}: {wl.description}, in-plane torus M={wl.bz}",
+                   "form": head, "rel_err": main_run["err_of"](head),
+                   "rel_err_kind": ("vs the FP64 oracle at sampled line modes and pad columns"
+                                    if h["oracle_samples"] == "modes" else
+                                    "vs the FP64 oracle at sampled pad columns" if h["oracle_samples"] else
+                                    "vs the FP64 form on the GPU"),
+                   "graph": bool(args.graph), "fp64_plain_form": ref,
+                   "fp64_plain_updates_per_s": out_forms[ref]["updates_per_s"] if ref else None,
+                   "speedup_vs_fp64_plain": (h["updates_per_s"] / out_forms[ref]["updates_per_s"]) if ref else None},
         "roofline": roof,
         "forms": out_forms,
     }
+    if second is not None:
+        s2 = second["forms"]
+        sref = second["ref_form"]
+        line["large"] = {"workload": f"large: {second['wl'].description}, in-plane torus M={second['wl'].bz}",
+                         "fastest_within_1e-6": second["head"], "fp64_plain_form": sref,
+                         "speedup_vs_fp64_plain": (s2[second["head"]]["updates_per_s"] / s2[sref]["updates_per_s"])
+                         if sref else None, "forms": s2}
     if not args.no_cpu and len(wl.cells) == 1:
         log("timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_modes)
+        line["cpu_baseline"] = cpu_baseline(wl, name)
+        if second is not None:
+            line["large"]["cpu_baseline"] = cpu_baseline(second["wl"], "large")
     print(json.dumps(line), flush=True)
     return 0
 

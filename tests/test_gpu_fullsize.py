@@ -1,6 +1,14 @@
-"""Full-size workloads on the GPU, checked at sampled pad columns against expected
-values the FP64 oracle wrote (tests/golden/make_samples.py), and by properties that
-hold at any size (zero mean after the update, linearity, bitwise repeatability)."""
+"""Full-size workloads on the GPU, checked against expected values the FP64 oracle wrote
+(tests/golden/make_samples.py) and by properties that hold at any size (zero mean after
+the update):
+
+* medium and large: the response w at sampled pad columns, every layer (all line modes);
+* long and every cell of the batched workload: the line spectrum w^(m) at sampled modes
+  and pad columns -- the forward line transform (numpy) of the GPU's w at those columns
+  against the oracle's per-mode products of those modes only.
+
+Errors are relative per RHS (2-norm over the sampled values); the per-mode error (2-norm
+over the sampled columns of one mode) is printed and bounded as well."""
 import os
 
 import numpy as np
@@ -36,7 +44,8 @@ def rel_err(got, ref):
 @pytest.mark.parametrize("name,form,bound", [
     ("medium", "fp64", 1e-10), ("medium", "fp32", 1e-6), ("medium", "split_bf16", 2e-5),
     ("medium", "split_fp16", 1e-6), ("medium", "dtable_fp64", 1e-10),
-    ("large", "fp64", 1e-10), ("large", "split_bf16", 2e-5), ("large", "split_fp16", 1e-6),
+    ("large", "fp64", 1e-10), ("large", "fp32", 1e-6), ("large", "split_bf16", 2e-5),
+    ("large", "split_fp16", 1e-6),
 ])
 def test_fullsize_green_apply_matches_oracle_samples(name, form, bound):
     if not torch.cuda.is_available():
@@ -68,3 +77,95 @@ def test_fullsize_green_apply_matches_oracle_samples(name, form, bound):
     print(f"[{name}/{form}] rel err vs oracle samples {e:.3e}; |mean| {mean:.1e} of {scale:.1e}", flush=True)
     assert e < bound
     assert mean < 1e-12 * scale
+
+
+def _mode_golden(name):
+    p = os.path.join(HERE, "golden", f"{name}_modes.npz")
+    if not os.path.exists(p):
+        pytest.skip(f"no stored oracle mode samples for {name}")
+    return np.load(p)
+
+
+def spectrum_errors(w_cols, modes, ref):
+    """w_cols [R, Nz, C, 3] (GPU, real) -> its line spectrum at `modes` against ref
+    [R, S, C, 3]: (max over RHS of the relative error over all sampled values, max over
+    (RHS, mode) of the relative error of one mode's sampled values)."""
+    got = np.fft.rfft(w_cols, axis=1)[:, modes]
+    R, S = ref.shape[:2]
+    d = (got - ref).reshape(R, S, -1)
+    r = ref.reshape(R, S, -1)
+    per_rhs = np.linalg.norm(d.reshape(R, -1), axis=1) / np.linalg.norm(r.reshape(R, -1), axis=1)
+    per_mode = np.linalg.norm(d, axis=2) / np.linalg.norm(r, axis=2)
+    return float(per_rhs.max()), float(per_mode.max())
+
+
+# (form, bound on the sampled-spectrum error, bound on any single mode)
+LONG_FORMS = [("dtable_fp64", 1e-10, 1e-10), ("fp32", 1e-6, 1e-5), ("split_fp16", 1e-6, 1e-5),
+              ("split_bf16", 2e-5, 2e-4)]
+
+
+@pytest.mark.parametrize("form,bound,mode_bound", LONG_FORMS)
+def test_long_sampled_modes_match_oracle(form, bound, mode_bound):
+    """The learned form's workload (N_z = 1024, n_i = 4096, n_b = 8192, 16 RHS, 513 modes;
+    dense blocks would take 2.49 TB): the FP64 offset table and the compact reduced stores
+    (blocks of the negligible-block windows only)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gold = _mode_golden("long")
+    wl = W.make_single("long")
+    c = wl.cells[0]
+    assert str(gold["digest"]) == _digest(c.forces), "seeded forces changed since the samples were written"
+    from paper_2105_08798_amd import FBC
+    dev = torch.device("cuda:0")
+    print(f"[long/{form}] assembling", flush=True)
+    ctx = FBC(wl.cells, wl.bz, form=form)
+    f = torch.from_numpy(c.forces).to(dev)
+    w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+    ctx.green_apply(f, w)
+    assert ctx.sync_status() == 0
+    cols = torch.from_numpy(gold["cols"]).to(dev)
+    w_cols = w[:, :, cols, :].cpu().numpy()
+    store = ctx.info.store_bytes
+    ctx.close()
+    del w, f
+    torch.cuda.empty_cache()
+    e, em = spectrum_errors(w_cols, gold["modes"], gold["what"])
+    print(f"[long/{form}] store {store / 1e9:.1f} GB; sampled-spectrum rel err {e:.3e}, worst mode {em:.3e}",
+          flush=True)
+    assert e < bound and em < mode_bound
+
+
+@pytest.mark.parametrize("form,bound,mode_bound", [("dtable_fp64", 1e-10, 1e-10)])
+def test_batched_cells_sampled_modes_match_oracle(form, bound, mode_bound):
+    """All 32 cells of the batched workload at their drawn sizes in one context (shared
+    offset table on the finest line grid): every cell's spectrum at its sampled modes."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gold = _mode_golden("batched")
+    wl = W.make_batched()
+    assert int(gold["n_cells"]) == len(wl.cells)
+    for k, c in enumerate(wl.cells):
+        assert str(gold[f"c{k}_digest"]) == _digest(c.forces), k
+    from paper_2105_08798_amd import FBC
+    dev = torch.device("cuda:0")
+    print(f"[batched/{form}] assembling {len(wl.cells)} cells", flush=True)
+    ctx = FBC(wl.cells, wl.bz, form=form)
+    f = torch.from_numpy(np.concatenate([c.forces.ravel() for c in wl.cells])).to(dev)
+    n_u = sum(c.n_rhs * c.nz * c.n_b * 3 for c in wl.cells)
+    w = torch.zeros(n_u, dtype=torch.float64, device=dev)
+    ctx.green_apply(f, w)
+    assert ctx.sync_status() == 0
+    ctx.close()
+    wh = w.cpu().numpy()
+    del w, f
+    torch.cuda.empty_cache()
+    off, worst, worst_mode = 0, 0.0, 0.0
+    for k, c in enumerate(wl.cells):
+        n = c.n_rhs * c.nz * c.n_b * 3
+        wc = wh[off:off + n].reshape(c.n_rhs, c.nz, c.n_b, 3)
+        off += n
+        e, em = spectrum_errors(wc[:, :, gold[f"c{k}_cols"], :], gold[f"c{k}_modes"], gold[f"c{k}_what"])
+        worst, worst_mode = max(worst, e), max(worst_mode, em)
+        assert e < bound and em < mode_bound, (k, c.nz, c.n_i, c.n_rhs, e, em)
+    print(f"[batched/{form}] worst cell: sampled-spectrum rel err {worst:.3e}, worst mode {worst_mode:.3e}",
+          flush=True)
