@@ -174,7 +174,9 @@ fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alph
  * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times the orders:
  * 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first, 3
  * persistent (jobs longest first, taken from a device work queue by as many work groups
- * as fit on the chip) -- with `reps` fbc_green_apply calls each on this context (input
+ * as fit on the chip), 4 persistent with one work list per XCD (the row tiles of a mode
+ * one after another on one XCD, so their f^ operands are shared in its L2; a group whose
+ * list is exhausted helps the others) -- with `reps` fbc_green_apply calls each on this context (input
  * f, device; w, device, same layout as u, is overwritten with G f), keeps the list with
  * the fastest whole call (the K slices also cost the inverse transform a read each) and
  * reports it in *out (may be NULL).  The surrogate form is refused (FBC_E_UNSUPPORTED):

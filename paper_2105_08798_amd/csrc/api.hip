@@ -646,7 +646,11 @@ static void product_stats(fbc_ctx* c) {
 //   2  longest-first: units by cost, natural order;
 //   3  jobs longest first, consumed by the persistent work-queue kernel: each work group
 //      takes the next job as it finishes the last (surrogate form: its mode-major chunks,
-//      longest job first inside each).
+//      longest job first inside each);
+//   4  one list per XCD for the persistent kernel: units, longest first, go to the least
+//      loaded XCD as in order 0, and each XCD's groups take the jobs of its list in order
+//      -- the row tiles of one mode after another, whose overlapping K windows share the
+//      f^ fragments in that XCD's L2 -- then help the other lists.
 // ----------------------------------------------------------------------------------
 struct Unit {
     int cell, m, t;
@@ -684,7 +688,7 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
         }
 }
 
-static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) {
+static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order, int* list_start = nullptr) {
     const bool dt = is_table_form(c->opt.form);
     std::vector<Unit> units;
     for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
@@ -721,6 +725,14 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) 
         unit_jobs(c, u, nsplit, per_xcd[x]);
         load[x] += (int64_t)(per_xcd[x].size() - before) * u.cost / std::max<int64_t>(1, nsplit);
     }
+    if (order == 4) {            // the XCD lists back to back
+        for (int x = 0; x < 8; ++x) {
+            if (list_start) list_start[x] = (int)out.size();
+            out.insert(out.end(), per_xcd[x].begin(), per_xcd[x].end());
+        }
+        if (list_start) list_start[8] = (int)out.size();
+        return out;
+    }
     size_t mx = 0;
     for (auto& v : per_xcd) mx = std::max(mx, v.size());
     out.reserve(mx * 8);
@@ -737,7 +749,16 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order) 
 }
 
 static fbc_status upload_jobs(fbc_ctx* c, int nsplit, int order, hipStream_t st) {
-    std::vector<GemmJob> jobs = build_jobs(c, nsplit, order);
+    int list_start[9] = {0};
+    std::vector<GemmJob> jobs = build_jobs(c, nsplit, order, list_start);
+    c->lists.ctr = c->status + 16;
+    c->lists.nl = (order == 4) ? 8 : 1;
+    if (order == 4)
+        for (int l = 0; l < 9; ++l) c->lists.start[l] = list_start[l];
+    else {
+        for (int l = 0; l < 9; ++l) c->lists.start[l] = (int)jobs.size();
+        c->lists.start[0] = 0;
+    }
     if ((int64_t)jobs.size() > c->jobs_cap) {
         fbc_status s = dev_alloc(c, (void**)&c->jobs, (int64_t)jobs.size() * sizeof(GemmJob));
         if (s != FBC_OK) return s;
@@ -890,7 +911,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     if ((s = dev_alloc(c, &c->bfrag, b_off * b_elem_bytes(form))) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->cbuf, c_off * 8)) != FBC_OK) goto fail_out;
     if ((s = dev_alloc(c, (void**)&c->wbuf, w_off * 8)) != FBC_OK) goto fail_out;
-    if ((s = dev_alloc(c, (void**)&c->status, 64)) != FBC_OK) goto fail_out;
+    if ((s = dev_alloc(c, (void**)&c->status, 128)) != FBC_OK) goto fail_out;
     c->scratch_bytes = b_off * b_elem_bytes(form) + c_off * 8 + w_off * 8;
     {
         // per-cell small buffers
@@ -956,7 +977,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
         HIPCHK(c, hipMemcpyAsync(c->celldev, cd.data(), cd.size() * sizeof(CellDev), hipMemcpyHostToDevice, st));
     }
     HIPCHK(c, hipMemsetAsync(c->bfrag, 0, (size_t)(b_off * b_elem_bytes(form)), st));
-    HIPCHK(c, hipMemsetAsync(c->status, 0, 64, st));
+    HIPCHK(c, hipMemsetAsync(c->status, 0, 128, st));
     {
         // sin(pi p / L) table, L = max over every line length and the torus sizes
         int L = std::max(opt->bz_m1, opt->bz_m2);
@@ -1041,17 +1062,22 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
                                 c->near_tab, c->n_near, c->n_offsets, c->n_need, c->off_d1, c->off_d2,
                                 c->cmatch, c->gen, max_need);
             const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
+            PqLists ql{};
+            ql.ctr = c->status + 16;
+            ql.nl = 1;
+            for (int l = 0; l < 9; ++l) ql.start[l] = j1 - j0;
+            ql.start[0] = 0;
             launch_gemm_dtab(st, c->jobs + j0, j1 - j0, c->ctmax, c->gen, (int64_t)t0 * c->n_offsets * 6,
                              (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2,
-                             c->n_need, c->n_offsets, c->job_order == 3 ? c->status + 8 : nullptr);
+                             c->n_need, c->n_offsets, c->job_order == 3 ? &ql : nullptr);
         }
     } else if (form == FBC_FORM_DTABLE_FP64)
         launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, 0, (const double*)c->bfrag, c->cbuf,
                          c->celldev, c->lut, c->d1min, c->d2min, c->w2, nullptr, c->n_offsets,
-                         c->job_order == 3 ? c->status + 8 : nullptr);
+                         c->job_order >= 3 ? &c->lists : nullptr);
     else
         launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf,
-                    c->job_order == 3 ? c->status + 8 : nullptr);
+                    c->job_order >= 3 ? &c->lists : nullptr);
     if (tm) {
         (void)hipEventRecord(c->ev[2 * c->n_timed + 1], st);
         ++c->n_timed;
@@ -1181,7 +1207,7 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
     }
     double best = 1e300, best_gemm = 0.0;
     int best_split = c->nsplit, best_order = c->job_order, ncand = 0;
-    for (int order = 0; order < 4 && s == FBC_OK; ++order)
+    for (int order = 0; order < 5 && s == FBC_OK; ++order)
         for (int ks = 1; ks <= c->nsplit_cap && s == FBC_OK; ks *= 2) {
             if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) break;
             if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) break;       // warm-up
@@ -1225,7 +1251,7 @@ extern "C" fbc_status fbc_set_work_list(fbc_ctx* c, int nsplit, int order, void*
     if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
     if (nsplit < 1 || nsplit > c->nsplit_cap)
         return fail(c, FBC_E_ARG, "nsplit must be in [1, " + std::to_string(c->nsplit_cap) + "]");
-    if (order < 0 || order > 3) return fail(c, FBC_E_ARG, "order must be 0, 1, 2 or 3");
+    if (order < 0 || order > 4) return fail(c, FBC_E_ARG, "order must be 0, 1, 2, 3 or 4");
     if (c->opt.form == FBC_FORM_SURROGATE && (nsplit != 1 || (order != 1 && order != 3)))
         return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major chunks (nsplit 1, order 1 or 3)");
     return upload_jobs(c, nsplit, order, (hipStream_t)stream);

@@ -106,6 +106,17 @@ struct GemmJob {
     int32_t crs;        // output row stride (doubles): the modes of a row are adjacent
 };
 
+// Work lists of a persistent product launch: one list consumed by every work group (the
+// jobs longest first), or one list per XCD (nl = 8: work group b takes jobs from list
+// b mod 8 -- the XCD it runs on under round-robin dispatch -- and, once that list is
+// exhausted, from the others in turn).  ctr: device counters, [l] the next job of list
+// l, [8] the work groups that have left; all zero between launches.
+struct PqLists {
+    int* ctr;
+    int nl;
+    int start[9];      // list l holds the jobs [start[l], start[l + 1])
+};
+
 // Physical index of a step of a cyclic K range (idx < 2 n).
 __host__ __device__ inline int wrap_k(int idx, int n) { return idx >= n ? idx - n : idx; }
 

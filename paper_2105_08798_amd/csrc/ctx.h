@@ -35,8 +35,9 @@ struct fbc_ctx {
     double* sum_part = nullptr;
     double* mean = nullptr;         // [total_rhs][3]
     double2* tw = nullptr;          // twiddle tables
-    int* status = nullptr;          // 64 bytes: [0] device latch; [8], [9] work queue of the
-                                    // persistent product (next job, groups done), zero between launches
+    int* status = nullptr;          // 128 bytes: [0] device latch; [16..24] counters of the
+                                    // persistent product's work lists, zero between launches
+    PqLists lists{};                // work lists of the persistent product (orders 3 and 4)
     GemmJob* jobs = nullptr;
     int njobs = 0;
     int nsplit = 1;                 // K slices of the per-mode product

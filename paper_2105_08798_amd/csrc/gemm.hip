@@ -59,25 +59,41 @@ __device__ inline bf8_t ld_stream(const bf8_t* p) { return __builtin_nontemporal
 __device__ inline h8_t ld_stream(const h8_t* p) { return __builtin_nontemporal_load(p); }
 
 // Persistent work-queue form of the product kernels: as many work groups as fit on the
-// chip at once, each taking the next job of the list from a device counter until the list
-// is exhausted (with the list longest first, the groups that finish early take the short
-// jobs: dynamic longest-processing-time scheduling of uneven jobs).  queue[0] is the next
-// job, queue[1] counts the groups that have left; the last one to leave sets both back to
-// zero for the next launch (so the launch can be replayed from a graph).  Every group
-// leaves as soon as it draws an index past the list.
-__device__ inline int pq_next(int* __restrict__ queue, int* slot) {
-    if (threadIdx.x == 0) *slot = atomicAdd(&queue[0], 1);
+// chip at once, each taking the next job of its list from a device counter until the
+// lists are exhausted (with a list longest first, the groups that finish early take the
+// short jobs: dynamic longest-processing-time scheduling of uneven jobs).  With one list
+// per XCD (PqLists), the groups of an XCD work through consecutive row tiles of the same
+// mode together, so the f^ fragments of their overlapping K windows are fetched into that
+// XCD's L2 once; a group whose list is exhausted takes jobs from the other lists in turn.
+// The last group to leave sets the counters back to zero for the next launch (so the
+// launch can be replayed from a graph).  `cur` (thread 0's) counts the lists this group
+// has exhausted; every group leaves once it has drawn past the end of all of them.
+__device__ inline int pq_next(const PqLists& q, int* slot, int& cur) {
+    if (threadIdx.x == 0) {
+        const int home = q.nl > 1 ? (int)(blockIdx.x % q.nl) : 0;
+        int j = 0x7fffffff;
+        while (cur < q.nl) {
+            const int l = (home + cur) % q.nl;
+            const int s = atomicAdd(&q.ctr[l], 1);
+            if (s < q.start[l + 1] - q.start[l]) {
+                j = q.start[l] + s;
+                break;
+            }
+            ++cur;
+        }
+        *slot = j;
+    }
     __syncthreads();
     const int j = __builtin_amdgcn_readfirstlane(*slot);   // uniform: the job fields go to SGPRs
     __syncthreads();                     // every thread has read the slot; LDS of the last job free
     return j;
 }
-__device__ inline void pq_done(int* __restrict__ queue) {
+__device__ inline void pq_done(const PqLists& q) {
     if (threadIdx.x == 0) {
         __threadfence();
-        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
-            atomicExch(&queue[0], 0);
-            atomicExch(&queue[1], 0);
+        if (atomicAdd(&q.ctr[8], 1) == (int)gridDim.x - 1) {
+            for (int l = 0; l < q.nl; ++l) atomicExch(&q.ctr[l], 0);
+            atomicExch(&q.ctr[8], 0);
         }
     }
 }
@@ -177,14 +193,15 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const GemmJob* __restrict__ jo
     gemm_f64_job<RB, CT, PF>(jb, A, B, C);
 }
 template <int RB, int CT, int PF>
-__global__ void __launch_bounds__(256) k_gemm_f64_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+__global__ void __launch_bounds__(256) k_gemm_f64_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
         const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C) {
     __shared__ int slot;
-    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+    int cur = 0;
+    for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
         gemm_f64_job<RB, CT, PF>(jb, A, B, C);
     }
-    pq_done(queue);
+    pq_done(q);
 }
 
 // ------------------------------- FP32 ---------------------------------------------
@@ -278,14 +295,15 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const GemmJob* __restrict__ jo
     gemm_f32_job<RB, CT, PF, KCH>(jb, A, B, C);
 }
 template <int RB, int CT, int PF, int KCH>
-__global__ void __launch_bounds__(256) k_gemm_f32_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+__global__ void __launch_bounds__(256) k_gemm_f32_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
         const float* __restrict__ A, const float* __restrict__ B, double* __restrict__ C) {
     __shared__ int slot;
-    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+    int cur = 0;
+    for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
         gemm_f32_job<RB, CT, PF, KCH>(jb, A, B, C);
     }
-    pq_done(queue);
+    pq_done(q);
 }
 
 // ------------------------------- split BF16 ---------------------------------------
@@ -405,14 +423,15 @@ __global__ void __launch_bounds__(256) k_gemm_split(const GemmJob* __restrict__ 
     gemm_split_job<VT, RB, CT, PF, KCH>(jb, A, B, C);
 }
 template <typename VT, int RB, int CT, int PF, int KCH>
-__global__ void __launch_bounds__(256) k_gemm_split_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+__global__ void __launch_bounds__(256) k_gemm_split_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
         const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, double* __restrict__ C) {
     __shared__ int slot;
-    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+    int cur = 0;
+    for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
         gemm_split_job<VT, RB, CT, PF, KCH>(jb, A, B, C);
     }
-    pq_done(queue);
+    pq_done(q);
 }
 
 // Variant for 4 or 8 column tiles (many RHS): the B fragments of a K step are the same
@@ -557,14 +576,15 @@ __global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restric
     gemm_split_lds_job<VT, RB, CT, PFA, KCH, S>(jb, A, B, C);
 }
 template <typename VT, int RB, int CT, int PFA, int KCH, int S>
-__global__ void __launch_bounds__(256) k_gemm_split_lds_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+__global__ void __launch_bounds__(256) k_gemm_split_lds_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
         const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, double* __restrict__ C) {
     __shared__ int slot;
-    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+    int cur = 0;
+    for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
         gemm_split_lds_job<VT, RB, CT, PFA, KCH, S>(jb, A, B, C);
     }
-    pq_done(queue);
+    pq_done(q);
 }
 
 // Row blocks per wave for a given column-tile count (register budget per lane).  The
@@ -580,21 +600,21 @@ int gemm_rb(int form, int ctmax) {
 
 template <typename TA>
 static void launch_dense(void (*kn)(const GemmJob*, const TA*, const TA*, double*),
-                         void (*kp)(const GemmJob*, int, int*, const TA*, const TA*, double*),
+                         void (*kp)(const GemmJob*, int, PqLists, const TA*, const TA*, double*),
                          hipStream_t st, const GemmJob* jobs, int njobs, const void* a, const void* b,
-                         double* c, int* queue) {
-    if (queue)
+                         double* c, const PqLists* q) {
+    if (q)
         hipLaunchKernelGGL(kp, dim3(std::min(njobs, pq_groups_of(kp, 256))), dim3(256), 0, st, jobs, njobs,
-                           queue, (const TA*)a, (const TA*)b, c);
+                           *q, (const TA*)a, (const TA*)b, c);
     else
         hipLaunchKernelGGL(kn, dim3(njobs), dim3(256), 0, st, jobs, (const TA*)a, (const TA*)b, c);
 }
 
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
-                 const void* a, const void* b, double* c, int* queue) {
+                 const void* a, const void* b, double* c, const PqLists* q) {
     if (njobs <= 0) return;
 #define GEMM_CASE(KERN, RB, CT, ...)                                                           \
-    launch_dense<TA>(KERN<RB, CT, __VA_ARGS__>, KERN##_pq<RB, CT, __VA_ARGS__>, st, jobs, njobs, a, b, c, queue)
+    launch_dense<TA>(KERN<RB, CT, __VA_ARGS__>, KERN##_pq<RB, CT, __VA_ARGS__>, st, jobs, njobs, a, b, c, q)
     if (form == FBC_FORM_FP64) {
         typedef double TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_f64, 4, 1, 4);
@@ -794,29 +814,30 @@ k_gemm_dtab(const GemmJob* __restrict__ jobs, const double2* __restrict__ tab, i
 // Persistent form (work queue as for the dense products).
 template <int CT>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
-k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, int* __restrict__ queue,
+k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
                const double2* __restrict__ tab, int64_t a_base, const double* __restrict__ B,
                double* __restrict__ C, const CellDev* __restrict__ cells,
                const int32_t* __restrict__ lut, int d1min, int d2min, int w2,
                const int32_t* __restrict__ need, int64_t n_off) {
     __shared__ int slot;
-    for (int j = pq_next(queue, &slot); j < njobs; j = pq_next(queue, &slot)) {
+    int cur = 0;
+    for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
         dtab_job<CT>(jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
     }
-    pq_done(queue);
+    pq_done(q);
 }
 
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
                       const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
-                      int64_t n_off, int* queue) {
+                      int64_t n_off, const PqLists* q) {
     if (njobs <= 0) return;
     dim3 blk(128);
-    if (queue) {
+    if (q) {
 #define PQ_CASE(CT)                                                                             \
     hipLaunchKernelGGL(k_gemm_dtab_pq<CT>, dim3(std::min(njobs, pq_groups_of(k_gemm_dtab_pq<CT>, 128))), blk, 0, st, jobs, \
-                       njobs, queue, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off)
+                       njobs, *q, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off)
         switch (ct) {
             case 1: PQ_CASE(1); break;
             case 2: PQ_CASE(2); break;

@@ -47,13 +47,13 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
                       const int* bexp);
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
                  const void* a, const void* b, double* c,
-                 int* queue);   // queue != NULL: persistent work-queue kernel
+                 const PqLists* q);   // q != NULL: persistent work-queue kernel on these lists
 // Offset-table form: 32 pad columns x all interface columns per work group, table
 // entries gathered into LDS in MFMA fragment order.
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
                       const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
-                      int64_t n_off, int* queue);   // queue != NULL: persistent work-queue kernel
+                      int64_t n_off, const PqLists* q);   // q != NULL: persistent work-queue kernel
 void irfft_shape(int nz, int* tr, int* pp);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,

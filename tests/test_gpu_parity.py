@@ -435,7 +435,7 @@ def test_work_lists_give_identical_results(form):
     stream = torch.cuda.Stream()
     for nsplit in (2, 1):
         ref_split = None
-        for order in (0, 1, 2, 3):
+        for order in (0, 1, 2, 3, 4):
             ctx.set_work_list(nsplit, order)
             assert ctx.info.nsplit == nsplit and ctx.info.job_order == order
             for rep in range(2):
@@ -450,22 +450,24 @@ def test_work_lists_give_identical_results(form):
             tol = 1e-13 if form in FP64_FORMS else 1e-6
             assert np.abs(ref_split - ref).max() <= tol * np.abs(ref).max()
         ref = ref_split
-    # persistent list replayed from a captured graph, with eager calls in between
-    ctx.set_work_list(1, 3)
-    u0 = torch.zeros(n_u, dtype=torch.float64, device=dev)
-    u_eager = u0.clone()
-    ctx.apply(f, u_eager, alpha=1.0)
-    torch.cuda.synchronize()
-    u = torch.empty_like(u0)          # one buffer: the first call captures, the rest replay
-    for rep in range(3):
-        u.copy_(u0)
+    # persistent lists (one, and one per XCD) replayed from a captured graph, with eager
+    # calls in between
+    for order in (3, 4):
+        ctx.set_work_list(1, order)
+        u0 = torch.zeros(n_u, dtype=torch.float64, device=dev)
+        u_eager = u0.clone()
+        ctx.apply(f, u_eager, alpha=1.0)
         torch.cuda.synchronize()
-        ctx.apply_graph(f, u, alpha=1.0, stream=stream)
-        stream.synchronize()
-        assert np.array_equal(u.cpu().numpy(), u_eager.cpu().numpy()), rep
-        w = torch.zeros(n_u, dtype=torch.float64, device=dev)
-        ctx.green_apply(f, w)
-        assert np.array_equal(w.cpu().numpy(), ref), rep
+        u = torch.empty_like(u0)          # one buffer: the first call captures, the rest replay
+        for rep in range(3):
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            ctx.apply_graph(f, u, alpha=1.0, stream=stream)
+            stream.synchronize()
+            assert np.array_equal(u.cpu().numpy(), u_eager.cpu().numpy()), (order, rep)
+            w = torch.zeros(n_u, dtype=torch.float64, device=dev)
+            ctx.green_apply(f, w)
+            assert np.array_equal(w.cpu().numpy(), ref), (order, rep)
     assert ctx.sync_status() == 0
     ctx.close()
 
@@ -475,7 +477,7 @@ def test_work_list_arguments_checked():
     wl = W.make_single("parity")
     from paper_2105_08798_amd.fbc import FbcError
     ctx = _ctx(wl.cells, wl.bz, form="fp64")
-    for nsplit, order in ((0, 0), (1, 4), (1, -1), (1 << 20, 0)):
+    for nsplit, order in ((0, 0), (1, 5), (1, -1), (1 << 20, 0)):
         with pytest.raises(FbcError):
             ctx.set_work_list(nsplit, order)
     ctx.close()
