@@ -13,7 +13,7 @@
 
 #include "ctx.h"
 
-int gemm_rb(int form, int ctmax);
+int gemm_tile_rows(int form, int ctmax);
 extern "C" fbc_status fbc_timing(fbc_ctx* c, int enable);
 extern "C" fbc_status fbc_timing_read(fbc_ctx* c, double* ms, int* n);
 
@@ -495,7 +495,7 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
                 rho_cut[t] = v;
             }
         }
-        const int rows_tile = 64 * gemm_rb(form, c->ctmax);
+        const int rows_tile = gemm_tile_rows(form, c->ctmax);
         compute_windows(c, rho_cut, rows_tile);
     }
     if (sur) {
@@ -543,7 +543,7 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
             c->scratch_bytes += tot_rm * 16;
         }
         // compact store: the chunk-tiles of every window, cell after cell
-        const int rows_tile = 64 * gemm_rb(form, c->ctmax);
+        const int rows_tile = gemm_tile_rows(form, c->ctmax);
         const int64_t cte = chunk_tile_elems(form, rows_tile);
         int64_t a_tot = 0, max_reg = 0;
         for (CellPlan& p : c->cells) {
@@ -602,7 +602,7 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
 static void product_stats(fbc_ctx* c) {
     const int form = c->opt.form;
     const bool dt = is_table_form(form);
-    const int rows_tile = dt ? 96 : 64 * gemm_rb(form, c->ctmax);
+    const int rows_tile = dt ? 96 : gemm_tile_rows(form, c->ctmax);
     const double eb = (form == FBC_FORM_FP64) ? 8.0 : 4.0;       // stored bytes per real entry
     const double fb = (form == FBC_FORM_FP64 || dt) ? 16.0 : 8.0; // bytes per complex f^
     double bytes = 0, flops = 0, area = 0, kept = 0;
@@ -661,7 +661,7 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
     const int form = c->opt.form;
     const CellPlan& p = c->cells[u.cell];
     const bool dt = is_table_form(form);
-    const int tile_rows = dt ? 96 : 64 * gemm_rb(form, c->ctmax);
+    const int tile_rows = dt ? 96 : gemm_tile_rows(form, c->ctmax);
     const int tiles = p.mp / tile_rows;
     const int unit_k = dt ? 8 : 64;
     for (int ks = 0; ks < nsplit; ++ks)
@@ -694,7 +694,7 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order, 
     for (int ci = 0; ci < (int)c->cells.size(); ++ci) {
         const CellPlan& p = c->cells[ci];
         const int mult = c->nz_max / p.nz;
-        const int64_t tile_rows = dt ? 96 : 64 * gemm_rb(c->opt.form, c->ctmax);
+        const int64_t tile_rows = dt ? 96 : gemm_tile_rows(c->opt.form, c->ctmax);
         const int64_t unit_k = dt ? 48 : 64;
         for (int m = 0; m < p.nm; ++m) {
             int64_t cost = 0;
@@ -835,7 +835,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     int ctmax = 1;
     for (int i = 0; i < n_cells; ++i) ctmax = std::max(ctmax, (cells[i].n_rhs + 7) / 8);
     const int ctl = ctmax <= 1 ? 1 : ctmax <= 2 ? 2 : ctmax <= 4 ? 4 : 8;
-    const int rows_tile = 64 * gemm_rb(form, ctl);
+    const int rows_tile = gemm_tile_rows(form, ctl);
     c->ctmax = ctl;
     int64_t f_off = 0, u_off = 0, b_off = 0, c_off = 0, w_off = 0;
     int rhs0 = 0;
@@ -1107,16 +1107,21 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
         const int* be = f16 ? c->bexp + p.rhs0 : nullptr;
         int tr, pp;
         if (!update_shape(p.nz, p.M, p.ctr, &tr, &pp)) {
-            // long or short lines: inverse transform into w, then the tiled transpose-update
+            // long or short lines: inverse transform into w, then the tiled transpose-update,
+            // which also removes the mean (known beforehand, as for the fused update)
             double* uc = u + p.u_off;
             double* sp = c->sum_part + c->sum_part_off[ci];
+            double* mu = nullptr;
+            if (mean_removal) {
+                mu = c->mean + 3 * p.rhs0;
+                launch_update_mean(st, uc, c->cbuf + p.c_off, sp, p.R, p.nz, p.mp, p.M, c->nsplit, p.c_split, rm,
+                                   sh, so, am, be, alpha, mu, c->status);
+            }
             launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
                               p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split, rm, sh,
                               so, am, be, nullptr);
             if (!mean_removal) launch_fill(st, uc, (int64_t)p.R * p.nz * p.M, 0.0);
-            launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr);
-            if (mean_removal)
-                launch_mean(st, uc, sp, c->npart_axpy[ci], c->mean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
+            launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr, mu);
             continue;
         }
         double* mu = nullptr;
@@ -1406,7 +1411,7 @@ extern "C" fbc_status fbc_copy_block_rows(fbc_ctx* c, int cell, int m, int b0, i
     if (c->opt.form != FBC_FORM_FP64) return fail(c, FBC_E_UNSUPPORTED, "FP64 forms only");
     // compact store: the row tiles covering the rows, their windows at mode m; blocks
     // outside a window are the product's zeros
-    const int rows_tile = 64 * gemm_rb(c->opt.form, c->ctmax);
+    const int rows_tile = gemm_tile_rows(c->opt.form, c->ctmax);
     const int64_t cte = chunk_tile_elems(c->opt.form, rows_tile);
     const int trb = rows_tile / 16;
     const int rows = 3 * (b1 - b0);

@@ -387,6 +387,9 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
     constexpr int budget = 8192;          // 64 KiB
     int tc = 256;
     while (tc > 2 && tc * (nz + 1) > budget) tc >>= 1;
+    // long lines: at least 8 columns (64-byte runs of each layer's forces) while the group's
+    // sequences fit in 66 KiB (two groups per CU)
+    while (tc < 8 && 2 * tc * (nz + 1) * 8 <= 66 * 1024) tc <<= 1;
     const int kk = (K + 1) & ~1;
     if (tc > kk) tc = kk;
     tc &= ~1;
@@ -936,13 +939,15 @@ void launch_update_mean(hipStream_t st, const double* u, const double* c, double
 }
 
 // ----------------------------------------------------------------------------------
-// u[r][n0][row] -= alpha_r * w[r][row][n0] (tiled transpose through LDS), with per
-// block partial sums of the updated u per Cartesian component (row % 3).
+// u[r][n0][row] -= alpha_r * w[r][row][n0] (+ mu[r][row % 3] when mu is given: the mean
+// of the result, known beforehand) by a tiled transpose through LDS, with per block
+// partial sums of the updated u per Cartesian component (row % 3).
 // Skipped entirely when a data check has latched an error.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, double* __restrict__ u,
                                              double* __restrict__ sum_part, int nz, int M,
                                              double alpha, const double* __restrict__ alpha_d,
+                                             const double* __restrict__ mu,
                                              const int* __restrict__ status) {
     __shared__ double tile[32][33];
     __shared__ double red[3 * NT];
@@ -963,7 +968,8 @@ __global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, doubl
         const int n0 = n00 + y, row = row0 + tx;
         if (row < M && n0 < nz) {
             const int64_t idx = (int64_t)n0 * M + row;
-            const double x = ur[idx] - a * tile[tx][y];
+            double x = ur[idx] - a * tile[tx][y];
+            if (mu) x -= mu[r * 3 + row % 3];
             ur[idx] = x;
             v[row % 3] += x;
         }
@@ -977,9 +983,10 @@ __global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, doubl
 }
 
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
-                 int M, double alpha, const double* alpha_d, const int* status, int* n_part_out) {
+                 int M, double alpha, const double* alpha_d, const int* status, int* n_part_out,
+                 const double* mu) {
     dim3 grid((M + 31) / 32, (nz + 31) / 32, R);
-    hipLaunchKernelGGL(k_axpy, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d,
+    hipLaunchKernelGGL(k_axpy, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d, mu,
                        status);
     if (n_part_out) *n_part_out = (int)(grid.x * grid.y);
 }

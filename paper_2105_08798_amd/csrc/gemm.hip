@@ -435,15 +435,17 @@ __global__ void __launch_bounds__(256) k_gemm_split_pq(const GemmJob* __restrict
 }
 
 // Variant for 4 or 8 column tiles (many RHS): the B fragments of a K step are the same
-// for the four waves of a work group, so they are loaded once per work group into LDS
+// for the NW waves of a work group, so they are loaded once per work group into LDS
 // (double buffered) instead of once per wave from L2, and the group meets at one barrier
-// per S steps.  A is streamed from HBM into a register ring PFA steps deep.  Each thread
+// per S steps.  NW waves per group: four at 64 RHS (the FP64 accumulators of 16 output
+// tiles and the A and B rings need more registers than two waves per SIMD leave, so a
+// group of eight waves, which would halve the B fetches per row, spills).  A is streamed from HBM into a register ring PFA steps deep.  Each thread
 // also keeps its share of B for the same PFA steps in a ring of its own: vector-memory
 // loads complete in issue order, so the wait for B before it is copied into LDS would
 // otherwise also wait for every A load issued before it, and cut the effective depth of
 // the A ring down to the distance at which B was fetched.  K windows and slices hold an
 // even number of steps, so S = 2 needs no tail.
-template <typename VT, int RB, int CT, int PFA, int KCH, int S>
+template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW>
 __device__ inline void gemm_split_lds_job(const GemmJob& jb,
                                                         const unsigned short* __restrict__ A,
                                                         const unsigned short* __restrict__ B,
@@ -451,15 +453,17 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
     static_assert(CT >= 2 && (CT % 2) == 0, "B staging assumes an even tile count");
     static_assert(S == 1 || S == 2, "one or two K steps per barrier");
     static_assert(PFA >= 2 * S && (PFA % (2 * S)) == 0, "ring depth must be a multiple of 2 S");
+    constexpr int NTH = 64 * NW;             // threads of the work group
     constexpr int STEP_UNITS = CT * 128;     // 16-byte units of B per step (hi and lo runs)
-    constexpr int NU = STEP_UNITS / 256;     // per thread and step
+    static_assert(STEP_UNITS % NTH == 0, "B units must spread evenly over the threads");
+    constexpr int NU = STEP_UNITS / NTH;     // per thread and step
     __shared__ VT bs[2][STEP_UNITS * S];
     if (jb.rb0 >= jb.mb) return;             // whole work group (empty job)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int rbw = jb.rb0 + wave * RB;
     const int kt = jb.kp >> 5;
     const int tb = jb.k0 >> 5, te = jb.k1 >> 5;    // te - tb is even (K slices of 64 k')
-    constexpr int TRB = 4 * RB;          // row blocks of the tile: the A step stride
+    constexpr int TRB = NW * RB;         // row blocks of the tile: the A step stride
     const VT* a = (const VT*)(A + jb.a_off) + (int64_t)(wave * RB) * 128 + lane;
     const VT* b = (const VT*)(B + jb.b_off);
     d4_t acc[RB][CT];
@@ -483,13 +487,13 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
         const int tw = wrap_k(t, kt);
 #pragma unroll
         for (int j = 0; j < NU; ++j) {
-            const int u = tid + 256 * j, c = u >> 7, rem = u & 127;
+            const int u = tid + NTH * j, c = u >> 7, rem = u & 127;
             dst[j] = b[((int64_t)c * kt + tw) * 128 + (rem & 64) + bpos(rem & 63)];
         }
     };
     auto store_b = [&](int buf, int sidx, const VT (&src)[NU]) {
 #pragma unroll
-        for (int j = 0; j < NU; ++j) bs[buf][sidx * STEP_UNITS + tid + 256 * j] = src[j];
+        for (int j = 0; j < NU; ++j) bs[buf][sidx * STEP_UNITS + tid + NTH * j] = src[j];
     };
     // rings: PFA steps of A and of this thread's share of B in flight
     VT ah[PFA][RB], al[PFA][RB], br[PFA][NU];
@@ -569,27 +573,26 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
         for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
 }
 
-template <typename VT, int RB, int CT, int PFA, int KCH, int S>
-__global__ void __launch_bounds__(256) k_gemm_split_lds(const GemmJob* __restrict__ jobs, const unsigned short* __restrict__ A,
+template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW>
+__global__ void __launch_bounds__(64 * NW) k_gemm_split_lds(const GemmJob* __restrict__ jobs, const unsigned short* __restrict__ A,
         const unsigned short* __restrict__ B, double* __restrict__ C) {
     const GemmJob jb = jobs[blockIdx.x];
-    gemm_split_lds_job<VT, RB, CT, PFA, KCH, S>(jb, A, B, C);
+    gemm_split_lds_job<VT, RB, CT, PFA, KCH, S, NW>(jb, A, B, C);
 }
-template <typename VT, int RB, int CT, int PFA, int KCH, int S>
-__global__ void __launch_bounds__(256) k_gemm_split_lds_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
+template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW>
+__global__ void __launch_bounds__(64 * NW) k_gemm_split_lds_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
         const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, double* __restrict__ C) {
     __shared__ int slot;
     int cur = 0;
     for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
-        gemm_split_lds_job<VT, RB, CT, PFA, KCH, S>(jb, A, B, C);
+        gemm_split_lds_job<VT, RB, CT, PFA, KCH, S, NW>(jb, A, B, C);
     }
     pq_done(q);
 }
 
-// Row blocks per wave for a given column-tile count (register budget per lane).  The
-// planner pads rows to 64*RB (a whole work-group tile) and K' to a multiple of 64.
-int gemm_rb(int form, int ctmax) {
+// Row blocks per wave for a given column-tile count (register budget per lane).
+static int gemm_rb(int form, int ctmax) {
     // one column tile: 2 row blocks per wave for the FP32 and split products (128-row work
     // groups: finer negligible-block windows and more work groups; measured 3 % faster
     // than 4 on the medium workload), 4 for FP64
@@ -597,17 +600,22 @@ int gemm_rb(int form, int ctmax) {
         return ctmax <= 1 ? 2 : ctmax <= 2 ? 4 : 2;
     return ctmax <= 2 ? 4 : 2;
 }
+// Waves per work group (every product kernel as launched runs four).
+static int gemm_waves(int, int) { return 4; }
+// Rows of a work group's tile (16 per row block): the planner pads rows to whole tiles,
+// K' to a multiple of 64, and lays the compact store out in tiles of this height.
+int gemm_tile_rows(int form, int ctmax) { return 16 * gemm_rb(form, ctmax) * gemm_waves(form, ctmax); }
 
 template <typename TA>
 static void launch_dense(void (*kn)(const GemmJob*, const TA*, const TA*, double*),
                          void (*kp)(const GemmJob*, int, PqLists, const TA*, const TA*, double*),
                          hipStream_t st, const GemmJob* jobs, int njobs, const void* a, const void* b,
-                         double* c, const PqLists* q) {
+                         double* c, const PqLists* q, int threads = 256) {
     if (q)
-        hipLaunchKernelGGL(kp, dim3(std::min(njobs, pq_groups_of(kp, 256))), dim3(256), 0, st, jobs, njobs,
+        hipLaunchKernelGGL(kp, dim3(std::min(njobs, pq_groups_of(kp, threads))), dim3(threads), 0, st, jobs, njobs,
                            *q, (const TA*)a, (const TA*)b, c);
     else
-        hipLaunchKernelGGL(kn, dim3(njobs), dim3(256), 0, st, jobs, (const TA*)a, (const TA*)b, c);
+        hipLaunchKernelGGL(kn, dim3(njobs), dim3(threads), 0, st, jobs, (const TA*)a, (const TA*)b, c);
 }
 
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
@@ -615,6 +623,7 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
     if (njobs <= 0) return;
 #define GEMM_CASE(KERN, RB, CT, ...)                                                           \
     launch_dense<TA>(KERN<RB, CT, __VA_ARGS__>, KERN##_pq<RB, CT, __VA_ARGS__>, st, jobs, njobs, a, b, c, q)
+
     if (form == FBC_FORM_FP64) {
         typedef double TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_f64, 4, 1, 4);
@@ -633,16 +642,16 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 2, 1, 2, 2);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2);
-        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2, 4);
+        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2, 4);
     } else {
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 2, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
         // two K steps per barrier: 2 % faster than one on the 64-RHS workload (measured;
         // the split-FP16 kernel gained nothing and keeps one)
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2);
-        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2);
+        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2, 4);
+        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2, 4);
     }
 #undef GEMM_CASE
 }

@@ -62,7 +62,7 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
                        int* n_part_out);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status,
-                 int* n_part_out);
+                 int* n_part_out, const double* mu = nullptr);
 void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, double* mean_out,
                  int R, int nz, int M, const int* status);
 // fused inverse transform + update (fbc_apply, fbc_green_apply), and the mean it removes;
