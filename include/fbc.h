@@ -227,9 +227,20 @@ fbc_status fbc_relax_begin(fbc_ctx* ctx, const fbc_relax_opts* opts, void* strea
 
 /* One pass of Algorithm 1 from the relaxation on, given f_in,k+1 (computed by the caller):
  * alpha from Relax on raw residuals (k >= 2), optional step bound, pad update, mean
- * removal.  No host synchronisation.  out_dev: device array [total RHS] or NULL. */
+ * removal.  No host synchronisation.  out_dev: device array [total RHS] or NULL.  The
+ * iteration index k is kept in device memory and advanced by the step's last kernel. */
 fbc_status fbc_relax_step(fbc_ctx* ctx, const double* f_in, double* u,
                           fbc_relax_out* out_dev, void* stream);
+
+/* fbc_relax_step replayed from a HIP graph (Algorithm 1's update with Algorithm 2 in one
+ * launch per iteration): the first call with a given (f_in, u, out_dev, stream) captures
+ * the step's kernels, later calls with the same arguments replay them; the kernels read
+ * the iteration index from device memory, so every replay takes the current k.  A call
+ * with other arguments, fbc_relax_begin, fbc_relax_set_state and a new work list capture
+ * again.  stream must be a created (non-default) stream that is not itself capturing.
+ * Same contract and results (bitwise) as fbc_relax_step. */
+fbc_status fbc_relax_step_graph(fbc_ctx* ctx, const double* f_in, double* u,
+                                fbc_relax_out* out_dev, void* stream);
 
 /* Checkpoint and resume of the relaxation (Section 2.3.3): the iteration's state is the
  * options, the index k, alpha_k of every RHS and the previous raw incompatibility forces

@@ -16,6 +16,7 @@
 int gemm_tile_rows(int form, int ctmax);
 extern "C" fbc_status fbc_timing(fbc_ctx* c, int enable);
 extern "C" fbc_status fbc_timing_read(fbc_ctx* c, double* ms, int* n);
+static void drop_relax_graph(fbc_ctx* c);
 
 
 
@@ -77,7 +78,7 @@ extern "C" const char* fbc_status_string(fbc_status s) {
         case FBC_OK: return "ok";
         case FBC_E_ARG: return "invalid argument";
         case FBC_E_NOMEM: return "out of device memory";
-        case FBC_E_NETFORCE: return "non-zero net force per layer";
+        case FBC_E_NETFORCE: return "non-zero net force of a cell (all interface atoms of all layers)";
         case FBC_E_NONFINITE: return "non-finite force";
         case FBC_E_DEVICE: return "device error";
         case FBC_E_STATE: return "call out of order";
@@ -790,6 +791,7 @@ static fbc_status upload_jobs(fbc_ctx* c, int nsplit, int order, hipStream_t st)
         c->graph_exec = nullptr;
         c->graph = nullptr;
     }
+    drop_relax_graph(c);
     return FBC_OK;
 }
 
@@ -1278,36 +1280,41 @@ static fbc_status check_relax_opts(fbc_ctx* c, const fbc_relax_opts* o) {
     return FBC_OK;
 }
 
+static void drop_relax_graph(fbc_ctx* c) {
+    if (c->rgraph_exec) (void)hipGraphExecDestroy(c->rgraph_exec);
+    if (c->rgraph) (void)hipGraphDestroy(c->rgraph);
+    c->rgraph_exec = nullptr;
+    c->rgraph = nullptr;
+}
+
 extern "C" fbc_status fbc_relax_begin(fbc_ctx* c, const fbc_relax_opts* o, void* stream) {
     if (!c || !o) return fail(c, FBC_E_ARG, "null argument");
     fbc_status s = check_relax_opts(c, o);
     if (s != FBC_OK) return s;
+    drop_relax_graph(c);                 // the options are kernel arguments of a captured step
     c->ropt = *o;
     c->relax_k = 0;
     launch_fill((hipStream_t)stream, c->alpha, c->total_rhs, 1.0);
+    launch_relax_index((hipStream_t)stream, c->status + 4, 0);
     HIPCHK(c, hipGetLastError());
     return FBC_OK;
 }
 
-extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, fbc_relax_out* out,
-                                     void* stream) {
-    fbc_status s = check_apply_args(c, f_in, u);
-    if (s != FBC_OK) return s;
-    if (c->relax_k < 0) return fail(c, FBC_E_STATE, "fbc_relax_begin was not called");
-    hipStream_t st = (hipStream_t)stream;
-    const int k = c->relax_k;
+// One relaxation step, enqueued; the iteration index is read and advanced on the device.
+static void enqueue_relax(fbc_ctx* c, const double* f_in, double* u, fbc_relax_out* out, hipStream_t st) {
+    int* kdev = c->status + 4;
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         const int64_t per_rhs = (int64_t)p.nz * p.K;
         launch_relax_alpha(st, f_in + p.f_off, c->fprev + p.f_off, c->rpart + c->rpart_off[ci],
-                           c->alpha + p.rhs0, c->finf + p.rhs0, p.R, per_rhs, k, c->ropt.relax,
+                           c->alpha + p.rhs0, c->finf + p.rhs0, p.R, per_rhs, kdev, c->ropt.relax,
                            c->ropt.alpha_min);
     }
     enqueue_forward(c, f_in, st, true);
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         launch_relax_clamp(st, c->wmax_part + c->wmax_off[ci], c->npart_irfft[ci], c->alpha + p.rhs0,
-                           c->stepinf + p.rhs0, p.R, c->ropt.du_max, k, c->ropt.relax);
+                           c->stepinf + p.rhs0, p.R, c->ropt.du_max, kdev, c->ropt.relax);
         double* uc = u + p.u_off;
         double* sp = c->sum_part + c->sum_part_off[ci];
         launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, 0.0, c->alpha + p.rhs0, c->status,
@@ -1315,9 +1322,54 @@ extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, 
         launch_mean(st, uc, sp, c->npart_axpy[ci], c->rmean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
     }
     launch_relax_finish(st, f_in, c->fprev, c->f_elems, c->alpha, c->finf, c->stepinf, c->rmean, out,
-                        c->total_rhs, k, c->ropt.tol_f);
-    c->relax_k = k + 1;
+                        c->total_rhs, kdev, c->ropt.tol_f);
+}
+
+extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, fbc_relax_out* out,
+                                     void* stream) {
+    fbc_status s = check_apply_args(c, f_in, u);
+    if (s != FBC_OK) return s;
+    if (c->relax_k < 0) return fail(c, FBC_E_STATE, "fbc_relax_begin was not called");
+    enqueue_relax(c, f_in, u, out, (hipStream_t)stream);
+    c->relax_k += 1;
     HIPCHK(c, hipGetLastError());
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_relax_step_graph(fbc_ctx* c, const double* f_in, double* u, fbc_relax_out* out,
+                                           void* stream) {
+    fbc_status s = check_apply_args(c, f_in, u);
+    if (s != FBC_OK) return s;
+    if (c->relax_k < 0) return fail(c, FBC_E_STATE, "fbc_relax_begin was not called");
+    if (!stream) return fail(c, FBC_E_ARG, "graph capture needs a non-default stream");
+    hipStream_t st = (hipStream_t)stream;
+    if (!(c->rgraph_exec && c->rg_f == f_in && c->rg_u == u && c->rg_out == out && c->rg_stream == stream)) {
+        drop_relax_graph(c);
+        const int timing = c->timing;
+        c->timing = 0;
+        HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        enqueue_relax(c, f_in, u, out, st);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        c->timing = timing;
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(c, FBC_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        }
+        e = hipGraphInstantiate(&c->rgraph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            c->rgraph_exec = nullptr;
+            return fail(c, FBC_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        c->rgraph = g;
+        c->rg_f = f_in;
+        c->rg_u = u;
+        c->rg_out = out;
+        c->rg_stream = stream;
+    }
+    HIPCHK(c, hipGraphLaunch(c->rgraph_exec, st));
+    c->relax_k += 1;
     return FBC_OK;
 }
 
@@ -1326,11 +1378,13 @@ extern "C" fbc_status fbc_relax_get_state(fbc_ctx* c, fbc_relax_opts* opts, int3
     if (!c || !opts || !k || !alpha || !f_prev) return fail(c, FBC_E_ARG, "null argument");
     if (c->relax_k < 0) return fail(c, FBC_E_STATE, "fbc_relax_begin was not called");
     hipStream_t st = (hipStream_t)stream;
+    int32_t kd = 0;
     HIPCHK(c, hipMemcpyAsync(alpha, c->alpha, (size_t)c->total_rhs * sizeof(double), hipMemcpyDefault, st));
     HIPCHK(c, hipMemcpyAsync(f_prev, c->fprev, (size_t)c->f_elems * sizeof(double), hipMemcpyDefault, st));
+    HIPCHK(c, hipMemcpyAsync(&kd, c->status + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     *opts = c->ropt;
-    *k = c->relax_k;
+    *k = kd;
     return FBC_OK;
 }
 
@@ -1341,9 +1395,12 @@ extern "C" fbc_status fbc_relax_set_state(fbc_ctx* c, const fbc_relax_opts* opts
     fbc_status s = check_relax_opts(c, opts);
     if (s != FBC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
+    drop_relax_graph(c);
     HIPCHK(c, hipMemcpyAsync(c->alpha, alpha, (size_t)c->total_rhs * sizeof(double), hipMemcpyDefault, st));
     if (k > 0)
         HIPCHK(c, hipMemcpyAsync(c->fprev, f_prev, (size_t)c->f_elems * sizeof(double), hipMemcpyDefault, st));
+    launch_relax_index(st, c->status + 4, k);
+    HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     c->ropt = *opts;
     c->relax_k = k;
@@ -1357,7 +1414,8 @@ extern "C" fbc_status fbc_sync_status(fbc_ctx* c, void* stream) {
     HIPCHK(c, hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemset(c->status, 0, sizeof(int)));
     if (st & ST_NONFINITE) return fail(c, FBC_E_NONFINITE, "non-finite interface force");
-    if (st & ST_NETFORCE) return fail(c, FBC_E_NETFORCE, "net force per layer exceeds tolerance");
+    if (st & ST_NETFORCE)
+        return fail(c, FBC_E_NETFORCE, "net force of a cell (all interface atoms of all layers) exceeds tolerance");
     return FBC_OK;
 }
 
@@ -1474,6 +1532,7 @@ extern "C" void fbc_destroy(fbc_ctx* c) {
     c->ev.clear();
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    drop_relax_graph(c);
     free_all(c);
     delete c;
 }

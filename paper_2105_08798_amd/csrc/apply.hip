@@ -1034,13 +1034,17 @@ void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, 
 // <f_k, f_{k+1} - f_k>, ||f_{k+1} - f_k||^2 and ||f_{k+1}||_inf.  Stage 2: one block per
 // RHS reduces them in fixed order and sets alpha_{k+1} (alpha = 1 before the third
 // iteration or without relaxation; alpha < 0 -> 1; zero denominator keeps alpha_k).
+// The iteration index k lives in device memory (kdev), read by the kernels and advanced
+// by the last one, so a step captured into a graph replays with the current k.
 // ----------------------------------------------------------------------------------
+__device__ inline int relax_on(const int* __restrict__ kdev, int relax) { return (relax && *kdev >= 2) ? 1 : 0; }
 #define RELAX_PARTS 64
 __global__ void __launch_bounds__(NT) k_relax_part(const double* __restrict__ fnew,
                                                    const double* __restrict__ fprev,
                                                    double* __restrict__ part, int64_t per_rhs,
-                                                   int use_prev) {
+                                                   const int* __restrict__ kdev, int relax) {
     __shared__ double red[3 * NT];
+    const int use_prev = relax_on(kdev, relax);
     const int r = blockIdx.y;
     const double* a = fnew + (int64_t)r * per_rhs;
     const double* b = fprev + (int64_t)r * per_rhs;
@@ -1069,9 +1073,10 @@ __global__ void __launch_bounds__(NT) k_relax_part(const double* __restrict__ fn
 
 __global__ void __launch_bounds__(NT) k_relax_alpha(const double* __restrict__ part, int n_part,
                                                     double* __restrict__ alpha_d,
-                                                    double* __restrict__ finf_d, int use_relax,
-                                                    double alpha_min) {
+                                                    double* __restrict__ finf_d, const int* __restrict__ kdev,
+                                                    int relax, double alpha_min) {
     __shared__ double red[2 * NT];
+    const int use_relax = relax_on(kdev, relax);
     const int r = blockIdx.x;
     double v[2] = {0, 0};
     double mx[1] = {0};
@@ -1097,21 +1102,21 @@ __global__ void __launch_bounds__(NT) k_relax_alpha(const double* __restrict__ p
 }
 
 void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
-                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, int k,
+                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, const int* kdev,
                         int relax, double alpha_min) {
-    const int use = (relax && k >= 2) ? 1 : 0;
     hipLaunchKernelGGL(k_relax_part, dim3(RELAX_PARTS, R), dim3(NT), 0, st, fnew, fprev, part,
-                       per_rhs, use);
+                       per_rhs, kdev, relax);
     hipLaunchKernelGGL(k_relax_alpha, dim3(R), dim3(NT), 0, st, part, RELAX_PARTS, alpha_d, finf_d,
-                       use, alpha_min);
+                       kdev, relax, alpha_min);
 }
 
 // Step bound (the optional bound on the step in Algorithm 2) from the per-block maxima of |w|.
 __global__ void __launch_bounds__(NT) k_relax_clamp(const double* __restrict__ wmax_part,
                                                     int n_part, double* __restrict__ alpha_d,
                                                     double* __restrict__ stepinf_d, double du_max,
-                                                    int use_bound) {
+                                                    const int* __restrict__ kdev, int relax) {
     __shared__ double red[NT];
+    const int use_bound = relax_on(kdev, relax);
     const int r = blockIdx.x;
     double mx[1] = {0};
     for (int b = threadIdx.x; b < n_part; b += NT)
@@ -1126,10 +1131,9 @@ __global__ void __launch_bounds__(NT) k_relax_clamp(const double* __restrict__ w
 }
 
 void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, double* alpha_d,
-                        double* stepinf_d, int R, double du_max, int k, int relax) {
-    const int use = (relax && k >= 2) ? 1 : 0;
+                        double* stepinf_d, int R, double du_max, const int* kdev, int relax) {
     hipLaunchKernelGGL(k_relax_clamp, dim3(R), dim3(NT), 0, st, wmax_part, n_part, alpha_d,
-                       stepinf_d, du_max, use);
+                       stepinf_d, du_max, kdev, relax);
 }
 
 __global__ void __launch_bounds__(NT) k_copy(const double* __restrict__ a, double* __restrict__ b,
@@ -1140,8 +1144,10 @@ __global__ void __launch_bounds__(NT) k_copy(const double* __restrict__ a, doubl
 
 __global__ void k_relax_out(const double* __restrict__ alpha_d, const double* __restrict__ finf_d,
                             const double* __restrict__ stepinf_d, const double* __restrict__ mean_d,
-                            fbc_relax_out* __restrict__ out, int R, int k, double tol_f) {
+                            fbc_relax_out* __restrict__ out, int R, const int* __restrict__ kdev,
+                            double tol_f) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = *kdev;
     if (r >= R) return;
     fbc_relax_out o;
     o.alpha = alpha_d[r];
@@ -1153,14 +1159,24 @@ __global__ void k_relax_out(const double* __restrict__ alpha_d, const double* __
     out[r] = o;
 }
 
+// kdev[0] <- v (v >= 0), or kdev[0] + 1 (v < 0): the iteration index of the relaxation.
+__global__ void k_relax_index(int* __restrict__ kdev, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) kdev[0] = v >= 0 ? v : kdev[0] + 1;
+}
+
+void launch_relax_index(hipStream_t st, int* kdev, int v) {
+    hipLaunchKernelGGL(k_relax_index, dim3(1), dim3(64), 0, st, kdev, v);
+}
+
 void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,
                          const double* alpha_d, const double* finf_d, const double* stepinf_d,
-                         const double* mean_d, fbc_relax_out* out, int R, int k, double tol_f) {
+                         const double* mean_d, fbc_relax_out* out, int R, int* kdev, double tol_f) {
     hipLaunchKernelGGL(k_copy, dim3((unsigned)grid_blocks(n)), dim3(NT), 0, st, fnew, fprev,
                        n);
     if (out)
         hipLaunchKernelGGL(k_relax_out, dim3((R + 63) / 64), dim3(64), 0, st, alpha_d, finf_d,
-                           stepinf_d, mean_d, out, R, k, tol_f);
+                           stepinf_d, mean_d, out, R, kdev, tol_f);
+    launch_relax_index(st, kdev, -1);     // after every reader of k in this step
 }
 
 __global__ void k_fill(double* p, int64_t n, double v) {

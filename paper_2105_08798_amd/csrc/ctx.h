@@ -80,7 +80,15 @@ struct fbc_ctx {
     double* rpart = nullptr;
     double* rmean = nullptr;
     fbc_relax_opts ropt{};
-    int relax_k = -1;
+    int relax_k = -1;               // -1 before fbc_relax_begin; else the host's count of steps
+                                    // (the index itself lives on the device: status[4])
+    // captured relaxation step (fbc_relax_step_graph)
+    hipGraph_t rgraph = nullptr;
+    hipGraphExec_t rgraph_exec = nullptr;
+    const double* rg_f = nullptr;
+    double* rg_u = nullptr;
+    fbc_relax_out* rg_out = nullptr;
+    void* rg_stream = nullptr;
     // per cell partial counts
     std::vector<int> npart_irfft, npart_axpy;
     std::vector<int64_t> wmax_off, sum_part_off, rpart_off;

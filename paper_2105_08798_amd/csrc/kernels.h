@@ -79,13 +79,15 @@ void launch_update_mean(hipStream_t st, const double* u, const double* c, double
                         const double2* shat, const int* shat_on, const unsigned long long* amax,
                         const int* bexp, double alpha, double* mu, const int* status);
 
-// ---- relax (Section 2.3.3, Algorithm 2) ----
+// ---- relax (Section 2.3.3, Algorithm 2); kdev: the iteration index on the device ----
 void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
-                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, int k, int relax,
+                        double* alpha_d, double* finf_d, int R, int64_t per_rhs, const int* kdev, int relax,
                         double alpha_min);
 void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, double* alpha_d,
-                        double* stepinf_d, int R, double du_max, int k, int relax);
+                        double* stepinf_d, int R, double du_max, const int* kdev, int relax);
 void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,
                          const double* alpha_d, const double* finf_d, const double* stepinf_d,
-                         const double* mean_d, fbc_relax_out* out, int R, int k, double tol_f);
+                         const double* mean_d, fbc_relax_out* out, int R, int* kdev, double tol_f);
+// kdev <- v (v >= 0) or kdev + 1 (v < 0)
+void launch_relax_index(hipStream_t st, int* kdev, int v);
 void launch_fill(hipStream_t st, double* p, int64_t n, double v);

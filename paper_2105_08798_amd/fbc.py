@@ -30,6 +30,7 @@ EXPORTED = [
     "fbc_plgf_last_error", "fbc_plgf_create", "fbc_plgf_destroy", "fbc_plgf_table", "fbc_plgf_eval",
     "fbc_hmat_last_error", "fbc_hmat_create", "fbc_hmat_destroy", "fbc_hmat_get_info", "fbc_hmat_partition",
     "fbc_hmat_ranks", "fbc_hmat_apply", "fbc_mlp_forward_noalloc", "fbc_mlp_forward_noalloc_max_rows",
+    "fbc_relax_step_graph",
 ]
 
 
@@ -112,6 +113,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_green_apply.argtypes = [vp, vp, vp, vp]
     lib.fbc_relax_begin.argtypes = [vp, C.POINTER(RelaxOpts), vp]
     lib.fbc_relax_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.fbc_relax_step_graph.argtypes = [vp, vp, vp, vp, vp]
     lib.fbc_relax_get_state.argtypes = [vp, C.POINTER(RelaxOpts), C.POINTER(C.c_int32), vp, vp, vp]
     lib.fbc_relax_set_state.argtypes = [vp, C.POINTER(RelaxOpts), C.c_int32, vp, vp, vp]
     lib.fbc_sync_status.argtypes = [vp, vp]
@@ -165,6 +167,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_hmat_ranks.argtypes = [vp, vp]
     lib.fbc_hmat_apply.argtypes = [vp, vp, vp, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
+                 "fbc_relax_step_graph",
                  "fbc_relax_get_state", "fbc_relax_set_state",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
@@ -278,6 +281,11 @@ class FBC:
         """out: float64 CUDA tensor of at least total_rhs * RELAX_OUT_DOUBLES elements, or None."""
         optr = _dptr(out) if out is not None else None
         self._check(self._lib.fbc_relax_step(self.ctx, _dptr(f), _dptr(u), optr, _stream_handle(stream)))
+
+    def relax_step_graph(self, f, u, out=None, stream=None):
+        """relax_step replayed from a captured HIP graph (stream: a created torch stream)."""
+        optr = _dptr(out) if out is not None else None
+        self._check(self._lib.fbc_relax_step_graph(self.ctx, _dptr(f), _dptr(u), optr, _stream_handle(stream)))
 
     def relax_state(self, stream=None) -> dict:
         """Checkpoint of the relaxation: options, k, alpha_k per RHS (host array) and the

@@ -90,8 +90,9 @@ def test_null_context_calls_fail_cleanly():
     assert lib.fbc_sync_status(None, None) == -1
     assert lib.fbc_relax_get_state(None, None, None, None, None, None) == -1
     assert lib.fbc_relax_set_state(None, None, 0, None, None, None) == -1
+    assert lib.fbc_relax_step_graph(None, None, None, None, None) == -1
     lib.fbc_destroy(None)
-    assert lib.fbc_status_string(-3) == b"non-zero net force per layer"
+    assert lib.fbc_status_string(-3) == b"non-zero net force of a cell (all interface atoms of all layers)"
 
 
 def test_surrogate_form_needs_a_surrogate_object():

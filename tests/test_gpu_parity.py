@@ -538,3 +538,53 @@ def test_relax_checkpoint_resume_is_bitwise(form):
     for g, e in zip(got_out, ref_out[3:]):
         assert np.array_equal(g, e)
     assert torch.equal(ur, ua)
+
+
+@pytest.mark.parametrize("form", ["fp64", "split_fp16"])
+def test_relax_step_graph_matches_eager(form):
+    """Algorithm 1's update with Algorithm 2 replayed from a captured graph: the iteration
+    index lives in device memory, so every replay takes the current k (relaxation from the
+    third step on); each step equals the eager step bit for bit, with eager work between
+    the replays, and the checkpointed index counts the replays."""
+    wl = W.make_single("parity")
+    c = wl.cells[0]
+    dev = _dev()
+    from paper_2105_08798_amd import RELAX_OUT_DOUBLES
+    rng = np.random.default_rng(5)
+    seq = [c.forces]
+    for k in range(6):
+        nxt = 0.5 * seq[-1] + 0.02 * rng.normal(size=c.forces.shape) * (0.5 ** k)
+        nxt -= nxt.mean(axis=2, keepdims=True)
+        seq.append(nxt)
+    u0 = torch.from_numpy(rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01).to(dev)
+    opts = dict(relax=True, du_max=0.05, tol_f=0.2, alpha_min=0.0)
+    a = _ctx(wl.cells, wl.bz, form=form)
+    g = _ctx(wl.cells, wl.bz, form=form)
+    a.relax_begin(**opts)
+    g.relax_begin(**opts)
+    ua, ug = u0.clone(), u0.clone()
+    fbuf = torch.empty(c.forces.size, dtype=torch.float64, device=dev)
+    out_a = torch.zeros(c.n_rhs * RELAX_OUT_DOUBLES, dtype=torch.float64, device=dev)
+    out_g = torch.zeros_like(out_a)
+    stream = torch.cuda.Stream()
+    alphas = []
+    for k, fk in enumerate(seq):
+        fdev = torch.from_numpy(fk.reshape(-1)).to(dev)
+        a.relax_step(fdev, ua, out_a)
+        fbuf.copy_(fdev)                          # the captured step reads this buffer
+        torch.cuda.synchronize()
+        g.relax_step_graph(fbuf, ug, out_g, stream=stream)
+        stream.synchronize()
+        assert a.sync_status() == 0 and g.sync_status() == 0
+        assert torch.equal(ug, ua), k
+        assert torch.equal(out_g, out_a), k
+        from paper_2105_08798_amd import parse_relax_out
+        o = parse_relax_out(out_g)
+        assert all(r["k"] == k for r in o), (k, o)
+        alphas.append([r["alpha"] for r in o])
+    # relaxation takes over at k = 2 (the third step): alpha moves off 1
+    assert all(x == 1.0 for x in alphas[0] + alphas[1])
+    assert any(x != 1.0 for x in sum(alphas[2:], []))
+    assert g.relax_state()["k"] == len(seq)
+    a.close()
+    g.close()
