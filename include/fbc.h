@@ -170,7 +170,8 @@ fbc_status fbc_green_apply(fbc_ctx* ctx, const double* f, double* w, void* strea
  * (non-default) stream that is not itself capturing.  Same contract as fbc_apply. */
 fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alpha, void* stream);
 
-/* Autotuner of the per-mode product launch.  Times every candidate work list -- K split
+/* Autotuner of the per-mode product launch.  Times every candidate -- the product kernel
+ * variants of this context (see fbc_set_kernel_variant) times the work lists: K split
  * into 1, 2, 4, 8 slices (as far as the context's output buffer holds) times the orders:
  * 0 XCD-grouped (all tiles of a mode on one XCD), 1 mode-major, 2 longest-first, 3
  * persistent (jobs longest first, taken from a device work queue by as many work groups
@@ -187,9 +188,27 @@ typedef struct {
     double gemm_ms;       /* average product time of the chosen list */
     int n_candidates;
     double call_ms;       /* average fbc_green_apply time of the chosen list */
+    int variant;          /* product kernel variant (fbc_set_kernel_variant) */
+    int from_cache;       /* fbc_autotune_cached: 1 when taken from the cache file, untimed */
 } fbc_tune_result;
 fbc_status fbc_autotune(fbc_ctx* ctx, const double* f, double* w, int reps, fbc_tune_result* out,
                         void* stream);
+
+/* fbc_autotune with a cache file (text, one line per tuned configuration): when the file
+ * holds a result for this context's key -- form, negligible-block tolerance, row gauge,
+ * in-plane torus, every cell's line length, column sets and RHS count, the product's column
+ * tiles, the device's architecture name and compute-unit count, and the cache format
+ * version -- it is applied without timing (from_cache = 1); otherwise the candidates are
+ * timed as by fbc_autotune and the result is appended to the file (created if missing).
+ * A line whose values fall outside this context's ranges is ignored.  cache_path: host
+ * string; FBC_E_ARG if NULL or the file cannot be written. */
+fbc_status fbc_autotune_cached(fbc_ctx* ctx, const double* f, double* w, int reps, const char* cache_path,
+                               fbc_tune_result* out, void* stream);
+
+/* Selects the product kernel variant: 0 (default) .. n-1, n from fbc_info.n_variants.  The
+ * variants share the store layout and the arithmetic order (prefetch-ring depth, K steps
+ * per barrier), so results are bitwise those of variant 0.  FBC_E_ARG out of range. */
+fbc_status fbc_set_kernel_variant(fbc_ctx* ctx, int variant);
 
 /* Pins the work list of the per-mode product: nsplit K slices (1 .. the context's limit,
  * fbc_info.nsplit after assembly is the default) in the given order (as listed for
@@ -279,6 +298,9 @@ typedef struct {
     double product_flops;      /* real flops of the blocks it does not skip (8 per
                                   complex multiply-add)                                 */
     double skipped_fraction;   /* fraction of the (row, K) block area skipped             */
+    int kernel_variant;        /* product kernel variant in use                           */
+    int n_variants;            /* variants of this context's product (1 for table forms)  */
+    char kernel_shape[96];     /* readable shape of the product kernel in use             */
 } fbc_info;
 fbc_status fbc_get_info(const fbc_ctx* ctx, fbc_info* info);
 

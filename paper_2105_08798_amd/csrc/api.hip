@@ -750,38 +750,46 @@ static std::vector<GemmJob> build_jobs(const fbc_ctx* c, int nsplit, int order, 
 }
 
 static fbc_status upload_jobs(fbc_ctx* c, int nsplit, int order, hipStream_t st) {
+    // the new list, its work lists and chunk starts are formed aside and take effect only
+    // once the list is on the device: a failure leaves the current list in place
     int list_start[9] = {0};
     std::vector<GemmJob> jobs = build_jobs(c, nsplit, order, list_start);
-    c->lists.ctr = c->status + 16;
-    c->lists.nl = (order == 4) ? 8 : 1;
-    if (order == 4)
-        for (int l = 0; l < 9; ++l) c->lists.start[l] = list_start[l];
-    else {
-        for (int l = 0; l < 9; ++l) c->lists.start[l] = (int)jobs.size();
-        c->lists.start[0] = 0;
-    }
-    if ((int64_t)jobs.size() > c->jobs_cap) {
-        fbc_status s = dev_alloc(c, (void**)&c->jobs, (int64_t)jobs.size() * sizeof(GemmJob));
-        if (s != FBC_OK) return s;
-        c->jobs_cap = (int64_t)jobs.size();
-    }
-    c->chunk_job0.clear();
+    PqLists lists{};
+    lists.ctr = c->status + 16;
+    lists.nl = (order == 4) ? 8 : 1;
+    for (int l = 0; l < 9; ++l) lists.start[l] = (order == 4) ? list_start[l] : (l ? (int)jobs.size() : 0);
+    std::vector<int> chunk_job0;
     if (c->opt.form == FBC_FORM_SURROGATE && c->gen_modes > 0) {
         // jobs are in table-mode order; record where each generated chunk starts
         const int T = c->nz_max / 2 + 1;
         size_t j = 0;
         for (int t0 = 0; t0 < T; t0 += c->gen_modes) {
             while (j < jobs.size() && jobs[j].a_off < (int64_t)t0 * c->n_offsets * 6) ++j;
-            c->chunk_job0.push_back((int)j);
+            chunk_job0.push_back((int)j);
         }
-        c->chunk_job0.push_back((int)jobs.size());
+        chunk_job0.push_back((int)jobs.size());
         if (order == 3)      // persistent per chunk: longest job first inside each chunk
-            for (size_t ch = 0; ch + 1 < c->chunk_job0.size(); ++ch)
-                std::stable_sort(jobs.begin() + c->chunk_job0[ch], jobs.begin() + c->chunk_job0[ch + 1],
+            for (size_t ch = 0; ch + 1 < chunk_job0.size(); ++ch)
+                std::stable_sort(jobs.begin() + chunk_job0[ch], jobs.begin() + chunk_job0[ch + 1],
                                  [](const GemmJob& a, const GemmJob& b) { return (a.k1 - a.k0) > (b.k1 - b.k0); });
     }
-    HIPCHK(c, hipMemcpyAsync(c->jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st));
+    // queued launches may still read the current list: wait for them before replacing it
     HIPCHK(c, hipStreamSynchronize(st));
+    GemmJob* dst = c->jobs;
+    if ((int64_t)jobs.size() > c->jobs_cap) {
+        // a larger list is allocated aside (the old one stays allocated until the context
+        // is destroyed), so a failed allocation changes nothing
+        fbc_status s = dev_alloc(c, (void**)&dst, (int64_t)jobs.size() * sizeof(GemmJob));
+        if (s != FBC_OK) return s;
+    }
+    HIPCHK(c, hipMemcpyAsync(dst, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (dst != c->jobs) {
+        c->jobs = dst;
+        c->jobs_cap = (int64_t)jobs.size();
+    }
+    c->lists = lists;
+    c->chunk_job0.swap(chunk_job0);
     c->njobs = (int)jobs.size();
     c->nsplit = nsplit;
     c->job_order = order;
@@ -1079,7 +1087,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
                          c->job_order >= 3 ? &c->lists : nullptr);
     else
         launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf,
-                    c->job_order >= 3 ? &c->lists : nullptr);
+                    c->job_order >= 3 ? &c->lists : nullptr, c->variant);
     if (tm) {
         (void)hipEventRecord(c->ev[2 * c->n_timed + 1], st);
         ++c->n_timed;
@@ -1194,6 +1202,8 @@ extern "C" fbc_status fbc_apply_graph(fbc_ctx* c, const double* f, double* u, do
     return FBC_OK;
 }
 
+static int n_variants(const fbc_ctx* c) { return is_table_form(c->opt.form) ? 1 : gemm_variants(c->opt.form, c->ctmax); }
+
 extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int reps,
                                    fbc_tune_result* out, void* stream) {
     fbc_status s = check_apply_args(c, f, w);
@@ -1213,34 +1223,39 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
         return fail(c, FBC_E_DEVICE, "hipEventCreate failed");
     }
     double best = 1e300, best_gemm = 0.0;
-    int best_split = c->nsplit, best_order = c->job_order, ncand = 0;
-    for (int order = 0; order < 5 && s == FBC_OK; ++order)
-        for (int ks = 1; ks <= c->nsplit_cap && s == FBC_OK; ks *= 2) {
-            if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) break;
-            if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) break;       // warm-up
-            if ((s = fbc_timing_read(c, &ms0, &n0)) != FBC_OK) break;
-            (void)hipEventRecord(e0, st);
-            for (int r = 0; r < reps && s == FBC_OK; ++r) s = fbc_green_apply(c, f, w, stream);
-            if (s != FBC_OK) break;
-            (void)hipEventRecord(e1, st);
-            double ms;
-            int n;
-            if ((s = fbc_timing_read(c, &ms, &n)) != FBC_OK) break;
-            float call = 0.0f;
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&call, e0, e1) != hipSuccess) {
-                s = fail(c, FBC_E_DEVICE, "hipEventElapsedTime failed");
-                break;
+    int best_split = c->nsplit, best_order = c->job_order, best_var = c->variant, ncand = 0;
+    const int nv = n_variants(c);
+    for (int var = 0; var < nv && s == FBC_OK; ++var)
+        for (int order = 0; order < 5 && s == FBC_OK; ++order)
+            for (int ks = 1; ks <= c->nsplit_cap && s == FBC_OK; ks *= 2) {
+                c->variant = var;
+                if ((s = upload_jobs(c, ks, order, st)) != FBC_OK) break;
+                if ((s = fbc_green_apply(c, f, w, stream)) != FBC_OK) break;       // warm-up
+                if ((s = fbc_timing_read(c, &ms0, &n0)) != FBC_OK) break;
+                (void)hipEventRecord(e0, st);
+                for (int r = 0; r < reps && s == FBC_OK; ++r) s = fbc_green_apply(c, f, w, stream);
+                if (s != FBC_OK) break;
+                (void)hipEventRecord(e1, st);
+                double ms;
+                int n;
+                if ((s = fbc_timing_read(c, &ms, &n)) != FBC_OK) break;
+                float call = 0.0f;
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&call, e0, e1) != hipSuccess) {
+                    s = fail(c, FBC_E_DEVICE, "hipEventElapsedTime failed");
+                    break;
+                }
+                ++ncand;
+                if (call / reps < best) {
+                    best = call / reps;
+                    best_gemm = ms / std::max(1, n);
+                    best_split = ks;
+                    best_order = order;
+                    best_var = var;
+                }
             }
-            ++ncand;
-            if (call / reps < best) {
-                best = call / reps;
-                best_gemm = ms / std::max(1, n);
-                best_split = ks;
-                best_order = order;
-            }
-        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    c->variant = best_var;
     if (s == FBC_OK) s = upload_jobs(c, best_split, best_order, st);
     c->timing = timing;
     if (s != FBC_OK) return s;
@@ -1250,7 +1265,100 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
         out->gemm_ms = best_gemm;
         out->n_candidates = ncand;
         out->call_ms = best;
+        out->variant = best_var;
+        out->from_cache = 0;
     }
+    return FBC_OK;
+}
+
+// Key of a tuned configuration: FNV-1a over everything that decides the product's work
+// (form, tolerance, row gauge, torus, cells with their column sets and RHS, column
+// tiles) and the device it ran on.
+static uint64_t tune_key(const fbc_ctx* c) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    const int version = 1;
+    mix(&version, sizeof version);
+    mix(&c->opt.form, sizeof c->opt.form);
+    mix(&c->opt.skip_tol, sizeof c->opt.skip_tol);
+    mix(&c->opt.row_gauge, sizeof c->opt.row_gauge);
+    mix(&c->opt.bz_m1, sizeof c->opt.bz_m1);
+    mix(&c->opt.bz_m2, sizeof c->opt.bz_m2);
+    mix(&c->ctmax, sizeof c->ctmax);
+    for (const CellPlan& p : c->cells) {
+        const int hd[4] = {p.nz, p.n_i, p.n_b, p.R};
+        mix(hd, sizeof hd);
+        mix(p.cols_i.data(), p.cols_i.size() * 4);
+        mix(p.cols_b.data(), p.cols_b.size() * 4);
+    }
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+        mix(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
+        mix(&prop.multiProcessorCount, sizeof prop.multiProcessorCount);
+    }
+    return h;
+}
+
+extern "C" fbc_status fbc_autotune_cached(fbc_ctx* c, const double* f, double* w, int reps, const char* path,
+                                          fbc_tune_result* out, void* stream) {
+    fbc_status s = check_apply_args(c, f, w);
+    if (s != FBC_OK) return s;
+    if (!path) return fail(c, FBC_E_ARG, "cache_path is NULL");
+    if (c->opt.form == FBC_FORM_SURROGATE) return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major list");
+    char key[17];
+    snprintf(key, sizeof key, "%016llx", (unsigned long long)tune_key(c));
+    // the last valid line for this key wins
+    int var = -1, ns = 0, ord = 0;
+    double gm = 0, cm = 0;
+    if (FILE* fp = std::fopen(path, "r")) {
+        char line[256];
+        while (std::fgets(line, sizeof line, fp)) {
+            char k[32];
+            int v, n, o;
+            double g, cc;
+            if (std::sscanf(line, "fbc-tune %31s %d %d %d %lf %lf", k, &v, &n, &o, &g, &cc) == 6 &&
+                std::strcmp(k, key) == 0 && v >= 0 && v < n_variants(c) && n >= 1 && n <= c->nsplit_cap && o >= 0 &&
+                o <= 4) {
+                var = v;
+                ns = n;
+                ord = o;
+                gm = g;
+                cm = cc;
+            }
+        }
+        std::fclose(fp);
+    }
+    if (var >= 0) {
+        c->variant = var;
+        if ((s = upload_jobs(c, ns, ord, (hipStream_t)stream)) != FBC_OK) return s;
+        if (out) *out = fbc_tune_result{ns, ord, gm, 0, cm, var, 1};
+        return FBC_OK;
+    }
+    fbc_tune_result r{};
+    if ((s = fbc_autotune(c, f, w, reps, &r, stream)) != FBC_OK) return s;
+    FILE* fp = std::fopen(path, "a");
+    if (!fp) return fail(c, FBC_E_ARG, std::string("cannot append to the cache file ") + path);
+    std::fprintf(fp, "fbc-tune %s %d %d %d %.6f %.6f\n", key, r.variant, r.nsplit, r.order, r.gemm_ms, r.call_ms);
+    std::fclose(fp);
+    if (out) *out = r;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_set_kernel_variant(fbc_ctx* c, int variant) {
+    if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
+    if (variant < 0 || variant >= n_variants(c))
+        return fail(c, FBC_E_ARG, "variant must be in [0, " + std::to_string(n_variants(c)) + ")");
+    if (variant != c->variant && c->graph_exec) {      // the captured update launches the old kernel
+        (void)hipGraphExecDestroy(c->graph_exec);
+        (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+    }
+    if (variant != c->variant) drop_relax_graph(c);
+    c->variant = variant;
     return FBC_OK;
 }
 
@@ -1434,6 +1542,11 @@ extern "C" fbc_status fbc_get_info(const fbc_ctx* c, fbc_info* info) {
     info->product_bytes = c->product_bytes;
     info->product_flops = c->product_flops;
     info->skipped_fraction = c->skipped_fraction;
+    info->kernel_variant = c->variant;
+    info->n_variants = n_variants(c);
+    const std::string shape = is_table_form(c->opt.form) ? std::string("offset table, 32 pad columns x 8 interface columns per step")
+                                                         : gemm_shape(c->opt.form, c->ctmax, c->variant);
+    std::snprintf(info->kernel_shape, sizeof info->kernel_shape, "%s", shape.c_str());
     return FBC_OK;
 }
 

@@ -42,7 +42,8 @@ struct fbc_ctx {
     int njobs = 0;
     int nsplit = 1;                 // K slices of the per-mode product
     int nsplit_cap = 1;             // K slices the output buffer holds
-    int job_order = 0;              // see build_jobs (3: persistent kernel, offset-table forms)
+    int job_order = 0;              // see build_jobs (3, 4: persistent kernel)
+    int variant = 0;                // product kernel variant (gemm_variants)
     int64_t jobs_cap = 0;
     // captured update (fbc_apply_graph)
     hipGraph_t graph = nullptr;

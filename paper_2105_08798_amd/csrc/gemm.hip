@@ -127,6 +127,8 @@ __device__ inline void gemm_f64_job(const GemmJob& jb,
                                                   const double* __restrict__ A,
                                                   const double* __restrict__ B,
                                                   double* __restrict__ C) {
+    // the main loop runs whole ring passes: the ring must divide the 8 steps of a 64-k' chunk
+    static_assert(8 % PF == 0, "ring depth must divide the steps of a chunk");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
@@ -211,6 +213,8 @@ __device__ inline void gemm_f32_job(const GemmJob& jb,
                                                   const float* __restrict__ A,
                                                   const float* __restrict__ B,
                                                   double* __restrict__ C) {
+    static_assert(4 % PF == 0, "ring depth must divide the 4 steps of a 64-k' chunk");
+    static_assert(KCH % PF == 0, "FP32 chunks are whole ring passes");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
@@ -323,6 +327,8 @@ __device__ inline void gemm_split_job(const GemmJob& jb,
                                                     const unsigned short* __restrict__ A,
                                                     const unsigned short* __restrict__ B,
                                                     double* __restrict__ C) {
+    static_assert(2 % PF == 0, "ring depth must divide the 2 steps of a 64-k' chunk");
+    static_assert(KCH % PF == 0, "FP32 chunks are whole ring passes");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int rbw = jb.rb0 + wave * RB;
     if (rbw >= jb.mb) return;
@@ -618,41 +624,80 @@ static void launch_dense(void (*kn)(const GemmJob*, const TA*, const TA*, double
         hipLaunchKernelGGL(kn, dim3(njobs), dim3(threads), 0, st, jobs, (const TA*)a, (const TA*)b, c);
 }
 
+// Kernel variants of a product class (form, column tiles) that the autotuner may choose
+// from.  They share the tile height (the compact store is laid out in tiles) and the
+// arithmetic order, so every variant gives bitwise the same result: variant 0 is the
+// default; variant 1 changes the depth of the prefetch ring (FP64, FP32) or the K steps
+// per barrier (split products staging B in LDS).  The split products with one or two
+// column tiles have one variant: their main loop runs whole ring passes, and a 64-k'
+// chunk is two of their steps, so the ring cannot be deeper than two steps.
+int gemm_variants(int form, int ctmax) {
+    if ((form == FBC_FORM_SPLIT_FP16 || form == FBC_FORM_SPLIT_BF16) && ctmax <= 2) return 1;
+    return 2;
+}
+
+// Readable shape of a variant: kernel, row blocks per wave, column tiles, ring depth,
+// FP32 chunk (K steps), K steps per barrier, waves per group.
+std::string gemm_shape(int form, int ctmax, int variant) {
+    const int ct = ctmax <= 1 ? 1 : ctmax <= 2 ? 2 : ctmax <= 4 ? 4 : 8;
+    const bool alt = variant == 1;
+    char buf[96];
+    if (form == FBC_FORM_FP64) {
+        const int rb = ct <= 2 ? 4 : 2, pf = (ct <= 2) != alt ? 4 : 2;
+        snprintf(buf, sizeof buf, "f64 RB=%d CT=%d PF=%d waves=4", rb, ct, pf);
+    } else if (form == FBC_FORM_FP32) {
+        const int rb = ct == 2 ? 4 : 2, pf = (ct <= 2) != alt ? 4 : 2;
+        snprintf(buf, sizeof buf, "f32 RB=%d CT=%d PF=%d KCH=16 waves=4", rb, ct, pf);
+    } else if (ct <= 2) {
+        const bool f16 = form == FBC_FORM_SPLIT_FP16;
+        snprintf(buf, sizeof buf, "split %s RB=%d CT=%d PF=2 KCH=%d waves=4", f16 ? "f16" : "bf16", ct == 2 ? 4 : 2,
+                 ct, f16 ? 2 : 8);
+    } else {
+        const bool f16 = form == FBC_FORM_SPLIT_FP16;
+        snprintf(buf, sizeof buf, "split_lds %s RB=2 CT=%d PFA=4 KCH=%d S=%d waves=4", f16 ? "f16" : "bf16", ct,
+                 f16 ? 4 : 8, alt ? 1 : 2);
+    }
+    return buf;
+}
+
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
-                 const void* a, const void* b, double* c, const PqLists* q) {
+                 const void* a, const void* b, double* c, const PqLists* q, int variant) {
     if (njobs <= 0) return;
 #define GEMM_CASE(KERN, RB, CT, ...)                                                           \
     launch_dense<TA>(KERN<RB, CT, __VA_ARGS__>, KERN##_pq<RB, CT, __VA_ARGS__>, st, jobs, njobs, a, b, c, q)
-
+#define GEMM_PICK(DEF, ALT) do { if (variant == 1) ALT; else DEF; } while (0)
     if (form == FBC_FORM_FP64) {
         typedef double TA;
-        if (ctmax <= 1) GEMM_CASE(k_gemm_f64, 4, 1, 4);
-        else if (ctmax <= 2) GEMM_CASE(k_gemm_f64, 4, 2, 4);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_f64, 2, 4, 2);
-        else GEMM_CASE(k_gemm_f64, 2, 8, 2);
+        if (ctmax <= 1) GEMM_PICK(GEMM_CASE(k_gemm_f64, 4, 1, 4), GEMM_CASE(k_gemm_f64, 4, 1, 2));
+        else if (ctmax <= 2) GEMM_PICK(GEMM_CASE(k_gemm_f64, 4, 2, 4), GEMM_CASE(k_gemm_f64, 4, 2, 2));
+        else if (ctmax <= 4) GEMM_PICK(GEMM_CASE(k_gemm_f64, 2, 4, 2), GEMM_CASE(k_gemm_f64, 2, 4, 4));
+        else GEMM_PICK(GEMM_CASE(k_gemm_f64, 2, 8, 2), GEMM_CASE(k_gemm_f64, 2, 8, 4));
     } else if (form == FBC_FORM_FP32) {
         typedef float TA;
-        if (ctmax <= 1) GEMM_CASE(k_gemm_f32, 2, 1, 4, 16);
-        else if (ctmax <= 2) GEMM_CASE(k_gemm_f32, 4, 2, 4, 16);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_f32, 2, 4, 2, 16);
-        else GEMM_CASE(k_gemm_f32, 2, 8, 2, 16);
+        if (ctmax <= 1) GEMM_PICK(GEMM_CASE(k_gemm_f32, 2, 1, 4, 16), GEMM_CASE(k_gemm_f32, 2, 1, 2, 16));
+        else if (ctmax <= 2) GEMM_PICK(GEMM_CASE(k_gemm_f32, 4, 2, 4, 16), GEMM_CASE(k_gemm_f32, 4, 2, 2, 16));
+        else if (ctmax <= 4) GEMM_PICK(GEMM_CASE(k_gemm_f32, 2, 4, 2, 16), GEMM_CASE(k_gemm_f32, 2, 4, 4, 16));
+        else GEMM_PICK(GEMM_CASE(k_gemm_f32, 2, 8, 2, 16), GEMM_CASE(k_gemm_f32, 2, 8, 4, 16));
     } else if (form == FBC_FORM_SPLIT_FP16) {
         // shorter FP32 chunks: the representation error is ~2^-23, so the FP32 sums must
         // not dominate
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 2, 1, 2, 2);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2, 4);
-        else GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2, 4);
+        else if (ctmax <= 4)
+            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2, 4), GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 1, 4));
+        else
+            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2, 4), GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 1, 4));
     } else {
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 2, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
-        // two K steps per barrier: 2 % faster than one on the 64-RHS workload (measured;
-        // the split-FP16 kernel gained nothing and keeps one)
-        else if (ctmax <= 4) GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2, 4);
-        else GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2, 4);
+        else if (ctmax <= 4)
+            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2, 4), GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 1, 4));
+        else
+            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2, 4), GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 1, 4));
     }
+#undef GEMM_PICK
 #undef GEMM_CASE
 }
 

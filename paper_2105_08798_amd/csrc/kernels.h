@@ -45,9 +45,12 @@ void launch_netforce(hipStream_t st, const double* f, double* sums, double* tot,
 void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
                       void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw,
                       const int* bexp);
+// variant: one of gemm_variants(form, ctmax) kernel instantiations (bitwise the same result)
 void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int ctmax,
                  const void* a, const void* b, double* c,
-                 const PqLists* q);   // q != NULL: persistent work-queue kernel on these lists
+                 const PqLists* q, int variant);   // q != NULL: persistent work-queue kernel on these lists
+int gemm_variants(int form, int ctmax);
+std::string gemm_shape(int form, int ctmax, int variant);
 // Offset-table form: 32 pad columns x all interface columns per work group, table
 // entries gathered into LDS in MFMA fragment order.
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,

@@ -30,7 +30,7 @@ EXPORTED = [
     "fbc_plgf_last_error", "fbc_plgf_create", "fbc_plgf_destroy", "fbc_plgf_table", "fbc_plgf_eval",
     "fbc_hmat_last_error", "fbc_hmat_create", "fbc_hmat_destroy", "fbc_hmat_get_info", "fbc_hmat_partition",
     "fbc_hmat_ranks", "fbc_hmat_apply", "fbc_mlp_forward_noalloc", "fbc_mlp_forward_noalloc_max_rows",
-    "fbc_relax_step_graph",
+    "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant",
 ]
 
 
@@ -73,7 +73,8 @@ class Info(C.Structure):
                 ("scratch_bytes", C.c_int64), ("f_elems", C.c_int64), ("u_elems", C.c_int64),
                 ("n_offsets", C.c_int64), ("nsplit", C.c_int), ("job_order", C.c_int),
                 ("n_jobs", C.c_int), ("product_bytes", C.c_double), ("product_flops", C.c_double),
-                ("skipped_fraction", C.c_double)]
+                ("skipped_fraction", C.c_double), ("kernel_variant", C.c_int), ("n_variants", C.c_int),
+                ("kernel_shape", C.c_char * 96)]
 
 
 class PlgfOpts(C.Structure):
@@ -91,7 +92,8 @@ class HmatInfo(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("nsplit", C.c_int), ("order", C.c_int), ("gemm_ms", C.c_double),
-                ("n_candidates", C.c_int), ("call_ms", C.c_double)]
+                ("n_candidates", C.c_int), ("call_ms", C.c_double), ("variant", C.c_int),
+                ("from_cache", C.c_int)]
 
 
 _lib = None
@@ -121,6 +123,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_copy_block_rows.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
     lib.fbc_apply_graph.argtypes = [vp, vp, vp, C.c_double, vp]
     lib.fbc_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(TuneResult), vp]
+    lib.fbc_autotune_cached.argtypes = [vp, vp, vp, C.c_int, cp, C.POINTER(TuneResult), vp]
+    lib.fbc_set_kernel_variant.argtypes = [vp, C.c_int]
     lib.fbc_set_work_list.argtypes = [vp, C.c_int, C.c_int, vp]
     lib.fbc_timing.argtypes = [vp, C.c_int]
     lib.fbc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
@@ -167,7 +171,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_hmat_ranks.argtypes = [vp, vp]
     lib.fbc_hmat_apply.argtypes = [vp, vp, vp, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
-                 "fbc_relax_step_graph",
+                 "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant",
                  "fbc_relax_get_state", "fbc_relax_set_state",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
@@ -261,13 +265,25 @@ class FBC:
         self._check(self._lib.fbc_set_work_list(self.ctx, int(nsplit), int(order), _stream_handle(stream)))
         self.info = self.get_info()
 
-    def autotune(self, f, w, reps: int = 3, stream=None) -> dict:
+    def autotune(self, f, w, reps: int = 3, cache: str | None = None, stream=None) -> dict:
+        """Tunes the product launch (kernel variant, K slices, order); with `cache` (a file
+        path) a stored result for the same configuration is applied untimed, and a new one
+        is appended."""
         r = TuneResult()
-        self._check(self._lib.fbc_autotune(self.ctx, _dptr(f), _dptr(w), int(reps), C.byref(r),
-                                           _stream_handle(stream)))
+        if cache is None:
+            self._check(self._lib.fbc_autotune(self.ctx, _dptr(f), _dptr(w), int(reps), C.byref(r),
+                                               _stream_handle(stream)))
+        else:
+            self._check(self._lib.fbc_autotune_cached(self.ctx, _dptr(f), _dptr(w), int(reps),
+                                                      os.fsencode(cache), C.byref(r), _stream_handle(stream)))
         self.info = self.get_info()
         return dict(nsplit=r.nsplit, order=r.order, gemm_ms=r.gemm_ms, n_candidates=r.n_candidates,
-                    call_ms=r.call_ms)
+                    call_ms=r.call_ms, variant=r.variant, from_cache=bool(r.from_cache),
+                    shape=self.info.kernel_shape.decode())
+
+    def set_kernel_variant(self, variant: int):
+        self._check(self._lib.fbc_set_kernel_variant(self.ctx, int(variant)))
+        self.info = self.get_info()
 
     def green_apply(self, f, w, stream=None):
         self._check(self._lib.fbc_green_apply(self.ctx, _dptr(f), _dptr(w), _stream_handle(stream)))

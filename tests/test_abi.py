@@ -120,5 +120,5 @@ def test_learned_calls_reject_bad_arguments_on_the_host():
 
 def test_tune_result_layout_and_null_context_work_list():
     fbc, lib = _lib()
-    assert C.sizeof(fbc.TuneResult) == 32
+    assert C.sizeof(fbc.TuneResult) == 40
     assert lib.fbc_set_work_list(None, 1, 0, None) == -1

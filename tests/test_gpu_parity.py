@@ -588,3 +588,67 @@ def test_relax_step_graph_matches_eager(form):
     assert g.relax_state()["k"] == len(seq)
     a.close()
     g.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("R", [3, 12, 20, 64])
+def test_kernel_variants_are_bitwise_equal(form, R):
+    """Every product kernel variant the autotuner may choose (ring depth, K steps per
+    barrier) for each column-tile class gives bitwise the result of the default, which
+    matches the oracle at the form's bound."""
+    dev = _dev()
+    wl = W.make_custom(8, 70, 110, R, 32, seed=R + 3)
+    c = wl.cells[0]
+    ctx = _ctx(wl.cells, wl.bz, form=form)
+    f = torch.from_numpy(c.forces).to(dev)
+    outs = []
+    for v in range(ctx.info.n_variants):
+        ctx.set_kernel_variant(v)
+        assert ctx.info.kernel_variant == v and ctx.info.kernel_shape
+        w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+        ctx.green_apply(f, w)
+        assert ctx.sync_status() == 0
+        outs.append(w.cpu().numpy())
+        print(form, R, v, ctx.info.kernel_shape.decode(), flush=True)
+    from paper_2105_08798_amd.fbc import FbcError
+    with pytest.raises(FbcError):
+        ctx.set_kernel_variant(ctx.info.n_variants)
+    ctx.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    ref = oap.apply_green(oracle_green(c, wl.bz), c.forces)
+    bound = {"fp64": 1e-10, "fp32": 1e-6, "split_bf16": 2e-5, "split_fp16": 1e-6}[form]
+    e2, _ = rel_err(outs[0], ref)
+    assert e2 < bound, (form, R, e2)
+
+
+def test_autotune_cache_file(tmp_path):
+    """The tuned choice is written to the cache file and applied untimed to a new context
+    of the same configuration (bitwise the same result); other configurations miss."""
+    dev = _dev()
+    wl = W.make_custom(16, 60, 100, 9, 32, seed=4)
+    c = wl.cells[0]
+    path = str(tmp_path / "tune.txt")
+    f = torch.from_numpy(c.forces).to(dev)
+    w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+    a = _ctx(wl.cells, wl.bz, form="fp32")
+    ra = a.autotune(f, w, reps=1, cache=path)
+    assert not ra["from_cache"] and ra["n_candidates"] > 1
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("fbc-tune ")
+    wa = torch.zeros_like(w)
+    a.green_apply(f, wa)
+    b = _ctx(wl.cells, wl.bz, form="fp32")
+    rb = b.autotune(f, w, reps=1, cache=path)
+    assert rb["from_cache"] and (rb["variant"], rb["nsplit"], rb["order"]) == (ra["variant"], ra["nsplit"], ra["order"])
+    assert (b.info.kernel_variant, b.info.nsplit, b.info.job_order) == (ra["variant"], ra["nsplit"], ra["order"])
+    wb = torch.zeros_like(w)
+    b.green_apply(f, wb)
+    assert a.sync_status() == 0 and b.sync_status() == 0
+    assert torch.equal(wa, wb)
+    # another form is another key: tuned and appended
+    d = _ctx(wl.cells, wl.bz, form="fp64")
+    rd = d.autotune(f, w, reps=1, cache=path)
+    assert not rd["from_cache"] and len(open(path).read().splitlines()) == 2
+    for x in (a, b, d):
+        x.close()
