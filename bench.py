@@ -95,11 +95,13 @@ def measured_traffic(workload: str, form: str, product_bytes: float):
     return None
 
 
-def train_surrogate(torch, wl, steps: int, seed: int = 0):
+def train_surrogate(torch, wl, steps: int, seed: int = 0, r_c: float = 6.0, s_exact: float = 12.0,
+                    s_learn: float = 20.0, keep_net: bool = False):
     """Far-field object with a trained MLP.  Training data: lattice values of an offset-table
     context of a ring of 1280 interface / 2560 pad columns -- a geometry none of the
     workloads uses, so the timed cell's offsets are held out -- on the workload's line grid
-    and in-plane torus; training runs on the library's own kernels."""
+    and in-plane torus; training runs on the library's own kernels.  The held-out error is
+    the network's relative error on samples of the same table drawn with another seed."""
     import math
     import fbc_workloads as W
     from paper_2105_08798_amd import FBC, MLP, Surrogate
@@ -108,8 +110,11 @@ def train_surrogate(torch, wl, steps: int, seed: int = 0):
     nz = max(c.nz for c in wl.cells)
     src = W.make_custom(nz, 1280, 2560, 1, wl.bz, seed=seed + 77)
     tab = FBC(src.cells, src.bz, form="dtable_fp64")
-    sur = Surrogate(r_c=6.0)
+    sur = Surrogate(r_c=r_c)
+    sur.set_exact_range(s_exact)
+    sur.set_learn_range(s_learn)
     x, t = sur.training_set(tab, 1 << 19, seed=seed)
+    xh, th = sur.training_set(tab, 1 << 13, seed=seed + 1000)     # one batch (max_batch rows)
     tab.close()
     del tab
     torch.cuda.empty_cache()
@@ -129,11 +134,18 @@ def train_surrogate(torch, wl, steps: int, seed: int = 0):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     sur.set_mlp(net)
+    yh = torch.empty_like(th)
+    net.forward(xh, yh)
+    torch.cuda.synchronize()
+    held = float((torch.linalg.norm(yh - th) / torch.linalg.norm(th)).item())
     info = dict(samples=int(n), steps=steps, batch=batch, final_batch_loss=float(loss.item()),
+                heldout_rel_err=held, r_c=r_c, s_exact=s_exact, s_learn=s_learn,
                 data_s=t_data, train_s=t_train, source=f"offset table, {src.description}, M={src.bz}")
-    net.close()
     log(f"surrogate: {n} samples in {t_data:.1f} s, {steps} Adam steps in {t_train:.1f} s, "
-        f"last batch loss {info['final_batch_loss']:.3e}")
+        f"last batch loss {info['final_batch_loss']:.3e}, held-out relative error {held:.3e}")
+    if keep_net:
+        return sur, info, net
+    net.close()
     return sur, info
 
 
@@ -590,14 +602,80 @@ def bench_hmat(args, torch) -> dict:
     return line
 
 
+def bench_learned_budget(args, torch) -> dict:
+    """Error budget of the learned far field on the long workload against the FP64 oracle's
+    sampled line spectrum (tests/golden/long_modes.npz).  The surrogate keeps a line mode's
+    exact lattice values out to the last block of exp(-s_exact) times the mode's largest,
+    applies continuum + learned correction out to exp(-s_learn), the continuum alone
+    beyond.  For (s_exact, s_learn) = (4, 12), (8, 16), (12, 20): the exact table's size,
+    and the error with the continuum alone in the learned band, with the learned
+    correction in BF16 weights, and with the same network's FP32 weights."""
+    import fbc_workloads as W
+    from paper_2105_08798_amd import FBC, MLP
+    wl = W.make_single("long")
+    c = wl.cells[0]
+    kind, gold = golden("long")
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(c.forces).to(dev)
+    cols = torch.from_numpy(np.asarray(gold["cols"])).to(dev)
+    zero = MLP(max_batch=16, seed=0)
+    zero.params(np.zeros(zero.n_params, dtype=np.float32))
+    rows = []
+
+    def err(sur):
+        ctx = FBC(wl.cells, wl.bz, form="surrogate", surrogate=sur)
+        store = ctx.info.store_bytes
+        w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
+        ctx.green_apply(f, w)
+        if ctx.sync_status() != 0:
+            raise RuntimeError("surrogate apply failed")
+        w_cols = w[:, :, cols, :].cpu().numpy()
+        ctx.close()
+        del w
+        torch.cuda.empty_cache()
+        # whole sampled spectrum, and per sampled mode (relative to that mode's values)
+        spec = np.fft.rfft(w_cols, axis=1)[:, gold["modes"]]
+        ref = gold["what"]
+        per_mode = [rel_err(spec[:, k], ref[:, k]) for k in range(ref.shape[1])]
+        return oracle_error(kind, gold, w_cols), per_mode, store
+
+    for s_exact, s_learn in ((4.0, 12.0), (8.0, 16.0), (12.0, 20.0)):
+        sur, info, net = train_surrogate(torch, wl, args.train_steps, s_exact=s_exact, s_learn=s_learn,
+                                         keep_net=True)
+        e_bf16, m_bf16, store = err(sur)
+        sur.set_mlp(net, fp32=True)
+        e_fp32, m_fp32, _ = err(sur)
+        sur.set_mlp(zero)
+        e_cont, m_cont, _ = err(sur)
+        row = dict(s_exact=s_exact, s_learn=s_learn, exact_table_bytes=int(store), continuum_only=e_cont,
+                   learned_bf16=e_bf16, learned_fp32=e_fp32, modes=[int(m) for m in gold["modes"]],
+                   per_mode_continuum_only=m_cont, per_mode_learned_bf16=m_bf16, per_mode_learned_fp32=m_fp32,
+                   heldout_rel_err=info["heldout_rel_err"], train_s=info["train_s"], steps=info["steps"])
+        log(f"budget s_exact={s_exact} s_learn={s_learn}: exact table {store / 1e9:.2f} GB; continuum "
+            f"{e_cont:.3e}, learned bf16 {e_bf16:.3e}, fp32 {e_fp32:.3e}, held-out {info['heldout_rel_err']:.3e}")
+        log(f"   per mode {row['modes']}: continuum {[f'{x:.1e}' for x in m_cont]}; "
+            f"bf16 {[f'{x:.1e}' for x in m_bf16]}; fp32 {[f'{x:.1e}' for x in m_fp32]}")
+        rows.append(row)
+        net.close()
+        sur.close()
+    zero.close()
+    return {"metric": "learned far field: relative pad-update error vs the FP64 oracle (sampled line spectrum)",
+            "value": min(r["learned_bf16"] for r in rows), "unit": "relative error", "n_gpus": 1,
+            "higher_is_better": False, "dtype": DTYPE["surrogate"], "data": "synthetic",
+            "config": {"workload": f"long: {wl.description}, in-plane torus M={wl.bz}",
+                       "oracle_samples": f"{len(gold['modes'])} line modes x {len(gold['cols'])} pad columns",
+                       "train_steps": args.train_steps},
+            "budget": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=None,
-                    help="one workload only (long, large, medium, batched, plgf, hmat); default: long "
-                         "(headline) and large in one line")
+                    help="one workload only (long, large, medium, batched, plgf, hmat, learned: the "
+                         "learned far field's error budget); default: long (headline) and large in one line")
     ap.add_argument("--forms", default=None, help="comma-separated forms of the headline workload")
     ap.add_argument("--graph", action="store_true", help="replay the update from a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
@@ -623,6 +701,9 @@ def main() -> int:
         return 0
     if args.workload == "hmat":
         print(json.dumps(bench_hmat(args, torch)), flush=True)
+        return 0
+    if args.workload == "learned":
+        print(json.dumps(bench_learned_budget(args, torch)), flush=True)
         return 0
 
     if args.copy_calibration:

@@ -85,11 +85,11 @@ typedef enum {
                                  (entries depend on n_b - n_i only), gathered into LDS
                                  tiles and applied on FP64 MFMA                               */
     FBC_FORM_SURROGATE = 4,   /* offset-table product whose table is generated per mode
-                                 chunk before each product: exact lattice values for
-                                 in-plane distances <= r_c (kept, FP64), beyond it the
-                                 continuum Green function plus a learned correction
-                                 (Appendix B: exact near field, continuum far field);
-                                 needs options.surrogate with MLP weights set             */
+                                 chunk before each product: exact lattice values (kept,
+                                 FP64) near the source, beyond them the continuum Green
+                                 function plus a learned correction (Appendix B: exact
+                                 near field, continuum far field; bands below); needs
+                                 options.surrogate with MLP weights set                    */
     FBC_FORM_SPLIT_FP16 = 5   /* dense split-FP16 blocks, scaled per line mode by a power of
                                  two (hi = fp16(2^e G), lo = fp16(2^e G - hi): 22 bits at the
                                  bytes of split BF16), forces likewise scaled per call, FP16
@@ -329,18 +329,30 @@ const char* fbc_last_error(const fbc_ctx* ctx);
  *     G_cgf(m; dn) = (1/c) exp(i pi theta0 dn1) G^_K(kappa, r_perp),
  * G^_K the line transform of the anisotropic Kelvin solution of the cubic continuum
  * with C11 = 2k/a, C12 = C44 = k/a (nearest-neighbour springs); m = 0 is regularised by
- * dropping the 2 G_K(t) log(kappa) divergence (a constant gauge).  As in Appendix B, the
- * lattice and continuum functions are matched by a constant: in a context, line mode 0
- * adds C = mean of (G_lgf - G_cgf) over its exact offsets with r_c - 1.5 < rho <= r_c.
- * The learned correction is
- *     G_lgf - G_cgf - C [m = 0] = env * exp(i pi theta0 dn1) * MLP(features),
- * features = (cos phi, sin phi, cos 2phi, sin 2phi, cos 4phi, sin 4phi, r_c / rho,
- * 8 theta0), phi the in-plane angle from [001] towards [110], env = ||G_cgf||_F + 1e-3,
- * the MLP 8 -> 128 -> 128 -> 128 -> 12 with SiLU activations giving the 6 complex
- * components of the symmetric 3x3 block (xx, yy, zz, xy, xz, yz).  The correction is
- * applied where kappa rho <= 6; beyond, blocks are below about 1e-3 of the line-mode-0
- * scale and the continuum value is used alone.  Offsets with rho <= r_c are always
- * taken from the exact table.
+ * dropping the 2 G_K(t) log(kappa) divergence (a constant gauge).  A surrogate context
+ * takes line mode 0 exact for every offset (a table of one mode): the exact Green function
+ * lives on the in-plane torus of the context, whose images act on line mode 0 only (they
+ * are damped by exp(-kappa L) at m >= 1), and no infinite-plane continuum far field can
+ * follow them -- which also makes Appendix B's matching constant unnecessary.  For m >= 1
+ * the offsets, sorted by in-plane distance rho, are split into bands by the lattice
+ * values themselves (a context computes every mode's exact values once, at creation, to
+ * find them; the values fall roughly like exp(-kappa rho), kappa = 2 pi theta0 / c, but
+ * more slowly than the continuum's at large theta0):
+ *   exact: rho <= r_c, and out to the last block (largest |component|) of at least
+ *     exp(-s_exact) times the mode's largest block (default s_exact = 12;
+ *     fbc_sur_set_exact_range); stored per mode as a ragged prefix;
+ *   learned: out to the last block of at least exp(-s_learn) times the largest (default
+ *     s_learn = 20; fbc_sur_set_learn_range): continuum plus the learned correction
+ *       G_lgf - G_cgf = env * exp(i pi theta0 dn1) * MLP(features),
+ *     features = (cos phi, sin phi, cos 2phi, sin 2phi, cos 4phi, sin 4phi, r_c / rho,
+ *     8 theta0), phi the in-plane angle from [001] towards [110], env = exp(-s_exact)
+ *     times the mode's largest block (the band's largest values, so the targets are of
+ *     order one or less), the MLP 8 -> 128 -> 128 -> 128 -> 12 with SiLU activations
+ *     giving the 6 complex components of the symmetric 3x3 block (xx, yy, zz, xy, xz,
+ *     yz); applied out to the largest distance of its training data, the continuum
+ *     alone beyond;
+ *   continuum: out to the last block above the context's skip tolerance (the continuum
+ *     value alone, zero where kappa rho > 40);  beyond: zero.
  * ------------------------------------------------------------------------------------ */
 
 /* Last error text of the fbc_sur_* / fbc_mlp_* calls on this host thread. */
@@ -358,22 +370,42 @@ void fbc_sur_destroy(fbc_sur* s);
  * Synchronises `stream`. */
 fbc_status fbc_sur_set_mlp(fbc_sur* s, const fbc_mlp* net, void* stream);
 
+/* The same with the FP32 weights kept as they are (inference with FP32 weights and FP32
+ * accumulation): the control that separates the BF16 rounding of the weights from the
+ * network's own fit in an error budget.  Replaces the BF16 weights until fbc_sur_set_mlp
+ * is called again.  Synchronises `stream`. */
+fbc_status fbc_sur_set_mlp_fp32(fbc_sur* s, const fbc_mlp* net, void* stream);
+
+/* End of the learned band (exp(-s_learn) of a mode's largest block): s_learn in (0, 40];
+ * default 20.  Read when a context is created and by fbc_sur_training_set. */
+fbc_status fbc_sur_set_learn_range(fbc_sur* s, double s_learn);
+
+/* End of the exact band (exp(-s_exact) of a mode's largest block): s_exact in [0, 40];
+ * default 12.  Read when a context is created (it fixes the size of the context's exact
+ * table, fbc_info's store_bytes) and by fbc_sur_training_set. */
+fbc_status fbc_sur_set_exact_range(fbc_sur* s, double s_exact);
+
 /* Evaluates n blocks: out[n][6] complex (interleaved re, im; device) at line wavenumber
  * theta0[n] in [0, 1/2] and column offsets dn1[n], dn2[n] (all device).  use_mlp = 0:
- * continuum value only; 1: continuum + learned correction (rho > r_c; rho <= r_c returns
- * the continuum value, since the exact table lives in a context).  The matching constant
- * C also belongs to a context and is not added here.  Asynchronous. */
+ * continuum value only; 1: continuum + the network's correction with env = 1 (a context
+ * scales it by its per-mode envelope; rho <= r_c returns the continuum value, since the
+ * exact values live in a context).  Asynchronous. */
 fbc_status fbc_sur_eval(const fbc_sur* s, const double* theta0, const int32_t* dn1,
                         const int32_t* dn2, int n, int use_mlp, double* out, void* stream);
 
 /* Training data from an FBC_FORM_DTABLE_FP64 context, whose table holds the lattice
- * values of every distinct offset and line mode of its cells: up to max_samples pairs
- * (table mode, offset) drawn by a host generator seeded with `seed`, restricted to
- * rho > r_c and kappa rho <= 6, each turned into features x[n][8] and target t[n][12]
- * (the correction above, with the table context's own C, divided by env and rotated by
- * exp(-i pi theta0 dn1)); x, t are
- * device FP32 buffers of max_samples rows.  *n_out = rows written.  Synchronises. */
-fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* table_ctx, int max_samples,
+ * values of every distinct offset and line mode of its cells: max_samples pairs
+ * (table mode >= 1, offset) in the learned band of that table (rho > r_c, found from the
+ * table's values as a surrogate context finds it) drawn by a host generator seeded with
+ * `seed` (a mode uniformly among those whose band holds an offset, then an offset
+ * uniformly in its band), each turned into
+ * features x[n][8] and target t[n][12] (the correction above divided by env and rotated
+ * by exp(-i pi theta0 dn1)); x, t are device FP32 buffers of max_samples rows.
+ * *n_out = rows written.  Also records in s the largest in-plane distance of the band:
+ * surrogate contexts apply the learned correction only out to it (no extrapolation
+ * beyond the training data; the continuum alone further out).  FBC_E_ARG when no offset
+ * of the context lies in the band.  Synchronises. */
+fbc_status fbc_sur_training_set(fbc_sur* s, const fbc_ctx* table_ctx, int max_samples,
                                 uint64_t seed, float* x, float* t, int* n_out, void* stream);
 
 /* Trainable MLP with FP32 parameters, Adam state and a workspace for batches of up to

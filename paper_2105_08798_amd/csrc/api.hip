@@ -335,9 +335,10 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
     const int form = c->opt.form;
     OffsetSet os = offsets_of(c->cells);
     const bool sur = (form == FBC_FORM_SURROGATE);
+    std::vector<double> rho_sorted;      // surrogate: in-plane distance of each offset, ascending
     if (sur) {
-        // number offsets by increasing in-plane distance: the exact near field is a prefix,
-        // and so is, for every line mode, the part where the far field is not negligible
+        // number offsets by increasing in-plane distance: for every line mode the exact part
+        // is a prefix, and so is the part where the far field is not negligible
         const int64_t n = (int64_t)os.d1.size();
         std::vector<double> rho(n);
         for (int64_t o = 0; o < n; ++o) {
@@ -359,27 +360,8 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         os.d2.swap(nd2);
         c->n_near = 0;
         while (c->n_near < n && rho[ord[c->n_near]] <= c->sur->r_c) ++c->n_near;
-        const int T0 = c->nz_max / 2 + 1;
-        std::vector<int32_t> need(T0);
-        for (int t = 0; t < T0; ++t) {
-            if (t == 0) {
-                need[t] = (int32_t)n;
-                continue;
-            }
-            const double kap = 2.0 * M_PI * ((double)t / c->nz_max) * M_SQRT2;
-            const double rmax = c->sur->k.s_max / kap;
-            int64_t lo = c->n_near, hi = n;       // first rank with rho > rmax
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) / 2;
-                if (rho[ord[mid]] <= rmax) lo = mid + 1; else hi = mid;
-            }
-            need[t] = (int32_t)lo;
-        }
-        c->n_need_h = need;
-        fbc_status s0;
-        if ((s0 = dev_alloc(c, (void**)&c->n_need, (int64_t)T0 * 4)) != FBC_OK) return s0;
-        HIPCHK(c, hipMemcpyAsync(c->n_need, need.data(), (size_t)T0 * 4, hipMemcpyHostToDevice, st));
-        HIPCHK(c, hipStreamSynchronize(st));
+        rho_sorted.resize(n);
+        for (int64_t r = 0; r < n; ++r) rho_sorted[r] = rho[ord[r]];
     }
     const int64_t n_off = (int64_t)os.d1.size();
     c->n_offsets = n_off;
@@ -405,15 +387,17 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
     fbc_status s;
     int32_t *d1_d, *d2_d;
     const bool keep = (form == FBC_FORM_DTABLE_FP64);
-    // the surrogate form keeps only the exact near field, for every table mode
-    const int64_t n_tab = sur ? c->n_near : n_off;
     if ((s = dev_alloc(c, (void**)&c->lut, (int64_t)os.lut.size() * 4)) != FBC_OK) return s;
     if (keep) {
         if ((s = dev_alloc(c, (void**)&c->tab, (int64_t)T * n_off * 96)) != FBC_OK) return s;
         c->store_bytes = (int64_t)T * n_off * 96;
     } else if (sur) {
-        if ((s = dev_alloc(c, (void**)&c->near_tab, (int64_t)T * std::max<int64_t>(1, n_tab) * 96)) != FBC_OK) return s;
-        c->store_bytes = (int64_t)T * n_tab * 96;
+        // generated slices: as many table modes per chunk as fit in about 2 GiB (also the
+        // workspace of the measuring pass below)
+        c->gen_modes = (int)std::max<int64_t>(1, std::min<int64_t>(T, ((int64_t)2 << 30) / std::max<int64_t>(1, n_off * 96)));
+        if (c->opt.gen_modes > 0) c->gen_modes = std::min(c->opt.gen_modes, T);
+        if ((s = dev_alloc(c, (void**)&c->gen, (int64_t)c->gen_modes * n_off * 96)) != FBC_OK) return s;
+        c->scratch_bytes += (int64_t)c->gen_modes * n_off * 96;
     } else if ((s = talloc((void**)&c->tab, (int64_t)T * n_off * 96)) != FBC_OK) {
         cleanup();
         return s;
@@ -453,33 +437,111 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         return s;
     }
     const double scale = 1.0 / ((double)m1 * m2);
-    for (int t0 = 0; t0 < T; t0 += chunk) {
-        const int nmc = std::min(chunk, T - t0);
+    // the lattice Green function of table modes t0 .. t0+nmc-1 in pt: [mode][comp][d2][d1]
+    auto lattice_modes = [&](int t0, int nmc) {
         launch_dinv(st, pk, t0, nmc, c->nz_max, m1, m2, logL, sn_d, bt);
         // inverse 2-D FFT: rows (m2 contiguous), transpose, rows again -> t[comp][d2][d1]
         launch_fft_rows(st, pk, (int64_t)nmc * 3 * m1, ilog2(m2), tw2_d, true);
         launch_transpose_c(st, pk, pt, nmc * 3, m1, m2);
         launch_fft_rows(st, pt, (int64_t)nmc * 3 * m2, ilog2(m1), tw1_d, true);
-        if (sur) {
-            if (n_tab > 0)
-                launch_gather_table(st, pt, c->near_tab + (int64_t)t0 * n_tab * 6, nmc, m1, m2, n_tab, d1_d,
-                                    d2_d, n_tab * 6, scale);
-        } else {
-            launch_gather_table(st, pt, c->tab + (int64_t)t0 * n_off * 6, nmc, m1, m2, n_off, d1_d, d2_d,
-                                n_off * 6, scale);
+    };
+    const double tau = skip_tolerance(c->opt);
+    if (sur) {
+        // Measuring pass: per table mode, the distances beyond which every block is below
+        // exp(-s_exact), exp(-s_learn) and tau of the mode's largest block; they fix the
+        // ragged exact prefix, the learned band and the generated prefix of every mode.
+        const double taus[3] = {std::exp(-c->sur->s_exact), std::exp(-c->sur->s_learn), tau};
+        const int nk = tau >= 0 ? 3 : 2;
+        unsigned long long* cut_d;
+        if ((s = talloc((void**)&cut_d, (int64_t)T * 8 * (nk + 1))) != FBC_OK) {
+            cleanup();
+            return s;
+        }
+        for (int t0 = 0; t0 < T; t0 += chunk) {
+            const int nmc = std::min(chunk, T - t0);
+            lattice_modes(t0, nmc);
+            for (int a = 0; a < nmc; a += c->gen_modes) {
+                const int ns = std::min(c->gen_modes, nmc - a);
+                launch_gather_table(st, pt + (int64_t)a * 3 * plane, c->gen, ns, m1, m2, n_off, d1_d, d2_d, n_off * 6,
+                                    scale);
+                for (int k = 0; k < nk; ++k)
+                    launch_tab_rhocut(st, c->gen, ns, n_off, d1_d, d2_d, taus[k], cut_d + (int64_t)nk * T + t0 + a,
+                                      cut_d + (int64_t)k * T + t0 + a);
+            }
+        }
+        std::vector<unsigned long long> bits((size_t)T * (nk + 1));     // cuts, then the largest blocks
+        HIPCHK(c, hipMemcpyAsync(bits.data(), cut_d, bits.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        auto cut = [&](int k, int t) {
+            double v;
+            std::memcpy(&v, &bits[(size_t)k * T + t], 8);
+            return v * (1.0 + 1e-12);          // the device and host distances may differ in the last bit
+        };
+        // number of offsets (a prefix in distance order) within distance r, at least n_near
+        auto within = [&](double r) {
+            const int64_t k = std::upper_bound(rho_sorted.begin(), rho_sorted.end(), r) - rho_sorted.begin();
+            return (int32_t)std::max<int64_t>(k, c->n_near);
+        };
+        std::vector<int32_t> nex(T), nle(T), need(T);
+        std::vector<int64_t> exo(T);
+        std::vector<double> envm(T);
+        int64_t n_ex = 0;
+        for (int t = 0; t < T; ++t) {
+            std::memcpy(&envm[t], &bits[(size_t)nk * T + t], 8);
+            envm[t] *= taus[0];
+            if (t == 0) {
+                nex[t] = nle[t] = need[t] = (int32_t)n_off;   // line mode 0: every offset, exact
+            } else {
+                nex[t] = within(cut(0, t));
+                nle[t] = std::max(nex[t], within(cut(1, t)));
+                need[t] = (nk == 3) ? std::max(nle[t], within(cut(2, t))) : (int32_t)n_off;
+            }
+            exo[t] = n_ex;
+            n_ex += nex[t];
+        }
+        c->n_need_h = need;
+        c->n_exact_h = nex;
+        c->n_learn_h = nle;
+        c->ex_off_h = exo;
+        if ((s = dev_alloc(c, (void**)&c->exact_tab, n_ex * 96)) != FBC_OK ||
+            (s = dev_alloc(c, (void**)&c->n_need, (int64_t)T * 4)) != FBC_OK ||
+            (s = dev_alloc(c, (void**)&c->n_exact, (int64_t)T * 4)) != FBC_OK ||
+            (s = dev_alloc(c, (void**)&c->n_learn, (int64_t)T * 4)) != FBC_OK ||
+            (s = dev_alloc(c, (void**)&c->ex_off, (int64_t)T * 8)) != FBC_OK ||
+            (s = dev_alloc(c, (void**)&c->env_mode, (int64_t)T * 8)) != FBC_OK) {
+            cleanup();
+            return s;
+        }
+        c->store_bytes = n_ex * 96;
+        HIPCHK(c, hipMemcpyAsync(c->n_need, need.data(), (size_t)T * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->n_exact, nex.data(), (size_t)T * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->n_learn, nle.data(), (size_t)T * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->ex_off, exo.data(), (size_t)T * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->env_mode, envm.data(), (size_t)T * 8, hipMemcpyHostToDevice, st));
+        // gathering pass: the exact prefix of every mode
+        for (int t0 = 0; t0 < T; t0 += chunk) {
+            const int nmc = std::min(chunk, T - t0);
+            lattice_modes(t0, nmc);
+            for (int t = t0; t < t0 + nmc; ++t)
+                if (nex[t] > 0)
+                    launch_gather_table(st, pt + (int64_t)(t - t0) * 3 * plane, c->exact_tab + exo[t] * 6, 1, m1, m2,
+                                        nex[t], d1_d, d2_d, 0, scale);
+        }
+    } else {
+        for (int t0 = 0; t0 < T; t0 += chunk) {
+            const int nmc = std::min(chunk, T - t0);
+            lattice_modes(t0, nmc);
+            launch_gather_table(st, pt, c->tab + (int64_t)t0 * n_off * 6, nmc, m1, m2, n_off, d1_d, d2_d, n_off * 6,
+                                scale);
         }
     }
     HIPCHK(c, hipGetLastError());
     {
         // distance cut-off per table mode, then the windows of every cell
         std::vector<double> rho_cut(T, INFINITY);
-        const double tau = skip_tolerance(c->opt);
         if (sur) {
-            if (tau >= 0)
-                for (int t = 1; t < T; ++t) {
-                    const double kap = 2.0 * M_PI * ((double)t / c->nz_max) * M_SQRT2;
-                    rho_cut[t] = std::max(c->sur->r_c, c->sur->k.s_max / kap);   // zero beyond
-                }
+            for (int t = 1; t < T; ++t)           // zero beyond the generated prefix
+                rho_cut[t] = c->n_need_h[t] > 0 ? rho_sorted[c->n_need_h[t] - 1] : 0.0;
         } else if (tau >= 0) {
             unsigned long long* st2;
             if ((s = talloc((void**)&st2, (int64_t)T * 16)) != FBC_OK) {
@@ -498,23 +560,6 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         }
         const int rows_tile = gemm_tile_rows(form, c->ctmax);
         compute_windows(c, rho_cut, rows_tile);
-    }
-    if (sur) {
-        if ((s = dev_alloc(c, (void**)&c->cmatch, 64)) != FBC_OK) {
-            cleanup();
-            return s;
-        }
-        launch_sur_const(st, c->sur->view(), c->near_tab, d1_d, d2_d, n_tab, c->sur->r_c - SUR_MATCH_SHELL,
-                         c->sur->r_c, c->cmatch);
-        HIPCHK(c, hipGetLastError());
-        // generated slices: as many table modes per chunk as fit in about 2 GiB
-        c->gen_modes = (int)std::max<int64_t>(1, std::min<int64_t>(T, ((int64_t)2 << 30) / std::max<int64_t>(1, n_off * 96)));
-        if (c->opt.gen_modes > 0) c->gen_modes = std::min(c->opt.gen_modes, T);
-        if ((s = dev_alloc(c, (void**)&c->gen, (int64_t)c->gen_modes * n_off * 96)) != FBC_OK) {
-            cleanup();
-            return s;
-        }
-        c->scratch_bytes += (int64_t)c->gen_modes * n_off * 96;
     }
     if (!keep && !sur) {
         if (form == FBC_FORM_SPLIT_FP16) {
@@ -1068,9 +1113,9 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
             const int nt = std::min(c->gen_modes, T - t0);
             int64_t max_need = 0;
             for (int t = t0; t < t0 + nt; ++t) max_need = std::max<int64_t>(max_need, c->n_need_h[t]);
-            launch_sur_generate(st, sv->view(), sv->wb, sv->bias, sv->r_c, sv->env_floor, c->nz_max, t0, nt,
-                                c->near_tab, c->n_near, c->n_offsets, c->n_need, c->off_d1, c->off_d2,
-                                c->cmatch, c->gen, max_need);
+            launch_sur_generate(st, sv->view(), sv->infer(), sv->r_c, c->env_mode, sv->rho_learn, c->nz_max, t0, nt,
+                                c->exact_tab, c->ex_off, c->n_exact, c->n_learn, c->n_offsets, c->n_need,
+                                c->off_d1, c->off_d2, c->gen, max_need);
             const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
             PqLists ql{};
             ql.ctr = c->status + 16;

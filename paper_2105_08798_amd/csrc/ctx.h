@@ -61,10 +61,16 @@ struct fbc_ctx {
     int32_t* lut = nullptr;
     int d1min = 0, d2min = 0, w2 = 0;
     CellDev* celldev = nullptr;
-    // surrogate form: exact near table, offsets by increasing distance, generated slices
+    // surrogate form: ragged exact table, offsets by increasing distance, generated slices
     const fbc_sur* sur = nullptr;
-    double2* near_tab = nullptr;     // [table mode][n_near][6]
-    int64_t n_near = 0;
+    double2* exact_tab = nullptr;    // mode t: the first n_exact[t] offsets at ex_off[t] (x 6)
+    int64_t* ex_off = nullptr;       // device [T]
+    int32_t* n_exact = nullptr;      // device [T]
+    int32_t* n_learn = nullptr;      // device [T]: offsets n_exact .. n_learn-1 get the learned correction
+    double* env_mode = nullptr;      // device [T]: envelope of the learned correction
+    std::vector<int32_t> n_exact_h, n_learn_h;   // host copies
+    std::vector<int64_t> ex_off_h;
+    int64_t n_near = 0;              // offsets with rho <= r_c
     int32_t* off_d1 = nullptr;       // device offsets in table order
     int32_t* off_d2 = nullptr;
     int32_t* n_need = nullptr;       // per table mode: offsets to generate (prefix)
@@ -72,7 +78,6 @@ struct fbc_ctx {
     double2* gen = nullptr;          // generated slices [chunk modes][n_off][6]
     int gen_modes = 0;               // table modes per generated chunk
     std::vector<int> chunk_job0;     // first job of each chunk (jobs sorted by table mode)
-    double* cmatch = nullptr;        // line-mode-0 matching constant (6 components)
     // relax
     double* fprev = nullptr;
     double* alpha = nullptr;
@@ -104,15 +109,20 @@ static const int kMaxTimed = 4096;
 // Learned far-field object (continuum table + inference weights).
 struct fbc_sur {
     double r_c = 6.0;
-    double env_floor = 1e-3;
     CgfConst k{};
     double2* H = nullptr;            // continuum table
     double* g0 = nullptr;
     unsigned short* wb = nullptr;    // transposed bf16 weights
+    float* wf = nullptr;             // transposed FP32 weights (inference control)
     float* bias = nullptr;
     int has_mlp = 0;
+    int mlp_fp32 = 0;                // 1: inference with the FP32 weights
+    double s_exact = SUR_S_EXACT;    // end of the exact band (exp(-s_exact) of a mode's largest block)
+    double s_learn = SUR_S_LEARN;    // end of the learned band (exp(-s_learn) of a mode's largest block)
+    double rho_learn = INFINITY;     // largest distance of the training data (set by fbc_sur_training_set)
     std::vector<void*> allocs;
     std::string err;
+    MlpInfer infer() const { return MlpInfer{wb, mlp_fp32 ? wf : nullptr, bias}; }
     CgfView view() const {
         CgfView v;
         v.H = H;

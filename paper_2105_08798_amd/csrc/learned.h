@@ -45,23 +45,31 @@ void launch_adam(hipStream_t st, float* p, const float* g, float* m, float* v, i
 #define MLP_NW (MLP_H * MLP_IN + 2 * MLP_H * MLP_H + MLP_OUT * MLP_H)
 #define MLP_NB (3 * MLP_H + MLP_OUT)
 
+// Inference weights of the learned correction: transposed BF16 weights (wb), or -- the
+// FP32 control -- transposed FP32 weights (wf != NULL), and FP32 biases.
+struct MlpInfer {
+    const unsigned short* wb;
+    const float* wf;
+    const float* bias;
+};
+
 void launch_sur_samples(hipStream_t st, const CgfView& v, const double2* tab, int64_t n_off, int nz_tab,
                         const int32_t* d1, const int32_t* d2, const int32_t* pick_t,
-                        const int32_t* pick_o, int n, double r_c, double env_floor,
-                        const double* cmatch, float* x, float* t);
-// width of the shell inside r_c over which the line-mode-0 matching constant is averaged
-#define SUR_MATCH_SHELL 1.5
-// the learned correction covers kappa rho <= SUR_S_LEARN (beyond it the blocks are below
-// about 1e-3 of the line-mode-0 scale and the continuum value is used alone)
-#define SUR_S_LEARN 6.0
-void launch_sur_const(hipStream_t st, const CgfView& v, const double2* tab0, const int32_t* d1,
-                      const int32_t* d2, int64_t n, double r_lo, double r_hi, double* cmatch);
-void launch_sur_points(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
-                       int use_mlp, double r_c, double env_floor, const double* theta0,
-                       const int32_t* d1, const int32_t* d2, int n, double2* out);
-void launch_sur_generate(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
-                         double r_c, double env_floor, int nz_tab, int t0, int nt,
-                         const double2* near_tab, int64_t n_near, int64_t n_off,
-                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, const double* cmatch,
-                         double2* out, int64_t max_need);
+                        const int32_t* pick_o, int n, double r_c, const double* env_mode, float* x, float* t);
+// Surrogate bands of every line mode m >= 1, by distance: exact lattice values within r_c
+// and out to the last block of at least exp(-s_exact) times the mode's largest block,
+// continuum + learned correction out to the last block of at least exp(-s_learn) times
+// it, continuum alone out to the last block above the context's skip tolerance, zero
+// beyond.
+#define SUR_S_EXACT 12.0
+#define SUR_S_LEARN 20.0
+void launch_sur_points(hipStream_t st, const CgfView& v, const MlpInfer& w, int use_mlp, double r_c,
+                       const double* theta0, const int32_t* d1,
+                       const int32_t* d2, int n, double2* out);
+void launch_sur_generate(hipStream_t st, const CgfView& v, const MlpInfer& w, double r_c, const double* env_mode,
+                         double rho_learn, int nz_tab, int t0, int nt, const double2* exact_tab, const int64_t* ex_off,
+                         const int32_t* n_exact, const int32_t* n_learn, int64_t n_off,
+                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, double2* out,
+                         int64_t max_need);
 void launch_mlp_to_bf16(hipStream_t st, const float* params, unsigned short* wb, float* bias);
+void launch_mlp_to_f32t(hipStream_t st, const float* params, float* wf, float* bias);

@@ -443,8 +443,12 @@ void launch_adam(hipStream_t st, float* p, const float* g, float* m, float* v, i
 // Features of (theta0, dn1, dn2): (cos phi, sin phi, cos 2phi, sin 2phi, cos 4phi,
 // sin 4phi, r_c / rho, 8 theta0); the low angular harmonics of the cubic anisotropy
 // are given explicitly.
-// Target / output: exp(-i pi theta0 dn1) (G^_lgf - G^_cgf) / env, env = |G^_cgf|_F + floor,
-// 6 complex components (xx yy zz xy xz yz) as 12 reals.
+// Target / output: exp(-i pi theta0 dn1) (G^_lgf - G^_cgf) / env, 6 complex components
+// (xx yy zz xy xz yz) as 12 reals, with env = env_mode[t] = exp(-s_exact) times the
+// largest block of table mode t: the learned band starts where the lattice blocks fall
+// below that, so the targets are of order one or less and the network's absolute error
+// is spread evenly over the band (the continuum is zero beyond kappa rho = 40, where the
+// lattice values at large theta0 still matter; a relative envelope would vanish there).
 // ----------------------------------------------------------------------------------
 __device__ inline void sur_features(double theta0, int dn1, int dn2, double r_c, float f[MLP_IN],
                                     double* rho_out) {
@@ -464,17 +468,7 @@ __device__ inline void sur_features(double theta0, int dn1, int dn2, double r_c,
     *rho_out = rho;
 }
 
-// kappa rho of line wavenumber theta0 at in-plane distance rho (a = 1, c = 1/sqrt2)
-__device__ inline double sur_s(double theta0, double rho) { return 2.0 * M_PI * theta0 * M_SQRT2 * rho; }
 
-__device__ inline double sur_env(const double2 g[6], double floor_) {
-    double s = 0.0;
-    for (int c = 0; c < 6; ++c) {
-        const double w = (c < 3) ? 1.0 : 2.0;     // off-diagonal entries appear twice
-        s += w * (g[c].x * g[c].x + g[c].y * g[c].y);
-    }
-    return sqrt(s) + floor_;
-}
 
 __global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* __restrict__ tab,
                                                      int64_t n_off, int nz_tab,
@@ -482,8 +476,7 @@ __global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* _
                                                      const int32_t* __restrict__ d2,
                                                      const int32_t* __restrict__ pick_t,
                                                      const int32_t* __restrict__ pick_o, int n,
-                                                     double r_c, double env_floor,
-                                                     const double* __restrict__ cmatch,
+                                                     double r_c, const double* __restrict__ env_mode,
                                                      float* __restrict__ x, float* __restrict__ t) {
     const int i = blockIdx.x * NTL + threadIdx.x;
     if (i >= n) return;
@@ -495,13 +488,13 @@ __global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* _
     float f[MLP_IN];
     double rho;
     sur_features(theta0, d1[o], d2[o], r_c, f, &rho);
-    const double env = sur_env(g, env_floor);
+    const double env = env_mode[tm];
     double sp, cp;
     sincospi(theta0 * d1[o], &sp, &cp);
     const double2* l = tab + ((int64_t)tm * n_off + o) * 6;
     for (int a = 0; a < MLP_IN; ++a) x[(int64_t)i * MLP_IN + a] = f[a];
     for (int c = 0; c < 6; ++c) {
-        const double dr = l[c].x - g[c].x - (tm == 0 ? cmatch[c] : 0.0), di = l[c].y - g[c].y;
+        const double dr = l[c].x - g[c].x, di = l[c].y - g[c].y;
         // multiply by exp(-i pi theta0 dn1)
         t[(int64_t)i * 12 + 2 * c] = (float)((dr * cp + di * sp) / env);
         t[(int64_t)i * 12 + 2 * c + 1] = (float)((di * cp - dr * sp) / env);
@@ -510,69 +503,37 @@ __global__ void __launch_bounds__(NTL) k_sur_samples(CgfView v, const double2* _
 
 void launch_sur_samples(hipStream_t st, const CgfView& v, const double2* tab, int64_t n_off, int nz_tab,
                         const int32_t* d1, const int32_t* d2, const int32_t* pick_t,
-                        const int32_t* pick_o, int n, double r_c, double env_floor,
-                        const double* cmatch, float* x, float* t) {
+                        const int32_t* pick_o, int n, double r_c, const double* env_mode, float* x, float* t) {
     if (n > 0)
         hipLaunchKernelGGL(k_sur_samples, dim3((n + NTL - 1) / NTL), dim3(NTL), 0, st, v, tab, n_off, nz_tab,
-                           d1, d2, pick_t, pick_o, n, r_c, env_floor, cmatch, x, t);
+                           d1, d2, pick_t, pick_o, n, r_c, env_mode, x, t);
 }
 
-// Matching constant of line mode 0 (Appendix B: the lattice and continuum functions differ
-// by a constant far from the source; it is measured where both are known): the mean of
-// G_lgf - G_cgf over the exact-table offsets with r_lo < rho <= r_hi.  One work group,
-// fixed assignment of offsets to threads and a fixed reduction tree: deterministic.
-__global__ void __launch_bounds__(NTL) k_sur_const(CgfView v, const double2* __restrict__ tab0,
-                                                   const int32_t* __restrict__ d1,
-                                                   const int32_t* __restrict__ d2, int64_t n,
-                                                   double r_lo, double r_hi,
-                                                   double* __restrict__ cmatch) {
-    __shared__ double red[7][NTL];
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t o = threadIdx.x; o < n; o += NTL) {
-        const double x = 0.5 * d1[o], y = (d1[o] + 2.0 * d2[o]) * (0.5 * M_SQRT1_2);
-        const double rho = sqrt(x * x + y * y);
-        if (!(rho > r_lo && rho <= r_hi)) continue;
-        double2 g[6];
-        cgf_eval(v, 0.0, d1[o], d2[o], g);
-        for (int c = 0; c < 6; ++c) acc[c] += tab0[o * 6 + c].x - g[c].x;
-        acc[6] += 1.0;
-    }
-    for (int c = 0; c < 7; ++c) red[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int st = NTL / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st)
-            for (int c = 0; c < 7; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x < 6) cmatch[threadIdx.x] = red[6][0] > 0 ? red[threadIdx.x][0] / red[6][0] : 0.0;
-}
-
-void launch_sur_const(hipStream_t st, const CgfView& v, const double2* tab0, const int32_t* d1,
-                      const int32_t* d2, int64_t n, double r_lo, double r_hi, double* cmatch) {
-    hipLaunchKernelGGL(k_sur_const, dim3(1), dim3(NTL), 0, st, v, tab0, d1, d2, n, r_lo, r_hi, cmatch);
-}
-
-// MLP forward of one sample, bf16 weights (transposed, [in][out], read with wave-uniform
-// addresses), FP32 accumulation.  The hidden vector of each thread lives in its own LDS
+// MLP forward of one sample, weights transposed ([in][out], read with wave-uniform
+// addresses) in BF16 (inference) or FP32 (the control that isolates the weights'
+// rounding), FP32 accumulation.  The hidden vector of each thread lives in its own LDS
 // column hl[i * stride]; every layer reads its inputs from there and overwrites them with
 // its outputs (the column is private to the thread, so no barrier is needed).
 #define MLP_BLOCK 64
-__device__ inline float bfv(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ inline float wval(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ inline float wval(float x) { return x; }
 
+template <typename WT>
 struct MlpW {
-    const unsigned short* w1t;   // [4][128]
-    const unsigned short* w2t;   // [128][128]
-    const unsigned short* w3t;   // [128][128]
-    const unsigned short* w4t;   // [128][12]
+    const WT* w1t;   // [8][128]
+    const WT* w2t;   // [128][128]
+    const WT* w3t;   // [128][128]
+    const WT* w4t;   // [128][12]
     const float* b1;
     const float* b2;
     const float* b3;
     const float* b4;
 };
 
-__device__ inline MlpW mlp_view(const unsigned short* wb, const float* bias) {
-    MlpW m;
-    m.w1t = wb;
+template <typename WT>
+__device__ inline MlpW<WT> mlp_view(const WT* w, const float* bias) {
+    MlpW<WT> m;
+    m.w1t = w;
     m.w2t = m.w1t + MLP_IN * MLP_H;
     m.w3t = m.w2t + MLP_H * MLP_H;
     m.w4t = m.w3t + MLP_H * MLP_H;
@@ -583,30 +544,30 @@ __device__ inline MlpW mlp_view(const unsigned short* wb, const float* bias) {
     return m;
 }
 
-__device__ inline void mlp_hidden(const unsigned short* __restrict__ wt, const float* __restrict__ b,
-                                  float* hl, int stride) {
+template <typename WT>
+__device__ inline void mlp_hidden(const WT* __restrict__ wt, const float* __restrict__ b, float* hl, int stride) {
     float acc[MLP_H];
 #pragma unroll
     for (int o = 0; o < MLP_H; ++o) acc[o] = b[o];
     for (int i = 0; i < MLP_H; ++i) {
         const float v = hl[i * stride];
-        const unsigned short* w = wt + i * MLP_H;
+        const WT* w = wt + i * MLP_H;
 #pragma unroll
-        for (int o = 0; o < MLP_H; ++o) acc[o] = fmaf(bfv(w[o]), v, acc[o]);
+        for (int o = 0; o < MLP_H; ++o) acc[o] = fmaf(wval(w[o]), v, acc[o]);
     }
 #pragma unroll
     for (int o = 0; o < MLP_H; ++o) hl[o * stride] = silu(acc[o]);
 }
 
-__device__ void mlp_bf16_eval(const MlpW& m, const float f[MLP_IN], float* hl, int stride,
-                              float y[MLP_OUT]) {
+template <typename WT>
+__device__ void mlp_eval(const MlpW<WT>& m, const float f[MLP_IN], float* hl, int stride, float y[MLP_OUT]) {
     {
         float acc[MLP_H];
 #pragma unroll
         for (int o = 0; o < MLP_H; ++o) {
             float a = m.b1[o];
 #pragma unroll
-            for (int i = 0; i < MLP_IN; ++i) a = fmaf(bfv(m.w1t[i * MLP_H + o]), f[i], a);
+            for (int i = 0; i < MLP_IN; ++i) a = fmaf(wval(m.w1t[i * MLP_H + o]), f[i], a);
             acc[o] = a;
         }
 #pragma unroll
@@ -619,20 +580,21 @@ __device__ void mlp_bf16_eval(const MlpW& m, const float f[MLP_IN], float* hl, i
     for (int i = 0; i < MLP_H; ++i) {
         const float v = hl[i * stride];
 #pragma unroll
-        for (int o = 0; o < MLP_OUT; ++o) y[o] = fmaf(bfv(m.w4t[i * MLP_OUT + o]), v, y[o]);
+        for (int o = 0; o < MLP_OUT; ++o) y[o] = fmaf(wval(m.w4t[i * MLP_OUT + o]), v, y[o]);
     }
 }
 
-// Far-field block (CGF, optionally + MLP correction) at arbitrary points (gain test).
-__global__ void __launch_bounds__(MLP_BLOCK) k_sur_points(CgfView v, const unsigned short* __restrict__ wb,
-                                                    const float* __restrict__ bias, int use_mlp,
-                                                    double r_c, double env_floor,
-                                                    const double* __restrict__ theta0,
-                                                    const int32_t* __restrict__ d1,
-                                                    const int32_t* __restrict__ d2, int n,
-                                                    double2* __restrict__ out) {
+// Far-field block (CGF, optionally + the network's correction with a unit envelope) at
+// arbitrary points.
+template <typename WT>
+__global__ void __launch_bounds__(MLP_BLOCK) k_sur_points(CgfView v, const WT* __restrict__ wt,
+                                                          const float* __restrict__ bias, int use_mlp,
+                                                          double r_c, const double* __restrict__ theta0,
+                                                          const int32_t* __restrict__ d1,
+                                                          const int32_t* __restrict__ d2, int n,
+                                                          double2* __restrict__ out) {
     __shared__ float hl[MLP_H * MLP_BLOCK];
-    const MlpW m = mlp_view(wb, bias);
+    const MlpW<WT> m = mlp_view(wt, bias);
     const int i = blockIdx.x * MLP_BLOCK + threadIdx.x;
     if (i >= n) return;
     double2 g[6];
@@ -640,13 +602,12 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_points(CgfView v, const unsig
     float f[MLP_IN], y[MLP_OUT];
     double rho;
     sur_features(theta0[i], d1[i], d2[i], r_c, f, &rho);
-    if (use_mlp && rho > r_c && sur_s(theta0[i], rho) <= SUR_S_LEARN) {
-        const double env = sur_env(g, env_floor);
-        mlp_bf16_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
+    if (use_mlp && rho > r_c) {
+        mlp_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
         double sp, cp;
         sincospi(theta0[i] * d1[i], &sp, &cp);
         for (int c = 0; c < 6; ++c) {
-            const double cr = env * y[2 * c], ci = env * y[2 * c + 1];
+            const double cr = y[2 * c], ci = y[2 * c + 1];
             g[c].x += cr * cp - ci * sp;
             g[c].y += cr * sp + ci * cp;
         }
@@ -654,38 +615,48 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_points(CgfView v, const unsig
     for (int c = 0; c < 6; ++c) out[(int64_t)i * 6 + c] = g[c];
 }
 
-void launch_sur_points(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
-                       int use_mlp, double r_c, double env_floor, const double* theta0,
-                       const int32_t* d1, const int32_t* d2, int n, double2* out) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_sur_points, dim3((n + MLP_BLOCK - 1) / MLP_BLOCK), dim3(MLP_BLOCK), 0, st, v, wb, bias, use_mlp,
-                           r_c, env_floor, theta0, d1, d2, n, out);
+void launch_sur_points(hipStream_t st, const CgfView& v, const MlpInfer& w, int use_mlp, double r_c,
+                       const double* theta0, const int32_t* d1,
+                       const int32_t* d2, int n, double2* out) {
+    if (n <= 0) return;
+    const dim3 grid((n + MLP_BLOCK - 1) / MLP_BLOCK);
+    if (w.wf)
+        hipLaunchKernelGGL(k_sur_points<float>, grid, dim3(MLP_BLOCK), 0, st, v, w.wf, w.bias, use_mlp, r_c,
+                           theta0, d1, d2, n, out);
+    else
+        hipLaunchKernelGGL(k_sur_points<unsigned short>, grid, dim3(MLP_BLOCK), 0, st, v, w.wb, w.bias, use_mlp,
+                           r_c, theta0, d1, d2, n, out);
 }
 
 // Table slice generator of the surrogate form: table modes t0 .. t0+nt-1 for every
-// offset o (offsets numbered by increasing rho): o < n_near: exact lattice value;
-// o < n_need[t]: continuum (+ matching constant at line mode 0, + learned correction
-// where kappa rho <= SUR_S_LEARN); beyond: zero (kappa rho > s_max), not written (the
-// product treats offsets at or beyond n_need[t] as zero).
-__global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const unsigned short* __restrict__ wb,
-                                                      const float* __restrict__ bias, double r_c,
-                                                      double env_floor, int nz_tab, int t0,
-                                                      const double2* __restrict__ near_tab,
-                                                      int64_t n_near, int64_t n_off,
-                                                      const int32_t* __restrict__ n_need,
-                                                      const int32_t* __restrict__ d1,
-                                                      const int32_t* __restrict__ d2,
-                                                      const double* __restrict__ cmatch,
-                                                      double2* __restrict__ out) {
+// offset o (offsets numbered by increasing rho; every band below is a prefix).
+// o < n_exact[t]: the exact lattice value from the ragged table (mode t at ex_off[t]);
+// o < n_learn[t]: continuum + learned correction (only out to rho_learn, the largest distance
+// of the training data: no extrapolation); o < n_need[t]: continuum alone; beyond:
+// zero, not written (the product treats offsets at or beyond n_need[t] as zero).
+template <typename WT>
+__global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const WT* __restrict__ wt,
+                                                            const float* __restrict__ bias, double r_c,
+                                                            const double* __restrict__ env_mode, double rho_learn,
+                                                            int nz_tab, int t0,
+                                                            const double2* __restrict__ exact_tab,
+                                                            const int64_t* __restrict__ ex_off,
+                                                            const int32_t* __restrict__ n_exact,
+                                                            const int32_t* __restrict__ n_learn,
+                                                            int64_t n_off,
+                                                            const int32_t* __restrict__ n_need,
+                                                            const int32_t* __restrict__ d1,
+                                                            const int32_t* __restrict__ d2,
+                                                            double2* __restrict__ out) {
     __shared__ float hl[MLP_H * MLP_BLOCK];
-    const MlpW m = mlp_view(wb, bias);
+    const MlpW<WT> m = mlp_view(wt, bias);
     const int tl = blockIdx.y;
     const int tm = t0 + tl;
     const int64_t o = (int64_t)blockIdx.x * MLP_BLOCK + threadIdx.x;
     if (o >= n_off) return;
     double2* dst = out + ((int64_t)tl * n_off + o) * 6;
-    if (o < n_near) {
-        const double2* src = near_tab + ((int64_t)tm * n_near + o) * 6;
+    if (o < n_exact[tm]) {
+        const double2* src = exact_tab + (ex_off[tm] + o) * 6;
         for (int c = 0; c < 6; ++c) dst[c] = src[c];
         return;
     }
@@ -696,11 +667,9 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const uns
     float f[MLP_IN], y[MLP_OUT];
     double rho;
     sur_features(theta0, d1[o], d2[o], r_c, f, &rho);
-    const double env = sur_env(g, env_floor);
-    if (tm == 0)
-        for (int c = 0; c < 6; ++c) g[c].x += cmatch[c];     // matching constant (line mode 0)
-    if (sur_s(theta0, rho) <= SUR_S_LEARN) {
-        mlp_bf16_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
+    const double env = env_mode[tm];
+    if (o < n_learn[tm] && rho <= rho_learn) {
+        mlp_eval(m, f, hl + threadIdx.x, MLP_BLOCK, y);
         double sp, cp;
         sincospi(theta0 * d1[o], &sp, &cp);
         for (int c = 0; c < 6; ++c) {
@@ -712,15 +681,19 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const uns
     for (int c = 0; c < 6; ++c) dst[c] = g[c];
 }
 
-void launch_sur_generate(hipStream_t st, const CgfView& v, const unsigned short* wb, const float* bias,
-                         double r_c, double env_floor, int nz_tab, int t0, int nt,
-                         const double2* near_tab, int64_t n_near, int64_t n_off,
-                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, const double* cmatch,
-                         double2* out, int64_t max_need) {
+void launch_sur_generate(hipStream_t st, const CgfView& v, const MlpInfer& w, double r_c, const double* env_mode,
+                         double rho_learn, int nz_tab, int t0, int nt, const double2* exact_tab, const int64_t* ex_off,
+                         const int32_t* n_exact, const int32_t* n_learn, int64_t n_off,
+                         const int32_t* n_need, const int32_t* d1, const int32_t* d2, double2* out,
+                         int64_t max_need) {
     if (max_need <= 0 || nt <= 0) return;
     dim3 grid((unsigned)((max_need + MLP_BLOCK - 1) / MLP_BLOCK), nt);
-    hipLaunchKernelGGL(k_sur_generate, grid, dim3(MLP_BLOCK), 0, st, v, wb, bias, r_c, env_floor, nz_tab, t0,
-                       near_tab, n_near, n_off, n_need, d1, d2, cmatch, out);
+    if (w.wf)
+        hipLaunchKernelGGL(k_sur_generate<float>, grid, dim3(MLP_BLOCK), 0, st, v, w.wf, w.bias, r_c, env_mode, rho_learn,
+                           nz_tab, t0, exact_tab, ex_off, n_exact, n_learn, n_off, n_need, d1, d2, out);
+    else
+        hipLaunchKernelGGL(k_sur_generate<unsigned short>, grid, dim3(MLP_BLOCK), 0, st, v, w.wb, w.bias, r_c,
+                           env_mode, rho_learn, nz_tab, t0, exact_tab, ex_off, n_exact, n_learn, n_off, n_need, d1, d2, out);
 }
 
 // FP32 weights -> transposed bf16 (round to nearest even) and biases, for inference.
@@ -745,4 +718,26 @@ __global__ void k_mlp_to_bf16(const float* __restrict__ params, unsigned short* 
 
 void launch_mlp_to_bf16(hipStream_t st, const float* params, unsigned short* wb, float* bias) {
     hipLaunchKernelGGL(k_mlp_to_bf16, dim3(1), dim3(256), 0, st, params, wb, bias);
+}
+
+// FP32 weights -> transposed FP32 weights and biases (the inference control without the
+// BF16 rounding of the weights).
+__global__ void k_mlp_to_f32t(const float* __restrict__ params, float* __restrict__ wf, float* __restrict__ bias) {
+    const int sizes[5] = {MLP_IN, MLP_H, MLP_H, MLP_H, MLP_OUT};
+    int64_t off = 0, ow = 0, ob = 0;
+    for (int l = 0; l < 4; ++l) {
+        const int ni = sizes[l], no = sizes[l + 1];
+        for (int e = threadIdx.x; e < no * ni; e += blockDim.x) {
+            const int o = e / ni, i = e - o * ni;
+            wf[ow + (int64_t)i * no + o] = params[off + e];
+        }
+        for (int i = threadIdx.x; i < no; i += blockDim.x) bias[ob + i] = params[off + (int64_t)no * ni + i];
+        off += (int64_t)no * ni + no;
+        ow += (int64_t)no * ni;
+        ob += no;
+    }
+}
+
+void launch_mlp_to_f32t(hipStream_t st, const float* params, float* wf, float* bias) {
+    hipLaunchKernelGGL(k_mlp_to_f32t, dim3(1), dim3(256), 0, st, params, wf, bias);
 }

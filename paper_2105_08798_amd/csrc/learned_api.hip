@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "kernels.h"
 
 static thread_local std::string g_lerr;
 
@@ -112,6 +113,7 @@ extern "C" fbc_status fbc_sur_create(const fbc_lattice* lat, double r_c, void* s
         (rc = lalloc(s->allocs, &s->err, &s->g0, 6 * 8)) ||
         (rc = lalloc(s->allocs, &s->err, &s->H, (int64_t)k.nphi * (k.ns + 1) * 6 * 16)) ||
         (rc = lalloc(s->allocs, &s->err, &s->wb, (int64_t)MLP_NW * 2)) ||
+        (rc = lalloc(s->allocs, &s->err, &s->wf, (int64_t)MLP_NW * 4)) ||
         (rc = lalloc(s->allocs, &s->err, &s->bias, (int64_t)MLP_NB * 4))) {
         cleanup();
         for (void* p : s->allocs) (void)hipFree(p);
@@ -149,6 +151,29 @@ extern "C" fbc_status fbc_sur_set_mlp(fbc_sur* s, const fbc_mlp* net, void* stre
     LCHK(&s->err, hipGetLastError());
     LCHK(&s->err, hipStreamSynchronize((hipStream_t)stream));
     s->has_mlp = 1;
+    s->mlp_fp32 = 0;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_sur_set_mlp_fp32(fbc_sur* s, const fbc_mlp* net, void* stream) {
+    if (!s || !net) return lfail(nullptr, FBC_E_ARG, "null argument");
+    launch_mlp_to_f32t((hipStream_t)stream, net->params, s->wf, s->bias);
+    LCHK(&s->err, hipGetLastError());
+    LCHK(&s->err, hipStreamSynchronize((hipStream_t)stream));
+    s->has_mlp = 1;
+    s->mlp_fp32 = 1;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_sur_set_learn_range(fbc_sur* s, double s_learn) {
+    if (!s || !(s_learn > 0) || !(s_learn <= 40.0)) return lfail(nullptr, FBC_E_ARG, "s_learn must be in (0, 40]");
+    s->s_learn = s_learn;
+    return FBC_OK;
+}
+
+extern "C" fbc_status fbc_sur_set_exact_range(fbc_sur* s, double s_exact) {
+    if (!s || !(s_exact >= 0) || !(s_exact <= 40.0)) return lfail(nullptr, FBC_E_ARG, "s_exact must be in [0, 40]");
+    s->s_exact = s_exact;
     return FBC_OK;
 }
 
@@ -156,16 +181,20 @@ extern "C" fbc_status fbc_sur_eval(const fbc_sur* s, const double* theta0, const
                                    const int32_t* dn2, int n, int use_mlp, double* out, void* stream) {
     if (!s || !theta0 || !dn1 || !dn2 || !out || n < 0) return lfail(nullptr, FBC_E_ARG, "null argument");
     if (use_mlp && !s->has_mlp) return lfail(nullptr, FBC_E_STATE, "no MLP weights set");
-    launch_sur_points((hipStream_t)stream, s->view(), s->wb, s->bias, use_mlp ? 1 : 0, s->r_c, s->env_floor,
+    launch_sur_points((hipStream_t)stream, s->view(), s->infer(), use_mlp ? 1 : 0, s->r_c,
                       theta0, dn1, dn2, n, (double2*)out);
     LCHK(nullptr, hipGetLastError());
     return FBC_OK;
 }
 
 // Training set from an offset-table context (its table holds lattice values for every
-// distinct offset and line mode of its cells): samples (mode t, offset o) with
-// |r_perp| > r_c and kappa |r_perp| <= SUR_S_LEARN, drawn with a seeded generator.
-extern "C" fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* c, int max_samples,
+// distinct offset and line mode of its cells): samples (mode t >= 1, offset o) in the
+// learned band of the table, drawn with a seeded generator: a line mode uniformly among
+// those whose band holds an offset, then an offset uniformly in that mode's band.  The
+// band is the one a surrogate context uses: offsets beyond r_c and beyond the last block
+// of at least exp(-s_exact) times the mode's largest block, out to the last block of at
+// least exp(-s_learn) times it.
+extern "C" fbc_status fbc_sur_training_set(fbc_sur* s, const fbc_ctx* c, int max_samples,
                                            uint64_t seed, float* x, float* t, int* n_out,
                                            void* stream) {
     if (!s || !c || !x || !t || !n_out || max_samples < 1) return lfail(nullptr, FBC_E_ARG, "null argument");
@@ -182,40 +211,80 @@ extern "C" fbc_status fbc_sur_training_set(const fbc_sur* s, const fbc_ctx* c, i
         const double xx = 0.5 * d1[o], yy = (d1[o] + 2.0 * d2[o]) * (0.5 * M_SQRT1_2);
         rho[o] = std::sqrt(xx * xx + yy * yy);
     }
-    std::mt19937_64 gen(seed);
-    std::uniform_int_distribution<int64_t> pick_o(0, n_off - 1);
-    std::uniform_int_distribution<int> pick_t(0, T - 1);
-    std::vector<int32_t> pt, po;
-    pt.reserve(max_samples);
-    po.reserve(max_samples);
-    int64_t tries = 0;
-    const int64_t max_tries = 200LL * max_samples + 1000;
-    while ((int)pt.size() < max_samples && tries < max_tries) {
-        ++tries;
-        const int64_t o = pick_o(gen);
-        const int tm = pick_t(gen);
-        if (rho[o] <= s->r_c) continue;
-        const double kap = 2.0 * M_PI * ((double)tm / c->nz_max) * M_SQRT2;
-        if (kap * rho[o] > SUR_S_LEARN) continue;
-        pt.push_back(tm);
-        po.push_back((int32_t)o);
+    std::vector<int32_t> ord(n_off);
+    for (int64_t o = 0; o < n_off; ++o) ord[o] = (int32_t)o;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return rho[a] < rho[b]; });
+    // per table mode, the distances beyond which every block is below exp(-s_exact) and
+    // exp(-s_learn) of the mode's largest block
+    unsigned long long* cut_d = nullptr;
+    LCHK(nullptr, hipMalloc((void**)&cut_d, (size_t)T * 8 * 3));
+    launch_tab_rhocut(st, c->tab, T, n_off, c->off_d1, c->off_d2, std::exp(-s->s_exact), cut_d + 2 * T, cut_d);
+    launch_tab_rhocut(st, c->tab, T, n_off, c->off_d1, c->off_d2, std::exp(-s->s_learn), cut_d + 2 * T, cut_d + T);
+    std::vector<unsigned long long> bits((size_t)T * 3);     // two cuts, then the largest blocks
+    const hipError_t ce = hipMemcpyAsync(bits.data(), cut_d, bits.size() * 8, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(cut_d);
+    LCHK(nullptr, ce);
+    auto cut = [&](int k, int t) {
+        double v;
+        std::memcpy(&v, &bits[(size_t)k * T + t], 8);
+        return v * (1.0 + 1e-12);              // the device and host distances may differ in the last bit
+    };
+    // band of line mode t in rank order: [lo, hi); line mode 0 is taken exact by the surrogate
+    // (the in-plane torus of the exact Green function acts on that mode only)
+    auto rank_beyond = [&](double r) {
+        return (int64_t)(std::upper_bound(ord.begin(), ord.end(), r,
+                                          [&](double v, int32_t o) { return v < rho[o]; }) - ord.begin());
+    };
+    std::vector<int> modes;
+    std::vector<int64_t> lo, hi;
+    const int64_t r_near = rank_beyond(s->r_c);
+    for (int tm = 1; tm < T; ++tm) {
+        const int64_t a = std::max(r_near, rank_beyond(cut(0, tm))), b = rank_beyond(cut(1, tm));
+        if (b > a) {
+            modes.push_back(tm);
+            lo.push_back(a);
+            hi.push_back(b);
+        }
     }
-    const int n = (int)pt.size();
-    if (n > 0) {
-        // index lists and the context's own matching constant (line mode 0)
+    if (modes.empty())
+        return lfail(nullptr, FBC_E_ARG, "no offset of the table context lies in the learned band");
+    double rho_band = 0.0;
+    for (size_t k = 0; k < modes.size(); ++k) rho_band = std::max(rho_band, rho[ord[hi[k] - 1]]);
+    std::mt19937_64 gen(seed);
+    std::uniform_int_distribution<int> pick_m(0, (int)modes.size() - 1);
+    std::uniform_real_distribution<double> u01(0.0, 1.0);
+    std::vector<int32_t> pt(max_samples), po(max_samples);
+    for (int i = 0; i < max_samples; ++i) {
+        const int k = pick_m(gen);
+        int64_t r = lo[k] + (int64_t)(u01(gen) * (double)(hi[k] - lo[k]));
+        r = std::min(r, hi[k] - 1);
+        pt[i] = modes[k];
+        po[i] = ord[r];
+    }
+    // envelope per table mode: exp(-s_exact) times the mode's largest block
+    std::vector<double> envm(T);
+    for (int tm = 0; tm < T; ++tm) {
+        std::memcpy(&envm[tm], &bits[(size_t)2 * T + tm], 8);
+        envm[tm] *= std::exp(-s->s_exact);
+    }
+    const int n = max_samples;
+    {
+        // envelopes and index lists
         char* buf = nullptr;
-        LCHK(nullptr, hipMalloc((void**)&buf, (size_t)n * 8 + 64));
-        int32_t* dpt = (int32_t*)buf;
+        LCHK(nullptr, hipMalloc((void**)&buf, (size_t)T * 8 + (size_t)n * 8));
+        double* denv = (double*)buf;
+        int32_t* dpt = (int32_t*)(buf + (size_t)T * 8);
         int32_t* dpo = dpt + n;
-        double* cm = (double*)(buf + (((size_t)n * 8 + 7) & ~(size_t)7));
+        (void)hipMemcpyAsync(denv, envm.data(), (size_t)T * 8, hipMemcpyHostToDevice, st);
         (void)hipMemcpyAsync(dpt, pt.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
         (void)hipMemcpyAsync(dpo, po.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
-        launch_sur_const(st, s->view(), c->tab, c->off_d1, c->off_d2, n_off, s->r_c - SUR_MATCH_SHELL, s->r_c, cm);
         launch_sur_samples(st, s->view(), c->tab, n_off, c->nz_max, c->off_d1, c->off_d2, dpt, dpo, n, s->r_c,
-                           s->env_floor, cm, x, t);
+                           denv, x, t);
         (void)hipStreamSynchronize(st);
         (void)hipFree(buf);
     }
+    s->rho_learn = rho_band;
     *n_out = n;
     LCHK(nullptr, hipGetLastError());
     return FBC_OK;

@@ -30,7 +30,8 @@ EXPORTED = [
     "fbc_plgf_last_error", "fbc_plgf_create", "fbc_plgf_destroy", "fbc_plgf_table", "fbc_plgf_eval",
     "fbc_hmat_last_error", "fbc_hmat_create", "fbc_hmat_destroy", "fbc_hmat_get_info", "fbc_hmat_partition",
     "fbc_hmat_ranks", "fbc_hmat_apply", "fbc_mlp_forward_noalloc", "fbc_mlp_forward_noalloc_max_rows",
-    "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant",
+    "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant", "fbc_sur_set_mlp_fp32",
+    "fbc_sur_set_learn_range", "fbc_sur_set_exact_range",
 ]
 
 
@@ -140,6 +141,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_sur_destroy.argtypes = [vp]
     lib.fbc_sur_destroy.restype = None
     lib.fbc_sur_set_mlp.argtypes = [vp, vp, vp]
+    lib.fbc_sur_set_mlp_fp32.argtypes = [vp, vp, vp]
+    lib.fbc_sur_set_learn_range.argtypes = [vp, C.c_double]
+    lib.fbc_sur_set_exact_range.argtypes = [vp, C.c_double]
     lib.fbc_sur_eval.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, vp, vp]
     lib.fbc_sur_training_set.argtypes = [vp, vp, C.c_int, C.c_uint64, vp, vp, C.POINTER(C.c_int), vp]
     lib.fbc_mlp_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
@@ -172,6 +176,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_hmat_apply.argtypes = [vp, vp, vp, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
                  "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant",
+                 "fbc_sur_set_mlp_fp32", "fbc_sur_set_learn_range", "fbc_sur_set_exact_range",
                  "fbc_relax_get_state", "fbc_relax_set_state",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
@@ -432,8 +437,18 @@ class Surrogate:
         lat = Lattice(float(lattice_a), float(spring_k))
         _lcheck(lib, lib.fbc_sur_create(C.byref(lat), self.r_c, _stream_handle(stream), C.byref(self.handle)))
 
-    def set_mlp(self, net: MLP, stream=None):
-        _lcheck(self._lib, self._lib.fbc_sur_set_mlp(self.handle, net.handle, _stream_handle(stream)))
+    def set_mlp(self, net: MLP, stream=None, fp32: bool = False):
+        """Inference weights from the network: BF16 (default) or, as a control, FP32."""
+        fn = self._lib.fbc_sur_set_mlp_fp32 if fp32 else self._lib.fbc_sur_set_mlp
+        _lcheck(self._lib, fn(self.handle, net.handle, _stream_handle(stream)))
+
+    def set_learn_range(self, s_learn: float):
+        """Upper end (kappa rho) of the learned band."""
+        _lcheck(self._lib, self._lib.fbc_sur_set_learn_range(self.handle, float(s_learn)))
+
+    def set_exact_range(self, s_exact: float):
+        """kappa rho range of the exact lattice values (read when a context is created)."""
+        _lcheck(self._lib, self._lib.fbc_sur_set_exact_range(self.handle, float(s_exact)))
 
     def eval(self, theta0, dn1, dn2, out, use_mlp: bool, stream=None):
         """theta0 float64, dn1/dn2 int32 (device); out float64 [n, 6, 2] (device)."""

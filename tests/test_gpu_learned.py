@@ -6,10 +6,10 @@
   the same FP32 parameters; BF16 inference against the oracle with BF16-rounded weights;
 * training data drawn from an offset-table context against oracle lattice and
   continuum values;
-* the surrogate product form: exact when every offset lies inside r_c (any chunking),
-  and the gain test -- with the same continuum far field, the learned correction
-  must bring the pad update much closer to the exact lattice result than the
-  continuum alone.
+* the surrogate product form: exact when every offset lies inside r_c (any chunking) or
+  when the exact band reaches the continuum table's end, and the gain test -- with the
+  same exact band and continuum far field, the learned correction must bring the pad
+  update much closer to the exact lattice result than the continuum alone.
 """
 import math
 
@@ -48,7 +48,8 @@ def _features(theta0, dn1, dn2, r_c=R_C):
     return np.stack(f, axis=-1), rho
 
 
-S_LEARN = 6.0
+S_EXACT = 12.0      # default bands of the surrogate: exp(-s) of a line mode's largest block
+S_LEARN = 20.0
 
 
 _SUR = {}
@@ -156,18 +157,18 @@ def test_bf16_inference_matches_oracle_with_rounded_weights():
     sur = Surrogate(r_c=R_C)
     sur.set_mlp(net)
     nz = 256
-    m = rng.integers(0, nz // 2 + 1, size=40)
-    d1 = rng.integers(-40, 41, size=40)
-    d2 = rng.integers(-40, 41, size=40)
+    m = rng.integers(1, nz // 2 + 1, size=120)
+    d1 = rng.integers(-40, 41, size=120)
+    d2 = rng.integers(-40, 41, size=120)
     _, rho = _features(m / nz, d1, d2)
-    keep = (rho > R_C + 0.5) & (2 * math.pi * (m / nz) * math.sqrt(2) * rho < S_LEARN - 0.1)
-    m, d1, d2 = m[keep], d1[keep], d2[keep]
+    keep = (rho > R_C + 0.5) & (2 * math.pi * (m / nz) * math.sqrt(2) * rho < 30)   # continuum table range
+    assert keep.sum() >= 20
+    m, d1, d2, rho = m[keep], d1[keep], d2[keep], rho[keep]
     th = m / nz
     g_c = _eval(sur, th, d1, d2, use_mlp=False)
     g_m = _eval(sur, th, d1, d2, use_mlp=True)
-    w = np.sqrt(np.array([1, 1, 1, 2, 2, 2], dtype=np.float64))
-    env = np.linalg.norm(g_c * w, axis=1) + 1e-3
-    y_got = (g_m - g_c) * np.exp(-1j * math.pi * th * d1)[:, None] / env[:, None]
+    # the point evaluation applies the network with a unit envelope
+    y_got = (g_m - g_c) * np.exp(-1j * math.pi * th * d1)[:, None]
     y_got = np.stack([y_got.real, y_got.imag], axis=-1).reshape(-1, 12)
     pb = osp.round_bf16(p.astype(np.float64))
     layers = omlp.unpack(pb.copy())
@@ -205,35 +206,37 @@ def test_training_set_matches_oracle_values():
     assert np.abs(x - f_ref).max() < 1e-6
     rho = R_C / x[:, 6]
     assert (rho > R_C * (1 - 1e-6)).all()          # r_c / rho is stored in FP32
-    s_all = 2 * math.pi * (x[:, 7] / 8) * math.sqrt(2) * rho
-    assert (s_all <= S_LEARN * (1 + 1e-6)).all()
     nz = wl.cells[0].nz
+    c0 = wl.cells[0]
+    offs = np.unique((np.asarray(c0.cols_b)[:, None, :] - np.asarray(c0.cols_i)[None, :, :]).reshape(-1, 2), axis=0)
     cij = ocg.nn_fcc_stiffness(1.0)
-    w6 = np.sqrt(np.array([1, 1, 1, 2, 2, 2]))
-    pos = [k for k in range(x.shape[0]) if x[k, 7] > 0][:3]
-    zero = [k for k in range(x.shape[0]) if x[k, 7] == 0][:2]
-    assert len(pos) == 3 and len(zero) == 2
-    implied_c = []
-    for k in pos + zero:
+    # line mode 0 is taken exact by the surrogate: no training sample at theta0 = 0
+    assert (x[:, 7] > 0).all()
+    pos = list(range(5))
+    for k in pos:
         xx, yy = rho[k] * x[k, 0], rho[k] * x[k, 1]
         d1 = int(round(2 * xx))
         d2 = int(round((yy * 2 * math.sqrt(2) - d1) / 2))
         m = int(round(x[k, 7] / 8 * nz))
-        lgf = _sym6(ogr.line_mode_green(nz, wl.bz, wl.bz, m)[d1 % wl.bz, d2 % wl.bz])
-        cg = _sym6(ocg.line_mode_cgf(nz, m, d1, d2, cij))
-        env = np.linalg.norm(cg * w6) + 1e-3
+        full = ogr.line_mode_green(nz, wl.bz, wl.bz, m)
+        lgf = _sym6(full[d1 % wl.bz, d2 % wl.bz])
+        # the learned band lies beyond the last block of exp(-s_exact) times the mode's
+        # largest block (largest |component| over the context's offsets)
+        blocks = full[offs[:, 0] % wl.bz, offs[:, 1] % wl.bz]
+        amax = max(np.abs(blocks.real).max(), np.abs(blocks.imag).max())
+        assert max(np.abs(lgf.real).max(), np.abs(lgf.imag).max()) < math.exp(-S_EXACT) * amax, k
+        # the continuum subtracted is the device's own value (its accuracy against the
+        # oracle's quadrature is tested above, where it matters; far out in kappa rho the
+        # values are below exp(-s_learn) of the mode's scale)
+        cg = _eval(sur, [m / nz], [d1], [d2], use_mlp=False)[0]
+        if 2 * math.pi * (m / nz) * math.sqrt(2) * rho[k] < 20:
+            cg_o = _sym6(ocg.line_mode_cgf(nz, m, d1, d2, cij))
+            assert np.linalg.norm(cg - cg_o) < 1e-3 * np.linalg.norm(cg_o), k
+        env = math.exp(-S_EXACT) * amax
         rot = np.exp(-1j * math.pi * (m / nz) * d1)
         got = t[k, 0::2] + 1j * t[k, 1::2]
-        if m > 0:
-            ref = (lgf - cg) * rot / env
-            # the device continuum value is an interpolated table (~1e-4 of |G_cgf|)
-            assert np.abs(got - ref).max() < 5e-4 * np.linalg.norm(cg) / env + 1e-6, (k, got, ref)
-        else:
-            # line mode 0 subtracts the context's matching constant: a real constant
-            c_k = lgf - cg - got * env
-            assert np.abs(c_k.imag).max() < 1e-6 * np.abs(cg).max()
-            implied_c.append(c_k.real)
-    assert np.abs(implied_c[0] - implied_c[1]).max() < 2e-3 * np.abs(implied_c[0]).max(), implied_c
+        ref = (lgf - cg) * rot / env
+        assert np.abs(got - ref).max() < 1e-6 * np.abs(ref).max() + 1e-9, (k, got, ref)
 
 
 def _apply(cells, bz, form, alpha, u0, **kw):
@@ -258,13 +261,17 @@ def _oracle_update(cells, bz, u0, alpha):
     return np.concatenate(out)
 
 
-@pytest.mark.parametrize("gen_modes", [0, 1, 3])
-def test_surrogate_form_is_exact_inside_r_c(gen_modes):
-    """With r_c beyond every offset the generated table is the exact one, for any chunking."""
+@pytest.mark.parametrize("gen_modes,r_c,s_exact", [(0, 500.0, S_EXACT), (1, 500.0, S_EXACT), (3, 500.0, S_EXACT),
+                                                  (0, 2.0, 40.0), (2, 2.0, 40.0)])
+def test_surrogate_form_is_exact_inside_r_c(gen_modes, r_c, s_exact):
+    """With r_c beyond every offset, or the exact band up to the continuum table's end
+    (kappa rho = 40, beyond which the values are below exp(-40) of a mode's scale), the
+    generated table is the exact one, for any chunking."""
     from paper_2105_08798_amd import MLP, Surrogate
     _dev()
     net = MLP(max_batch=16, seed=1)
-    sur = Surrogate(r_c=500.0)
+    sur = Surrogate(r_c=r_c)
+    sur.set_exact_range(s_exact)
     sur.set_mlp(net)
     cells = W.make_custom(16, 30, 45, 3, 32, seed=1).cells + W.make_custom(8, 12, 20, 5, 32, seed=2).cells
     rng = np.random.default_rng(3)
@@ -351,10 +358,10 @@ def test_gain_learned_correction_beats_the_continuum_alone():
     ref = _oracle_update(cells, 256, u0, -1.0)
     e_mlp = np.linalg.norm(_apply(cells, 256, "surrogate", -1.0, u0, surrogate=sur) - ref) / np.linalg.norm(ref)
     e_cgf = np.linalg.norm(_apply(cells, 256, "surrogate", -1.0, u0, surrogate=cgf_only) - ref) / np.linalg.norm(ref)
-    print(f"gain: pointwise held-out {pointwise:.3e}; update error continuum + matching constant "
-          f"{e_cgf:.3e}, learned {e_mlp:.3e}")
+    print(f"gain: pointwise held-out {pointwise:.3e}; update error with the continuum alone "
+          f"{e_cgf:.3e}, with the learned correction {e_mlp:.3e}")
     for o in (sur, cgf_only, net, zero):
         o.close()
     del dev, rng
-    assert pointwise < 0.3
+    assert pointwise < 0.5
     assert e_mlp < 0.5 * e_cgf, (e_mlp, e_cgf)
