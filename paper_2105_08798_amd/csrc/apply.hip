@@ -251,13 +251,17 @@ __device__ inline void put_b_units(void* bm, int n, int kq0, int kp, const doubl
     }
 }
 
+typedef double dv2_t __attribute__((ext_vector_type(2)));
+
+// pairs: K even and f 16-byte aligned, so two adjacent columns load as one 16-byte access
+// and store as one complex LDS entry.
 template <int FORM>
 __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
                                                   const double* __restrict__ tot, int project,
                                                   void* __restrict__ bfrag, int nz, int logn,
                                                   int n_i, int kp, int ct, int tc,
                                                   const double2* __restrict__ tw, double inv_cnt,
-                                                  const int* __restrict__ bexp) {
+                                                  const int* __restrict__ bexp, int pairs) {
     extern __shared__ double2 lds[];
     // RHS fastest across blocks: the 8 RHS of a column tile, whose 64-byte column runs
     // fill the same 1 KiB fragment blocks, are written by neighbouring blocks close in time
@@ -274,6 +278,38 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     // the forces are read once per update: nontemporal loads keep them from displacing
     // the fragments the product reads next (measured: 2 % faster large step)
     constexpr int LU = 8;
+    if (pairs) {
+        const int hp = tc >> 1;
+        for (int t0 = threadIdx.x; t0 < nz * hp; t0 += NT * LU) {
+            dv2_t v[LU];
+#pragma unroll
+            for (int q = 0; q < LU; ++q) {
+                const int t = t0 + q * NT;
+                const int n0 = t / hp, k = k0 + 2 * (t - n0 * hp);
+                v[q] = (t < nz * hp && k < K)
+                           ? __builtin_nontemporal_load((const dv2_t*)(f + ((int64_t)r * nz + n0) * K + k))
+                           : dv2_t{0.0, 0.0};
+            }
+#pragma unroll
+            for (int q = 0; q < LU; ++q) {
+                const int t = t0 + q * NT;
+                if (t >= nz * hp) break;
+                const int n0 = t / hp, p = t - n0 * hp, k = k0 + 2 * p;
+                double x0 = v[q].x, x1 = v[q].y;
+                if (k < K) {
+                    if (project) {                  // mean over the cell's atoms
+                        x0 -= tot[r * 3 + (k % 3)] * inv_cnt;
+                        x1 -= tot[r * 3 + ((k + 1) % 3)] * inv_cnt;
+                    }
+                    if (FORM == FBC_FORM_SPLIT_FP16) {
+                        x0 = ldexp(x0, esc);
+                        x1 = ldexp(x1, esc);
+                    }
+                }
+                lds[p * ss + (int)bitrev(n0, logn)] = make_double2(x0, x1);
+            }
+        }
+    } else
     for (int t0 = threadIdx.x; t0 < nz * tc; t0 += NT * LU) {
         double v[LU];
 #pragma unroll
@@ -394,24 +430,25 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
     if (tc > kk) tc = kk;
     tc &= ~1;
     dim3 grid(R, (unsigned)std::min((K + tc - 1) / tc, 65535));
+    const int pairs = ((K & 1) == 0 && ((uintptr_t)f & 15) == 0) ? 1 : 0;
     const size_t lds = (size_t)(nz + 1) * tc * sizeof(double);
     const double inv_cnt = 1.0 / ((double)n_i * nz);
     switch (form) {
         case FBC_FORM_FP32:
             hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP32>, grid, dim3(NT), lds, st, f, tot, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
             break;
         case FBC_FORM_SPLIT_FP16:
             hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_FP16>, grid, dim3(NT), lds, st, f, tot,
-                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
+                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
             break;
         case FBC_FORM_SPLIT_BF16:
             hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_BF16>, grid, dim3(NT), lds, st, f, tot,
-                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
+                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
             break;
         default:
             hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP64>, grid, dim3(NT), lds, st, f, tot, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp);
+                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
             break;
     }
 }
