@@ -568,6 +568,31 @@ def bench_hmat(args, torch) -> dict:
     torch.cuda.synchronize()
     dense_ms, n_d = ctx.timing_read()
     dense_ms = dense_ms / max(n_d, 1)
+
+    # whole fbc_apply steps: dense FP64 store, offset-table product, and the H-matrix
+    # attached as the table context's product step
+    def apply_ms(cx):
+        u = torch.zeros(R * c.nz * c.n_b * 3, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            cx.apply(f, u, alpha=1.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            cx.apply(f, u, alpha=1.0)
+        torch.cuda.synchronize()
+        ms_ = 1000.0 * (time.perf_counter() - t) / args.steps
+        u.zero_()
+        cx.apply(f, u, alpha=1.0)
+        return ms_, u.cpu().numpy()
+
+    step_ms = {}
+    step_ms["fp64"], u_dense = apply_ms(ctx)
+    step_ms["dtable_fp64"], _ = apply_ms(tab)
+    tab.set_hmat(h)
+    step_ms["dtable_fp64+hmat"], u_h = apply_ms(tab)
+    tab.set_hmat(None)
+    upd_err = float(np.linalg.norm(u_h - u_dense) / np.linalg.norm(u_dense))
+    log(f"hmat: fbc_apply ms/step {step_ms}; H-matrix update vs dense FP64 update {upd_err:.2e}")
     info = h.info
     from oracle import green
     yy = y.cpu().numpy()
@@ -591,7 +616,8 @@ def bench_hmat(args, torch) -> dict:
                    "build_s": t_build, "n_blocks": info.n_blocks, "n_low_rank": info.n_low_rank,
                    "max_rank_used": info.max_rank_used, "n_over_rank": info.n_over_rank,
                    "stored_fraction": info.stored_entries / info.dense_entries,
-                   "dense_fp64_product_ms": dense_ms, "rel_err_modes_0_7_64": errs},
+                   "dense_fp64_product_ms": dense_ms, "rel_err_modes_0_7_64": errs,
+                   "apply_ms_per_step": step_ms, "hmat_update_rel_err_vs_dense": upd_err},
         "roofline": {"bound": "hbm", "achieved": bytes_ / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_hmat_vt + k_hmat_y", "bytes_per_launch": bytes_},

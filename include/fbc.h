@@ -557,6 +557,18 @@ fbc_status fbc_hmat_ranks(const fbc_hmat* h, int32_t* out);
  * object must be ordered (it holds the products V^T f of the call in flight). */
 fbc_status fbc_hmat_apply(fbc_hmat* h, const double* fhat, double* what, void* stream);
 
+/* Attaches h (built from c by fbc_hmat_create) as the product step of c's pipeline:
+ * fbc_apply, fbc_apply_graph, fbc_green_apply, fbc_relax_step and fbc_relax_step_graph
+ * then apply the H-matrix of every line mode (Section 3.2 / Appendix C) in place of the
+ * offset-table product, reading the forward transform's output and writing the records
+ * the inverse transform reads (no extra pass); h = NULL detaches.  The work list is set
+ * to one K slice while attached (its K slices come back on detaching); fbc_autotune and
+ * fbc_set_work_list return FBC_E_STATE while an H-matrix is attached; captured graphs are
+ * dropped.  fbc_hmat_destroy of an attached
+ * object detaches it.  FBC_E_ARG when h was built from another context.  Synchronises
+ * `stream`. */
+fbc_status fbc_set_hmat(fbc_ctx* c, fbc_hmat* h, void* stream);
+
 const char* fbc_status_string(fbc_status s);
 
 #ifdef __cplusplus

@@ -1126,6 +1126,10 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
                              (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2,
                              c->n_need, c->n_offsets, c->job_order == 3 ? &ql : nullptr);
         }
+    } else if (form == FBC_FORM_DTABLE_FP64 && c->hmat) {
+        const CellPlan& p = c->cells[0];          // one cell (checked when attached)
+        hmat_enqueue_pipeline(c->hmat, (const double*)c->bfrag + p.b_off, b_mode_elems(form, p), p.kp,
+                              c->cbuf + p.c_off, p.mp, p.nm, p.ct, st);
     } else if (form == FBC_FORM_DTABLE_FP64)
         launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, 0, (const double*)c->bfrag, c->cbuf,
                          c->celldev, c->lut, c->d1min, c->d2min, c->w2, nullptr, c->n_offsets,
@@ -1253,6 +1257,7 @@ extern "C" fbc_status fbc_autotune(fbc_ctx* c, const double* f, double* w, int r
                                    fbc_tune_result* out, void* stream) {
     fbc_status s = check_apply_args(c, f, w);
     if (s != FBC_OK) return s;
+    if (c->hmat) return fail(c, FBC_E_STATE, "an H-matrix is attached: its product has no work list to tune");
     if (reps < 1 || reps > 1000) return fail(c, FBC_E_ARG, "reps must be in [1, 1000]");
     if (c->opt.form == FBC_FORM_SURROGATE) return fail(c, FBC_E_UNSUPPORTED, "the surrogate form keeps its mode-major list");
     hipStream_t st = (hipStream_t)stream;
@@ -1409,6 +1414,7 @@ extern "C" fbc_status fbc_set_kernel_variant(fbc_ctx* c, int variant) {
 
 extern "C" fbc_status fbc_set_work_list(fbc_ctx* c, int nsplit, int order, void* stream) {
     if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
+    if (c->hmat) return fail(c, FBC_E_STATE, "an H-matrix is attached: detach it first");
     if (nsplit < 1 || nsplit > c->nsplit_cap)
         return fail(c, FBC_E_ARG, "nsplit must be in [1, " + std::to_string(c->nsplit_cap) + "]");
     if (order < 0 || order > 4) return fail(c, FBC_E_ARG, "order must be 0, 1, 2, 3 or 4");
@@ -1438,6 +1444,35 @@ static void drop_relax_graph(fbc_ctx* c) {
     if (c->rgraph) (void)hipGraphDestroy(c->rgraph);
     c->rgraph_exec = nullptr;
     c->rgraph = nullptr;
+}
+
+extern "C" fbc_status fbc_set_hmat(fbc_ctx* c, fbc_hmat* h, void* stream) {
+    if (!c) return fail(nullptr, FBC_E_ARG, "ctx is NULL");
+    if (h && hmat_context(h) != c) return fail(c, FBC_E_ARG, "the H-matrix was built from another context");
+    if (h == c->hmat) return FBC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (h && !c->hmat) {
+        // the products land in one K slice: the inverse transform must read one; the work
+        // list in place comes back on detaching
+        c->hmat_prev_nsplit = c->nsplit;
+        if (c->nsplit != 1) {
+            fbc_status s = upload_jobs(c, 1, c->job_order, st);
+            if (s != FBC_OK) return s;
+        }
+    } else if (!h && c->hmat_prev_nsplit != c->nsplit) {
+        fbc_status s = upload_jobs(c, c->hmat_prev_nsplit, c->job_order, st);
+        if (s != FBC_OK) return s;
+    }
+    HIPCHK(c, hipStreamSynchronize(st));        // queued applies may still use the old product
+    c->hmat = h;
+    if (c->graph_exec) {                        // captured updates launch the old product
+        (void)hipGraphExecDestroy(c->graph_exec);
+        (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+    }
+    drop_relax_graph(c);
+    return FBC_OK;
 }
 
 extern "C" fbc_status fbc_relax_begin(fbc_ctx* c, const fbc_relax_opts* o, void* stream) {

@@ -9,6 +9,8 @@ struct fbc_sur;
 
 struct fbc_ctx {
     int device = 0;
+    fbc_hmat* hmat = nullptr;        // attached H-matrix: the product step of the apply pipeline
+    int hmat_prev_nsplit = 1;        // K slices of the work list before attaching
     fbc_options opt{};
     fbc_lattice lat{};
     std::vector<CellPlan> cells;

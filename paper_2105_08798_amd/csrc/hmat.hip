@@ -143,6 +143,41 @@ __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Operands of the product: either the plain layouts of fbc_hmat_apply (x [mode][3 n_i][R],
+// y [mode][3 n_b][R], complex) or, inside a context's apply pipeline, the context's own
+// ones: x read from the forward transform's FP64 B fragments (RHS r = 8 tile + j: column
+// 16 tile + j holds Re f^ at K' = 2k, column 16 tile + j + 8 holds Im f^ there) and y
+// written as the product records the inverse transform reads ([tile][row][mode][16]:
+// Re of the tile's 8 RHS, then Im), every RHS slot of the tiles written (zeros past R).
+struct HIo {
+    const double2* x;      // plain input (NULL: fragments)
+    double2* y;            // plain output (NULL: records)
+    const double* bf;      // fragments of mode 0; mode m at + m * bf_mode
+    int64_t bf_mode;
+    int kp;
+    double* rec;           // records of the cell
+    int mp, nm;
+    int r_out;             // RHS slots written per row: R (plain) or 8 x tiles (records)
+};
+
+__device__ inline double2 xval(const HIo& io, int m, int col, int r, int n_i, int R) {
+    if (io.x) return io.x[((int64_t)m * 3 * n_i + col) * R + r];
+    const double* b = io.bf + (int64_t)m * io.bf_mode;
+    const int tile = r >> 3, j = r & 7;
+    return make_double2(b[frag_off_f64(16 * tile + j, 2 * col, io.kp)],
+                        b[frag_off_f64(16 * tile + j + 8, 2 * col, io.kp)]);
+}
+
+__device__ inline void yput(const HIo& io, int m, int row, int r, int n_b, int R, double2 v) {
+    if (io.y) {
+        io.y[((int64_t)m * 3 * n_b + row) * R + r] = v;
+        return;
+    }
+    double* rec = io.rec + (((int64_t)(r >> 3) * io.mp + row) * io.nm + m) * 16;
+    rec[r & 7] = v.x;
+    rec[8 + (r & 7)] = v.y;
+}
+
 // Fixed-order reductions over the work group.
 __device__ inline double block_sum_d(double v, double* red) {
     red[threadIdx.x] = v;
@@ -307,7 +342,7 @@ __global__ void __launch_bounds__(NTH) k_hmat_aca(const HBlk* __restrict__ blks,
 __global__ void __launch_bounds__(NTH) k_hmat_vt(const HBlk* __restrict__ blks, const int* __restrict__ lr_ids,
                                                  const int32_t* __restrict__ scols, const double2* __restrict__ V,
                                                  int64_t v_mode, const int* __restrict__ rank, int n_lr,
-                                                 int max_rank, const double2* __restrict__ x, int n_i, int R,
+                                                 int max_rank, HIo io, int n_i, int R,
                                                  double2* __restrict__ T) {
     const int li = blockIdx.x, m = blockIdx.y;
     const int k = rank[(int64_t)m * n_lr + li];
@@ -315,13 +350,12 @@ __global__ void __launch_bounds__(NTH) k_hmat_vt(const HBlk* __restrict__ blks, 
     const HBlk b = blks[lr_ids[li]];
     const int nc = 3 * b.ns;
     const double2* Vb = V + (int64_t)m * v_mode + b.v_off;
-    const double2* xm = x + (int64_t)m * 3 * n_i * R;
     double2* Tb = T + ((int64_t)m * n_lr + li) * max_rank * R;
     for (int e = threadIdx.x; e < k * R; e += NTH) {
         const int l = e / R, r = e - l * R;
         double2 acc = make_double2(0, 0);
         for (int j = 0; j < nc; ++j) {
-            const double2 p = cmul(Vb[(int64_t)l * nc + j], xm[(int64_t)gcol(scols, b.s_off, j) * R + r]);
+            const double2 p = cmul(Vb[(int64_t)l * nc + j], xval(io, m, gcol(scols, b.s_off, j), r, n_i, R));
             acc.x += p.x;
             acc.y += p.y;
         }
@@ -336,7 +370,8 @@ struct HContrib {
 
 // y rows of one pad leaf: sum over the blocks that cover it (low rank: U rows times T;
 // dense or over the rank bound: the stored entries times x).  A thread owns one row and
-// up to HR right-hand sides, so each factor or stored entry is read once per HR of them.
+// up to HR right-hand sides, so each factor or stored entry is read once per HR of them;
+// the RHS slots from R to io.r_out are written as zeros.
 #define HR 8
 __global__ void __launch_bounds__(NTH) k_hmat_y(const HBlk* __restrict__ blks, const int32_t* __restrict__ scols,
                                                 const int32_t* __restrict__ leaf_cols,
@@ -345,15 +380,14 @@ __global__ void __launch_bounds__(NTH) k_hmat_y(const HBlk* __restrict__ blks, c
                                                 const int* __restrict__ contrib_off, HStore st,
                                                 const double2* __restrict__ U, int64_t u_mode,
                                                 const double2* __restrict__ T, const int* __restrict__ rank,
-                                                int n_lr, int max_rank, const double2* __restrict__ x, int n_i,
-                                                int n_b, int R, double2* __restrict__ y) {
+                                                int n_lr, int max_rank, HIo io, int n_i,
+                                                int n_b, int R) {
     const int leaf = blockIdx.x, m = blockIdx.y;
     const int c0 = leaf_off[leaf], nl = leaf_off[leaf + 1] - c0;
-    const int nrc = (R + HR - 1) / HR;
-    const double2* xm = x + (int64_t)m * 3 * n_i * R;
+    const int nrc = (io.r_out + HR - 1) / HR;
     for (int e = threadIdx.x; e < 3 * nl * nrc; e += NTH) {
         const int rl = e / nrc, r0 = (e - rl * nrc) * HR;       // row within the leaf, first RHS
-        const int nr_here = min(HR, R - r0);
+        const int nr_here = min(HR, R - r0);                      // <= 0: zero slots only
         const int grow = 3 * leaf_cols[c0 + rl / 3] + rl % 3;
         double2 acc[HR];
 #pragma unroll
@@ -377,25 +411,23 @@ __global__ void __launch_bounds__(NTH) k_hmat_y(const HBlk* __restrict__ blks, c
                             acc[q].y += p.y;
                         }
                 }
-            } else {
+            } else if (nr_here > 0) {
                 for (int j = 0; j < 3 * b.ns; ++j) {
                     const int gc = gcol(scols, b.s_off, j);
                     const double2 a = entry(st, m, grow, gc);
-                    const double2* xr = xm + (int64_t)gc * R + r0;
 #pragma unroll
                     for (int q = 0; q < HR; ++q)
                         if (q < nr_here) {
-                            const double2 p = cmul(a, xr[q]);
+                            const double2 p = cmul(a, xval(io, m, gc, r0 + q, n_i, R));
                             acc[q].x += p.x;
                             acc[q].y += p.y;
                         }
                 }
             }
         }
-        double2* yr = y + ((int64_t)m * 3 * n_b + grow) * R + r0;
 #pragma unroll
         for (int q = 0; q < HR; ++q)
-            if (q < nr_here) yr[q] = acc[q];
+            if (r0 + q < io.r_out) yput(io, m, grow, r0 + q, n_b, R, acc[q]);
     }
 }
 
@@ -611,7 +643,12 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
     return FBC_OK;
 }
 
-extern "C" void fbc_hmat_destroy(fbc_hmat* h) { hmat_free(h); }
+extern "C" void fbc_hmat_destroy(fbc_hmat* h) {
+    // an object attached to its context is detached first (the context's applies then
+    // go back to the offset-table product)
+    if (h && h->ctx && h->ctx->hmat == h) (void)fbc_set_hmat(const_cast<fbc_ctx*>(h->ctx), nullptr, nullptr);
+    hmat_free(h);
+}
 
 extern "C" fbc_status fbc_hmat_get_info(const fbc_hmat* h, fbc_hmat_info* info) {
     if (!h || !info) return hfail(FBC_E_ARG, "null argument");
@@ -641,17 +678,41 @@ extern "C" fbc_status fbc_hmat_ranks(const fbc_hmat* h, int32_t* out) {
     return FBC_OK;
 }
 
+static void hmat_launch(fbc_hmat* h, const HIo& io, hipStream_t sm) {
+    if (h->n_lr > 0)
+        hipLaunchKernelGGL(k_hmat_vt, dim3(h->n_lr, h->nm), dim3(NTH), 0, sm, h->blk_d, h->lr_ids, h->scols, h->V,
+                           h->v_mode, h->rank, h->n_lr, h->max_rank, io, h->n_i, h->R, h->T);
+    hipLaunchKernelGGL(k_hmat_y, dim3(h->n_leaves, h->nm), dim3(NTH), 0, sm, h->blk_d, h->scols, h->leaf_cols,
+                       h->leaf_off, h->contrib, h->contrib_off, h->st, h->U, h->u_mode, h->T, h->rank, h->n_lr,
+                       h->max_rank, io, h->n_i, h->n_b, h->R);
+}
+
 extern "C" fbc_status fbc_hmat_apply(fbc_hmat* h, const double* fhat, double* what, void* stream) {
     if (!h) return hfail(FBC_E_ARG, "object is NULL");
     if (!fhat || !what) return hfail(FBC_E_ARG, "fhat and what must be device pointers");
-    hipStream_t sm = (hipStream_t)stream;
-    if (h->n_lr > 0)
-        hipLaunchKernelGGL(k_hmat_vt, dim3(h->n_lr, h->nm), dim3(NTH), 0, sm, h->blk_d, h->lr_ids, h->scols, h->V,
-                           h->v_mode, h->rank, h->n_lr, h->max_rank, (const double2*)fhat, h->n_i, h->R, h->T);
-    hipLaunchKernelGGL(k_hmat_y, dim3(h->n_leaves, h->nm), dim3(NTH), 0, sm, h->blk_d, h->scols, h->leaf_cols,
-                       h->leaf_off, h->contrib, h->contrib_off, h->st, h->U, h->u_mode, h->T, h->rank, h->n_lr,
-                       h->max_rank, (const double2*)fhat, h->n_i, h->n_b, h->R, (double2*)what);
+    HIo io{};
+    io.x = (const double2*)fhat;
+    io.y = (double2*)what;
+    io.r_out = h->R;
+    hmat_launch(h, io, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hfail(FBC_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     return FBC_OK;
 }
+
+// The product step of a context's apply pipeline (fbc_set_hmat): B fragments in, product
+// records out (one K slice).
+void hmat_enqueue_pipeline(fbc_hmat* h, const double* bfrag, int64_t bf_mode, int kp, double* rec, int mp, int nm,
+                           int ct, hipStream_t st) {
+    HIo io{};
+    io.bf = bfrag;
+    io.bf_mode = bf_mode;
+    io.kp = kp;
+    io.rec = rec;
+    io.mp = mp;
+    io.nm = nm;
+    io.r_out = 8 * ct;
+    hmat_launch(h, io, st);
+}
+
+const fbc_ctx* hmat_context(const fbc_hmat* h) { return h->ctx; }

@@ -57,6 +57,10 @@ void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, co
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
                       const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
                       int64_t n_off, const PqLists* q);   // q != NULL: persistent work-queue kernel
+// H-matrix product step (hmat.hip): B fragments of one FP64 cell in, product records out
+void hmat_enqueue_pipeline(fbc_hmat* h, const double* bfrag, int64_t bf_mode, int kp, double* rec, int mp, int nm,
+                           int ct, hipStream_t st);
+const fbc_ctx* hmat_context(const fbc_hmat* h);
 void irfft_shape(int nz, int* tr, int* pp);
 void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_part, int R,
                        int nz, int mp, int M, int ct, int ct_grid, const double2* tw, int nsplit,

@@ -31,7 +31,7 @@ EXPORTED = [
     "fbc_hmat_last_error", "fbc_hmat_create", "fbc_hmat_destroy", "fbc_hmat_get_info", "fbc_hmat_partition",
     "fbc_hmat_ranks", "fbc_hmat_apply", "fbc_mlp_forward_noalloc", "fbc_mlp_forward_noalloc_max_rows",
     "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant", "fbc_sur_set_mlp_fp32",
-    "fbc_sur_set_learn_range", "fbc_sur_set_exact_range",
+    "fbc_sur_set_learn_range", "fbc_sur_set_exact_range", "fbc_set_hmat",
 ]
 
 
@@ -174,9 +174,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_hmat_partition.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.fbc_hmat_ranks.argtypes = [vp, vp]
     lib.fbc_hmat_apply.argtypes = [vp, vp, vp, vp]
+    lib.fbc_set_hmat.argtypes = [vp, vp, vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
                  "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant",
-                 "fbc_sur_set_mlp_fp32", "fbc_sur_set_learn_range", "fbc_sur_set_exact_range",
+                 "fbc_sur_set_mlp_fp32", "fbc_sur_set_learn_range", "fbc_sur_set_exact_range", "fbc_set_hmat",
                  "fbc_relax_get_state", "fbc_relax_set_state",
                  "fbc_sync_status", "fbc_get_info", "fbc_copy_block_rows", "fbc_timing", "fbc_timing_read",
                  "fbc_apply_graph", "fbc_autotune", "fbc_set_work_list", "fbc_sur_create", "fbc_sur_set_mlp", "fbc_sur_eval",
@@ -288,6 +289,13 @@ class FBC:
 
     def set_kernel_variant(self, variant: int):
         self._check(self._lib.fbc_set_kernel_variant(self.ctx, int(variant)))
+        self.info = self.get_info()
+
+    def set_hmat(self, h, stream=None):
+        """Product step from the H-matrix h (an HMatrix of this context), or None: the
+        offset-table product again."""
+        self._check(self._lib.fbc_set_hmat(self.ctx, h.handle if h is not None else None, _stream_handle(stream)))
+        self._hmat = h                       # keep it alive while attached
         self.info = self.get_info()
 
     def green_apply(self, f, w, stream=None):

@@ -138,3 +138,56 @@ def test_degenerate_partitions_reproduce_the_dense_product(small, kw):
     if kw.get("max_rank") == 1:
         assert h.info.n_over_rank > 0
     h.close()
+
+
+def _update(ctx, c, u0, alpha=0.7):
+    dev = _dev()
+    f = torch.from_numpy(c.forces).to(dev)
+    u = torch.from_numpy(u0.copy()).to(dev)
+    ctx.apply(f, u, alpha=alpha)
+    assert ctx.sync_status() == 0
+    w = torch.zeros_like(u)
+    ctx.green_apply(f, w)
+    assert ctx.sync_status() == 0
+    return u.cpu().numpy(), w.cpu().numpy()
+
+
+@pytest.mark.parametrize("kw,tol", [(dict(max_rank=1), 1e-12), (dict(eps=1e-8, max_rank=64), 1e-6)])
+def test_attached_hmatrix_is_the_product_step_of_apply(kw, tol):
+    """fbc_set_hmat: fbc_apply and fbc_green_apply of the context run the H-matrix products
+    (forward transform's fragments in, inverse transform's records out).  With every
+    low-rank block sent back to the store (max_rank = 1) the update equals the
+    offset-table product's to rounding; with eps = 1e-8 it stays within the compression's
+    accuracy of the oracle's update.  Odd RHS count (a padded RHS slot in the records);
+    detaching, and destroying an attached object, give the offset-table product back."""
+    from paper_2105_08798_amd import FbcError, HMatrix
+    from oracle import apply as oap
+    _dev()
+    wl = W.make_custom(16, 400, 800, 3, 256, seed=41)
+    c = wl.cells[0]
+    ctx = _ctx(wl)
+    rng = np.random.default_rng(5)
+    u0 = rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 1e-3
+    u_tab, w_tab = _update(ctx, c, u0)
+    h = HMatrix(ctx, b_min=20, gamma=2, **{"eps": 1e-5, **kw})
+    ctx.set_hmat(h)
+    with pytest.raises(FbcError):
+        ctx.set_work_list(1, 1)
+    u_h, w_h = _update(ctx, c, u0)
+    g = green.green_modes_dense(c.nz, wl.bz, wl.bz, c.cols_b, c.cols_i)
+    u_ref = oap.pad_update(u0, oap.apply_green(g, c.forces), 0.7)[0]
+    e_tab = np.linalg.norm(u_h - u_tab) / np.linalg.norm(u_tab - u0)
+    e_ref = np.linalg.norm(u_h - u_ref) / np.linalg.norm(u_ref - u0)
+    e_w = np.linalg.norm(w_h - w_tab) / np.linalg.norm(w_tab)
+    print(f"[hmat {kw}] update vs table product {e_tab:.2e}, vs oracle {e_ref:.2e}; response {e_w:.2e}")
+    assert e_ref < tol and e_w < max(tol, 1e-12)
+    if kw.get("max_rank") == 1:
+        assert e_tab < 1e-12
+    ctx.set_hmat(None)
+    u_back, _ = _update(ctx, c, u0)
+    assert np.array_equal(u_back, u_tab)
+    ctx.set_hmat(h)
+    h.close()                        # destroying the attached object detaches it
+    u_back, _ = _update(ctx, c, u0)
+    assert np.array_equal(u_back, u_tab)
+    ctx.close()
