@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "assemble.hip", "apply.hip", "gemm.hip", "learned.hip", "learned_api.hip", "plgf.hip", "hmat.hip"]
+SOURCES = ["api.hip", "assemble.hip", "apply.hip", "gemm.hip", "learned.hip", "learned_api.hip", "plgf.hip", "hmat.hip",
+           "plan.cpp"]
 LIB = os.path.join(HERE, "libfbc.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -26,7 +27,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         cmd.remove("-shared")

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "ctx.h"
+#include "plan.h"
 
 int gemm_tile_rows(int form, int ctmax);
 extern "C" fbc_status fbc_timing(fbc_ctx* c, int enable);
@@ -167,60 +168,17 @@ static int64_t b_elem_bytes(int form) {
 // ----------------------------------------------------------------------------------
 // Assembly of one cell's offset table and store.
 // ----------------------------------------------------------------------------------
-struct OffsetSet {
-    int d1min, d2min, w1, w2;
-    std::vector<int32_t> lut, d1, d2;
-};
+using OffsetSet = PlanOffsets;
+
+static std::vector<PlanGeom> plan_geoms(const std::vector<CellPlan>& cells) {
+    std::vector<PlanGeom> g;
+    for (const CellPlan& p : cells) g.push_back(PlanGeom{p.n_i, p.n_b, p.cols_i.data(), p.cols_b.data()});
+    return g;
+}
 
 // Distinct column offsets n_b - n_i over every cell, indexed through a dense lookup
 // table over their bounding box (row-major over (d1, d2), so the numbering is fixed).
-static OffsetSet offsets_of(const std::vector<CellPlan>& cells) {
-    OffsetSet o{};
-    int lo1 = INT32_MAX, hi1 = INT32_MIN, lo2 = INT32_MAX, hi2 = INT32_MIN;
-    for (const CellPlan& p : cells) {
-        int b1lo = INT32_MAX, b1hi = INT32_MIN, b2lo = INT32_MAX, b2hi = INT32_MIN;
-        int i1lo = INT32_MAX, i1hi = INT32_MIN, i2lo = INT32_MAX, i2hi = INT32_MIN;
-        for (int b = 0; b < p.n_b; ++b) {
-            b1lo = std::min(b1lo, p.cols_b[2 * b]);
-            b1hi = std::max(b1hi, p.cols_b[2 * b]);
-            b2lo = std::min(b2lo, p.cols_b[2 * b + 1]);
-            b2hi = std::max(b2hi, p.cols_b[2 * b + 1]);
-        }
-        for (int i = 0; i < p.n_i; ++i) {
-            i1lo = std::min(i1lo, p.cols_i[2 * i]);
-            i1hi = std::max(i1hi, p.cols_i[2 * i]);
-            i2lo = std::min(i2lo, p.cols_i[2 * i + 1]);
-            i2hi = std::max(i2hi, p.cols_i[2 * i + 1]);
-        }
-        lo1 = std::min(lo1, b1lo - i1hi);
-        hi1 = std::max(hi1, b1hi - i1lo);
-        lo2 = std::min(lo2, b2lo - i2hi);
-        hi2 = std::max(hi2, b2hi - i2lo);
-    }
-    o.d1min = lo1;
-    o.d2min = lo2;
-    o.w1 = hi1 - lo1 + 1;
-    o.w2 = hi2 - lo2 + 1;
-    o.lut.assign((size_t)o.w1 * o.w2, -1);
-    for (const CellPlan& p : cells)
-        for (int b = 0; b < p.n_b; ++b)
-            for (int i = 0; i < p.n_i; ++i) {
-                const int x = p.cols_b[2 * b] - p.cols_i[2 * i] - o.d1min;
-                const int y = p.cols_b[2 * b + 1] - p.cols_i[2 * i + 1] - o.d2min;
-                o.lut[(size_t)x * o.w2 + y] = 0;
-            }
-    int32_t n = 0;
-    for (int x = 0; x < o.w1; ++x)
-        for (int y = 0; y < o.w2; ++y) {
-            int32_t& e = o.lut[(size_t)x * o.w2 + y];
-            if (e == 0) {
-                e = n++;
-                o.d1.push_back(x + o.d1min);
-                o.d2.push_back(y + o.d2min);
-            }
-        }
-    return o;
-}
+static OffsetSet offsets_of(const std::vector<CellPlan>& cells) { return plan_offsets(plan_geoms(cells)); }
 
 // ----------------------------------------------------------------------------------
 // Negligible-block windows.  At line mode m the Green function decays with kappa rho;
@@ -229,12 +187,6 @@ static OffsetSet offsets_of(const std::vector<CellPlan>& cells) {
 // pairs lie farther than that; the product then runs, per (mode, tile), over the cyclic
 // window of chunks that contains every non-negligible one.
 // ----------------------------------------------------------------------------------
-static double pair_rho(int32_t a1, int32_t a2, int32_t b1, int32_t b2) {
-    const int d1 = a1 - b1, d2 = a2 - b2;
-    const double x = 0.5 * d1, y = (d1 + 2.0 * d2) * (0.5 * M_SQRT1_2);
-    return std::sqrt(x * x + y * y);
-}
-
 static double skip_tolerance(const fbc_options& o) {
     if (o.skip_tol < 0) return -1.0;
     if (o.skip_tol > 0) return o.skip_tol;
@@ -247,81 +199,14 @@ static double skip_tolerance(const fbc_options& o) {
 static void compute_windows(fbc_ctx* c, const std::vector<double>& rho_cut, int rows_tile) {
     const bool dt = is_table_form(c->opt.form);
     for (CellPlan& p : c->cells) {
-        const int mult = c->nz_max / p.nz;
-        p.n_tiles = dt ? p.mp / 96 : p.mp / rows_tile;
-        p.n_chunks = dt ? (p.n_i + 7) / 8 : p.kp / 64;
-        const int NT_ = p.n_tiles, NC = p.n_chunks;
-        // pad columns of a tile and interface columns of a chunk
-        auto tile_cols = [&](int tl, int& b0, int& b1) {
-            if (dt) { b0 = 32 * tl; b1 = std::min(p.n_b, b0 + 32); }
-            else { b0 = (tl * rows_tile) / 3; b1 = std::min(p.n_b, ((tl + 1) * rows_tile + 2) / 3); }
-        };
-        auto chunk_cols = [&](int ch, int& i0, int& i1) {
-            if (dt) { i0 = 8 * ch; i1 = std::min(p.n_i, i0 + 8); }
-            else { i0 = (32 * ch) / 3; i1 = std::min(p.n_i, (32 * (ch + 1) + 2) / 3); }
-        };
-        std::vector<float> rmin((size_t)NT_ * NC, INFINITY);
-        std::vector<uint8_t> real_chunk(NC, 0);
-        for (int ch = 0; ch < NC; ++ch) {
-            int i0, i1;
-            chunk_cols(ch, i0, i1);
-            real_chunk[ch] = i0 < i1;
-        }
-        for (int tl = 0; tl < NT_; ++tl) {
-            int b0, b1;
-            tile_cols(tl, b0, b1);
-            for (int b = b0; b < b1; ++b) {
-                const int32_t a1 = p.cols_b[2 * b], a2 = p.cols_b[2 * b + 1];
-                for (int ch = 0; ch < NC; ++ch) {
-                    int i0, i1;
-                    chunk_cols(ch, i0, i1);
-                    float& r = rmin[(size_t)tl * NC + ch];
-                    for (int i = i0; i < i1; ++i)
-                        r = std::min(r, (float)pair_rho(a1, a2, p.cols_i[2 * i], p.cols_i[2 * i + 1]));
-                }
-            }
-        }
-        p.win_start.assign((size_t)p.nm * NT_, 0);
-        p.win_len.assign((size_t)p.nm * NT_, NC);
-        p.mode_skips.assign(p.nm, 0);
-        std::vector<uint8_t> neg(NC);
-        for (int m = 0; m < p.nm; ++m) {
-            const double rc = rho_cut[(size_t)m * mult];
-            for (int tl = 0; tl < NT_; ++tl) {
-                int b0, b1;
-                tile_cols(tl, b0, b1);
-                int nneg = 0;
-                for (int ch = 0; ch < NC; ++ch) {
-                    // (float) rmin rounds; a 1e-6 relative margin keeps the test on the safe side
-                    neg[ch] = (double)rmin[(size_t)tl * NC + ch] > rc * (1.0 + 1e-6) + 1e-6;
-                    nneg += neg[ch];
-                }
-                int start = 0, len = NC;
-                if (nneg == NC) {
-                    len = 0;
-                } else if (nneg > 0) {
-                    // longest cyclic run of negligible chunks
-                    int best = 0, best_end = 0, run = 0;
-                    for (int q = 0; q < 2 * NC; ++q) {
-                        if (neg[q % NC]) {
-                            ++run;
-                            if (run > best && run <= NC) { best = run; best_end = q; }
-                        } else {
-                            run = 0;
-                        }
-                    }
-                    start = (best_end + 1) % NC;
-                    len = NC - best;
-                }
-                p.win_start[(size_t)m * NT_ + tl] = start;
-                p.win_len[(size_t)m * NT_ + tl] = len;
-                if (b0 < b1 && len < NC)
-                    for (int ch = 0; ch < NC; ++ch) {
-                        const bool in = ((ch - start + NC) % NC) < len;
-                        if (!in && real_chunk[ch]) p.mode_skips[m] = 1;
-                    }
-            }
-        }
+        PlanWindows w;
+        plan_windows(PlanGeom{p.n_i, p.n_b, p.cols_i.data(), p.cols_b.data()}, p.nm, p.mp, p.kp, dt, rows_tile,
+                     c->nz_max / p.nz, rho_cut, w);
+        p.n_tiles = w.n_tiles;
+        p.n_chunks = w.n_chunks;
+        p.win_start.swap(w.win_start);
+        p.win_len.swap(w.win_len);
+        p.mode_skips.swap(w.mode_skips);
     }
 }
 

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "plan.h"
 
 #define NTH 256
 
@@ -31,84 +32,8 @@ static fbc_status hfail(fbc_status s, const std::string& m) {
 // ---------------------------------------------------------------------------------------
 // Host planning: cluster trees and block partition (geometry only, exact integers)
 // ---------------------------------------------------------------------------------------
-struct HNode {
-    std::vector<int> idx;             // column indices in tree order
-    long long xlo, xhi, ylo, yhi, sx, sy;
-    long long n, diam8;               // 8 diam^2 = 2 dX^2 + dY^2
-    int child[2] = {-1, -1};
-};
-
-static int build_tree(std::vector<HNode>& nodes, const std::vector<int32_t>& cols, std::vector<int> idx,
-                      int b_min) {
-    HNode h;
-    h.n = (long long)idx.size();
-    h.xlo = h.ylo = (1LL << 40);
-    h.xhi = h.yhi = -(1LL << 40);
-    h.sx = h.sy = 0;
-    for (int c : idx) {
-        const long long X = cols[2 * c], Y = (long long)cols[2 * c] + 2LL * cols[2 * c + 1];
-        h.xlo = std::min(h.xlo, X); h.xhi = std::max(h.xhi, X);
-        h.ylo = std::min(h.ylo, Y); h.yhi = std::max(h.yhi, Y);
-        h.sx += X; h.sy += Y;
-    }
-    const long long dx = h.xhi - h.xlo, dy = h.yhi - h.ylo;
-    h.diam8 = 2 * dx * dx + dy * dy;
-    const int me = (int)nodes.size();
-    nodes.push_back(h);
-    if ((int)idx.size() > b_min) {
-        const bool on_x = 2 * dx * dx >= dy * dy;      // longer side of the bounding box
-        auto key = [&](int c) -> long long {
-            return on_x ? (long long)cols[2 * c] : (long long)cols[2 * c] + 2LL * cols[2 * c + 1];
-        };
-        std::sort(idx.begin(), idx.end(), [&](int a, int b) {
-            const long long ka = key(a), kb = key(b);
-            return ka != kb ? ka < kb : a < b;
-        });
-        const size_t half = idx.size() / 2;
-        std::vector<int> lo(idx.begin(), idx.begin() + half), hi(idx.begin() + half, idx.end());
-        const int c0 = build_tree(nodes, cols, lo, b_min);
-        const int c1 = build_tree(nodes, cols, hi, b_min);
-        nodes[me].child[0] = c0;
-        nodes[me].child[1] = c1;
-        nodes[me].idx.clear();
-        nodes[me].idx.insert(nodes[me].idx.end(), nodes[c0].idx.begin(), nodes[c0].idx.end());
-        nodes[me].idx.insert(nodes[me].idx.end(), nodes[c1].idx.begin(), nodes[c1].idx.end());
-    } else {
-        nodes[me].idx = idx;
-    }
-    return me;
-}
-
-// eq. geom_adm on bounding boxes: min(diam t, diam s) <= gamma dist(t, s), with
-// 8 diam^2 = 2 dX^2 + dY^2 and 8 dist^2 = 2 gX^2 + gY^2 (gX, gY: gaps between the boxes).
-static bool admissible(const HNode& t, const HNode& s, int gamma) {
-    const long long gx = std::max(0LL, std::max(s.xlo - t.xhi, t.xlo - s.xhi));
-    const long long gy = std::max(0LL, std::max(s.ylo - t.yhi, t.ylo - s.yhi));
-    return std::min(t.diam8, s.diam8) <= (long long)gamma * gamma * (2 * gx * gx + gy * gy);
-}
-
-struct HPart {
-    int kind;      // 1 low rank, 0 dense
-    int t, s;      // tree nodes
-};
-
-static void partition(const std::vector<HNode>& tb, const std::vector<HNode>& ti, int t, int s, int gamma,
-                      std::vector<HPart>& out) {
-    if (admissible(tb[t], ti[s], gamma)) {
-        out.push_back({1, t, s});
-        return;
-    }
-    const bool tl = tb[t].child[0] < 0, sl = ti[s].child[0] < 0;
-    if (tl && sl) {
-        out.push_back({0, t, s});
-        return;
-    }
-    const int tc[2] = {tl ? t : tb[t].child[0], tl ? -1 : tb[t].child[1]};
-    const int sc[2] = {sl ? s : ti[s].child[0], sl ? -1 : ti[s].child[1]};
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            if (tc[a] >= 0 && sc[b] >= 0) partition(tb, ti, tc[a], sc[b], gamma, out);
-}
+using HNode = PlanNode;
+using HPart = PlanBlock;
 
 // Device block description.
 struct HBlk {
@@ -118,6 +43,7 @@ struct HBlk {
     int cap;             // rank capacity (low rank)
     int64_t u_off, v_off;   // factor offsets within a mode (double2)
     int lr;              // index among the low-rank blocks (T workspace)
+    int64_t d_off;       // dense leaves: offset of the entries within a mode (double2)
 };
 
 // Entries of G^(m): the offset table [mode][offset][6] of a one-cell FP64 offset-table
@@ -160,22 +86,33 @@ struct HIo {
     int r_out;             // RHS slots written per row: R (plain) or 8 x tiles (records)
 };
 
+template <bool PIPE>
 __device__ inline double2 xval(const HIo& io, int m, int col, int r, int n_i, int R) {
-    if (io.x) return io.x[((int64_t)m * 3 * n_i + col) * R + r];
-    const double* b = io.bf + (int64_t)m * io.bf_mode;
-    const int tile = r >> 3, j = r & 7;
-    return make_double2(b[frag_off_f64(16 * tile + j, 2 * col, io.kp)],
-                        b[frag_off_f64(16 * tile + j + 8, 2 * col, io.kp)]);
+    return io.x[((int64_t)m * 3 * n_i + col) * R + r];
 }
 
-__device__ inline void yput(const HIo& io, int m, int row, int r, int n_b, int R, double2 v) {
-    if (io.y) {
-        io.y[((int64_t)m * 3 * n_b + row) * R + r] = v;
-        return;
+// The pipeline's input in the plain layout x [mode][3 n_i][R] (one pass over the
+// fragments; the products then read x with unit stride over the right-hand sides).
+__global__ void __launch_bounds__(NTH) k_hmat_x(HIo io, int n_i, int R, double2* __restrict__ x) {
+    const int m = blockIdx.y;
+    const double* b = io.bf + (int64_t)m * io.bf_mode;
+    for (int e = blockIdx.x * NTH + threadIdx.x; e < 3 * n_i * R; e += gridDim.x * NTH) {
+        const int col = e / R, r = e - col * R;
+        const int tile = r >> 3, j = r & 7;
+        x[(int64_t)m * 3 * n_i * R + e] = make_double2(b[frag_off_f64(16 * tile + j, 2 * col, io.kp)],
+                                                       b[frag_off_f64(16 * tile + j + 8, 2 * col, io.kp)]);
     }
-    double* rec = io.rec + (((int64_t)(r >> 3) * io.mp + row) * io.nm + m) * 16;
-    rec[r & 7] = v.x;
-    rec[8 + (r & 7)] = v.y;
+}
+
+template <bool PIPE>
+__device__ inline void yput(const HIo& io, int m, int row, int r, int n_b, int R, double2 v) {
+    if constexpr (!PIPE) {
+        io.y[((int64_t)m * 3 * n_b + row) * R + r] = v;
+    } else {
+        double* rec = io.rec + (((int64_t)(r >> 3) * io.mp + row) * io.nm + m) * 16;
+        rec[r & 7] = v.x;
+        rec[8 + (r & 7)] = v.y;
+    }
 }
 
 // Fixed-order reductions over the work group.
@@ -338,11 +275,13 @@ __global__ void __launch_bounds__(NTH) k_hmat_aca(const HBlk* __restrict__ blks,
     if (threadIdx.x == 0) rank[(int64_t)m * n_lr + li] = (result < 0) ? -1 : k;
 }
 
-// T[lr][l][r] = sum_j V[l][j] x[col_j][r] for the low-rank blocks.
+// T[lr][l][r] = sum_j V[l][j] x[col_j][r] for the low-rank blocks, Rp columns per l (the
+// columns from R on zero, so the y kernel runs whole groups of HR right-hand sides).
+template <bool PIPE>
 __global__ void __launch_bounds__(NTH) k_hmat_vt(const HBlk* __restrict__ blks, const int* __restrict__ lr_ids,
                                                  const int32_t* __restrict__ scols, const double2* __restrict__ V,
                                                  int64_t v_mode, const int* __restrict__ rank, int n_lr,
-                                                 int max_rank, HIo io, int n_i, int R,
+                                                 int max_rank, HIo io, int n_i, int R, int Rp,
                                                  double2* __restrict__ T) {
     const int li = blockIdx.x, m = blockIdx.y;
     const int k = rank[(int64_t)m * n_lr + li];
@@ -350,16 +289,17 @@ __global__ void __launch_bounds__(NTH) k_hmat_vt(const HBlk* __restrict__ blks, 
     const HBlk b = blks[lr_ids[li]];
     const int nc = 3 * b.ns;
     const double2* Vb = V + (int64_t)m * v_mode + b.v_off;
-    double2* Tb = T + ((int64_t)m * n_lr + li) * max_rank * R;
-    for (int e = threadIdx.x; e < k * R; e += NTH) {
-        const int l = e / R, r = e - l * R;
+    double2* Tb = T + ((int64_t)m * n_lr + li) * max_rank * Rp;
+    for (int e = threadIdx.x; e < k * Rp; e += NTH) {
+        const int l = e / Rp, r = e - l * Rp;
         double2 acc = make_double2(0, 0);
-        for (int j = 0; j < nc; ++j) {
-            const double2 p = cmul(Vb[(int64_t)l * nc + j], xval(io, m, gcol(scols, b.s_off, j), r, n_i, R));
-            acc.x += p.x;
-            acc.y += p.y;
-        }
-        Tb[(int64_t)l * R + r] = acc;
+        if (r < R)
+            for (int j = 0; j < nc; ++j) {
+                const double2 p = cmul(Vb[(int64_t)l * nc + j], xval<PIPE>(io, m, gcol(scols, b.s_off, j), r, n_i, R));
+                acc.x += p.x;
+                acc.y += p.y;
+            }
+        Tb[(int64_t)l * Rp + r] = acc;
     }
 }
 
@@ -368,66 +308,104 @@ struct HContrib {
     int row0;          // first row of this leaf within the block's rows
 };
 
+// Entries of the dense leaves, per mode, column-major per block (entry (row i, column j)
+// at d_off + j * 3 nt + i), so that the rows of a leaf read consecutive addresses.
+__global__ void __launch_bounds__(NTH) k_hmat_dense(const HBlk* __restrict__ blks, const int* __restrict__ d_ids,
+                                                    const int32_t* __restrict__ tcols,
+                                                    const int32_t* __restrict__ scols, HStore st,
+                                                    double2* __restrict__ D, int64_t d_mode) {
+    const HBlk b = blks[d_ids[blockIdx.x]];
+    const int m = blockIdx.y;
+    const int nr = 3 * b.nt, n = nr * 3 * b.ns;
+    double2* Db = D + (int64_t)m * d_mode + b.d_off;
+    for (int e = threadIdx.x; e < n; e += NTH) {
+        const int j = e / nr, i = e - j * nr;
+        Db[e] = entry(st, m, gcol(tcols, b.t_off, i), gcol(scols, b.s_off, j));
+    }
+}
+
 // y rows of one pad leaf: sum over the blocks that cover it (low rank: U rows times T;
-// dense or over the rank bound: the stored entries times x).  A thread owns one row and
-// up to HR right-hand sides, so each factor or stored entry is read once per HR of them;
-// the RHS slots from R to io.r_out are written as zeros.
+// dense leaves: their stored entries times x; low-rank blocks over the rank bound: the
+// offset table's entries times x).  One wave per (leaf, mode), four modes per work group;
+// a lane owns one row of the leaf (rows past 64 in further passes) and HR right-hand sides
+// at a time, so each factor or stored entry is read once per HR of them, and the lanes
+// read consecutive rows of U and of the dense entries.  The RHS slots from R to
+// io.r_out are written as zeros.
 #define HR 8
+template <bool PIPE>
 __global__ void __launch_bounds__(NTH) k_hmat_y(const HBlk* __restrict__ blks, const int32_t* __restrict__ scols,
                                                 const int32_t* __restrict__ leaf_cols,
                                                 const int* __restrict__ leaf_off,
                                                 const HContrib* __restrict__ contrib,
                                                 const int* __restrict__ contrib_off, HStore st,
                                                 const double2* __restrict__ U, int64_t u_mode,
+                                                const double2* __restrict__ D, int64_t d_mode,
                                                 const double2* __restrict__ T, const int* __restrict__ rank,
                                                 int n_lr, int max_rank, HIo io, int n_i,
-                                                int n_b, int R) {
-    const int leaf = blockIdx.x, m = blockIdx.y;
-    const int c0 = leaf_off[leaf], nl = leaf_off[leaf + 1] - c0;
-    const int nrc = (io.r_out + HR - 1) / HR;
-    for (int e = threadIdx.x; e < 3 * nl * nrc; e += NTH) {
-        const int rl = e / nrc, r0 = (e - rl * nrc) * HR;       // row within the leaf, first RHS
-        const int nr_here = min(HR, R - r0);                      // <= 0: zero slots only
-        const int grow = 3 * leaf_cols[c0 + rl / 3] + rl % 3;
-        double2 acc[HR];
+                                                int n_b, int R, int Rp, int nm) {
+    const int leaf = blockIdx.x, lane = threadIdx.x & 63;
+    const int m = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
+    if (m >= nm) return;
+    const int c0 = leaf_off[leaf], nrow = 3 * (leaf_off[leaf + 1] - c0);
+    for (int rl = lane; rl - lane < nrow; rl += 64) {          // every lane runs every pass
+        const bool live = rl < nrow;
+        const int grow = live ? 3 * leaf_cols[c0 + rl / 3] + rl % 3 : 0;
+        for (int r0 = 0; r0 < io.r_out; r0 += HR) {
+            const int nr_here = min(HR, R - r0);                  // <= 0: zero slots only
+            double2 acc[HR];
 #pragma unroll
-        for (int q = 0; q < HR; ++q) acc[q] = make_double2(0, 0);
-        for (int q2 = contrib_off[leaf]; q2 < contrib_off[leaf + 1]; ++q2) {
-            const HContrib cb = contrib[q2];
-            const HBlk b = blks[cb.blk];
-            const int br = cb.row0 + rl;                 // row within the block
-            const int k = (b.kind == 1) ? rank[(int64_t)m * n_lr + b.lr] : -1;
-            if (k >= 0) {
-                const double2* Ub = U + (int64_t)m * u_mode + b.u_off;
-                const double2* Tb = T + ((int64_t)m * n_lr + b.lr) * max_rank * R + r0;
+            for (int q = 0; q < HR; ++q) acc[q] = make_double2(0, 0);
+            for (int q2 = contrib_off[leaf]; q2 < contrib_off[leaf + 1] && nr_here > 0 && live; ++q2) {
+                const HContrib cb = contrib[q2];
+                const HBlk b = blks[cb.blk];
+                const int br = cb.row0 + rl;                 // row within the block
                 const int nr = 3 * b.nt;
-                for (int l = 0; l < k; ++l) {
-                    const double2 u = Ub[(int64_t)l * nr + br];
+                const int k = (b.kind == 1) ? rank[(int64_t)m * n_lr + b.lr] : -1;
+                if (k >= 0) {
+                    // T holds Rp >= r0 + HR columns, zeros past R: no per-RHS test
+                    const double2* Ub = U + (int64_t)m * u_mode + b.u_off + br;
+                    const double2* Tb = T + ((int64_t)m * n_lr + b.lr) * max_rank * Rp + r0;
+                    for (int l = 0; l < k; ++l) {
+                        const double2 u = Ub[(int64_t)l * nr];
 #pragma unroll
-                    for (int q = 0; q < HR; ++q)
-                        if (q < nr_here) {
-                            const double2 p = cmul(u, Tb[(int64_t)l * R + q]);
-                            acc[q].x += p.x;
-                            acc[q].y += p.y;
+                        for (int q = 0; q < HR; ++q) {
+                            const double2 t = Tb[(int64_t)l * Rp + q];
+                            acc[q].x += u.x * t.x - u.y * t.y;
+                            acc[q].y += u.x * t.y + u.y * t.x;
                         }
-                }
-            } else if (nr_here > 0) {
-                for (int j = 0; j < 3 * b.ns; ++j) {
-                    const int gc = gcol(scols, b.s_off, j);
-                    const double2 a = entry(st, m, grow, gc);
+                    }
+                } else {
+                    const double2* Db = (b.kind == 0) ? D + (int64_t)m * d_mode + b.d_off + br : nullptr;
+                    if (nr_here == HR) {
+                        for (int j = 0; j < 3 * b.ns; ++j) {
+                            const int gc = gcol(scols, b.s_off, j);
+                            const double2 a = Db ? Db[(int64_t)j * nr] : entry(st, m, grow, gc);
 #pragma unroll
-                    for (int q = 0; q < HR; ++q)
-                        if (q < nr_here) {
-                            const double2 p = cmul(a, xval(io, m, gc, r0 + q, n_i, R));
-                            acc[q].x += p.x;
-                            acc[q].y += p.y;
+                            for (int q = 0; q < HR; ++q) {
+                                const double2 x = xval<PIPE>(io, m, gc, r0 + q, n_i, R);
+                                acc[q].x += a.x * x.x - a.y * x.y;
+                                acc[q].y += a.x * x.y + a.y * x.x;
+                            }
                         }
+                    } else {
+                        for (int j = 0; j < 3 * b.ns; ++j) {
+                            const int gc = gcol(scols, b.s_off, j);
+                            const double2 a = Db ? Db[(int64_t)j * nr] : entry(st, m, grow, gc);
+                            for (int q = 0; q < nr_here; ++q) {
+                                const double2 x = xval<PIPE>(io, m, gc, r0 + q, n_i, R);
+                                acc[q].x += a.x * x.x - a.y * x.y;
+                                acc[q].y += a.x * x.y + a.y * x.x;
+                            }
+                        }
+                    }
                 }
             }
-        }
+            if (live) {
 #pragma unroll
-        for (int q = 0; q < HR; ++q)
-            if (r0 + q < io.r_out) yput(io, m, grow, r0 + q, n_b, R, acc[q]);
+                for (int q = 0; q < HR; ++q)
+                    if (r0 + q < io.r_out) yput<PIPE>(io, m, grow, r0 + q, n_b, R, acc[q]);
+            }
+        }
     }
 }
 
@@ -446,10 +424,13 @@ struct fbc_hmat {
     std::vector<void*> allocs;
     HBlk* blk_d = nullptr;
     int* lr_ids = nullptr;
+    int* d_ids_d = nullptr;
     int32_t *tcols = nullptr, *scols = nullptr, *leaf_cols = nullptr;
     int *leaf_off = nullptr, *contrib_off = nullptr;
     HContrib* contrib = nullptr;
-    double2 *U = nullptr, *V = nullptr, *T = nullptr;
+    double2 *U = nullptr, *V = nullptr, *T = nullptr, *D = nullptr;
+    double2* xbuf = nullptr;              // pipeline input in the plain layout
+    int64_t d_mode = 0;
     int* rank = nullptr;
     double stored = 0, dense_total = 0;
     int max_rank_used = 0, n_overflow = 0;
@@ -507,13 +488,13 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
     std::vector<int> all_b(p.n_b), all_i(p.n_i);
     for (int c = 0; c < p.n_b; ++c) all_b[c] = c;
     for (int c = 0; c < p.n_i; ++c) all_i[c] = c;
-    build_tree(tb, p.cols_b, all_b, o->b_min);
-    build_tree(ti, p.cols_i, all_i, o->b_min);
+    plan_tree(tb, p.cols_b, all_b, o->b_min);
+    plan_tree(ti, p.cols_i, all_i, o->b_min);
     std::vector<HPart> part;
-    partition(tb, ti, 0, 0, o->gamma, part);
+    plan_partition(tb, ti, 0, 0, o->gamma, part);
     std::vector<int32_t> tcols, scols;
-    std::vector<int> lr_ids;
-    int64_t u_mode = 0, v_mode = 0;
+    std::vector<int> lr_ids, d_ids;
+    int64_t u_mode = 0, v_mode = 0, d_mode = 0;
     for (const HPart& q : part) {
         HBlk b{};
         b.kind = q.kind;
@@ -537,6 +518,10 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
             v_mode += (int64_t)3 * b.ns * b.cap;
             b.lr = (int)lr_ids.size();
             lr_ids.push_back((int)h->blk.size());
+        } else {
+            b.d_off = d_mode;
+            d_mode += (int64_t)9 * b.nt * b.ns;
+            d_ids.push_back((int)h->blk.size());
         }
         h->blk.push_back(b);
     }
@@ -544,6 +529,7 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
     h->n_dense = (int)h->blk.size() - h->n_lr;
     h->u_mode = u_mode;
     h->v_mode = v_mode;
+    h->d_mode = d_mode;
     // pad leaves and the blocks covering them: a leaf's columns are a contiguous run of the
     // columns of every ancestor, in tree order
     std::vector<int> leaf_node;
@@ -571,7 +557,8 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
     }
     // device data
     fbc_status s;
-    const int64_t t_elems = (int64_t)p.nm * std::max(h->n_lr, 1) * o->max_rank * p.R;
+    // T workspace: the right-hand sides padded to whole groups of HR (zeros)
+    const int64_t t_elems = (int64_t)p.nm * std::max(h->n_lr, 1) * o->max_rank * (HR * ((p.R + HR - 1) / HR));
     if ((s = halloc(h, &h->blk_d, (int64_t)h->blk.size() * sizeof(HBlk))) != FBC_OK ||
         (s = halloc(h, &h->lr_ids, (int64_t)lr_ids.size() * 4)) != FBC_OK ||
         (s = halloc(h, &h->tcols, (int64_t)tcols.size() * 4)) != FBC_OK ||
@@ -583,6 +570,9 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
         (s = halloc(h, &h->U, (int64_t)p.nm * u_mode * 16)) != FBC_OK ||
         (s = halloc(h, &h->V, (int64_t)p.nm * v_mode * 16)) != FBC_OK ||
         (s = halloc(h, &h->T, t_elems * 16)) != FBC_OK ||
+        (s = halloc(h, &h->xbuf, (int64_t)p.nm * 3 * p.n_i * p.R * 16)) != FBC_OK ||
+        (s = halloc(h, &h->D, (int64_t)p.nm * d_mode * 16)) != FBC_OK ||
+        (s = halloc(h, &h->d_ids_d, (int64_t)d_ids.size() * 4)) != FBC_OK ||
         (s = halloc(h, &h->rank, (int64_t)p.nm * std::max(h->n_lr, 1) * 4)) != FBC_OK) {
         hmat_free(h);
         return s;
@@ -593,6 +583,7 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
     };
     up(h->blk_d, h->blk.data(), h->blk.size() * sizeof(HBlk));
     up(h->lr_ids, lr_ids.data(), lr_ids.size() * 4);
+    up(h->d_ids_d, d_ids.data(), d_ids.size() * 4);
     up(h->tcols, tcols.data(), tcols.size() * 4);
     up(h->scols, scols.data(), scols.size() * 4);
     up(h->leaf_cols, leaf_cols.data(), leaf_cols.size() * 4);
@@ -604,7 +595,10 @@ extern "C" fbc_status fbc_hmat_create(const fbc_ctx* ctx, const fbc_hmat_opts* o
         hmat_free(h);
         return hfail(FBC_E_DEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
-    // Step 3 on the device
+    // the dense leaves' entries, then step 3 on the device
+    if (!d_ids.empty())
+        hipLaunchKernelGGL(k_hmat_dense, dim3((unsigned)d_ids.size(), p.nm), dim3(NTH), 0, sm, h->blk_d, h->d_ids_d,
+                           h->tcols, h->scols, h->st, h->D, d_mode);
     if (h->n_lr > 0) {
         int max_rows = 1;
         for (int li : lr_ids) max_rows = std::max(max_rows, 3 * h->blk[li].nt);
@@ -678,13 +672,28 @@ extern "C" fbc_status fbc_hmat_ranks(const fbc_hmat* h, int32_t* out) {
     return FBC_OK;
 }
 
-static void hmat_launch(fbc_hmat* h, const HIo& io, hipStream_t sm) {
+template <bool PIPE>
+static void hmat_launch_t(fbc_hmat* h, const HIo& io, hipStream_t sm) {
+    const int Rp = HR * ((h->R + HR - 1) / HR);
     if (h->n_lr > 0)
-        hipLaunchKernelGGL(k_hmat_vt, dim3(h->n_lr, h->nm), dim3(NTH), 0, sm, h->blk_d, h->lr_ids, h->scols, h->V,
-                           h->v_mode, h->rank, h->n_lr, h->max_rank, io, h->n_i, h->R, h->T);
-    hipLaunchKernelGGL(k_hmat_y, dim3(h->n_leaves, h->nm), dim3(NTH), 0, sm, h->blk_d, h->scols, h->leaf_cols,
-                       h->leaf_off, h->contrib, h->contrib_off, h->st, h->U, h->u_mode, h->T, h->rank, h->n_lr,
-                       h->max_rank, io, h->n_i, h->n_b, h->R);
+        hipLaunchKernelGGL(k_hmat_vt<PIPE>, dim3(h->n_lr, h->nm), dim3(NTH), 0, sm, h->blk_d, h->lr_ids, h->scols,
+                           h->V, h->v_mode, h->rank, h->n_lr, h->max_rank, io, h->n_i, h->R, Rp, h->T);
+    hipLaunchKernelGGL(k_hmat_y<PIPE>, dim3(h->n_leaves, (h->nm + 3) / 4), dim3(NTH), 0, sm, h->blk_d, h->scols,
+                       h->leaf_cols, h->leaf_off, h->contrib, h->contrib_off, h->st, h->U, h->u_mode, h->D,
+                       h->d_mode, h->T, h->rank, h->n_lr, h->max_rank, io, h->n_i, h->n_b, h->R, Rp, h->nm);
+}
+
+static void hmat_launch(fbc_hmat* h, const HIo& io, hipStream_t sm) {
+    if (io.x) {
+        hmat_launch_t<false>(h, io, sm);
+        return;
+    }
+    HIo pio = io;
+    pio.x = h->xbuf;
+    const int n = 3 * h->n_i * h->R;
+    hipLaunchKernelGGL(k_hmat_x, dim3((unsigned)std::min(1024, (n + NTH - 1) / NTH), h->nm), dim3(NTH), 0, sm, io,
+                       h->n_i, h->R, h->xbuf);
+    hmat_launch_t<true>(h, pio, sm);
 }
 
 extern "C" fbc_status fbc_hmat_apply(fbc_hmat* h, const double* fhat, double* what, void* stream) {
