@@ -37,7 +37,7 @@ MFMA_PER_ALG = {"split_bf16": 3.0, "split_fp16": 3.0}
 F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "split_fp16": 8, "dtable_fp64": 16, "surrogate": 16}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16 hi+lo (fp32 acc)",
          "split_fp16": "fp16 hi+lo, power-of-two scaled (fp32 acc)", "dtable_fp64": "f64",
-         "surrogate": "f64 (generated table; bf16-weight MLP, fp32 acc)"}
+         "surrogate": "f64 (generated table; bf16 MLP on MFMA, fp32 acc)"}
 FP64_FORMS = ("fp64", "dtable_fp64")
 DEFAULT_FORMS = {"long": ["dtable_fp64", "fp32", "split_fp16", "split_bf16", "surrogate"],
                  "large": ["fp64", "fp32", "split_bf16", "split_fp16"],

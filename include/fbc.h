@@ -368,12 +368,14 @@ void fbc_sur_destroy(fbc_sur* s);
 
 /* Copies the network's current FP32 weights into the object as BF16 (round to nearest
  * even) for inference; later training of `net` does not change them until called again.
- * Synchronises `stream`. */
+ * A surrogate context evaluates the learned band with them on MFMA (BF16 weights and
+ * activations, FP32 accumulation, biases and SiLU in FP32); fbc_sur_eval on the SIMT
+ * path (FP32 activations).  Synchronises `stream`. */
 fbc_status fbc_sur_set_mlp(fbc_sur* s, const fbc_mlp* net, void* stream);
 
-/* The same with the FP32 weights kept as they are (inference with FP32 weights and FP32
- * accumulation): the control that separates the BF16 rounding of the weights from the
- * network's own fit in an error budget.  Replaces the BF16 weights until fbc_sur_set_mlp
+/* The same with the FP32 weights kept as they are (inference with FP32 weights, FP32
+ * activations and FP32 accumulation, on the SIMT path): the control that separates the
+ * BF16 rounding of weights and activations from the network's own fit in an error budget.  Replaces the BF16 weights until fbc_sur_set_mlp
  * is called again.  Synchronises `stream`. */
 fbc_status fbc_sur_set_mlp_fp32(fbc_sur* s, const fbc_mlp* net, void* stream);
 

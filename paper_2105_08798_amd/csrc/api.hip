@@ -998,11 +998,17 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
         for (size_t ch = 0; ch + 1 < c->chunk_job0.size(); ++ch) {
             const int t0 = (int)ch * c->gen_modes;
             const int nt = std::min(c->gen_modes, T - t0);
-            int64_t max_need = 0;
-            for (int t = t0; t < t0 + nt; ++t) max_need = std::max<int64_t>(max_need, c->n_need_h[t]);
+            int64_t max_need = 0, min_exact = INT64_MAX, max_exact = 0, min_learn = INT64_MAX, max_band = 0;
+            for (int t = t0; t < t0 + nt; ++t) {
+                max_need = std::max<int64_t>(max_need, c->n_need_h[t]);
+                min_exact = std::min<int64_t>(min_exact, c->n_exact_h[t]);
+                max_exact = std::max<int64_t>(max_exact, c->n_exact_h[t]);
+                min_learn = std::min<int64_t>(min_learn, c->n_learn_h[t]);
+                max_band = std::max<int64_t>(max_band, (int64_t)c->n_learn_h[t] - c->n_exact_h[t]);
+            }
             launch_sur_generate(st, sv->view(), sv->infer(), sv->r_c, c->env_mode, sv->rho_learn, c->nz_max, t0, nt,
                                 c->exact_tab, c->ex_off, c->n_exact, c->n_learn, c->n_offsets, c->n_need,
-                                c->off_d1, c->off_d2, c->gen, max_need);
+                                c->off_d1, c->off_d2, c->gen, min_exact, max_exact, min_learn, max_band, max_need);
             const int j0 = c->chunk_job0[ch], j1 = c->chunk_job0[ch + 1];
             PqLists ql{};
             ql.ctr = c->status + 16;

@@ -115,6 +115,7 @@ struct fbc_sur {
     double2* H = nullptr;            // continuum table
     double* g0 = nullptr;
     unsigned short* wb = nullptr;    // transposed bf16 weights
+    unsigned short* wm = nullptr;    // bf16 weights in MFMA fragment order (learned band)
     float* wf = nullptr;             // transposed FP32 weights (inference control)
     float* bias = nullptr;
     int has_mlp = 0;
@@ -124,7 +125,7 @@ struct fbc_sur {
     double rho_learn = INFINITY;     // largest distance of the training data (set by fbc_sur_training_set)
     std::vector<void*> allocs;
     std::string err;
-    MlpInfer infer() const { return MlpInfer{wb, mlp_fp32 ? wf : nullptr, bias}; }
+    MlpInfer infer() const { return MlpInfer{wb, mlp_fp32 ? wf : nullptr, bias, wm}; }
     CgfView view() const {
         CgfView v;
         v.H = H;

@@ -51,6 +51,7 @@ struct MlpInfer {
     const unsigned short* wb;
     const float* wf;
     const float* bias;
+    const unsigned short* wm;      // BF16 fragments of the MFMA inference (k_sur_learned)
 };
 
 void launch_sur_samples(hipStream_t st, const CgfView& v, const double2* tab, int64_t n_off, int nz_tab,
@@ -70,6 +71,8 @@ void launch_sur_generate(hipStream_t st, const CgfView& v, const MlpInfer& w, do
                          double rho_learn, int nz_tab, int t0, int nt, const double2* exact_tab, const int64_t* ex_off,
                          const int32_t* n_exact, const int32_t* n_learn, int64_t n_off,
                          const int32_t* n_need, const int32_t* d1, const int32_t* d2, double2* out,
-                         int64_t max_need);
+                         int64_t min_exact, int64_t max_exact, int64_t min_learn, int64_t max_band, int64_t max_need);
 void launch_mlp_to_bf16(hipStream_t st, const float* params, unsigned short* wb, float* bias);
 void launch_mlp_to_f32t(hipStream_t st, const float* params, float* wf, float* bias);
+#define MLP_MFMA_ELEMS ((8 + 32 + 32 + 4) * 512)
+void launch_mlp_to_mfma(hipStream_t st, const float* params, unsigned short* wm);

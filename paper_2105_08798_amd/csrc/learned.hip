@@ -628,9 +628,23 @@ void launch_sur_points(hipStream_t st, const CgfView& v, const MlpInfer& w, int 
                            r_c, theta0, d1, d2, n, out);
 }
 
+// The exact prefix of each table mode t0 .. t0+nt-1 into the generated slice: one
+// contiguous run per mode (ragged table: mode t at ex_off[t], n_exact[t] offsets).
+__global__ void __launch_bounds__(256) k_sur_copy_exact(const double2* __restrict__ exact_tab,
+                                                        const int64_t* __restrict__ ex_off,
+                                                        const int32_t* __restrict__ n_exact, int t0, int64_t n_off,
+                                                        double2* __restrict__ out) {
+    const int tl = blockIdx.y, tm = t0 + tl;
+    const int64_t n = (int64_t)n_exact[tm] * 6;
+    const double2* src = exact_tab + ex_off[tm] * 6;
+    double2* dst = out + (int64_t)tl * n_off * 6;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 // Table slice generator of the surrogate form: table modes t0 .. t0+nt-1 for every
 // offset o (offsets numbered by increasing rho; every band below is a prefix).
-// o < n_exact[t]: the exact lattice value from the ragged table (mode t at ex_off[t]);
+// o < n_exact[t]: the exact lattice value (copied from the ragged table by
+// k_sur_copy_exact; this kernel starts at o0, the smallest n_exact of the chunk);
 // o < n_learn[t]: continuum + learned correction (only out to rho_learn, the largest distance
 // of the training data: no extrapolation); o < n_need[t]: continuum alone; beyond:
 // zero, not written (the product treats offsets at or beyond n_need[t] as zero).
@@ -639,27 +653,22 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const WT*
                                                             const float* __restrict__ bias, double r_c,
                                                             const double* __restrict__ env_mode, double rho_learn,
                                                             int nz_tab, int t0,
-                                                            const double2* __restrict__ exact_tab,
-                                                            const int64_t* __restrict__ ex_off,
                                                             const int32_t* __restrict__ n_exact,
                                                             const int32_t* __restrict__ n_learn,
-                                                            int64_t n_off,
+                                                            int64_t o0, int64_t n_off,
                                                             const int32_t* __restrict__ n_need,
                                                             const int32_t* __restrict__ d1,
                                                             const int32_t* __restrict__ d2,
-                                                            double2* __restrict__ out) {
+                                                            double2* __restrict__ out, int band_done) {
     __shared__ float hl[MLP_H * MLP_BLOCK];
     const MlpW<WT> m = mlp_view(wt, bias);
     const int tl = blockIdx.y;
     const int tm = t0 + tl;
-    const int64_t o = (int64_t)blockIdx.x * MLP_BLOCK + threadIdx.x;
+    const int64_t o = o0 + (int64_t)blockIdx.x * MLP_BLOCK + threadIdx.x;
     if (o >= n_off) return;
     double2* dst = out + ((int64_t)tl * n_off + o) * 6;
-    if (o < n_exact[tm]) {
-        const double2* src = exact_tab + (ex_off[tm] + o) * 6;
-        for (int c = 0; c < 6; ++c) dst[c] = src[c];
-        return;
-    }
+    if (o < n_exact[tm]) return;      // copied by k_sur_copy_exact
+    if (band_done && o < n_learn[tm]) return;     // made by k_sur_learned
     if (o >= n_need[tm]) return;      // zero by definition; the product does not read it
     const double theta0 = (double)tm / nz_tab;
     double2 g[6];
@@ -681,19 +690,195 @@ __global__ void __launch_bounds__(MLP_BLOCK) k_sur_generate(CgfView v, const WT*
     for (int c = 0; c < 6; ++c) dst[c] = g[c];
 }
 
+// ----------------------------------------------------------------------------------
+// Learned band on MFMA: the network's layers are dense products over a batch of samples,
+// run as v_mfma_f32_16x16x32_bf16 (weights and activations in BF16, FP32 accumulation,
+// biases and SiLU in FP32).  Weights in fragment order (k_mlp_to_mfma): layer l's
+// fragment (row block rb, K block kb) is 64 lanes x 8 BF16, lane L holding
+// W[16 rb + L % 16][32 kb + 8 (L / 16) + j]; layers 8 -> 128 (K padded to 32), 128 ->
+// 128 twice, 128 -> 12 (rows padded to 16).  One wave takes 64 samples (one per lane for
+// the continuum, the features and the final combination) and runs the network on them
+// in four groups of 16 (the MFMA columns); between layers the activations go through a
+// per-wave LDS buffer [sample][row] (row stride 136: the lanes' 8- and 16-byte accesses
+// fall on distinct banks), which turns the accumulator layout (rows 16 rb + 4 (L / 16) +
+// j) into the operand layout (rows 32 kb + 8 (L / 16) + j).
+// ----------------------------------------------------------------------------------
+#define LRN_WAVES 4
+#define LRN_ACT 136
+#define LRN_FRAGS (8 + 32 + 32 + 4)
+
+__device__ inline unsigned short to_bf16(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);       // round to nearest even (finite values)
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline bf8_t frag_at(const unsigned short* p) { return *(const bf8_t*)p; }
+
+// bias + SiLU of one layer's accumulators, into the activation buffer act[sample][row]
+__device__ inline void put_act(unsigned short* act, const f4_t (&acc)[8], const float* __restrict__ b, int lane) {
+    const int n = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+        unsigned short h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h[j] = to_bf16(silu(acc[rb][j] + b[16 * rb + 4 * q + j]));
+        uint2 pk;
+        pk.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
+        pk.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
+        *(uint2*)(act + n * LRN_ACT + 16 * rb + 4 * q) = pk;
+    }
+}
+
+// Offsets n_exact[t] .. n_learn[t] - 1 of table modes t0 .. t0 + nt - 1: continuum + the
+// network's correction (within rho_learn; the continuum alone beyond), as k_sur_generate.
+__global__ void __launch_bounds__(64 * LRN_WAVES) k_sur_learned(CgfView v, const unsigned short* __restrict__ wm,
+                                                               const float* __restrict__ bias, double r_c,
+                                                               const double* __restrict__ env_mode,
+                                                               double rho_learn, int nz_tab, int t0,
+                                                               const int32_t* __restrict__ n_exact,
+                                                               const int32_t* __restrict__ n_learn, int64_t n_off,
+                                                               const int32_t* __restrict__ d1,
+                                                               const int32_t* __restrict__ d2,
+                                                               double2* __restrict__ out) {
+    __shared__ __align__(16) unsigned short feat[LRN_WAVES][64][8];
+    __shared__ __align__(16) unsigned short act[LRN_WAVES][16 * LRN_ACT];
+    __shared__ float yo[LRN_WAVES][64][MLP_OUT];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tl = blockIdx.y, tm = t0 + tl;
+    const int64_t o = (int64_t)n_exact[tm] + ((int64_t)blockIdx.x * LRN_WAVES + wave) * 64 + lane;
+    const bool live = o < n_learn[tm];
+    const double theta0 = (double)tm / nz_tab;
+    double2 g[6];
+    float f[MLP_IN];
+    double rho = 0.0;
+    bool use = false;
+    if (live) {
+        cgf_eval(v, theta0, d1[o], d2[o], g);
+        sur_features(theta0, d1[o], d2[o], r_c, f, &rho);
+        use = rho <= rho_learn;
+    }
+#pragma unroll
+    for (int a = 0; a < MLP_IN; ++a) feat[wave][lane][a] = use ? to_bf16(f[a]) : (unsigned short)0;
+    const int any = __syncthreads_or(use ? 1 : 0);       // work-group uniform
+    if (any) {
+        const int n = lane & 15, q = lane >> 4;
+        unsigned short* aw = act[wave];
+        const f4_t zero = {0.f, 0.f, 0.f, 0.f};
+        for (int sb = 0; sb < 4; ++sb) {
+            f4_t acc[8];
+            // layer 1: the 8 features are K rows 0..7 (the first lane quarter), zeros beyond
+            bf8_t b1;
+            if (q == 0) b1 = *(const bf8_t*)&feat[wave][16 * sb + n][0];
+            else b1 = (bf8_t){};
+#pragma unroll
+            for (int rb = 0; rb < 8; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_at(wm + rb * 512 + lane * 8), b1, zero, 0, 0, 0);
+            put_act(aw, acc, bias, lane);
+            __syncthreads();
+            // layers 2 and 3
+            for (int l = 0; l < 2; ++l) {
+                bf8_t bk[4];
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) bk[kb] = *(const bf8_t*)(aw + n * LRN_ACT + 32 * kb + 8 * q);
+                __syncthreads();             // every lane has its operands before any overwrite
+                const unsigned short* wl = wm + (8 + 32 * l) * 512;
+#pragma unroll
+                for (int rb = 0; rb < 8; ++rb) {
+                    acc[rb] = zero;
+#pragma unroll
+                    for (int kb = 0; kb < 4; ++kb)
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_at(wl + (rb * 4 + kb) * 512 + lane * 8),
+                                                                          bk[kb], acc[rb], 0, 0, 0);
+                }
+                put_act(aw, acc, bias + MLP_H * (l + 1), lane);
+                __syncthreads();
+            }
+            // layer 4: 12 outputs (rows 12..15 of the fragment are zero)
+            bf8_t bk[4];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) bk[kb] = *(const bf8_t*)(aw + n * LRN_ACT + 32 * kb + 8 * q);
+            f4_t a4 = zero;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+                a4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_at(wm + (72 + kb) * 512 + lane * 8), bk[kb], a4, 0, 0,
+                                                             0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = 4 * q + j;
+                if (row < MLP_OUT) yo[wave][16 * sb + n][row] = a4[j] + bias[3 * MLP_H + row];
+            }
+            __syncthreads();                 // layer 4 has read act; yo complete after the last group
+        }
+    }
+    if (!live) return;
+    if (use) {
+        const double env = env_mode[tm];
+        double sp, cp;
+        sincospi(theta0 * d1[o], &sp, &cp);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const double cr = env * yo[wave][lane][2 * c], ci = env * yo[wave][lane][2 * c + 1];
+            g[c].x += cr * cp - ci * sp;
+            g[c].y += cr * sp + ci * cp;
+        }
+    }
+    double2* dst = out + ((int64_t)tl * n_off + o) * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dst[c] = g[c];
+}
+
+// FP32 weights -> BF16 fragments of k_sur_learned (round to nearest even; zeros in the
+// padding).
+__global__ void k_mlp_to_mfma(const float* __restrict__ params, unsigned short* __restrict__ wm) {
+    for (int e = threadIdx.x; e < LRN_FRAGS * 512; e += blockDim.x) {
+        const int fr = e / 512, rem = e - fr * 512, lane = rem / 8, j = rem - lane * 8;
+        int l, rb, kb;
+        if (fr < 8) { l = 0; rb = fr; kb = 0; }
+        else if (fr < 40) { l = 1; rb = (fr - 8) / 4; kb = (fr - 8) % 4; }
+        else if (fr < 72) { l = 2; rb = (fr - 40) / 4; kb = (fr - 40) % 4; }
+        else { l = 3; rb = 0; kb = fr - 72; }
+        const int ni = (l == 0) ? MLP_IN : MLP_H, no = (l == 3) ? MLP_OUT : MLP_H;
+        int64_t off = 0;
+        if (l > 0) off += (int64_t)MLP_H * MLP_IN + MLP_H;
+        if (l > 1) off += (int64_t)MLP_H * MLP_H + MLP_H;
+        if (l > 2) off += (int64_t)MLP_H * MLP_H + MLP_H;
+        const int row = 16 * rb + (lane & 15), col = 32 * kb + 8 * (lane >> 4) + j;
+        wm[e] = (row < no && col < ni) ? to_bf16(params[off + (int64_t)row * ni + col]) : (unsigned short)0;
+    }
+}
+
+void launch_mlp_to_mfma(hipStream_t st, const float* params, unsigned short* wm) {
+    hipLaunchKernelGGL(k_mlp_to_mfma, dim3(1), dim3(256), 0, st, params, wm);
+}
+
 void launch_sur_generate(hipStream_t st, const CgfView& v, const MlpInfer& w, double r_c, const double* env_mode,
                          double rho_learn, int nz_tab, int t0, int nt, const double2* exact_tab, const int64_t* ex_off,
                          const int32_t* n_exact, const int32_t* n_learn, int64_t n_off,
                          const int32_t* n_need, const int32_t* d1, const int32_t* d2, double2* out,
-                         int64_t max_need) {
-    if (max_need <= 0 || nt <= 0) return;
-    dim3 grid((unsigned)((max_need + MLP_BLOCK - 1) / MLP_BLOCK), nt);
-    if (w.wf)
+                         int64_t min_exact, int64_t max_exact, int64_t min_learn, int64_t max_band, int64_t max_need) {
+    if (nt <= 0) return;
+    if (max_exact > 0) {
+        const int64_t per = (max_exact * 6 + 255) / 256;
+        hipLaunchKernelGGL(k_sur_copy_exact, dim3((unsigned)std::min<int64_t>(per, 1024), nt), dim3(256), 0, st,
+                           exact_tab, ex_off, n_exact, t0, n_off, out);
+    }
+    if (w.wf) {          // FP32 control: the whole non-exact prefix on the SIMT network
+        if (max_need <= min_exact) return;
+        dim3 grid((unsigned)((max_need - min_exact + MLP_BLOCK - 1) / MLP_BLOCK), nt);
         hipLaunchKernelGGL(k_sur_generate<float>, grid, dim3(MLP_BLOCK), 0, st, v, w.wf, w.bias, r_c, env_mode, rho_learn,
-                           nz_tab, t0, exact_tab, ex_off, n_exact, n_learn, n_off, n_need, d1, d2, out);
-    else
-        hipLaunchKernelGGL(k_sur_generate<unsigned short>, grid, dim3(MLP_BLOCK), 0, st, v, w.wb, w.bias, r_c,
-                           env_mode, rho_learn, nz_tab, t0, exact_tab, ex_off, n_exact, n_learn, n_off, n_need, d1, d2, out);
+                           nz_tab, t0, n_exact, n_learn, min_exact, n_off, n_need, d1, d2, out, 0);
+        return;
+    }
+    if (max_band > 0) {   // learned band on MFMA
+        const int64_t per = (max_band + 64 * LRN_WAVES - 1) / (64 * LRN_WAVES);
+        hipLaunchKernelGGL(k_sur_learned, dim3((unsigned)per, nt), dim3(64 * LRN_WAVES), 0, st, v, w.wm, w.bias, r_c,
+                           env_mode, rho_learn, nz_tab, t0, n_exact, n_learn, n_off, d1, d2, out);
+    }
+    if (max_need <= min_learn) return;     // continuum alone beyond the learned band
+    dim3 grid((unsigned)((max_need - min_learn + MLP_BLOCK - 1) / MLP_BLOCK), nt);
+    hipLaunchKernelGGL(k_sur_generate<unsigned short>, grid, dim3(MLP_BLOCK), 0, st, v, w.wb, w.bias, r_c,
+                       env_mode, rho_learn, nz_tab, t0, n_exact, n_learn, min_learn, n_off, n_need, d1, d2, out, 1);
 }
 
 // FP32 weights -> transposed bf16 (round to nearest even) and biases, for inference.

@@ -113,6 +113,7 @@ extern "C" fbc_status fbc_sur_create(const fbc_lattice* lat, double r_c, void* s
         (rc = lalloc(s->allocs, &s->err, &s->g0, 6 * 8)) ||
         (rc = lalloc(s->allocs, &s->err, &s->H, (int64_t)k.nphi * (k.ns + 1) * 6 * 16)) ||
         (rc = lalloc(s->allocs, &s->err, &s->wb, (int64_t)MLP_NW * 2)) ||
+        (rc = lalloc(s->allocs, &s->err, &s->wm, (int64_t)MLP_MFMA_ELEMS * 2)) ||
         (rc = lalloc(s->allocs, &s->err, &s->wf, (int64_t)MLP_NW * 4)) ||
         (rc = lalloc(s->allocs, &s->err, &s->bias, (int64_t)MLP_NB * 4))) {
         cleanup();
@@ -148,6 +149,7 @@ extern "C" void fbc_sur_destroy(fbc_sur* s) {
 extern "C" fbc_status fbc_sur_set_mlp(fbc_sur* s, const fbc_mlp* net, void* stream) {
     if (!s || !net) return lfail(nullptr, FBC_E_ARG, "null argument");
     launch_mlp_to_bf16((hipStream_t)stream, net->params, s->wb, s->bias);
+    launch_mlp_to_mfma((hipStream_t)stream, net->params, s->wm);
     LCHK(&s->err, hipGetLastError());
     LCHK(&s->err, hipStreamSynchronize((hipStream_t)stream));
     s->has_mlp = 1;

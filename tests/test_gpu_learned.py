@@ -365,3 +365,36 @@ def test_gain_learned_correction_beats_the_continuum_alone():
     del dev, rng
     assert pointwise < 0.5
     assert e_mlp < 0.5 * e_cgf, (e_mlp, e_cgf)
+
+
+def test_mfma_inference_matches_the_fp32_control():
+    """The learned band's network runs on MFMA (BF16 weights and activations, FP32
+    accumulation); the FP32-weight control runs the same network on the SIMT kernel whose
+    forward pass equals the oracle's (above).  Their pad updates must agree to the BF16
+    rounding of the correction: within 2 % of the correction's own contribution (a layout
+    mistake in the fragments would be of order one)."""
+    from paper_2105_08798_amd import MLP, Surrogate
+    _dev()
+    rng = np.random.default_rng(12)
+    net = MLP(max_batch=16, seed=5)
+    p = (omlp.init_params(rng) + 0.05 * rng.normal(size=omlp.n_params())).astype(np.float32)
+    net.params(p)
+    zero = MLP(max_batch=16, seed=0)
+    zero.params(np.zeros(zero.n_params, dtype=np.float32))
+    cells = W.make_custom(32, 256, 512, 2, 256, seed=23).cells
+    u0 = [np.zeros((c.n_rhs, c.nz, c.n_b, 3)) for c in cells]
+    out = {}
+    for name, w, fp32 in (("cont", zero, False), ("mfma", net, False), ("fp32", net, True)):
+        sur = Surrogate(r_c=R_C)
+        sur.set_exact_range(4.0)          # a wide learned band
+        sur.set_learn_range(16.0)
+        sur.set_mlp(w, fp32=fp32)
+        out[name] = _apply(cells, 256, "surrogate", -1.0, u0, surrogate=sur)
+        sur.close()
+    net.close()
+    zero.close()
+    corr = np.linalg.norm(out["fp32"] - out["cont"])
+    diff = np.linalg.norm(out["mfma"] - out["fp32"])
+    print(f"mfma vs fp32 control: {diff:.3e} of a correction of {corr:.3e}")
+    assert corr > 1e-6 * np.linalg.norm(out["cont"])
+    assert diff < 0.02 * corr, (diff, corr)
