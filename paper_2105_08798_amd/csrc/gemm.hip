@@ -451,13 +451,22 @@ __global__ void __launch_bounds__(256) k_gemm_split_pq(const GemmJob* __restrict
 // otherwise also wait for every A load issued before it, and cut the effective depth of
 // the A ring down to the distance at which B was fetched.  K windows and slices hold an
 // even number of steps, so S = 2 needs no tail.
-template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW>
+// CH = 2 splits the column tiles between two halves of the waves (eight waves: four row
+// groups x two column halves, the same 128-row tile): each wave holds the accumulators of
+// half the tiles, so two waves fit per SIMD; the two waves of a row group read the same A
+// (ordinary loads, so the second finds it in L2).  Every output tile sees the same
+// sequence of MFMAs, so the result is bitwise that of CH = 1.
+template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW, int CH = 1>
 __device__ inline void gemm_split_lds_job(const GemmJob& jb,
                                                         const unsigned short* __restrict__ A,
                                                         const unsigned short* __restrict__ B,
                                                         double* __restrict__ C) {
     static_assert(CT >= 2 && (CT % 2) == 0, "B staging assumes an even tile count");
+    static_assert(CH == 1 || CH == 2, "one or two column halves");
+    static_assert(NW % CH == 0 && ((CT / CH) % 2) == 0, "column halves of an even tile count");
     static_assert(S == 1 || S == 2, "one or two K steps per barrier");
+    constexpr int RG = NW / CH;              // row groups of the tile
+    constexpr int CTW = CT / CH;             // column tiles per wave
     static_assert(PFA >= 2 * S && (PFA % (2 * S)) == 0, "ring depth must be a multiple of 2 S");
     constexpr int NTH = 64 * NW;             // threads of the work group
     constexpr int STEP_UNITS = CT * 128;     // 16-byte units of B per step (hi and lo runs)
@@ -466,18 +475,23 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
     __shared__ VT bs[2][STEP_UNITS * S];
     if (jb.rb0 >= jb.mb) return;             // whole work group (empty job)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int rbw = jb.rb0 + wave * RB;
+    const int rg = wave % RG, c0w = (wave / RG) * CTW;
+    const int rbw = jb.rb0 + rg * RB;
     const int kt = jb.kp >> 5;
     const int tb = jb.k0 >> 5, te = jb.k1 >> 5;    // te - tb is even (K slices of 64 k')
-    constexpr int TRB = NW * RB;         // row blocks of the tile: the A step stride
-    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)(wave * RB) * 128 + lane;
+    constexpr int TRB = RG * RB;         // row blocks of the tile: the A step stride
+    const VT* a = (const VT*)(A + jb.a_off) + (int64_t)(rg * RB) * 128 + lane;
     const VT* b = (const VT*)(B + jb.b_off);
-    d4_t acc[RB][CT];
-    f4_t ac32[RB][CT];
+    auto lda = [](const VT* p) -> VT {
+        if constexpr (CH == 1) return ld_stream(p);
+        else return *p;
+    };
+    d4_t acc[RB][CTW];
+    f4_t ac32[RB][CTW];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
+        for (int c = 0; c < CTW; ++c) {
             acc[r][c] = (d4_t){0, 0, 0, 0};
             ac32[r][c] = (f4_t){0, 0, 0, 0};
         }
@@ -485,7 +499,7 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+            for (int c = 0; c < CTW; ++c) store_c_f32acc(C, jb, rbw + r, c0w + c, lane, acc[r][c]);
         return;
     }
     // this thread's share of B for step t: LDS in lane order, global in column-run order
@@ -508,8 +522,8 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
         const int tl = min(tb + u, te - 1);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            ah[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128));
-            al[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128 + 64));
+            ah[u][r] = lda(a + (((int64_t)(tl - tb) * TRB + r) * 128));
+            al[u][r] = lda(a + (((int64_t)(tl - tb) * TRB + r) * 128 + 64));
         }
         load_b(br[u], tl);
     }
@@ -527,9 +541,9 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
             // two column tiles at a time, the three products of a tile interleaved with
             // the other tile's, so dependent MFMAs are 2 RB instructions apart
 #pragma unroll
-            for (int c = 0; c < CT; c += 2) {
-                const VT bh0 = bb[c * 128 + lane], bl0 = bb[c * 128 + 64 + lane];
-                const VT bh1 = bb[(c + 1) * 128 + lane], bl1 = bb[(c + 1) * 128 + 64 + lane];
+            for (int c = 0; c < CTW; c += 2) {
+                const VT bh0 = bb[(c0w + c) * 128 + lane], bl0 = bb[(c0w + c) * 128 + 64 + lane];
+                const VT bh1 = bb[(c0w + c + 1) * 128 + lane], bl1 = bb[(c0w + c + 1) * 128 + 64 + lane];
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     ac32[r][c] = mfma_16x16x32(al[u][r], bh0, ac32[r][c]);
@@ -550,15 +564,15 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
             const int tl = min(t + PFA, te - 1);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                ah[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128));
-                al[u][r] = ld_stream(a + (((int64_t)(tl - tb) * TRB + r) * 128 + 64));
+                ah[u][r] = lda(a + (((int64_t)(tl - tb) * TRB + r) * 128));
+                al[u][r] = lda(a + (((int64_t)(tl - tb) * TRB + r) * 128 + 64));
             }
             load_b(br[u], tl);
             if (((t - tb + 1) % KCH) == 0 || t + 1 == te) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) {
+                    for (int c = 0; c < CTW; ++c) {
 #pragma unroll
                         for (int j = 0; j < 4; ++j) acc[r][c][j] += (double)ac32[r][c][j];
                         ac32[r][c] = (f4_t){0, 0, 0, 0};
@@ -576,23 +590,23 @@ __device__ inline void gemm_split_lds_job(const GemmJob& jb,
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) store_c_f32acc(C, jb, rbw + r, c, lane, acc[r][c]);
+        for (int c = 0; c < CTW; ++c) store_c_f32acc(C, jb, rbw + r, c0w + c, lane, acc[r][c]);
 }
 
-template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW>
+template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW, int CH = 1>
 __global__ void __launch_bounds__(64 * NW) k_gemm_split_lds(const GemmJob* __restrict__ jobs, const unsigned short* __restrict__ A,
         const unsigned short* __restrict__ B, double* __restrict__ C) {
     const GemmJob jb = jobs[blockIdx.x];
-    gemm_split_lds_job<VT, RB, CT, PFA, KCH, S, NW>(jb, A, B, C);
+    gemm_split_lds_job<VT, RB, CT, PFA, KCH, S, NW, CH>(jb, A, B, C);
 }
-template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW>
+template <typename VT, int RB, int CT, int PFA, int KCH, int S, int NW, int CH = 1>
 __global__ void __launch_bounds__(64 * NW) k_gemm_split_lds_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
         const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, double* __restrict__ C) {
     __shared__ int slot;
     int cur = 0;
     for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
-        gemm_split_lds_job<VT, RB, CT, PFA, KCH, S, NW>(jb, A, B, C);
+        gemm_split_lds_job<VT, RB, CT, PFA, KCH, S, NW, CH>(jb, A, B, C);
     }
     pq_done(q);
 }
@@ -628,11 +642,12 @@ static void launch_dense(void (*kn)(const GemmJob*, const TA*, const TA*, double
 // from.  They share the tile height (the compact store is laid out in tiles) and the
 // arithmetic order, so every variant gives bitwise the same result: variant 0 is the
 // default; variant 1 changes the depth of the prefetch ring (FP64, FP32) or the K steps
-// per barrier (split products staging B in LDS).  The split products with one or two
+// per barrier (split products staging B in LDS); variant 2 of those splits the column
+// tiles between two halves of eight waves (two waves per SIMD).  The split products with one or two
 // column tiles have one variant: their main loop runs whole ring passes, and a 64-k'
 // chunk is two of their steps, so the ring cannot be deeper than two steps.
 int gemm_variants(int form, int ctmax) {
-    if ((form == FBC_FORM_SPLIT_FP16 || form == FBC_FORM_SPLIT_BF16) && ctmax <= 2) return 1;
+    if (form == FBC_FORM_SPLIT_FP16 || form == FBC_FORM_SPLIT_BF16) return ctmax <= 2 ? 1 : 3;
     return 2;
 }
 
@@ -654,8 +669,12 @@ std::string gemm_shape(int form, int ctmax, int variant) {
                  ct, f16 ? 2 : 8);
     } else {
         const bool f16 = form == FBC_FORM_SPLIT_FP16;
-        snprintf(buf, sizeof buf, "split_lds %s RB=2 CT=%d PFA=4 KCH=%d S=%d waves=4", f16 ? "f16" : "bf16", ct,
-                 f16 ? 4 : 8, alt ? 1 : 2);
+        if (variant == 2)
+            snprintf(buf, sizeof buf, "split_lds %s RB=2 CT=%d PFA=4 KCH=%d S=2 waves=8 (column halves)",
+                     f16 ? "f16" : "bf16", ct, f16 ? 4 : 8);
+        else
+            snprintf(buf, sizeof buf, "split_lds %s RB=2 CT=%d PFA=4 KCH=%d S=%d waves=4", f16 ? "f16" : "bf16", ct,
+                     f16 ? 4 : 8, alt ? 1 : 2);
     }
     return buf;
 }
@@ -666,6 +685,9 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 #define GEMM_CASE(KERN, RB, CT, ...)                                                           \
     launch_dense<TA>(KERN<RB, CT, __VA_ARGS__>, KERN##_pq<RB, CT, __VA_ARGS__>, st, jobs, njobs, a, b, c, q)
 #define GEMM_PICK(DEF, ALT) do { if (variant == 1) ALT; else DEF; } while (0)
+#define GEMM_CASE8(KERN, ...)                                                                  \
+    launch_dense<TA>(KERN<__VA_ARGS__, 8, 2>, KERN##_pq<__VA_ARGS__, 8, 2>, st, jobs, njobs, a, b, c, q, 512)
+#define GEMM_PICK3(DEF, ALT, CS) do { if (variant == 2) CS; else if (variant == 1) ALT; else DEF; } while (0)
     if (form == FBC_FORM_FP64) {
         typedef double TA;
         if (ctmax <= 1) GEMM_PICK(GEMM_CASE(k_gemm_f64, 4, 1, 4), GEMM_CASE(k_gemm_f64, 4, 1, 2));
@@ -685,18 +707,24 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, h8_t, 2, 1, 2, 2);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, h8_t, 4, 2, 2, 2);
         else if (ctmax <= 4)
-            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2, 4), GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 1, 4));
+            GEMM_PICK3(GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2, 4), GEMM_CASE(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 1, 4),
+                       GEMM_CASE8(k_gemm_split_lds, h8_t, 2, 4, 4, 4, 2));
         else
-            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2, 4), GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 1, 4));
+            GEMM_PICK3(GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2, 4), GEMM_CASE(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 1, 4),
+                       GEMM_CASE8(k_gemm_split_lds, h8_t, 2, 8, 4, 4, 2));
     } else {
         typedef unsigned short TA;
         if (ctmax <= 1) GEMM_CASE(k_gemm_split, bf8_t, 2, 1, 2, 8);
         else if (ctmax <= 2) GEMM_CASE(k_gemm_split, bf8_t, 4, 2, 2, 8);
         else if (ctmax <= 4)
-            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2, 4), GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 1, 4));
+            GEMM_PICK3(GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2, 4), GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 1, 4),
+                       GEMM_CASE8(k_gemm_split_lds, bf8_t, 2, 4, 4, 8, 2));
         else
-            GEMM_PICK(GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2, 4), GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 1, 4));
+            GEMM_PICK3(GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2, 4), GEMM_CASE(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 1, 4),
+                       GEMM_CASE8(k_gemm_split_lds, bf8_t, 2, 8, 4, 8, 2));
     }
+#undef GEMM_PICK3
+#undef GEMM_CASE8
 #undef GEMM_PICK
 #undef GEMM_CASE
 }
