@@ -75,10 +75,11 @@ def kernel_matches(form: str, name: str) -> bool:
     return name.startswith("k_gemm_dtab<")
 
 
-def measured_traffic(workload: str, form: str, product_bytes: float):
+def measured_traffic(workload: str, form: str, product_bytes: float, tuned: dict | None):
     """HBM bytes per product launch from the committed counter runs, or None when they
-    were taken on another workload, before the product kernels last changed, or on a
-    product of other algorithmic bytes (another set of kept blocks)."""
+    were taken on another workload, before the product kernels last changed, on a product
+    of other algorithmic bytes (another set of kept blocks) or with another kernel variant
+    or work list than the autotuner chose in this run."""
     import hashlib
     p = os.path.join(ROOT, "profiles", f"gemm_traffic_{workload}.json")
     if not os.path.exists(p):
@@ -90,6 +91,9 @@ def measured_traffic(workload: str, form: str, product_bytes: float):
     for name, v in t["kernels"].items():
         if kernel_matches(form, name) and v.get("form", form) == form:
             if v.get("algorithmic_bytes") != product_bytes:
+                return None
+            run = v.get("launch")
+            if tuned is None or run is None or any(run.get(k) != tuned.get(k) for k in ("variant", "nsplit", "order")):
                 return None
             return v["traffic_bytes"]
     return None
@@ -170,7 +174,8 @@ def unbalanced_forces(c, seed: int = 5) -> np.ndarray:
 
 
 def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: bool, keep_cols,
-              train_steps: int = 20000, extras: bool = False) -> tuple[dict, np.ndarray | None]:
+              train_steps: int = 20000, extras: bool = False,
+              tune_cache: str | None = None) -> tuple[dict, np.ndarray | None]:
     """Times `steps` fbc_apply calls after `warmup`; returns the timings and the raw response
     w = G f at the pad columns keep_cols (every layer; one-cell workloads) or in full."""
     from paper_2105_08798_amd import FBC, RELAX_OUT_DOUBLES
@@ -191,7 +196,7 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     tuned = None
     if tune:
         w = torch.zeros_like(u)
-        tuned = ctx.autotune(f, w, reps=3)
+        tuned = ctx.autotune(f, w, reps=3, cache=tune_cache)
         del w
         log(f"{form}: autotuned work list {tuned}")
     ctx.timing(True)
@@ -399,7 +404,7 @@ def run_workload(torch, args, name: str, forms: list, extras_for=None) -> dict:
     for form in forms:
         r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph,
                          not args.no_autotune and form != "surrogate", keep, args.train_steps,
-                         extras=(form == extras_for))
+                         extras=(form == extras_for), tune_cache=args.tune_cache)
         r["w"] = w
         res[form] = r
     ref_form = next((f for f in FP64_FORMS if f in res), None)
@@ -706,6 +711,9 @@ def main() -> int:
     ap.add_argument("--graph", action="store_true", help="replay the update from a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default work list (the library's autotuner picks K slices and order otherwise)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: a stored choice for the same configuration is applied "
+                         "untimed, a new one appended (keeps separate profiling runs on one work list)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000, help="Adam steps of the surrogate's MLP")
     ap.add_argument("--max-rank", type=int, default=64, help="rank bound of the H-matrix workload")
@@ -750,7 +758,7 @@ def main() -> int:
     h = out_forms[head]
     ref = main_run["ref_form"]
     roof = dict(h["roofline"])
-    roof["traffic"] = measured_traffic(name, head, h["product_bytes"])
+    roof["traffic"] = measured_traffic(name, head, h["product_bytes"], h.get("autotune"))
     roof["kernel"] = f"per-mode product ({head})"
     line = {
         "metric": METRIC, "value": h["updates_per_s"], "unit": "FBC updates/s", "n_gpus": 1,

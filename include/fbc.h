@@ -179,9 +179,10 @@ fbc_status fbc_apply_graph(fbc_ctx* ctx, const double* f, double* u, double alph
  * as fit on the chip), 4 persistent with one work list per XCD (the row tiles of a mode
  * one after another on one XCD, so their f^ operands are shared in its L2; a group whose
  * list is exhausted helps the others) -- with `reps` fbc_green_apply calls each on this context (input
- * f, device; w, device, same layout as u, is overwritten with G f), keeps the list with
- * the fastest whole call (the K slices also cost the inverse transform a read each) and
- * reports it in *out (may be NULL).  The surrogate form is refused (FBC_E_UNSUPPORTED):
+ * f, device; w, device, same layout as u, is overwritten with G f), times the candidates
+ * within 4 % of the fastest again in three interleaved rounds, keeps the one with the
+ * fastest whole call over those rounds (the K slices also cost the inverse transform a
+ * read each) and reports it in *out (may be NULL).  The surrogate form is refused (FBC_E_UNSUPPORTED):
  * it keeps its mode-major chunks.  Synchronises the stream. */
 typedef struct {
     int nsplit;
