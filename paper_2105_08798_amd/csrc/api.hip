@@ -865,7 +865,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             int tr, pp;
             irfft_shape(p.nz, &tr, &pp);
             const int np_ir = (p.M + tr - 1) / tr;
-            const int np_ax = ((p.M + 31) / 32) * ((p.nz + 31) / 32);
+            const int np_ax = axpy_parts(p.M, p.nz);
             c->wmax_off.push_back(wmax_n);
             c->sum_part_off.push_back(sp_n);
             c->rpart_off.push_back(rp_n);
@@ -1073,7 +1073,8 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
                               p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split, rm, sh,
                               so, am, be, nullptr);
             if (!mean_removal) launch_fill(st, uc, (int64_t)p.R * p.nz * p.M, 0.0);
-            launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr, mu);
+            // the mean is known beforehand: no partial sums
+            launch_axpy(st, c->wbuf + p.w_off, uc, nullptr, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr, mu);
             continue;
         }
         double* mu = nullptr;

@@ -589,13 +589,35 @@ __device__ inline void gather_inverse(double2* lds, const double* __restrict__ c
     lds_fft_s<true>(lds, tr * pp, ss, logn, tw);
 }
 
-// Inverse transform into the scratch w[r][row][n0] (scaled by 1/Nz), with per block and
-// RHS the maximum |w| (the step bound of Algorithm 2).  Used by the relaxation step,
+// Work unit of a work group of the inverse transforms: units (row group rg of column tile
+// `tile`, numbered tile-major) are split into 8 contiguous ranges, one per XCD (work
+// groups are dealt to the XCDs round robin by index), and the 4/pp pair groups of a unit
+// take consecutive places in its XCD's sequence.  So the pair groups of a unit, which read
+// disjoint parts of the same 128-byte product records, run on one XCD at about the same
+// time and share those records through its L2, and so do neighbouring row groups, which
+// (in the fused update) write neighbouring runs of each layer of u.  Measured on MI355X:
+// the inverse transform into w at Nz = 1024 3-4 % faster than with a row x tile x pair grid.
+__device__ inline bool xcd_unit(int n_units, int n_rg, int npg, int& tile, int& rg, int& pg) {
+    const int u8 = (n_units + 7) >> 3;
+    const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+    pg = k % npg;
+    const int ul = k / npg, unit = xcd * u8 + ul;
+    if (ul >= u8 || unit >= n_units) return false;
+    tile = unit / n_rg;
+    rg = unit - tile * n_rg;
+    return true;
+}
+
+static inline int xcd_groups(int n_units, int npg) { return 8 * npg * ((n_units + 7) / 8); }
+
+// Inverse transform into the scratch w[r][row][n0] (scaled by 1/Nz), with per row group
+// and RHS the maximum |w| (the step bound of Algorithm 2).  Used by the relaxation step,
 // whose step size depends on the whole of w before any update.
 __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    double* __restrict__ w,
                                                    double* __restrict__ wmax_part, int R, int nz,
-                                                   int logn, int mp, int M, int tr, int pp,
+                                                   int logn, int mp, int M, int tr, int pp, int n_rg,
+                                                   int n_units,
                                                    const double2* __restrict__ tw, int nsplit,
                                                    int64_t split_stride,
                                                    const double2* __restrict__ rowmean,
@@ -604,9 +626,10 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
                                                    const unsigned long long* __restrict__ amax,
                                                    const int* __restrict__ bexp) {
     extern __shared__ double2 lds[];
-    const int row0 = blockIdx.x * tr;
-    const int tile = blockIdx.y;
-    const int pair0 = blockIdx.z * pp;          // first RHS pair inside the 8-RHS tile
+    int tile, rg, pg;
+    if (!xcd_unit(n_units, n_rg, 4 / pp, tile, rg, pg)) return;
+    const int row0 = rg * tr;
+    const int pair0 = pg * pp;                  // first RHS pair inside the 8-RHS tile
     const int nseq = tr * pp;
     const int ss = nz + 1;
     gather_inverse(lds, c, tile, row0, pair0, tr, pp, ss, R, nz, logn, mp, M, tw, nsplit, split_stride,
@@ -637,9 +660,9 @@ __global__ void __launch_bounds__(NT) k_line_irfft(const double* __restrict__ c,
     if (threadIdx.x < 8) {
         const int rr = 8 * tile + threadIdx.x;
         const int jj = threadIdx.x;
-        // each RHS is covered by exactly one pair group (blockIdx.z)
+        // each RHS is covered by exactly one pair group
         if (rr < R && jj >= 2 * pair0 && jj < 2 * (pair0 + pp))
-            wmax_part[(int64_t)rr * gridDim.x + blockIdx.x] = mx[jj];
+            wmax_part[(int64_t)rr * n_rg + rg] = mx[jj];
     }
 }
 
@@ -666,12 +689,14 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
     while ((1 << logn) < nz) ++logn;
     int pp, tr;
     irfft_shape(nz, &tr, &pp);
-    dim3 grid((M + tr - 1) / tr, ct_grid, 4 / pp);
+    const int n_rg = (M + tr - 1) / tr;
+    const int n_units = ct_grid * n_rg;
     size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
     if (lds < 8 * NT * sizeof(double)) lds = 8 * NT * sizeof(double);   // reused by the max
-    hipLaunchKernelGGL(k_line_irfft, grid, dim3(NT), lds, st, c, w, wmax_part, R, nz, logn, mp, M,
-                       tr, pp, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, bexp);
-    if (n_part_out) *n_part_out = (int)grid.x;
+    hipLaunchKernelGGL(k_line_irfft, dim3(xcd_groups(n_units, 4 / pp)), dim3(NT), lds, st, c, w, wmax_part,
+                       R, nz, logn, mp, M, tr, pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat,
+                       shat_on, amax, bexp);
+    if (n_part_out) *n_part_out = n_rg;
 }
 
 // ----------------------------------------------------------------------------------
@@ -679,9 +704,9 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
 //   u[r][n0][row] <- (read_u ? u : 0) - alpha * w[r][row][n0] - mu[r][row % 3]
 // straight from the product output, without the w scratch.  A work group owns tr
 // consecutive rows (one contiguous run of u per layer) and pp RHS pairs of one column
-// tile.  Work groups are dealt to the 8 XCDs round robin by index; the 4/pp pair groups
-// of a row block get indices 8 apart, so they run on one XCD at about the same time and
-// share the product records (128 bytes per row and mode) through its L2.
+// tile, placed on the XCDs by xcd_unit: the 4/pp pair groups of a row block run on one
+// XCD at about the same time and share the product records (128 bytes per row and mode)
+// through its L2.
 //  1. gather: the spectra in natural order (mode fastest across threads, so the LDS
 //     writes are consecutive), the K slices of LU work items loaded before any is used;
 //  2. decimation-in-frequency stages of half length Nz/2 .. 4 in LDS, neighbouring
@@ -707,12 +732,8 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
                                                      const int* __restrict__ status) {
     extern __shared__ double2 lds[];
     if (status && *status) return;
-    const int npg = 4 / pp;
-    const int xcd = blockIdx.x & 7, q8 = blockIdx.x >> 3;
-    const int pg = q8 % npg;
-    const int unit = (q8 / npg) * 8 + xcd;
-    if (unit >= n_units) return;
-    const int tile = unit / n_rg, rg = unit - tile * n_rg;
+    int tile, rg, pg;
+    if (!xcd_unit(n_units, n_rg, 4 / pp, tile, rg, pg)) return;
     const int row0 = rg * tr, pair0 = pg * pp;
     const int ss = nz + 1;
     const int nm = (nz >> 1) + 1;
@@ -841,10 +862,11 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
 // of 32-byte runs is) and match or beat 16 (half the groups per CU); one pair per group,
 // the pair groups sharing the product records through L2, beats two or four pairs per
 // group.  Returns false outside 16 <= Nz <= 256: the update then goes through the w
-// scratch and the tiled transpose.
+// scratch and the tiled transpose.  (At Nz = 1024, 4 rows per group -- 64 KiB of LDS,
+// 32-byte runs of u -- measured no faster than the two passes: 3.7-4.9 ms against 4.45 ms
+// on the long workload.)
 static int update_groups(int tr, int pp, int M, int ct_grid) {
-    const int n_units = ct_grid * ((M + tr - 1) / tr);
-    return 8 * (4 / pp) * ((n_units + 7) / 8);
+    return xcd_groups(ct_grid * ((M + tr - 1) / tr), 4 / pp);
 }
 
 bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp) {
@@ -977,54 +999,122 @@ void launch_update_mean(hipStream_t st, const double* u, const double* c, double
 
 // ----------------------------------------------------------------------------------
 // u[r][n0][row] -= alpha_r * w[r][row][n0] (+ mu[r][row % 3] when mu is given: the mean
-// of the result, known beforehand) by a tiled transpose through LDS, with per block
-// partial sums of the updated u per Cartesian component (row % 3).
+// of the result, known beforehand) by a tiled transpose through LDS: tiles of 64 rows x
+// 32 layers, 16-byte accesses along the contiguous axis of each array (two rows of a
+// layer of u, two layers of a row of w per thread) where the arrays allow; the old values
+// of u are loaded before the tile of w.  SUMS: per block partial sums of the updated u per
+// Cartesian component (row % 3), for the mean removal that follows (the relaxation step).
 // Skipped entirely when a data check has latched an error.
 // ----------------------------------------------------------------------------------
+#define AX_TR 64
+#define AX_TN 32
+
+int axpy_parts(int M, int nz) { return ((M + AX_TR - 1) / AX_TR) * ((nz + AX_TN - 1) / AX_TN); }
+
+template <bool SUMS>
 __global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, double* __restrict__ u,
                                              double* __restrict__ sum_part, int nz, int M,
                                              double alpha, const double* __restrict__ alpha_d,
-                                             const double* __restrict__ mu,
+                                             const double* __restrict__ mu, int vec,
                                              const int* __restrict__ status) {
-    __shared__ double tile[32][33];
-    __shared__ double red[3 * NT];
+    __shared__ double tile[AX_TR][AX_TN + 1];
+    __shared__ double red[SUMS ? 3 * NT : 1];
     if (status && *status) return;
     const int r = blockIdx.z;
-    const int row0 = blockIdx.x * 32, n00 = blockIdx.y * 32;
+    const int row0 = blockIdx.x * AX_TR, n00 = blockIdx.y * AX_TN;
     const double a = alpha_d ? alpha_d[r] : alpha;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const double* wr = w + (int64_t)r * M * nz;
-    for (int y = ty; y < 32; y += 8) {
-        const int row = row0 + y, n0 = n00 + tx;
-        if (row < M && n0 < nz) tile[y][tx] = wr[(int64_t)row * nz + n0];
+    double* ur = u + (int64_t)r * nz * M;
+    double m3[3] = {0.0, 0.0, 0.0};
+    if (mu)
+        for (int cc = 0; cc < 3; ++cc) m3[cc] = mu[r * 3 + cc];
+    // old u: rows 2 tx, 2 tx + 1 of layers ty + 8 k
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int row = row0 + 2 * tx;
+    double uo[4][2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int n0 = n00 + ty + 8 * k;
+        uo[k][0] = uo[k][1] = 0.0;
+        if (n0 < nz) {
+            const double* p = ur + (int64_t)n0 * M + row;
+            if (vec && row + 1 < M) {
+                const double2 x = *(const double2*)p;
+                uo[k][0] = x.x;
+                uo[k][1] = x.y;
+            } else {
+                if (row < M) uo[k][0] = p[0];
+                if (row + 1 < M) uo[k][1] = p[1];
+            }
+        }
+    }
+    // w: layers 2 sx, 2 sx + 1 of rows sy + 16 k
+    {
+        const int sx = threadIdx.x & 15, sy = threadIdx.x >> 4;
+        const int n0 = n00 + 2 * sx;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int rr = row0 + sy + 16 * k;
+            double x0 = 0.0, x1 = 0.0;
+            if (rr < M) {
+                const double* p = wr + (int64_t)rr * nz + n0;
+                if (vec && n0 + 1 < nz) {
+                    const double2 x = *(const double2*)p;
+                    x0 = x.x;
+                    x1 = x.y;
+                } else {
+                    if (n0 < nz) x0 = p[0];
+                    if (n0 + 1 < nz) x1 = p[1];
+                }
+            }
+            tile[sy + 16 * k][2 * sx] = x0;
+            tile[sy + 16 * k][2 * sx + 1] = x1;
+        }
     }
     __syncthreads();
     double v[3] = {0, 0, 0};
-    double* ur = u + (int64_t)r * nz * M;
-    for (int y = ty; y < 32; y += 8) {
-        const int n0 = n00 + y, row = row0 + tx;
-        if (row < M && n0 < nz) {
-            const int64_t idx = (int64_t)n0 * M + row;
-            double x = ur[idx] - a * tile[tx][y];
-            if (mu) x -= mu[r * 3 + row % 3];
-            ur[idx] = x;
-            v[row % 3] += x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int n0 = n00 + ty + 8 * k;
+        if (n0 >= nz) continue;
+        double x[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int rr = row + e;
+            x[e] = uo[k][e] - a * tile[2 * tx + e][ty + 8 * k];
+            if (mu) x[e] -= m3[rr % 3];
+            if (SUMS && rr < M) v[rr % 3] += x[e];
+        }
+        double* p = ur + (int64_t)n0 * M + row;
+        if (vec && row + 1 < M) {
+            *(double2*)p = make_double2(x[0], x[1]);
+        } else {
+            if (row < M) p[0] = x[0];
+            if (row + 1 < M) p[1] = x[1];
         }
     }
-    block_sum<3>(v, red);
-    if (threadIdx.x == 0) {
-        const int64_t nb = (int64_t)gridDim.x * gridDim.y;
-        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-        for (int c = 0; c < 3; ++c) sum_part[((int64_t)r * nb + b) * 3 + c] = v[c];
+    if (SUMS) {
+        block_sum<3>(v, red);
+        if (threadIdx.x == 0) {
+            const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+            const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+            for (int c = 0; c < 3; ++c) sum_part[((int64_t)r * nb + b) * 3 + c] = v[c];
+        }
     }
 }
 
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status, int* n_part_out,
                  const double* mu) {
-    dim3 grid((M + 31) / 32, (nz + 31) / 32, R);
-    hipLaunchKernelGGL(k_axpy, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d, mu,
-                       status);
+    dim3 grid((M + AX_TR - 1) / AX_TR, (nz + AX_TN - 1) / AX_TN, R);
+    // 16-byte accesses: every row pair of u and layer pair of w starts 16-byte aligned
+    const int vec = ((M & 1) == 0 && (nz & 1) == 0 && ((uintptr_t)u & 15) == 0 && ((uintptr_t)w & 15) == 0) ? 1 : 0;
+    if (sum_part)
+        hipLaunchKernelGGL(k_axpy<true>, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d, mu, vec,
+                           status);
+    else
+        hipLaunchKernelGGL(k_axpy<false>, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d, mu, vec,
+                           status);
     if (n_part_out) *n_part_out = (int)(grid.x * grid.y);
 }
 

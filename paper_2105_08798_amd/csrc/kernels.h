@@ -67,6 +67,8 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
                        int64_t split_stride, const double2* rowmean, const double2* shat,
                        const int* shat_on, const unsigned long long* amax, const int* bexp,
                        int* n_part_out);
+// Partial-sum blocks of the transpose-update (per RHS) for M rows and Nz layers.
+int axpy_parts(int M, int nz);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
                  int M, double alpha, const double* alpha_d, const int* status,
                  int* n_part_out, const double* mu = nullptr);

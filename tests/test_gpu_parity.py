@@ -95,7 +95,8 @@ def test_fp64_apply_matches_oracle(name, form):
 @pytest.mark.parametrize("nz,n_i,n_b,R,bz", [(2, 7, 11, 1, 16), (32, 33, 50, 9, 32), (64, 21, 40, 17, 16),
                                              (8, 1, 1, 2, 8), (16, 130, 260, 33, 64),
                                              (8, 20, 30, 2, 2048), (256, 20, 30, 2, 32), (16, 50, 80, 64, 64),
-                                             (1024, 9, 13, 3, 16), (4, 12, 20, 1, 4096)])
+                                             (1024, 9, 13, 3, 16), (4, 12, 20, 1, 4096), (512, 17, 40, 5, 16),
+                                             (1024, 30, 70, 9, 16), (2048, 5, 9, 2, 16)])
 @pytest.mark.parametrize("form", FP64_FORMS)
 def test_fp64_ragged_shapes(nz, n_i, n_b, R, bz, form):
     wl = W.make_custom(nz, n_i, n_b, R, bz, seed=nz + n_i)
