@@ -89,13 +89,12 @@ def measured_traffic(workload: str, form: str, product_bytes: float, tuned: dict
     if hashlib.sha256(src).hexdigest() != t.get("gemm_source_sha256"):
         return None
     for name, v in t["kernels"].items():
-        if kernel_matches(form, name) and v.get("form", form) == form:
-            if v.get("algorithmic_bytes") != product_bytes:
-                return None
-            run = v.get("launch")
-            if tuned is None or run is None or any(run.get(k) != tuned.get(k) for k in ("variant", "nsplit", "order")):
-                return None
-            return v["traffic_bytes"]
+        if not (kernel_matches(form, name) and v.get("form", form) == form):
+            continue
+        run = v.get("launch")
+        if tuned is None or run is None or any(run.get(k) != tuned.get(k) for k in ("variant", "nsplit", "order")):
+            continue
+        return v["traffic_bytes"] if v.get("algorithmic_bytes") == product_bytes else None
     return None
 
 
@@ -175,7 +174,7 @@ def unbalanced_forces(c, seed: int = 5) -> np.ndarray:
 
 def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: bool, keep_cols,
               train_steps: int = 20000, extras: bool = False,
-              tune_cache: str | None = None) -> tuple[dict, np.ndarray | None]:
+              tune_cache: str | None = None, work_list: str | None = None) -> tuple[dict, np.ndarray | None]:
     """Times `steps` fbc_apply calls after `warmup`; returns the timings and the raw response
     w = G f at the pad columns keep_cols (every layer; one-cell workloads) or in full."""
     from paper_2105_08798_amd import FBC, RELAX_OUT_DOUBLES
@@ -194,7 +193,13 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     n_u = sum(c.n_rhs * c.nz * c.n_b * 3 for c in wl.cells)
     u = torch.zeros(n_u, dtype=torch.float64, device=dev)
     tuned = None
-    if tune:
+    if work_list and form != "surrogate":
+        var, nsplit, order = (int(x) for x in work_list.split(":"))
+        ctx.set_kernel_variant(var)
+        ctx.set_work_list(nsplit, order)
+        tuned = dict(nsplit=nsplit, order=order, variant=var, forced=True, shape=ctx.info.kernel_shape.decode())
+        log(f"{form}: work list set to {tuned}")
+    elif tune:
         w = torch.zeros_like(u)
         tuned = ctx.autotune(f, w, reps=3, cache=tune_cache)
         del w
@@ -404,7 +409,7 @@ def run_workload(torch, args, name: str, forms: list, extras_for=None) -> dict:
     for form in forms:
         r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph,
                          not args.no_autotune and form != "surrogate", keep, args.train_steps,
-                         extras=(form == extras_for), tune_cache=args.tune_cache)
+                         extras=(form == extras_for), tune_cache=args.tune_cache, work_list=args.work_list)
         r["w"] = w
         res[form] = r
     ref_form = next((f for f in FP64_FORMS if f in res), None)
@@ -714,6 +719,9 @@ def main() -> int:
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: a stored choice for the same configuration is applied "
                          "untimed, a new one appended (keeps separate profiling runs on one work list)")
+    ap.add_argument("--work-list", default=None, metavar="VARIANT:NSPLIT:ORDER",
+                    help="product kernel variant and work list for every form instead of the autotuner's choice "
+                         "(for counter runs of one launch configuration)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000, help="Adam steps of the surrogate's MLP")
     ap.add_argument("--max-rank", type=int, default=64, help="rank bound of the H-matrix workload")
