@@ -638,6 +638,28 @@ def bench_hmat(args, torch) -> dict:
     return line
 
 
+def bench_hbm_read(args, torch) -> dict:
+    """The device memory's practical streaming-read rate (fbc_probe_read: a plain read kernel,
+    16-byte nontemporal loads, each work group its own contiguous share), for buffers of 16,
+    64 and 128 GiB (the long workload's compact store holds 121.5 GB) and 512 to 4096 work
+    groups, beside the 8 TB/s peak the roofline fractions are quoted against."""
+    from paper_2105_08798_amd import probe_read
+    rows = []
+    for gib in (16, 64, 128):
+        buf = torch.ones((gib << 30) // 8, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        for groups in (512, 1024, 2048, 4096):
+            gbs = probe_read(buf, groups, reps=3)
+            rows.append(dict(gib=gib, groups=groups, gbs=gbs, frac_of_peak=gbs / HBM_PEAK_GBS))
+            log(f"{gib} GiB, {groups} groups: {gbs:.0f} GB/s")
+        del buf
+        torch.cuda.empty_cache()
+    best = max(r["gbs"] for r in rows)
+    return {"metric": "streaming-read rate of the device memory (plain read kernel)", "unit": "GB/s",
+            "value": best, "peak": HBM_PEAK_GBS, "frac_of_peak": best / HBM_PEAK_GBS, "rows": rows,
+            "data": "synthetic (a buffer of ones)"}
+
+
 def bench_learned_budget(args, torch) -> dict:
     """Error budget of the learned far field on the long workload against the FP64 oracle's
     sampled line spectrum (tests/golden/long_modes.npz).  The surrogate keeps a line mode's
@@ -711,7 +733,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=None,
                     help="one workload only (long, large, medium, batched, plgf, hmat, learned: the "
-                         "learned far field's error budget); default: long (headline) and large in one line")
+                         "learned far field's error budget, hbm: the memory's streaming-read rate); default: "
+                         "long (headline) and large in one line")
     ap.add_argument("--forms", default=None, help="comma-separated forms of the headline workload")
     ap.add_argument("--graph", action="store_true", help="replay the update from a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
@@ -746,6 +769,9 @@ def main() -> int:
         return 0
     if args.workload == "learned":
         print(json.dumps(bench_learned_budget(args, torch)), flush=True)
+        return 0
+    if args.workload == "hbm":
+        print(json.dumps(bench_hbm_read(args, torch)), flush=True)
         return 0
 
     if args.copy_calibration:

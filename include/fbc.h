@@ -575,6 +575,16 @@ fbc_status fbc_set_hmat(fbc_ctx* c, fbc_hmat* h, void* stream);
 
 const char* fbc_status_string(fbc_status s);
 
+/* Diagnostic for callers that weigh a kernel against the memory's practical rate (not part
+ * of the method): reads `bytes` of the device buffer `buf` (16-byte aligned, a multiple of
+ * 16 bytes) with a plain streaming-read kernel -- `groups` work groups of 256 threads, each
+ * its own contiguous share, 16-byte nontemporal loads, eight in flight per thread -- once
+ * untimed, then `reps` times between HIP events on `stream`, and sets *gbs to the rate in
+ * GB/s (1e9 bytes).  Allocates and frees a small output buffer; synchronises `stream`.
+ * FBC_E_ARG for a bad pointer, size, alignment, groups outside [1, 65536] or reps outside
+ * [1, 1000]; FBC_E_NOMEM / FBC_E_DEVICE on a runtime failure. */
+fbc_status fbc_probe_read(const void* buf, int64_t bytes, int groups, int reps, double* gbs, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["api.hip", "assemble.hip", "apply.hip", "gemm.hip", "learned.hip", "learned_api.hip", "plgf.hip", "hmat.hip",
-           "plan.cpp"]
+           "probe.hip", "plan.cpp"]
 LIB = os.path.join(HERE, "libfbc.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

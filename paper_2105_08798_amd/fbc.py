@@ -31,7 +31,7 @@ EXPORTED = [
     "fbc_hmat_last_error", "fbc_hmat_create", "fbc_hmat_destroy", "fbc_hmat_get_info", "fbc_hmat_partition",
     "fbc_hmat_ranks", "fbc_hmat_apply", "fbc_mlp_forward_noalloc", "fbc_mlp_forward_noalloc_max_rows",
     "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant", "fbc_sur_set_mlp_fp32",
-    "fbc_sur_set_learn_range", "fbc_sur_set_exact_range", "fbc_set_hmat",
+    "fbc_sur_set_learn_range", "fbc_sur_set_exact_range", "fbc_set_hmat", "fbc_probe_read",
 ]
 
 
@@ -175,6 +175,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fbc_hmat_ranks.argtypes = [vp, vp]
     lib.fbc_hmat_apply.argtypes = [vp, vp, vp, vp]
     lib.fbc_set_hmat.argtypes = [vp, vp, vp]
+    lib.fbc_probe_read.argtypes = [vp, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_double), vp]
     for name in ("fbc_assemble_G", "fbc_apply", "fbc_green_apply", "fbc_relax_begin", "fbc_relax_step",
                  "fbc_relax_step_graph", "fbc_autotune_cached", "fbc_set_kernel_variant",
                  "fbc_sur_set_mlp_fp32", "fbc_sur_set_learn_range", "fbc_sur_set_exact_range", "fbc_set_hmat",
@@ -184,7 +185,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                  "fbc_sur_training_set", "fbc_mlp_create", "fbc_mlp_num_params", "fbc_mlp_params",
                  "fbc_mlp_grad", "fbc_mlp_loss_grad", "fbc_mlp_adam_step", "fbc_mlp_forward",
                  "fbc_mlp_forward_noalloc", "fbc_plgf_create", "fbc_plgf_table", "fbc_plgf_eval", "fbc_hmat_create", "fbc_hmat_get_info",
-                 "fbc_hmat_partition", "fbc_hmat_ranks", "fbc_hmat_apply"):
+                 "fbc_hmat_partition", "fbc_hmat_ranks", "fbc_hmat_apply", "fbc_probe_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -592,6 +593,19 @@ class HMatrix:
             self.close()
         except Exception:
             pass
+
+
+def probe_read(buf, groups: int, reps: int = 5, stream=None) -> float:
+    """Streaming-read rate (GB/s) of the device buffer `buf` (a CUDA tensor, 16-byte aligned,
+    a multiple of 16 bytes) with `groups` work groups: fbc_probe_read, a diagnostic for
+    weighing the kernels against the memory's practical rate."""
+    lib = load_library()
+    out = C.c_double(0.0)
+    rc = lib.fbc_probe_read(C.c_void_p(buf.data_ptr()), C.c_int64(buf.numel() * buf.element_size()), int(groups),
+                            int(reps), C.byref(out), _stream_handle(stream))
+    if rc != 0:
+        raise FbcError(rc, f"fbc_probe_read: {lib.fbc_status_string(rc).decode()}")
+    return out.value
 
 
 def parse_relax_out(t) -> list[dict]:

@@ -122,3 +122,15 @@ def test_tune_result_layout_and_null_context_work_list():
     fbc, lib = _lib()
     assert C.sizeof(fbc.TuneResult) == 40
     assert lib.fbc_set_work_list(None, 1, 0, None) == -1
+
+
+def test_read_probe_rejects_bad_arguments_on_the_host():
+    fbc, lib = _lib()
+    g = C.c_double(0.0)
+    assert lib.fbc_probe_read(None, 1 << 20, 512, 1, C.byref(g), None) == -1
+    fake = C.c_void_p(1 << 20)                    # never dereferenced: the checks come first
+    assert lib.fbc_probe_read(fake, 24, 512, 1, C.byref(g), None) == -1        # not a multiple of 16
+    assert lib.fbc_probe_read(fake, 1 << 20, 0, 1, C.byref(g), None) == -1
+    assert lib.fbc_probe_read(fake, 1 << 20, 512, 0, C.byref(g), None) == -1
+    assert lib.fbc_probe_read(fake, 1 << 20, 512, 1, None, None) == -1
+    assert lib.fbc_probe_read(C.c_void_p((1 << 20) + 8), 1 << 20, 512, 1, C.byref(g), None) == -1   # alignment
