@@ -138,9 +138,10 @@ typedef struct {
                                 (the line-mode Green function decays with kappa rho).
                                 0: default (1e-16 for the FP64 forms, at the rounding
                                 of their assembly; 1e-9 for the reduced forms, two orders
-                                below their rounding of ~1e-7; 1e-12 for the surrogate,
-                                far below its learned band's ~2e-9; it also ends the
-                                generated part of each mode); < 0: none                   */
+                                below their rounding of ~1e-7, and for the surrogate, two
+                                orders below its error of ~1e-8, just inside its learned
+                                band's end at ~2e-9; there it also ends the generated part
+                                of each mode); < 0: none                                  */
 } fbc_options;
 
 /* Fills *opt with defaults: FP64, 1024 x 1024 torus, check on, no projection, tol 1e-10,

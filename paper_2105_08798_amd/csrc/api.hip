@@ -191,11 +191,13 @@ static double skip_tolerance(const fbc_options& o) {
     if (o.skip_tol < 0) return -1.0;
     if (o.skip_tol > 0) return o.skip_tol;
     // FP64 forms: at the rounding of their assembly; reduced forms: two orders of
-    // magnitude below their own rounding (~1e-7); the learned form: far below the error of
-    // its learned band (whose blocks end at exp(-s_learn) ~ 2e-9 of a mode's largest)
-    if (o.form == FBC_FORM_SURROGATE) return 1e-12;
-    return (o.form == FBC_FORM_FP32 || o.form == FBC_FORM_SPLIT_BF16 || o.form == FBC_FORM_SPLIT_FP16) ? 1e-9
-                                                                                                    : 1e-16;
+    // magnitude below their own rounding (~1e-7); the learned form likewise: two orders
+    // below its own error (~1e-8), just inside the end of its learned band (blocks down to
+    // exp(-s_learn) ~ 2e-9 of a mode's largest)
+    return (o.form == FBC_FORM_FP32 || o.form == FBC_FORM_SPLIT_BF16 || o.form == FBC_FORM_SPLIT_FP16 ||
+            o.form == FBC_FORM_SURROGATE)
+               ? 1e-9
+               : 1e-16;
 }
 
 static void compute_windows(fbc_ctx* c, const std::vector<double>& rho_cut, int rows_tile) {
