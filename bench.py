@@ -175,7 +175,7 @@ def unbalanced_forces(c, seed: int = 5) -> np.ndarray:
 def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: bool, keep_cols,
               train_steps: int = 20000, extras: bool = False,
               tune_cache: str | None = None, work_list: str | None = None,
-              skip_tol: float = 0.0) -> tuple[dict, np.ndarray | None]:
+              skip_tol: float = 0.0, gen_modes: int = 0) -> tuple[dict, np.ndarray | None]:
     """Times `steps` fbc_apply calls after `warmup`; returns the timings and the raw response
     w = G f at the pad columns keep_cols (every layer; one-cell workloads) or in full."""
     from paper_2105_08798_amd import FBC, RELAX_OUT_DOUBLES
@@ -185,7 +185,7 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     if form == "surrogate":
         sur, sur_info = train_surrogate(torch, wl, train_steps)
     t0 = time.perf_counter()
-    ctx = FBC(wl.cells, wl.bz, form=form, surrogate=sur, skip_tol=skip_tol)
+    ctx = FBC(wl.cells, wl.bz, form=form, surrogate=sur, skip_tol=skip_tol, gen_modes=gen_modes)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     log(f"{form}: assembled in {t_asm:.2f} s (store {ctx.info.store_bytes / 1e9:.2f} GB, "
@@ -411,7 +411,7 @@ def run_workload(torch, args, name: str, forms: list, extras_for=None) -> dict:
         r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph,
                          not args.no_autotune and form != "surrogate", keep, args.train_steps,
                          extras=(form == extras_for), tune_cache=args.tune_cache, work_list=args.work_list,
-                         skip_tol=args.skip_tol)
+                         skip_tol=args.skip_tol, gen_modes=args.gen_modes)
         r["w"] = w
         res[form] = r
     ref_form = next((f for f in FP64_FORMS if f in res), None)
@@ -749,6 +749,8 @@ def main() -> int:
                          "(for counter runs of one launch configuration)")
     ap.add_argument("--skip-tol", type=float, default=0.0,
                     help="negligible-block tolerance of every form (0: the library's default per form, < 0: none)")
+    ap.add_argument("--gen-modes", type=int, default=0,
+                    help="learned form: table modes generated per chunk (0: the library's default)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000, help="Adam steps of the surrogate's MLP")
     ap.add_argument("--max-rank", type=int, default=64, help="rank bound of the H-matrix workload")

@@ -131,7 +131,7 @@ typedef struct {
     const fbc_sur* surrogate;/* FBC_FORM_SURROGATE: far-field object (not owned; must
                                 outlive the context and keep its MLP weights); else NULL */
     int gen_modes;           /* FBC_FORM_SURROGATE: table modes generated per chunk
-                                (>= 0; 0: as many as fit in 2 GiB of scratch)            */
+                                (>= 0; 0: as many as fit in 4 GiB of scratch)            */
     double skip_tol;         /* negligible blocks: at line mode m the product skips the
                                 K chunks of a row tile whose blocks all lie farther than
                                 the farthest offset with |G^(m)| >= skip_tol * max |G^(m)|
