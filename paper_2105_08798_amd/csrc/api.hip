@@ -281,9 +281,8 @@ static fbc_status assemble_all(fbc_ctx* c, hipStream_t st, const BondTable& bt, 
         if ((s = dev_alloc(c, (void**)&c->tab, (int64_t)T * n_off * 96)) != FBC_OK) return s;
         c->store_bytes = (int64_t)T * n_off * 96;
     } else if (sur) {
-        // generated slices: as many table modes per chunk as fit in about 2 GiB (also the
-        // workspace of the measuring pass below)
-        // default: as many modes as fit in 4 GiB (long workload: 40 modes per chunk, 4 % faster
+        // generated slices (also the workspace of the measuring pass below): by default as many
+        // table modes per chunk as fit in 4 GiB (long workload: 40 modes per chunk, 4 % faster
         // than the 21 of 2 GiB, within 1 % of 80 or 171)
         c->gen_modes = (int)std::max<int64_t>(1, std::min<int64_t>(T, ((int64_t)4 << 30) / std::max<int64_t>(1, n_off * 96)));
         if (c->opt.gen_modes > 0) c->gen_modes = std::min(c->opt.gen_modes, T);
