@@ -32,14 +32,17 @@ HBM_PEAK_GBS = 8000.0
 # dense MFMA peak of the arithmetic each product runs on (TFLOP/s; the split forms run
 # three BF16 / FP16 products per algorithmic one)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0, "dtable_fp64": 78.6,
-               "surrogate": 78.6}
+               "surrogate": 78.6, "surrogate_fp32": 157.3}
 MFMA_PER_ALG = {"split_bf16": 3.0, "split_fp16": 3.0}
-F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "split_fp16": 8, "dtable_fp64": 16, "surrogate": 16}
+F_BYTES = {"fp64": 16, "fp32": 8, "split_bf16": 8, "split_fp16": 8, "dtable_fp64": 16, "surrogate": 16,
+           "surrogate_fp32": 16}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16 hi+lo (fp32 acc)",
          "split_fp16": "fp16 hi+lo, power-of-two scaled (fp32 acc)", "dtable_fp64": "f64",
-         "surrogate": "f64 (generated table; bf16 MLP on MFMA, fp32 acc)"}
+         "surrogate": "f64 (generated table; bf16 MLP on MFMA, fp32 acc)",
+         "surrogate_fp32": "f32 MFMA on the generated f64 table, f64 across chunks and at modes without skipped "
+                           "blocks (bf16 MLP on MFMA)"}
 FP64_FORMS = ("fp64", "dtable_fp64")
-DEFAULT_FORMS = {"long": ["dtable_fp64", "fp32", "split_fp16", "split_bf16", "surrogate"],
+DEFAULT_FORMS = {"long": ["dtable_fp64", "fp32", "split_fp16", "split_bf16", "surrogate", "surrogate_fp32"],
                  "large": ["fp64", "fp32", "split_bf16", "split_fp16"],
                  "medium": ["fp64", "fp32", "split_bf16", "split_fp16", "surrogate"],
                  "batched": ["dtable_fp64"]}
@@ -96,6 +99,9 @@ def measured_traffic(workload: str, form: str, product_bytes: float, tuned: dict
             continue
         return v["traffic_bytes"] if v.get("algorithmic_bytes") == product_bytes else None
     return None
+
+
+_TRAINED = {}
 
 
 def train_surrogate(torch, wl, steps: int, seed: int = 0, r_c: float = 6.0, s_exact: float = 12.0,
@@ -182,10 +188,16 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream() if graph else None
     sur = sur_info = None
-    if form == "surrogate":
-        sur, sur_info = train_surrogate(torch, wl, train_steps)
+    # surrogate_fp32: the learned form with its table products on FP32 MFMA (table_fp32)
+    lib_form = "surrogate" if form.startswith("surrogate") else form
+    if lib_form == "surrogate":
+        key = (wl.description, train_steps)
+        if key not in _TRAINED:            # one network per workload serves both learned forms
+            _TRAINED[key] = train_surrogate(torch, wl, train_steps)
+        sur, sur_info = _TRAINED[key]
     t0 = time.perf_counter()
-    ctx = FBC(wl.cells, wl.bz, form=form, surrogate=sur, skip_tol=skip_tol, gen_modes=gen_modes)
+    ctx = FBC(wl.cells, wl.bz, form=lib_form, surrogate=sur, skip_tol=skip_tol, gen_modes=gen_modes,
+              table_fp32=form == "surrogate_fp32")
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     log(f"{form}: assembled in {t_asm:.2f} s (store {ctx.info.store_bytes / 1e9:.2f} GB, "
@@ -194,7 +206,7 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
     n_u = sum(c.n_rhs * c.nz * c.n_b * 3 for c in wl.cells)
     u = torch.zeros(n_u, dtype=torch.float64, device=dev)
     tuned = None
-    if work_list and form != "surrogate":
+    if work_list and lib_form != "surrogate":
         var, nsplit, order = (int(x) for x in work_list.split(":"))
         ctx.set_kernel_variant(var)
         ctx.set_work_list(nsplit, order)
@@ -275,9 +287,7 @@ def time_form(torch, wl, form: str, steps: int, warmup: int, graph: bool, tune: 
         w_keep = w.view(c.n_rhs, c.nz, c.n_b, 3)[:, :, idx, :].cpu().numpy()
     else:
         w_keep = w.cpu().numpy()
-    ctx.close()
-    if sur is not None:
-        sur.close()
+    ctx.close()                      # a trained surrogate stays for the workload's other learned form
     del ctx, u, w, f
     torch.cuda.empty_cache()
     ms = 1000.0 * dt / steps
@@ -409,7 +419,7 @@ def run_workload(torch, args, name: str, forms: list, extras_for=None) -> dict:
     res = {}
     for form in forms:
         r, w = time_form(torch, wl, form, args.steps, args.warmup, args.graph,
-                         not args.no_autotune and form != "surrogate", keep, args.train_steps,
+                         not args.no_autotune and not form.startswith("surrogate"), keep, args.train_steps,
                          extras=(form == extras_for), tune_cache=args.tune_cache, work_list=args.work_list,
                          skip_tol=args.skip_tol, gen_modes=args.gen_modes)
         r["w"] = w
@@ -424,7 +434,8 @@ def run_workload(torch, args, name: str, forms: list, extras_for=None) -> dict:
                 if len(wl.cells) == 1 else None
         e_or = oracle_error(g[0], g[1], r["w"]) if g is not None else None
         roof = roofline_of(form, r) if r["gemm_ms"] else None
-        g_kept = r["product"]["bytes"] - io["fhat_what"] if form not in ("dtable_fp64", "surrogate") else None
+        g_kept = r["product"]["bytes"] - io["fhat_what"] if form not in ("dtable_fp64", "surrogate",
+                                                                            "surrogate_fp32") else None
         out_forms[form] = dict(
             updates_per_s=r["updates_per_s"], ms_per_step=r["ms_per_step"], gemm_ms=r["gemm_ms"],
             roofline=roof, rel_err_vs_oracle=e_or, oracle_samples=(g[0] if g else None),
@@ -446,6 +457,9 @@ def run_workload(torch, args, name: str, forms: list, extras_for=None) -> dict:
     ok = [f for f in out_forms if err_of(f) is not None and err_of(f) <= 1e-6] or \
          [f for f in out_forms if f in FP64_FORMS]
     head = max(ok, key=lambda f: out_forms[f]["updates_per_s"]) if ok else forms[0]
+    for sur, _ in _TRAINED.values():
+        sur.close()
+    _TRAINED.clear()
     return dict(wl=wl, forms=out_forms, head=head, err_of=err_of, ref_form=ref_form)
 
 

@@ -142,6 +142,15 @@ typedef struct {
                                 orders below its error of ~1e-8, just inside its learned
                                 band's end at ~2e-9; there it also ends the generated part
                                 of each mode); < 0: none                                  */
+    int table_fp32;          /* offset-table forms (FBC_FORM_DTABLE_FP64, FBC_FORM_SURROGATE):
+                                1 = the products of the line modes whose far blocks are
+                                skipped (skip_tol) on FP32 MFMA -- the gathered FP64 blocks
+                                and f^ rounded to FP32, FP32 sums over 8 interface columns,
+                                FP64 across them -- and FP64 MFMA at the modes without
+                                skipping (mode 0 among them: its long-range part carries
+                                the gauge constant); error of the order of the FP32 form's.
+                                0 (default) = FP64 MFMA everywhere.  FBC_E_ARG for other
+                                values or forms                                           */
 } fbc_options;
 
 /* Fills *opt with defaults: FP64, 1024 x 1024 torus, check on, no projection, tol 1e-10,

@@ -620,6 +620,10 @@ static void unit_jobs(const fbc_ctx* c, const Unit& u, int nsplit, std::vector<G
             j.k0 = (a == e) ? 0 : unit_k * (ws + a);
             j.k1 = (a == e) ? 0 : unit_k * (ws + e);
             j.ct_active = p.ctr;
+            // FP32 MFMA only at modes whose far blocks are skipped: a mode without skipping
+            // (mode 0 among them) keeps its whole long-range part, gauge constant included,
+            // which FP32 rounding of the blocks would not carry to 1e-6
+            j.prec = (dt && c->opt.table_fp32 && p.mode_skips[u.m]) ? 1 : 0;
             out.push_back(j);
         }
 }
@@ -750,6 +754,9 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     if (opt->form == FBC_FORM_SURROGATE && (!opt->surrogate || !opt->surrogate->has_mlp))
         return fail(nullptr, FBC_E_ARG, "the surrogate form needs an fbc_sur with MLP weights");
     if (opt->gen_modes < 0) return fail(nullptr, FBC_E_ARG, "gen_modes must be >= 0");
+    if (opt->table_fp32 != 0 && opt->table_fp32 != 1) return fail(nullptr, FBC_E_ARG, "table_fp32 must be 0 or 1");
+    if (opt->table_fp32 && !is_table_form(opt->form))
+        return fail(nullptr, FBC_E_ARG, "table_fp32 applies to the offset-table forms (FP64 table, surrogate)");
     if (!is_pow2(opt->bz_m1) || !is_pow2(opt->bz_m2) || opt->bz_m1 < 8 || opt->bz_m2 < 8 ||
         opt->bz_m1 > 4096 || opt->bz_m2 > 4096)
         return fail(nullptr, FBC_E_ARG, "bz_m1, bz_m2 must be powers of two in [8, 4096]");
@@ -1020,7 +1027,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
             ql.start[0] = 0;
             launch_gemm_dtab(st, c->jobs + j0, j1 - j0, c->ctmax, c->gen, (int64_t)t0 * c->n_offsets * 6,
                              (const double*)c->bfrag, c->cbuf, c->celldev, c->lut, c->d1min, c->d2min, c->w2,
-                             c->n_need, c->n_offsets, c->job_order == 3 ? &ql : nullptr);
+                             c->n_need, c->n_offsets, c->job_order == 3 ? &ql : nullptr, c->opt.table_fp32);
         }
     } else if (form == FBC_FORM_DTABLE_FP64 && c->hmat) {
         const CellPlan& p = c->cells[0];          // one cell (checked when attached)
@@ -1029,7 +1036,7 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
     } else if (form == FBC_FORM_DTABLE_FP64)
         launch_gemm_dtab(st, c->jobs, c->njobs, c->ctmax, c->tab, 0, (const double*)c->bfrag, c->cbuf,
                          c->celldev, c->lut, c->d1min, c->d2min, c->w2, nullptr, c->n_offsets,
-                         c->job_order >= 3 ? &c->lists : nullptr);
+                         c->job_order >= 3 ? &c->lists : nullptr, c->opt.table_fp32);
     else
         launch_gemm(st, form, c->jobs, c->njobs, c->ctmax, c->store, c->bfrag, c->cbuf,
                     c->job_order >= 3 ? &c->lists : nullptr, c->variant);

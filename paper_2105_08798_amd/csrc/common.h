@@ -104,6 +104,7 @@ struct GemmJob {
     int32_t k0, k1;
     int32_t ct_active;  // column tiles holding RHS of this cell (offset form skips the rest)
     int32_t crs;        // output row stride (doubles): the modes of a row are adjacent
+    int32_t prec;       // offset forms: 1 = this job on FP32 MFMA (options.table_fp32), 0 = FP64
 };
 
 // Work lists of a persistent product launch: one list consumed by every work group (the

@@ -740,23 +740,34 @@ void launch_gemm(hipStream_t st, int form, const GemmJob* jobs, int njobs, int c
 // Register-prefetch pipeline: the gathers of chunk i+1 are issued right after chunk i has
 // been written to LDS, so their latency hides behind the MFMAs of chunk i.  jb.ct_active
 // column tiles carry RHS of this cell; the others are skipped.
+// F32 (jobs with jb.prec = 1): the same gathered values rounded to FP32 on FP32 MFMA
+// 16x16x4 (same operand lanes as the FP64 one), accumulated in FP32 over a chunk of 48
+// k' and in FP64 across chunks.
+// LDS of the offset-table product, declared once by each kernel and shared by both
+// precisions: the A chunk in natural order [row][k'] with an odd row stride (the gathering
+// threads' 8-byte writes and the MFMA lanes' 8-byte reads both fall into distinct banks);
+// for CT > 2 the chunk's B fragments, staged once for both waves (CT <= 2: each wave keeps
+// them in registers, so four work groups fit per CU); the tile's pad columns.
+#define DT_AS 49
+template <int CT>
+struct DtabLds {
+    double As[96 * DT_AS];
+    double Bs[(CT <= 2 ? 1 : CT * 6 * 128)];   // [ct][p][lane][2]
+    int scb[2 * DT_TB];
+};
 // One job of the offset-table product.  Every thread of the work group calls it with the
 // same job (its barriers are uniform); it leaves LDS free for the next job once a barrier
 // has followed it.
-template <int CT>
-__device__ inline void dtab_job(const GemmJob& jb, const double2* __restrict__ tab, int64_t a_base,
+template <int CT, bool F32>
+__device__ inline void dtab_job(DtabLds<CT>& sh, const GemmJob& jb, const double2* __restrict__ tab, int64_t a_base,
                                 const double* __restrict__ B, double* __restrict__ C,
                                 const CellDev* __restrict__ cells, const int32_t* __restrict__ lut,
                                 int d1min, int d2min, int w2, const int32_t* __restrict__ need,
                                 int64_t n_off) {
-    // A chunk in natural order [row][k'] with an odd row stride: the gathering threads'
-    // 8-byte writes and the MFMA lanes' 8-byte reads both fall into distinct banks
-    constexpr int AS = 49;
-    __shared__ double As[96 * AS];
-    // CT <= 2: each wave keeps the chunk's B fragments in registers (no LDS, so four work
-    // groups fit per CU); more tiles are staged in LDS once for both waves
-    __shared__ double Bs[(CT <= 2 ? 1 : CT * 6 * 128)];   // [ct][p][lane][2]
-    __shared__ int scb[2 * DT_TB];
+    constexpr int AS = DT_AS;
+    double* As = sh.As;
+    double* Bs = sh.Bs;
+    int* scb = sh.scb;
     if (jb.mb == 0) return;
     const CellDev cd = cells[jb.cell];
     const int nca = jb.ct_active;
@@ -849,6 +860,13 @@ __device__ inline void dtab_job(const GemmJob& jb, const double2* __restrict__ t
         }
         if (i0 + DT_TI < jb.k1) prefetch(i0 + DT_TI);
         __syncthreads();
+        f4_t a32[3][CT];
+        if constexpr (F32) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) a32[r][c] = (f4_t){0, 0, 0, 0};
+        }
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
             double2 av[3], bv[CT];
@@ -869,32 +887,62 @@ __device__ inline void dtab_job(const GemmJob& jb, const double2* __restrict__ t
                 for (int r = 0; r < 3; ++r)
 #pragma unroll
                     for (int c = 0; c < CT; ++c)
-                        if (c < nca)
-                            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(h ? av[r].y : av[r].x,
-                                                                             h ? bv[c].y : bv[c].x,
-                                                                             acc[r][c], 0, 0, 0);
+                        if (c < nca) {
+                            if constexpr (F32)
+                                a32[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    (float)(h ? av[r].y : av[r].x), (float)(h ? bv[c].y : bv[c].x), a32[r][c], 0, 0,
+                                    0);
+                            else
+                                acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(h ? av[r].y : av[r].x,
+                                                                                 h ? bv[c].y : bv[c].x,
+                                                                                 acc[r][c], 0, 0, 0);
+                        }
+        }
+        if constexpr (F32) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[r][c][j] += (double)a32[r][c][j];
         }
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < CT; ++c)
-            if (c < nca) store_c_f64(C, jb, jb.rb0 + 3 * wave + r, c, lane, acc[r][c]);
+            if (c < nca) {
+                if constexpr (F32) store_c_f32acc(C, jb, jb.rb0 + 3 * wave + r, c, lane, acc[r][c]);
+                else store_c_f64(C, jb, jb.rb0 + 3 * wave + r, c, lane, acc[r][c]);
+            }
+}
+
+// MIX = 0: every job on FP64 MFMA; MIX = 1 (options.table_fp32): each job in its own
+// precision (jb.prec).  Separate instantiations, so that the FP64 kernel keeps its own
+// register allocation.
+template <int CT, int MIX>
+__device__ inline void dtab_any(DtabLds<CT>& sh, const GemmJob& jb, const double2* __restrict__ tab, int64_t a_base,
+                                const double* __restrict__ B, double* __restrict__ C,
+                                const CellDev* __restrict__ cells, const int32_t* __restrict__ lut, int d1min,
+                                int d2min, int w2, const int32_t* __restrict__ need, int64_t n_off) {
+    if (MIX && jb.prec) dtab_job<CT, true>(sh, jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
+    else dtab_job<CT, false>(sh, jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
 }
 
 // One work group per job, in list order.
-template <int CT>
+template <int CT, int MIX>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
 k_gemm_dtab(const GemmJob* __restrict__ jobs, const double2* __restrict__ tab, int64_t a_base,
             const double* __restrict__ B, double* __restrict__ C, const CellDev* __restrict__ cells,
             const int32_t* __restrict__ lut, int d1min, int d2min, int w2,
             const int32_t* __restrict__ need, int64_t n_off) {
+    __shared__ DtabLds<CT> sh;
     const GemmJob jb = jobs[blockIdx.x];
-    dtab_job<CT>(jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
+    dtab_any<CT, MIX>(sh, jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
 }
 
 // Persistent form (work queue as for the dense products).
-template <int CT>
+template <int CT, int MIX>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(CT == 2 ? 2 : 1)))
 k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
                const double2* __restrict__ tab, int64_t a_base, const double* __restrict__ B,
@@ -902,10 +950,11 @@ k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
                const int32_t* __restrict__ lut, int d1min, int d2min, int w2,
                const int32_t* __restrict__ need, int64_t n_off) {
     __shared__ int slot;
+    __shared__ DtabLds<CT> sh;
     int cur = 0;
     for (int j = pq_next(q, &slot, cur); j < njobs; j = pq_next(q, &slot, cur)) {
         const GemmJob jb = jobs[j];
-        dtab_job<CT>(jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
+        dtab_any<CT, MIX>(sh, jb, tab, a_base, B, C, cells, lut, d1min, d2min, w2, need, n_off);
     }
     pq_done(q);
 }
@@ -913,27 +962,35 @@ k_gemm_dtab_pq(const GemmJob* __restrict__ jobs, int njobs, PqLists q,
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
                       const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
-                      int64_t n_off, const PqLists* q) {
+                      int64_t n_off, const PqLists* q, int mixed) {
     if (njobs <= 0) return;
     dim3 blk(128);
     if (q) {
-#define PQ_CASE(CT)                                                                             \
-    hipLaunchKernelGGL(k_gemm_dtab_pq<CT>, dim3(std::min(njobs, pq_groups_of(k_gemm_dtab_pq<CT>, 128))), blk, 0, st, jobs, \
-                       njobs, *q, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off)
+#define PQ_CASE(CT, MIX)                                                                             \
+    hipLaunchKernelGGL((k_gemm_dtab_pq<CT, MIX>), dim3(std::min(njobs, pq_groups_of(k_gemm_dtab_pq<CT, MIX>, 128))), blk, 0, \
+                       st, jobs, njobs, *q, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off)
+#define PQ_CT(CT) do { if (mixed) PQ_CASE(CT, 1); else PQ_CASE(CT, 0); } while (0)
         switch (ct) {
-            case 1: PQ_CASE(1); break;
-            case 2: PQ_CASE(2); break;
-            case 4: PQ_CASE(4); break;
-            default: PQ_CASE(8); break;
+            case 1: PQ_CT(1); break;
+            case 2: PQ_CT(2); break;
+            case 4: PQ_CT(4); break;
+            default: PQ_CT(8); break;
         }
+#undef PQ_CT
 #undef PQ_CASE
         return;
     }
     dim3 grid(njobs);
+#define DT_CASE(CT, MIX)                                                                              \
+    hipLaunchKernelGGL((k_gemm_dtab<CT, MIX>), grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, \
+                       w2, need, n_off)
+#define DT_CT(CT) do { if (mixed) DT_CASE(CT, 1); else DT_CASE(CT, 0); } while (0)
     switch (ct) {
-        case 1: hipLaunchKernelGGL(k_gemm_dtab<1>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
-        case 2: hipLaunchKernelGGL(k_gemm_dtab<2>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
-        case 4: hipLaunchKernelGGL(k_gemm_dtab<4>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
-        default: hipLaunchKernelGGL(k_gemm_dtab<8>, grid, blk, 0, st, jobs, tab, a_base, b, c, cells, lut, d1min, d2min, w2, need, n_off); break;
+        case 1: DT_CT(1); break;
+        case 2: DT_CT(2); break;
+        case 4: DT_CT(4); break;
+        default: DT_CT(8); break;
     }
+#undef DT_CT
+#undef DT_CASE
 }

@@ -56,7 +56,7 @@ std::string gemm_shape(int form, int ctmax, int variant);
 void launch_gemm_dtab(hipStream_t st, const GemmJob* jobs, int njobs, int ct, const double2* tab,
                       int64_t a_base, const double* b, double* c, const CellDev* cells,
                       const int32_t* lut, int d1min, int d2min, int w2, const int32_t* need,
-                      int64_t n_off, const PqLists* q);   // q != NULL: persistent work-queue kernel
+                      int64_t n_off, const PqLists* q, int mixed = 0);   // q != NULL: persistent work-queue kernel
 // H-matrix product step (hmat.hip): B fragments of one FP64 cell in, product records out
 void hmat_enqueue_pipeline(fbc_hmat* h, const double* bfrag, int64_t bf_mode, int kp, double* rec, int mp, int nm,
                            int ct, hipStream_t st);

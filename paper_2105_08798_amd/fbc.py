@@ -54,7 +54,7 @@ class Options(C.Structure):
     _fields_ = [("form", C.c_int), ("bz_m1", C.c_int), ("bz_m2", C.c_int),
                 ("check_netforce", C.c_int), ("project_netforce", C.c_int),
                 ("netforce_tol", C.c_double), ("row_gauge", C.c_int), ("surrogate", C.c_void_p),
-                ("gen_modes", C.c_int), ("skip_tol", C.c_double)]
+                ("gen_modes", C.c_int), ("skip_tol", C.c_double), ("table_fp32", C.c_int)]
 
 
 class RelaxOpts(C.Structure):
@@ -219,7 +219,7 @@ class FBC:
     def __init__(self, cells, bz: int | tuple, form: str = "fp64", spring_k: float = 1.0,
                  lattice_a: float = 1.0, check_netforce: bool = True, project_netforce: bool = False,
                  netforce_tol: float = 1e-10, row_gauge: bool = True, surrogate=None, gen_modes: int = 0,
-                 skip_tol: float = 0.0, stream=None):
+                 skip_tol: float = 0.0, table_fp32: bool = False, stream=None):
         lib = load_library()
         self._lib = lib
         self.ctx = C.c_void_p()
@@ -235,6 +235,7 @@ class FBC:
         opt.surrogate = surrogate.handle.value if surrogate is not None else None
         opt.gen_modes = int(gen_modes)
         opt.skip_tol = float(skip_tol)
+        opt.table_fp32 = int(bool(table_fp32))
         self._sur = surrogate          # the context reads it on every apply
         self.form = form
         self._keep = []

@@ -42,7 +42,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(fbc.Cell) == 32
     assert C.sizeof(fbc.RelaxOut) == 56
     assert C.sizeof(fbc.RelaxOpts) == 32
-    assert C.sizeof(fbc.Options) == 64
+    assert C.sizeof(fbc.Options) == 72
 
 
 def test_default_options():
@@ -53,7 +53,7 @@ def test_default_options():
 
 
 def _assemble(lib, fbc, nz=8, n_i=4, n_b=6, n_rhs=1, bz=16, form=0, ncells=1, null_cols=False,
-              k=1.0):
+              k=1.0, table_fp32=0):
     ci = np.zeros((n_i, 2), np.int32)
     ci[:, 0] = np.arange(n_i)
     cb = np.zeros((n_b, 2), np.int32)
@@ -66,6 +66,7 @@ def _assemble(lib, fbc, nz=8, n_i=4, n_b=6, n_rhs=1, bz=16, form=0, ncells=1, nu
     lib.fbc_default_options(C.byref(opt))
     opt.bz_m1 = opt.bz_m2 = bz
     opt.form = form
+    opt.table_fp32 = table_fp32
     lat = fbc.Lattice(1.0, k)
     out = C.c_void_p()
     rc = lib.fbc_assemble_G(C.byref(lat), cells, ncells, C.byref(opt), None, C.byref(out))
@@ -74,7 +75,8 @@ def _assemble(lib, fbc, nz=8, n_i=4, n_b=6, n_rhs=1, bz=16, form=0, ncells=1, nu
 
 @pytest.mark.parametrize("kw", [dict(nz=12), dict(nz=1), dict(nz=8192), dict(bz=12), dict(bz=4),
                                 dict(n_i=0), dict(n_rhs=0), dict(form=9), dict(ncells=0),
-                                dict(null_cols=True), dict(k=-1.0)])
+                                dict(null_cols=True), dict(k=-1.0), dict(table_fp32=2),
+                                dict(form=1, table_fp32=1), dict(form=5, table_fp32=1)])
 def test_invalid_arguments_rejected_before_device_work(kw):
     fbc, lib = _lib()
     rc, out = _assemble(lib, fbc, **kw)

@@ -101,7 +101,7 @@ def spectrum_errors(w_cols, modes, ref):
 
 # (form, bound on the sampled-spectrum error, bound on any single mode)
 LONG_FORMS = [("dtable_fp64", 1e-10, 1e-10), ("fp32", 1e-6, 1e-5), ("split_fp16", 1e-6, 1e-5),
-              ("split_bf16", 2e-5, 2e-4)]
+              ("split_bf16", 2e-5, 2e-4), ("dtable_fp64+table_fp32", 1e-6, 1e-5)]
 
 
 @pytest.mark.parametrize("form,bound,mode_bound", LONG_FORMS)
@@ -118,7 +118,10 @@ def test_long_sampled_modes_match_oracle(form, bound, mode_bound):
     from paper_2105_08798_amd import FBC
     dev = torch.device("cuda:0")
     print(f"[long/{form}] assembling", flush=True)
-    ctx = FBC(wl.cells, wl.bz, form=form)
+    # "+table_fp32": the offset table's products on FP32 MFMA where far blocks are skipped
+    base = form.split("+")[0]
+    ctx = FBC(wl.cells, wl.bz, form=base, table_fp32=form.endswith("+table_fp32"),
+              skip_tol=1e-9 if form.endswith("+table_fp32") else 0.0)
     f = torch.from_numpy(c.forces).to(dev)
     w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
     ctx.green_apply(f, w)
@@ -209,9 +212,9 @@ def test_long_surrogate_learned_band_beats_the_continuum():
     f = torch.from_numpy(c.forces).to(dev)
     cols = torch.from_numpy(gold["cols"]).to(dev)
     errs = {}
-    for name, weights in (("learned", net), ("continuum", zero)):
+    for name, weights, t32 in (("learned", net, False), ("continuum", zero, False), ("learned, FP32 products", net, True)):
         sur.set_mlp(weights)
-        ctx = FBC(wl.cells, wl.bz, form="surrogate", surrogate=sur)
+        ctx = FBC(wl.cells, wl.bz, form="surrogate", surrogate=sur, table_fp32=t32)
         w = torch.zeros((c.n_rhs, c.nz, c.n_b, 3), dtype=torch.float64, device=dev)
         ctx.green_apply(f, w)
         assert ctx.sync_status() == 0
@@ -227,3 +230,5 @@ def test_long_surrogate_learned_band_beats_the_continuum():
         o.close()
     assert errs["learned"][0] < 1e-7 and errs["learned"][1] < 1e-5
     assert errs["learned"][0] < errs["continuum"][0], errs
+    # the table products on FP32 MFMA at the modes with skipped far blocks: within 1e-6
+    assert errs["learned, FP32 products"][0] < 1e-6 and errs["learned, FP32 products"][1] < 1e-5, errs
