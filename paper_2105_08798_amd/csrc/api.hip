@@ -1069,7 +1069,7 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
         const int* be = f16 ? c->bexp + p.rhs0 : nullptr;
         int tr, pp;
         if (!update_shape(p.nz, p.M, p.ctr, &tr, &pp)) {
-            // long or short lines: inverse transform into w, then the tiled transpose-update,
+            // lines outside 16..1024 layers: inverse transform into w, then the tiled transpose-update,
             // which also removes the mean (known beforehand, as for the fused update)
             double* uc = u + p.u_off;
             double* sp = c->sum_part + c->sum_part_off[ci];

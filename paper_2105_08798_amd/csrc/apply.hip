@@ -717,8 +717,8 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
 // mu (mean of the updated u, from k_update_mean) may be NULL (no mean removal).
 // Skipped entirely when a data check has latched an error.  Needs Nz >= 16.
 // ----------------------------------------------------------------------------------
-template <int NSM>
-__global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ c,
+template <int NSM, int NTH>
+__global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__ c,
                                                      double* __restrict__ u, int R, int nz, int logn,
                                                      int mp, int M, int tr, int pp, int n_rg,
                                                      int n_units, const double2* __restrict__ tw,
@@ -742,11 +742,11 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
     {
         constexpr int LU = NSM >= 8 ? 1 : 8 / NSM;
         const int nload = nm * nseq;
-        for (int t0 = threadIdx.x; t0 < nload; t0 += NT * LU) {
+        for (int t0 = threadIdx.x; t0 < nload; t0 += NTH * LU) {
             double2 v0[LU][NSM], v1[LU][NSM];
 #pragma unroll
             for (int k = 0; k < LU; ++k) {
-                const int t = t0 + k * NT;
+                const int t = t0 + k * NTH;
                 const int mm = t % nm, rest = t / nm;
                 const int pj = rest % pp, trr = rest / pp;
                 const int row = row0 + trr;
@@ -763,7 +763,7 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
             }
 #pragma unroll
             for (int k = 0; k < LU; ++k) {
-                const int t = t0 + k * NT;
+                const int t = t0 + k * NTH;
                 if (t >= nload) break;
                 const int mm = t % nm, rest = t / nm;
                 const int pj = rest % pp, trr = rest / pp;
@@ -802,11 +802,11 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
     const int nq = nz >> 2;
     const int nitem = nseq * nq;
     constexpr int LV = 2;
-    for (int t0 = threadIdx.x; t0 < nitem; t0 += NT * LV) {
+    for (int t0 = threadIdx.x; t0 < nitem; t0 += NTH * LV) {
         double oa[LV][4], ob[LV][4];
 #pragma unroll
         for (int k = 0; k < LV; ++k) {
-            const int t = t0 + k * NT;
+            const int t = t0 + k * NTH;
             const int trr = t % tr, rest = t / tr;
             const int g = rest % nq, pj = rest / nq;
             const int row = row0 + trr;
@@ -823,7 +823,7 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
         }
 #pragma unroll
         for (int k = 0; k < LV; ++k) {
-            const int t = t0 + k * NT;
+            const int t = t0 + k * NTH;
             if (t >= nitem) break;
             const int trr = t % tr, rest = t / tr;
             const int g = rest % nq, pj = rest / nq;
@@ -861,10 +861,12 @@ __global__ void __launch_bounds__(NT) k_irfft_update(const double* __restrict__ 
 // lists): 8 rows beat 4 (fewer groups in flight are not the limit; the read amplification
 // of 32-byte runs is) and match or beat 16 (half the groups per CU); one pair per group,
 // the pair groups sharing the product records through L2, beats two or four pairs per
-// group.  Returns false outside 16 <= Nz <= 256: the update then goes through the w
-// scratch and the tiled transpose.  (At Nz = 1024, 4 rows per group -- 64 KiB of LDS,
-// 32-byte runs of u -- measured no faster than the two passes: 3.7-4.9 ms against 4.45 ms
-// on the long workload.)
+// group.  Lines of 512 and 1024 layers keep the 8 rows (66 and 131 KiB of LDS) with 1024
+// threads per group (sixteen waves on the CU it fills): on the long workload 2.8-3.4 ms
+// against 4.3 ms for the inverse transform into w and the transpose-update, where 256
+// threads took 3.9-4.4 ms and 4 or 2 rows 4.2-7.9 ms; at Nz = 256, 1024 or 512 threads
+// are 9-40 % slower than 256.  Returns false outside 16 <= Nz <= 1024: the update then
+// goes through the w scratch and the tiled transpose.
 static int update_groups(int tr, int pp, int M, int ct_grid) {
     return xcd_groups(ct_grid * ((M + tr - 1) / tr), 4 / pp);
 }
@@ -874,7 +876,7 @@ bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp) {
     (void)ct_grid;
     *pp = 1;
     *tr = 8;
-    return nz >= 16 && nz <= 256;
+    return nz >= 16 && nz <= 1024;
 }
 
 void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
@@ -890,11 +892,21 @@ void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int 
     const int n_units = ct_grid * n_rg;
     const int nblk = update_groups(tr, pp, M, ct_grid);
     const size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
-#define UPD_CASE(NS) \
-    hipLaunchKernelGGL(k_irfft_update<NS>, dim3(nblk), dim3(NT), lds, st, c, u, R, nz, logn, mp, M, tr, \
-                       pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, bexp,  \
-                       alpha, mu, \
-                       read_u, status)
+    // lines of 512 and 1024 layers: 1024 threads per work group (one group per CU with its
+    // 66-131 KiB of LDS), 256 below
+#define UPD_CASE(NS) do {                                                                              \
+    if (nz > 256) {                                                                                   \
+        (void)hipFuncSetAttribute((const void*)k_irfft_update<NS, 1024>,                            \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
+        hipLaunchKernelGGL((k_irfft_update<NS, 1024>), dim3(nblk), dim3(1024), lds, st, c, u, R, nz, logn, mp, \
+                           M, tr, pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, \
+                           bexp, alpha, mu, read_u, status);                                          \
+    } else {                                                                                          \
+        hipLaunchKernelGGL((k_irfft_update<NS, NT>), dim3(nblk), dim3(NT), lds, st, c, u, R, nz, logn, mp, M, \
+                           tr, pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, \
+                           bexp, alpha, mu, read_u, status);                                          \
+    }                                                                                                 \
+} while (0)
     if (nsplit <= 1) UPD_CASE(1);
     else if (nsplit <= 2) UPD_CASE(2);
     else if (nsplit <= 4) UPD_CASE(4);
