@@ -255,8 +255,8 @@ typedef double dv2_t __attribute__((ext_vector_type(2)));
 
 // pairs: K even and f 16-byte aligned, so two adjacent columns load as one 16-byte access
 // and store as one complex LDS entry.
-template <int FORM>
-__global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
+template <int FORM, int NTH>
+__global__ void __launch_bounds__(NTH) k_line_rfft(const double* __restrict__ f,
                                                   const double* __restrict__ tot, int project,
                                                   void* __restrict__ bfrag, int nz, int logn,
                                                   int n_i, int kp, int ct, int tc,
@@ -280,11 +280,11 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     constexpr int LU = 8;
     if (pairs) {
         const int hp = tc >> 1;
-        for (int t0 = threadIdx.x; t0 < nz * hp; t0 += NT * LU) {
+        for (int t0 = threadIdx.x; t0 < nz * hp; t0 += NTH * LU) {
             dv2_t v[LU];
 #pragma unroll
             for (int q = 0; q < LU; ++q) {
-                const int t = t0 + q * NT;
+                const int t = t0 + q * NTH;
                 const int n0 = t / hp, k = k0 + 2 * (t - n0 * hp);
                 v[q] = (t < nz * hp && k < K)
                            ? __builtin_nontemporal_load((const dv2_t*)(f + ((int64_t)r * nz + n0) * K + k))
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
             }
 #pragma unroll
             for (int q = 0; q < LU; ++q) {
-                const int t = t0 + q * NT;
+                const int t = t0 + q * NTH;
                 if (t >= nz * hp) break;
                 const int n0 = t / hp, p = t - n0 * hp, k = k0 + 2 * p;
                 double x0 = v[q].x, x1 = v[q].y;
@@ -310,17 +310,17 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
             }
         }
     } else
-    for (int t0 = threadIdx.x; t0 < nz * tc; t0 += NT * LU) {
+    for (int t0 = threadIdx.x; t0 < nz * tc; t0 += NTH * LU) {
         double v[LU];
 #pragma unroll
         for (int q = 0; q < LU; ++q) {
-            const int t = t0 + q * NT;
+            const int t = t0 + q * NTH;
             const int n0 = t / tc, c = t - n0 * tc, k = k0 + c;
             v[q] = (t < nz * tc && k < K) ? __builtin_nontemporal_load(&f[((int64_t)r * nz + n0) * K + k]) : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < LU; ++q) {
-            const int t = t0 + q * NT;
+            const int t = t0 + q * NTH;
             if (t >= nz * tc) break;
             const int n0 = t / tc, c = t - n0 * tc, k = k0 + c;
             double x = v[q];
@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     constexpr int G = (FORM == FBC_FORM_FP32) ? 8 : 4;
     if (tc % G == 0) {
         const int ng = tc / G;
-        for (int t = threadIdx.x; t < nm * ng; t += NT) {
+        for (int t = threadIdx.x; t < nm * ng; t += NTH) {
             const int m = t / ng, g = t - m * ng;
             const int kb = k0 + g * G;
             if (kb >= K) continue;
@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
         __syncthreads();        // the next chunk overwrites the LDS sequences
         continue;
     }
-    for (int t = threadIdx.x; t < nm * tc; t += NT) {
+    for (int t = threadIdx.x; t < nm * tc; t += NTH) {
         const int m = t / tc, c = t - m * tc, k = k0 + c;
         if (k >= K) continue;
         const double2 z = lds[(c >> 1) * ss + m];
@@ -412,6 +412,8 @@ __global__ void __launch_bounds__(NT) k_line_rfft(const double* __restrict__ f,
     }
 }
 
+
+
 void launch_line_rfft(hipStream_t st, int form, const double* f, const double* tot, int project,
                       void* bfrag, int R, int nz, int n_i, int kp, int ct, const double2* tw,
                       const int* bexp) {
@@ -426,6 +428,16 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
     // long lines: at least 8 columns (64-byte runs of each layer's forces) while the group's
     // sequences fit in 66 KiB (two groups per CU)
     while (tc < 8 && 2 * tc * (nz + 1) * 8 <= 66 * 1024) tc <<= 1;
+    // lines of 1024 layers and more: 1024 threads per work group over 16 columns (128-byte
+    // runs of each layer; 131 KiB of LDS at Nz = 1024, one group filling a CU with sixteen
+    // waves), fewer columns where the LDS does not hold them.  Measured on the long
+    // workload: 1.13-1.15 ms against 1.27 ms for 4 columns x 256 threads (and 1.39 / 1.93
+    // ms for 8 / 4 columns x 1024 threads)
+    const bool wide = nz >= 1024;
+    if (wide) {
+        tc = 16;
+        while (tc > 2 && (size_t)(nz + 1) * tc * sizeof(double) > 160 * 1024) tc >>= 1;   // the CU's LDS
+    }
     const int kk = (K + 1) & ~1;
     if (tc > kk) tc = kk;
     tc &= ~1;
@@ -433,24 +445,25 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
     const int pairs = ((K & 1) == 0 && ((uintptr_t)f & 15) == 0) ? 1 : 0;
     const size_t lds = (size_t)(nz + 1) * tc * sizeof(double);
     const double inv_cnt = 1.0 / ((double)n_i * nz);
+#define RF_LAUNCH(FM)                                                                                       \
+    do {                                                                                                    \
+        if (wide) {                                                                                         \
+            (void)hipFuncSetAttribute((const void*)k_line_rfft<FM, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                      (int)lds);                                                            \
+            hipLaunchKernelGGL((k_line_rfft<FM, 1024>), grid, dim3(1024), lds, st, f, tot, project, bfrag, nz, logn, \
+                               n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);                                  \
+        } else {                                                                                            \
+            hipLaunchKernelGGL((k_line_rfft<FM, NT>), grid, dim3(NT), lds, st, f, tot, project, bfrag, nz, logn, \
+                               n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);                                  \
+        }                                                                                                   \
+    } while (0)
     switch (form) {
-        case FBC_FORM_FP32:
-            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP32>, grid, dim3(NT), lds, st, f, tot, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
-            break;
-        case FBC_FORM_SPLIT_FP16:
-            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_FP16>, grid, dim3(NT), lds, st, f, tot,
-                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
-            break;
-        case FBC_FORM_SPLIT_BF16:
-            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_SPLIT_BF16>, grid, dim3(NT), lds, st, f, tot,
-                               project, bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
-            break;
-        default:
-            hipLaunchKernelGGL(k_line_rfft<FBC_FORM_FP64>, grid, dim3(NT), lds, st, f, tot, project,
-                               bfrag, nz, logn, n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);
-            break;
+        case FBC_FORM_FP32: RF_LAUNCH(FBC_FORM_FP32); break;
+        case FBC_FORM_SPLIT_FP16: RF_LAUNCH(FBC_FORM_SPLIT_FP16); break;
+        case FBC_FORM_SPLIT_BF16: RF_LAUNCH(FBC_FORM_SPLIT_BF16); break;
+        default: RF_LAUNCH(FBC_FORM_FP64); break;
     }
+#undef RF_LAUNCH
 }
 
 // ----------------------------------------------------------------------------------
