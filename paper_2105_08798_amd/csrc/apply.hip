@@ -877,8 +877,8 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
 // group.  Lines of 512 and 1024 layers keep the 8 rows (66 and 131 KiB of LDS) with 1024
 // threads per group (sixteen waves on the CU it fills): on the long workload 2.8-3.4 ms
 // against 4.3 ms for the inverse transform into w and the transpose-update, where 256
-// threads took 3.9-4.4 ms and 4 or 2 rows 4.2-7.9 ms; at Nz = 256, 1024 or 512 threads
-// are 9-40 % slower than 256.  Returns false outside 16 <= Nz <= 1024: the update then
+// threads took 3.9-4.4 ms, 4 or 2 rows 4.2-7.9 ms, and 4 rows with 512 or 1024 threads (two
+// groups per CU) 4.2-5.1 ms; at Nz = 256, 1024 or 512 threads are 9-40 % slower than 256.  Returns false outside 16 <= Nz <= 1024: the update then
 // goes through the w scratch and the tiled transpose.
 static int update_groups(int tr, int pp, int M, int ct_grid) {
     return xcd_groups(ct_grid * ((M + tr - 1) / tr), 4 / pp);
