@@ -779,6 +779,7 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
     c->lat = *lat;
     c->sur = opt->surrogate;
     (void)hipGetDevice(&c->device);
+    apply_kernels_init();            // dynamic-LDS limits of the long-line transforms, before any capture
     hipStream_t st = (hipStream_t)stream;
     const int form = opt->form;
 

@@ -5,6 +5,8 @@
 // reproducible from run to run (no floating-point atomics).
 #include "fft_lds.h"
 #include <algorithm>
+#include <mutex>
+#include <set>
 
 #include "kernels.h"
 
@@ -448,8 +450,6 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
 #define RF_LAUNCH(FM)                                                                                       \
     do {                                                                                                    \
         if (wide) {                                                                                         \
-            (void)hipFuncSetAttribute((const void*)k_line_rfft<FM, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                      (int)lds);                                                            \
             hipLaunchKernelGGL((k_line_rfft<FM, 1024>), grid, dim3(1024), lds, st, f, tot, project, bfrag, nz, logn, \
                                n_i, kp, ct, tc, tw, inv_cnt, bexp, pairs);                                  \
         } else {                                                                                            \
@@ -909,8 +909,6 @@ void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int 
     // 66-131 KiB of LDS), 256 below
 #define UPD_CASE(NS) do {                                                                              \
     if (nz > 256) {                                                                                   \
-        (void)hipFuncSetAttribute((const void*)k_irfft_update<NS, 1024>,                            \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
         hipLaunchKernelGGL((k_irfft_update<NS, 1024>), dim3(nblk), dim3(1024), lds, st, c, u, R, nz, logn, mp, \
                            M, tr, pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, \
                            bexp, alpha, mu, read_u, status);                                          \
@@ -1339,4 +1337,30 @@ __global__ void k_fill(double* p, int64_t n, double v) {
 void launch_fill(hipStream_t st, double* p, int64_t n, double v) {
     if (n > 0)
         hipLaunchKernelGGL(k_fill, dim3((unsigned)grid_blocks(n)), dim3(NT), 0, st, p, n, v);
+}
+
+// The 1024-thread forms of the forward transform and of the fused update take more than
+// the default 64 KiB of dynamic LDS: raise their limit to the CU's 160 KiB once, at context
+// creation (not in a launch path, which may be under stream capture).
+void apply_kernels_init() {
+    static std::mutex mu;
+    static std::set<int> done;               // devices whose limits are set
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done.insert(dev).second) return;
+    {
+        const int lim = 160 * 1024;
+        (void)hipFuncSetAttribute((const void*)k_line_rfft<FBC_FORM_FP64, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)k_line_rfft<FBC_FORM_FP32, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)k_line_rfft<FBC_FORM_SPLIT_BF16, 1024>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)k_line_rfft<FBC_FORM_SPLIT_FP16, 1024>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)k_irfft_update<1, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)k_irfft_update<2, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)k_irfft_update<4, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)k_irfft_update<8, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipGetLastError();
+    }
 }

@@ -67,6 +67,9 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
                        int64_t split_stride, const double2* rowmean, const double2* shat,
                        const int* shat_on, const unsigned long long* amax, const int* bexp,
                        int* n_part_out);
+// Raises the dynamic-LDS limit of the 1024-thread line-transform kernels on the current
+// device (once per device; call outside stream capture, e.g. at context creation).
+void apply_kernels_init();
 // Partial-sum blocks of the transpose-update (per RHS) for M rows and Nz layers.
 int axpy_parts(int M, int nz);
 void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,

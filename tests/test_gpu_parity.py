@@ -653,3 +653,36 @@ def test_autotune_cache_file(tmp_path):
     assert not rd["from_cache"] and len(open(path).read().splitlines()) == 2
     for x in (a, b, d):
         x.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "split_fp16"])
+def test_graph_replay_long_lines(form):
+    """Lines of 1024 layers (the forward transform and the fused update on 1024-thread work
+    groups with more than 64 KiB of LDS): a captured update replays bitwise like the eager
+    one, also when the context's first call is the captured one."""
+    dev = _dev()
+    wl = W.make_custom(1024, 30, 70, 9, 16, seed=5)
+    c = wl.cells[0]
+    f = torch.from_numpy(c.forces).to(dev)
+    u0 = torch.from_numpy(np.random.default_rng(4).normal(size=c.n_rhs * c.nz * c.n_b * 3) * 0.01).to(dev)
+    s = torch.cuda.Stream()
+    ctx = _ctx(wl.cells, wl.bz, form=form)
+    u = torch.empty_like(u0)
+    outs = []
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            u.copy_(u0)
+            ctx.apply_graph(f, u, alpha=0.7, stream=s)
+        s.synchronize()
+        assert ctx.sync_status(stream=s) == 0
+        outs.append(u.clone())
+    ref = u0.clone()
+    ctx.apply(f, ref, alpha=0.7)
+    assert ctx.sync_status() == 0
+    ctx.close()
+    for rep, o in enumerate(outs):
+        assert torch.equal(o, ref), rep
+    if form == "fp64":
+        exp = oracle_update(wl, [u0.cpu().numpy().reshape(c.n_rhs, c.nz, c.n_b, 3)], 0.7)[0]
+        e2, emax = rel_err(ref.cpu().numpy().reshape(exp.shape), exp)
+        assert e2 < 1e-10 and emax < 1e-10, (e2, emax)
