@@ -804,7 +804,7 @@ def main() -> int:
 
     name = args.workload or "long"
     forms = [s for s in (args.forms or ",".join(DEFAULT_FORMS[name])).split(",") if s]
-    main_run = run_workload(torch, args, name, forms)
+    main_run = run_workload(torch, args, name, forms, extras_for="split_fp16")
     second = None
     if args.workload is None:
         second = run_workload(torch, args, "large", DEFAULT_FORMS["large"], extras_for="split_fp16")

@@ -600,6 +600,8 @@ def probe_read(buf, groups: int, reps: int = 5, stream=None) -> float:
     """Streaming-read rate (GB/s) of the device buffer `buf` (a CUDA tensor, 16-byte aligned,
     a multiple of 16 bytes) with `groups` work groups: fbc_probe_read, a diagnostic for
     weighing the kernels against the memory's practical rate."""
+    if not buf.is_contiguous():
+        raise ValueError("probe_read needs a contiguous tensor")
     lib = load_library()
     out = C.c_double(0.0)
     rc = lib.fbc_probe_read(C.c_void_p(buf.data_ptr()), C.c_int64(buf.numel() * buf.element_size()), int(groups),
