@@ -245,7 +245,20 @@ def test_projection_in_reduced_forms(form):
 @pytest.mark.parametrize("alpha_min", [0.0, 3.0])
 @pytest.mark.parametrize("form", FP64_FORMS)
 def test_relax_sequence_matches_oracle(form, alpha_min):
-    wl = W.make_single("parity")
+    _relax_sequence_check(W.make_single("parity"), form, alpha_min)
+
+
+@pytest.mark.parametrize("nz,n_i,n_b,R", [(256, 9, 17, 3), (512, 7, 15, 9), (1024, 9, 13, 5), (1024, 6, 11, 16),
+                                          (2048, 5, 9, 2)])
+def test_relax_sequence_long_lines(nz, n_i, n_b, R):
+    """Relaxation steps on long lines (the inverse transform into w with 1024 threads at 512
+    and 1024 layers, 2 rows x 4 RHS pairs per work group): odd pad row counts leave the last
+    group half full, and RHS counts off a multiple of 8 leave pairs of the last column tile
+    empty; the step bound reads every group's partial maximum."""
+    _relax_sequence_check(W.make_custom(nz, n_i, n_b, R, 16, seed=nz + n_b), "fp64", 0.0)
+
+
+def _relax_sequence_check(wl, form, alpha_min):
     c = wl.cells[0]
     dev = _dev()
     from paper_2105_08798_amd import RELAX_OUT_DOUBLES, parse_relax_out
