@@ -474,19 +474,51 @@ void launch_line_rfft(hipStream_t st, int form, const double* f, const double* t
 // record per K slice (split_stride apart).
 // ----------------------------------------------------------------------------------
 
-// Final value of one (row, mode) of an RHS pair (columns ja, ja + 1 of the tile): K
-// slices summed in fixed order, the split-FP16 scale removed, the row-gauge compensation
-// + R_b(m) . s^(m) added in FP64.  v0, v1: slice 0 at columns ja and ja + 8.  Every
-// kernel that consumes the product output goes through this function, so they agree
-// bit for bit.
-__device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R,
-                                   const double2* __restrict__ rowmean,
-                                   const double2* __restrict__ shat,
-                                   const int* __restrict__ shat_on,
-                                   const unsigned long long* __restrict__ amax,
-                                   const int* __restrict__ bexp,
-                                   double& ar, double& br, double& ai, double& bi) {
-    if (amax) {     // split FP16: the product of RHS r carries 2^(e_A(m) + e_B(r))
+// The row-gauge compensation terms R_b(m) . s^(m) of one row (atom b, component cc) for
+// the two RHS of a pair, from the three entries g[d] = R_b(m)[cc][d] and s^ of each RHS:
+// explicit fused multiply-adds in a fixed order, so that a kernel that stages the terms
+// ahead of the product records gets the same bits as one that computes them in place.
+__device__ inline void comp_core(const double2 (&g)[3], const double2 (&sa)[3], const double2 (&sb)[3],
+                                 double& dar, double& dai, double& dbr, double& dbi) {
+    dar = dai = dbr = dbi = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        dar = fma(-g[d].y, sa[d].y, fma(g[d].x, sa[d].x, dar));
+        dai = fma(g[d].y, sa[d].x, fma(g[d].x, sa[d].y, dai));
+        dbr = fma(-g[d].y, sb[d].y, fma(g[d].x, sb[d].x, dbr));
+        dbi = fma(g[d].y, sb[d].x, fma(g[d].x, sb[d].y, dbi));
+    }
+}
+
+// The compensation is zero for RHS whose per-layer net forces all vanish (s^ = 0): skipped
+// for pairs with no such RHS (shat_on[r] = 0), which saves its loads for the usual forces.
+__device__ inline bool comp_on(int ra, int R, const double2* __restrict__ rowmean,
+                               const int* __restrict__ shat_on) {
+    return rowmean && ((ra < R && shat_on[ra]) || (ra + 1 < R && shat_on[ra + 1]));
+}
+
+__device__ inline void comp_load_s(int mm, int nm, int ra, int R, const double2* __restrict__ shat,
+                                   double2 (&sa)[3], double2 (&sb)[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sa[d] = ra < R ? shat[((int64_t)ra * nm + mm) * 3 + d] : make_double2(0, 0);
+        sb[d] = ra + 1 < R ? shat[((int64_t)(ra + 1) * nm + mm) * 3 + d] : make_double2(0, 0);
+    }
+}
+
+__device__ inline void comp_load_g(int mm, int row, int M, const double2* __restrict__ rowmean,
+                                   double2 (&g)[3]) {
+    const int b = row / 3, cc = row - 3 * b;
+    const double2* rm = rowmean + ((int64_t)mm * (M / 3) + b) * 6;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] = rm[sym_idx(cc, d)];
+}
+
+// split FP16: the product of RHS r carries 2^(e_A(m) + e_B(r))
+__device__ inline void mode_scale(int mm, int ra, int R, const unsigned long long* __restrict__ amax,
+                                  const int* __restrict__ bexp, double& ar, double& br, double& ai,
+                                  double& bi) {
+    if (amax) {
         const int ea = split16_exp_a(amax[mm]);
         const double sa = ldexp(1.0, -(ea + (ra < R ? bexp[ra] : 0)));
         const double sb = ldexp(1.0, -(ea + (ra + 1 < R ? bexp[ra + 1] : 0)));
@@ -495,24 +527,31 @@ __device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R
         br *= sb;
         bi *= sb;
     }
-    // the compensation is zero for RHS whose per-layer net forces all vanish (s^ = 0):
-    // skipped for them (shat_on[r] = 0), which saves its loads for the usual forces
-    if (rowmean && ((ra < R && shat_on[ra]) || (ra + 1 < R && shat_on[ra + 1]))) {
-        const int b = row / 3, cc = row - 3 * b;
-        const double2* rm = rowmean + ((int64_t)mm * (M / 3) + b) * 6;
-        for (int d = 0; d < 3; ++d) {
-            const double2 g = rm[sym_idx(cc, d)];
-            if (ra < R) {
-                const double2 sv = shat[((int64_t)ra * nm + mm) * 3 + d];
-                ar += g.x * sv.x - g.y * sv.y;
-                ai += g.x * sv.y + g.y * sv.x;
-            }
-            if (ra + 1 < R) {
-                const double2 sv = shat[((int64_t)(ra + 1) * nm + mm) * 3 + d];
-                br += g.x * sv.x - g.y * sv.y;
-                bi += g.x * sv.y + g.y * sv.x;
-            }
-        }
+}
+
+// Final value of one (row, mode) of an RHS pair (columns ja, ja + 1 of the tile): K
+// slices summed in fixed order, the split-FP16 scale removed, the row-gauge compensation
+// + R_b(m) . s^(m) added in FP64.  v0, v1: slice 0 at columns ja and ja + 8.  Every
+// kernel that consumes the product output goes through mode_scale, comp_core and the
+// same additions, so they agree bit for bit.
+__device__ inline void mode_adjust(int mm, int row, int M, int nm, int ra, int R,
+                                   const double2* __restrict__ rowmean,
+                                   const double2* __restrict__ shat,
+                                   const int* __restrict__ shat_on,
+                                   const unsigned long long* __restrict__ amax,
+                                   const int* __restrict__ bexp,
+                                   double& ar, double& br, double& ai, double& bi) {
+    mode_scale(mm, ra, R, amax, bexp, ar, br, ai, bi);
+    if (comp_on(ra, R, rowmean, shat_on)) {
+        double2 g[3], sa[3], sb[3];
+        comp_load_g(mm, row, M, rowmean, g);
+        comp_load_s(mm, nm, ra, R, shat, sa, sb);
+        double dar, dai, dbr, dbi;
+        comp_core(g, sa, sb, dar, dai, dbr, dbi);
+        ar += dar;
+        ai += dai;
+        br += dbr;
+        bi += dbi;
     }
     if (mm == 0 || mm == nm - 1) {      // modes 0 and Nz/2 are real
         ai = 0.0;
@@ -751,6 +790,46 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
     const int ss = nz + 1;
     const int nm = (nz >> 1) + 1;
     const int nseq = tr * pp;
+    // 0. row-gauge compensation (pairs with per-layer net force only): the terms of every
+    //    (row, mode) staged in the LDS slots of the mode and its mirror, the s^ of a mode
+    //    loaded once per 4 rows and all loads of a thread issued before any is used
+    //    (computed inside the gather, each term waited for its own loads after the
+    //    records': 1.5 ms more per update of the long lines)
+    bool stage = false;                         // the same for the whole work group
+    for (int pj = 0; pj < pp; ++pj) stage = stage || comp_on(8 * tile + 2 * (pair0 + pj), R, rowmean, shat_on);
+    if (stage) {
+        constexpr int CR = 4;
+        const int nch = (tr + CR - 1) / CR;
+        const int n0 = nm * pp * nch;
+        for (int t = threadIdx.x; t < n0; t += NTH) {
+            const int mm = t % nm, rest = t / nm;
+            const int pj = rest % pp, ch = rest / pp;
+            const int ra = 8 * tile + 2 * (pair0 + pj);
+            if (!comp_on(ra, R, rowmean, shat_on)) continue;
+            double2 sa[3], sb[3], g[CR][3];
+            comp_load_s(mm, nm, ra, R, shat, sa, sb);
+#pragma unroll
+            for (int q = 0; q < CR; ++q) {
+                const int trr = ch * CR + q, row = row0 + trr;
+                if (trr < tr && row < M) {
+                    comp_load_g(mm, row, M, rowmean, g[q]);
+                } else {
+                    g[q][0] = g[q][1] = g[q][2] = make_double2(0, 0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < CR; ++q) {
+                const int trr = ch * CR + q, row = row0 + trr;
+                if (trr >= tr || row >= M) continue;
+                double dar, dai, dbr, dbi;
+                comp_core(g[q], sa, sb, dar, dai, dbr, dbi);
+                double2* sq = lds + (pj * tr + trr) * ss;
+                sq[mm] = make_double2(dar, dbr);
+                if (mm > 0 && 2 * mm < nz) sq[nz - mm] = make_double2(dai, dbi);
+            }
+        }
+        __syncthreads();
+    }
     // 1. gather
     {
         constexpr int LU = NSM >= 8 ? 1 : 8 / NSM;
@@ -793,13 +872,25 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
                     }
                 }
                 double2 z = make_double2(0, 0), zc = make_double2(0, 0);
+                double2* sq = lds + (pj * tr + trr) * ss;
                 if (row < M) {
-                    mode_adjust(mm, row, M, nm, 8 * tile + ja, R, rowmean, shat, shat_on, amax, bexp, ar, br,
-                                ai, bi);
+                    const int ra = 8 * tile + ja;
+                    mode_scale(mm, ra, R, amax, bexp, ar, br, ai, bi);
+                    if (comp_on(ra, R, rowmean, shat_on)) {     // the terms staged in step 0
+                        const double2 d0 = sq[mm];
+                        const double2 d1 = (mm > 0 && 2 * mm < nz) ? sq[nz - mm] : make_double2(0, 0);
+                        ar += d0.x;
+                        ai += d1.x;
+                        br += d0.y;
+                        bi += d1.y;
+                    }
+                    if (mm == 0 || mm == nm - 1) {      // modes 0 and Nz/2 are real
+                        ai = 0.0;
+                        bi = 0.0;
+                    }
                     z = make_double2(ar - bi, ai + br);     // U_a + i U_b at m
                     zc = make_double2(ar + bi, br - ai);    // conj U_a + i conj U_b at Nz - m
                 }
-                double2* sq = lds + (pj * tr + trr) * ss;
                 sq[mm] = z;
                 if (mm > 0 && 2 * mm < nz) sq[nz - mm] = zc;
             }
