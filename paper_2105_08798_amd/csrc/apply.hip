@@ -897,17 +897,17 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
         }
     }
     __syncthreads();
-    // 2. stages of half length Nz/2 .. 4
-    lds_fft_dif_s<true>(lds, nseq, ss, logn, 2, tw);
-    // 3. last two stages in registers, then the update (old values of u loaded LV items
-    //    ahead; loading them before the transform measured slower)
+    // 2. stages of half length Nz/2 .. 4; in groups of 1024 threads (one per CU, nothing
+    //    else to cover the transform's latency) with the old values of u and the means for
+    //    the first LV items of each thread already on their way (long lines: 3.2 against
+    //    3.4 ms; 256-thread groups, four per CU, load them after the transform)
+    constexpr bool early = NTH >= 1024;
     const double scale = 1.0 / nz;
-    const double2 w0 = twid<true>(tw, 0), w1 = twid<true>(tw, nz >> 2);
     const int nq = nz >> 2;
     const int nitem = nseq * nq;
     constexpr int LV = 2;
-    for (int t0 = threadIdx.x; t0 < nitem; t0 += NTH * LV) {
-        double oa[LV][4], ob[LV][4];
+    double oa[LV][4], ob[LV][4], ma[LV], mb[LV];
+    auto load_old = [&](int t0) {
 #pragma unroll
         for (int k = 0; k < LV; ++k) {
             const int t = t0 + k * NTH;
@@ -915,6 +915,9 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
             const int g = rest % nq, pj = rest / nq;
             const int row = row0 + trr;
             const int ra = 8 * tile + 2 * (pair0 + pj);
+            const bool live = t < nitem && row < M;
+            ma[k] = (mu && live && ra < R) ? mu[ra * 3 + row % 3] : 0.0;
+            mb[k] = (mu && live && ra + 1 < R) ? mu[(ra + 1) * 3 + row % 3] : 0.0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 oa[k][e] = ob[k][e] = 0.0;
@@ -925,6 +928,13 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
                 }
             }
         }
+    };
+    if (early) load_old(threadIdx.x);
+    lds_fft_dif_s<true>(lds, nseq, ss, logn, 2, tw);
+    // 3. last two stages in registers, then the update
+    const double2 w0 = twid<true>(tw, 0), w1 = twid<true>(tw, nz >> 2);
+    for (int t0 = threadIdx.x; t0 < nitem; t0 += NTH * LV) {
+        if (!early || t0 != (int)threadIdx.x) load_old(t0);
 #pragma unroll
         for (int k = 0; k < LV; ++k) {
             const int t = t0 + k * NTH;
@@ -941,19 +951,16 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
             dif(x0, x1, w0);
             dif(x2, x3, w0);
             const double2 xv[4] = {x0, x1, x2, x3};
-            const int cc = row % 3;
-            const double ma = (mu && ra < R) ? mu[ra * 3 + cc] : 0.0;
-            const double mb = (mu && ra + 1 < R) ? mu[(ra + 1) * 3 + cc] : 0.0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int n0 = (int)bitrev(4 * g + e, logn);
                 if (ra < R) {
                     const double x = oa[k][e] - alpha * (xv[e].x * scale);
-                    u[((int64_t)ra * nz + n0) * M + row] = mu ? x - ma : x;
+                    u[((int64_t)ra * nz + n0) * M + row] = mu ? x - ma[k] : x;
                 }
                 if (ra + 1 < R) {
                     const double x = ob[k][e] - alpha * (xv[e].y * scale);
-                    u[((int64_t)(ra + 1) * nz + n0) * M + row] = mu ? x - mb : x;
+                    u[((int64_t)(ra + 1) * nz + n0) * M + row] = mu ? x - mb[k] : x;
                 }
             }
         }
