@@ -149,6 +149,31 @@ def test_multi_cell_context_matches_per_cell_oracle(form):
         assert e2 < tol and emax < tol, (form, e2, emax)
 
 
+@pytest.mark.parametrize("form,tol", [("split_fp16", 1e-6), ("fp32", 1e-6)])
+def test_multi_cell_layer_net_forces(form, tol):
+    """Cells of different line lengths in one context, some with per-layer net force
+    (zero cell total) and some balanced: each cell's row-gauge compensation reads its own
+    R_b(m) and s^ (the fused update at 16 and 512 layers, the inverse into w at 2048)."""
+    specs = [(16, 30, 45, 3, 21, False), (512, 7, 13, 9, 22, True), (2048, 5, 9, 2, 23, False),
+             (512, 6, 11, 5, 24, False)]
+    cells = []
+    for nz, n_i, n_b, R, seed, balanced in specs:
+        c = W.make_custom(nz, n_i, n_b, R, 32, seed=seed, zero_net_force=False).cells[0]
+        f = c.forces - c.forces.mean(axis=(1, 2), keepdims=True)
+        if balanced:
+            f = f - f.mean(axis=2, keepdims=True)
+        else:
+            assert np.abs(f.sum(axis=2)).max() > 1e-2
+        c.forces = np.ascontiguousarray(f)
+        cells.append(c)
+    wl = W.Workload("mixed", cells, bz=32)
+    rc, got, u0 = run_apply(wl, form, alpha=0.9)
+    assert rc == 0
+    for k, (g, r) in enumerate(zip(split_cells(wl, got), oracle_update(wl, u0, 0.9))):
+        e2, emax = rel_err(g, r)
+        assert e2 < tol and emax < 3 * tol, (form, k, e2, emax)
+
+
 def test_net_force_violation_latched_and_u_untouched():
     wl = W.make_custom(8, 20, 30, 2, 16, seed=5, zero_net_force=False)
     rc, got, u0 = run_apply(wl, "fp64")
