@@ -876,14 +876,12 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             int tr, pp;
             irfft_shape(p.nz, &tr, &pp);
             const int np_ir = (p.M + tr - 1) / tr;
-            const int np_ax = axpy_parts(p.M, p.nz);
             c->wmax_off.push_back(wmax_n);
             c->sum_part_off.push_back(sp_n);
             c->rpart_off.push_back(rp_n);
             c->npart_irfft.push_back(np_ir);
-            c->npart_axpy.push_back(np_ax);
             wmax_n += (int64_t)p.R * np_ir;
-            sp_n += (int64_t)p.R * std::max(np_ax * 3, mean_blocks((int64_t)p.nz * p.M) * 6);
+            sp_n += (int64_t)p.R * mean_blocks((int64_t)p.nz * p.M) * 6;
             rp_n += (int64_t)p.R * 64 * 3;
         }
         if ((s = dev_alloc(c, (void**)&c->sums, sums_n * 8)) != FBC_OK) goto fail_out;
@@ -1085,7 +1083,7 @@ static void enqueue_update(fbc_ctx* c, double* u, double alpha, bool mean_remova
                               so, am, be, nullptr);
             if (!mean_removal) launch_fill(st, uc, (int64_t)p.R * p.nz * p.M, 0.0);
             // the mean is known beforehand: no partial sums
-            launch_axpy(st, c->wbuf + p.w_off, uc, nullptr, p.R, p.nz, p.M, alpha, nullptr, c->status, nullptr, mu);
+            launch_axpy(st, c->wbuf + p.w_off, uc, p.R, p.nz, p.M, alpha, nullptr, c->status, mu);
             continue;
         }
         double* mu = nullptr;
@@ -1438,15 +1436,23 @@ static void enqueue_relax(fbc_ctx* c, const double* f_in, double* u, fbc_relax_o
                            c->ropt.alpha_min);
     }
     enqueue_forward(c, f_in, st, true);
+    const bool comp = row_gauge_active(c);
+    const bool f16 = (c->opt.form == FBC_FORM_SPLIT_FP16);
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
         launch_relax_clamp(st, c->wmax_part + c->wmax_off[ci], c->npart_irfft[ci], c->alpha + p.rhs0,
                            c->stepinf + p.rhs0, p.R, c->ropt.du_max, kdev, c->ropt.relax);
+        // the mean of the updated u, (sum u - alpha_r sum w) / N with sum w from the mode-0
+        // records, is known once the step factors are: the transpose-update removes it (one
+        // read of u for its sum instead of a pass over the result)
         double* uc = u + p.u_off;
-        double* sp = c->sum_part + c->sum_part_off[ci];
-        launch_axpy(st, c->wbuf + p.w_off, uc, sp, p.R, p.nz, p.M, 0.0, c->alpha + p.rhs0, c->status,
-                    nullptr);
-        launch_mean(st, uc, sp, c->npart_axpy[ci], c->rmean + 3 * p.rhs0, p.R, p.nz, p.M, c->status);
+        double* mu = c->rmean + 3 * p.rhs0;
+        launch_update_mean(st, uc, c->cbuf + p.c_off, c->sum_part + c->sum_part_off[ci], p.R, p.nz, p.mp, p.M,
+                           c->nsplit, p.c_split, comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
+                           comp ? c->shat + c->shat_off[ci] : nullptr, comp ? c->shat_on + p.rhs0 : nullptr,
+                           f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + p.rhs0 : nullptr, 0.0, mu,
+                           c->status, c->alpha + p.rhs0);
+        launch_axpy(st, c->wbuf + p.w_off, uc, p.R, p.nz, p.M, 0.0, c->alpha + p.rhs0, c->status, mu);
     }
     launch_relax_finish(st, f_in, c->fprev, c->f_elems, c->alpha, c->finf, c->stepinf, c->rmean, out,
                         c->total_rhs, kdev, c->ropt.tol_f);

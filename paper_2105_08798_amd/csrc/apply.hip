@@ -1092,7 +1092,8 @@ int mean_blocks(int64_t per_rhs) {
 }
 
 __global__ void __launch_bounds__(NT) k_update_mean(const double* __restrict__ part, int nbr, int nz, int n_b,
-                                                    double alpha, double* __restrict__ mu,
+                                                    double alpha, const double* __restrict__ alpha_d,
+                                                    double* __restrict__ mu,
                                                     const int* __restrict__ status) {
     __shared__ double red[6 * NT];
     if (status && *status) return;
@@ -1103,19 +1104,21 @@ __global__ void __launch_bounds__(NT) k_update_mean(const double* __restrict__ p
     block_sum<6>(v, red);
     if (threadIdx.x == 0) {
         const double inv_n = 1.0 / ((double)nz * n_b);
-        for (int cc = 0; cc < 3; ++cc) mu[r * 3 + cc] = (v[cc] - alpha * v[3 + cc]) * inv_n;
+        const double a = alpha_d ? alpha_d[r] : alpha;
+        for (int cc = 0; cc < 3; ++cc) mu[r * 3 + cc] = (v[cc] - a * v[3 + cc]) * inv_n;
     }
 }
 
 void launch_update_mean(hipStream_t st, const double* u, const double* c, double* part, int R, int nz,
                         int mp, int M, int nsplit, int64_t split_stride, const double2* rowmean,
                         const double2* shat, const int* shat_on, const unsigned long long* amax,
-                        const int* bexp, double alpha, double* mu, const int* status) {
+                        const int* bexp, double alpha, double* mu, const int* status,
+                        const double* alpha_d) {
     const int64_t per_rhs = (int64_t)nz * M;
     const int nbr = mean_blocks(per_rhs);
     hipLaunchKernelGGL(k_mean_parts, dim3(nbr, R), dim3(NT), 0, st, u, c, per_rhs, nbr, R, nz, mp, M, nsplit,
                        split_stride, rowmean, shat, shat_on, amax, bexp, part, status);
-    hipLaunchKernelGGL(k_update_mean, dim3(R), dim3(NT), 0, st, part, nbr, nz, M / 3, alpha, mu, status);
+    hipLaunchKernelGGL(k_update_mean, dim3(R), dim3(NT), 0, st, part, nbr, nz, M / 3, alpha, alpha_d, mu, status);
 }
 
 // ----------------------------------------------------------------------------------
@@ -1123,23 +1126,17 @@ void launch_update_mean(hipStream_t st, const double* u, const double* c, double
 // of the result, known beforehand) by a tiled transpose through LDS: tiles of 64 rows x
 // 32 layers, 16-byte accesses along the contiguous axis of each array (two rows of a
 // layer of u, two layers of a row of w per thread) where the arrays allow; the old values
-// of u are loaded before the tile of w.  SUMS: per block partial sums of the updated u per
-// Cartesian component (row % 3), for the mean removal that follows (the relaxation step).
-// Skipped entirely when a data check has latched an error.
+// of u are loaded before the tile of w.  Skipped entirely when a data check has latched an
+// error.
 // ----------------------------------------------------------------------------------
 #define AX_TR 64
 #define AX_TN 32
 
-int axpy_parts(int M, int nz) { return ((M + AX_TR - 1) / AX_TR) * ((nz + AX_TN - 1) / AX_TN); }
-
-template <bool SUMS>
-__global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, double* __restrict__ u,
-                                             double* __restrict__ sum_part, int nz, int M,
-                                             double alpha, const double* __restrict__ alpha_d,
+__global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, double* __restrict__ u, int nz,
+                                             int M, double alpha, const double* __restrict__ alpha_d,
                                              const double* __restrict__ mu, int vec,
                                              const int* __restrict__ status) {
     __shared__ double tile[AX_TR][AX_TN + 1];
-    __shared__ double red[SUMS ? 3 * NT : 1];
     if (status && *status) return;
     const int r = blockIdx.z;
     const int row0 = blockIdx.x * AX_TR, n00 = blockIdx.y * AX_TN;
@@ -1193,7 +1190,6 @@ __global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, doubl
         }
     }
     __syncthreads();
-    double v[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int n0 = n00 + ty + 8 * k;
@@ -1204,7 +1200,6 @@ __global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, doubl
             const int rr = row + e;
             x[e] = uo[k][e] - a * tile[2 * tx + e][ty + 8 * k];
             if (mu) x[e] -= m3[rr % 3];
-            if (SUMS && rr < M) v[rr % 3] += x[e];
         }
         double* p = ur + (int64_t)n0 * M + row;
         if (vec && row + 1 < M) {
@@ -1214,67 +1209,14 @@ __global__ void __launch_bounds__(NT) k_axpy(const double* __restrict__ w, doubl
             if (row + 1 < M) p[1] = x[1];
         }
     }
-    if (SUMS) {
-        block_sum<3>(v, red);
-        if (threadIdx.x == 0) {
-            const int64_t nb = (int64_t)gridDim.x * gridDim.y;
-            const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-            for (int c = 0; c < 3; ++c) sum_part[((int64_t)r * nb + b) * 3 + c] = v[c];
-        }
-    }
 }
 
-void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
-                 int M, double alpha, const double* alpha_d, const int* status, int* n_part_out,
-                 const double* mu) {
+void launch_axpy(hipStream_t st, const double* w, double* u, int R, int nz, int M, double alpha,
+                 const double* alpha_d, const int* status, const double* mu) {
     dim3 grid((M + AX_TR - 1) / AX_TR, (nz + AX_TN - 1) / AX_TN, R);
     // 16-byte accesses: every row pair of u and layer pair of w starts 16-byte aligned
     const int vec = ((M & 1) == 0 && (nz & 1) == 0 && ((uintptr_t)u & 15) == 0 && ((uintptr_t)w & 15) == 0) ? 1 : 0;
-    if (sum_part)
-        hipLaunchKernelGGL(k_axpy<true>, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d, mu, vec,
-                           status);
-    else
-        hipLaunchKernelGGL(k_axpy<false>, grid, dim3(NT), 0, st, w, u, sum_part, nz, M, alpha, alpha_d, mu, vec,
-                           status);
-    if (n_part_out) *n_part_out = (int)(grid.x * grid.y);
-}
-
-// Mean over all pad atoms and layers per RHS and component, then subtraction.
-__global__ void __launch_bounds__(NT) k_mean_reduce(const double* __restrict__ part, int n_part,
-                                                    double* __restrict__ mean_out, double inv_n,
-                                                    const int* __restrict__ status) {
-    __shared__ double red[3 * NT];
-    if (status && *status) return;
-    const int r = blockIdx.x;
-    double v[3] = {0, 0, 0};
-    for (int b = threadIdx.x; b < n_part; b += NT)
-        for (int c = 0; c < 3; ++c) v[c] += part[((int64_t)r * n_part + b) * 3 + c];
-    block_sum<3>(v, red);
-    if (threadIdx.x == 0)
-        for (int c = 0; c < 3; ++c) mean_out[r * 3 + c] = v[c] * inv_n;
-}
-
-__global__ void __launch_bounds__(NT) k_mean_sub(double* __restrict__ u,
-                                                 const double* __restrict__ mean, int64_t per_rhs,
-                                                 int R, const int* __restrict__ status) {
-    if (status && *status) return;
-    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < per_rhs * R;
-         idx += (int64_t)gridDim.x * NT) {
-        const int r = (int)(idx / per_rhs);
-        const int64_t e = idx - (int64_t)r * per_rhs;
-        u[idx] -= mean[r * 3 + (int)(e % 3)];
-    }
-}
-
-void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, double* mean_out,
-                 int R, int nz, int M, const int* status) {
-    const double inv_n = 1.0 / ((double)nz * (M / 3));
-    hipLaunchKernelGGL(k_mean_reduce, dim3(R), dim3(NT), 0, st, sum_part, n_part, mean_out, inv_n,
-                       status);
-    const int64_t per_rhs = (int64_t)nz * M;
-    const int64_t total = per_rhs * R;
-    hipLaunchKernelGGL(k_mean_sub, dim3((unsigned)grid_blocks(total)), dim3(NT), 0, st, u,
-                       mean_out, per_rhs, R, status);
+    hipLaunchKernelGGL(k_axpy, grid, dim3(NT), 0, st, w, u, nz, M, alpha, alpha_d, mu, vec, status);
 }
 
 // ----------------------------------------------------------------------------------

@@ -70,13 +70,9 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
 // Raises the dynamic-LDS limit of the 1024-thread line-transform kernels on the current
 // device (once per device; call outside stream capture, e.g. at context creation).
 void apply_kernels_init();
-// Partial-sum blocks of the transpose-update (per RHS) for M rows and Nz layers.
-int axpy_parts(int M, int nz);
-void launch_axpy(hipStream_t st, const double* w, double* u, double* sum_part, int R, int nz,
-                 int M, double alpha, const double* alpha_d, const int* status,
-                 int* n_part_out, const double* mu = nullptr);
-void launch_mean(hipStream_t st, double* u, const double* sum_part, int n_part, double* mean_out,
-                 int R, int nz, int M, const int* status);
+// u <- u - alpha_r w - mu_r (mu optional) through a tiled transpose
+void launch_axpy(hipStream_t st, const double* w, double* u, int R, int nz, int M, double alpha,
+                 const double* alpha_d, const int* status, const double* mu);
 // fused inverse transform + update (fbc_apply, fbc_green_apply), and the mean it removes;
 // update_shape is false where the line is too long for the fused kernel
 bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp);
@@ -89,7 +85,8 @@ int mean_blocks(int64_t per_rhs);
 void launch_update_mean(hipStream_t st, const double* u, const double* c, double* part, int R, int nz,
                         int mp, int M, int nsplit, int64_t split_stride, const double2* rowmean,
                         const double2* shat, const int* shat_on, const unsigned long long* amax,
-                        const int* bexp, double alpha, double* mu, const int* status);
+                        const int* bexp, double alpha, double* mu, const int* status,
+                        const double* alpha_d = nullptr);
 
 // ---- relax (Section 2.3.3, Algorithm 2); kdev: the iteration index on the device ----
 void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,

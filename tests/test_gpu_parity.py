@@ -329,6 +329,9 @@ def _relax_sequence_check(wl, form, alpha_min, du_max=0.05, tol=1e-10, balanced=
             assert abs(got[r]["f_inf"] - oref["f_inf"][r]) <= 1e-15 * oref["f_inf"][r]
             assert abs(got[r]["step_inf"] - oref["step_inf"][r]) <= tol * oref["step_inf"][r]
             assert got[r]["converged"] == bool(oref["converged"][r])
+            # the removed mean, against the size of the displacements
+            scale = np.abs(uref[r]).max()
+            assert np.abs(np.array(got[r]["mean_removed"]) - oref["mean_removed"][r]).max() <= tol * scale
         e2, emax = rel_err(u.cpu().numpy(), uref)
         assert e2 < tol and emax < (1 if tol == 1e-10 else 3) * tol
     ctx.close()
