@@ -876,11 +876,14 @@ extern "C" fbc_status fbc_assemble_G(const fbc_lattice* lat, const fbc_cell* cel
             int tr, pp;
             irfft_shape(p.nz, &tr, &pp);
             const int np_ir = (p.M + tr - 1) / tr;
+            int np_up = 0;                   // the fused update's row groups (relaxation without a bound)
+            if (update_shape(p.nz, p.M, p.ctr, &tr, &pp)) np_up = (p.M + tr - 1) / tr;
             c->wmax_off.push_back(wmax_n);
             c->sum_part_off.push_back(sp_n);
             c->rpart_off.push_back(rp_n);
             c->npart_irfft.push_back(np_ir);
-            wmax_n += (int64_t)p.R * np_ir;
+            c->npart_update.push_back(np_up);
+            wmax_n += (int64_t)p.R * std::max(np_ir, np_up);
             sp_n += (int64_t)p.R * mean_blocks((int64_t)p.nz * p.M) * 6;
             rp_n += (int64_t)p.R * 64 * 3;
         }
@@ -977,7 +980,20 @@ fail_out:
 // ----------------------------------------------------------------------------------
 // Apply pipeline: net force -> line rFFT -> per-mode products -> inverse rFFT.
 // ----------------------------------------------------------------------------------
-static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to_w) {
+// Inverse transform of one cell's product output into the w scratch, with the per-row-group
+// maxima of |w| (the step bound of Algorithm 2).
+static void enqueue_to_w(fbc_ctx* c, size_t ci, hipStream_t st) {
+    const bool comp = row_gauge_active(c);
+    const bool f16 = (c->opt.form == FBC_FORM_SPLIT_FP16);
+    auto& p = c->cells[ci];
+    launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R, p.nz,
+                      p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split,
+                      comp ? c->rowmean + c->rowmean_off[ci] : nullptr, comp ? c->shat + c->shat_off[ci] : nullptr,
+                      comp ? c->shat_on + p.rhs0 : nullptr, f16 ? c->amax + c->amax_off[ci] : nullptr,
+                      f16 ? c->bexp + p.rhs0 : nullptr, nullptr);
+}
+
+static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st) {
     const int form = c->opt.form;
     int64_t sums_off = 0;
     const bool comp = row_gauge_active(c);
@@ -1043,15 +1059,6 @@ static void enqueue_forward(fbc_ctx* c, const double* f, hipStream_t st, bool to
         (void)hipEventRecord(c->ev[2 * c->n_timed + 1], st);
         ++c->n_timed;
     }
-    if (!to_w) return;
-    for (size_t ci = 0; ci < c->cells.size(); ++ci) {
-        auto& p = c->cells[ci];
-        launch_line_irfft(st, c->cbuf + p.c_off, c->wbuf + p.w_off, c->wmax_part + c->wmax_off[ci], p.R,
-                          p.nz, p.mp, p.M, p.ct, p.ctr, c->tw + p.tw_off, c->nsplit, p.c_split,
-                          comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
-                          comp ? c->shat + c->shat_off[ci] : nullptr, comp ? c->shat_on + p.rhs0 : nullptr,
-                          f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + p.rhs0 : nullptr, nullptr);
-    }
 }
 
 // Fused inverse transform and update of every cell: u <- u - alpha G f minus the mean of
@@ -1111,7 +1118,7 @@ extern "C" fbc_status fbc_apply(fbc_ctx* c, const double* f, double* u, double a
     if (!std::isfinite(alpha)) return fail(c, FBC_E_ARG, "alpha must be finite");
     hipStream_t st = (hipStream_t)stream;
     // the forward half, then per cell the mean and the fused inverse transform + update
-    enqueue_forward(c, f, st, false);
+    enqueue_forward(c, f, st);
     enqueue_update(c, u, alpha, true, st);
     HIPCHK(c, hipGetLastError());
     return FBC_OK;
@@ -1364,7 +1371,7 @@ extern "C" fbc_status fbc_green_apply(fbc_ctx* c, const double* f, double* w, vo
     fbc_status s = check_apply_args(c, f, w);
     if (s != FBC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    enqueue_forward(c, f, st, false);
+    enqueue_forward(c, f, st);
     enqueue_update(c, w, -1.0, false, st);
     HIPCHK(c, hipGetLastError());
     return FBC_OK;
@@ -1435,23 +1442,38 @@ static void enqueue_relax(fbc_ctx* c, const double* f_in, double* u, fbc_relax_o
                            c->alpha + p.rhs0, c->finf + p.rhs0, p.R, per_rhs, kdev, c->ropt.relax,
                            c->ropt.alpha_min);
     }
-    enqueue_forward(c, f_in, st, true);
+    enqueue_forward(c, f_in, st);
     const bool comp = row_gauge_active(c);
     const bool f16 = (c->opt.form == FBC_FORM_SPLIT_FP16);
     for (size_t ci = 0; ci < c->cells.size(); ++ci) {
         auto& p = c->cells[ci];
-        launch_relax_clamp(st, c->wmax_part + c->wmax_off[ci], c->npart_irfft[ci], c->alpha + p.rhs0,
-                           c->stepinf + p.rhs0, p.R, c->ropt.du_max, kdev, c->ropt.relax);
-        // the mean of the updated u, (sum u - alpha_r sum w) / N with sum w from the mode-0
-        // records, is known once the step factors are: the transpose-update removes it (one
-        // read of u for its sum instead of a pass over the result)
+        const double2* rm = comp ? c->rowmean + c->rowmean_off[ci] : nullptr;
+        const double2* sh = comp ? c->shat + c->shat_off[ci] : nullptr;
+        const int* so = comp ? c->shat_on + p.rhs0 : nullptr;
+        const unsigned long long* am = f16 ? c->amax + c->amax_off[ci] : nullptr;
+        const int* be = f16 ? c->bexp + p.rhs0 : nullptr;
         double* uc = u + p.u_off;
         double* mu = c->rmean + 3 * p.rhs0;
+        double* wm = c->wmax_part + c->wmax_off[ci];
+        // the mean of the updated u, (sum u - alpha_r sum w) / N with sum w from the mode-0
+        // records, is known once the step factors are: the update removes it
+        if (c->ropt.du_max <= 0.0 && c->npart_update[ci] > 0) {
+            // no step bound: the step factors are known before w, so the fused inverse
+            // transform and update takes them, and leaves the maxima of |w| for step_inf
+            launch_update_mean(st, uc, c->cbuf + p.c_off, c->sum_part + c->sum_part_off[ci], p.R, p.nz, p.mp,
+                               p.M, c->nsplit, p.c_split, rm, sh, so, am, be, 0.0, mu, c->status, c->alpha + p.rhs0);
+            launch_irfft_update(st, c->cbuf + p.c_off, uc, p.R, p.nz, p.mp, p.M, p.ctr, c->tw + p.tw_off, c->nsplit,
+                                p.c_split, rm, sh, so, am, be, 0.0, mu, 1, c->status, c->alpha + p.rhs0, wm);
+            launch_relax_clamp(st, wm, c->npart_update[ci], c->alpha + p.rhs0, c->stepinf + p.rhs0, p.R,
+                               c->ropt.du_max, kdev, c->ropt.relax);
+            continue;
+        }
+        // the step bound needs the whole of w first
+        enqueue_to_w(c, ci, st);
+        launch_relax_clamp(st, wm, c->npart_irfft[ci], c->alpha + p.rhs0, c->stepinf + p.rhs0, p.R,
+                           c->ropt.du_max, kdev, c->ropt.relax);
         launch_update_mean(st, uc, c->cbuf + p.c_off, c->sum_part + c->sum_part_off[ci], p.R, p.nz, p.mp, p.M,
-                           c->nsplit, p.c_split, comp ? c->rowmean + c->rowmean_off[ci] : nullptr,
-                           comp ? c->shat + c->shat_off[ci] : nullptr, comp ? c->shat_on + p.rhs0 : nullptr,
-                           f16 ? c->amax + c->amax_off[ci] : nullptr, f16 ? c->bexp + p.rhs0 : nullptr, 0.0, mu,
-                           c->status, c->alpha + p.rhs0);
+                           c->nsplit, p.c_split, rm, sh, so, am, be, 0.0, mu, c->status, c->alpha + p.rhs0);
         launch_axpy(st, c->wbuf + p.w_off, uc, p.R, p.nz, p.M, 0.0, c->alpha + p.rhs0, c->status, mu);
     }
     launch_relax_finish(st, f_in, c->fprev, c->f_elems, c->alpha, c->finf, c->stepinf, c->rmean, out,

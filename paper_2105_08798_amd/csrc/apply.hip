@@ -31,17 +31,17 @@ __device__ inline void block_sum(double (&v)[NV], double* red) {
     for (int c = 0; c < NV; ++c) v[c] = red[c * NT];
     __syncthreads();
 }
-template <int NV>
+template <int NV, int NTH = NT>
 __device__ inline void block_max(double (&v)[NV], double* red) {
-    for (int c = 0; c < NV; ++c) red[c * NT + threadIdx.x] = v[c];
+    for (int c = 0; c < NV; ++c) red[c * NTH + threadIdx.x] = v[c];
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
+    for (int s = NTH / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s)
             for (int c = 0; c < NV; ++c)
-                red[c * NT + threadIdx.x] = fmax(red[c * NT + threadIdx.x], red[c * NT + threadIdx.x + s]);
+                red[c * NTH + threadIdx.x] = fmax(red[c * NTH + threadIdx.x], red[c * NTH + threadIdx.x + s]);
         __syncthreads();
     }
-    for (int c = 0; c < NV; ++c) v[c] = red[c * NT];
+    for (int c = 0; c < NV; ++c) v[c] = red[c * NTH];
     __syncthreads();
 }
 
@@ -780,7 +780,9 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
         const int* __restrict__ shat_on,
                                                      const unsigned long long* __restrict__ amax,
                                                      const int* __restrict__ bexp, double alpha,
+                                                     const double* __restrict__ alpha_d,
                                                      const double* __restrict__ mu, int read_u,
+                                                     double* __restrict__ wmax_part,
                                                      const int* __restrict__ status) {
     extern __shared__ double2 lds[];
     if (status && *status) return;
@@ -931,8 +933,10 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
     };
     if (early) load_old(threadIdx.x);
     lds_fft_dif_s<true>(lds, nseq, ss, logn, 2, tw);
-    // 3. last two stages in registers, then the update
+    // 3. last two stages in registers, then the update; with per-RHS step factors alpha_d
+    //    (one RHS pair per group then) the group's largest |w| per RHS goes to wmax_part
     const double2 w0 = twid<true>(tw, 0), w1 = twid<true>(tw, nz >> 2);
+    double mxw[2] = {0.0, 0.0};
     for (int t0 = threadIdx.x; t0 < nitem; t0 += NTH * LV) {
         if (!early || t0 != (int)threadIdx.x) load_old(t0);
 #pragma unroll
@@ -951,19 +955,33 @@ __global__ void __launch_bounds__(NTH) k_irfft_update(const double* __restrict__
             dif(x0, x1, w0);
             dif(x2, x3, w0);
             const double2 xv[4] = {x0, x1, x2, x3};
+            const double aa = (alpha_d && ra < R) ? alpha_d[ra] : alpha;
+            const double ab = (alpha_d && ra + 1 < R) ? alpha_d[ra + 1] : alpha;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int n0 = (int)bitrev(4 * g + e, logn);
+                const double wa = xv[e].x * scale, wb = xv[e].y * scale;
+                if (wmax_part) {
+                    mxw[0] = fmax(mxw[0], fabs(wa));
+                    mxw[1] = fmax(mxw[1], fabs(wb));
+                }
                 if (ra < R) {
-                    const double x = oa[k][e] - alpha * (xv[e].x * scale);
+                    const double x = oa[k][e] - aa * wa;
                     u[((int64_t)ra * nz + n0) * M + row] = mu ? x - ma[k] : x;
                 }
                 if (ra + 1 < R) {
-                    const double x = ob[k][e] - alpha * (xv[e].y * scale);
+                    const double x = ob[k][e] - ab * wb;
                     u[((int64_t)(ra + 1) * nz + n0) * M + row] = mu ? x - mb[k] : x;
                 }
             }
         }
+    }
+    if (wmax_part) {
+        __syncthreads();                     // the transform buffer is free again
+        block_max<2, NTH>(mxw, (double*)lds);
+        const int ra = 8 * tile + 2 * pair0;
+        if (threadIdx.x == 0 && ra < R) wmax_part[(int64_t)ra * n_rg + rg] = mxw[0];
+        if (threadIdx.x == 0 && ra + 1 < R) wmax_part[(int64_t)(ra + 1) * n_rg + rg] = mxw[1];
     }
 }
 
@@ -994,26 +1012,31 @@ void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int 
                          int ct_grid, const double2* tw, int nsplit, int64_t split_stride,
                          const double2* rowmean, const double2* shat, const int* shat_on,
                          const unsigned long long* amax, const int* bexp, double alpha,
-                         const double* mu, int read_u, const int* status) {
+                         const double* mu, int read_u, const int* status, const double* alpha_d,
+                         double* wmax_part) {
     int logn = 0;
     while ((1 << logn) < nz) ++logn;
     int tr, pp;
     update_shape(nz, M, ct_grid, &tr, &pp);
+    if (pp != 1) wmax_part = nullptr;        // the group's maxima are per RHS pair (never taken)
     const int n_rg = (M + tr - 1) / tr;
     const int n_units = ct_grid * n_rg;
     const int nblk = update_groups(tr, pp, M, ct_grid);
-    const size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
+    size_t lds = (size_t)tr * pp * (nz + 1) * sizeof(double2);
+    // the maxima of |w| are reduced in the same LDS: 2 values per thread
+    const size_t lds_max = 2 * (size_t)(nz > 256 ? 1024 : NT) * sizeof(double);
+    if (wmax_part && lds < lds_max) lds = lds_max;
     // lines of 512 and 1024 layers: 1024 threads per work group (one group per CU with its
     // 66-131 KiB of LDS), 256 below
 #define UPD_CASE(NS) do {                                                                              \
     if (nz > 256) {                                                                                   \
         hipLaunchKernelGGL((k_irfft_update<NS, 1024>), dim3(nblk), dim3(1024), lds, st, c, u, R, nz, logn, mp, \
                            M, tr, pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, \
-                           bexp, alpha, mu, read_u, status);                                          \
+                           bexp, alpha, alpha_d, mu, read_u, wmax_part, status);                      \
     } else {                                                                                          \
         hipLaunchKernelGGL((k_irfft_update<NS, NT>), dim3(nblk), dim3(NT), lds, st, c, u, R, nz, logn, mp, M, \
                            tr, pp, n_rg, n_units, tw, nsplit, split_stride, rowmean, shat, shat_on, amax, \
-                           bexp, alpha, mu, read_u, status);                                          \
+                           bexp, alpha, alpha_d, mu, read_u, wmax_part, status);                      \
     }                                                                                                 \
 } while (0)
     if (nsplit <= 1) UPD_CASE(1);

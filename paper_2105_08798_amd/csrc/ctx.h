@@ -98,7 +98,7 @@ struct fbc_ctx {
     fbc_relax_out* rg_out = nullptr;
     void* rg_stream = nullptr;
     // per cell partial counts
-    std::vector<int> npart_irfft;
+    std::vector<int> npart_irfft, npart_update;
     std::vector<int64_t> wmax_off, sum_part_off, rpart_off;
     std::string err;
     // timing of the product kernel

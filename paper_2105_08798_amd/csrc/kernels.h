@@ -73,14 +73,17 @@ void apply_kernels_init();
 // u <- u - alpha_r w - mu_r (mu optional) through a tiled transpose
 void launch_axpy(hipStream_t st, const double* w, double* u, int R, int nz, int M, double alpha,
                  const double* alpha_d, const int* status, const double* mu);
-// fused inverse transform + update (fbc_apply, fbc_green_apply), and the mean it removes;
-// update_shape is false where the line is too long for the fused kernel
+// fused inverse transform + update (fbc_apply, fbc_green_apply, the relaxation step without
+// a step bound), and the mean it removes; update_shape is false where the line is too long
+// for the fused kernel.  alpha_d: per-RHS step factors on the device (else alpha);
+// wmax_part: per RHS and row group (ceil(M / tr) of them) the largest |w|, or NULL.
 bool update_shape(int nz, int M, int ct_grid, int* tr, int* pp);
 void launch_irfft_update(hipStream_t st, const double* c, double* u, int R, int nz, int mp, int M,
                          int ct_grid, const double2* tw, int nsplit, int64_t split_stride,
                          const double2* rowmean, const double2* shat, const int* shat_on,
                          const unsigned long long* amax, const int* bexp, double alpha,
-                         const double* mu, int read_u, const int* status);
+                         const double* mu, int read_u, const int* status,
+                         const double* alpha_d = nullptr, double* wmax_part = nullptr);
 int mean_blocks(int64_t per_rhs);
 void launch_update_mean(hipStream_t st, const double* u, const double* c, double* part, int R, int nz,
                         int mp, int M, int nsplit, int64_t split_stride, const double2* rowmean,

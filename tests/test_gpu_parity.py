@@ -295,6 +295,16 @@ def test_relax_sequence_unbalanced_layers_long_lines(nz, n_i, n_b, R, form, tol)
     _relax_sequence_check(wl, form, 0.0, du_max=0.0, tol=tol, balanced=False)
 
 
+@pytest.mark.parametrize("shape", [None, (1024, 9, 13, 5), (512, 7, 15, 9), (16, 30, 45, 11), (2048, 5, 9, 2)])
+@pytest.mark.parametrize("form", FP64_FORMS)
+def test_relax_sequence_without_step_bound(form, shape):
+    """Without the step bound the step factors are known before w: lines of 16-1024 layers
+    take the fused inverse transform and update, whose work groups leave the maxima of |w|
+    that step_inf reports (2048 layers still go through w)."""
+    wl = W.make_single("parity") if shape is None else W.make_custom(*shape, 16, seed=sum(shape))
+    _relax_sequence_check(wl, form, 0.0, du_max=0.0)
+
+
 def _relax_sequence_check(wl, form, alpha_min, du_max=0.05, tol=1e-10, balanced=True):
     c = wl.cells[0]
     dev = _dev()
@@ -620,8 +630,9 @@ def test_relax_checkpoint_resume_is_bitwise(form):
     assert torch.equal(ur, ua)
 
 
+@pytest.mark.parametrize("du_max", [0.05, 0.0])
 @pytest.mark.parametrize("form", ["fp64", "split_fp16"])
-def test_relax_step_graph_matches_eager(form):
+def test_relax_step_graph_matches_eager(form, du_max):
     """Algorithm 1's update with Algorithm 2 replayed from a captured graph: the iteration
     index lives in device memory, so every replay takes the current k (relaxation from the
     third step on); each step equals the eager step bit for bit, with eager work between
@@ -637,7 +648,7 @@ def test_relax_step_graph_matches_eager(form):
         nxt -= nxt.mean(axis=2, keepdims=True)
         seq.append(nxt)
     u0 = torch.from_numpy(rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01).to(dev)
-    opts = dict(relax=True, du_max=0.05, tol_f=0.2, alpha_min=0.0)
+    opts = dict(relax=True, du_max=du_max, tol_f=0.2, alpha_min=0.0)
     a = _ctx(wl.cells, wl.bz, form=form)
     g = _ctx(wl.cells, wl.bz, form=form)
     a.relax_begin(**opts)
