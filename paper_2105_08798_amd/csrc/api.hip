@@ -1476,8 +1476,7 @@ static void enqueue_relax(fbc_ctx* c, const double* f_in, double* u, fbc_relax_o
                            c->nsplit, p.c_split, rm, sh, so, am, be, 0.0, mu, c->status, c->alpha + p.rhs0);
         launch_axpy(st, c->wbuf + p.w_off, uc, p.R, p.nz, p.M, 0.0, c->alpha + p.rhs0, c->status, mu);
     }
-    launch_relax_finish(st, f_in, c->fprev, c->f_elems, c->alpha, c->finf, c->stepinf, c->rmean, out,
-                        c->total_rhs, kdev, c->ropt.tol_f);
+    launch_relax_finish(st, c->alpha, c->finf, c->stepinf, c->rmean, out, c->total_rhs, kdev, c->ropt.tol_f);
 }
 
 extern "C" fbc_status fbc_relax_step(fbc_ctx* c, const double* f_in, double* u, fbc_relax_out* out,

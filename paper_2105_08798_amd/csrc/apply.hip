@@ -1252,15 +1252,14 @@ void launch_axpy(hipStream_t st, const double* w, double* u, int R, int nz, int 
 // ----------------------------------------------------------------------------------
 __device__ inline int relax_on(const int* __restrict__ kdev, int relax) { return (relax && *kdev >= 2) ? 1 : 0; }
 #define RELAX_PARTS 64
-__global__ void __launch_bounds__(NT) k_relax_part(const double* __restrict__ fnew,
-                                                   const double* __restrict__ fprev,
+__global__ void __launch_bounds__(NT) k_relax_part(const double* __restrict__ fnew, double* fprev,
                                                    double* __restrict__ part, int64_t per_rhs,
                                                    const int* __restrict__ kdev, int relax) {
     __shared__ double red[3 * NT];
     const int use_prev = relax_on(kdev, relax);
     const int r = blockIdx.y;
     const double* a = fnew + (int64_t)r * per_rhs;
-    const double* b = fprev + (int64_t)r * per_rhs;
+    double* b = fprev + (int64_t)r * per_rhs;     // f_k read, then f_k+1 kept for the next step
     double v[2] = {0, 0};
     double mx[1] = {0};
     for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < per_rhs;
@@ -1273,6 +1272,7 @@ __global__ void __launch_bounds__(NT) k_relax_part(const double* __restrict__ fn
             v[0] += y * d;
             v[1] += d * d;
         }
+        b[e] = x;
     }
     block_sum<2>(v, red);
     block_max<1>(mx, red);
@@ -1314,7 +1314,7 @@ __global__ void __launch_bounds__(NT) k_relax_alpha(const double* __restrict__ p
     }
 }
 
-void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
+void launch_relax_alpha(hipStream_t st, const double* fnew, double* fprev, double* part,
                         double* alpha_d, double* finf_d, int R, int64_t per_rhs, const int* kdev,
                         int relax, double alpha_min) {
     hipLaunchKernelGGL(k_relax_part, dim3(RELAX_PARTS, R), dim3(NT), 0, st, fnew, fprev, part,
@@ -1349,12 +1349,6 @@ void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, dou
                        stepinf_d, du_max, kdev, relax);
 }
 
-__global__ void __launch_bounds__(NT) k_copy(const double* __restrict__ a, double* __restrict__ b,
-                                             int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
-        b[i] = a[i];
-}
-
 __global__ void k_relax_out(const double* __restrict__ alpha_d, const double* __restrict__ finf_d,
                             const double* __restrict__ stepinf_d, const double* __restrict__ mean_d,
                             fbc_relax_out* __restrict__ out, int R, const int* __restrict__ kdev,
@@ -1381,11 +1375,8 @@ void launch_relax_index(hipStream_t st, int* kdev, int v) {
     hipLaunchKernelGGL(k_relax_index, dim3(1), dim3(64), 0, st, kdev, v);
 }
 
-void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,
-                         const double* alpha_d, const double* finf_d, const double* stepinf_d,
+void launch_relax_finish(hipStream_t st, const double* alpha_d, const double* finf_d, const double* stepinf_d,
                          const double* mean_d, fbc_relax_out* out, int R, int* kdev, double tol_f) {
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)grid_blocks(n)), dim3(NT), 0, st, fnew, fprev,
-                       n);
     if (out)
         hipLaunchKernelGGL(k_relax_out, dim3((R + 63) / 64), dim3(64), 0, st, alpha_d, finf_d,
                            stepinf_d, mean_d, out, R, kdev, tol_f);

@@ -92,13 +92,14 @@ void launch_update_mean(hipStream_t st, const double* u, const double* c, double
                         const double* alpha_d = nullptr);
 
 // ---- relax (Section 2.3.3, Algorithm 2); kdev: the iteration index on the device ----
-void launch_relax_alpha(hipStream_t st, const double* fnew, const double* fprev, double* part,
+void launch_relax_alpha(hipStream_t st, const double* fnew, double* fprev, double* part,
                         double* alpha_d, double* finf_d, int R, int64_t per_rhs, const int* kdev, int relax,
                         double alpha_min);
 void launch_relax_clamp(hipStream_t st, const double* wmax_part, int n_part, double* alpha_d,
                         double* stepinf_d, int R, double du_max, const int* kdev, int relax);
-void launch_relax_finish(hipStream_t st, const double* fnew, double* fprev, int64_t n,
-                         const double* alpha_d, const double* finf_d, const double* stepinf_d,
+// relaxation output and the index advance; the partials kernel (launch_relax_alpha) keeps
+// f_k+1 in fprev for the next step
+void launch_relax_finish(hipStream_t st, const double* alpha_d, const double* finf_d, const double* stepinf_d,
                          const double* mean_d, fbc_relax_out* out, int R, int* kdev, double tol_f);
 // kdev <- v (v >= 0) or kdev + 1 (v < 0)
 void launch_relax_index(hipStream_t st, int* kdev, int v);
