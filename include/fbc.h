@@ -236,7 +236,10 @@ fbc_status fbc_set_work_list(fbc_ctx* ctx, int nsplit, int order, void* stream);
 /* Residual-based relaxation (Section 2.3.3, eq. alpha, Algorithm 2). */
 typedef struct {
     int relax;        /* 1: relax from the third iteration on (Algorithm 1)               */
-    double du_max;    /* > 0: bound ||alpha G f||_inf by du_max (Algorithm 2)             */
+    double du_max;    /* > 0: bound ||alpha G f||_inf by du_max (Algorithm 2); the bound
+                         needs the whole of G f before the update, so a step with it writes
+                         G f to a scratch first; <= 0: off, and lines of 16-1024 layers
+                         update u straight from the product output                         */
     double tol_f;     /* convergence flag: ||f_in||_inf < tol_f (Section 2.3.3)           */
     double alpha_min; /* > 0: lower bound on alpha_{k+1} (the preprint's variant, Remark in
                          Section 2.3.3), applied after the reset of negative values and
