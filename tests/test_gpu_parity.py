@@ -305,6 +305,51 @@ def test_relax_sequence_without_step_bound(form, shape):
     _relax_sequence_check(wl, form, 0.0, du_max=0.0)
 
 
+@pytest.mark.parametrize("du_max", [0.0, 0.05])
+def test_relax_multi_cell(du_max):
+    """Relaxation steps of a context whose cells take different update paths (16 and 512
+    layers: the fused update without the step bound; 2048 layers: through w), each cell's
+    RHS with their own relaxation factors: every cell against the oracle's sequence."""
+    dev = _dev()
+    from paper_2105_08798_amd import RELAX_OUT_DOUBLES, parse_relax_out
+    cells = [W.make_custom(16, 30, 45, 3, 32, seed=31).cells[0], W.make_custom(2048, 5, 9, 2, 32, seed=32).cells[0],
+             W.make_custom(512, 7, 13, 9, 32, seed=33).cells[0]]
+    wl = W.Workload("mixed-relax", cells, bz=32)
+    ctx = _ctx(wl.cells, wl.bz, form="fp64")
+    rng = np.random.default_rng(17)
+    seqs = []
+    for c in cells:
+        base = c.forces - c.forces.mean(axis=2, keepdims=True)
+        seq = [base]
+        for k in range(4):
+            nxt = 0.6 * seq[-1] + 0.02 * rng.normal(size=base.shape) * (0.5 ** k)
+            seq.append(nxt - nxt.mean(axis=2, keepdims=True))
+        seqs.append(seq)
+    u0 = [rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 0.01 for c in cells]
+    u = torch.from_numpy(np.concatenate([x.ravel() for x in u0])).to(dev)
+    greens = [oracle_green(c, wl.bz) for c in cells]
+    states = [orx.RelaxState(n_rhs=c.n_rhs, relax=True, du_max=du_max, tol_f=0.2) for c in cells]
+    uref = [x.copy() for x in u0]
+    ctx.relax_begin(relax=True, du_max=du_max, tol_f=0.2)
+    out = torch.zeros(sum(c.n_rhs for c in cells) * RELAX_OUT_DOUBLES, dtype=torch.float64, device=dev)
+    for k in range(len(seqs[0])):
+        f = np.concatenate([seqs[i][k].ravel() for i in range(len(cells))])
+        ctx.relax_step(torch.from_numpy(f).to(dev), u, out)
+        assert ctx.sync_status() == 0
+        got = parse_relax_out(out)
+        r0 = 0
+        for i, c in enumerate(cells):
+            uref[i], oref = orx.relax_step(states[i], seqs[i][k], uref[i], lambda x, g=greens[i]: oap.apply_green(g, x))
+            for r in range(c.n_rhs):
+                assert abs(got[r0 + r]["alpha"] - oref["alpha"][r]) <= 1e-10 * abs(oref["alpha"][r]), (k, i, r)
+                assert abs(got[r0 + r]["step_inf"] - oref["step_inf"][r]) <= 1e-10 * oref["step_inf"][r], (k, i, r)
+            r0 += c.n_rhs
+        for i, (g_, r_) in enumerate(zip(split_cells(wl, u.cpu().numpy()), uref)):
+            e2, emax = rel_err(g_, r_)
+            assert e2 < 1e-10 and emax < 1e-10, (k, i, e2, emax)
+    ctx.close()
+
+
 def _relax_sequence_check(wl, form, alpha_min, du_max=0.05, tol=1e-10, balanced=True):
     c = wl.cells[0]
     dev = _dev()
