@@ -191,3 +191,42 @@ def test_attached_hmatrix_is_the_product_step_of_apply(kw, tol):
     u_back, _ = _update(ctx, c, u0)
     assert np.array_equal(u_back, u_tab)
     ctx.close()
+
+
+@pytest.mark.parametrize("du_max", [0.0, 0.05])
+def test_attached_hmatrix_serves_the_relaxation_step(du_max):
+    """fbc_relax_step with an attached H-matrix (every low-rank block sent back to the
+    store): the same relaxation factors and, to rounding, the same displacements as with
+    the offset-table product, without the step bound (the fused update reads the H-matrix
+    product's records) and with it (through w)."""
+    from paper_2105_08798_amd import HMatrix, RELAX_OUT_DOUBLES, parse_relax_out
+    dev = _dev()
+    wl = W.make_custom(16, 400, 800, 3, 256, seed=43)
+    c = wl.cells[0]
+    rng = np.random.default_rng(9)
+    seq = [c.forces]
+    for k in range(3):
+        nxt = 0.6 * seq[-1] + 0.02 * rng.normal(size=c.forces.shape) * (0.5 ** k)
+        seq.append(nxt - nxt.mean(axis=2, keepdims=True))
+    u0 = rng.normal(size=(c.n_rhs, c.nz, c.n_b, 3)) * 1e-3
+    ctx = _ctx(wl)
+
+    def run():
+        u = torch.from_numpy(u0.copy()).to(dev)
+        out = torch.zeros(c.n_rhs * RELAX_OUT_DOUBLES, dtype=torch.float64, device=dev)
+        ctx.relax_begin(relax=True, du_max=du_max, tol_f=1e-3)
+        alphas = []
+        for fk in seq:
+            ctx.relax_step(torch.from_numpy(fk).to(dev), u, out)
+            assert ctx.sync_status() == 0
+            alphas.append([o["alpha"] for o in parse_relax_out(out)])
+        return u.cpu().numpy(), np.array(alphas)
+
+    u_tab, a_tab = run()
+    h = HMatrix(ctx, b_min=20, gamma=2, eps=1e-5, max_rank=1)
+    ctx.set_hmat(h)
+    u_h, a_h = run()
+    e = np.linalg.norm(u_h - u_tab) / np.linalg.norm(u_tab - u0)
+    assert np.allclose(a_h, a_tab, rtol=1e-12, atol=0) and e < 1e-12, (e, a_h, a_tab)
+    h.close()
+    ctx.close()
