@@ -766,7 +766,9 @@ void launch_line_irfft(hipStream_t st, const double* c, double* w, double* wmax_
 //  3. per thread four consecutive bit-reversed slots of one sequence: the stages of half
 //     length 2 and 1 in registers, then four layers n0 = bitrev(slot) of u, rows fastest
 //     across threads (runs of tr values of u per layer).
-// mu (mean of the updated u, from k_update_mean) may be NULL (no mean removal).
+// mu (mean of the updated u, from k_update_mean) may be NULL (no mean removal).  alpha_d:
+// per-RHS step factors on the device in place of alpha (the relaxation step without its
+// bound); wmax_part (one RHS pair per group): per RHS and row group the largest |w|.
 // Skipped entirely when a data check has latched an error.  Needs Nz >= 16.
 // ----------------------------------------------------------------------------------
 template <int NSM, int NTH>
